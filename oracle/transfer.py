@@ -1,0 +1,373 @@
+"""Sigma, Lambda and the linear solve (oracle, FP64).
+
+Vector layout: I[z][Omega][n][s], z slowest, Stokes s fastest (Sect. 2.6,
+lexicographic ordering; Sigma is block-diagonal in z).
+
+Per-height physics (Sects. 2.3, 6.1):
+  dnu_D(z) = (nu0/c) sqrt(2 k T / M + xi^2);  reduced frequency u = x * lam,
+  lam = dnu_D_ref / dnu_D(z), dnu_D_ref = dnu_D(T_ref, xi = 0);
+  a = (G_R + G_I + G_E)/(4 pi dnu_D);  eps = G_I/(G_R + G_I);
+  G_E = r_E (G_R + G_I);
+  u_b(Omega) = (nu0/c)(v . Omega)/dnu_D = (v . Omega)/v_th;
+  alpha_{u,u'} = G_R/(G_R + G_I + G_E + 2 pi i nu_{u,u'}),
+  beta_{u,u'}  = G_R/(G_R + G_I + 2 pi i nu_{u,u'})       (App. B).
+
+Quantities are per unit reduced frequency: eta~ = eta dnu_D / k and
+eps~ = eps dnu_D / k.  The transfer only needs the source vector eps/eta_I
+and the ray optical depth, so k itself never appears.
+
+Absorption (the propagation matrix, Sect. 2.1 and LL04 ch. 7): the 2x2
+transverse Jones operator of the medium is
+  N(nu) = c_abs sum_{u,l} Phi_{ul}(nu) (P d_ul^*)(P d_ul)^T,
+  Phi_{ul} = conj(W(a, u + u_b + s_ul))/sqrt(pi),
+where P projects on (e_a, e_b); the coherency C = <E E^dagger> obeys
+dC/ds = -(N C + C N^dagger)/2, which gives K_{jk} = Tr((N A_k + A_k N^dagger) A_j)/4
+for the Stokes matrices A = (1, sigma_z, sigma_x, -sigma_y) with
+S_j = Tr(C A_j).  The sign of A_V makes eta_V = (phi_r - phi_b) cos(theta_B)/2
+for sigma components with M_u - M_l = +1 (phi_b) and -1 (phi_r).
+
+Emission (Eq. eps_sc_l with Eqs. RQIIKKp, G, RIIIQKKp, evaluated as in
+App. D Eq. eps_sc_II_exp, in the comoving frame of Sect. 4.1):
+  eps_bar^II_i(Omega, u; l, l') = c_sc/(2 pi) sum_{u,u'} alpha_{u u'} sum_{Omega'} w_{Omega'}
+      sum_j E_i(u', u, l'; Omega) A_j(u, u', l; Omega')
+      [W_{u' l, j}(Omega', Theta, u) + conj(W_{u l, j}(Omega', Theta, u))]
+  with E_i(u', u, l') = d_{u'l'}^T Acart_i(Omega) d_{u l'}^*,
+       A_j(u, u', l)  = d_{u l}^T Acart_j(Omega')/2 d_{u' l}^*,
+       Acart_j = sum_ab (A_j)_ab e_a e_b^T,
+       W_{t,j}(Omega', Theta, u_n) = sum_m M_{Theta t}[n, m] Ibar_j(Omega', u_m);
+  eps_bar^III likewise with (beta - alpha)/(4 pi) and the separable incoming
+  and outgoing factors of Eq. RIIIQKKp;
+  eps^sc_i(Omega, u_n) = sum_{l,l'} S[eps_bar_i(Omega, .; l, l')](u_n + u_b(Omega) + u_{l,l'});
+  eps^sc_I *= f (App. E normalisation).
+
+Formal solution (Sect. 3): trapezoidal ray optical depth
+  dtau = (eta_I/eta_0 (z_k) + eta_I/eta_0 (z_k+1))/2 |dtau_line| / |mu|,
+eta_0 = field-free line-centre value, and DELO-linear steps
+  (Id + psi_c K'_c) I_c = (e^{-dtau} Id - psi_u K'_u) I_u + psi_u S_u + psi_c S_c,
+K' = K/eta_I - Id, S = eps/eta_I, with psi_u = [1 - e^{-x}(1+x)]/x and
+psi_c = [x - 1 + e^{-x}]/x.  Boundaries: (W_T(z_min), 0, 0, 0) entering from
+below, nothing from above (Sect. 3).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+from scipy.sparse.linalg import LinearOperator, gmres
+
+from .atom import build_atom
+from .grids import angular_grid, theta_table, SplineBasis
+from .redistribution import SQRT_PI, faddeeva, kernel_matrix, r3_weights
+
+C_CGS = 2.99792458e10
+K_B = 1.380649e-16
+AMU = 1.66053906660e-24
+
+# Stokes matrices A_j (S_j = Tr(C A_j)), I, Q, U, V
+A_STOKES = np.array([[[1, 0], [0, 1]],
+                     [[1, 0], [0, -1]],
+                     [[0, 1], [1, 0]],
+                     [[0, 1j], [-1j, 0]]], dtype=complex)
+
+
+@dataclass
+class OracleProblem:
+    prob: object
+    ang: dict
+    theta: np.ndarray
+    pair: np.ndarray
+    basis: SplineBasis
+    lam: np.ndarray
+    dnuD: np.ndarray
+    ub: np.ndarray            # [z, Omega]
+    atoms: list
+    s_ul: np.ndarray          # [z, n_u, n_l] profile shifts (reduced)
+    s_ll: np.ndarray          # [z, n_l, n_l] lower-level shifts u_{l,l'}
+    alpha: np.ndarray         # [z, n_u, n_u]
+    beta: np.ndarray
+    K: np.ndarray             # [z, Omega, n, 4, 4]
+    eta0: np.ndarray          # [z]
+    eps_th: np.ndarray        # [z, Omega, n, 4]
+    Acart: np.ndarray         # [Omega, 4, 3, 3]
+    opts: dict
+    M: dict = field(default_factory=dict)
+    r3: dict = field(default_factory=dict)
+    f: np.ndarray = None      # [z, Omega, n]
+
+
+def _acart(ang):
+    ea, eb = ang["e_a"], ang["e_b"]
+    basis = np.stack([ea, eb], axis=1)          # [Omega, 2(a,b), 3]
+    return np.einsum("jab,oax,oby->ojxy", A_STOKES, basis, basis)
+
+
+def setup(prob, opts=None) -> OracleProblem:
+    """Per-height physics, angular grid, Theta table, propagation matrix.
+
+    opts (test switches, all default off):
+      alpha_zero:   alpha = 0 (complete redistribution: R_III carries beta)
+      no_RII, no_RIII: drop one redistribution term
+      zero_profile_shifts: transitions at the zero-field frequency in all
+                    profiles while alpha/beta keep the sublevel splittings
+      normalize:    apply the App. E factor f (default True)
+    """
+    opts = dict({"normalize": True}, **(opts or {}))
+    atom = prob.atom
+    nu0 = C_CGS / (atom.lambda0_A * 1e-8)
+    mass = atom.mass_amu * AMU
+    vth = np.sqrt(2.0 * K_B * prob.T / mass + (prob.xi * 1e5) ** 2)
+    vth_ref = np.sqrt(2.0 * K_B * prob.T_ref / mass)
+    dnuD = nu0 * vth / C_CGS
+    dnuD_ref = nu0 * vth_ref / C_CGS
+    lam = dnuD_ref / dnuD
+    ang = angular_grid(prob.n_mu, prob.n_chi)
+    theta, pair = theta_table(ang["dirs"])
+    basis = SplineBasis(prob.x)
+    nz, nd, nn = prob.n_z, prob.n_dir, prob.n_nu
+    ub = (prob.v * 1e5) @ ang["dirs"].T / vth[:, None]
+    atoms = [build_atom(atom, *prob.B[z], dnuD_ref) for z in range(nz)]
+    nU = atoms[0].E_u.size
+    nL = atoms[0].E_l.size
+    s_ul = np.zeros((nz, nU, nL))
+    s_ll = np.zeros((nz, nL, nL))
+    alpha = np.zeros((nz, nU, nU), complex)
+    beta = np.zeros((nz, nU, nU), complex)
+    K = np.zeros((nz, nd, nn, 4, 4))
+    eta0 = np.zeros(nz)
+    Acart = _acart(ang)
+    for z in range(nz):
+        at = atoms[z]
+        s_ul[z] = (at.E_u[:, None] - at.E_l[None, :]) / dnuD[z]
+        s_ll[z] = (at.E_l[:, None] - at.E_l[None, :]) / dnuD[z]
+        if opts.get("zero_profile_shifts"):
+            s_ul[z] = 0.0
+            s_ll[z] = 0.0
+        g_tot = 4.0 * np.pi * prob.a[z] * dnuD[z]
+        g_ri = g_tot / (1.0 + atom.r_E)
+        g_r = (1.0 - prob.eps[z]) * g_ri
+        nuuu = at.E_u[:, None] - at.E_u[None, :]
+        alpha[z] = g_r / (g_tot + 2j * np.pi * nuuu)
+        beta[z] = g_r / (g_ri + 2j * np.pi * nuuu)
+        if opts.get("alpha_zero"):
+            alpha[z] = 0.0
+        eta0[z] = faddeeva(prob.a[z], 0.0).real / SQRT_PI
+        # propagation matrix per (Omega, n)
+        u = lam[z] * prob.x
+        arg = u[None, :, None, None] + ub[z][:, None, None, None] + s_ul[z][None, None]
+        Phi = np.conj(faddeeva(prob.a[z], arg)) / SQRT_PI          # [Om, n, u, l]
+        pa = np.einsum("oi,uli->oul", ang["e_a"], np.conj(at.d))    # e_a . d^*
+        pb = np.einsum("oi,uli->oul", ang["e_b"], np.conj(at.d))
+        P = np.stack([pa, pb], axis=1)                               # [Om, 2, u, l]
+        Nt = np.einsum("oaul,obul->oulab", P, np.conj(P))            # (e_a.d^*)(e_b.d)
+        Nmed = at.c_abs * np.einsum("onul,oulab->onab", Phi, Nt)
+        Ndag = np.conj(np.swapaxes(Nmed, -1, -2))
+        t1 = np.einsum("onab,kbc,jca->onjk", Nmed, A_STOKES, A_STOKES)
+        t2 = np.einsum("kab,onbc,jca->onjk", A_STOKES, Ndag, A_STOKES)
+        K[z] = 0.25 * (t1 + t2).real
+    eps_th = (prob.eps * prob.W_T)[:, None, None, None] * K[:, :, :, 0, :]
+    op = OracleProblem(prob=prob, ang=ang, theta=theta, pair=pair, basis=basis, lam=lam,
+                       dnuD=dnuD, ub=ub, atoms=atoms, s_ul=s_ul, s_ll=s_ll, alpha=alpha,
+                       beta=beta, K=K, eta0=eta0, eps_th=eps_th, Acart=Acart, opts=opts)
+    if opts["normalize"]:
+        op.f = normalization(op)
+    else:
+        op.f = np.ones((nz, nd, nn))
+    return op
+
+
+def _kernel(op, z, th, u, l):
+    # heights with identical (Theta, shift, damping, grid scale) share a kernel
+    key = (float(op.theta[th]), float(op.s_ul[z, u, l]), float(op.prob.a[z]), float(op.lam[z]))
+    if key not in op.M:
+        op.M[key] = kernel_matrix(op.theta[th], op.s_ul[z, u, l], op.prob.a[z],
+                                  op.lam[z], op.basis)
+    return op.M[key]
+
+
+def _r3(op, z, u, l):
+    key = (float(op.s_ul[z, u, l]), float(op.prob.a[z]), float(op.lam[z]))
+    if key not in op.r3:
+        op.r3[key] = r3_weights(op.s_ul[z, u, l], op.prob.a[z], op.lam[z], op.basis)
+    return op.r3[key]
+
+
+def sigma_height(op, z, Iz, normalize=True):
+    """eps^sc at height z for the local field Iz[Omega, n, 4]."""
+    prob = op.prob
+    at = op.atoms[z]
+    nd, nn = prob.n_dir, prob.n_nu
+    nU, nL = at.E_u.size, at.E_l.size
+    x = prob.x
+    lam = op.lam[z]
+    w = op.ang["w"]
+    # 1. comoving field: Ibar(u_m) = S[I](u_m - u_b(Omega'))
+    Ibar = np.empty_like(Iz)
+    for o in range(nd):
+        Ibar[o] = op.basis.interpolate(Iz[o], x - op.ub[z, o] / lam, axis=0)
+    # 2. W for every ordered pair (outgoing Omega, incoming Omega')
+    W = np.zeros((nU, nL, nd, nd, nn, 4), complex)
+    if not op.opts.get("no_RII"):
+        for u in range(nU):
+            for l in range(nL):
+                for o in range(nd):
+                    for oi in range(nd):
+                        W[u, l, o, oi] = _kernel(op, z, op.pair[o, oi], u, l) @ Ibar[oi]
+    # 3. R_III incoming factor Y_{ul, j}(Omega') and outgoing profiles on the comoving grid
+    Y = np.zeros((nU, nL, nd, 4), complex)
+    prof = np.zeros((nU, nL, nn), complex)
+    if not op.opts.get("no_RIII"):
+        for u in range(nU):
+            for l in range(nL):
+                Y[u, l] = np.einsum("m,omj->oj", _r3(op, z, u, l), Ibar)
+                prof[u, l] = faddeeva(prob.a[z], lam * x + op.s_ul[z, u, l])
+    # 4. angular and sublevel sums, every pair explicitly
+    d = at.d
+    # E[o, i, u', u, l'] = d[u', l']^T Acart_i(o) d[u, l']^*
+    E = np.einsum("prx,oixy,qry->oipqr", d, op.Acart, np.conj(d))
+    # A[o', j, u, u', l] = d[u, l]^T Acart_j(o')/2 d[u', l]^*
+    A = 0.5 * np.einsum("qlx,ojxy,ply->ojqpl", d, op.Acart, np.conj(d))
+    al = op.alpha[z]
+    bma = op.beta[z] - op.alpha[z]
+    eps_bar = np.zeros((nL, nL, nd, nn, 4))
+    for l in range(nL):
+        for lp in range(nL):
+            # 4x4 coefficients per (Omega, Omega', u, u'), quadrature weight included
+            Cf = np.einsum("oipq,xjqp->oxijqp", E[..., lp], A[..., l])
+            Cf = Cf * (at.c_sc * w)[None, :, None, None, None, None]
+            # R_II: alpha_{u u'} [W_{u' l} + conj(W_{u l})]
+            term_II = (np.einsum("oxijqp,qp,poxnj->oni", Cf, al, W[:, l])
+                       + np.einsum("oxijqp,qp,qoxnj->oni", Cf, al, np.conj(W[:, l])))
+            # R_III: (beta - alpha)_{u u'} (Y_{u'l} + conj Y_{ul})(prof_{u'l} + conj prof_{ul});
+            # outgoing profiles on the comoving grid carry the shift s_{u,l}, the
+            # back-interpolation adds u_{l,l'}
+            inc = Y[:, l][None, :, :, :] + np.conj(Y[:, l])[:, None, :, :]      # [u, u', o', j]
+            outp = prof[:, l][None, :, :] + np.conj(prof[:, l])[:, None, :]   # [u, u', n]
+            term_III = np.einsum("oxijqp,qp,qpxj,qpn->oni", Cf, bma, inc, outp)
+            eps_bar[l, lp] = (term_II / (2.0 * np.pi) + term_III / (4.0 * np.pi)).real
+    # 5. back to the observer frame with the lower-level shift of each (l, l')
+    out = np.zeros((nd, nn, 4))
+    for l in range(nL):
+        for lp in range(nL):
+            for o in range(nd):
+                y = x + (op.ub[z, o] + op.s_ll[z, l, lp]) / lam
+                out[o] += op.basis.interpolate(eps_bar[l, lp, o], y, axis=0)
+    if normalize:
+        out[..., 0] *= op.f[z]
+    return out
+
+
+def normalization(op):
+    """App. E: f = (1 - eps) W_T eta_I / eps^sc_I[I = (W_T, 0, 0, 0)], Stokes I only."""
+    prob = op.prob
+    f = np.ones((prob.n_z, prob.n_dir, prob.n_nu))
+    for z in range(prob.n_z):
+        Iz = np.zeros((prob.n_dir, prob.n_nu, 4))
+        Iz[..., 0] = prob.W_T[z]
+        num = sigma_height(op, z, Iz, normalize=False)[..., 0]
+        ref = (1.0 - prob.eps[z]) * prob.W_T[z] * op.K[z, :, :, 0, 0]
+        f[z] = ref / num
+    return f
+
+
+def sigma_apply(op, I, normalize=True):
+    """eps^sc = Sigma I for the full vector I[z, Omega, n, 4]."""
+    out = np.zeros_like(I)
+    for z in range(op.prob.n_z):
+        out[z] = sigma_height(op, z, I[z], normalize=normalize)
+    return out
+
+
+def _psi(x):
+    """DELO-linear weights psi_u, psi_c and exp(-x), series for small x."""
+    x = np.asarray(x, float)
+    ex = np.exp(-x)
+    small = x < 0.1
+    psi_u = np.empty_like(x)
+    psi_c = np.empty_like(x)
+    xl = np.where(small, 1.0, x)
+    psi_u[~small] = ((1.0 - ex * (1.0 + xl)) / xl)[~small]
+    psi_c[~small] = ((xl - 1.0 + ex) / xl)[~small]
+    xs = x[small]
+    # sum_{m>=2} (-1)^m (m-1) x^(m-1)/m!  and  sum_{m>=2} (-1)^m x^(m-1)/m!
+    pu = np.zeros_like(xs)
+    pc = np.zeros_like(xs)
+    fact = 1.0
+    for m in range(2, 22):
+        fact *= m
+        pu += (-1.0) ** m * (m - 1) * xs ** (m - 1) / fact
+        pc += (-1.0) ** m * xs ** (m - 1) / fact
+    psi_u[small] = pu
+    psi_c[small] = pc
+    return psi_u, psi_c, ex
+
+
+def formal_solve(op, eps, boundary=True, I_bottom=None):
+    """Lambda eps (+ t if boundary): DELO-linear sweeps along every ray."""
+    prob = op.prob
+    nz, nd, nn = prob.n_z, prob.n_dir, prob.n_nu
+    K = op.K
+    etaI = K[..., 0, 0]                                  # [z, o, n]
+    Kp = K / etaI[..., None, None] - np.eye(4)
+    S = eps / etaI[..., None]
+    ratio = etaI / op.eta0[:, None, None]
+    mu = op.ang["mu"]
+    dtl = np.abs(np.diff(prob.tau_line))                 # [nz-1]
+    I = np.zeros((nz, nd, nn, 4))
+    for o in range(nd):
+        up = mu[o] > 0
+        order = range(nz) if up else range(nz - 1, -1, -1)
+        order = list(order)
+        Icur = np.zeros((nn, 4))
+        if up and boundary:
+            if I_bottom is None:
+                Icur[:, 0] = prob.W_T[0]
+            else:
+                Icur = np.array(I_bottom[o], float)
+        I[order[0], o] = Icur
+        for k in range(1, nz):
+            zu, zc = order[k - 1], order[k]
+            x = 0.5 * (ratio[zu, o] + ratio[zc, o]) * dtl[min(zu, zc)] / abs(mu[o])
+            pu, pc, ex = _psi(x)
+            lhs = np.eye(4)[None] + pc[:, None, None] * Kp[zc, o]
+            rhs = (ex[:, None, None] * np.eye(4)[None] - pu[:, None, None] * Kp[zu, o])
+            b = np.einsum("nij,nj->ni", rhs, Icur) + pu[:, None] * S[zu, o] + pc[:, None] * S[zc, o]
+            Icur = np.linalg.solve(lhs, b[..., None])[..., 0]
+            I[zc, o] = Icur
+    return I
+
+
+def apply_operator(op, x):
+    """(Id - Lambda Sigma) x, with Lambda without boundary radiation."""
+    return x - formal_solve(op, sigma_apply(op, x), boundary=False)
+
+
+def rhs(op):
+    """b = Lambda eps_th + t."""
+    return formal_solve(op, op.eps_th, boundary=True)
+
+
+def solve(op, tol=1e-12, method="gmres", restart=200, maxiter=4000):
+    """Solution of (Id - Lambda Sigma) I = Lambda eps_th + t."""
+    b = rhs(op)
+    shape = b.shape
+    n = b.size
+    if method == "dense":
+        A = np.empty((n, n))
+        e = np.zeros(n)
+        for k in range(n):
+            e[:] = 0.0
+            e[k] = 1.0
+            A[:, k] = apply_operator(op, e.reshape(shape)).ravel()
+        return np.linalg.solve(A, b.ravel()).reshape(shape)
+    Aop = LinearOperator((n, n), matvec=lambda v: apply_operator(op, v.reshape(shape)).ravel(),
+                         dtype=float)
+    xsol, info = gmres(Aop, b.ravel(), rtol=tol, atol=0.0, restart=restart, maxiter=maxiter)
+    if info != 0:
+        raise RuntimeError(f"oracle GMRES did not converge (info={info})")
+    return xsol.reshape(shape)
+
+
+def emergent(op, I):
+    """Stokes vectors at z_max for every outgoing (mu > 0) direction: [o, n, 4]."""
+    up = op.ang["mu"] > 0
+    return I[-1][up]
