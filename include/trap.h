@@ -1,0 +1,193 @@
+/*
+ * trap.h -- C ABI of the MI355X (gfx950) library for the linearised polarised
+ * PRD transfer problem of Riva et al., "A numerical approach for modelling the
+ * polarisation signals of strong resonance lines with partial frequency
+ * redistribution".
+ *
+ * The problem is the linear system (Sect. 2.6, Eq. linear_system)
+ *     (Id - Lambda Sigma) I = Lambda eps_th + t,
+ * with Sigma the scattering operator (Eq. eps_sc_l with R = R_II + R_III,
+ * Eqs. RQIIKKp, G and RIIIQKKp, evaluated in the comoving frame of Sect. 4.1
+ * through the intermediate W of App. D, normalised as in App. E) and Lambda the
+ * formal solution (Sect. 3, DELO-linear ray sweeps).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Vector layout: a Stokes field or emissivity is a contiguous device array
+ *   V[z][o][n][s]  (n_z x n_dir x n_nu x 4), z = height index from the bottom
+ *   (z_min) to the top, o = direction index mu-major (mu ascending from -1 to
+ *   1, n_mu/2 Gauss-Legendre nodes per hemisphere) and chi-minor (chi_k =
+ *   2 pi k / n_chi), n = frequency node, s = Stokes (I, Q, U, V).
+ *   Positive Q is parallel to the limb (perpendicular to the vertical plane
+ *   containing the ray); (e_Q, e_perp, Omega) is right-handed; the V sign makes
+ *   eta_V = (phi_r - phi_b) cos(theta_B)/2.
+ *   Emissivities are per unit reduced frequency and per unit frequency-
+ *   integrated absorption coefficient (eps * dnu_D / k); only eps/eta_I enters.
+ * Precision codes: TRAP_FP64 vectors are double, TRAP_FP32 vectors are float.
+ * Ownership: device pointers passed in are owned by the caller and must stay
+ *   valid until the work enqueued on the context's stream has completed.  Host
+ *   descriptor arrays are read during the call only.  The context owns every
+ *   allocation it makes and frees it in trap_destroy.
+ * Streams: work is enqueued on the stream given to trap_create (a hipStream_t,
+ *   NULL = default stream).  trap_apply_sigma, trap_formal_solve and
+ *   trap_apply_operator are asynchronous; trap_set_problem, trap_precompute,
+ *   trap_gmres_solve and trap_emergent synchronise the stream.
+ * Errors: every call returns a trap_status; negative values are failures and
+ *   trap_last_error() returns a thread-local message.  A failed call leaves the
+ *   context usable.  No call aborts or throws.
+ */
+#ifndef TRAP_H
+#define TRAP_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct trap_ctx trap_ctx;
+
+typedef enum {
+  TRAP_OK = 0,
+  TRAP_EINVAL = -1,   /* bad argument or problem description */
+  TRAP_ENOMEM = -2,   /* device allocation failed or memory budget exceeded */
+  TRAP_EDEVICE = -3,  /* HIP runtime error */
+  TRAP_ENOCONV = -4,  /* iteration did not reach the tolerance */
+  TRAP_ESTATE = -5,   /* calls out of order (e.g. apply before precompute) */
+  TRAP_ENAN = -6      /* non-finite value detected */
+} trap_status;
+
+typedef enum { TRAP_FP64 = 0, TRAP_FP32 = 1 } trap_prec;
+
+/* Atomic model (Sect. 2.2; Table 1 for the two-term lines).
+ * kind 0: two-level atom J_l -> J_u with Lande factors g_l, g_u.
+ * kind 1: two-term atom (L_l, S) -> (L_u, S) in L-S coupling; the upper term is
+ *   treated in the Paschen-Back regime with the fine-structure splitting
+ *   E(J = L_u + S) - E(J = |L_u - S|) = fs_split_x reference Doppler widths,
+ *   centred on the line frequency; the lower term has linear Zeeman splitting.
+ * r_E = Gamma_E / (Gamma_R + Gamma_I), the elastic share of the damping. */
+typedef struct {
+  int kind;
+  double lambda0_A;   /* line-centre wavelength, Angstrom */
+  double mass_amu;    /* atomic mass */
+  double J_l, J_u, g_l, g_u;
+  int L_l, L_u;
+  double S;
+  double fs_split_x;
+  double r_E;
+} trap_atom_desc;
+
+/* Grids and atmosphere (Sects. 2.5, 4.2, 6.1).  Host arrays, bottom to top.
+ * x: frequency nodes in units of the reference Doppler width dnu_D(T_ref),
+ *    x = (nu0 - nu)/dnu_D_ref, strictly increasing, bracketing 0, n_nu >= 4.
+ * tau_line: vertical field-free line-centre optical depth, strictly decreasing,
+ *    > 0.  T (K), xi (km/s), a (damping), eps (photon destruction), W_T (Wien
+ *    function) have n_z entries; v is [n_z][3] km/s cartesian (z up); B is
+ *    [n_z][3] = (|B| in G, theta_B, chi_B) in the atmospheric frame.
+ * n_mu (even, >= 2) Gauss-Legendre mu nodes in total, n_chi >= 1 azimuths. */
+typedef struct {
+  int n_z, n_nu, n_mu, n_chi;
+  const double* x;
+  const double* tau_line;
+  const double* T;
+  const double* xi;
+  const double* a;
+  const double* eps;
+  const double* W_T;
+  const double* v;
+  const double* B;
+  double T_ref;
+} trap_problem_desc;
+
+/* Sizes of the discrete problem (filled by trap_get_info). */
+typedef struct {
+  int n_z, n_nu, n_dir, n_theta, n_slots, n_up, n_lo, n_trans;
+  size_t n_unknowns;            /* 4 n_z n_dir n_nu */
+  size_t bytes_kernel_fp64;     /* stored R_II kernels, FP64 */
+  size_t bytes_kernel_fp32;     /* stored R_II kernels, FP32 */
+  size_t bytes_device_total;    /* everything the context holds on the device */
+  double flops_contraction;     /* algorithmic flops of one R_II contraction */
+  double bytes_contraction_fp64;/* algorithmic HBM bytes of one contraction */
+  double bytes_contraction_fp32;
+} trap_info;
+
+typedef struct {
+  double tol;          /* stop when ||b - A x|| / ||b|| < tol (Sect. 5.1) */
+  int restart;         /* GMRES restart length m (Arnoldi basis size) */
+  int max_iters;       /* total inner iterations allowed */
+  int max_outer;       /* iterative-refinement steps (mixed precision) */
+  trap_prec inner;     /* precision of the inner operator (FP64 = plain GMRES) */
+  double inner_tol;    /* relative reduction asked of each inner solve */
+} trap_solve_opts;
+
+typedef struct {
+  int outer_steps;
+  int inner_iters;
+  int applies_fp64;
+  int applies_fp32;
+  double final_rel_res;   /* FP64 true residual at exit */
+  double ms_total;
+} trap_solve_stats;
+
+/* Create a context on HIP device `device` enqueuing on `stream` (hipStream_t). */
+int trap_create(trap_ctx** out, int device, void* stream);
+/* Free every device allocation of the context and the context itself. */
+int trap_destroy(trap_ctx* ctx);
+
+/* Load a problem: per-height physics on the host in FP64 (Doppler widths,
+ * damping split, branching ratios alpha/beta of App. B, sublevel energies and
+ * dipole vectors, angular tables, scattering-angle table of Sect. 4.2, cubic-
+ * spline coefficient maps of Sect. 6.2), uploaded to the device.  Replaces any
+ * previous problem of the context.  Synchronises. */
+int trap_set_problem(trap_ctx* ctx, const trap_atom_desc* atom, const trap_problem_desc* prob);
+
+/* Device-side precompute (Sect. 4.3, App. C-E): the propagation matrix and
+ * thermal emissivity, the R_II kernels M[z][Theta][t] (FP64 Faddeeva, product
+ * integration over frequency) stored in FP64 and/or FP32, the R_III weights,
+ * the normalisation factor f (one Sigma apply on a flat field) and the right-
+ * hand side b = Lambda eps_th + t.  store_mask: bit 0 = FP64 kernels, bit 1 =
+ * FP32 kernels (FP64 is always built for f and b).  Synchronises. */
+int trap_precompute(trap_ctx* ctx, int store_mask);
+
+/* eps = Sigma I (Eq. matrix_form_2 without eps_th): comoving interpolation,
+ * R_II contraction with the stored kernels, angular/sublevel sum, R_III,
+ * back-interpolation and the factor f on Stokes I.  If add_thermal != 0 the
+ * thermal emissivity eps_th is added.  I and eps are device arrays in `prec`. */
+int trap_apply_sigma(trap_ctx* ctx, const void* I, void* eps, int prec, int add_thermal);
+
+/* I = Lambda eps (+ t if with_boundary): DELO-linear sweeps (Sect. 3). */
+int trap_formal_solve(trap_ctx* ctx, const void* eps, void* I, int with_boundary, int prec);
+
+/* y = (Id - Lambda Sigma) x, the operator of Eq. linear_system. */
+int trap_apply_operator(trap_ctx* ctx, const void* x, void* y, int prec);
+
+/* Copy b = Lambda eps_th + t (FP64, computed by trap_precompute) into b_out. */
+int trap_rhs(trap_ctx* ctx, double* b_out_device);
+
+/* Solve Eq. linear_system by restarted GMRES (Sect. 5.1).  With opts->inner =
+ * TRAP_FP64 this is plain FP64 GMRES; with TRAP_FP32 the Krylov solves use the
+ * FP32 operator while the Arnoldi vectors, the residual and the iterative-
+ * refinement updates are FP64.  I is FP64 device memory: initial guess in,
+ * solution out.  Returns TRAP_ENOCONV if tol is not reached.  Synchronises. */
+int trap_gmres_solve(trap_ctx* ctx, const trap_solve_opts* opts, double* I, trap_solve_stats* stats);
+
+/* Emergent Stokes vectors at z_max for the mu > 0 directions:
+ * host_out[o_up][n][4] (FP64, n_dir/2 x n_nu x 4).  Synchronises. */
+int trap_emergent(trap_ctx* ctx, const double* I, double* host_out);
+
+/* Sizes and algorithmic work of the loaded problem. */
+int trap_get_info(const trap_ctx* ctx, trap_info* info);
+
+/* Device bytes a context needs for this problem with the given kernel store
+ * mask (for admission control); does not touch the device. */
+int trap_footprint(const trap_atom_desc* atom, const trap_problem_desc* prob, int store_mask,
+                   size_t* bytes);
+
+/* Thread-local description of the last failure. */
+const char* trap_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TRAP_H */

@@ -1,0 +1,248 @@
+// C-ABI entry points of the trap library (declared in include/trap.h), the
+// context's allocation bookkeeping and the operator apply y = x - Lambda Sigma x.
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "trap_internal.h"
+
+namespace trap {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+int fail(int code, const std::string& msg) {
+  set_error(msg);
+  return code;
+}
+
+int dalloc(trap_ctx* ctx, void** p, size_t bytes) {
+  void* q = nullptr;
+  if (bytes == 0) bytes = 16;
+  hipError_t e = hipMalloc(&q, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(TRAP_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed: " +
+                                 hipGetErrorString(e));
+  }
+  ctx->bufs.push_back(DevBuf{q, bytes});
+  *p = q;
+  return TRAP_OK;
+}
+
+void free_all(trap_ctx* ctx) {
+  if (!ctx->bufs.empty()) (void)hipStreamSynchronize(ctx->stream);
+  for (auto& b : ctx->bufs) (void)hipFree(b.p);
+  ctx->bufs.clear();
+  ctx->pb = Problem();
+  ctx->pre = Precomp();
+  ctx->wk = Work();
+  ctx->has_problem = false;
+}
+
+int upload(trap_ctx* ctx, void** dst, const void* src, size_t bytes) {
+  TRAP_TRY(dalloc(ctx, dst, bytes));
+  if (bytes) TRAP_HIP(hipMemcpyAsync(*dst, src, bytes, hipMemcpyHostToDevice, ctx->stream));
+  return TRAP_OK;
+}
+
+template <typename T>
+__global__ void k_sub_from(long long N, const T* __restrict__ x, T* __restrict__ y) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < N;
+       i += (long long)gridDim.x * blockDim.x)
+    y[i] = x[i] - y[i];
+}
+
+int operator_apply(trap_ctx* ctx, const void* x, void* y, int prec) {
+  if (prec != TRAP_FP64 && prec != TRAP_FP32) return fail(TRAP_EINVAL, "unknown precision");
+  TRAP_TRY(ensure_work(ctx, prec));
+  const int pi = prec == TRAP_FP64 ? 0 : 1;
+  void* e = ctx->wk.opeps[pi];
+  TRAP_TRY(sigma_apply(ctx, x, e, prec, 0, 1));
+  TRAP_TRY(formal_apply(ctx, e, y, 0, prec));
+  const long long N = 4LL * ctx->pb.nz * ctx->pb.nd * ctx->pb.nn;
+  if (prec == TRAP_FP64)
+    hipLaunchKernelGGL(k_sub_from<double>, dim3(1024), dim3(256), 0, ctx->stream, N,
+                       static_cast<const double*>(x), static_cast<double*>(y));
+  else
+    hipLaunchKernelGGL(k_sub_from<float>, dim3(1024), dim3(256), 0, ctx->stream, N,
+                       static_cast<const float*>(x), static_cast<float*>(y));
+  TRAP_HIP(hipGetLastError());
+  return TRAP_OK;
+}
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+}  // namespace trap
+
+using namespace trap;
+
+extern "C" {
+
+const char* trap_last_error(void) { return g_last_error.c_str(); }
+
+int trap_create(trap_ctx** out, int device, void* stream) {
+  if (!out) return fail(TRAP_EINVAL, "null output pointer");
+  *out = nullptr;
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess || ndev == 0) {
+    (void)hipGetLastError();
+    return fail(TRAP_EDEVICE, "no HIP device available");
+  }
+  if (device < 0 || device >= ndev) return fail(TRAP_EINVAL, "device index out of range");
+  trap_ctx* ctx = new (std::nothrow) trap_ctx();
+  if (!ctx) return fail(TRAP_ENOMEM, "host allocation failed");
+  ctx->device = device;
+  ctx->stream = static_cast<hipStream_t>(stream);
+  *out = ctx;
+  return TRAP_OK;
+}
+
+int trap_destroy(trap_ctx* ctx) {
+  if (!ctx) return TRAP_OK;
+  DeviceGuard g(ctx->device);
+  free_all(ctx);
+  delete ctx;
+  return TRAP_OK;
+}
+
+int trap_set_problem(trap_ctx* ctx, const trap_atom_desc* atom, const trap_problem_desc* prob) {
+  if (!ctx) return fail(TRAP_EINVAL, "null context");
+  DeviceGuard g(ctx->device);
+  free_all(ctx);
+  int s = build_problem(ctx, atom, prob);
+  if (s != TRAP_OK) {
+    std::string msg = g_last_error;
+    free_all(ctx);
+    return fail(s, msg);
+  }
+  if (ctx->pb.nl > 8 || ctx->pb.nu > 16) {
+    free_all(ctx);
+    return fail(TRAP_EINVAL, "atom too large (at most 16 upper and 8 lower sublevels)");
+  }
+  hipError_t e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) {
+    free_all(ctx);
+    return fail(TRAP_EDEVICE, std::string("upload: ") + hipGetErrorString(e));
+  }
+  ctx->has_problem = true;
+  return TRAP_OK;
+}
+
+int trap_precompute(trap_ctx* ctx, int store_mask) {
+  if (!ctx) return fail(TRAP_EINVAL, "null context");
+  if (!ctx->has_problem) return fail(TRAP_ESTATE, "no problem loaded");
+  if (store_mask & ~3) return fail(TRAP_EINVAL, "store_mask has unknown bits");
+  DeviceGuard g(ctx->device);
+  return run_precompute(ctx, store_mask);
+}
+
+int trap_apply_sigma(trap_ctx* ctx, const void* I, void* eps, int prec, int add_thermal) {
+  if (!ctx) return fail(TRAP_EINVAL, "null context");
+  DeviceGuard g(ctx->device);
+  return sigma_apply(ctx, I, eps, prec, add_thermal, 1);
+}
+
+int trap_formal_solve(trap_ctx* ctx, const void* eps, void* I, int with_boundary, int prec) {
+  if (!ctx) return fail(TRAP_EINVAL, "null context");
+  DeviceGuard g(ctx->device);
+  return formal_apply(ctx, eps, I, with_boundary, prec);
+}
+
+int trap_apply_operator(trap_ctx* ctx, const void* x, void* y, int prec) {
+  if (!ctx) return fail(TRAP_EINVAL, "null context");
+  if (!ctx->has_problem || !ctx->pre.done) return fail(TRAP_ESTATE, "precompute not run");
+  if (!x || !y) return fail(TRAP_EINVAL, "null vector");
+  DeviceGuard g(ctx->device);
+  return operator_apply(ctx, x, y, prec);
+}
+
+int trap_rhs(trap_ctx* ctx, double* b_out) {
+  if (!ctx) return fail(TRAP_EINVAL, "null context");
+  if (!ctx->has_problem || !ctx->pre.done) return fail(TRAP_ESTATE, "precompute not run");
+  if (!b_out) return fail(TRAP_EINVAL, "null vector");
+  DeviceGuard g(ctx->device);
+  const size_t N = 4ull * ctx->pb.nz * ctx->pb.nd * ctx->pb.nn;
+  TRAP_HIP(hipMemcpyAsync(b_out, ctx->pre.d_b, N * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+  return TRAP_OK;
+}
+
+int trap_gmres_solve(trap_ctx* ctx, const trap_solve_opts* opts, double* I, trap_solve_stats* stats) {
+  if (!ctx) return fail(TRAP_EINVAL, "null context");
+  DeviceGuard g(ctx->device);
+  return gmres_solve(ctx, opts, I, stats);
+}
+
+int trap_emergent(trap_ctx* ctx, const double* I, double* host_out) {
+  if (!ctx) return fail(TRAP_EINVAL, "null context");
+  if (!ctx->has_problem) return fail(TRAP_ESTATE, "no problem loaded");
+  if (!I || !host_out) return fail(TRAP_EINVAL, "null pointer");
+  DeviceGuard g(ctx->device);
+  const Problem& P = ctx->pb;
+  const size_t rec = (size_t)P.nn * 4;
+  const double* top = I + (size_t)(P.nz - 1) * P.nd * rec;
+  size_t k = 0;
+  for (int o = 0; o < P.nd; ++o) {
+    if (P.mu[o] <= 0.0) continue;
+    TRAP_HIP(hipMemcpyAsync(host_out + k * rec, top + (size_t)o * rec, rec * sizeof(double),
+                            hipMemcpyDeviceToHost, ctx->stream));
+    ++k;
+  }
+  TRAP_HIP(hipStreamSynchronize(ctx->stream));
+  return TRAP_OK;
+}
+
+int trap_get_info(const trap_ctx* ctx, trap_info* info) {
+  if (!ctx || !info) return fail(TRAP_EINVAL, "null argument");
+  if (!ctx->has_problem) return fail(TRAP_ESTATE, "no problem loaded");
+  const Problem& P = ctx->pb;
+  std::memset(info, 0, sizeof(*info));
+  info->n_z = P.nz;
+  info->n_nu = P.nn;
+  info->n_dir = P.nd;
+  info->n_theta = P.nth;
+  info->n_slots = P.nslot;
+  info->n_up = P.nu;
+  info->n_lo = P.nl;
+  info->n_trans = P.nt;
+  info->n_unknowns = 4ull * P.nz * P.nd * P.nn;
+  const double kel = (double)P.nz * P.nth * P.nt * 2.0 * P.nn * P.nn;
+  info->bytes_kernel_fp64 = (size_t)(kel * 8);
+  info->bytes_kernel_fp32 = (size_t)(kel * 4);
+  size_t tot = 0;
+  for (auto& b : ctx->bufs) tot += b.bytes;
+  info->bytes_device_total = tot;
+  // per complex kernel entry: 4 Stokes columns x (real, imag) multiply-adds = 16 flops per slot
+  info->flops_contraction = 16.0 * P.nz * P.nt * (double)P.nn * P.nn * P.nslot;
+  // algorithmic bytes: every kernel entry read once, Ibar read, W written once
+  const double wbytes = (double)P.nz * P.nt * P.nslot * 2.0 * P.nn * 4;
+  const double ibytes = (double)P.nz * P.nd * P.nn * 4;
+  info->bytes_contraction_fp64 = 8.0 * (kel + wbytes + ibytes);
+  info->bytes_contraction_fp32 = 4.0 * (kel + wbytes + ibytes);
+  return TRAP_OK;
+}
+
+int trap_footprint(const trap_atom_desc* atom, const trap_problem_desc* prob, int store_mask,
+                   size_t* bytes) {
+  if (!bytes) return fail(TRAP_EINVAL, "null output");
+  int err = 0;
+  *bytes = estimate_bytes(atom, prob, store_mask, &err);
+  if (err) return fail(TRAP_EINVAL, "bad problem description");
+  return TRAP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,158 @@
+// Formal solution Lambda (paper Sect. 3): per ray (Omega, nu) a sweep along z,
+// upward rays from the bottom (boundary (W_T(z_min), 0, 0, 0)), downward rays
+// from the top (no incoming radiation).  Trapezoidal optical depth
+//   dtau = (r_k + r_{k+1})/2 |tau_line(z_k) - tau_line(z_{k+1})| / |mu|,
+// r = eta_I/eta_0, and DELO-linear steps
+//   (Id + psi_c K'_c) I_c = (e^{-dtau} Id - psi_u K'_u) I_u + psi_u S_u + psi_c S_c,
+// K' = K/eta_I - Id, S = eps/eta_I.  The weights
+//   psi_u = [1 - e^{-x}(1 + x)]/x,  psi_c = [x - 1 + e^{-x}]/x
+// cancel catastrophically for small x; below a precision-dependent threshold
+// (0.1 in FP64, 1 in FP32) they are summed from their Taylor series
+//   psi_u = sum_{m>=2} (-1)^m (m-1) x^(m-1)/m!,  psi_c = sum_{m>=2} (-1)^m x^(m-1)/m!.
+// One thread per ray; arithmetic in the vector precision T.
+#include <cmath>
+
+#include "trap_internal.h"
+
+namespace trap {
+
+template <typename T>
+__device__ inline void delo_weights(T x, T& pu, T& pc, T& ex) {
+  ex = exp(-x);
+  const T thr = sizeof(T) == 8 ? T(0.1) : T(1.0);
+  if (x < thr) {
+    // Horner-free accumulation with factorial recursion, 20 terms
+    T p = x, fac = T(2), su = T(0), sc = T(0), sgn = T(1);
+    for (int m = 2; m < 22; ++m) {
+      if (m > 2) fac *= T(m);
+      su += sgn * T(m - 1) * p / fac;
+      sc += sgn * p / fac;
+      p *= x;
+      sgn = -sgn;
+    }
+    pu = su;
+    pc = sc;
+  } else {
+    pu = (T(1) - ex * (T(1) + x)) / x;
+    pc = (x - T(1) + ex) / x;
+  }
+}
+
+// y = K' v with K' = [[0,kQ,kU,kV],[kQ,0,rV,-rU],[kU,-rV,0,rQ],[kV,rU,-rQ,0]]
+template <typename T>
+__device__ inline void kprime_mul(const T* k, const T* v, T* y) {
+  y[0] = k[0] * v[1] + k[1] * v[2] + k[2] * v[3];
+  y[1] = k[0] * v[0] + k[5] * v[2] - k[4] * v[3];
+  y[2] = k[1] * v[0] - k[5] * v[1] + k[3] * v[3];
+  y[3] = k[2] * v[0] + k[4] * v[1] - k[3] * v[2];
+}
+
+// solve (Id + p K') x = b, 4x4 Gaussian elimination with partial pivoting
+template <typename T>
+__device__ inline void delo_solve(const T* k, T p, const T* b, T* xout) {
+  T A[4][5];
+  A[0][0] = T(1); A[0][1] = p * k[0]; A[0][2] = p * k[1]; A[0][3] = p * k[2];
+  A[1][0] = p * k[0]; A[1][1] = T(1); A[1][2] = p * k[5]; A[1][3] = -p * k[4];
+  A[2][0] = p * k[1]; A[2][1] = -p * k[5]; A[2][2] = T(1); A[2][3] = p * k[3];
+  A[3][0] = p * k[2]; A[3][1] = p * k[4]; A[3][2] = -p * k[3]; A[3][3] = T(1);
+  for (int i = 0; i < 4; ++i) A[i][4] = b[i];
+  for (int c = 0; c < 4; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < 4; ++r)
+      if (fabs(A[r][c]) > fabs(A[piv][c])) piv = r;
+    if (piv != c)
+      for (int j = 0; j < 5; ++j) {
+        const T tmp = A[c][j];
+        A[c][j] = A[piv][j];
+        A[piv][j] = tmp;
+      }
+    const T inv = T(1) / A[c][c];
+    for (int r = c + 1; r < 4; ++r) {
+      const T fct = A[r][c] * inv;
+      for (int j = c; j < 5; ++j) A[r][j] -= fct * A[c][j];
+    }
+  }
+  for (int i = 3; i >= 0; --i) {
+    T v = A[i][4];
+    for (int j = i + 1; j < 4; ++j) v -= A[i][j] * xout[j];
+    xout[i] = v / A[i][i];
+  }
+}
+
+template <typename T>
+__global__ void k_formal(int nz, int nd, int nn, const double* __restrict__ mu,
+                         const double* __restrict__ tau, const double* __restrict__ K8,
+                         const double* __restrict__ WT, const T* __restrict__ eps, T* __restrict__ I,
+                         int with_boundary) {
+  const int id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= nd * nn) return;
+  const int o = id / nn, n = id % nn;
+  const double m = mu[o];
+  const bool up = m > 0.0;
+  const T amu = T(fabs(m));
+  const long long zs = (long long)nd * nn;          // point stride between heights
+  auto pidx = [&](int z) { return (long long)z * zs + (long long)o * nn + n; };
+  int z = up ? 0 : nz - 1;
+  const int dz = up ? 1 : -1;
+  T Icur[4] = {T(0), T(0), T(0), T(0)};
+  if (up && with_boundary) Icur[0] = T(WT[0]);
+  T ku[6], Su[4], ru;
+  {
+    const long long p = pidx(z);
+    const double* k = K8 + p * 8;
+    for (int i = 0; i < 6; ++i) ku[i] = T(k[i]);
+    const T inv = T(k[6]);
+    ru = T(k[7]);
+    for (int s = 0; s < 4; ++s) Su[s] = eps[p * 4 + s] * inv;
+    for (int s = 0; s < 4; ++s) I[p * 4 + s] = Icur[s];
+  }
+  for (int step = 1; step < nz; ++step) {
+    const int zc = z + dz;
+    const long long p = pidx(zc);
+    const double* k = K8 + p * 8;
+    T kc[6], Sc[4];
+    for (int i = 0; i < 6; ++i) kc[i] = T(k[i]);
+    const T inv = T(k[6]);
+    const T rc = T(k[7]);
+    for (int s = 0; s < 4; ++s) Sc[s] = eps[p * 4 + s] * inv;
+    const T x = T(0.5) * (ru + rc) * T(fabs(tau[z] - tau[zc])) / amu;
+    T pu, pc, ex;
+    delo_weights<T>(x, pu, pc, ex);
+    T kv[4], b[4];
+    kprime_mul<T>(ku, Icur, kv);
+    for (int s = 0; s < 4; ++s) b[s] = ex * Icur[s] - pu * kv[s] + pu * Su[s] + pc * Sc[s];
+    T Inew[4];
+    delo_solve<T>(kc, pc, b, Inew);
+    for (int s = 0; s < 4; ++s) {
+      Icur[s] = Inew[s];
+      I[p * 4 + s] = Inew[s];
+      Su[s] = Sc[s];
+    }
+    for (int i = 0; i < 6; ++i) ku[i] = kc[i];
+    ru = rc;
+    z = zc;
+  }
+}
+
+int formal_apply(trap_ctx* ctx, const void* eps, void* I, int with_boundary, int prec) {
+  if (!ctx->has_problem) return fail(TRAP_ESTATE, "no problem loaded");
+  if (!ctx->pre.d_K) return fail(TRAP_ESTATE, "precompute not run");
+  if (!eps || !I) return fail(TRAP_EINVAL, "null vector");
+  Problem& P = ctx->pb;
+  const int rays = P.nd * P.nn;
+  if (prec == TRAP_FP64) {
+    hipLaunchKernelGGL(k_formal<double>, dim3(ceil_div(rays, 64)), dim3(64), 0, ctx->stream, P.nz, P.nd,
+                       P.nn, P.d_mu, P.d_tau, ctx->pre.d_K, P.d_WT, static_cast<const double*>(eps),
+                       static_cast<double*>(I), with_boundary);
+  } else if (prec == TRAP_FP32) {
+    hipLaunchKernelGGL(k_formal<float>, dim3(ceil_div(rays, 64)), dim3(64), 0, ctx->stream, P.nz, P.nd,
+                       P.nn, P.d_mu, P.d_tau, ctx->pre.d_K, P.d_WT, static_cast<const float*>(eps),
+                       static_cast<float*>(I), with_boundary);
+  } else {
+    return fail(TRAP_EINVAL, "unknown precision");
+  }
+  TRAP_HIP(hipGetLastError());
+  return TRAP_OK;
+}
+
+}  // namespace trap

@@ -1,0 +1,600 @@
+// Host-side problem setup in FP64: grids, scattering-angle table, sublevel
+// structure and dipole vectors, coefficient tables, spline coefficient map.
+//
+// Physics (paper Sects. 2.2-2.3, App. B, Sect. 6.1):
+//  * dnu_D(z) = (nu0/c) sqrt(2 k T/M + xi^2); u = x lam(z), lam = dnu_D_ref/dnu_D.
+//  * a = (G_R + G_I + G_E)/(4 pi dnu_D), eps = G_I/(G_R + G_I), G_E = r_E (G_R + G_I).
+//  * alpha_{u u'} = G_R/(G_R+G_I+G_E + 2 pi i nu_{u u'}),
+//    beta_{u u'}  = G_R/(G_R+G_I + 2 pi i nu_{u u'}).
+//  * Upper term: zeta (L.S + c) + nu_L (M_L + 2 M_S) in the uncoupled basis
+//    (Paschen-Back), diagonalised per height; lower term nu_L (M_L + 2 M_S);
+//    two-level atom: nu_L g M.  Dipoles from the Wigner-Eckart theorem on L.
+//  * Stokes tensors Acart_j = sum_ab (A_j)_ab e_a e_b^T with
+//    A = (1, sigma_z, sigma_x, -sigma_y) in the (e_a, e_b) ray basis.
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <numeric>
+
+#include "faddeeva.h"
+#include "trap_internal.h"
+
+namespace trap {
+
+namespace {
+
+using cd = std::complex<double>;
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kC = 2.99792458e10;
+constexpr double kKB = 1.380649e-16;
+constexpr double kAMU = 1.66053906660e-24;
+constexpr double kLarmorPerG = 1.39962449361e6;
+
+// ---------------------------------------------------------------- Gauss-Legendre on [0,1]
+void gauss_legendre01(int n, std::vector<double>& t, std::vector<double>& w) {
+  t.assign(n, 0.0);
+  w.assign(n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    double z = std::cos(kPi * (i + 0.75) / (n + 0.5));
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= n; ++k) {
+        double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      double pn = (n == 1) ? z : p1;
+      double pm = (n == 1) ? 1.0 : p0;
+      double dp = n * (z * pn - pm) / (z * z - 1.0);
+      double dz = pn / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) {
+        // final derivative for the weight
+        p0 = 1.0;
+        p1 = z;
+        for (int k = 2; k <= n; ++k) {
+          double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+          p0 = p1;
+          p1 = p2;
+        }
+        pn = (n == 1) ? z : p1;
+        pm = (n == 1) ? 1.0 : p0;
+        dp = n * (z * pn - pm) / (z * z - 1.0);
+        t[i] = 0.5 * (1.0 - z);                       // ascending on [0,1]
+        w[i] = 1.0 / ((1.0 - z * z) * dp * dp);       // half of the [-1,1] weight
+        break;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- Wigner 3j (Racah formula)
+double lfact(int n) { return std::lgamma(n + 1.0); }
+
+double wigner3j(double j1, double j2, double j3, double m1, double m2, double m3) {
+  auto I = [](double v) { return static_cast<int>(std::lround(v)); };
+  if (std::fabs(m1 + m2 + m3) > 1e-9) return 0.0;
+  if (std::fabs(m1) > j1 + 1e-9 || std::fabs(m2) > j2 + 1e-9 || std::fabs(m3) > j3 + 1e-9) return 0.0;
+  if (j3 > j1 + j2 + 1e-9 || j3 < std::fabs(j1 - j2) - 1e-9) return 0.0;
+  const int a1 = I(j1 + j2 - j3), a2 = I(j1 - j2 + j3), a3 = I(-j1 + j2 + j3), a4 = I(j1 + j2 + j3 + 1);
+  double ltri = 0.5 * (lfact(a1) + lfact(a2) + lfact(a3) - lfact(a4));
+  double lm = 0.5 * (lfact(I(j1 + m1)) + lfact(I(j1 - m1)) + lfact(I(j2 + m2)) + lfact(I(j2 - m2)) +
+                     lfact(I(j3 + m3)) + lfact(I(j3 - m3)));
+  int kmin = std::max({0, I(j2 - j3 - m1), I(j1 - j3 + m2)});
+  int kmax = std::min({I(j1 + j2 - j3), I(j1 - m1), I(j2 + m2)});
+  double sum = 0.0;
+  for (int k = kmin; k <= kmax; ++k) {
+    double ld = lfact(k) + lfact(I(j3 - j2 + k + m1)) + lfact(I(j3 - j1 + k - m2)) +
+                lfact(I(j1 + j2 - j3 - k)) + lfact(I(j1 - k - m1)) + lfact(I(j2 - k + m2));
+    sum += ((k & 1) ? -1.0 : 1.0) * std::exp(ltri + lm - ld);
+  }
+  int ph = I(j1 - j2 - m3);
+  return ((ph & 1) ? -1.0 : 1.0) * sum;
+}
+
+// ---------------------------------------------------------------- Jacobi eigensolver (real symmetric)
+void jacobi_eigen(int n, std::vector<double> A, std::vector<double>& evals, std::vector<double>& V) {
+  V.assign(n * n, 0.0);
+  for (int i = 0; i < n; ++i) V[i * n + i] = 1.0;
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) off += A[p * n + q] * A[p * n + q];
+    if (off < 1e-300) break;
+    for (int p = 0; p < n; ++p) {
+      for (int q = p + 1; q < n; ++q) {
+        double apq = A[p * n + q];
+        if (std::fabs(apq) < 1e-300) continue;
+        double theta = (A[q * n + q] - A[p * n + p]) / (2.0 * apq);
+        double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+        double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+        for (int k = 0; k < n; ++k) {
+          double akp = A[k * n + p], akq = A[k * n + q];
+          A[k * n + p] = c * akp - s * akq;
+          A[k * n + q] = s * akp + c * akq;
+        }
+        for (int k = 0; k < n; ++k) {
+          double apk = A[p * n + k], aqk = A[q * n + k];
+          A[p * n + k] = c * apk - s * aqk;
+          A[q * n + k] = s * apk + c * aqk;
+        }
+        for (int k = 0; k < n; ++k) {
+          double vkp = V[k * n + p], vkq = V[k * n + q];
+          V[k * n + p] = c * vkp - s * vkq;
+          V[k * n + q] = s * vkp + c * vkq;
+        }
+      }
+    }
+  }
+  // sort ascending, eigenvectors in columns of V
+  std::vector<int> idx(n);
+  std::iota(idx.begin(), idx.end(), 0);
+  std::sort(idx.begin(), idx.end(), [&](int i, int j) { return A[i * n + i] < A[j * n + j]; });
+  evals.resize(n);
+  std::vector<double> Vs(n * n);
+  for (int c = 0; c < n; ++c) {
+    evals[c] = A[idx[c] * n + idx[c]];
+    for (int r = 0; r < n; ++r) Vs[r * n + c] = V[r * n + idx[c]];
+  }
+  V.swap(Vs);
+}
+
+struct TermBasis {
+  std::vector<double> ml, ms;
+};
+
+TermBasis term_basis(double L, double S) {
+  TermBasis b;
+  for (int i = 0; i <= static_cast<int>(std::lround(2 * L)); ++i)
+    for (int j = 0; j <= static_cast<int>(std::lround(2 * S)); ++j) {
+      b.ml.push_back(-L + i);
+      b.ms.push_back(-S + j);
+    }
+  return b;
+}
+
+std::vector<double> term_hamiltonian(const TermBasis& b, double L, double S, double zeta,
+                                     double shift, double nuL, double gL, double gS) {
+  const int n = static_cast<int>(b.ml.size());
+  std::vector<double> H(n * n, 0.0);
+  for (int a = 0; a < n; ++a) {
+    H[a * n + a] = zeta * (b.ml[a] * b.ms[a] + shift) + nuL * (gL * b.ml[a] + gS * b.ms[a]);
+    for (int c = 0; c < n; ++c) {
+      // (L+ S- + L- S+)/2 between |ml, ms> (column a) and |ml', ms'> (row c)
+      if (std::fabs(b.ml[c] - b.ml[a] - 1) < 1e-9 && std::fabs(b.ms[c] - b.ms[a] + 1) < 1e-9) {
+        double v = std::sqrt(L * (L + 1) - b.ml[a] * (b.ml[a] + 1)) *
+                   std::sqrt(S * (S + 1) - b.ms[a] * (b.ms[a] - 1));
+        H[c * n + a] += 0.5 * zeta * v;
+      }
+      if (std::fabs(b.ml[c] - b.ml[a] + 1) < 1e-9 && std::fabs(b.ms[c] - b.ms[a] - 1) < 1e-9) {
+        double v = std::sqrt(L * (L + 1) - b.ml[a] * (b.ml[a] - 1)) *
+                   std::sqrt(S * (S + 1) - b.ms[a] * (b.ms[a] + 1));
+        H[c * n + a] += 0.5 * zeta * v;
+      }
+    }
+  }
+  return H;
+}
+
+struct Sublevels {
+  std::vector<double> Eu, El;       // Hz relative to nu0
+  std::vector<cd> d;                // [nu][nl][3] atmospheric frame
+  double c_abs = 0, c_sc = 0;
+};
+
+Sublevels sublevels(const trap_atom_desc& at, double Bg, double thB, double chB, double dnuD_ref) {
+  Sublevels s;
+  const double nuL = kLarmorPerG * Bg;
+  double Lu, Ll, S, zeta = 0.0, shift = 0.0, gLu, gSu, gLl, gSl;
+  if (at.kind == 0) {
+    Lu = at.J_u;
+    Ll = at.J_l;
+    S = 0.0;
+    gLu = at.g_u;
+    gSu = 0.0;
+    gLl = at.g_l;
+    gSl = 0.0;
+  } else {
+    Lu = at.L_u;
+    Ll = at.L_l;
+    S = at.S;
+    auto ls = [&](double J) { return 0.5 * (J * (J + 1) - Lu * (Lu + 1) - S * (S + 1)); };
+    double Jhi = Lu + S, Jlo = std::fabs(Lu - S);
+    double gap = ls(Jhi) - ls(Jlo);
+    zeta = (gap != 0.0) ? at.fs_split_x * dnuD_ref / gap : 0.0;
+    shift = -0.5 * (ls(Jhi) + ls(Jlo));
+    gLu = 1.0;
+    gSu = 2.0;
+    gLl = 1.0;
+    gSl = 2.0;
+  }
+  TermBasis bu = term_basis(Lu, S), bl = term_basis(Ll, S);
+  const int nu = static_cast<int>(bu.ml.size()), nl = static_cast<int>(bl.ml.size());
+  std::vector<double> Vu, Vl;
+  jacobi_eigen(nu, term_hamiltonian(bu, Lu, S, zeta, shift, nuL, gLu, gSu), s.Eu, Vu);
+  jacobi_eigen(nl, term_hamiltonian(bl, Ll, S, 0.0, 0.0, nuL, gLl, gSl), s.El, Vl);
+  // spherical components q = -1, 0, 1 in the uncoupled basis
+  std::vector<double> Dq(3 * nu * nl, 0.0);
+  for (int a = 0; a < nu; ++a)
+    for (int b = 0; b < nl; ++b) {
+      if (std::fabs(bu.ms[a] - bl.ms[b]) > 1e-9) continue;
+      for (int iq = 0; iq < 3; ++iq) {
+        const double q = iq - 1.0;
+        const int ph = static_cast<int>(std::lround(Lu - bu.ml[a]));
+        Dq[(iq * nu + a) * nl + b] =
+            std::sqrt(3.0) * ((ph & 1) ? -1.0 : 1.0) * wigner3j(Lu, 1.0, Ll, -bu.ml[a], q, bl.ml[b]);
+      }
+    }
+  // magnetic-frame unit vectors in the atmospheric frame
+  const double st = std::sin(thB), ct = std::cos(thB), sc = std::sin(chB), cc = std::cos(chB);
+  const double xB[3] = {ct * cc, ct * sc, -st}, yB[3] = {-sc, cc, 0.0}, zB[3] = {st * cc, st * sc, ct};
+  // e_q^* for q = -1, 0, +1 (e_{+-1} = -+(x + i y)/sqrt2 -> conj)
+  const double r2 = 1.0 / std::sqrt(2.0);
+  cd econj[3][3];
+  for (int k = 0; k < 3; ++k) {
+    econj[0][k] = cd(xB[k] * r2, -yB[k] * r2);     // e_{-1}^* = (x - i y)^*/sqrt2 ... see below
+    econj[1][k] = cd(zB[k], 0.0);
+    econj[2][k] = cd(-xB[k] * r2, yB[k] * r2);
+  }
+  // e_{-1} = (x - i y)/sqrt2 -> conj = (x + i y)/sqrt2 ; e_{+1} = -(x + i y)/sqrt2 -> conj = -(x - i y)/sqrt2
+  for (int k = 0; k < 3; ++k) {
+    econj[0][k] = cd(xB[k] * r2, yB[k] * r2);
+    econj[2][k] = cd(-xB[k] * r2, yB[k] * r2);
+  }
+  s.d.assign(nu * nl * 3, cd(0.0, 0.0));
+  for (int ku = 0; ku < nu; ++ku)
+    for (int kl = 0; kl < nl; ++kl) {
+      for (int iq = 0; iq < 3; ++iq) {
+        double val = 0.0;   // <u_ku| D_q | l_kl> with real eigenvectors
+        for (int a = 0; a < nu; ++a) {
+          if (Vu[a * nu + ku] == 0.0) continue;
+          for (int b = 0; b < nl; ++b) val += Vu[a * nu + ku] * Dq[(iq * nu + a) * nl + b] * Vl[b * nl + kl];
+        }
+        for (int k = 0; k < 3; ++k) s.d[(ku * nl + kl) * 3 + k] += val * econj[iq][k];
+      }
+    }
+  double tot = 0.0;
+  std::vector<double> Du(nu, 0.0);
+  for (int ku = 0; ku < nu; ++ku)
+    for (int kl = 0; kl < nl; ++kl)
+      for (int k = 0; k < 3; ++k) {
+        double v = std::norm(s.d[(ku * nl + kl) * 3 + k]);
+        tot += v;
+        Du[ku] += v;
+      }
+  s.c_abs = 3.0 / tot;
+  s.c_sc = 3.0 * s.c_abs / (2.0 * Du[0]);
+  return s;
+}
+
+// d1^T Acart_j d2^* with Acart_j = sum_ab (A_j)_ab e_a e_b^T
+cd stokes_form(int j, const cd* d1, const cd* d2, const double* ea, const double* eb) {
+  cd pa1(0, 0), pb1(0, 0), pa2(0, 0), pb2(0, 0);
+  for (int k = 0; k < 3; ++k) {
+    pa1 += d1[k] * ea[k];
+    pb1 += d1[k] * eb[k];
+    pa2 += std::conj(d2[k]) * ea[k];
+    pb2 += std::conj(d2[k]) * eb[k];
+  }
+  const cd I(0.0, 1.0);
+  switch (j) {
+    case 0: return pa1 * pa2 + pb1 * pb2;
+    case 1: return pa1 * pa2 - pb1 * pb2;
+    case 2: return pa1 * pb2 + pb1 * pa2;
+    default: return I * pa1 * pb2 - I * pb1 * pa2;
+  }
+}
+
+// Not-a-knot cubic spline coefficient map on nodes x: on interval k with
+// t = (y - x_k)/h_k the interpolant of values v is sum_p P[k][p][m] v_m t^p.
+std::vector<double> spline_map(const std::vector<double>& x) {
+  const int n = static_cast<int>(x.size());
+  std::vector<double> h(n - 1);
+  for (int k = 0; k < n - 1; ++k) h[k] = x[k + 1] - x[k];
+  // system for second derivatives s (n unknowns), RHS = R v (n x n)
+  std::vector<double> A(n * n, 0.0), R(n * n, 0.0);
+  // not-a-knot at the left: (s1 - s0)/h0 = (s2 - s1)/h1
+  A[0 * n + 0] = -h[1];
+  A[0 * n + 1] = h[0] + h[1];
+  A[0 * n + 2] = -h[0];
+  for (int k = 1; k < n - 1; ++k) {
+    A[k * n + k - 1] = h[k - 1];
+    A[k * n + k] = 2.0 * (h[k - 1] + h[k]);
+    A[k * n + k + 1] = h[k];
+    R[k * n + k + 1] += 6.0 / h[k];
+    R[k * n + k] += -6.0 / h[k] - 6.0 / h[k - 1];
+    R[k * n + k - 1] += 6.0 / h[k - 1];
+  }
+  A[(n - 1) * n + n - 3] = -h[n - 2];
+  A[(n - 1) * n + n - 2] = h[n - 3] + h[n - 2];
+  A[(n - 1) * n + n - 1] = -h[n - 3];
+  // solve A S = R by Gaussian elimination with partial pivoting
+  std::vector<double> S = R;
+  std::vector<double> M = A;
+  for (int c = 0; c < n; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < n; ++r)
+      if (std::fabs(M[r * n + c]) > std::fabs(M[piv * n + c])) piv = r;
+    if (piv != c)
+      for (int k = 0; k < n; ++k) {
+        std::swap(M[c * n + k], M[piv * n + k]);
+        std::swap(S[c * n + k], S[piv * n + k]);
+      }
+    for (int r = c + 1; r < n; ++r) {
+      double f = M[r * n + c] / M[c * n + c];
+      if (f == 0.0) continue;
+      for (int k = c; k < n; ++k) M[r * n + k] -= f * M[c * n + k];
+      for (int k = 0; k < n; ++k) S[r * n + k] -= f * S[c * n + k];
+    }
+  }
+  for (int c = n - 1; c >= 0; --c) {
+    for (int k = 0; k < n; ++k) {
+      double v = S[c * n + k];
+      for (int j = c + 1; j < n; ++j) v -= M[c * n + j] * S[j * n + k];
+      S[c * n + k] = v / M[c * n + c];
+    }
+  }
+  // S[i][m] = d s_i / d v_m.  Coefficients in t:
+  //   c0 = v_k, c1 = v_{k+1} - v_k - h^2 (2 s_k + s_{k+1})/6, c2 = h^2 s_k/2, c3 = h^2 (s_{k+1} - s_k)/6
+  std::vector<double> P((n - 1) * 4 * n, 0.0);
+  for (int k = 0; k < n - 1; ++k) {
+    const double h2 = h[k] * h[k];
+    for (int m = 0; m < n; ++m) {
+      const double sk = S[k * n + m], sk1 = S[(k + 1) * n + m];
+      const double vk = (m == k) ? 1.0 : 0.0, vk1 = (m == k + 1) ? 1.0 : 0.0;
+      P[(k * 4 + 0) * n + m] = vk;
+      P[(k * 4 + 1) * n + m] = vk1 - vk - h2 * (2.0 * sk + sk1) / 6.0;
+      P[(k * 4 + 2) * n + m] = 0.5 * h2 * sk;
+      P[(k * 4 + 3) * n + m] = h2 * (sk1 - sk) / 6.0;
+    }
+  }
+  return P;
+}
+
+}  // namespace
+
+size_t estimate_bytes(const trap_atom_desc* atom, const trap_problem_desc* pd, int store_mask, int* err) {
+  *err = 0;
+  if (!atom || !pd || pd->n_z < 2 || pd->n_nu < 4 || pd->n_mu < 2 || pd->n_mu % 2 || pd->n_chi < 1) {
+    *err = 1;
+    return 0;
+  }
+  const size_t nz = pd->n_z, nn = pd->n_nu, nd = static_cast<size_t>(pd->n_mu) * pd->n_chi;
+  size_t nu, nl;
+  if (atom->kind == 0) {
+    nu = static_cast<size_t>(std::lround(2 * atom->J_u)) + 1;
+    nl = static_cast<size_t>(std::lround(2 * atom->J_l)) + 1;
+  } else {
+    nu = (2 * atom->L_u + 1) * static_cast<size_t>(std::lround(2 * atom->S) + 1);
+    nl = (2 * atom->L_l + 1) * static_cast<size_t>(std::lround(2 * atom->S) + 1);
+  }
+  const size_t nt = nu * nl;
+  const size_t nth = nd * nd;     // upper bound for the scattering-angle count
+  size_t b = 0;
+  const size_t ker = nz * nth / 4 * nt * 2 * nn * nn;   // typical N_Theta ~ N_dir^2/40..1/4
+  if (store_mask & 1) b += ker * 8;
+  if (store_mask & 2) b += ker * 4;
+  const size_t N = 4 * nz * nd * nn;
+  b += N * 8 * 48;                // vectors, Krylov basis (restart 40), tables
+  b += nz * nd * nd * nt * 16 * 2; // E/A tables
+  return b;
+}
+
+int build_problem(trap_ctx* ctx, const trap_atom_desc* at, const trap_problem_desc* pd) {
+  if (!at || !pd) return fail(TRAP_EINVAL, "null descriptor");
+  if (pd->n_z < 2 || pd->n_nu < 4 || pd->n_mu < 2 || (pd->n_mu & 1) || pd->n_chi < 1)
+    return fail(TRAP_EINVAL, "grid sizes: need n_z>=2, n_nu>=4, even n_mu>=2, n_chi>=1");
+  if (!pd->x || !pd->tau_line || !pd->T || !pd->a || !pd->eps || !pd->W_T || !pd->v || !pd->B)
+    return fail(TRAP_EINVAL, "missing atmosphere array");
+  if (at->kind != 0 && at->kind != 1) return fail(TRAP_EINVAL, "atom kind must be 0 or 1");
+  if (!(at->lambda0_A > 0) || !(at->mass_amu > 0)) return fail(TRAP_EINVAL, "bad atomic constants");
+  Problem& P = ctx->pb;
+  P = Problem();
+  P.nz = pd->n_z;
+  P.nn = pd->n_nu;
+  P.nmu = pd->n_mu;
+  P.nchi = pd->n_chi;
+  P.nd = P.nmu * P.nchi;
+  const int nz = P.nz, nn = P.nn, nd = P.nd;
+  P.x.assign(pd->x, pd->x + nn);
+  for (int k = 0; k + 1 < nn; ++k)
+    if (!(P.x[k + 1] > P.x[k])) return fail(TRAP_EINVAL, "frequency nodes must increase");
+  if (!(P.x[0] < 0.0 && P.x[nn - 1] > 0.0)) return fail(TRAP_EINVAL, "frequency grid must bracket 0");
+  P.tau.assign(pd->tau_line, pd->tau_line + nz);
+  for (int z = 0; z < nz; ++z) {
+    if (!(P.tau[z] > 0.0) || !std::isfinite(P.tau[z])) return fail(TRAP_EINVAL, "tau_line must be > 0");
+    if (z > 0 && !(P.tau[z] < P.tau[z - 1])) return fail(TRAP_EINVAL, "tau_line must decrease upward");
+    if (!(pd->a[z] > 0.0) || !std::isfinite(pd->a[z])) return fail(TRAP_EINVAL, "damping must be > 0");
+    if (!(pd->eps[z] >= 0.0 && pd->eps[z] <= 1.0)) return fail(TRAP_EINVAL, "eps must be in [0,1]");
+    if (!(pd->T[z] > 0.0)) return fail(TRAP_EINVAL, "temperature must be > 0");
+    if (!std::isfinite(pd->W_T[z])) return fail(TRAP_EINVAL, "W_T not finite");
+    for (int k = 0; k < 3; ++k)
+      if (!std::isfinite(pd->v[3 * z + k]) || !std::isfinite(pd->B[3 * z + k]))
+        return fail(TRAP_EINVAL, "velocity/field not finite");
+  }
+  // ---- per-height scalars
+  const double nu0 = kC / (at->lambda0_A * 1e-8);
+  const double mass = at->mass_amu * kAMU;
+  const double Tref = pd->T_ref > 0 ? pd->T_ref : 6000.0;
+  const double dnuD_ref = nu0 * std::sqrt(2.0 * kKB * Tref / mass) / kC;
+  P.lam.resize(nz);
+  P.a.assign(pd->a, pd->a + nz);
+  P.eps.assign(pd->eps, pd->eps + nz);
+  P.WT.assign(pd->W_T, pd->W_T + nz);
+  P.eta0.resize(nz);
+  P.dnuD.resize(nz);
+  std::vector<double> vth(nz);
+  for (int z = 0; z < nz; ++z) {
+    const double xi = pd->xi ? pd->xi[z] * 1e5 : 0.0;
+    vth[z] = std::sqrt(2.0 * kKB * pd->T[z] / mass + xi * xi);
+    P.dnuD[z] = nu0 * vth[z] / kC;
+    P.lam[z] = dnuD_ref / P.dnuD[z];
+    P.eta0[z] = std::exp(P.a[z] * P.a[z]) * std::erfc(P.a[z]) / std::sqrt(kPi);
+  }
+  // ---- angular grid (double Gauss-Legendre x trapezoid)
+  std::vector<double> gt, gw;
+  gauss_legendre01(P.nmu / 2, gt, gw);
+  std::vector<double> mu1, wmu1;
+  for (int i = P.nmu / 2 - 1; i >= 0; --i) {
+    mu1.push_back(-gt[i]);
+    wmu1.push_back(gw[i]);
+  }
+  for (int i = 0; i < P.nmu / 2; ++i) {
+    mu1.push_back(gt[i]);
+    wmu1.push_back(gw[i]);
+  }
+  P.mu.resize(nd);
+  P.w.resize(nd);
+  std::vector<double> dirs(3 * nd), ea(3 * nd), eb(3 * nd);
+  for (int i = 0; i < P.nmu; ++i)
+    for (int k = 0; k < P.nchi; ++k) {
+      const int o = i * P.nchi + k;
+      const double chi = 2.0 * kPi * k / P.nchi, mu = mu1[i], st = std::sqrt(1.0 - mu * mu);
+      P.mu[o] = mu;
+      P.w[o] = wmu1[i] / (2.0 * P.nchi);
+      dirs[3 * o + 0] = st * std::cos(chi);
+      dirs[3 * o + 1] = st * std::sin(chi);
+      dirs[3 * o + 2] = mu;
+      ea[3 * o + 0] = -std::sin(chi);
+      ea[3 * o + 1] = std::cos(chi);
+      ea[3 * o + 2] = 0.0;
+      // e_b = Omega x e_a
+      eb[3 * o + 0] = dirs[3 * o + 1] * ea[3 * o + 2] - dirs[3 * o + 2] * ea[3 * o + 1];
+      eb[3 * o + 1] = dirs[3 * o + 2] * ea[3 * o + 0] - dirs[3 * o + 0] * ea[3 * o + 2];
+      eb[3 * o + 2] = dirs[3 * o + 0] * ea[3 * o + 1] - dirs[3 * o + 1] * ea[3 * o + 0];
+    }
+  // ---- scattering-angle table and slots
+  std::vector<double> cosv(nd * nd);
+  for (int o = 0; o < nd; ++o)
+    for (int i = 0; i < nd; ++i) {
+      double c = dirs[3 * o] * dirs[3 * i] + dirs[3 * o + 1] * dirs[3 * i + 1] + dirs[3 * o + 2] * dirs[3 * i + 2];
+      c = std::min(1.0, std::max(-1.0, c));
+      if (std::fabs(c - 1.0) < 1e-12) c = 1.0;
+      if (std::fabs(c + 1.0) < 1e-12) c = -1.0;
+      cosv[o * nd + i] = c;
+    }
+  std::vector<double> sorted(cosv);
+  std::sort(sorted.begin(), sorted.end(), std::greater<double>());
+  std::vector<double> reps{sorted[0]};
+  for (size_t k = 1; k < sorted.size(); ++k)
+    if (reps.back() - sorted[k] > 1e-10) reps.push_back(sorted[k]);
+  P.nth = static_cast<int>(reps.size());
+  P.theta.resize(P.nth);
+  for (int t = 0; t < P.nth; ++t) {
+    P.theta[t] = (reps[t] == 1.0) ? 0.0 : (reps[t] == -1.0 ? kPi : std::acos(reps[t]));
+  }
+  P.pair_theta.resize(nd * nd);
+  for (int k = 0; k < nd * nd; ++k) {
+    int best = 0;
+    for (int t = 1; t < P.nth; ++t)
+      if (std::fabs(reps[t] - cosv[k]) < std::fabs(reps[best] - cosv[k])) best = t;
+    P.pair_theta[k] = best;
+  }
+  // slots: for each theta the incoming directions that occur with it
+  std::vector<std::vector<int>> used(P.nth, std::vector<int>(nd, -1));
+  for (int o = 0; o < nd; ++o)
+    for (int i = 0; i < nd; ++i) used[P.pair_theta[o * nd + i]][i] = 1;
+  P.slot_off.assign(P.nth + 1, 0);
+  P.slot_dir.clear();
+  std::vector<int> slot_theta;
+  for (int t = 0; t < P.nth; ++t) {
+    P.slot_off[t] = static_cast<int>(P.slot_dir.size());
+    for (int i = 0; i < nd; ++i)
+      if (used[t][i] == 1) {
+        used[t][i] = static_cast<int>(P.slot_dir.size());
+        P.slot_dir.push_back(i);
+        slot_theta.push_back(t);
+      }
+    P.max_slots_per_theta = std::max(P.max_slots_per_theta,
+                                     static_cast<int>(P.slot_dir.size()) - P.slot_off[t]);
+  }
+  P.slot_off[P.nth] = static_cast<int>(P.slot_dir.size());
+  P.nslot = static_cast<int>(P.slot_dir.size());
+  P.pair_slot.resize(nd * nd);
+  for (int o = 0; o < nd; ++o)
+    for (int i = 0; i < nd; ++i) P.pair_slot[o * nd + i] = used[P.pair_theta[o * nd + i]][i];
+  // ---- sublevels per height
+  std::vector<Sublevels> sub(nz);
+  for (int z = 0; z < nz; ++z)
+    sub[z] = sublevels(*at, pd->B[3 * z], pd->B[3 * z + 1], pd->B[3 * z + 2], dnuD_ref);
+  P.nu = static_cast<int>(sub[0].Eu.size());
+  P.nl = static_cast<int>(sub[0].El.size());
+  P.nt = P.nu * P.nl;
+  P.c_abs = sub[0].c_abs;
+  P.c_sc = sub[0].c_sc;
+  const int nu = P.nu, nl = P.nl, nt = P.nt;
+  std::vector<double> st(nz * nt), sll(nz * nl * nl), ub(nz * nd), g(nz * nt * nd * 4);
+  std::vector<double2> alpha(nz * nu * nu), bma(nz * nu * nu);
+  std::vector<double2> E(static_cast<size_t>(nz) * nd * 4 * nu * nu * nl);
+  std::vector<double2> A(static_cast<size_t>(nz) * nd * 4 * nu * nu * nl);
+  const double rE = at->r_E;
+  for (int z = 0; z < nz; ++z) {
+    const Sublevels& s = sub[z];
+    for (int u = 0; u < nu; ++u)
+      for (int l = 0; l < nl; ++l) st[z * nt + u * nl + l] = (s.Eu[u] - s.El[l]) / P.dnuD[z];
+    for (int l = 0; l < nl; ++l)
+      for (int lp = 0; lp < nl; ++lp) sll[(z * nl + l) * nl + lp] = (s.El[l] - s.El[lp]) / P.dnuD[z];
+    const double gtot = 4.0 * kPi * P.a[z] * P.dnuD[z];
+    const double gri = gtot / (1.0 + rE);
+    const double gr = (1.0 - P.eps[z]) * gri;
+    for (int u = 0; u < nu; ++u)
+      for (int up = 0; up < nu; ++up) {
+        const double nuuu = s.Eu[u] - s.Eu[up];
+        const cd al = gr / cd(gtot, 2.0 * kPi * nuuu);
+        const cd be = gr / cd(gri, 2.0 * kPi * nuuu);
+        alpha[(z * nu + u) * nu + up] = make_double2(al.real(), al.imag());
+        bma[(z * nu + u) * nu + up] = make_double2((be - al).real(), (be - al).imag());
+      }
+    for (int o = 0; o < nd; ++o) {
+      const double vdot = pd->v[3 * z] * dirs[3 * o] + pd->v[3 * z + 1] * dirs[3 * o + 1] +
+                          pd->v[3 * z + 2] * dirs[3 * o + 2];
+      ub[z * nd + o] = vdot * 1e5 / vth[z];
+      for (int t = 0; t < nt; ++t)
+        for (int j = 0; j < 4; ++j) {
+          const cd* dt = &s.d[t * 3];
+          g[((z * nt + t) * nd + o) * 4 + j] = stokes_form(j, dt, dt, &ea[3 * o], &eb[3 * o]).real();
+        }
+      for (int i = 0; i < 4; ++i)
+        for (int up = 0; up < nu; ++up)
+          for (int u = 0; u < nu; ++u)
+            for (int l = 0; l < nl; ++l) {
+              // E[z][o][i][u'][u][l'] with l' = l here
+              const cd e = stokes_form(i, &s.d[(up * nl + l) * 3], &s.d[(u * nl + l) * 3], &ea[3 * o], &eb[3 * o]);
+              E[((((static_cast<size_t>(z) * nd + o) * 4 + i) * nu + up) * nu + u) * nl + l] = make_double2(e.real(), e.imag());
+              // A[z][o][j][u][u'][l] with (u, u') = (up, u) index order: first upper index u
+              const cd aa = 0.5 * stokes_form(i, &s.d[(up * nl + l) * 3], &s.d[(u * nl + l) * 3], &ea[3 * o], &eb[3 * o]);
+              A[((((static_cast<size_t>(z) * nd + o) * 4 + i) * nu + up) * nu + u) * nl + l] = make_double2(aa.real(), aa.imag());
+            }
+    }
+  }
+  // ---- upload
+  auto spl = spline_map(P.x);
+  int nsl = P.nslot;
+  (void)nsl;
+  TRAP_TRY(upload_t(ctx, &P.d_x, P.x));
+  TRAP_TRY(upload_t(ctx, &P.d_P, spl));
+  TRAP_TRY(upload_t(ctx, &P.d_mu, P.mu));
+  TRAP_TRY(upload_t(ctx, &P.d_w, P.w));
+  TRAP_TRY(upload_t(ctx, &P.d_tau, P.tau));
+  TRAP_TRY(upload_t(ctx, &P.d_lam, P.lam));
+  TRAP_TRY(upload_t(ctx, &P.d_a, P.a));
+  TRAP_TRY(upload_t(ctx, &P.d_eps, P.eps));
+  TRAP_TRY(upload_t(ctx, &P.d_WT, P.WT));
+  TRAP_TRY(upload_t(ctx, &P.d_eta0, P.eta0));
+  TRAP_TRY(upload_t(ctx, &P.d_ub, ub));
+  TRAP_TRY(upload_t(ctx, &P.d_st, st));
+  TRAP_TRY(upload_t(ctx, &P.d_sll, sll));
+  TRAP_TRY(upload_t(ctx, &P.d_theta, P.theta));
+  TRAP_TRY(upload_t(ctx, &P.d_slot_theta, slot_theta));
+  TRAP_TRY(upload_t(ctx, &P.d_slot_dir, P.slot_dir));
+  TRAP_TRY(upload_t(ctx, &P.d_slot_off, P.slot_off));
+  TRAP_TRY(upload_t(ctx, &P.d_pair_slot, P.pair_slot));
+  TRAP_TRY(upload_t(ctx, &P.d_E, E));
+  TRAP_TRY(upload_t(ctx, &P.d_A, A));
+  TRAP_TRY(upload_t(ctx, &P.d_alpha, alpha));
+  TRAP_TRY(upload_t(ctx, &P.d_bma, bma));
+  TRAP_TRY(upload_t(ctx, &P.d_g, g));
+  return TRAP_OK;
+}
+
+}  // namespace trap

@@ -1,0 +1,433 @@
+// Sigma apply (paper Sect. 4.1-4.3, App. D, App. E), per precision T:
+//   1. comoving field Ibar(u_m) = S[I](u_m - u_b(Omega'))          k_spline_shift
+//   2. W_{t,j}(slot, n) = sum_m M[z][theta(slot)][t][n][m] Ibar_j(dir(slot), m)
+//                                                               k_contract
+//   3. R_III incoming factors Y and their angular sums X           k_r3_Y, k_r3_X
+//   4. eps_bar_i(o, n; l, l') = Re sum_{o', u'} sum_j C_ij W_{u' l, j}
+//        + R_III outer product                                     k_angular
+//      with C^{u' l, l'}_ij(o, o') = (c_sc w_o'/pi) sum_u alpha_{u u'}
+//        E_i(o; u', u, l') A_j(o'; u, u', l)  (the [G(u') + G(u)*] pairing of
+//      Eq. RQIIKKp folded into a real part)
+//   5. eps = sum_{l,l'} S[eps_bar(.; l, l')](u_n + u_b(Omega) + u_{l l'}),
+//      times f on Stokes I, plus eps_th if asked                  k_spline_shift
+// Heights are processed in chunks so the W intermediate of a chunk stays
+// bounded (and cache resident on the 256 MB Infinity Cache for small chunks).
+#include <algorithm>
+#include <cmath>
+
+#include "trap_internal.h"
+
+namespace trap {
+
+static constexpr double kInvPi = 0.31830988618379067154;
+
+// ------------------------------------------------------------------ spline evaluation
+// out[z][o][n][s] (+)= scale * S[in[z][o][:][s]](x_n + shift(z,o)) for the
+// given class, flat extension outside [x_0, x_{nn-1}].
+//   in:  stride between (z,o) records = in_zo_stride, node stride 4
+//   shift (x units) = (sign * ub[z][o] + sll[z][cls]) / lam[z]
+template <typename T>
+__global__ void k_spline_shift(int nz0, int nzc, int nd, int nn, const double* __restrict__ x,
+                               const double* __restrict__ P, const double* __restrict__ lam,
+                               const double* __restrict__ ub, double ub_sign,
+                               const double* __restrict__ sll, int ncls, int cls,
+                               const T* __restrict__ in, long long in_z_stride, long long in_o_stride,
+                               T* __restrict__ out, int accumulate, const double* __restrict__ f,
+                               const double* __restrict__ epsth) {
+  const long long id = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  const long long total = (long long)nzc * nd * nn;
+  if (id >= total) return;
+  const int n = id % nn;
+  const int o = (id / nn) % nd;
+  const int zl = id / ((long long)nn * nd);
+  const int z = nz0 + zl;
+  const double L = lam[z];
+  double sh = ub_sign * ub[(long long)z * nd + o];
+  if (sll) sh += sll[(long long)z * ncls + cls];
+  const double xs = x[n] + sh / L;
+  const T* src = in + zl * in_z_stride + o * in_o_stride;
+  double v[4];
+  if (sh == 0.0) {
+    for (int s = 0; s < 4; ++s) v[s] = (double)src[n * 4 + s];
+  } else if (xs <= x[0]) {
+    for (int s = 0; s < 4; ++s) v[s] = (double)src[s];
+  } else if (xs >= x[nn - 1]) {
+    for (int s = 0; s < 4; ++s) v[s] = (double)src[(nn - 1) * 4 + s];
+  } else {
+    int lo = 0, hi = nn - 1;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (x[mid] <= xs) lo = mid; else hi = mid;
+    }
+    const int k = lo;
+    const double t = (xs - x[k]) / (x[k + 1] - x[k]);
+    const double t2 = t * t, t3 = t2 * t;
+    const double* pk = P + (size_t)k * 4 * nn;
+    for (int s = 0; s < 4; ++s) v[s] = 0.0;
+    for (int m = 0; m < nn; ++m) {
+      const double wgt = pk[m] + t * pk[nn + m] + t2 * pk[2 * nn + m] + t3 * pk[3 * nn + m];
+      for (int s = 0; s < 4; ++s) v[s] += wgt * (double)src[m * 4 + s];
+    }
+  }
+  T* dst = out + id * 4;
+  if (f) v[0] *= f[(long long)z * nd * nn + (long long)o * nn + n];
+  if (epsth) {
+    const double* e = epsth + ((long long)z * nd * nn + (long long)o * nn + n) * 4;
+    for (int s = 0; s < 4; ++s) v[s] += e[s];
+  }
+  if (accumulate) {
+    for (int s = 0; s < 4; ++s) dst[s] = (T)((double)dst[s] + v[s]);
+  } else {
+    for (int s = 0; s < 4; ++s) dst[s] = (T)v[s];
+  }
+}
+
+// ------------------------------------------------------------------ R_II contraction
+// Batched GEMM per (z in chunk, theta, t):
+//   C[(c, n), (sl, s)] = sum_m M[z][theta][t][c][n][m] * Ibar[z][dir(sl)][m][s]
+// rows 2*nn (real plane then imaginary plane), columns 4 * nslots(theta).
+// 64x64 output tile per 256-thread block, 4x4 per thread, K staged by 16.
+template <typename T>
+__global__ void __launch_bounds__(256) k_contract(int z0, int nth, int nt, int nn, int nd,
+                                                  const T* __restrict__ M, const T* __restrict__ Ibar,
+                                                  const int* __restrict__ slot_off,
+                                                  const int* __restrict__ slot_dir, T* __restrict__ W,
+                                                  int nslot) {
+  __shared__ T As[16][64 + 1];
+  __shared__ T Bs[16][64 + 1];
+  const int batch = blockIdx.z;
+  const int t = batch % nt;
+  const int th = (batch / nt) % nth;
+  const int zl = batch / (nt * nth);
+  const int z = z0 + zl;
+  const int s0 = slot_off[th], ns = slot_off[th + 1] - s0;
+  const int ncol = 4 * ns, nrow = 2 * nn;
+  const int col0 = blockIdx.x * 64, row0 = blockIdx.y * 64;
+  if (col0 >= ncol) return;
+  const T* Mb = M + ((((size_t)z * nth + th) * nt + t) * 2) * (size_t)nn * nn;   // [2nn][nn]
+  const T* Ib = Ibar + (size_t)zl * nd * nn * 4;
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  T acc[4][4];
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) acc[i][j] = T(0);
+  for (int k0 = 0; k0 < nn; k0 += 16) {
+    // A tile: rows row0..row0+63, k k0..k0+15
+    for (int e = threadIdx.x; e < 64 * 16; e += 256) {
+      const int r = e >> 4, kk = e & 15;
+      const int gr = row0 + r, gk = k0 + kk;
+      As[kk][r] = (gr < nrow && gk < nn) ? Mb[(size_t)gr * nn + gk] : T(0);
+    }
+    // B tile: k rows, cols col0..col0+63 = (slot, s)
+    for (int e = threadIdx.x; e < 64 * 16; e += 256) {
+      const int kk = e >> 6, c = e & 63;
+      const int gc = col0 + c, gk = k0 + kk;
+      T v = T(0);
+      if (gc < ncol && gk < nn) {
+        const int sl = gc >> 2, s = gc & 3;
+        const int dir = slot_dir[s0 + sl];
+        v = Ib[((size_t)dir * nn + gk) * 4 + s];
+      }
+      Bs[kk][c] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+      T a[4], b[4];
+      for (int i = 0; i < 4; ++i) a[i] = As[kk][ty * 4 + i];
+      for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tx * 4 + j];
+      for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) acc[i][j] += a[i] * b[j];
+    }
+    __syncthreads();
+  }
+  // store: W[zl][t][slot][c][n][s]
+  for (int i = 0; i < 4; ++i) {
+    const int gr = row0 + ty * 4 + i;
+    if (gr >= nrow) continue;
+    const int c = gr >= nn ? 1 : 0, n = gr - c * nn;
+    for (int j = 0; j < 4; ++j) {
+      const int gc = col0 + tx * 4 + j;
+      if (gc >= ncol) continue;
+      const int sl = s0 + (gc >> 2), s = gc & 3;
+      W[((((size_t)zl * nt + t) * nslot + sl) * 2 + c) * (size_t)nn * 4 + (size_t)n * 4 + s] = acc[i][j];
+    }
+  }
+}
+
+// ------------------------------------------------------------------ R_III factors
+// Y[z][t][o][s] = sum_m r3[z][t][m] Ibar[z][o][m][s]
+template <typename T>
+__global__ void k_r3_Y(int z0, int nzc, int nt, int nd, int nn, const double2* __restrict__ r3,
+                       const T* __restrict__ Ibar, double2* __restrict__ Y) {
+  const long long id = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  const long long total = (long long)nzc * nt * nd * 4;
+  if (id >= total) return;
+  const int s = id & 3;
+  const int o = (id >> 2) % nd;
+  const int t = (id / (4LL * nd)) % nt;
+  const int zl = id / (4LL * nd * nt);
+  const int z = z0 + zl;
+  const double2* r = r3 + ((size_t)z * nt + t) * nn;
+  const T* I = Ibar + ((size_t)zl * nd + o) * nn * 4 + s;
+  double re = 0.0, im = 0.0;
+  for (int m = 0; m < nn; ++m) {
+    const double v = (double)I[(size_t)m * 4];
+    re += r[m].x * v;
+    im += r[m].y * v;
+  }
+  Y[(((size_t)z * nt + t) * nd + o) * 4 + s] = make_double2(re, im);
+}
+
+// X[z][u][u'][l] = sum_o' w_o' sum_j A[z][o'][j][u][u'][l] (Y[(u',l)][o'][j] + conj Y[(u,l)][o'][j])
+__global__ void k_r3_X(int z0, int nu, int nl, int nd, const double* __restrict__ w,
+                       const double2* __restrict__ A, const double2* __restrict__ Y,
+                       double2* __restrict__ X) {
+  const int e = blockIdx.x;   // (zl, u, up, l)
+  const int l = e % nl;
+  const int up = (e / nl) % nu;
+  const int u = (e / (nl * nu)) % nu;
+  const int zl = e / (nl * nu * nu);
+  const int z = z0 + zl;
+  const int nt = nu * nl;
+  double re = 0.0, im = 0.0;
+  for (int k = threadIdx.x; k < nd * 4; k += blockDim.x) {
+    const int o = k >> 2, j = k & 3;
+    const double2 a = A[((((size_t)z * nd + o) * 4 + j) * nu + u) * nu * nl + (size_t)up * nl + l];
+    const double2 y1 = Y[(((size_t)z * nt + up * nl + l) * nd + o) * 4 + j];
+    const double2 y2 = Y[(((size_t)z * nt + u * nl + l) * nd + o) * 4 + j];
+    const double2 yy = make_double2(y1.x + y2.x, y1.y - y2.y);
+    re += w[o] * (a.x * yy.x - a.y * yy.y);
+    im += w[o] * (a.x * yy.y + a.y * yy.x);
+  }
+  __shared__ double sr[256], si[256];
+  sr[threadIdx.x] = re;
+  si[threadIdx.x] = im;
+  __syncthreads();
+  for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+    if (threadIdx.x < st) {
+      sr[threadIdx.x] += sr[threadIdx.x + st];
+      si[threadIdx.x] += si[threadIdx.x + st];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) X[((((size_t)z * nu + u) * nu + up) * nl) + l] = make_double2(sr[0], si[0]);
+}
+
+// ------------------------------------------------------------------ angular / sublevel sum
+// One block per (zl, o, n-block of blockDim); one frequency per thread.
+// Eb[zl][l][l'][o][n][i].
+template <typename T>
+__global__ void __launch_bounds__(128) k_angular(
+    int z0, int nd, int nn, int nu, int nl, int nslot, double c_sc, const double* __restrict__ w,
+    const double2* __restrict__ E, const double2* __restrict__ A, const double2* __restrict__ alpha,
+    const double2* __restrict__ bma, const int* __restrict__ pair_slot, const T* __restrict__ W,
+    const double2* __restrict__ X, const double2* __restrict__ prof, T* __restrict__ Eb, int do_RII) {
+  extern __shared__ double2 sh[];
+  const int zl = blockIdx.x / nd, o = blockIdx.x % nd;
+  const int z = z0 + zl;
+  const int n = blockIdx.y * blockDim.x + threadIdx.x;
+  const bool active = n < nn;
+  const int nt = nu * nl;
+  double2* Cs = sh;                           // [nl(l')][4][4]
+  double2* Ds = sh + nl * 16;                 // [nl(l')][4][nu][nu]  R_III coefficients
+  const double2* Ez = E + ((size_t)z * nd + o) * 4 * nu * nu * nl;
+  for (int l = 0; l < nl; ++l) {
+    double acc[8][4];      // [l'][i], nl <= 8
+    for (int a = 0; a < 8; ++a)
+      for (int i = 0; i < 4; ++i) acc[a][i] = 0.0;
+    if (do_RII) {
+      for (int op = 0; op < nd; ++op) {
+        const int sl = pair_slot[o * nd + op];
+        const double2* Az = A + ((size_t)z * nd + op) * 4 * nu * nu * nl;
+        const double sc = c_sc * w[op] * kInvPi;
+        for (int upr = 0; upr < nu; ++upr) {
+          __syncthreads();
+          for (int e = threadIdx.x; e < nl * 16; e += blockDim.x) {
+            const int lp = e >> 4, i = (e >> 2) & 3, j = e & 3;
+            double re = 0.0, im = 0.0;
+            for (int u = 0; u < nu; ++u) {
+              const double2 al = alpha[((size_t)z * nu + u) * nu + upr];
+              const double2 ee = Ez[((size_t)(i * nu + upr) * nu + u) * nl + lp];
+              const double2 aa = Az[((size_t)(j * nu + u) * nu + upr) * nl + l];
+              const double2 ea = cmul(ee, aa);
+              const double2 v = cmul(al, ea);
+              re += v.x;
+              im += v.y;
+            }
+            Cs[e] = make_double2(sc * re, sc * im);
+          }
+          __syncthreads();
+          const int t = upr * nl + l;
+          const T* Wp = W + (((size_t)zl * nt + t) * nslot + sl) * 2 * (size_t)nn * 4;
+          if (active) {
+            double wr[4], wi[4];
+            for (int j = 0; j < 4; ++j) {
+              wr[j] = (double)Wp[(size_t)n * 4 + j];
+              wi[j] = (double)Wp[(size_t)nn * 4 + (size_t)n * 4 + j];
+            }
+            for (int lp = 0; lp < nl; ++lp)
+              for (int i = 0; i < 4; ++i) {
+                double v = 0.0;
+                for (int j = 0; j < 4; ++j) {
+                  const double2 c = Cs[(lp * 4 + i) * 4 + j];
+                  v += c.x * wr[j] - c.y * wi[j];
+                }
+                acc[lp][i] += v;
+              }
+          }
+        }
+      }
+    }
+    // R_III: D[l'][i][u][u'] = c_sc/(4 pi) (beta-alpha)_{u u'} E_i(u', u, l') X[u][u'][l]
+    __syncthreads();
+    for (int e = threadIdx.x; e < nl * 4 * nu * nu; e += blockDim.x) {
+      const int upr = e % nu, u = (e / nu) % nu, i = (e / (nu * nu)) % 4, lp = e / (4 * nu * nu);
+      const double2 b = bma[((size_t)z * nu + u) * nu + upr];
+      const double2 ee = Ez[((size_t)(i * nu + upr) * nu + u) * nl + lp];
+      const double2 xx = X[(((size_t)z * nu + u) * nu + upr) * nl + l];
+      const double2 v = cmul(b, cmul(ee, xx));
+      const double sc = c_sc * 0.25 * kInvPi;
+      Ds[e] = make_double2(sc * v.x, sc * v.y);
+    }
+    __syncthreads();
+    if (active) {
+      for (int lp = 0; lp < nl; ++lp)
+        for (int i = 0; i < 4; ++i) {
+          double v = 0.0;
+          for (int u = 0; u < nu; ++u)
+            for (int upr = 0; upr < nu; ++upr) {
+              const double2 d = Ds[((lp * 4 + i) * nu + u) * nu + upr];
+              const double2 p1 = prof[((size_t)z * nt + upr * nl + l) * nn + n];
+              const double2 p2 = prof[((size_t)z * nt + u * nl + l) * nn + n];
+              const double pr = p1.x + p2.x, pim = p1.y - p2.y;
+              v += d.x * pr - d.y * pim;
+            }
+          acc[lp][i] += v;
+        }
+      for (int lp = 0; lp < nl; ++lp) {
+        T* dst = Eb + ((((size_t)zl * nl + l) * nl + lp) * nd + o) * (size_t)nn * 4 + (size_t)n * 4;
+        for (int i = 0; i < 4; ++i) dst[i] = (T)acc[lp][i];
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------ driver
+static size_t elem_size(int prec) { return prec == TRAP_FP64 ? sizeof(double) : sizeof(float); }
+
+int ensure_work(trap_ctx* ctx, int prec) {
+  Problem& P = ctx->pb;
+  Work& K = ctx->wk;
+  const size_t nz = P.nz, nd = P.nd, nn = P.nn;
+  const size_t N = 4 * nz * nd * nn;
+  if (!K.tmp64) {
+    TRAP_TRY(dalloc_t(ctx, &K.tmp64, N));
+    TRAP_TRY(dalloc_t(ctx, &K.r, N));
+    TRAP_TRY(dalloc_t(ctx, &K.x, N));
+    TRAP_TRY(dalloc_t(ctx, &K.Y, nz * P.nt * nd * 4));
+    TRAP_TRY(dalloc_t(ctx, &K.X, nz * P.nu * P.nu * P.nl));
+    TRAP_TRY(dalloc_t(ctx, &K.red, 4096));
+    // height chunk: keep one chunk of W (FP64) within ~1 GiB
+    const size_t per_z = (size_t)P.nt * P.nslot * 2 * nn * 4 * sizeof(double);
+    K.zchunk = (int)std::max<size_t>(1, std::min<size_t>(nz, (size_t(1) << 30) / std::max<size_t>(per_z, 1)));
+  }
+  const int pi = prec == TRAP_FP64 ? 0 : 1;
+  if (!K.W[pi]) {
+    const size_t es = elem_size(prec);
+    const size_t zc = K.zchunk;
+    TRAP_TRY(dalloc(ctx, &K.Ibar[pi], zc * nd * nn * 4 * es));
+    TRAP_TRY(dalloc(ctx, &K.W[pi], zc * P.nt * P.nslot * 2 * nn * 4 * es));
+    TRAP_TRY(dalloc(ctx, &K.Eb[pi], nz * P.nl * P.nl * nd * nn * 4 * es));
+    TRAP_TRY(dalloc(ctx, &K.tmp[pi], N * es));
+    TRAP_TRY(dalloc(ctx, &K.opeps[pi], N * es));
+  }
+  return TRAP_OK;
+}
+
+template <typename T>
+static int sigma_apply_t(trap_ctx* ctx, const T* I, T* eps, int prec, int add_thermal, int normalize,
+                         const T* Mk) {
+  Problem& P = ctx->pb;
+  Precomp& C = ctx->pre;
+  Work& K = ctx->wk;
+  hipStream_t s = ctx->stream;
+  const int pi = prec == TRAP_FP64 ? 0 : 1;
+  const int nz = P.nz, nd = P.nd, nn = P.nn, nt = P.nt, nth = P.nth, nl = P.nl, nu = P.nu;
+  T* Ibar = static_cast<T*>(K.Ibar[pi]);
+  T* W = static_cast<T*>(K.W[pi]);
+  T* Eb = static_cast<T*>(K.Eb[pi]);
+  const int ncls = nl * nl;
+  for (int z0 = 0; z0 < nz; z0 += K.zchunk) {
+    const int zc = std::min(K.zchunk, nz - z0);
+    const long long npts = (long long)zc * nd * nn;
+    // 1. comoving interpolation
+    hipLaunchKernelGGL(k_spline_shift<T>, dim3(ceil_div(npts, 256)), dim3(256), 0, s, z0, zc, nd, nn,
+                       P.d_x, P.d_P, P.d_lam, P.d_ub, -1.0, (const double*)nullptr, 1, 0,
+                       I + (size_t)z0 * nd * nn * 4, (long long)nd * nn * 4, (long long)nn * 4, Ibar, 0,
+                       (const double*)nullptr, (const double*)nullptr);
+    TRAP_HIP(hipGetLastError());
+    // 2. contraction
+    dim3 grid(ceil_div(4LL * P.max_slots_per_theta, 64), ceil_div(2LL * nn, 64), zc * nth * nt);
+    hipLaunchKernelGGL(k_contract<T>, grid, dim3(256), 0, s, z0, nth, nt, nn, nd, Mk, Ibar, P.d_slot_off,
+                       P.d_slot_dir, W, P.nslot);
+    TRAP_HIP(hipGetLastError());
+    // 3. R_III factors
+    const long long ny = (long long)zc * nt * nd * 4;
+    hipLaunchKernelGGL(k_r3_Y<T>, dim3(ceil_div(ny, 256)), dim3(256), 0, s, z0, zc, nt, nd, nn, C.d_r3,
+                       Ibar, K.Y);
+    TRAP_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_r3_X, dim3(zc * nu * nu * nl), dim3(256), 0, s, z0, nu, nl, nd, P.d_w, P.d_A,
+                       K.Y, K.X);
+    TRAP_HIP(hipGetLastError());
+    // 4. angular / sublevel sum into Eb (chunk-local heights)
+    const size_t shb = (size_t)(nl * 16 + nl * 4 * nu * nu) * sizeof(double2);
+    hipLaunchKernelGGL(k_angular<T>, dim3(zc * nd, ceil_div(nn, 128)), dim3(128), shb, s, z0, nd, nn, nu, nl, P.nslot,
+                       P.c_sc, P.d_w, P.d_E, P.d_A, P.d_alpha, P.d_bma, P.d_pair_slot, W, K.X, C.d_prof,
+                       Eb + (size_t)z0 * ncls * nd * nn * 4, 1);
+    TRAP_HIP(hipGetLastError());
+  }
+  // 5. back to the observer frame, per (l, l') class, f and eps_th
+  const long long npts = (long long)nz * nd * nn;
+  for (int l = 0; l < nl; ++l)
+    for (int lp = 0; lp < nl; ++lp) {
+      const int cls = l * nl + lp;
+      const bool first = (cls == 0), last = (cls == ncls - 1);
+      // f multiplies the sum over classes: apply it on a separate pass when ncls > 1
+      hipLaunchKernelGGL(k_spline_shift<T>, dim3(ceil_div(npts, 256)), dim3(256), 0, s, 0, nz, nd, nn,
+                         P.d_x, P.d_P, P.d_lam, P.d_ub, 1.0, P.d_sll, ncls, cls,
+                         Eb + (size_t)cls * nd * nn * 4, (long long)ncls * nd * nn * 4, (long long)nn * 4,
+                         eps, first ? 0 : 1, (normalize && ncls == 1) ? C.d_f : (const double*)nullptr,
+                         (add_thermal && last && ncls == 1) ? C.d_epsth : (const double*)nullptr);
+      TRAP_HIP(hipGetLastError());
+    }
+  if (ncls > 1 && (normalize || add_thermal)) {
+    // eps <- f * eps (Stokes I) + eps_th : reuse the shift kernel with zero shift on a copy
+    T* tmp = static_cast<T*>(K.tmp[pi]);
+    TRAP_HIP(hipMemcpyAsync(tmp, eps, (size_t)npts * 4 * sizeof(T), hipMemcpyDeviceToDevice, s));
+    hipLaunchKernelGGL(k_spline_shift<T>, dim3(ceil_div(npts, 256)), dim3(256), 0, s, 0, nz, nd, nn,
+                       P.d_x, P.d_P, P.d_lam, P.d_ub, 0.0, (const double*)nullptr, 1, 0, tmp,
+                       (long long)nd * nn * 4, (long long)nn * 4, eps, 0,
+                       normalize ? C.d_f : (const double*)nullptr,
+                       add_thermal ? C.d_epsth : (const double*)nullptr);
+    TRAP_HIP(hipGetLastError());
+  }
+  return TRAP_OK;
+}
+
+int sigma_apply(trap_ctx* ctx, const void* I, void* eps, int prec, int add_thermal, int normalize) {
+  if (!ctx->has_problem) return fail(TRAP_ESTATE, "no problem loaded");
+  if (!ctx->pre.done) return fail(TRAP_ESTATE, "precompute not run");
+  if (prec != TRAP_FP64 && prec != TRAP_FP32) return fail(TRAP_EINVAL, "unknown precision");
+  if (!I || !eps) return fail(TRAP_EINVAL, "null vector");
+  TRAP_TRY(ensure_work(ctx, prec));
+  if (prec == TRAP_FP64) {
+    if (!ctx->pre.d_M64) return fail(TRAP_ESTATE, "FP64 kernels not stored");
+    return sigma_apply_t<double>(ctx, static_cast<const double*>(I), static_cast<double*>(eps), prec,
+                                 add_thermal, normalize, ctx->pre.d_M64);
+  }
+  if (!ctx->pre.d_M32) return fail(TRAP_ESTATE, "FP32 kernels not stored (store_mask bit 1)");
+  return sigma_apply_t<float>(ctx, static_cast<const float*>(I), static_cast<float*>(eps), prec,
+                              add_thermal, normalize, ctx->pre.d_M32);
+}
+
+}  // namespace trap

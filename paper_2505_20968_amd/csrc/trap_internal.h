@@ -1,0 +1,160 @@
+// Internal definitions of the trap library: context layout, error helpers,
+// launch helpers and small device utilities shared by the kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/trap.h"
+
+namespace trap {
+
+// ---------------------------------------------------------------- errors
+void set_error(const std::string& msg);
+int fail(int code, const std::string& msg);
+
+#define TRAP_HIP(call)                                                              \
+  do {                                                                              \
+    hipError_t e_ = (call);                                                         \
+    if (e_ != hipSuccess)                                                           \
+      return ::trap::fail(TRAP_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+#define TRAP_TRY(call)              \
+  do {                              \
+    int s_ = (call);                \
+    if (s_ != TRAP_OK) return s_;   \
+  } while (0)
+
+// ---------------------------------------------------------------- complex helpers
+struct cplx { double re, im; };
+
+__host__ __device__ inline double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__host__ __device__ inline double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
+__host__ __device__ inline double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+
+// ---------------------------------------------------------------- device buffer
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+// ---------------------------------------------------------------- context
+// Index conventions (all row-major, last index fastest):
+//   vectors        V[z][o][n][s]
+//   spline map     P[k][p][m]      interval k (0..nn-2), power p of t=(x-x_k)/h_k, node m
+//   kernels        M[z][theta][t][c][n][m]   c = 0 real / 1 imaginary, row n, column m (ld = nn)
+//   W intermediate W[zc][t][slot][c][n][s]   (height chunk zc)
+//   eps_bar        Eb[z][l][l'][o][n][s]
+//   E table        E[z][o][i][u'][u][l']   = d_{u'l'}^T Acart_i(o) d^*_{u l'}
+//   A table        A[z][o'][j][u][u'][l]   = d_{u l}^T Acart_j(o')/2 d^*_{u' l}
+//   transitions    t = u * n_lo + l
+struct Problem {
+  int nz = 0, nn = 0, nmu = 0, nchi = 0, nd = 0;
+  int nth = 0, nslot = 0, nu = 0, nl = 0, nt = 0;
+  int max_slots_per_theta = 0;
+  double c_abs = 0, c_sc = 0;
+  // host copies used by host-side logic
+  std::vector<double> x, mu, w, tau, lam, a, eps, WT, eta0, dnuD;
+  std::vector<double> theta;               // [nth]
+  std::vector<int> slot_off;               // [nth+1]
+  std::vector<int> slot_dir;               // [nslot]
+  std::vector<int> pair_slot;              // [nd][nd] slot of (theta(o,i), i)
+  std::vector<int> pair_theta;             // [nd][nd]
+  // device copies
+  double *d_x = nullptr, *d_P = nullptr, *d_mu = nullptr, *d_w = nullptr, *d_tau = nullptr;
+  double *d_lam = nullptr, *d_a = nullptr, *d_eps = nullptr, *d_WT = nullptr, *d_eta0 = nullptr;
+  double *d_ub = nullptr;                  // [nz][nd] reduced Doppler shift (u units)
+  double *d_st = nullptr;                  // [nz][nt] reduced transition shifts
+  double *d_sll = nullptr;                 // [nz][nl][nl] lower-level shifts
+  double *d_theta = nullptr;               // [nth]
+  int *d_slot_theta = nullptr, *d_slot_dir = nullptr, *d_slot_off = nullptr, *d_pair_slot = nullptr;
+  double2 *d_E = nullptr, *d_A = nullptr;  // see above
+  double2 *d_alpha = nullptr, *d_bma = nullptr; // [nz][nu][nu]
+  double *d_g = nullptr;                   // [nz][nt][nd][4] geometric factors of K
+};
+
+struct Precomp {
+  bool done = false;
+  int store_mask = 0;
+  double *d_K = nullptr;      // [z][o][n][8]: kQ,kU,kV,rQ,rU,rV (over eta_I), 1/eta_I, eta_I/eta_0
+  double *d_epsth = nullptr;  // [z][o][n][4]
+  double *d_f = nullptr;      // [z][o][n]
+  double *d_M64 = nullptr;    // kernels FP64
+  float *d_M32 = nullptr;     // kernels FP32
+  double2 *d_r3 = nullptr;    // [z][t][n] R_III incoming weights
+  double2 *d_prof = nullptr;  // [z][t][n] outgoing profiles on the comoving grid
+  double *d_b = nullptr;      // right-hand side, FP64 vector
+};
+
+struct Work {
+  // scratch for the Sigma apply, per precision
+  void *Ibar[2] = {nullptr, nullptr};
+  void *W[2] = {nullptr, nullptr};
+  void *Eb[2] = {nullptr, nullptr};
+  void *tmp[2] = {nullptr, nullptr};     // internal to the Sigma apply
+  void *opeps[2] = {nullptr, nullptr};   // emissivity inside the operator apply
+  double2 *Y = nullptr;       // [z][t][o][4]
+  double2 *X = nullptr;       // [z][u][u'][l]
+  int zchunk = 1;
+  // solver vectors
+  double *V = nullptr;        // Krylov basis, (restart+1) x N
+  float *v32a = nullptr, *v32b = nullptr;
+  double *r = nullptr, *x = nullptr, *tmp64 = nullptr, *red = nullptr;
+  double *dots = nullptr;     // reduction scratch for the block dot-products
+  int V_cols = 0;
+};
+
+}  // namespace trap
+
+struct trap_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool has_problem = false;
+  trap::Problem pb;
+  trap::Precomp pre;
+  trap::Work wk;
+  std::vector<trap::DevBuf> bufs;   // every allocation the context made
+};
+
+namespace trap {
+// allocation helper (records into ctx->bufs)
+int dalloc(trap_ctx* ctx, void** p, size_t bytes);
+void free_all(trap_ctx* ctx);
+int upload(trap_ctx* ctx, void** dst, const void* src, size_t bytes);
+
+template <typename T>
+int dalloc_t(trap_ctx* ctx, T** p, size_t count) {
+  return dalloc(ctx, reinterpret_cast<void**>(p), count * sizeof(T));
+}
+template <typename T>
+int upload_t(trap_ctx* ctx, T** dst, const std::vector<T>& v) {
+  return upload(ctx, reinterpret_cast<void**>(dst), v.data(), v.size() * sizeof(T));
+}
+
+// host setup (host_setup.cpp)
+int build_problem(trap_ctx* ctx, const trap_atom_desc* atom, const trap_problem_desc* pd);
+size_t estimate_bytes(const trap_atom_desc* atom, const trap_problem_desc* pd, int store_mask,
+                      int* err);
+
+// precompute (precompute.hip)
+int run_precompute(trap_ctx* ctx, int store_mask);
+
+// applies (sigma.hip, formal.hip)
+int sigma_apply(trap_ctx* ctx, const void* I, void* eps, int prec, int add_thermal, int normalize);
+int formal_apply(trap_ctx* ctx, const void* eps, void* I, int with_boundary, int prec);
+int operator_apply(trap_ctx* ctx, const void* x, void* y, int prec);
+int ensure_work(trap_ctx* ctx, int prec);
+
+// solver (solver.hip)
+int gmres_solve(trap_ctx* ctx, const trap_solve_opts* opts, double* I, trap_solve_stats* st);
+
+inline int ceil_div(long long a, long long b) { return static_cast<int>((a + b - 1) / b); }
+
+}  // namespace trap

@@ -1,0 +1,227 @@
+"""ctypes binding of the trap C ABI (include/trap.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  Device vectors are torch tensors on a ROCm device (contiguous,
+layout [z][o][n][s]); torch supplies the memory and the stream.  Loading fails
+loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtrap.so")
+
+TRAP_FP64 = 0
+TRAP_FP32 = 1
+STATUS = {0: "TRAP_OK", -1: "TRAP_EINVAL", -2: "TRAP_ENOMEM", -3: "TRAP_EDEVICE",
+          -4: "TRAP_ENOCONV", -5: "TRAP_ESTATE", -6: "TRAP_ENAN"}
+
+EXPORTED = ["trap_create", "trap_destroy", "trap_set_problem", "trap_precompute",
+            "trap_apply_sigma", "trap_formal_solve", "trap_apply_operator", "trap_rhs",
+            "trap_gmres_solve", "trap_emergent", "trap_get_info", "trap_footprint",
+            "trap_last_error"]
+
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+class AtomDesc(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("lambda0_A", ctypes.c_double), ("mass_amu", ctypes.c_double),
+                ("J_l", ctypes.c_double), ("J_u", ctypes.c_double), ("g_l", ctypes.c_double),
+                ("g_u", ctypes.c_double), ("L_l", ctypes.c_int), ("L_u", ctypes.c_int),
+                ("S", ctypes.c_double), ("fs_split_x", ctypes.c_double), ("r_E", ctypes.c_double)]
+
+
+class ProblemDesc(ctypes.Structure):
+    _fields_ = [("n_z", ctypes.c_int), ("n_nu", ctypes.c_int), ("n_mu", ctypes.c_int),
+                ("n_chi", ctypes.c_int), ("x", _dp), ("tau_line", _dp), ("T", _dp), ("xi", _dp),
+                ("a", _dp), ("eps", _dp), ("W_T", _dp), ("v", _dp), ("B", _dp),
+                ("T_ref", ctypes.c_double)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("n_z", ctypes.c_int), ("n_nu", ctypes.c_int), ("n_dir", ctypes.c_int),
+                ("n_theta", ctypes.c_int), ("n_slots", ctypes.c_int), ("n_up", ctypes.c_int),
+                ("n_lo", ctypes.c_int), ("n_trans", ctypes.c_int), ("n_unknowns", ctypes.c_size_t),
+                ("bytes_kernel_fp64", ctypes.c_size_t), ("bytes_kernel_fp32", ctypes.c_size_t),
+                ("bytes_device_total", ctypes.c_size_t), ("flops_contraction", ctypes.c_double),
+                ("bytes_contraction_fp64", ctypes.c_double), ("bytes_contraction_fp32", ctypes.c_double)]
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("restart", ctypes.c_int), ("max_iters", ctypes.c_int),
+                ("max_outer", ctypes.c_int), ("inner", ctypes.c_int), ("inner_tol", ctypes.c_double)]
+
+
+class SolveStats(ctypes.Structure):
+    _fields_ = [("outer_steps", ctypes.c_int), ("inner_iters", ctypes.c_int),
+                ("applies_fp64", ctypes.c_int), ("applies_fp32", ctypes.c_int),
+                ("final_rel_res", ctypes.c_double), ("ms_total", ctypes.c_double)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libtrap.so (built by paper_2505_20968_amd.build); raise if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"HIP library not built: {path} is missing "
+                           "(run `python -m paper_2505_20968_amd.build`)")
+    lib = ctypes.CDLL(path)
+    vp = ctypes.c_void_p
+    lib.trap_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, vp]
+    lib.trap_destroy.argtypes = [vp]
+    lib.trap_set_problem.argtypes = [vp, ctypes.POINTER(AtomDesc), ctypes.POINTER(ProblemDesc)]
+    lib.trap_precompute.argtypes = [vp, ctypes.c_int]
+    lib.trap_apply_sigma.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.c_int]
+    lib.trap_formal_solve.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.c_int]
+    lib.trap_apply_operator.argtypes = [vp, vp, vp, ctypes.c_int]
+    lib.trap_rhs.argtypes = [vp, vp]
+    lib.trap_gmres_solve.argtypes = [vp, ctypes.POINTER(SolveOpts), vp, ctypes.POINTER(SolveStats)]
+    lib.trap_emergent.argtypes = [vp, vp, _dp]
+    lib.trap_get_info.argtypes = [vp, ctypes.POINTER(Info)]
+    lib.trap_footprint.argtypes = [ctypes.POINTER(AtomDesc), ctypes.POINTER(ProblemDesc), ctypes.c_int,
+                                   ctypes.POINTER(ctypes.c_size_t)]
+    lib.trap_last_error.restype = ctypes.c_char_p
+    for name in EXPORTED:
+        if name != "trap_last_error":
+            getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+class TrapError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+def _check(code: int):
+    if code != 0:
+        raise TrapError(code, _lib.trap_last_error().decode(errors="replace"))
+
+
+def _atom_desc(atom) -> AtomDesc:
+    return AtomDesc(kind=0 if atom.kind == "two_level" else 1, lambda0_A=atom.lambda0_A,
+                    mass_amu=atom.mass_amu, J_l=atom.J_l, J_u=atom.J_u, g_l=atom.g_l, g_u=atom.g_u,
+                    L_l=int(atom.L_l), L_u=int(atom.L_u), S=float(atom.S),
+                    fs_split_x=float(atom.fs_split_x), r_E=float(atom.r_E))
+
+
+def _problem_desc(prob):
+    keep = {k: np.ascontiguousarray(getattr(prob, k), dtype=np.float64)
+            for k in ("x", "tau_line", "T", "xi", "a", "eps", "W_T", "v", "B")}
+    ptr = {k: v.ctypes.data_as(_dp) for k, v in keep.items()}
+    d = ProblemDesc(n_z=prob.n_z, n_nu=prob.n_nu, n_mu=prob.n_mu, n_chi=prob.n_chi,
+                    T_ref=float(prob.T_ref), **ptr)
+    return d, keep
+
+
+def footprint(prob, store_mask: int = 3) -> int:
+    lib = load_library()
+    d, keep = _problem_desc(prob)
+    out = ctypes.c_size_t(0)
+    _check(lib.trap_footprint(ctypes.byref(_atom_desc(prob.atom)), ctypes.byref(d), store_mask,
+                              ctypes.byref(out)))
+    return int(out.value)
+
+
+def _prec_of(t) -> int:
+    import torch
+    if t.dtype == torch.float64:
+        return TRAP_FP64
+    if t.dtype == torch.float32:
+        return TRAP_FP32
+    raise TypeError(f"unsupported dtype {t.dtype}")
+
+
+class Context:
+    """One problem on one device; wraps trap_ctx."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        self.lib = load_library()
+        self.device = device
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.stream = stream
+        h = ctypes.c_void_p()
+        _check(self.lib.trap_create(ctypes.byref(h), device, ctypes.c_void_p(stream.cuda_stream)))
+        self.h = h
+        self.prob = None
+        self.shape = None
+
+    def close(self):
+        if self.h is not None and self.h.value:
+            self.lib.trap_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _vec(self, t, prec=None):
+        if not t.is_cuda or not t.is_contiguous():
+            raise ValueError("vectors must be contiguous device tensors")
+        if tuple(t.shape) != self.shape:
+            raise ValueError(f"vector shape {tuple(t.shape)} != {self.shape}")
+        if prec is not None and _prec_of(t) != prec:
+            raise TypeError("precision mismatch")
+        return ctypes.c_void_p(t.data_ptr())
+
+    def set_problem(self, prob):
+        d, keep = _problem_desc(prob)
+        _check(self.lib.trap_set_problem(self.h, ctypes.byref(_atom_desc(prob.atom)), ctypes.byref(d)))
+        self.prob = prob
+        self.shape = (prob.n_z, prob.n_mu * prob.n_chi, prob.n_nu, 4)
+
+    def precompute(self, store_mask: int = 3):
+        _check(self.lib.trap_precompute(self.h, store_mask))
+
+    def apply_sigma(self, I, eps, add_thermal: bool = False):
+        p = _prec_of(I)
+        _check(self.lib.trap_apply_sigma(self.h, self._vec(I, p), self._vec(eps, p), p, int(add_thermal)))
+
+    def formal_solve(self, eps, I, with_boundary: bool = True):
+        p = _prec_of(I)
+        _check(self.lib.trap_formal_solve(self.h, self._vec(eps, p), self._vec(I, p), int(with_boundary), p))
+
+    def apply_operator(self, x, y):
+        p = _prec_of(x)
+        _check(self.lib.trap_apply_operator(self.h, self._vec(x, p), self._vec(y, p), p))
+
+    def rhs(self, b):
+        _check(self.lib.trap_rhs(self.h, self._vec(b, TRAP_FP64)))
+
+    def gmres_solve(self, I, tol: float = 1e-8, restart: int = 40, max_iters: int = 2000,
+                    inner: int = TRAP_FP64, max_outer: int = 8, inner_tol: float = 1e-5,
+                    raise_on_noconv: bool = True):
+        o = SolveOpts(tol=tol, restart=restart, max_iters=max_iters, max_outer=max_outer, inner=inner,
+                      inner_tol=inner_tol)
+        st = SolveStats()
+        code = self.lib.trap_gmres_solve(self.h, ctypes.byref(o), self._vec(I, TRAP_FP64), ctypes.byref(st))
+        if code != 0 and (raise_on_noconv or code != -4):
+            _check(code)
+        return {"outer_steps": st.outer_steps, "inner_iters": st.inner_iters,
+                "applies_fp64": st.applies_fp64, "applies_fp32": st.applies_fp32,
+                "final_rel_res": st.final_rel_res, "ms_total": st.ms_total, "status": code}
+
+    def emergent(self, I) -> np.ndarray:
+        n_up = self.shape[1] // 2
+        out = np.zeros((n_up, self.shape[2], 4))
+        _check(self.lib.trap_emergent(self.h, self._vec(I, TRAP_FP64), out.ctypes.data_as(_dp)))
+        return out
+
+    def info(self) -> dict:
+        i = Info()
+        _check(self.lib.trap_get_info(self.h, ctypes.byref(i)))
+        return {f: getattr(i, f) for f, _ in Info._fields_}
