@@ -1,0 +1,187 @@
+#!/usr/bin/env python3
+"""Benchmark of the GPU hot path: full Stokes solves of the two-level,
+chromosphere-like PRD problem (N_z = 70, N_nu = 101 on [-12, 12] Doppler
+widths, 4+4 Gauss-Legendre mu x 8 azimuths, seeded atmosphere, tolerance 1e-8).
+
+One step = one whole pass of the method on a fresh seeded atmosphere:
+per-height setup, device precompute (R_II kernels by product integration,
+R_III weights, propagation matrix, normalisation, right-hand side) and the
+GMRES solve to tolerance (mixed precision: FP32 inner operator, FP64 Arnoldi,
+residual and iterative refinement; or plain FP64 with --precision fp64).
+
+Prints one JSON line.  `value` is solves/s; `roofline` covers the dominant
+kernel (the FP32 R_II contraction), timed with HIP events on the library's
+stream over the timed region; `cpu_baseline` times the FP64 oracle on a
+bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+METRIC = ("Stokes solves/s + emissivity-apply GB/s or TFLOP/s at 1e-6 rel; "
+          "p50/p99 latency")
+PEAK = {"fp32": 157.3, "fp64": 78.6}     # dense TFLOP/s, MI355X published figures
+HBM_PEAK = 8000.0                        # GB/s
+
+
+def _pct(v, q):
+    s = sorted(v)
+    if not s:
+        return None
+    k = (len(s) - 1) * q
+    lo = int(k)
+    hi = min(lo + 1, len(s) - 1)
+    return s[lo] + (s[hi] - s[lo]) * (k - lo)
+
+
+def cpu_baseline(n_applies: float, seed: int, budget_heights: int = 1):
+    """Time the FP64 oracle on a bounded sample of the workload and scale it to
+    one full solve: setup + kernels and one Sigma per sampled height (scaled by
+    N_z, Sigma being height-local) + the full Lambda, times the apply count
+    the GPU solve needed."""
+    from threadpoolctl import threadpool_limits
+    import numpy as np
+    from workloads import cfg2
+    from oracle import transfer as T
+    with threadpool_limits(limits=1):
+        prob = cfg2(seed)
+        t0 = time.perf_counter()
+        op = T.setup(prob, {"normalize": False})
+        t_setup = time.perf_counter() - t0
+        rng = np.random.default_rng(0)
+        I = rng.random((prob.n_z, prob.n_dir, prob.n_nu, 4))
+        zs = list(range(0, prob.n_z, max(1, prob.n_z // budget_heights)))[:budget_heights]
+        t_first = t_second = 0.0
+        for z in zs:
+            t0 = time.perf_counter()
+            T.sigma_height(op, z, I[z], normalize=False)      # builds this height's kernels
+            t_first += time.perf_counter() - t0
+            t0 = time.perf_counter()
+            T.sigma_height(op, z, I[z], normalize=False)
+            t_second += time.perf_counter() - t0
+        t0 = time.perf_counter()
+        T.formal_solve(op, I)
+        t_formal = time.perf_counter() - t0
+    k = len(zs)
+    t_kernels = (t_first - t_second) / k * prob.n_z
+    t_sigma = t_second / k * prob.n_z
+    # +1 Sigma for the normalisation factor, +1 Lambda for the right-hand side
+    t_solve = t_setup + t_kernels + (n_applies + 1) * t_sigma + (n_applies + 1) * t_formal
+    return {"value": 1.0 / t_solve, "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": (f"oracle on seed {seed}: setup, R_II/R_III kernels and one Sigma apply "
+                       f"at {k} of {prob.n_z} heights (scaled by N_z; Sigma is height-local), "
+                       f"one full Lambda; scaled to {n_applies:.1f} operator applies per solve "
+                       f"as measured on the GPU; single BLAS thread"),
+            "seconds_measured": t_setup + t_first + t_second + t_formal,
+            "seconds_per_solve_est": t_solve}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--restart", type=int, default=40)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE={world}); "
+              "this build has no multi-GPU path: heights shard with zero communication for Sigma "
+              "and one all-to-all per apply for Lambda, see DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2505_20968_amd import Context, TRAP_FP32, TRAP_FP64
+    from workloads import cfg2
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a ROCm GPU", file=sys.stderr)
+        sys.exit(1)
+    mixed = args.precision == "mixed"
+    ctx = Context(0)
+
+    def one_step(seed):
+        prob = cfg2(seed)
+        ctx.set_problem(prob)
+        ctx.precompute(3 if mixed else 1)
+        x = torch.zeros(ctx.shape, dtype=torch.float64, device="cuda")
+        st = ctx.gmres_solve(x, tol=args.tol, restart=args.restart, max_iters=2000,
+                             inner=TRAP_FP32 if mixed else TRAP_FP64, max_outer=10, inner_tol=1e-4)
+        return st
+
+    for i in range(args.warmup):
+        one_step(1000 + i)
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    lat, stats = [], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ts = time.perf_counter()
+        st = one_step(2 + i)
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - ts)
+        stats.append(st)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    stage = ctx.stage_times()
+    ctx.profile(False)
+    info = ctx.info()
+    ctx.close()
+
+    key = "fp32" if mixed else "fp64"
+    cstage = stage["contract_fp32" if mixed else "contract_fp64"]
+    flops = stage["flops_contraction"][key]
+    cbytes = stage["bytes_contraction"][key]
+    ms_c = cstage["ms"]
+    achieved = flops / (ms_c * 1e-3) / 1e12 if ms_c > 0 else 0.0
+    n_applies = sum(s["applies_fp32"] + s["applies_fp64"] for s in stats) / len(stats)
+    apply_ms = {k: v["ms"] / max(v["launches"], 1) for k, v in stage.items() if isinstance(v, dict) and "ms" in v}
+    out = {
+        "metric": METRIC,
+        "value": args.steps / elapsed,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if mixed else "f64",
+        "data": "synthetic",
+        "config": {"workload": "two-level J0->1 PRD-AD chromosphere-like column: N_z=70, "
+                               "N_nu=101 on [-12,12], 4+4 GL mu x 8 chi, seeded B/v/a/eps, tol 1e-8",
+                   "precision": ("FP32 inner operator, FP64 Arnoldi/residual/refinement" if mixed
+                                 else "FP64 throughout"),
+                   "n_unknowns": info["n_unknowns"], "n_theta": info["n_theta"],
+                   "n_slots": info["n_slots"], "restart": args.restart},
+        "latency_ms": {"p50": 1e3 * _pct(lat, 0.5), "p99": 1e3 * _pct(lat, 0.99)},
+        "solver": {"inner_iters_mean": sum(s["inner_iters"] for s in stats) / len(stats),
+                   "outer_steps_mean": sum(s["outer_steps"] for s in stats) / len(stats),
+                   "applies_mean": n_applies,
+                   "max_final_rel_res": max(s["final_rel_res"] for s in stats)},
+        "emissivity_apply": {"contraction_tflops": achieved,
+                             "contraction_ms_per_launch": ms_c / max(cstage["launches"], 1),
+                             "contraction_launches": cstage["launches"],
+                             "stage_ms_per_launch": apply_ms},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK[key], "unit": "TFLOP/s",
+                     "frac": achieved / PEAK[key], "traffic": None,
+                     "algorithmic_bytes_per_launch": cbytes / max(cstage["launches"], 1),
+                     "algorithmic_flops_per_launch": flops / max(cstage["launches"], 1),
+                     "kernel": "k_contract<float>" if mixed else "k_contract<double>"},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(n_applies, seed=2)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

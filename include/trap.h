@@ -183,6 +183,27 @@ int trap_get_info(const trap_ctx* ctx, trap_info* info);
 int trap_footprint(const trap_atom_desc* atom, const trap_problem_desc* prob, int store_mask,
                    size_t* bytes);
 
+/* Per-stage device timing.  trap_profile(ctx, 1) starts recording HIP events
+ * around every kernel launch of the listed stages on the context's stream
+ * (and clears earlier records); trap_profile(ctx, 0) stops.  trap_stage_times
+ * synchronises the stream and returns, per stage, the summed elapsed device
+ * milliseconds and the launch count since recording started, plus the
+ * algorithmic flops of the R_II contraction launches recorded (16 per complex
+ * kernel entry per incoming-direction slot). */
+enum { TRAP_STAGE_COMOVING = 0, TRAP_STAGE_CONTRACT = 1, TRAP_STAGE_R3 = 2, TRAP_STAGE_ANGULAR = 3,
+       TRAP_STAGE_BACKINTERP = 4, TRAP_STAGE_FORMAL = 5, TRAP_STAGE_KERNEL_ROWS = 6,
+       TRAP_STAGE_CONTRACT_FP64 = 7, TRAP_STAGE_COUNT = 8 };
+/* TRAP_STAGE_CONTRACT counts FP32 contraction launches, TRAP_STAGE_CONTRACT_FP64
+ * the FP64 ones; flops/bytes are kept per precision (index 0 FP32, 1 FP64). */
+typedef struct {
+  double ms[TRAP_STAGE_COUNT];
+  int launches[TRAP_STAGE_COUNT];
+  double flops_contraction[2];
+  double bytes_contraction[2];  /* algorithmic bytes of the recorded contraction launches */
+} trap_stage_stats;
+int trap_profile(trap_ctx* ctx, int enable);
+int trap_stage_times(trap_ctx* ctx, trap_stage_stats* out);
+
 /* Thread-local description of the last failure. */
 const char* trap_last_error(void);
 

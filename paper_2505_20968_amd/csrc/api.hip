@@ -74,6 +74,42 @@ int operator_apply(trap_ctx* ctx, const void* x, void* y, int prec) {
   return TRAP_OK;
 }
 
+int prof_begin(trap_ctx* ctx, int stage, double flops, double bytes) {
+  Prof& P = ctx->prof;
+  if (!P.on) return -1;
+  if (P.used == P.rec.size()) {
+    ProfRec r{stage, nullptr, nullptr, 0.0, 0.0};
+    if (hipEventCreate(&r.a) != hipSuccess) return -1;
+    if (hipEventCreate(&r.b) != hipSuccess) {
+      (void)hipEventDestroy(r.a);
+      return -1;
+    }
+    P.rec.push_back(r);
+  }
+  ProfRec& r = P.rec[P.used];
+  r.stage = stage;
+  r.flops = flops;
+  r.bytes = bytes;
+  (void)hipEventRecord(r.a, ctx->stream);
+  return static_cast<int>(P.used++);
+}
+
+void prof_end(trap_ctx* ctx, int idx) {
+  if (idx < 0) return;
+  (void)hipEventRecord(ctx->prof.rec[idx].b, ctx->stream);
+}
+
+static void prof_clear(trap_ctx* ctx, bool release) {
+  if (release) {
+    for (auto& r : ctx->prof.rec) {
+      (void)hipEventDestroy(r.a);
+      (void)hipEventDestroy(r.b);
+    }
+    ctx->prof.rec.clear();
+  }
+  ctx->prof.used = 0;
+}
+
 struct DeviceGuard {
   int prev = -1;
   explicit DeviceGuard(int dev) {
@@ -115,6 +151,7 @@ int trap_create(trap_ctx** out, int device, void* stream) {
 int trap_destroy(trap_ctx* ctx) {
   if (!ctx) return TRAP_OK;
   DeviceGuard g(ctx->device);
+  prof_clear(ctx, true);
   free_all(ctx);
   delete ctx;
   return TRAP_OK;
@@ -233,6 +270,37 @@ int trap_get_info(const trap_ctx* ctx, trap_info* info) {
   const double ibytes = (double)P.nz * P.nd * P.nn * 4;
   info->bytes_contraction_fp64 = 8.0 * (kel + wbytes + ibytes);
   info->bytes_contraction_fp32 = 4.0 * (kel + wbytes + ibytes);
+  return TRAP_OK;
+}
+
+int trap_profile(trap_ctx* ctx, int enable) {
+  if (!ctx) return fail(TRAP_EINVAL, "null context");
+  DeviceGuard g(ctx->device);
+  if (enable) {
+    TRAP_HIP(hipStreamSynchronize(ctx->stream));
+    prof_clear(ctx, false);
+  }
+  ctx->prof.on = enable != 0;
+  return TRAP_OK;
+}
+
+int trap_stage_times(trap_ctx* ctx, trap_stage_stats* out) {
+  if (!ctx || !out) return fail(TRAP_EINVAL, "null argument");
+  DeviceGuard g(ctx->device);
+  std::memset(out, 0, sizeof(*out));
+  TRAP_HIP(hipStreamSynchronize(ctx->stream));
+  for (size_t i = 0; i < ctx->prof.used; ++i) {
+    const ProfRec& r = ctx->prof.rec[i];
+    float ms = 0.0f;
+    TRAP_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+    if (r.stage >= 0 && r.stage < TRAP_STAGE_COUNT) {
+      out->ms[r.stage] += ms;
+      out->launches[r.stage] += 1;
+    }
+    const int pi = r.stage == TRAP_STAGE_CONTRACT_FP64 ? 1 : 0;
+    out->flops_contraction[pi] += r.flops;
+    out->bytes_contraction[pi] += r.bytes;
+  }
   return TRAP_OK;
 }
 

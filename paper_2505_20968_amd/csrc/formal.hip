@@ -140,6 +140,7 @@ int formal_apply(trap_ctx* ctx, const void* eps, void* I, int with_boundary, int
   if (!eps || !I) return fail(TRAP_EINVAL, "null vector");
   Problem& P = ctx->pb;
   const int rays = P.nd * P.nn;
+  const int pr = prof_begin(ctx, TRAP_STAGE_FORMAL);
   if (prec == TRAP_FP64) {
     hipLaunchKernelGGL(k_formal<double>, dim3(ceil_div(rays, 64)), dim3(64), 0, ctx->stream, P.nz, P.nd,
                        P.nn, P.d_mu, P.d_tau, ctx->pre.d_K, P.d_WT, static_cast<const double*>(eps),
@@ -152,6 +153,7 @@ int formal_apply(trap_ctx* ctx, const void* eps, void* I, int with_boundary, int
     return fail(TRAP_EINVAL, "unknown precision");
   }
   TRAP_HIP(hipGetLastError());
+  prof_end(ctx, pr);
   return TRAP_OK;
 }
 

@@ -381,6 +381,7 @@ int run_precompute(trap_ctx* ctx, int store_mask) {
   const size_t lds = (size_t)(nn + 1) * 4 * sizeof(double2);
   if (lds > 64 * 1024) return fail(TRAP_EINVAL, "frequency grid too large for the kernel precompute");
   const long long chunk = 1 << 20;
+  const int pr = prof_begin(ctx, TRAP_STAGE_KERNEL_ROWS);
   for (long long r0 = 0; r0 < nrows; r0 += chunk) {
     const long long nr = std::min(chunk, nrows - r0);
     hipLaunchKernelGGL(k_kernel_rows, dim3((unsigned)nr), dim3(64), lds, s, nth, nt, nn, P.d_x, P.d_P,
@@ -388,6 +389,7 @@ int run_precompute(trap_ctx* ctx, int store_mask) {
                        (mask & 2) ? C.d_M32 : nullptr, r0);
     TRAP_HIP(hipGetLastError());
   }
+  prof_end(ctx, pr);
   hipLaunchKernelGGL(k_r3_rows, dim3(nz * nt), dim3(64), lds, s, nt, nn, P.d_x, P.d_P, P.d_lam, P.d_a,
                      P.d_st, C.d_r3, C.d_prof);
   TRAP_HIP(hipGetLastError());

@@ -361,17 +361,27 @@ static int sigma_apply_t(trap_ctx* ctx, const T* I, T* eps, int prec, int add_th
     const int zc = std::min(K.zchunk, nz - z0);
     const long long npts = (long long)zc * nd * nn;
     // 1. comoving interpolation
+    int pr = prof_begin(ctx, TRAP_STAGE_COMOVING);
     hipLaunchKernelGGL(k_spline_shift<T>, dim3(ceil_div(npts, 256)), dim3(256), 0, s, z0, zc, nd, nn,
                        P.d_x, P.d_P, P.d_lam, P.d_ub, -1.0, (const double*)nullptr, 1, 0,
                        I + (size_t)z0 * nd * nn * 4, (long long)nd * nn * 4, (long long)nn * 4, Ibar, 0,
                        (const double*)nullptr, (const double*)nullptr);
     TRAP_HIP(hipGetLastError());
+    prof_end(ctx, pr);
     // 2. contraction
     dim3 grid(ceil_div(4LL * P.max_slots_per_theta, 64), ceil_div(2LL * nn, 64), zc * nth * nt);
+    {
+      const double kel = (double)zc * nth * nt * 2.0 * nn * nn;
+      const double flops = 16.0 * zc * nt * (double)nn * nn * P.nslot;
+      const double bytes = sizeof(T) * (kel + (double)zc * nt * P.nslot * 2.0 * nn * 4 + (double)zc * nd * nn * 4);
+      pr = prof_begin(ctx, sizeof(T) == 8 ? TRAP_STAGE_CONTRACT_FP64 : TRAP_STAGE_CONTRACT, flops, bytes);
+    }
     hipLaunchKernelGGL(k_contract<T>, grid, dim3(256), 0, s, z0, nth, nt, nn, nd, Mk, Ibar, P.d_slot_off,
                        P.d_slot_dir, W, P.nslot);
     TRAP_HIP(hipGetLastError());
+    prof_end(ctx, pr);
     // 3. R_III factors
+    pr = prof_begin(ctx, TRAP_STAGE_R3);
     const long long ny = (long long)zc * nt * nd * 4;
     hipLaunchKernelGGL(k_r3_Y<T>, dim3(ceil_div(ny, 256)), dim3(256), 0, s, z0, zc, nt, nd, nn, C.d_r3,
                        Ibar, K.Y);
@@ -379,15 +389,19 @@ static int sigma_apply_t(trap_ctx* ctx, const T* I, T* eps, int prec, int add_th
     hipLaunchKernelGGL(k_r3_X, dim3(zc * nu * nu * nl), dim3(256), 0, s, z0, nu, nl, nd, P.d_w, P.d_A,
                        K.Y, K.X);
     TRAP_HIP(hipGetLastError());
+    prof_end(ctx, pr);
     // 4. angular / sublevel sum into Eb (chunk-local heights)
+    pr = prof_begin(ctx, TRAP_STAGE_ANGULAR);
     const size_t shb = (size_t)(nl * 16 + nl * 4 * nu * nu) * sizeof(double2);
     hipLaunchKernelGGL(k_angular<T>, dim3(zc * nd, ceil_div(nn, 128)), dim3(128), shb, s, z0, nd, nn, nu, nl, P.nslot,
                        P.c_sc, P.d_w, P.d_E, P.d_A, P.d_alpha, P.d_bma, P.d_pair_slot, W, K.X, C.d_prof,
                        Eb + (size_t)z0 * ncls * nd * nn * 4, 1);
     TRAP_HIP(hipGetLastError());
+    prof_end(ctx, pr);
   }
   // 5. back to the observer frame, per (l, l') class, f and eps_th
   const long long npts = (long long)nz * nd * nn;
+  const int prb = prof_begin(ctx, TRAP_STAGE_BACKINTERP);
   for (int l = 0; l < nl; ++l)
     for (int lp = 0; lp < nl; ++lp) {
       const int cls = l * nl + lp;
@@ -411,6 +425,7 @@ static int sigma_apply_t(trap_ctx* ctx, const T* I, T* eps, int prec, int add_th
                        add_thermal ? C.d_epsth : (const double*)nullptr);
     TRAP_HIP(hipGetLastError());
   }
+  prof_end(ctx, prb);
   return TRAP_OK;
 }
 

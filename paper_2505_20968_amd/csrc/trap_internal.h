@@ -111,6 +111,18 @@ struct Work {
   int V_cols = 0;
 };
 
+struct ProfRec {
+  int stage;
+  hipEvent_t a, b;
+  double flops, bytes;
+};
+
+struct Prof {
+  bool on = false;
+  std::vector<ProfRec> rec;      // records [0, used) are live; events are reused
+  size_t used = 0;
+};
+
 }  // namespace trap
 
 struct trap_ctx {
@@ -120,6 +132,7 @@ struct trap_ctx {
   trap::Problem pb;
   trap::Precomp pre;
   trap::Work wk;
+  trap::Prof prof;
   std::vector<trap::DevBuf> bufs;   // every allocation the context made
 };
 
@@ -156,5 +169,9 @@ int ensure_work(trap_ctx* ctx, int prec);
 int gmres_solve(trap_ctx* ctx, const trap_solve_opts* opts, double* I, trap_solve_stats* st);
 
 inline int ceil_div(long long a, long long b) { return static_cast<int>((a + b - 1) / b); }
+
+// profiling: returns a record index (or -1 when profiling is off)
+int prof_begin(trap_ctx* ctx, int stage, double flops = 0.0, double bytes = 0.0);
+void prof_end(trap_ctx* ctx, int idx);
 
 }  // namespace trap

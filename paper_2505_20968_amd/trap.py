@@ -24,7 +24,9 @@ STATUS = {0: "TRAP_OK", -1: "TRAP_EINVAL", -2: "TRAP_ENOMEM", -3: "TRAP_EDEVICE"
 EXPORTED = ["trap_create", "trap_destroy", "trap_set_problem", "trap_precompute",
             "trap_apply_sigma", "trap_formal_solve", "trap_apply_operator", "trap_rhs",
             "trap_gmres_solve", "trap_emergent", "trap_get_info", "trap_footprint",
-            "trap_last_error"]
+            "trap_profile", "trap_stage_times", "trap_last_error"]
+STAGES = ["comoving", "contract_fp32", "r3", "angular", "backinterp", "formal", "kernel_rows",
+          "contract_fp64"]
 
 _dp = ctypes.POINTER(ctypes.c_double)
 
@@ -63,6 +65,11 @@ class SolveStats(ctypes.Structure):
                 ("final_rel_res", ctypes.c_double), ("ms_total", ctypes.c_double)]
 
 
+class StageStats(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double * 8), ("launches", ctypes.c_int * 8),
+                ("flops_contraction", ctypes.c_double * 2), ("bytes_contraction", ctypes.c_double * 2)]
+
+
 _lib = None
 
 
@@ -89,6 +96,8 @@ def load_library(path: str = LIB_PATH):
     lib.trap_get_info.argtypes = [vp, ctypes.POINTER(Info)]
     lib.trap_footprint.argtypes = [ctypes.POINTER(AtomDesc), ctypes.POINTER(ProblemDesc), ctypes.c_int,
                                    ctypes.POINTER(ctypes.c_size_t)]
+    lib.trap_profile.argtypes = [vp, ctypes.c_int]
+    lib.trap_stage_times.argtypes = [vp, ctypes.POINTER(StageStats)]
     lib.trap_last_error.restype = ctypes.c_char_p
     for name in EXPORTED:
         if name != "trap_last_error":
@@ -219,6 +228,17 @@ class Context:
         n_up = self.shape[1] // 2
         out = np.zeros((n_up, self.shape[2], 4))
         _check(self.lib.trap_emergent(self.h, self._vec(I, TRAP_FP64), out.ctypes.data_as(_dp)))
+        return out
+
+    def profile(self, enable: bool = True):
+        _check(self.lib.trap_profile(self.h, int(enable)))
+
+    def stage_times(self) -> dict:
+        st = StageStats()
+        _check(self.lib.trap_stage_times(self.h, ctypes.byref(st)))
+        out = {name: {"ms": st.ms[i], "launches": st.launches[i]} for i, name in enumerate(STAGES)}
+        out["flops_contraction"] = {"fp32": st.flops_contraction[0], "fp64": st.flops_contraction[1]}
+        out["bytes_contraction"] = {"fp32": st.bytes_contraction[0], "fp64": st.bytes_contraction[1]}
         return out
 
     def info(self) -> dict:
