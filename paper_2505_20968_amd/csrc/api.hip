@@ -258,8 +258,8 @@ int trap_get_info(const trap_ctx* ctx, trap_info* info) {
   info->n_trans = P.nt;
   info->n_unknowns = 4ull * P.nz * P.nd * P.nn;
   const double kel = (double)P.nz * P.nth * P.nt * 2.0 * P.nn * P.nn;
-  info->bytes_kernel_fp64 = (size_t)(kel * 8);
-  info->bytes_kernel_fp32 = (size_t)(kel * 4);
+  info->bytes_kernel_fp64 = (size_t)((double)P.nz * P.nth * P.nt * 2.0 * P.nn * P.ldm * 8);
+  info->bytes_kernel_fp32 = (size_t)((double)P.nz * P.nth * P.nt * 2.0 * P.nn * P.ldm * 4);
   size_t tot = 0;
   for (auto& b : ctx->bufs) tot += b.bytes;
   info->bytes_device_total = tot;

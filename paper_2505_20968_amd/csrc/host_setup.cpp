@@ -395,6 +395,7 @@ int build_problem(trap_ctx* ctx, const trap_atom_desc* at, const trap_problem_de
   P.nmu = pd->n_mu;
   P.nchi = pd->n_chi;
   P.nd = P.nmu * P.nchi;
+  P.ldm = (P.nn + 7) / 8 * 8;
   const int nz = P.nz, nn = P.nn, nd = P.nd;
   P.x.assign(pd->x, pd->x + nn);
   for (int k = 0; k + 1 < nn; ++k)

@@ -155,7 +155,7 @@ __device__ inline int upper_interval(const double* x, int nn, double v) {
 // ------------------------------------------------------------------ R_II kernel rows
 // One 64-thread block per row (z, theta, t, n).
 __global__ void __launch_bounds__(64) k_kernel_rows(
-    int nth, int nt, int nn, const double* __restrict__ x, const double* __restrict__ P,
+    int nth, int nt, int nn, int ldm, const double* __restrict__ x, const double* __restrict__ P,
     const double* __restrict__ lam, const double* __restrict__ av, const double* __restrict__ st,
     const double* __restrict__ theta, double* __restrict__ M64, float* __restrict__ M32,
     long long row0) {
@@ -167,11 +167,11 @@ __global__ void __launch_bounds__(64) k_kernel_rows(
   const int th = (row / ((long long)nn * nt)) % nth;
   const int z = row / ((long long)nn * nt * nth);
   const double L = lam[z], a = av[z], s = st[z * nt + t], Th = theta[th];
-  const size_t base = (size_t)((((size_t)z * nth + th) * nt + t) * 2) * nn * nn;
-  const size_t rre = base + (size_t)n * nn, rim = base + (size_t)nn * nn + (size_t)n * nn;
+  const size_t base = (size_t)((((size_t)z * nth + th) * nt + t) * 2) * nn * ldm;
+  const size_t rre = base + (size_t)n * ldm, rim = base + (size_t)nn * ldm + (size_t)n * ldm;
   if (Th == 0.0) {
     const double2 w = wz(L * x[n] + s, a);
-    for (int m = lane; m < nn; m += 64) {
+    for (int m = lane; m < ldm; m += 64) {
       const double re = (m == n) ? kSqrtPi * w.x : 0.0, im = (m == n) ? kSqrtPi * w.y : 0.0;
       if (M64) { M64[rre + m] = re; M64[rim + m] = im; }
       if (M32) { M32[rre + m] = (float)re; M32[rim + m] = (float)im; }
@@ -216,8 +216,13 @@ __global__ void __launch_bounds__(64) k_kernel_rows(
   }
   __syncthreads();
   const int klo = max(plo, 0), khi = min(phi, nn - 2);
-  for (int m = lane; m < nn; m += 64) {
+  for (int m = lane; m < ldm; m += 64) {
     double re = 0.0, im = 0.0;
+    if (m >= nn) {      // zero padding of the row
+      if (M64) { M64[rre + m] = 0.0; M64[rim + m] = 0.0; }
+      if (M32) { M32[rre + m] = 0.0f; M32[rim + m] = 0.0f; }
+      continue;
+    }
     for (int k = klo; k <= khi; ++k) {
       const double* pk = P + (size_t)k * 4 * nn + m;
       for (int q = 0; q < 4; ++q) {
@@ -372,7 +377,7 @@ int run_precompute(trap_ctx* ctx, int store_mask) {
                      P.d_lam, P.d_a, P.d_ub, P.d_st, P.d_g, P.d_eta0, P.d_eps, P.d_WT, P.c_abs, C.d_K,
                      C.d_epsth);
   TRAP_HIP(hipGetLastError());
-  const size_t kelems = (size_t)nz * nth * nt * 2 * nn * nn;
+  const size_t kelems = (size_t)nz * nth * nt * 2 * nn * P.ldm;
   const int mask = store_mask | 1;     // FP64 kernels always exist (residual, f, b)
   if ((mask & 1) && !C.d_M64) TRAP_TRY(dalloc_t(ctx, &C.d_M64, kelems));
   if ((mask & 2) && !C.d_M32) TRAP_TRY(dalloc_t(ctx, &C.d_M32, kelems));
@@ -384,7 +389,7 @@ int run_precompute(trap_ctx* ctx, int store_mask) {
   const int pr = prof_begin(ctx, TRAP_STAGE_KERNEL_ROWS);
   for (long long r0 = 0; r0 < nrows; r0 += chunk) {
     const long long nr = std::min(chunk, nrows - r0);
-    hipLaunchKernelGGL(k_kernel_rows, dim3((unsigned)nr), dim3(64), lds, s, nth, nt, nn, P.d_x, P.d_P,
+    hipLaunchKernelGGL(k_kernel_rows, dim3((unsigned)nr), dim3(64), lds, s, nth, nt, nn, P.ldm, P.d_x, P.d_P,
                        P.d_lam, P.d_a, P.d_st, P.d_theta, (mask & 1) ? C.d_M64 : nullptr,
                        (mask & 2) ? C.d_M32 : nullptr, r0);
     TRAP_HIP(hipGetLastError());

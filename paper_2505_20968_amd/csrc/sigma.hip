@@ -83,73 +83,166 @@ __global__ void k_spline_shift(int nz0, int nzc, int nd, int nn, const double* _
 }
 
 // ------------------------------------------------------------------ R_II contraction
-// Batched GEMM per (z in chunk, theta, t):
-//   C[(c, n), (sl, s)] = sum_m M[z][theta][t][c][n][m] * Ibar[z][dir(sl)][m][s]
-// rows 2*nn (real plane then imaginary plane), columns 4 * nslots(theta).
-// 64x64 output tile per 256-thread block, 4x4 per thread, K staged by 16.
+// One GEMM per (z, theta) over every transition at once:
+//   C[(t, c, n), (sl, s)] = sum_m M[z][theta][(t, c, n)][m] * Ibar[z][dir(sl)][m][s]
+// rows R = 2 nt nn (transition, real/imaginary plane, frequency), columns
+// 4 nslots(theta) (incoming-direction slot, Stokes), K = nn.  Matrix cores:
+// v_mfma_{f32,f64}_16x16x4 with the operands swapped (A_in = B^T, B_in = M^T)
+// so that each lane's four accumulators are the four Stokes components of one
+// (row, slot) entry of W -- one contiguous 16/32-byte store.
+// Block: 4 waves, 64 rows (16 per wave) x up to 256 columns (16 column tiles
+// held in registers), K staged through LDS in chunks of KC.
+typedef float floatx4_t __attribute__((ext_vector_type(4)));
+typedef double doublex4_t __attribute__((ext_vector_type(4)));
+
+template <typename T> struct MfmaOp;
+// Output layouts differ: for the f32 16x16x4 instruction lane l holds rows
+// 4 (l/16) + r of the 16x16 result, for the f64 one rows (l/16) + 4 r.  The f64
+// path stores the B tile with its 16 columns transposed as a 4x4 grid so that
+// both end up with one slot's four Stokes values per lane.
+template <> struct MfmaOp<float> {
+  typedef floatx4_t acc_t;
+  static constexpr int KC = 32;
+  static constexpr bool kInterleavedRows = false;
+  __device__ static inline acc_t run(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+template <> struct MfmaOp<double> {
+  typedef doublex4_t acc_t;
+  static constexpr int KC = 16;
+  static constexpr bool kInterleavedRows = true;
+  __device__ static inline acc_t run(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+
+constexpr int kMaxColTiles = 16;   // 256 columns = 64 slots per column group
+constexpr int kRowsPerBlock = 128; // 8 waves x 16 rows
+
+template <typename T> struct Vec4;
+template <> struct Vec4<float> { typedef float4 type; };
+template <> struct Vec4<double> { typedef double4 type; };
+
+// Block: 8 waves = 128 rows (16 per wave) x up to 256 columns (16 column tiles in
+// registers).  K is staged through LDS in chunks of KC with the next chunk's
+// global loads issued before the current chunk's matrix-core work (register
+// double buffering).  LDS row strides are 16 (mod 64) elements so the four
+// k-rows of a fragment read fall in different bank groups.
 template <typename T>
-__global__ void __launch_bounds__(256) k_contract(int z0, int nth, int nt, int nn, int nd,
+__global__ void __launch_bounds__(512) k_contract(int z0, int nth, int nt, int nn, int ldm, int nd,
                                                   const T* __restrict__ M, const T* __restrict__ Ibar,
                                                   const int* __restrict__ slot_off,
                                                   const int* __restrict__ slot_dir, T* __restrict__ W,
                                                   int nslot) {
-  __shared__ T As[16][64 + 1];
-  __shared__ T Bs[16][64 + 1];
-  const int batch = blockIdx.z;
-  const int t = batch % nt;
-  const int th = (batch / nt) % nth;
-  const int zl = batch / (nt * nth);
+  using Op = MfmaOp<T>;
+  using acc_t = typename Op::acc_t;
+  using V4 = typename Vec4<T>::type;
+  constexpr int KC = Op::KC;
+  constexpr int NCOL = kMaxColTiles * 16;
+  constexpr int AST = kRowsPerBlock + 16;   // As[k][row]
+  constexpr int BST = NCOL + 16;            // Bs[k][col]
+  constexpr int APT = KC / 4;               // A elements per thread per chunk (row, 4 threads per row)
+  constexpr int BPT = KC / 8;               // B k-rows per thread per chunk (8 k-lanes)
+  __shared__ T As[KC * AST];
+  __shared__ T Bs[KC * BST];
+  const int th = blockIdx.y;
+  const int zl = blockIdx.z;
   const int z = z0 + zl;
+  const int R = 2 * nt * nn;
+  const int row0 = blockIdx.x * kRowsPerBlock;
+  if (row0 >= R) return;
   const int s0 = slot_off[th], ns = slot_off[th + 1] - s0;
-  const int ncol = 4 * ns, nrow = 2 * nn;
-  const int col0 = blockIdx.x * 64, row0 = blockIdx.y * 64;
-  if (col0 >= ncol) return;
-  const T* Mb = M + ((((size_t)z * nth + th) * nt + t) * 2) * (size_t)nn * nn;   // [2nn][nn]
+  const T* Mb = M + ((size_t)z * nth + th) * (size_t)R * ldm;
   const T* Ib = Ibar + (size_t)zl * nd * nn * 4;
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  T acc[4][4];
-  for (int i = 0; i < 4; ++i)
-    for (int j = 0; j < 4; ++j) acc[i][j] = T(0);
-  for (int k0 = 0; k0 < nn; k0 += 16) {
-    // A tile: rows row0..row0+63, k k0..k0+15
-    for (int e = threadIdx.x; e < 64 * 16; e += 256) {
-      const int r = e >> 4, kk = e & 15;
-      const int gr = row0 + r, gk = k0 + kk;
-      As[kk][r] = (gr < nrow && gk < nn) ? Mb[(size_t)gr * nn + gk] : T(0);
-    }
-    // B tile: k rows, cols col0..col0+63 = (slot, s)
-    for (int e = threadIdx.x; e < 64 * 16; e += 256) {
-      const int kk = e >> 6, c = e & 63;
-      const int gc = col0 + c, gk = k0 + kk;
-      T v = T(0);
-      if (gc < ncol && gk < nn) {
-        const int sl = gc >> 2, s = gc & 3;
-        const int dir = slot_dir[s0 + sl];
-        v = Ib[((size_t)dir * nn + gk) * 4 + s];
-      }
-      Bs[kk][c] = v;
-    }
-    __syncthreads();
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int lr = lane & 15, lk = lane >> 4;
+  // loader roles
+  const int a_row = tid >> 2, a_kq = tid & 3;          // A: 4 threads per row, APT consecutive k each
+  const int b_sl = tid & 63, b_ky = tid >> 6;          // B: one slot per lane, k rows b_ky + 8 i
+  const int ga_row = row0 + a_row;
+  const T* a_src = Mb + (size_t)min(ga_row, R - 1) * ldm;
+  // output coordinates of this lane's row
+  const int grow = row0 + wave * 16 + lr;
+  const int rt = grow / (2 * nn), rc = (grow / nn) & 1, rn = grow % nn;
+  const int nchunks = (nn + KC - 1) / KC;
+  for (int sg0 = 0; sg0 < ns; sg0 += NCOL / 4) {
+    const int nsg = min(NCOL / 4, ns - sg0);      // slots in this column group
+    const int nsub = (4 * nsg + 15) >> 4;
+    const bool b_live = b_sl < nsg;
+    const int b_dir = b_live ? slot_dir[s0 + sg0 + b_sl] : 0;
+    const T* b_src = Ib + (size_t)b_dir * nn * 4;
+    const bool b_store = b_sl < 4 * nsub;        // zero-fill padded columns of the last tile
+    acc_t acc[kMaxColTiles];
 #pragma unroll
-    for (int kk = 0; kk < 16; ++kk) {
-      T a[4], b[4];
-      for (int i = 0; i < 4; ++i) a[i] = As[kk][ty * 4 + i];
-      for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tx * 4 + j];
-      for (int i = 0; i < 4; ++i)
-        for (int j = 0; j < 4; ++j) acc[i][j] += a[i] * b[j];
+    for (int j = 0; j < kMaxColTiles; ++j)
+      for (int r = 0; r < 4; ++r) acc[j][r] = T(0);
+    T ra[APT];
+    V4 rb[BPT];
+    auto load = [&](int k0) {
+#pragma unroll
+      for (int i = 0; i < APT; ++i) {
+        const int gk = k0 + a_kq * APT + i;
+        ra[i] = (ga_row < R && gk < ldm) ? a_src[gk] : T(0);
+      }
+#pragma unroll
+      for (int i = 0; i < BPT; ++i) {
+        const int gk = k0 + b_ky + 8 * i;
+        if (b_live && gk < nn) {
+          rb[i] = *reinterpret_cast<const V4*>(b_src + (size_t)gk * 4);
+        } else {
+          rb[i].x = T(0); rb[i].y = T(0); rb[i].z = T(0); rb[i].w = T(0);
+        }
+      }
+    };
+    load(0);
+    for (int c = 0; c < nchunks; ++c) {
+      const int k0 = c * KC;
+      if (c > 0) __syncthreads();
+#pragma unroll
+      for (int i = 0; i < APT; ++i) As[(a_kq * APT + i) * AST + a_row] = ra[i];
+      if (b_store) {
+#pragma unroll
+        for (int i = 0; i < BPT; ++i) {
+          T* dst = Bs + (b_ky + 8 * i) * BST;
+          const T v[4] = {rb[i].x, rb[i].y, rb[i].z, rb[i].w};
+          if (Op::kInterleavedRows) {
+            const int base = (b_sl >> 2) * 16 + (b_sl & 3);
+            for (int q = 0; q < 4; ++q) dst[base + 4 * q] = v[q];
+          } else {
+            for (int q = 0; q < 4; ++q) dst[4 * b_sl + q] = v[q];
+          }
+        }
+      }
+      __syncthreads();
+      if (c + 1 < nchunks) load(k0 + KC);
+      const int ksteps = (min(KC, nn - k0) + 3) >> 2;
+#pragma unroll
+      for (int ks = 0; ks < KC / 4; ++ks) {
+        if (ks < ksteps) {
+          const T bf = As[(ks * 4 + lk) * AST + wave * 16 + lr];
+#pragma unroll
+          for (int j = 0; j < kMaxColTiles; ++j) {
+            if (j < nsub) {
+              const T af = Bs[(ks * 4 + lk) * BST + j * 16 + lr];
+              acc[j] = Op::run(af, bf, acc[j]);
+            }
+          }
+        }
+      }
     }
     __syncthreads();
-  }
-  // store: W[zl][t][slot][c][n][s]
-  for (int i = 0; i < 4; ++i) {
-    const int gr = row0 + ty * 4 + i;
-    if (gr >= nrow) continue;
-    const int c = gr >= nn ? 1 : 0, n = gr - c * nn;
-    for (int j = 0; j < 4; ++j) {
-      const int gc = col0 + tx * 4 + j;
-      if (gc >= ncol) continue;
-      const int sl = s0 + (gc >> 2), s = gc & 3;
-      W[((((size_t)zl * nt + t) * nslot + sl) * 2 + c) * (size_t)nn * 4 + (size_t)n * 4 + s] = acc[i][j];
+    // lane holds C[grow][16 j + 4 lk + r], r = 0..3 -> slot 4 j + lk, Stokes r
+    if (grow < R) {
+#pragma unroll
+      for (int j = 0; j < kMaxColTiles; ++j) {
+        const int sl = 4 * j + lk;
+        if (j < nsub && sl < nsg) {
+          V4 o;
+          o.x = acc[j][0]; o.y = acc[j][1]; o.z = acc[j][2]; o.w = acc[j][3];
+          *reinterpret_cast<V4*>(W + (((((size_t)zl * nt + rt) * nslot + s0 + sg0 + sl) * 2 + rc) * nn + rn) * 4) = o;
+        }
+      }
     }
   }
 }
@@ -369,15 +462,15 @@ static int sigma_apply_t(trap_ctx* ctx, const T* I, T* eps, int prec, int add_th
     TRAP_HIP(hipGetLastError());
     prof_end(ctx, pr);
     // 2. contraction
-    dim3 grid(ceil_div(4LL * P.max_slots_per_theta, 64), ceil_div(2LL * nn, 64), zc * nth * nt);
+    dim3 grid(ceil_div(2LL * nt * nn, kRowsPerBlock), nth, zc);
     {
-      const double kel = (double)zc * nth * nt * 2.0 * nn * nn;
+      const double kel = (double)zc * nth * nt * 2.0 * nn * P.ldm;
       const double flops = 16.0 * zc * nt * (double)nn * nn * P.nslot;
       const double bytes = sizeof(T) * (kel + (double)zc * nt * P.nslot * 2.0 * nn * 4 + (double)zc * nd * nn * 4);
       pr = prof_begin(ctx, sizeof(T) == 8 ? TRAP_STAGE_CONTRACT_FP64 : TRAP_STAGE_CONTRACT, flops, bytes);
     }
-    hipLaunchKernelGGL(k_contract<T>, grid, dim3(256), 0, s, z0, nth, nt, nn, nd, Mk, Ibar, P.d_slot_off,
-                       P.d_slot_dir, W, P.nslot);
+    hipLaunchKernelGGL(k_contract<T>, grid, dim3(512), 0, s, z0, nth, nt, nn, P.ldm, nd, Mk, Ibar,
+                       P.d_slot_off, P.d_slot_dir, W, P.nslot);
     TRAP_HIP(hipGetLastError());
     prof_end(ctx, pr);
     // 3. R_III factors

@@ -49,7 +49,8 @@ struct DevBuf {
 // Index conventions (all row-major, last index fastest):
 //   vectors        V[z][o][n][s]
 //   spline map     P[k][p][m]      interval k (0..nn-2), power p of t=(x-x_k)/h_k, node m
-//   kernels        M[z][theta][t][c][n][m]   c = 0 real / 1 imaginary, row n, column m (ld = nn)
+//   kernels        M[z][theta][t][c][n][m]   c = 0 real / 1 imaginary, row n, column m
+//                  (row stride ldm >= nn, zero padded)
 //   W intermediate W[zc][t][slot][c][n][s]   (height chunk zc)
 //   eps_bar        Eb[z][l][l'][o][n][s]
 //   E table        E[z][o][i][u'][u][l']   = d_{u'l'}^T Acart_i(o) d^*_{u l'}
@@ -59,6 +60,7 @@ struct Problem {
   int nz = 0, nn = 0, nmu = 0, nchi = 0, nd = 0;
   int nth = 0, nslot = 0, nu = 0, nl = 0, nt = 0;
   int max_slots_per_theta = 0;
+  int ldm = 0;                             // padded row length of the stored kernels (multiple of 8)
   double c_abs = 0, c_sc = 0;
   // host copies used by host-side logic
   std::vector<double> x, mu, w, tau, lam, a, eps, WT, eta0, dnuD;
