@@ -287,7 +287,8 @@ cd stokes_form(int j, const cd* d1, const cd* d2, const double* ea, const double
 
 // Not-a-knot cubic spline coefficient map on nodes x: on interval k with
 // t = (y - x_k)/h_k the interpolant of values v is sum_p P[k][p][m] v_m t^p.
-std::vector<double> spline_map(const std::vector<double>& x) {
+// sig_out (optional) receives the second-derivative map Sig[i][m] = d s_i / d v_m.
+std::vector<double> spline_map(const std::vector<double>& x, std::vector<double>* sig_out = nullptr) {
   const int n = static_cast<int>(x.size());
   std::vector<double> h(n - 1);
   for (int k = 0; k < n - 1; ++k) h[k] = x[k + 1] - x[k];
@@ -334,6 +335,7 @@ std::vector<double> spline_map(const std::vector<double>& x) {
       S[c * n + k] = v / M[c * n + c];
     }
   }
+  if (sig_out) *sig_out = S;
   // S[i][m] = d s_i / d v_m.  Coefficients in t:
   //   c0 = v_k, c1 = v_{k+1} - v_k - h^2 (2 s_k + s_{k+1})/6, c2 = h^2 s_k/2, c3 = h^2 (s_{k+1} - s_k)/6
   std::vector<double> P((n - 1) * 4 * n, 0.0);
@@ -569,11 +571,13 @@ int build_problem(trap_ctx* ctx, const trap_atom_desc* at, const trap_problem_de
     }
   }
   // ---- upload
-  auto spl = spline_map(P.x);
+  std::vector<double> sig;
+  auto spl = spline_map(P.x, &sig);
   int nsl = P.nslot;
   (void)nsl;
   TRAP_TRY(upload_t(ctx, &P.d_x, P.x));
   TRAP_TRY(upload_t(ctx, &P.d_P, spl));
+  TRAP_TRY(upload_t(ctx, &P.d_Sig, sig));
   TRAP_TRY(upload_t(ctx, &P.d_mu, P.mu));
   TRAP_TRY(upload_t(ctx, &P.d_w, P.w));
   TRAP_TRY(upload_t(ctx, &P.d_tau, P.tau));

@@ -152,29 +152,85 @@ __device__ inline int upper_interval(const double* x, int nn, double v) {
   return lo;
 }
 
+// ------------------------------------------------------------------ factor tables (uniform grids)
+// On a uniform grid x_k = x_0 + k h with the same 16 Gauss-Legendre nodes t_i
+// in every knot interval, the node x' = x_k + h t_i of interval k seen from row
+// n has  x_n - x' = h (n - k - t_i)  and  x_n + x' = 2 x_0 + h (n + k + t_i).
+// The Gaussian factor of F therefore depends on (d = n - k, i) only and the
+// Faddeeva factor on (p = n + k, i) only; both are tabulated per (height,
+// Theta[, transition]) so the row integration needs no transcendental calls.
+//   G[d + nn - 1][i] = exp(-(lam h (d - t_i) / (2 sin(Theta/2)))^2)
+//   V[p][i]          = W(a/cos(Theta/2), (lam (2 x_0 + h (p + t_i)) + 2 s)/(2 cos(Theta/2)))
+// (Theta = pi: exp(-(lam h (d - t_i)/2)^2) and i/(2 sqrt(pi)(m + i a)), m = half the sum.)
+__global__ void k_kernel_tables(int z0, int nth, int nt, int nn, double x0, double h,
+                                const double* __restrict__ lam, const double* __restrict__ av,
+                                const double* __restrict__ st, const double* __restrict__ theta,
+                                double* __restrict__ Gt, double2* __restrict__ Vt) {
+  const int t = blockIdx.x % nt;
+  const int th = (blockIdx.x / nt) % nth;
+  const int zl = blockIdx.x / (nt * nth);
+  const int z = z0 + zl;
+  const double L = lam[z], a = av[z], s = st[z * nt + t], Th = theta[th];
+  if (Th == 0.0) return;
+  const bool pil = Th >= kPiD;
+  const double sG = pil ? 1.0 : sin(0.5 * Th), cG = pil ? 0.0 : cos(0.5 * Th);
+  const int nd2 = 2 * nn - 1;
+  double2* V = Vt + ((size_t)(zl * nth + th) * nt + t) * nd2 * 16;
+  for (int e = threadIdx.x; e < nd2 * 16; e += blockDim.x) {
+    const int p = e >> 4, i = e & 15;
+    const double xs = 2.0 * x0 + h * (p + c_gl_t[i]);
+    if (pil) {
+      const double m = 0.5 * (L * xs + 2.0 * s);
+      const double d = 2.0 * kSqrtPi * (m * m + a * a);
+      V[e] = make_double2(a / d, m / d);
+    } else {
+      V[e] = wz((L * xs + 2.0 * s) / (2.0 * cG), a / cG);
+    }
+  }
+  if (t == 0) {
+    double* G = Gt + (size_t)(zl * nth + th) * nd2 * 16;
+    for (int e = threadIdx.x; e < nd2 * 16; e += blockDim.x) {
+      const int dd = (e >> 4) - (nn - 1), i = e & 15;
+      const double q = L * h * (dd - c_gl_t[i]) / (2.0 * sG);
+      G[e] = exp(-q * q);
+    }
+  }
+}
+
 // ------------------------------------------------------------------ R_II kernel rows
-// One 64-thread block per row (z, theta, t, n).
+// One 64-thread block per complex row (z, theta, t, n) of a height chunk.
+// The integral of F against the spline piece on interval k is written with the
+// piece's node values v_k, v_{k+1} and second derivatives s_k, s_{k+1}:
+//   int F S = mu0 v_k + mu1 (v_{k+1} - v_k)
+//           + h^2 (-mu1/3 + mu2/2 - mu3/6) s_k + h^2 (mu3 - mu1)/6 s_{k+1},
+// mu_q = int_0^1 F t^q.  Collecting per node gives the row as
+//   M[n][m] = L[m] + sum_j Gam[j] Sig[j][m]
+// with Sig = d s / d v the spline's second-derivative map; L and Gam are
+// written here, the dense product is one batched GEMM (k_sig_gemm).
 __global__ void __launch_bounds__(64) k_kernel_rows(
-    int nth, int nt, int nn, int ldm, const double* __restrict__ x, const double* __restrict__ P,
+    int nth, int nt, int nn, int ldm, const double* __restrict__ x,
     const double* __restrict__ lam, const double* __restrict__ av, const double* __restrict__ st,
-    const double* __restrict__ theta, double* __restrict__ M64, float* __restrict__ M32,
-    long long row0) {
+    const double* __restrict__ theta, double* __restrict__ Lout, double* __restrict__ Gout,
+    long long row0, int z0, double h_uniform, const double* __restrict__ Gt,
+    const double2* __restrict__ Vt) {
   extern __shared__ double2 mom[];     // [(nn+1)][4], piece index shifted by one
   const long long row = row0 + blockIdx.x;
   const int lane = threadIdx.x;
   const int n = row % nn;
   const int t = (row / nn) % nt;
   const int th = (row / ((long long)nn * nt)) % nth;
-  const int z = row / ((long long)nn * nt * nth);
+  const int z = z0 + (int)(row / ((long long)nn * nt * nth));
   const double L = lam[z], a = av[z], s = st[z * nt + t], Th = theta[th];
-  const size_t base = (size_t)((((size_t)z * nth + th) * nt + t) * 2) * nn * ldm;
-  const size_t rre = base + (size_t)n * ldm, rim = base + (size_t)nn * ldm + (size_t)n * ldm;
+  // chunk-local row index of the real plane; the imaginary plane follows nn rows later
+  const size_t cbase = (size_t)((((size_t)(z - z0) * nth + th) * nt + t) * 2) * nn * ldm;
+  const size_t rre = cbase + (size_t)n * ldm, rim = cbase + (size_t)nn * ldm + (size_t)n * ldm;
   if (Th == 0.0) {
     const double2 w = wz(L * x[n] + s, a);
     for (int m = lane; m < ldm; m += 64) {
-      const double re = (m == n) ? kSqrtPi * w.x : 0.0, im = (m == n) ? kSqrtPi * w.y : 0.0;
-      if (M64) { M64[rre + m] = re; M64[rim + m] = im; }
-      if (M32) { M32[rre + m] = (float)re; M32[rim + m] = (float)im; }
+      Lout[rre + m] = (m == n) ? kSqrtPi * w.x : 0.0;
+      Lout[rim + m] = (m == n) ? kSqrtPi * w.y : 0.0;
+      Gout[rre + m] = 0.0;
+      Gout[rim + m] = 0.0;
     }
     return;
   }
@@ -202,40 +258,152 @@ __global__ void __launch_bounds__(64) k_kernel_rows(
     const double2 F = Ffun(fp, L * xp + s, un);
     return make_double2(L * F.x, L * F.y);
   };
-  for (int p = plo + lane; p <= phi; p += 64) {
+  // table fast path: uniform grid, Gaussian resolved by the interval nodes
+  const bool fast = (Gt != nullptr) && (sigma >= 0.5 * h_uniform);
+  const int nd2 = 2 * nn - 1;
+  const double* Grow = fast ? Gt + (size_t)((z - z0) * nth + th) * nd2 * 16 : nullptr;
+  const double2* Vrow = fast ? Vt + ((size_t)((z - z0) * nth + th) * nt + t) * nd2 * 16 : nullptr;
+  const double fscale = L * h_uniform * (fp.pi_limit ? 1.0 : fp.inv_sinT);
+  const bool sharp = wc < h_uniform;      // Voigt core narrower than an interval
+  // knot intervals inside the support: one lane per interval
+  const int ilo = max(plo, 0), ihi = min(phi, nn - 2);
+  for (int p = ilo + lane; p <= ihi; p += 64) {
     double2 acc[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
-    if (p < 0) {
-      graded_integrate(lo, x[0], xc, wc, Lg, 0.0, 0.0, 1, integrand, acc);
-    } else if (p >= nn - 1) {
-      graded_integrate(x[nn - 1], hi, xc, wc, Lg, 0.0, 0.0, 1, integrand, acc);
+    const bool near_core = sharp && xc > x[p] - h_uniform && xc < x[p + 1] + h_uniform;
+    if (fast && !near_core) {
+      const double* g = Grow + (size_t)(n - p + nn - 1) * 16;
+      const double2* v = Vrow + (size_t)(n + p) * 16;
+      for (int i = 0; i < 16; ++i) {
+        const double f = fscale * c_gl_w[i] * g[i];
+        const double2 vv = v[i];
+        double tp = f;
+        const double ti = c_gl_t[i];
+        for (int q = 0; q < 4; ++q) {
+          acc[q].x += tp * vv.x;
+          acc[q].y += tp * vv.y;
+          tp *= ti;
+        }
+      }
     } else {
       const double pa = fmax(x[p], lo), pb = fmin(x[p + 1], hi);
       graded_integrate(pa, pb, xc, wc, Lg, x[p], 1.0 / (x[p + 1] - x[p]), 4, integrand, acc);
     }
     for (int q = 0; q < 4; ++q) mom[(p + 1) * 4 + q] = acc[q];
   }
-  __syncthreads();
-  const int klo = max(plo, 0), khi = min(phi, nn - 2);
-  for (int m = lane; m < ldm; m += 64) {
-    double re = 0.0, im = 0.0;
-    if (m >= nn) {      // zero padding of the row
-      if (M64) { M64[rre + m] = 0.0; M64[rim + m] = 0.0; }
-      if (M32) { M32[rre + m] = 0.0f; M32[rim + m] = 0.0f; }
-      continue;
+  // tails beyond the grid (flat extension: they weigh the edge nodes); each
+  // tail is split into 64 equal pieces, one per lane, then reduced
+  __shared__ double2 tred[2][64];
+  for (int side = 0; side < 2; ++side) {
+    const bool present = side == 0 ? (plo < 0) : (phi >= nn - 1);
+    double2 acc = make_double2(0.0, 0.0);
+    if (present) {
+      const double ta = side == 0 ? lo : x[nn - 1];
+      const double tb = side == 0 ? x[0] : hi;
+      const double wpiece = (tb - ta) / 64.0;
+      const double pa = ta + wpiece * lane, pb = (lane == 63) ? tb : ta + wpiece * (lane + 1);
+      graded_integrate(pa, pb, xc, wc, Lg, 0.0, 0.0, 1, integrand, &acc);
     }
-    for (int k = klo; k <= khi; ++k) {
-      const double* pk = P + (size_t)k * 4 * nn + m;
-      for (int q = 0; q < 4; ++q) {
-        const double c = pk[(size_t)q * nn];
-        const double2 mm = mom[(k + 1) * 4 + q];
-        re += c * mm.x;
-        im += c * mm.y;
+    tred[side][lane] = acc;
+  }
+  __syncthreads();
+  if (lane < 2) {
+    double2 tot = make_double2(0.0, 0.0);
+    for (int i = 0; i < 64; ++i) {
+      tot.x += tred[lane][i].x;
+      tot.y += tred[lane][i].y;
+    }
+    mom[(lane == 0 ? 0 : nn) * 4] = tot;
+  }
+  __syncthreads();
+  // per node m: L[m] = (mu0 - mu1)_m + (mu1)_{m-1} (+ tails), Gam[m] = g_m + e_{m-1}
+  for (int m = lane; m < ldm; m += 64) {
+    double lr = 0.0, li = 0.0, gr = 0.0, gi = 0.0;
+    if (m < nn) {
+      if (m <= nn - 2) {          // interval m starts at node m
+        const double2 m0 = mom[(m + 1) * 4 + 0], m1 = mom[(m + 1) * 4 + 1];
+        const double2 m2 = mom[(m + 1) * 4 + 2], m3 = mom[(m + 1) * 4 + 3];
+        const double hh = (x[m + 1] - x[m]) * (x[m + 1] - x[m]);
+        lr += m0.x - m1.x;
+        li += m0.y - m1.y;
+        gr += hh * (-m1.x / 3.0 + 0.5 * m2.x - m3.x / 6.0);
+        gi += hh * (-m1.y / 3.0 + 0.5 * m2.y - m3.y / 6.0);
+      }
+      if (m >= 1) {               // interval m-1 ends at node m
+        const double2 m1 = mom[m * 4 + 1], m3 = mom[m * 4 + 3];
+        const double hh = (x[m] - x[m - 1]) * (x[m] - x[m - 1]);
+        lr += m1.x;
+        li += m1.y;
+        gr += hh * (m3.x - m1.x) / 6.0;
+        gi += hh * (m3.y - m1.y) / 6.0;
+      }
+      if (m == 0) { lr += mom[0].x; li += mom[0].y; }
+      if (m == nn - 1) { lr += mom[nn * 4].x; li += mom[nn * 4].y; }
+    }
+    Lout[rre + m] = lr;
+    Lout[rim + m] = li;
+    Gout[rre + m] = gr;
+    Gout[rim + m] = gi;
+  }
+}
+
+// ------------------------------------------------------------------ M = L + Gam Sig on matrix cores
+// rows = every (theta, t, plane, n) of a height chunk; K = columns = nn.
+// v_mfma_f64_16x16x4: A_in = Gam tile, B_in = Sig tile; lane l holds
+// D[(l/16) + 4 r][l % 16].  Block: 4 waves x 16 rows = 64 rows, 8 column tiles.
+constexpr int kSigColTiles = 8;
+typedef double doublex4_g __attribute__((ext_vector_type(4)));
+
+__global__ void __launch_bounds__(256) k_sig_gemm(long long nrows, int nn, int ldm,
+                                                  const double* __restrict__ Gam,
+                                                  const double* __restrict__ Lrow,
+                                                  const double* __restrict__ Sig,
+                                                  double* __restrict__ M64, float* __restrict__ M32,
+                                                  long long out_row0) {
+  constexpr int KC = 16;
+  __shared__ double As[64][KC + 1];
+  __shared__ double Bs[KC][kSigColTiles * 16 + 4];
+  const long long row0 = (long long)blockIdx.x * 64;
+  const int col_base = blockIdx.y * kSigColTiles * 16;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int lr = lane & 15, lk = lane >> 4;
+  doublex4_g acc[kSigColTiles];
+  for (int j = 0; j < kSigColTiles; ++j)
+    for (int r = 0; r < 4; ++r) acc[j][r] = 0.0;
+  for (int k0 = 0; k0 < nn; k0 += KC) {
+    for (int e = tid; e < 64 * KC; e += 256) {
+      const int r = e / KC, kk = e % KC;
+      const long long gr = row0 + r;
+      const int gk = k0 + kk;
+      As[r][kk] = (gr < nrows && gk < nn) ? Gam[gr * ldm + gk] : 0.0;
+    }
+    for (int e = tid; e < KC * kSigColTiles * 16; e += 256) {
+      const int kk = e / (kSigColTiles * 16), c = e % (kSigColTiles * 16);
+      const int gk = k0 + kk, gc = col_base + c;
+      Bs[kk][c] = (gk < nn && gc < nn) ? Sig[(size_t)gk * nn + gc] : 0.0;
+    }
+    __syncthreads();
+    for (int kk = 0; kk < KC; kk += 4) {
+      const double af = As[wave * 16 + lr][kk + lk];
+#pragma unroll
+      for (int j = 0; j < kSigColTiles; ++j) {
+        const double bf = Bs[kk + lk][j * 16 + lr];
+        acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af, bf, acc[j], 0, 0, 0);
       }
     }
-    if (m == 0) { re += mom[0].x; im += mom[0].y; }
-    if (m == nn - 1) { re += mom[nn * 4].x; im += mom[nn * 4].y; }
-    if (M64) { M64[rre + m] = re; M64[rim + m] = im; }
-    if (M32) { M32[rre + m] = (float)re; M32[rim + m] = (float)im; }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int j = 0; j < kSigColTiles; ++j) {
+    const int col = col_base + j * 16 + lr;
+    if (col >= ldm) continue;
+    for (int r = 0; r < 4; ++r) {
+      const long long gr = row0 + wave * 16 + lk + 4 * r;
+      if (gr >= nrows) continue;
+      const double v = (col < nn) ? acc[j][r] + Lrow[gr * ldm + col] : 0.0;
+      const size_t o = (size_t)(out_row0 + gr) * ldm + col;
+      if (M64) M64[o] = v;
+      if (M32) M32[o] = (float)v;
+    }
   }
 }
 
@@ -382,16 +550,51 @@ int run_precompute(trap_ctx* ctx, int store_mask) {
   if ((mask & 1) && !C.d_M64) TRAP_TRY(dalloc_t(ctx, &C.d_M64, kelems));
   if ((mask & 2) && !C.d_M32) TRAP_TRY(dalloc_t(ctx, &C.d_M32, kelems));
   C.store_mask = mask;
-  const long long nrows = (long long)nz * nth * nt * nn;
   const size_t lds = (size_t)(nn + 1) * 4 * sizeof(double2);
   if (lds > 64 * 1024) return fail(TRAP_EINVAL, "frequency grid too large for the kernel precompute");
-  const long long chunk = 1 << 20;
+  // uniform grid -> factor tables, heights in chunks so the tables stay cache sized
+  const double h = (P.x[nn - 1] - P.x[0]) / (nn - 1);
+  bool uniform = true;
+  for (int k = 0; k + 1 < nn; ++k)
+    if (std::fabs(P.x[k + 1] - P.x[k] - h) > 1e-12 * std::fabs(h)) uniform = false;
+  const int nd2 = 2 * nn - 1;
+  const size_t tab_per_z = (size_t)nth * nd2 * 16 * (sizeof(double) + nt * sizeof(double2));
+  const size_t rows_per_z = (size_t)nth * nt * 2 * nn;
+  const size_t lg_per_z = rows_per_z * P.ldm * sizeof(double) * 2;
+  size_t zc_lim = std::max<size_t>(1, (size_t(1) << 30) / lg_per_z);
+  if (uniform) zc_lim = std::min(zc_lim, std::max<size_t>(1, (size_t(192) << 20) / tab_per_z));
+  const int zc_tab = (int)std::min<size_t>(nz, zc_lim);
+  if (uniform && !C.d_Gt) {
+    TRAP_TRY(dalloc_t(ctx, &C.d_Gt, (size_t)zc_tab * nth * nd2 * 16));
+    TRAP_TRY(dalloc_t(ctx, &C.d_Vt, (size_t)zc_tab * nth * nt * nd2 * 16));
+  }
+  if (!C.d_Lrow || C.zc_rows < zc_tab) {
+    TRAP_TRY(dalloc_t(ctx, &C.d_Lrow, (size_t)zc_tab * rows_per_z * P.ldm));
+    TRAP_TRY(dalloc_t(ctx, &C.d_Grow, (size_t)zc_tab * rows_per_z * P.ldm));
+    C.zc_rows = zc_tab;
+  }
   const int pr = prof_begin(ctx, TRAP_STAGE_KERNEL_ROWS);
-  for (long long r0 = 0; r0 < nrows; r0 += chunk) {
-    const long long nr = std::min(chunk, nrows - r0);
-    hipLaunchKernelGGL(k_kernel_rows, dim3((unsigned)nr), dim3(64), lds, s, nth, nt, nn, P.ldm, P.d_x, P.d_P,
-                       P.d_lam, P.d_a, P.d_st, P.d_theta, (mask & 1) ? C.d_M64 : nullptr,
-                       (mask & 2) ? C.d_M32 : nullptr, r0);
+  for (int z0 = 0; z0 < nz; z0 += zc_tab) {
+    const int zc = std::min(zc_tab, nz - z0);
+    if (uniform) {
+      hipLaunchKernelGGL(k_kernel_tables, dim3(zc * nth * nt), dim3(256), 0, s, z0, nth, nt, nn, P.x[0], h,
+                         P.d_lam, P.d_a, P.d_st, P.d_theta, C.d_Gt, C.d_Vt);
+      TRAP_HIP(hipGetLastError());
+    }
+    const long long nrows = (long long)zc * nth * nt * nn;      // complex rows of this chunk
+    const long long chunk = 1 << 20;
+    for (long long r0 = 0; r0 < nrows; r0 += chunk) {
+      const long long nr = std::min(chunk, nrows - r0);
+      hipLaunchKernelGGL(k_kernel_rows, dim3((unsigned)nr), dim3(64), lds, s, nth, nt, nn, P.ldm, P.d_x,
+                         P.d_lam, P.d_a, P.d_st, P.d_theta, C.d_Lrow, C.d_Grow, r0, z0, h,
+                         uniform ? C.d_Gt : nullptr, uniform ? C.d_Vt : nullptr);
+      TRAP_HIP(hipGetLastError());
+    }
+    const long long rrows = 2 * nrows;                           // real rows (both planes)
+    dim3 gg(ceil_div(rrows, 64), ceil_div(P.ldm, kSigColTiles * 16));
+    hipLaunchKernelGGL(k_sig_gemm, gg, dim3(256), 0, s, rrows, nn, P.ldm, C.d_Grow, C.d_Lrow, P.d_Sig,
+                       (mask & 1) ? C.d_M64 : nullptr, (mask & 2) ? C.d_M32 : nullptr,
+                       (long long)z0 * nth * nt * 2 * nn);
     TRAP_HIP(hipGetLastError());
   }
   prof_end(ctx, pr);

@@ -71,6 +71,7 @@ struct Problem {
   std::vector<int> pair_theta;             // [nd][nd]
   // device copies
   double *d_x = nullptr, *d_P = nullptr, *d_mu = nullptr, *d_w = nullptr, *d_tau = nullptr;
+  double *d_Sig = nullptr;                 // [nn][nn] second-derivative map of the spline
   double *d_lam = nullptr, *d_a = nullptr, *d_eps = nullptr, *d_WT = nullptr, *d_eta0 = nullptr;
   double *d_ub = nullptr;                  // [nz][nd] reduced Doppler shift (u units)
   double *d_st = nullptr;                  // [nz][nt] reduced transition shifts
@@ -93,6 +94,11 @@ struct Precomp {
   double2 *d_r3 = nullptr;    // [z][t][n] R_III incoming weights
   double2 *d_prof = nullptr;  // [z][t][n] outgoing profiles on the comoving grid
   double *d_b = nullptr;      // right-hand side, FP64 vector
+  double *d_Gt = nullptr;     // Gaussian factor table of the kernel precompute (uniform grids)
+  double2 *d_Vt = nullptr;    // Faddeeva factor table of the kernel precompute (uniform grids)
+  double *d_Lrow = nullptr;   // local part of the kernel rows, [rows][ldm] (height chunk)
+  double *d_Grow = nullptr;   // second-derivative weights of the kernel rows, [rows][ldm]
+  int zc_rows = 0;            // heights per precompute chunk
 };
 
 struct Work {
