@@ -167,9 +167,9 @@ int trap_set_problem(trap_ctx* ctx, const trap_atom_desc* atom, const trap_probl
     free_all(ctx);
     return fail(s, msg);
   }
-  if (ctx->pb.nl > 8 || ctx->pb.nu > 16) {
+  if (ctx->pb.nl > 8 || ctx->pb.nu > 16 || ctx->pb.nchi > 16) {
     free_all(ctx);
-    return fail(TRAP_EINVAL, "atom too large (at most 16 upper and 8 lower sublevels)");
+    return fail(TRAP_EINVAL, "too many sublevels or azimuths (n_lower <= 8, n_upper <= 16, n_chi <= 16)");
   }
   hipError_t e = hipStreamSynchronize(ctx->stream);
   if (e != hipSuccess) {

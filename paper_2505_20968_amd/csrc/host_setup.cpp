@@ -578,6 +578,10 @@ int build_problem(trap_ctx* ctx, const trap_atom_desc* at, const trap_problem_de
   TRAP_TRY(upload_t(ctx, &P.d_x, P.x));
   TRAP_TRY(upload_t(ctx, &P.d_P, spl));
   TRAP_TRY(upload_t(ctx, &P.d_Sig, sig));
+  std::vector<double> sigT(sig.size());
+  for (int i = 0; i < nn; ++i)
+    for (int j = 0; j < nn; ++j) sigT[(size_t)j * nn + i] = sig[(size_t)i * nn + j];
+  TRAP_TRY(upload_t(ctx, &P.d_SigT, sigT));
   TRAP_TRY(upload_t(ctx, &P.d_mu, P.mu));
   TRAP_TRY(upload_t(ctx, &P.d_w, P.w));
   TRAP_TRY(upload_t(ctx, &P.d_tau, P.tau));

@@ -22,63 +22,86 @@ namespace trap {
 static constexpr double kInvPi = 0.31830988618379067154;
 
 // ------------------------------------------------------------------ spline evaluation
-// out[z][o][n][s] (+)= scale * S[in[z][o][:][s]](x_n + shift(z,o)) for the
-// given class, flat extension outside [x_0, x_{nn-1}].
-//   in:  stride between (z,o) records = in_zo_stride, node stride 4
-//   shift (x units) = (sign * ub[z][o] + sll[z][cls]) / lam[z]
+// out[z][o][n][s] (+)= S[in[z][o][:][s]](x_n + shift) for one (l, l') class,
+// flat extension outside [x_0, x_{nn-1}];  shift (x units) =
+// (ub_sign * ub[z][o] + sll[z][cls]) / lam[z].  One block per (z, o): the
+// column goes to LDS, the spline's second derivatives s = Sig v (Sig^T stored,
+// so the reads are coalesced) are formed once, then every frequency evaluates
+//   S(x) = (1-t) v_k + t v_{k+1} + h^2 [((1-t)^3 - (1-t)) s_k + (t^3 - t) s_{k+1}] / 6.
+// Optionally multiplies Stokes I by f and adds eps_th.
 template <typename T>
-__global__ void k_spline_shift(int nz0, int nzc, int nd, int nn, const double* __restrict__ x,
-                               const double* __restrict__ P, const double* __restrict__ lam,
-                               const double* __restrict__ ub, double ub_sign,
-                               const double* __restrict__ sll, int ncls, int cls,
-                               const T* __restrict__ in, long long in_z_stride, long long in_o_stride,
-                               T* __restrict__ out, int accumulate, const double* __restrict__ f,
-                               const double* __restrict__ epsth) {
-  const long long id = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  const long long total = (long long)nzc * nd * nn;
-  if (id >= total) return;
-  const int n = id % nn;
-  const int o = (id / nn) % nd;
-  const int zl = id / ((long long)nn * nd);
+__global__ void __launch_bounds__(128) k_spline_shift(
+    int nz0, int nzc, int nd, int nn, const double* __restrict__ x, const double* __restrict__ SigT,
+    const double* __restrict__ lam, const double* __restrict__ ub, double ub_sign,
+    const double* __restrict__ sll, int ncls, int cls, const T* __restrict__ in, long long in_z_stride,
+    long long in_o_stride, T* __restrict__ out, int accumulate, const double* __restrict__ f,
+    const double* __restrict__ epsth) {
+  extern __shared__ double spl[];
+  double* v = spl;               // [nn][4]
+  double* sd = spl + 4 * nn;     // [nn][4]
+  const int zl = blockIdx.x / nd, o = blockIdx.x % nd;
   const int z = nz0 + zl;
   const double L = lam[z];
   double sh = ub_sign * ub[(long long)z * nd + o];
   if (sll) sh += sll[(long long)z * ncls + cls];
-  const double xs = x[n] + sh / L;
   const T* src = in + zl * in_z_stride + o * in_o_stride;
-  double v[4];
-  if (sh == 0.0) {
-    for (int s = 0; s < 4; ++s) v[s] = (double)src[n * 4 + s];
-  } else if (xs <= x[0]) {
-    for (int s = 0; s < 4; ++s) v[s] = (double)src[s];
-  } else if (xs >= x[nn - 1]) {
-    for (int s = 0; s < 4; ++s) v[s] = (double)src[(nn - 1) * 4 + s];
-  } else {
-    int lo = 0, hi = nn - 1;
-    while (hi - lo > 1) {
-      const int mid = (lo + hi) >> 1;
-      if (x[mid] <= xs) lo = mid; else hi = mid;
+  const bool shifted = sh != 0.0;
+  if (shifted) {
+    for (int e = threadIdx.x; e < 4 * nn; e += blockDim.x) v[e] = (double)src[e];
+    __syncthreads();
+    for (int m = threadIdx.x; m < nn; m += blockDim.x) {
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+      for (int j = 0; j < nn; ++j) {
+        const double g = SigT[(size_t)j * nn + m];
+        a0 += g * v[4 * j];
+        a1 += g * v[4 * j + 1];
+        a2 += g * v[4 * j + 2];
+        a3 += g * v[4 * j + 3];
+      }
+      sd[4 * m] = a0;
+      sd[4 * m + 1] = a1;
+      sd[4 * m + 2] = a2;
+      sd[4 * m + 3] = a3;
     }
-    const int k = lo;
-    const double t = (xs - x[k]) / (x[k + 1] - x[k]);
-    const double t2 = t * t, t3 = t2 * t;
-    const double* pk = P + (size_t)k * 4 * nn;
-    for (int s = 0; s < 4; ++s) v[s] = 0.0;
-    for (int m = 0; m < nn; ++m) {
-      const double wgt = pk[m] + t * pk[nn + m] + t2 * pk[2 * nn + m] + t3 * pk[3 * nn + m];
-      for (int s = 0; s < 4; ++s) v[s] += wgt * (double)src[m * 4 + s];
+    __syncthreads();
+  }
+  const double dx = sh / L;
+  for (int n = threadIdx.x; n < nn; n += blockDim.x) {
+    double val[4];
+    if (!shifted) {
+      for (int q = 0; q < 4; ++q) val[q] = (double)src[n * 4 + q];
+    } else {
+      const double xs = x[n] + dx;
+      if (xs <= x[0]) {
+        for (int q = 0; q < 4; ++q) val[q] = v[q];
+      } else if (xs >= x[nn - 1]) {
+        for (int q = 0; q < 4; ++q) val[q] = v[4 * (nn - 1) + q];
+      } else {
+        int lo = 0, hi = nn - 1;
+        while (hi - lo > 1) {
+          const int mid = (lo + hi) >> 1;
+          if (x[mid] <= xs) lo = mid; else hi = mid;
+        }
+        const double h = x[lo + 1] - x[lo];
+        const double t = (xs - x[lo]) / h, u = 1.0 - t;
+        const double cs = h * h / 6.0;
+        const double wk = cs * (u * u * u - u), wk1 = cs * (t * t * t - t);
+        for (int q = 0; q < 4; ++q)
+          val[q] = u * v[4 * lo + q] + t * v[4 * lo + 4 + q] + wk * sd[4 * lo + q] + wk1 * sd[4 * lo + 4 + q];
+      }
     }
-  }
-  T* dst = out + id * 4;
-  if (f) v[0] *= f[(long long)z * nd * nn + (long long)o * nn + n];
-  if (epsth) {
-    const double* e = epsth + ((long long)z * nd * nn + (long long)o * nn + n) * 4;
-    for (int s = 0; s < 4; ++s) v[s] += e[s];
-  }
-  if (accumulate) {
-    for (int s = 0; s < 4; ++s) dst[s] = (T)((double)dst[s] + v[s]);
-  } else {
-    for (int s = 0; s < 4; ++s) dst[s] = (T)v[s];
+    const long long pidx = ((long long)z * nd + o) * nn + n;
+    if (f) val[0] *= f[pidx];
+    if (epsth) {
+      const double* e = epsth + pidx * 4;
+      for (int q = 0; q < 4; ++q) val[q] += e[q];
+    }
+    T* dst = out + (((long long)zl * nd + o) * nn + n) * 4;
+    if (accumulate) {
+      for (int q = 0; q < 4; ++q) dst[q] = (T)((double)dst[q] + val[q]);
+    } else {
+      for (int q = 0; q < 4; ++q) dst[q] = (T)val[q];
+    }
   }
 }
 
@@ -307,74 +330,101 @@ __global__ void k_r3_X(int z0, int nu, int nl, int nd, const double* __restrict_
 }
 
 // ------------------------------------------------------------------ angular / sublevel sum
-// One block per (zl, o, n-block of blockDim); one frequency per thread.
-// Eb[zl][l][l'][o][n][i].
+// One block per (zl, mu index, block of 32 frequencies); thread (k, n) handles
+// outgoing direction (mu, chi_k) at one frequency, so the mirror directions
+// that read the same W slot sit in one block.  For a chunk of incoming
+// directions the 4x4 coefficients
+//   C^{u' l, l'}_ij(o, o') = (c_sc w_o'/pi) sum_u alpha_{u u'} E_i(o; u', u, l') A_j(o'; u, u', l)
+// are built in LDS by the whole block; the accumulation Re sum_j C_ij W_j then
+// runs without barriers.
+constexpr int kAngN = 32;
+
 template <typename T>
-__global__ void __launch_bounds__(128) k_angular(
-    int z0, int nd, int nn, int nu, int nl, int nslot, double c_sc, const double* __restrict__ w,
-    const double2* __restrict__ E, const double2* __restrict__ A, const double2* __restrict__ alpha,
-    const double2* __restrict__ bma, const int* __restrict__ pair_slot, const T* __restrict__ W,
-    const double2* __restrict__ X, const double2* __restrict__ prof, T* __restrict__ Eb, int do_RII) {
+__global__ void __launch_bounds__(512) k_angular(
+    int z0, int nd, int nchi, int nn, int nu, int nl, int nslot, int oc_max, double c_sc,
+    const double* __restrict__ w, const double2* __restrict__ E, const double2* __restrict__ A,
+    const double2* __restrict__ alpha, const double2* __restrict__ bma, const int* __restrict__ pair_slot,
+    const T* __restrict__ W, const double2* __restrict__ X, const double2* __restrict__ prof,
+    T* __restrict__ Eb) {
   extern __shared__ double2 sh[];
-  const int zl = blockIdx.x / nd, o = blockIdx.x % nd;
+  const int nmu = nd / nchi;
+  const int zl = blockIdx.x / nmu, imu = blockIdx.x % nmu;
   const int z = z0 + zl;
-  const int n = blockIdx.y * blockDim.x + threadIdx.x;
-  const bool active = n < nn;
   const int nt = nu * nl;
-  double2* Cs = sh;                           // [nl(l')][4][4]
-  double2* Ds = sh + nl * 16;                 // [nl(l')][4][nu][nu]  R_III coefficients
-  const double2* Ez = E + ((size_t)z * nd + o) * 4 * nu * nu * nl;
+  const int o_first = imu * nchi;
+  const int k = threadIdx.x / kAngN;
+  const int n = blockIdx.y * kAngN + (threadIdx.x % kAngN);
+  const bool active = n < nn && k < nchi;
+  const int o = o_first + k;
+  double2* Cs = sh;
+  int* slots = reinterpret_cast<int*>(sh + (size_t)oc_max * nu * nchi * nl * 16);
+  double2* Ds = sh;
   for (int l = 0; l < nl; ++l) {
-    double acc[8][4];      // [l'][i], nl <= 8
+    double acc[8][4];
     for (int a = 0; a < 8; ++a)
       for (int i = 0; i < 4; ++i) acc[a][i] = 0.0;
-    if (do_RII) {
-      for (int op = 0; op < nd; ++op) {
-        const int sl = pair_slot[o * nd + op];
+    for (int o0 = 0; o0 < nd; o0 += oc_max) {
+      const int oc_n = min(oc_max, nd - o0);
+      __syncthreads();
+      const int nC = oc_n * nu * nchi * nl * 16;
+      for (int e = threadIdx.x; e < nC; e += blockDim.x) {
+        const int j = e & 3, i = (e >> 2) & 3;
+        int r = e >> 4;
+        const int lp = r % nl; r /= nl;
+        const int kk = r % nchi; r /= nchi;
+        const int upr = r % nu; r /= nu;
+        const int oc = r;
+        const int oo = o_first + kk, op = o0 + oc;
+        const double2* Ez = E + ((size_t)z * nd + oo) * 4 * nu * nu * nl;
         const double2* Az = A + ((size_t)z * nd + op) * 4 * nu * nu * nl;
+        double re = 0.0, im = 0.0;
+        for (int u = 0; u < nu; ++u) {
+          const double2 al = alpha[((size_t)z * nu + u) * nu + upr];
+          const double2 ee = Ez[((size_t)(i * nu + upr) * nu + u) * nl + lp];
+          const double2 aa = Az[((size_t)(j * nu + u) * nu + upr) * nl + l];
+          const double2 v = cmul(al, cmul(ee, aa));
+          re += v.x;
+          im += v.y;
+        }
         const double sc = c_sc * w[op] * kInvPi;
+        Cs[e] = make_double2(sc * re, sc * im);
+      }
+      for (int e = threadIdx.x; e < oc_n * nchi; e += blockDim.x) {
+        const int oc = e / nchi, kk = e % nchi;
+        slots[e] = pair_slot[(o_first + kk) * nd + o0 + oc];
+      }
+      __syncthreads();
+      if (!active) continue;
+      for (int oc = 0; oc < oc_n; ++oc) {
+        const int sl = slots[oc * nchi + k];
         for (int upr = 0; upr < nu; ++upr) {
-          __syncthreads();
-          for (int e = threadIdx.x; e < nl * 16; e += blockDim.x) {
-            const int lp = e >> 4, i = (e >> 2) & 3, j = e & 3;
-            double re = 0.0, im = 0.0;
-            for (int u = 0; u < nu; ++u) {
-              const double2 al = alpha[((size_t)z * nu + u) * nu + upr];
-              const double2 ee = Ez[((size_t)(i * nu + upr) * nu + u) * nl + lp];
-              const double2 aa = Az[((size_t)(j * nu + u) * nu + upr) * nl + l];
-              const double2 ea = cmul(ee, aa);
-              const double2 v = cmul(al, ea);
-              re += v.x;
-              im += v.y;
-            }
-            Cs[e] = make_double2(sc * re, sc * im);
-          }
-          __syncthreads();
           const int t = upr * nl + l;
           const T* Wp = W + (((size_t)zl * nt + t) * nslot + sl) * 2 * (size_t)nn * 4;
-          if (active) {
-            double wr[4], wi[4];
-            for (int j = 0; j < 4; ++j) {
-              wr[j] = (double)Wp[(size_t)n * 4 + j];
-              wi[j] = (double)Wp[(size_t)nn * 4 + (size_t)n * 4 + j];
-            }
-            for (int lp = 0; lp < nl; ++lp)
-              for (int i = 0; i < 4; ++i) {
-                double v = 0.0;
-                for (int j = 0; j < 4; ++j) {
-                  const double2 c = Cs[(lp * 4 + i) * 4 + j];
-                  v += c.x * wr[j] - c.y * wi[j];
-                }
-                acc[lp][i] += v;
+          typedef typename Vec4<T>::type V4;
+          const V4 a = *reinterpret_cast<const V4*>(Wp + (size_t)n * 4);
+          const V4 b = *reinterpret_cast<const V4*>(Wp + (size_t)nn * 4 + (size_t)n * 4);
+          const double wr[4] = {(double)a.x, (double)a.y, (double)a.z, (double)a.w};
+          const double wi[4] = {(double)b.x, (double)b.y, (double)b.z, (double)b.w};
+          const double2* Cb = Cs + (((size_t)oc * nu + upr) * nchi + k) * nl * 16;
+          for (int lp = 0; lp < nl; ++lp)
+            for (int i = 0; i < 4; ++i) {
+              double v = 0.0;
+              for (int jj = 0; jj < 4; ++jj) {
+                const double2 c = Cb[(lp * 4 + i) * 4 + jj];
+                v += c.x * wr[jj] - c.y * wi[jj];
               }
-          }
+              acc[lp][i] += v;
+            }
         }
       }
     }
-    // R_III: D[l'][i][u][u'] = c_sc/(4 pi) (beta-alpha)_{u u'} E_i(u', u, l') X[u][u'][l]
+    // R_III: D[k][l'][i][u][u'] = c_sc/(4 pi) (beta-alpha)_{u u'} E_i(o; u', u, l') X[u][u'][l]
     __syncthreads();
-    for (int e = threadIdx.x; e < nl * 4 * nu * nu; e += blockDim.x) {
-      const int upr = e % nu, u = (e / nu) % nu, i = (e / (nu * nu)) % 4, lp = e / (4 * nu * nu);
+    const int nD = nchi * nl * 4 * nu * nu;
+    for (int e = threadIdx.x; e < nD; e += blockDim.x) {
+      const int upr = e % nu, u = (e / nu) % nu, i = (e / (nu * nu)) % 4;
+      const int lp = (e / (4 * nu * nu)) % nl, kk = e / (4 * nu * nu * nl);
+      const double2* Ez = E + ((size_t)z * nd + o_first + kk) * 4 * nu * nu * nl;
       const double2 b = bma[((size_t)z * nu + u) * nu + upr];
       const double2 ee = Ez[((size_t)(i * nu + upr) * nu + u) * nl + lp];
       const double2 xx = X[(((size_t)z * nu + u) * nu + upr) * nl + l];
@@ -389,11 +439,10 @@ __global__ void __launch_bounds__(128) k_angular(
           double v = 0.0;
           for (int u = 0; u < nu; ++u)
             for (int upr = 0; upr < nu; ++upr) {
-              const double2 d = Ds[((lp * 4 + i) * nu + u) * nu + upr];
+              const double2 d = Ds[(((k * nl + lp) * 4 + i) * nu + u) * nu + upr];
               const double2 p1 = prof[((size_t)z * nt + upr * nl + l) * nn + n];
               const double2 p2 = prof[((size_t)z * nt + u * nl + l) * nn + n];
-              const double pr = p1.x + p2.x, pim = p1.y - p2.y;
-              v += d.x * pr - d.y * pim;
+              v += d.x * (p1.x + p2.x) - d.y * (p1.y - p2.y);
             }
           acc[lp][i] += v;
         }
@@ -402,6 +451,7 @@ __global__ void __launch_bounds__(128) k_angular(
         for (int i = 0; i < 4; ++i) dst[i] = (T)acc[lp][i];
       }
     }
+    __syncthreads();
   }
 }
 
@@ -450,13 +500,14 @@ static int sigma_apply_t(trap_ctx* ctx, const T* I, T* eps, int prec, int add_th
   T* W = static_cast<T*>(K.W[pi]);
   T* Eb = static_cast<T*>(K.Eb[pi]);
   const int ncls = nl * nl;
+  const size_t spl_lds = (size_t)8 * nn * sizeof(double);
   for (int z0 = 0; z0 < nz; z0 += K.zchunk) {
     const int zc = std::min(K.zchunk, nz - z0);
     const long long npts = (long long)zc * nd * nn;
     // 1. comoving interpolation
     int pr = prof_begin(ctx, TRAP_STAGE_COMOVING);
-    hipLaunchKernelGGL(k_spline_shift<T>, dim3(ceil_div(npts, 256)), dim3(256), 0, s, z0, zc, nd, nn,
-                       P.d_x, P.d_P, P.d_lam, P.d_ub, -1.0, (const double*)nullptr, 1, 0,
+    hipLaunchKernelGGL(k_spline_shift<T>, dim3(zc * nd), dim3(128), spl_lds, s, z0, zc, nd, nn, P.d_x,
+                       P.d_SigT, P.d_lam, P.d_ub, -1.0, (const double*)nullptr, 1, 0,
                        I + (size_t)z0 * nd * nn * 4, (long long)nd * nn * 4, (long long)nn * 4, Ibar, 0,
                        (const double*)nullptr, (const double*)nullptr);
     TRAP_HIP(hipGetLastError());
@@ -485,10 +536,16 @@ static int sigma_apply_t(trap_ctx* ctx, const T* I, T* eps, int prec, int add_th
     prof_end(ctx, pr);
     // 4. angular / sublevel sum into Eb (chunk-local heights)
     pr = prof_begin(ctx, TRAP_STAGE_ANGULAR);
-    const size_t shb = (size_t)(nl * 16 + nl * 4 * nu * nu) * sizeof(double2);
-    hipLaunchKernelGGL(k_angular<T>, dim3(zc * nd, ceil_div(nn, 128)), dim3(128), shb, s, z0, nd, nn, nu, nl, P.nslot,
-                       P.c_sc, P.d_w, P.d_E, P.d_A, P.d_alpha, P.d_bma, P.d_pair_slot, W, K.X, C.d_prof,
-                       Eb + (size_t)z0 * ncls * nd * nn * 4, 1);
+    {
+      const int nchi = P.nchi;
+      const size_t per_oc = (size_t)nu * nchi * nl * 16 * sizeof(double2) + nchi * sizeof(int);
+      const int oc_max = (int)std::max<size_t>(1, std::min<size_t>(nd, (48u << 10) / per_oc));
+      const size_t shb = std::max((size_t)oc_max * per_oc + 64,
+                                  (size_t)nchi * nl * 4 * nu * nu * sizeof(double2));
+      hipLaunchKernelGGL(k_angular<T>, dim3(zc * (nd / nchi), ceil_div(nn, kAngN)), dim3(kAngN * nchi), shb, s, z0, nd,
+                         nchi, nn, nu, nl, P.nslot, oc_max, P.c_sc, P.d_w, P.d_E, P.d_A, P.d_alpha, P.d_bma,
+                         P.d_pair_slot, W, K.X, C.d_prof, Eb + (size_t)z0 * ncls * nd * nn * 4);
+    }
     TRAP_HIP(hipGetLastError());
     prof_end(ctx, pr);
   }
@@ -500,8 +557,8 @@ static int sigma_apply_t(trap_ctx* ctx, const T* I, T* eps, int prec, int add_th
       const int cls = l * nl + lp;
       const bool first = (cls == 0), last = (cls == ncls - 1);
       // f multiplies the sum over classes: apply it on a separate pass when ncls > 1
-      hipLaunchKernelGGL(k_spline_shift<T>, dim3(ceil_div(npts, 256)), dim3(256), 0, s, 0, nz, nd, nn,
-                         P.d_x, P.d_P, P.d_lam, P.d_ub, 1.0, P.d_sll, ncls, cls,
+      hipLaunchKernelGGL(k_spline_shift<T>, dim3(nz * nd), dim3(128), spl_lds, s, 0, nz, nd, nn,
+                         P.d_x, P.d_SigT, P.d_lam, P.d_ub, 1.0, P.d_sll, ncls, cls,
                          Eb + (size_t)cls * nd * nn * 4, (long long)ncls * nd * nn * 4, (long long)nn * 4,
                          eps, first ? 0 : 1, (normalize && ncls == 1) ? C.d_f : (const double*)nullptr,
                          (add_thermal && last && ncls == 1) ? C.d_epsth : (const double*)nullptr);
@@ -511,8 +568,8 @@ static int sigma_apply_t(trap_ctx* ctx, const T* I, T* eps, int prec, int add_th
     // eps <- f * eps (Stokes I) + eps_th : reuse the shift kernel with zero shift on a copy
     T* tmp = static_cast<T*>(K.tmp[pi]);
     TRAP_HIP(hipMemcpyAsync(tmp, eps, (size_t)npts * 4 * sizeof(T), hipMemcpyDeviceToDevice, s));
-    hipLaunchKernelGGL(k_spline_shift<T>, dim3(ceil_div(npts, 256)), dim3(256), 0, s, 0, nz, nd, nn,
-                       P.d_x, P.d_P, P.d_lam, P.d_ub, 0.0, (const double*)nullptr, 1, 0, tmp,
+    hipLaunchKernelGGL(k_spline_shift<T>, dim3(nz * nd), dim3(128), spl_lds, s, 0, nz, nd, nn,
+                       P.d_x, P.d_SigT, P.d_lam, P.d_ub, 0.0, (const double*)nullptr, 1, 0, tmp,
                        (long long)nd * nn * 4, (long long)nn * 4, eps, 0,
                        normalize ? C.d_f : (const double*)nullptr,
                        add_thermal ? C.d_epsth : (const double*)nullptr);

@@ -72,6 +72,7 @@ struct Problem {
   // device copies
   double *d_x = nullptr, *d_P = nullptr, *d_mu = nullptr, *d_w = nullptr, *d_tau = nullptr;
   double *d_Sig = nullptr;                 // [nn][nn] second-derivative map of the spline
+  double *d_SigT = nullptr;                // its transpose
   double *d_lam = nullptr, *d_a = nullptr, *d_eps = nullptr, *d_WT = nullptr, *d_eta0 = nullptr;
   double *d_ub = nullptr;                  // [nz][nd] reduced Doppler shift (u units)
   double *d_st = nullptr;                  // [nz][nt] reduced transition shifts
