@@ -26,6 +26,9 @@ METRIC = ("Stokes solves/s + emissivity-apply GB/s or TFLOP/s at 1e-6 rel; "
           "p50/p99 latency")
 PEAK = {"fp32": 157.3, "fp64": 78.6}     # dense TFLOP/s, MI355X published figures
 HBM_PEAK = 8000.0                        # GB/s
+COPY_PROBE_BYTES = 256 << 20
+ROOT = os.path.dirname(os.path.abspath(__file__))
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_contract_f32_cfg2_traffic.txt")
 
 
 def _pct(v, q):
@@ -36,6 +39,27 @@ def _pct(v, q):
     lo = int(k)
     hi = min(lo + 1, len(s) - 1)
     return s[lo] + (s[hi] - s[lo]) * (k - lo)
+
+
+def measured_traffic():
+    """HBM bytes per launch of the FP32 contraction from the committed counter
+    summary, or None when the contraction's source changed since the counters
+    were taken."""
+    from paper_2505_20968_amd.profile_summary import contraction_source_hash
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    rec = {}
+    with open(TRAFFIC_FILE) as f:
+        for line in f:
+            if ":" in line:
+                k, v = line.split(":", 1)
+                rec[k.strip()] = v.strip()
+    if rec.get("contraction_source_sha256") != contraction_source_hash():
+        return None
+    try:
+        return float(rec["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(n_applies: float, seed: int, budget_heights: int = 1):
@@ -89,6 +113,9 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--restart", type=int, default=40)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="before the timed region, run one elementwise kernel over a known byte "
+                         "count (reads and writes 256 MiB) to calibrate HBM traffic counters")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -116,6 +143,12 @@ def main():
                              inner=TRAP_FP32 if mixed else TRAP_FP64, max_outer=10, inner_tol=1e-4)
         return st
 
+    if args.copy_probe:
+        xs = torch.ones(COPY_PROBE_BYTES // 4, dtype=torch.float32, device="cuda")
+        ys = torch.empty_like(xs)
+        torch.neg(xs, out=ys)
+        torch.cuda.synchronize()
+        del xs, ys
     for i in range(args.warmup):
         one_step(1000 + i)
     torch.cuda.synchronize()
@@ -173,7 +206,7 @@ def main():
                              "contraction_launches": cstage["launches"],
                              "stage_ms_per_launch": apply_ms},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK[key], "unit": "TFLOP/s",
-                     "frac": achieved / PEAK[key], "traffic": None,
+                     "frac": achieved / PEAK[key], "traffic": measured_traffic() if mixed else None,
                      "algorithmic_bytes_per_launch": cbytes / max(cstage["launches"], 1),
                      "algorithmic_flops_per_launch": flops / max(cstage["launches"], 1),
                      "kernel": "k_contract<float>" if mixed else "k_contract<double>"},

@@ -1,0 +1,118 @@
+"""Reduce rocprofv3 CSV output to the short text summaries kept in profiles/.
+
+    python -m paper_2505_20968_amd.profile_summary stats KERNEL_STATS_CSV OUT --command "..."
+    python -m paper_2505_20968_amd.profile_summary traffic FETCH_CSV WRITE_CSV OUT --command "..."
+
+`stats` keeps the per-kernel table of a `--kernel-trace --stats` run.
+`traffic` takes two `--pmc FETCH_SIZE` / `--pmc WRITE_SIZE` runs of a command
+that also launched the calibration kernel (an elementwise negation reading and
+writing COPY_BYTES), scales both counters by what they read for that kernel,
+and records HBM bytes per launch of the FP32 contraction together with a hash
+of the contraction's source, so that a stale figure is not reported after the
+kernel changes.
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import hashlib
+import os
+import statistics
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SIGMA_SRC = os.path.join(HERE, "csrc", "sigma.hip")
+CONTRACT_BEGIN = "// ------------------------------------------------------------------ R_II contraction"
+CONTRACT_END = "// ------------------------------------------------------------------ R_III factors"
+COPY_BYTES = 256 << 20
+CONTRACT_NAME = "k_contract<float>"
+COPY_NAME = "neg"
+
+
+def contraction_source_hash() -> str:
+    with open(SIGMA_SRC) as f:
+        src = f.read()
+    i, j = src.index(CONTRACT_BEGIN), src.index(CONTRACT_END)
+    return hashlib.sha256(src[i:j].encode()).hexdigest()
+
+
+def _short(name: str, width: int = 72) -> str:
+    name = name.split("(")[0] if "(" in name and not name.startswith("void at::") else name
+    return name if len(name) <= width else name[: width - 3] + "..."
+
+
+def stats(path: str, out: str, command: str, top: int = 25) -> None:
+    with open(path) as f:
+        rows = list(csv.DictReader(f))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    total = sum(float(r["TotalDurationNs"]) for r in rows)
+    lines = [f"command: {command}", f"source: {os.path.basename(path)}",
+             f"total kernel time: {total / 1e6:.2f} ms over {sum(int(r['Calls']) for r in rows)} dispatches",
+             "",
+             f"{'kernel':72s} {'calls':>7s} {'total_ms':>10s} {'avg_us':>10s} {'min_us':>9s} {'max_us':>9s} {'pct':>6s}"]
+    for r in rows[:top]:
+        lines.append(f"{_short(r['Name']):72s} {int(r['Calls']):7d} {float(r['TotalDurationNs']) / 1e6:10.2f} "
+                     f"{float(r['AverageNs']) / 1e3:10.1f} {float(r['MinNs']) / 1e3:9.1f} "
+                     f"{float(r['MaxNs']) / 1e3:9.1f} {100 * float(r['TotalDurationNs']) / total:6.1f}")
+    with open(out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
+def _counter_by_kernel(path: str, counter: str):
+    vals: dict[str, list[float]] = {}
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            if r.get("Counter_Name") != counter:
+                continue
+            vals.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+    return vals
+
+
+def _pick(vals, needle):
+    hits = {k: v for k, v in vals.items() if needle in k}
+    if not hits:
+        raise SystemExit(f"no dispatch of a kernel named like {needle!r}")
+    return [x for v in hits.values() for x in v]
+
+
+def traffic(fetch_csv: str, write_csv: str, out: str, command: str) -> None:
+    fv = _counter_by_kernel(fetch_csv, "FETCH_SIZE")
+    wv = _counter_by_kernel(write_csv, "WRITE_SIZE")
+    copy_kib = COPY_BYTES / 1024.0
+    f_copy, w_copy = statistics.mean(_pick(fv, COPY_NAME)), statistics.mean(_pick(wv, COPY_NAME))
+    f_scale, w_scale = copy_kib / f_copy, copy_kib / w_copy
+    fc, wc = _pick(fv, CONTRACT_NAME), _pick(wv, CONTRACT_NAME)
+    f_bytes = statistics.mean(fc) * f_scale * 1024.0
+    w_bytes = statistics.mean(wc) * w_scale * 1024.0
+    lines = [f"command: {command}",
+             f"calibration kernel: elementwise negation over {COPY_BYTES} bytes "
+             f"(FETCH_SIZE {f_copy:.0f} KiB -> scale {f_scale:.4f}; WRITE_SIZE {w_copy:.0f} KiB -> scale {w_scale:.4f})",
+             f"kernel: {CONTRACT_NAME}, {len(fc)} dispatches with FETCH_SIZE, {len(wc)} with WRITE_SIZE",
+             f"fetch_bytes_per_launch: {f_bytes:.6e}",
+             f"write_bytes_per_launch: {w_bytes:.6e}",
+             f"traffic_bytes_per_launch: {f_bytes + w_bytes:.6e}",
+             f"contraction_source_sha256: {contraction_source_hash()}"]
+    with open(out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    sub = ap.add_subparsers(dest="mode", required=True)
+    a = sub.add_parser("stats")
+    a.add_argument("csv")
+    a.add_argument("out")
+    a.add_argument("--command", required=True)
+    b = sub.add_parser("traffic")
+    b.add_argument("fetch_csv")
+    b.add_argument("write_csv")
+    b.add_argument("out")
+    b.add_argument("--command", required=True)
+    args = ap.parse_args()
+    if args.mode == "stats":
+        stats(args.csv, args.out, args.command)
+    else:
+        traffic(args.fetch_csv, args.write_csv, args.out, args.command)
+
+
+if __name__ == "__main__":
+    main()
