@@ -121,7 +121,7 @@ def main():
     if args.gpus != 1 or world != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE={world}); "
               "this build has no multi-GPU path: heights shard with zero communication for Sigma "
-              "and one all-to-all per apply for Lambda, see DESIGN.md", file=sys.stderr)
+              "and one all-to-all per apply for Lambda", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -28,7 +28,8 @@ that produces the [G(k_u') + G(k_u)*] pairing of Eq. RQIIKKp.  That regroups
 exactly into the paper's multipole form; the pins in ``tests/`` check it
 against closed forms that do not go through the dipole vectors.
 
-Every reading of a point the paper leaves open is listed in the design doc.
+Where the paper leaves a point open, the reading taken is stated beside the
+function that implements it.
 """
 from .grids import angular_grid, theta_table, SplineBasis
 from .atom import AtomModel, build_atom
