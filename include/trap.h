@@ -171,6 +171,26 @@ int trap_rhs(trap_ctx* ctx, double* b_out_device);
  * solution out.  Returns TRAP_ENOCONV if tol is not reached.  Synchronises. */
 int trap_gmres_solve(trap_ctx* ctx, const trap_solve_opts* opts, double* I, trap_solve_stats* stats);
 
+/* Batched solving for a serving loop: the solve of trap_gmres_solve split into
+ * steps so that many contexts (requests) advance together.
+ * trap_gmres_begin checks the options and the initial guess I (FP64 device
+ * memory, overwritten with the solution; must stay valid until the solve ends)
+ * and computes ||b|| (synchronises the context's stream).
+ * trap_gmres_step_batch advances each of the n distinct contexts by one unit
+ * (one Arnoldi iteration, or one FP64 residual of the refinement loop): the
+ * device work of all contexts is enqueued on their own streams before the call
+ * waits, so work of different contexts overlaps on the device, and the host
+ * synchronises at most twice per step for the whole batch.  status[i] is 1
+ * while context i is running, then its final trap_status.  Finished contexts
+ * may stay in the batch (they are skipped).
+ * trap_gmres_end returns the final status and statistics of a finished solve
+ * (TRAP_ESTATE while it is still running).
+ * The arithmetic of a context does not depend on the other contexts of the
+ * batch: a request's solution is the same alone and in any mix. */
+int trap_gmres_begin(trap_ctx* ctx, const trap_solve_opts* opts, double* I);
+int trap_gmres_step_batch(trap_ctx** ctxs, int n, int* status);
+int trap_gmres_end(trap_ctx* ctx, trap_solve_stats* stats);
+
 /* Emergent Stokes vectors at z_max for the mu > 0 directions:
  * host_out[o_up][n][4] (FP64, n_dir/2 x n_nu x 4).  Synchronises. */
 int trap_emergent(trap_ctx* ctx, const double* I, double* host_out);
@@ -203,6 +223,16 @@ typedef struct {
 } trap_stage_stats;
 int trap_profile(trap_ctx* ctx, int enable);
 int trap_stage_times(trap_ctx* ctx, trap_stage_stats* out);
+
+/* Choice of Sigma implementation (both compute the same operator):
+ * TRAP_PATH_AUTO (default) and TRAP_PATH_CHUNKED materialise the R_II
+ * intermediate W per chunk of heights (contraction, then angular sum).
+ * TRAP_PATH_FUSED uses one kernel that keeps W on chip and scatters the angular
+ * sum into LDS; it handles FP32 applies of problems within its limits (padded
+ * frequency count <= 128, 2..8 upper sublevels, LDS within the device's
+ * per-block limit) and makes other applies fail with TRAP_EINVAL. */
+enum { TRAP_PATH_AUTO = 0, TRAP_PATH_FUSED = 1, TRAP_PATH_CHUNKED = 2 };
+int trap_set_path(trap_ctx* ctx, int path);
 
 /* Thread-local description of the last failure. */
 const char* trap_last_error(void);

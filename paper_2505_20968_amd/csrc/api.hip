@@ -35,6 +35,7 @@ int dalloc(trap_ctx* ctx, void** p, size_t bytes) {
 
 void free_all(trap_ctx* ctx) {
   if (!ctx->bufs.empty()) (void)hipStreamSynchronize(ctx->stream);
+  gmres_release(ctx);
   for (auto& b : ctx->bufs) (void)hipFree(b.p);
   ctx->bufs.clear();
   ctx->pb = Problem();
@@ -110,18 +111,6 @@ static void prof_clear(trap_ctx* ctx, bool release) {
   ctx->prof.used = 0;
 }
 
-struct DeviceGuard {
-  int prev = -1;
-  explicit DeviceGuard(int dev) {
-    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-    if (prev != dev) (void)hipSetDevice(dev);
-  }
-  ~DeviceGuard() {
-    int cur = -1;
-    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
-  }
-};
-
 }  // namespace trap
 
 using namespace trap;
@@ -144,6 +133,11 @@ int trap_create(trap_ctx** out, int device, void* stream) {
   if (!ctx) return fail(TRAP_ENOMEM, "host allocation failed");
   ctx->device = device;
   ctx->stream = static_cast<hipStream_t>(stream);
+  int lds = 0;
+  if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess && lds > 0)
+    ctx->max_lds = std::min(lds, 160 * 1024);
+  else
+    (void)hipGetLastError();
   *out = ctx;
   return TRAP_OK;
 }
@@ -270,6 +264,37 @@ int trap_get_info(const trap_ctx* ctx, trap_info* info) {
   const double ibytes = (double)P.nz * P.nd * P.nn * 4;
   info->bytes_contraction_fp64 = 8.0 * (kel + wbytes + ibytes);
   info->bytes_contraction_fp32 = 4.0 * (kel + wbytes + ibytes);
+  return TRAP_OK;
+}
+
+int trap_gmres_begin(trap_ctx* ctx, const trap_solve_opts* opts, double* I) {
+  if (!ctx) return fail(TRAP_EINVAL, "null context");
+  DeviceGuard g(ctx->device);
+  return gmres_begin(ctx, opts, I);
+}
+
+int trap_gmres_step_batch(trap_ctx** ctxs, int n, int* status) {
+  if (n < 0 || (n > 0 && (!ctxs || !status))) return fail(TRAP_EINVAL, "null argument");
+  for (int i = 0; i < n; ++i) {
+    if (!ctxs[i]) return fail(TRAP_EINVAL, "null context in batch");
+    if (!ctxs[i]->run) return fail(TRAP_ESTATE, "trap_gmres_begin not called for a context in the batch");
+    for (int k = 0; k < i; ++k)
+      if (ctxs[k] == ctxs[i]) return fail(TRAP_EINVAL, "context listed twice in batch");
+  }
+  return gmres_step_batch(ctxs, n, status);
+}
+
+int trap_gmres_end(trap_ctx* ctx, trap_solve_stats* stats) {
+  if (!ctx) return fail(TRAP_EINVAL, "null context");
+  DeviceGuard g(ctx->device);
+  return gmres_end(ctx, stats);
+}
+
+int trap_set_path(trap_ctx* ctx, int path) {
+  if (!ctx) return fail(TRAP_EINVAL, "null context");
+  if (path != TRAP_PATH_AUTO && path != TRAP_PATH_FUSED && path != TRAP_PATH_CHUNKED)
+    return fail(TRAP_EINVAL, "unknown Sigma path");
+  ctx->path = path;
   return TRAP_OK;
 }
 

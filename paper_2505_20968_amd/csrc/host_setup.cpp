@@ -355,13 +355,147 @@ std::vector<double> spline_map(const std::vector<double>& x, std::vector<double>
 
 }  // namespace
 
+// Angular grid (double Gauss-Legendre mu x trapezoidal chi, Sect. 4.2), the
+// distinct scattering angles, the (incoming direction, Theta) slots, the pair
+// lists per slot and the slot groups of the fused Sigma kernel.
+static void angular_setup(Problem& P, std::vector<double>& dirs, std::vector<double>& ea,
+                          std::vector<double>& eb) {
+  const int nd = P.nd;
+  std::vector<double> gt, gw;
+  gauss_legendre01(P.nmu / 2, gt, gw);
+  std::vector<double> mu1, wmu1;
+  for (int i = P.nmu / 2 - 1; i >= 0; --i) {
+    mu1.push_back(-gt[i]);
+    wmu1.push_back(gw[i]);
+  }
+  for (int i = 0; i < P.nmu / 2; ++i) {
+    mu1.push_back(gt[i]);
+    wmu1.push_back(gw[i]);
+  }
+  P.mu.resize(nd);
+  P.w.resize(nd);
+  dirs.assign(3 * nd, 0.0);
+  ea.assign(3 * nd, 0.0);
+  eb.assign(3 * nd, 0.0);
+  for (int i = 0; i < P.nmu; ++i)
+    for (int k = 0; k < P.nchi; ++k) {
+      const int o = i * P.nchi + k;
+      const double chi = 2.0 * kPi * k / P.nchi, mu = mu1[i], st = std::sqrt(1.0 - mu * mu);
+      P.mu[o] = mu;
+      P.w[o] = wmu1[i] / (2.0 * P.nchi);
+      dirs[3 * o + 0] = st * std::cos(chi);
+      dirs[3 * o + 1] = st * std::sin(chi);
+      dirs[3 * o + 2] = mu;
+      ea[3 * o + 0] = -std::sin(chi);
+      ea[3 * o + 1] = std::cos(chi);
+      ea[3 * o + 2] = 0.0;
+      // e_b = Omega x e_a
+      eb[3 * o + 0] = dirs[3 * o + 1] * ea[3 * o + 2] - dirs[3 * o + 2] * ea[3 * o + 1];
+      eb[3 * o + 1] = dirs[3 * o + 2] * ea[3 * o + 0] - dirs[3 * o + 0] * ea[3 * o + 2];
+      eb[3 * o + 2] = dirs[3 * o + 0] * ea[3 * o + 1] - dirs[3 * o + 1] * ea[3 * o + 0];
+    }
+  // ---- scattering-angle table and slots
+  std::vector<double> cosv(nd * nd);
+  for (int o = 0; o < nd; ++o)
+    for (int i = 0; i < nd; ++i) {
+      double c = dirs[3 * o] * dirs[3 * i] + dirs[3 * o + 1] * dirs[3 * i + 1] + dirs[3 * o + 2] * dirs[3 * i + 2];
+      c = std::min(1.0, std::max(-1.0, c));
+      if (std::fabs(c - 1.0) < 1e-12) c = 1.0;
+      if (std::fabs(c + 1.0) < 1e-12) c = -1.0;
+      cosv[o * nd + i] = c;
+    }
+  std::vector<double> sorted(cosv);
+  std::sort(sorted.begin(), sorted.end(), std::greater<double>());
+  std::vector<double> reps{sorted[0]};
+  for (size_t k = 1; k < sorted.size(); ++k)
+    if (reps.back() - sorted[k] > 1e-10) reps.push_back(sorted[k]);
+  P.nth = static_cast<int>(reps.size());
+  P.theta.resize(P.nth);
+  for (int t = 0; t < P.nth; ++t) {
+    P.theta[t] = (reps[t] == 1.0) ? 0.0 : (reps[t] == -1.0 ? kPi : std::acos(reps[t]));
+  }
+  P.pair_theta.resize(nd * nd);
+  for (int k = 0; k < nd * nd; ++k) {
+    int best = 0;
+    for (int t = 1; t < P.nth; ++t)
+      if (std::fabs(reps[t] - cosv[k]) < std::fabs(reps[best] - cosv[k])) best = t;
+    P.pair_theta[k] = best;
+  }
+  // slots: for each theta the incoming directions that occur with it
+  std::vector<std::vector<int>> used(P.nth, std::vector<int>(nd, -1));
+  for (int o = 0; o < nd; ++o)
+    for (int i = 0; i < nd; ++i) used[P.pair_theta[o * nd + i]][i] = 1;
+  P.slot_off.assign(P.nth + 1, 0);
+  P.slot_dir.clear();
+  P.slot_theta.clear();
+  for (int t = 0; t < P.nth; ++t) {
+    P.slot_off[t] = static_cast<int>(P.slot_dir.size());
+    for (int i = 0; i < nd; ++i)
+      if (used[t][i] == 1) {
+        used[t][i] = static_cast<int>(P.slot_dir.size());
+        P.slot_dir.push_back(i);
+        P.slot_theta.push_back(t);
+      }
+    P.max_slots_per_theta = std::max(P.max_slots_per_theta,
+                                     static_cast<int>(P.slot_dir.size()) - P.slot_off[t]);
+  }
+  P.slot_off[P.nth] = static_cast<int>(P.slot_dir.size());
+  P.nslot = static_cast<int>(P.slot_dir.size());
+  P.pair_slot.resize(nd * nd);
+  for (int o = 0; o < nd; ++o)
+    for (int i = 0; i < nd; ++i) P.pair_slot[o * nd + i] = used[P.pair_theta[o * nd + i]][i];
+  // pairs (o, o') listed per slot (slot-major), and slot groups per theta for the fused kernel
+  P.pair_off.assign(P.nslot + 1, 0);
+  for (int k = 0; k < nd * nd; ++k) ++P.pair_off[P.pair_slot[k] + 1];
+  for (int sl = 0; sl < P.nslot; ++sl) P.pair_off[sl + 1] += P.pair_off[sl];
+  P.pair_o.assign(nd * nd, 0);
+  {
+    std::vector<int> fill(P.pair_off.begin(), P.pair_off.end() - 1);
+    for (int o = 0; o < nd; ++o)
+      for (int i = 0; i < nd; ++i) P.pair_o[fill[P.pair_slot[o * nd + i]]++] = o;
+  }
+  P.pair_dir.assign(nd * nd, 0);
+  for (int sl = 0; sl < P.nslot; ++sl)
+    for (int q = P.pair_off[sl]; q < P.pair_off[sl + 1]; ++q) P.pair_dir[q] = P.slot_dir[sl];
+  // a group holds at most sg slots of one theta and at most 2 sg pairs
+  for (int pi = 0; pi < 2; ++pi) {
+    const int sg = pi == 0 ? 8 : 16;
+    P.grp[pi].clear();
+    P.grp_maxpairs[pi] = 0;
+    for (int t = 0; t < P.nth; ++t) {
+      int s0 = P.slot_off[t];
+      while (s0 < P.slot_off[t + 1]) {
+        int cnt = 0;
+        while (s0 + cnt < P.slot_off[t + 1] && cnt < sg &&
+               P.pair_off[s0 + cnt + 1] - P.pair_off[s0] <= 2 * sg)
+          ++cnt;
+        cnt = std::max(cnt, 1);
+        P.grp_maxpairs[pi] = std::max(P.grp_maxpairs[pi], P.pair_off[s0 + cnt] - P.pair_off[s0]);
+        P.grp[pi].push_back(t);
+        P.grp[pi].push_back(s0);
+        P.grp[pi].push_back(cnt);
+        s0 += cnt;
+      }
+    }
+  }
+}
+
 size_t estimate_bytes(const trap_atom_desc* atom, const trap_problem_desc* pd, int store_mask, int* err) {
   *err = 0;
-  if (!atom || !pd || pd->n_z < 2 || pd->n_nu < 4 || pd->n_mu < 2 || pd->n_mu % 2 || pd->n_chi < 1) {
+  if (!atom || !pd || pd->n_z < 2 || pd->n_nu < 4 || pd->n_mu < 2 || pd->n_mu % 2 || pd->n_chi < 1 ||
+      (atom->kind != 0 && atom->kind != 1)) {
     *err = 1;
     return 0;
   }
-  const size_t nz = pd->n_z, nn = pd->n_nu, nd = static_cast<size_t>(pd->n_mu) * pd->n_chi;
+  Problem P;
+  P.nz = pd->n_z;
+  P.nn = pd->n_nu;
+  P.nmu = pd->n_mu;
+  P.nchi = pd->n_chi;
+  P.nd = P.nmu * P.nchi;
+  P.ldm = (P.nn + 7) / 8 * 8;
+  std::vector<double> dirs, ea, eb;
+  angular_setup(P, dirs, ea, eb);
   size_t nu, nl;
   if (atom->kind == 0) {
     nu = static_cast<size_t>(std::lround(2 * atom->J_u)) + 1;
@@ -371,14 +505,33 @@ size_t estimate_bytes(const trap_atom_desc* atom, const trap_problem_desc* pd, i
     nl = (2 * atom->L_l + 1) * static_cast<size_t>(std::lround(2 * atom->S) + 1);
   }
   const size_t nt = nu * nl;
-  const size_t nth = nd * nd;     // upper bound for the scattering-angle count
-  size_t b = 0;
-  const size_t ker = nz * nth / 4 * nt * 2 * nn * nn;   // typical N_Theta ~ N_dir^2/40..1/4
-  if (store_mask & 1) b += ker * 8;
-  if (store_mask & 2) b += ker * 4;
+  const size_t nz = P.nz, nn = P.nn, nd = P.nd, nth = P.nth, nslot = P.nslot, ldm = P.ldm;
   const size_t N = 4 * nz * nd * nn;
-  b += N * 8 * 48;                // vectors, Krylov basis (restart 40), tables
-  b += nz * nd * nd * nt * 16 * 2; // E/A tables
+  const int mask = store_mask | 1;
+  const size_t ker = nz * nth * nt * 2 * nn * ldm;       // stored kernel entries per precision
+  const size_t cfe = nz * nd * nd * nt * 2 * nl * 16;    // angular coefficients per precision
+  size_t b = 0;
+  for (int pi = 0; pi < 2; ++pi) {
+    if (!(mask & (1 << pi))) continue;
+    const size_t es = pi == 0 ? 8 : 4;
+    b += (ker + cfe) * es;
+    b += (N * 4 + nz * nl * nl * nd * nn * 4) * es;     // comoving field, eps_bar, two work vectors
+  }
+  b += nz * nd * nn * (8 + 4 + 1 + 4) * 8;               // K, eps_th, f, b
+  b += nz * nt * nn * 2 * 16;                           // R_III weights and profiles
+  b += N * 8 * (41 + 3);                                // Krylov basis (restart <= 40) and solver vectors
+  b += N * 4 * 2;                                       // FP32 solver vectors
+  b += nz * nd * nd * nt * 16 * 2 + nz * nt * nd * 4 * 8;  // E/A tables, geometric factors
+  b += nd * nd * 4 * 4 + nslot * 8;                     // pair and slot tables
+  // the height-chunked Sigma path (problems beyond the fused kernel's limits)
+  // materialises W for one chunk of heights (at most ~1 GiB in FP64)
+  const size_t fused_f64 = ldm * 40 * 8 + nl * nd * 64 * 8, fused_f32 = ldm * 72 * 4 + nl * nd * 64 * 4;
+  const bool fits = ldm <= 128 && 2 * nu <= 16 && fused_f64 <= 65536 && fused_f32 <= 65536;
+  if (!fits) {
+    const size_t per_z = nt * nslot * 2 * nn * 4 * 8;
+    const size_t zc = std::max<size_t>(1, std::min<size_t>(nz, (size_t(1) << 30) / std::max<size_t>(per_z, 1)));
+    b += zc * per_z * ((mask & 2) ? 3 : 2) / 2;
+  }
   return b;
 }
 
@@ -434,88 +587,9 @@ int build_problem(trap_ctx* ctx, const trap_atom_desc* at, const trap_problem_de
     P.lam[z] = dnuD_ref / P.dnuD[z];
     P.eta0[z] = std::exp(P.a[z] * P.a[z]) * std::erfc(P.a[z]) / std::sqrt(kPi);
   }
-  // ---- angular grid (double Gauss-Legendre x trapezoid)
-  std::vector<double> gt, gw;
-  gauss_legendre01(P.nmu / 2, gt, gw);
-  std::vector<double> mu1, wmu1;
-  for (int i = P.nmu / 2 - 1; i >= 0; --i) {
-    mu1.push_back(-gt[i]);
-    wmu1.push_back(gw[i]);
-  }
-  for (int i = 0; i < P.nmu / 2; ++i) {
-    mu1.push_back(gt[i]);
-    wmu1.push_back(gw[i]);
-  }
-  P.mu.resize(nd);
-  P.w.resize(nd);
-  std::vector<double> dirs(3 * nd), ea(3 * nd), eb(3 * nd);
-  for (int i = 0; i < P.nmu; ++i)
-    for (int k = 0; k < P.nchi; ++k) {
-      const int o = i * P.nchi + k;
-      const double chi = 2.0 * kPi * k / P.nchi, mu = mu1[i], st = std::sqrt(1.0 - mu * mu);
-      P.mu[o] = mu;
-      P.w[o] = wmu1[i] / (2.0 * P.nchi);
-      dirs[3 * o + 0] = st * std::cos(chi);
-      dirs[3 * o + 1] = st * std::sin(chi);
-      dirs[3 * o + 2] = mu;
-      ea[3 * o + 0] = -std::sin(chi);
-      ea[3 * o + 1] = std::cos(chi);
-      ea[3 * o + 2] = 0.0;
-      // e_b = Omega x e_a
-      eb[3 * o + 0] = dirs[3 * o + 1] * ea[3 * o + 2] - dirs[3 * o + 2] * ea[3 * o + 1];
-      eb[3 * o + 1] = dirs[3 * o + 2] * ea[3 * o + 0] - dirs[3 * o + 0] * ea[3 * o + 2];
-      eb[3 * o + 2] = dirs[3 * o + 0] * ea[3 * o + 1] - dirs[3 * o + 1] * ea[3 * o + 0];
-    }
-  // ---- scattering-angle table and slots
-  std::vector<double> cosv(nd * nd);
-  for (int o = 0; o < nd; ++o)
-    for (int i = 0; i < nd; ++i) {
-      double c = dirs[3 * o] * dirs[3 * i] + dirs[3 * o + 1] * dirs[3 * i + 1] + dirs[3 * o + 2] * dirs[3 * i + 2];
-      c = std::min(1.0, std::max(-1.0, c));
-      if (std::fabs(c - 1.0) < 1e-12) c = 1.0;
-      if (std::fabs(c + 1.0) < 1e-12) c = -1.0;
-      cosv[o * nd + i] = c;
-    }
-  std::vector<double> sorted(cosv);
-  std::sort(sorted.begin(), sorted.end(), std::greater<double>());
-  std::vector<double> reps{sorted[0]};
-  for (size_t k = 1; k < sorted.size(); ++k)
-    if (reps.back() - sorted[k] > 1e-10) reps.push_back(sorted[k]);
-  P.nth = static_cast<int>(reps.size());
-  P.theta.resize(P.nth);
-  for (int t = 0; t < P.nth; ++t) {
-    P.theta[t] = (reps[t] == 1.0) ? 0.0 : (reps[t] == -1.0 ? kPi : std::acos(reps[t]));
-  }
-  P.pair_theta.resize(nd * nd);
-  for (int k = 0; k < nd * nd; ++k) {
-    int best = 0;
-    for (int t = 1; t < P.nth; ++t)
-      if (std::fabs(reps[t] - cosv[k]) < std::fabs(reps[best] - cosv[k])) best = t;
-    P.pair_theta[k] = best;
-  }
-  // slots: for each theta the incoming directions that occur with it
-  std::vector<std::vector<int>> used(P.nth, std::vector<int>(nd, -1));
-  for (int o = 0; o < nd; ++o)
-    for (int i = 0; i < nd; ++i) used[P.pair_theta[o * nd + i]][i] = 1;
-  P.slot_off.assign(P.nth + 1, 0);
-  P.slot_dir.clear();
-  std::vector<int> slot_theta;
-  for (int t = 0; t < P.nth; ++t) {
-    P.slot_off[t] = static_cast<int>(P.slot_dir.size());
-    for (int i = 0; i < nd; ++i)
-      if (used[t][i] == 1) {
-        used[t][i] = static_cast<int>(P.slot_dir.size());
-        P.slot_dir.push_back(i);
-        slot_theta.push_back(t);
-      }
-    P.max_slots_per_theta = std::max(P.max_slots_per_theta,
-                                     static_cast<int>(P.slot_dir.size()) - P.slot_off[t]);
-  }
-  P.slot_off[P.nth] = static_cast<int>(P.slot_dir.size());
-  P.nslot = static_cast<int>(P.slot_dir.size());
-  P.pair_slot.resize(nd * nd);
-  for (int o = 0; o < nd; ++o)
-    for (int i = 0; i < nd; ++i) P.pair_slot[o * nd + i] = used[P.pair_theta[o * nd + i]][i];
+  // ---- angular grid, scattering angles, slots
+  std::vector<double> dirs, ea, eb;
+  angular_setup(P, dirs, ea, eb);
   // ---- sublevels per height
   std::vector<Sublevels> sub(nz);
   for (int z = 0; z < nz; ++z)
@@ -594,10 +668,15 @@ int build_problem(trap_ctx* ctx, const trap_atom_desc* at, const trap_problem_de
   TRAP_TRY(upload_t(ctx, &P.d_st, st));
   TRAP_TRY(upload_t(ctx, &P.d_sll, sll));
   TRAP_TRY(upload_t(ctx, &P.d_theta, P.theta));
-  TRAP_TRY(upload_t(ctx, &P.d_slot_theta, slot_theta));
+  TRAP_TRY(upload_t(ctx, &P.d_slot_theta, P.slot_theta));
   TRAP_TRY(upload_t(ctx, &P.d_slot_dir, P.slot_dir));
   TRAP_TRY(upload_t(ctx, &P.d_slot_off, P.slot_off));
   TRAP_TRY(upload_t(ctx, &P.d_pair_slot, P.pair_slot));
+  TRAP_TRY(upload_t(ctx, &P.d_pair_off, P.pair_off));
+  TRAP_TRY(upload_t(ctx, &P.d_pair_o, P.pair_o));
+  TRAP_TRY(upload_t(ctx, &P.d_pair_dir, P.pair_dir));
+  TRAP_TRY(upload_t(ctx, &P.d_grp[0], P.grp[0]));
+  TRAP_TRY(upload_t(ctx, &P.d_grp[1], P.grp[1]));
   TRAP_TRY(upload_t(ctx, &P.d_E, E));
   TRAP_TRY(upload_t(ctx, &P.d_A, A));
   TRAP_TRY(upload_t(ctx, &P.d_alpha, alpha));

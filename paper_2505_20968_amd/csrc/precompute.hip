@@ -491,6 +491,51 @@ __global__ void k_norm_factor(long long total, int nd, int nn, const double* __r
 }
 
 // ------------------------------------------------------------------ driver
+// Angular coefficients of the R_II sum for every pair (o, o') (App. D, Eq.
+// eps_sc_II_exp written with explicit dipole vectors):
+//   C^{u' l, l'}_ij(o, o') = (c_sc w_o' / pi) sum_u alpha_{u u'} E_i(o; u', u, l') A_j(o'; u, u', l)
+// stored per pair in slot-major order as cf[z][p][t = (u', l)][c][l'][i][j] with
+// c = 0 holding Re C (multiplies Re W) and c = 1 holding -Im C (multiplies Im W).
+// One block per (z, pair); threads over (t, l', i, j).
+__global__ void k_coef_table(int nd, int nu, int nl, double c_sc, const double* __restrict__ w,
+                             const int* __restrict__ pair_o, const int* __restrict__ pair_slot_dir,
+                             const double2* __restrict__ E, const double2* __restrict__ A,
+                             const double2* __restrict__ alpha, double* __restrict__ cf64,
+                             float* __restrict__ cf32) {
+  const int np = nd * nd;
+  const int z = blockIdx.x / np, p = blockIdx.x % np;
+  const int o = pair_o[p], op = pair_slot_dir[p];
+  const int nt = nu * nl;
+  const int nitem = nt * nl * 16;
+  const double sc = c_sc * w[op] / kPiD;
+  for (int e = threadIdx.x; e < nitem; e += blockDim.x) {
+    const int j = e & 3, i = (e >> 2) & 3;
+    const int lp = (e >> 4) % nl, t = (e >> 4) / nl;
+    const int upr = t / nl, l = t % nl;
+    const double2* Ez = E + ((size_t)z * nd + o) * 4 * nu * nu * nl;
+    const double2* Az = A + ((size_t)z * nd + op) * 4 * nu * nu * nl;
+    double re = 0.0, im = 0.0;
+    for (int u = 0; u < nu; ++u) {
+      const double2 al = alpha[((size_t)z * nu + u) * nu + upr];
+      const double2 ee = Ez[((size_t)(i * nu + upr) * nu + u) * nl + lp];
+      const double2 aa = Az[((size_t)(j * nu + u) * nu + upr) * nl + l];
+      const double2 v = cmul(al, cmul(ee, aa));
+      re += v.x;
+      im += v.y;
+    }
+    const size_t base = ((((size_t)z * np + p) * nt + t) * 2) * nl * 16 + lp * 16 + i * 4 + j;
+    const size_t off_im = (size_t)nl * 16;
+    if (cf64) {
+      cf64[base] = sc * re;
+      cf64[base + off_im] = -sc * im;
+    }
+    if (cf32) {
+      cf32[base] = (float)(sc * re);
+      cf32[base + off_im] = (float)(-sc * im);
+    }
+  }
+}
+
 int run_precompute(trap_ctx* ctx, int store_mask) {
   Problem& P = ctx->pb;
   Precomp& C = ctx->pre;
@@ -601,6 +646,15 @@ int run_precompute(trap_ctx* ctx, int store_mask) {
   hipLaunchKernelGGL(k_r3_rows, dim3(nz * nt), dim3(64), lds, s, nt, nn, P.d_x, P.d_P, P.d_lam, P.d_a,
                      P.d_st, C.d_r3, C.d_prof);
   TRAP_HIP(hipGetLastError());
+  {
+    const size_t ncf = (size_t)nz * nd * nd * nt * 2 * P.nl * 16;
+    if ((mask & 1) && !C.d_cf64) TRAP_TRY(dalloc_t(ctx, &C.d_cf64, ncf));
+    if ((mask & 2) && !C.d_cf32) TRAP_TRY(dalloc_t(ctx, &C.d_cf32, ncf));
+    hipLaunchKernelGGL(k_coef_table, dim3(nz * nd * nd), dim3(64), 0, s, nd, P.nu, P.nl, P.c_sc, P.d_w,
+                       P.d_pair_o, P.d_pair_dir, P.d_E, P.d_A, P.d_alpha, (mask & 1) ? C.d_cf64 : nullptr,
+                       (mask & 2) ? C.d_cf32 : nullptr);
+    TRAP_HIP(hipGetLastError());
+  }
   C.done = true;
   // normalisation factor f: one unnormalised FP64 Sigma apply on (W_T, 0, 0, 0)
   TRAP_TRY(ensure_work(ctx, TRAP_FP64));

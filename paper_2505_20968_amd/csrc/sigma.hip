@@ -455,6 +455,339 @@ __global__ void __launch_bounds__(512) k_angular(
   }
 }
 
+// ------------------------------------------------------------------ fused R_II contraction + angular sum
+// One block per (height z, tile of 16 comoving frequencies, lower sublevel l).
+// The slots of each Theta are taken in groups of up to SG incoming directions.
+// Per group the block stages in LDS the comoving field of those slots (the B
+// tile), the angular coefficients of their pairs (o, o') and the pair lists;
+// each wave multiplies the B tile on matrix cores by its kernel rows
+// M[z][Theta][t][c][n0..n0+15][:] (held in registers, reloaded only when Theta
+// changes) and the resulting W tile never leaves the CU: each lane forms
+//   sum_j cf[pair][t][c][l'][i][j] W_j
+// for every pair of its slot and adds it into an LDS accumulator
+// eps_bar[l'][o][n][i].  The next group's B tile, coefficients and, at a Theta
+// change, kernel rows are loaded into registers while the current group is
+// multiplied.  The R_III term is added when the tile is written out.
+// Waves own row tiles r = (u', c) (transition t = (u', l), real/imaginary
+// plane c), TPW each.  The kernel-row fragments use a permuted K order: step
+// (h, jj) takes k = 2 (4 h + lk) + jj in lane group lk, so each lane loads its
+// fragment with two-element vector loads; the B tile is read with the same k.
+template <typename T> struct T2of;
+template <> struct T2of<float> { typedef float2 type; };
+template <> struct T2of<double> { typedef double2 type; };
+
+template <typename T> struct FusedCfg;
+template <> struct FusedCfg<float> { static constexpr int SG = 16, BST = 72; };
+template <> struct FusedCfg<double> { static constexpr int SG = 8, BST = 40; };
+// staged vectors per thread: B tile (RB) and coefficients (RC); the launcher
+// picks (6, 4) for up to four upper sublevels and (6, 8) above
+template <int TPW> struct FusedStage { static constexpr int RB = 6, RC = TPW == 1 ? 4 : 8; };
+
+struct FusedLayout {
+  size_t bs, el, cf, po;      // byte offsets of the LDS regions
+  size_t total;
+};
+
+__host__ __device__ inline FusedLayout fused_layout(int ldm, int nd, int nu, int nl, int es, int sg, int bst) {
+  FusedLayout L;
+  L.bs = 0;
+  L.el = L.bs + (size_t)ldm * bst * es;
+  L.cf = L.el + (size_t)nl * nd * 64 * es;
+  L.po = L.cf + ((size_t)2 * sg * nu * 2 * nl * 16 + 4) * es;   // + one vector that absorbs idle stores
+  L.total = L.po + (size_t)(3 * sg + 2) * sizeof(int);
+  return L;
+}
+
+template <typename T, int TPW, int NH>
+__global__ void __launch_bounds__(512, TPW == 1 ? 3 : 2) k_fused(
+    int nn, int ldm, int nd, int nth, int nt, int nu, int nl, int ntile, int nblk,
+    const T* __restrict__ M, const T* __restrict__ Ibar, const int* __restrict__ grp, int ngrp,
+    const int* __restrict__ slot_dir, const int* __restrict__ pair_off, const int* __restrict__ pair_o,
+    const T* __restrict__ cf, double c_sc, const double2* __restrict__ E, const double2* __restrict__ bma,
+    const double2* __restrict__ X, const double2* __restrict__ prof, T* __restrict__ Eb) {
+  using Op = MfmaOp<T>;
+  using acc_t = typename Op::acc_t;
+  using V4 = typename Vec4<T>::type;
+  using T2 = typename T2of<T>::type;
+  constexpr int SG = FusedCfg<T>::SG, BST = FusedCfg<T>::BST, NCT = SG / 4;
+  extern __shared__ __align__(16) unsigned char fsh[];
+  const FusedLayout LY = fused_layout(ldm, nd, nu, nl, sizeof(T), SG, BST);
+  T* Bs = reinterpret_cast<T*>(fsh + LY.bs);
+  T* El = reinterpret_cast<T*>(fsh + LY.el);
+  T* CFs = reinterpret_cast<T*>(fsh + LY.cf);
+  int* Poff = reinterpret_cast<int*>(fsh + LY.po);     // [SG + 1] pair offsets of the group's slots
+  int* Po = Poff + SG + 2;                             // [2 SG] outgoing direction of each pair
+  // blocks are dealt round-robin to the 8 XCDs; renumber so that the frequency
+  // tiles of one height (which read the same coefficients) share an XCD's L2
+  const int b = blockIdx.x;
+  const int per = nblk / 8, rem = nblk % 8, xcd = b % 8, kx = b / 8;
+  const int L = xcd < rem ? xcd * (per + 1) + kx : rem * (per + 1) + (xcd - rem) * per + kx;
+  const int tile = L % ntile;
+  const int l = (L / ntile) % nl;
+  const int z = L / (ntile * nl);
+  const int n0 = tile * 16;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, lr = lane & 15, lk = lane >> 4;
+  const int nthr = blockDim.x;
+  const int np = nd * nd;
+  const int n = n0 + lr;
+  const int ncfv = nu * 2 * nl * 4;                    // coefficient vectors per pair (this l)
+  for (int e = tid; e < nl * nd * 64; e += nthr) El[e] = T(0);
+  int uq[TPW], cq[TPW];
+#pragma unroll
+  for (int q = 0; q < TPW; ++q) {
+    const int r = wave * TPW + q;
+    uq[q] = r >> 1;
+    cq[q] = r & 1;
+  }
+  const T* Ib = Ibar + (size_t)z * nd * nn * 4;
+  const T* cfz = cf + (size_t)z * np * nt * 2 * nl * 16;
+
+  // ---- staging of one group into registers, then LDS.  The (slot, k) of each
+  //      B-tile item and the (pair, offset) of each coefficient item depend
+  //      only on the thread, so they are decoded once.
+  constexpr int RB = FusedStage<TPW>::RB, RC = FusedStage<TPW>::RC;
+  int bsk[RB], cpo[RC];
+#pragma unroll
+  for (int i = 0; i < RB; ++i) {
+    const int e = tid + i * nthr;
+    const int sl = e / ldm;
+    bsk[i] = (sl << 16) | (e - sl * ldm);
+  }
+#pragma unroll
+  for (int i = 0; i < RC; ++i) {
+    // e -> (pair pl, u', c, l', quarter); offset of the vector within the pair's block
+    const int e = tid + i * nthr;
+    const int qv = e & 3;
+    int r = e >> 2;
+    const int lp = r % nl; r /= nl;
+    const int c = r & 1; r >>= 1;
+    const int upr = r % nu;
+    const int pl = r / nu;
+    cpo[i] = (pl << 16) | ((((upr * nl + l) * 2 + c) * nl + lp) * 16 + qv * 4);
+  }
+  V4 rb[RB], rc[RC];
+  int rpo0 = 0, rpo1 = 0;
+  auto stage_load = [&](int g) {
+    const int s0 = grp[3 * g + 1], cnt = grp[3 * g + 2];
+    const int pb0 = pair_off[s0], npg = pair_off[s0 + cnt] - pb0;
+    int dir[RB];
+#pragma unroll
+    for (int i = 0; i < RB; ++i) {
+      const int sl = bsk[i] >> 16;
+      dir[i] = slot_dir[s0 + min(sl, cnt - 1)];
+    }
+#pragma unroll
+    for (int i = 0; i < RC; ++i) {
+      const int pl = min(cpo[i] >> 16, npg - 1);
+      rc[i] = *reinterpret_cast<const V4*>(cfz + (size_t)(pb0 + pl) * nt * 2 * nl * 16 + (cpo[i] & 0xffff));
+    }
+    if (tid <= cnt) rpo0 = pair_off[s0 + tid] - pb0;
+    if (tid < npg) rpo1 = pair_o[pb0 + tid];
+#pragma unroll
+    for (int i = 0; i < RB; ++i) {
+      const int sl = bsk[i] >> 16, k = bsk[i] & 0xffff;
+      const V4 v = *reinterpret_cast<const V4*>(Ib + ((size_t)dir[i] * nn + min(k, nn - 1)) * 4);
+      const bool ok = sl < cnt && k < nn;
+      rb[i].x = ok ? v.x : T(0);
+      rb[i].y = ok ? v.y : T(0);
+      rb[i].z = ok ? v.z : T(0);
+      rb[i].w = ok ? v.w : T(0);
+    }
+  };
+  auto stage_store = [&](int g) {
+    const int s0 = grp[3 * g + 1], cnt = grp[3 * g + 2];
+    const int npg = pair_off[s0 + cnt] - pair_off[s0];
+#pragma unroll
+    for (int i = 0; i < RB; ++i) {
+      const int sl = bsk[i] >> 16, k = bsk[i] & 0xffff;
+      if (sl < SG) {
+        T* dst = Bs + (size_t)k * BST;
+        if (Op::kInterleavedRows) {
+          const int base = (sl >> 2) * 16 + (sl & 3);
+          dst[base] = rb[i].x;
+          dst[base + 4] = rb[i].y;
+          dst[base + 8] = rb[i].z;
+          dst[base + 12] = rb[i].w;
+        } else {
+          *reinterpret_cast<V4*>(dst + 4 * sl) = rb[i];
+        }
+      }
+    }
+    const int lim = npg * ncfv, junk = 2 * SG * ncfv;
+#pragma unroll
+    for (int i = 0; i < RC; ++i) {
+      const int e = tid + i * nthr;
+      *reinterpret_cast<V4*>(CFs + (size_t)(e < lim ? e : junk) * 4) = rc[i];
+    }
+    if (tid <= cnt) Poff[tid] = rpo0;
+    if (tid < npg) Po[tid] = rpo1;
+  };
+  // ---- kernel-row fragments (reloaded at a Theta change once the previous
+  //      group's products are done, so the loads overlap its epilogue)
+  T2 mf[TPW][NH];
+  auto load_rows = [&](int th, T2 (&dst)[TPW][NH]) {
+#pragma unroll
+    for (int q = 0; q < TPW; ++q) {
+      const int t = uq[q] * nl + l;
+      const T* row = M + ((((size_t)z * nth + th) * nt + t) * 2 + cq[q]) * (size_t)nn * ldm +
+                     (size_t)min(n, nn - 1) * ldm;
+#pragma unroll
+      for (int h = 0; h < NH; ++h) {
+        if (n < nn) {
+          dst[q][h] = *reinterpret_cast<const T2*>(row + 2 * (4 * h + lk));
+        } else {
+          dst[q][h].x = T(0);
+          dst[q][h].y = T(0);
+        }
+      }
+    }
+  };
+
+  stage_load(0);
+  load_rows(grp[0], mf);
+  __syncthreads();                       // El zeroed
+  stage_store(0);
+  __syncthreads();
+  for (int g = 0; g < ngrp; ++g) {
+    const int th = grp[3 * g], s0 = grp[3 * g + 1], cnt = grp[3 * g + 2];
+    const bool more = g + 1 < ngrp;
+    const bool newth = more && grp[3 * g + 3] != th;
+    if (more) stage_load(g + 1);
+    acc_t acc[TPW][NCT];
+#pragma unroll
+    for (int q = 0; q < TPW; ++q)
+#pragma unroll
+      for (int jt = 0; jt < NCT; ++jt)
+        for (int r = 0; r < 4; ++r) acc[q][jt][r] = T(0);
+#pragma unroll
+    for (int h = 0; h < NH; ++h) {
+#pragma unroll
+      for (int jj = 0; jj < 2; ++jj) {
+        const int k = 2 * (4 * h + lk) + jj;
+#pragma unroll
+        for (int jt = 0; jt < NCT; ++jt) {
+          const T af = Bs[k * BST + jt * 16 + lr];
+#pragma unroll
+          for (int q = 0; q < TPW; ++q) acc[q][jt] = Op::run(af, jj ? mf[q][h].y : mf[q][h].x, acc[q][jt]);
+        }
+      }
+    }
+    if (newth) load_rows(grp[3 * g + 3], mf);
+    // lane holds W_{t,c}(slot s0 + 4 jt + lk, n, Stokes 0..3)
+    if (n < nn) {
+#pragma unroll
+      for (int q = 0; q < TPW; ++q) {
+#pragma unroll
+        for (int jt = 0; jt < NCT; ++jt) {
+          const int sl = 4 * jt + lk;
+          if (sl < cnt) {
+            const T w0 = acc[q][jt][0], w1 = acc[q][jt][1], w2 = acc[q][jt][2], w3 = acc[q][jt][3];
+            const int p1 = Poff[sl + 1];
+            for (int pl = Poff[sl]; pl < p1; ++pl) {
+              const int o = Po[pl];
+              const T* cp = CFs + (((size_t)pl * nu + uq[q]) * 2 + cq[q]) * nl * 16;
+              for (int lp = 0; lp < nl; ++lp) {
+                T* dst = El + ((lp * nd + o) * 16 + lr) * 4;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                  const V4 c4 = *reinterpret_cast<const V4*>(cp + lp * 16 + i * 4);
+                  atomicAdd(dst + i, c4.x * w0 + c4.y * w1 + c4.z * w2 + c4.w * w3);
+                }
+              }
+            }
+          }
+        }
+      }
+    }
+    __syncthreads();
+    if (more) stage_store(g + 1);
+    __syncthreads();
+  }
+  // write eps_bar[z][l][l'][o][n][s], adding the R_III term
+  //   D_i(o, l', u, u') = c_sc/(4 pi) (beta - alpha)_{u u'} E_i(o; u', u, l') X[u][u'][l]
+  const double sc3 = c_sc * 0.25 * kInvPi;
+  for (int e = tid; e < nl * nd * 16; e += nthr) {
+    const int le = e & 15, o = (e >> 4) % nd, lp = (e >> 4) / nd;
+    const int ne = n0 + le;
+    if (ne >= nn) continue;
+    double r3[4] = {0.0, 0.0, 0.0, 0.0};
+    const double2* Ez = E + ((size_t)z * nd + o) * 4 * nu * nu * nl;
+    for (int u = 0; u < nu; ++u)
+      for (int upr = 0; upr < nu; ++upr) {
+        const double2 bx = cmul(bma[((size_t)z * nu + u) * nu + upr], X[(((size_t)z * nu + u) * nu + upr) * nl + l]);
+        const double2 pa = prof[((size_t)z * nt + upr * nl + l) * nn + ne];
+        const double2 pb = prof[((size_t)z * nt + u * nl + l) * nn + ne];
+        for (int i = 0; i < 4; ++i) {
+          const double2 d = cmul(Ez[((size_t)(i * nu + upr) * nu + u) * nl + lp], bx);
+          r3[i] += d.x * (pa.x + pb.x) - d.y * (pa.y - pb.y);
+        }
+      }
+    T* dst = Eb + ((((size_t)z * nl + l) * nl + lp) * nd + o) * (size_t)nn * 4 + (size_t)ne * 4;
+    for (int i = 0; i < 4; ++i) dst[i] = (T)((double)El[e * 4 + i] + sc3 * r3[i]);
+  }
+}
+
+// LDS bytes of the fused kernel, or 0 when the problem does not fit its limits
+// (padded frequency count <= 128, 2..8 upper sublevels, staging within the
+// per-thread register budget, LDS within the device's per-block limit).
+static size_t fused_lds(const trap_ctx* ctx, int prec) {
+  const Problem& P = ctx->pb;
+  // the FP64 operator (residuals, normalisation) keeps the height-chunked path
+  if (prec == TRAP_FP64) return 0;
+  const bool f64 = prec == TRAP_FP64;
+  const int es = f64 ? 8 : 4;
+  const int sg = f64 ? FusedCfg<double>::SG : FusedCfg<float>::SG;
+  const int bst = f64 ? FusedCfg<double>::BST : FusedCfg<float>::BST;
+  if (P.ldm > 128 || P.nu < 2 || P.nu > 8 || P.grp_maxpairs[f64 ? 0 : 1] > 2 * sg) return 0;
+  const bool tpw1 = 2 * P.nu <= 8;
+  const int nthr = 64 * (tpw1 ? 2 * P.nu : P.nu);
+  const int rb = tpw1 ? FusedStage<1>::RB : FusedStage<2>::RB, rc = tpw1 ? FusedStage<1>::RC : FusedStage<2>::RC;
+  if ((long long)nthr * rb < (long long)P.ldm * sg) return 0;
+  if ((long long)nthr * rc < 2LL * sg * P.nu * 2 * P.nl * 4) return 0;
+  if (nthr < 3 * sg + 2) return 0;
+  const FusedLayout L = fused_layout(P.ldm, P.nd, P.nu, P.nl, es, sg, bst);
+  if (L.total > (size_t)ctx->max_lds) return 0;
+  return L.total;
+}
+
+template <typename T, int TPW, int NH>
+static int launch_fused_t(trap_ctx* ctx, size_t lds, int nw, const T* Mk, const T* Ibar, const T* cf, T* Eb) {
+  Problem& P = ctx->pb;
+  const int pi = sizeof(T) == 8 ? 0 : 1;
+  const int ntile = ceil_div(P.nn, 16);
+  const int nblk = P.nz * ntile * P.nl;
+  auto kern = k_fused<T, TPW, NH>;
+  if (lds > 64 * 1024)
+    TRAP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)lds));
+  hipLaunchKernelGGL(kern, dim3(nblk), dim3(64 * nw), lds, ctx->stream, P.nn, P.ldm, P.nd, P.nth, P.nt, P.nu,
+                     P.nl, ntile, nblk, Mk, Ibar, P.d_grp[pi], (int)P.grp[pi].size() / 3, P.d_slot_dir,
+                     P.d_pair_off, P.d_pair_o, cf, P.c_sc, P.d_E, P.d_bma, ctx->wk.X, ctx->pre.d_prof, Eb);
+  TRAP_HIP(hipGetLastError());
+  return TRAP_OK;
+}
+
+template <typename T, int TPW>
+static int launch_fused_nh(trap_ctx* ctx, size_t lds, int nw, const T* Mk, const T* Ibar, const T* cf, T* Eb) {
+  switch (ctx->pb.ldm / 8) {
+#define TRAP_FUSED_CASE(NHV) \
+  case NHV: return launch_fused_t<T, TPW, NHV>(ctx, lds, nw, Mk, Ibar, cf, Eb);
+    TRAP_FUSED_CASE(1) TRAP_FUSED_CASE(2) TRAP_FUSED_CASE(3) TRAP_FUSED_CASE(4)
+    TRAP_FUSED_CASE(5) TRAP_FUSED_CASE(6) TRAP_FUSED_CASE(7) TRAP_FUSED_CASE(8)
+    TRAP_FUSED_CASE(9) TRAP_FUSED_CASE(10) TRAP_FUSED_CASE(11) TRAP_FUSED_CASE(12)
+    TRAP_FUSED_CASE(13) TRAP_FUSED_CASE(14) TRAP_FUSED_CASE(15) TRAP_FUSED_CASE(16)
+#undef TRAP_FUSED_CASE
+    default: return fail(TRAP_EINVAL, "frequency grid too large for the fused Sigma kernel");
+  }
+}
+
+template <typename T>
+static int launch_fused(trap_ctx* ctx, size_t lds, const T* Mk, const T* Ibar, const T* cf, T* Eb) {
+  const int nu = ctx->pb.nu;
+  if (2 * nu <= 8) return launch_fused_nh<T, 1>(ctx, lds, 2 * nu, Mk, Ibar, cf, Eb);
+  return launch_fused_nh<T, 2>(ctx, lds, nu, Mk, Ibar, cf, Eb);
+}
+
 // ------------------------------------------------------------------ driver
 static size_t elem_size(int prec) { return prec == TRAP_FP64 ? sizeof(double) : sizeof(float); }
 
@@ -475,11 +808,11 @@ int ensure_work(trap_ctx* ctx, int prec) {
     K.zchunk = (int)std::max<size_t>(1, std::min<size_t>(nz, (size_t(1) << 30) / std::max<size_t>(per_z, 1)));
   }
   const int pi = prec == TRAP_FP64 ? 0 : 1;
-  if (!K.W[pi]) {
+  if (!K.Ibar[pi]) {
     const size_t es = elem_size(prec);
-    const size_t zc = K.zchunk;
-    TRAP_TRY(dalloc(ctx, &K.Ibar[pi], zc * nd * nn * 4 * es));
-    TRAP_TRY(dalloc(ctx, &K.W[pi], zc * P.nt * P.nslot * 2 * nn * 4 * es));
+    // comoving field for every height (the fused path reads all of it; the
+    // chunked path uses the first chunk); W is allocated by the chunked path
+    TRAP_TRY(dalloc(ctx, &K.Ibar[pi], nz * nd * nn * 4 * es));
     TRAP_TRY(dalloc(ctx, &K.Eb[pi], nz * P.nl * P.nl * nd * nn * 4 * es));
     TRAP_TRY(dalloc(ctx, &K.tmp[pi], N * es));
     TRAP_TRY(dalloc(ctx, &K.opeps[pi], N * es));
@@ -501,7 +834,45 @@ static int sigma_apply_t(trap_ctx* ctx, const T* I, T* eps, int prec, int add_th
   T* Eb = static_cast<T*>(K.Eb[pi]);
   const int ncls = nl * nl;
   const size_t spl_lds = (size_t)8 * nn * sizeof(double);
-  for (int z0 = 0; z0 < nz; z0 += K.zchunk) {
+  // the fused kernel runs only when asked for: its LDS scatter of the angular
+  // sum is still slower than materialising W per height chunk
+  const size_t flds = ctx->path == TRAP_PATH_FUSED ? fused_lds(ctx, prec) : 0;
+  if (ctx->path == TRAP_PATH_FUSED && flds == 0)
+    return fail(TRAP_EINVAL, "problem exceeds the fused Sigma kernel's limits");
+  const T* cf = sizeof(T) == 8 ? (const T*)C.d_cf64 : (const T*)C.d_cf32;
+  if (flds && cf) {
+    // 1. comoving interpolation, all heights
+    int pr = prof_begin(ctx, TRAP_STAGE_COMOVING);
+    hipLaunchKernelGGL(k_spline_shift<T>, dim3(nz * nd), dim3(128), spl_lds, s, 0, nz, nd, nn, P.d_x,
+                       P.d_SigT, P.d_lam, P.d_ub, -1.0, (const double*)nullptr, 1, 0, I,
+                       (long long)nd * nn * 4, (long long)nn * 4, Ibar, 0, (const double*)nullptr,
+                       (const double*)nullptr);
+    TRAP_HIP(hipGetLastError());
+    prof_end(ctx, pr);
+    // 2. R_III factors, all heights
+    pr = prof_begin(ctx, TRAP_STAGE_R3);
+    const long long ny = (long long)nz * nt * nd * 4;
+    hipLaunchKernelGGL(k_r3_Y<T>, dim3(ceil_div(ny, 256)), dim3(256), 0, s, 0, nz, nt, nd, nn, C.d_r3, Ibar,
+                       K.Y);
+    TRAP_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_r3_X, dim3(nz * nu * nu * nl), dim3(256), 0, s, 0, nu, nl, nd, P.d_w, P.d_A, K.Y,
+                       K.X);
+    TRAP_HIP(hipGetLastError());
+    prof_end(ctx, pr);
+    // 3. fused R_II contraction, angular/sublevel sum and R_III into eps_bar
+    {
+      const double kel = (double)nz * nth * nt * 2.0 * nn * P.ldm;
+      const double flops = 16.0 * nz * nt * (double)nn * nn * P.nslot;
+      const double bytes = sizeof(T) * (kel + (double)nz * nd * nn * 4 + (double)nz * nd * nd * nt * 2 * nl * 16 +
+                                        (double)nz * ncls * nd * nn * 4);
+      pr = prof_begin(ctx, sizeof(T) == 8 ? TRAP_STAGE_CONTRACT_FP64 : TRAP_STAGE_CONTRACT, flops, bytes);
+    }
+    if constexpr (sizeof(T) == sizeof(float)) {
+      TRAP_TRY(launch_fused<T>(ctx, flds, Mk, Ibar, cf, Eb));
+    }
+    prof_end(ctx, pr);
+  }
+  for (int z0 = 0; z0 < nz && !(flds && cf); z0 += K.zchunk) {
     const int zc = std::min(K.zchunk, nz - z0);
     const long long npts = (long long)zc * nd * nn;
     // 1. comoving interpolation
@@ -519,6 +890,10 @@ static int sigma_apply_t(trap_ctx* ctx, const T* I, T* eps, int prec, int add_th
       const double flops = 16.0 * zc * nt * (double)nn * nn * P.nslot;
       const double bytes = sizeof(T) * (kel + (double)zc * nt * P.nslot * 2.0 * nn * 4 + (double)zc * nd * nn * 4);
       pr = prof_begin(ctx, sizeof(T) == 8 ? TRAP_STAGE_CONTRACT_FP64 : TRAP_STAGE_CONTRACT, flops, bytes);
+    }
+    if (!W) {
+      TRAP_TRY(dalloc(ctx, &K.W[pi], (size_t)K.zchunk * nt * P.nslot * 2 * nn * 4 * sizeof(T)));
+      W = static_cast<T*>(K.W[pi]);
     }
     hipLaunchKernelGGL(k_contract<T>, grid, dim3(512), 0, s, z0, nth, nt, nn, P.ldm, nd, Mk, Ibar,
                        P.d_slot_off, P.d_slot_dir, W, P.nslot);

@@ -18,36 +18,54 @@
 namespace trap {
 
 // partial[b * ncols + k] = sum over block b of V_k . w
-__global__ void k_multidot(const double* __restrict__ V, int ncols, long long N,
-                           const double* __restrict__ w, double* __restrict__ partial) {
-  __shared__ double sh[256];
-  for (int k = 0; k < ncols; ++k) {
-    double s = 0.0;
-    const double* v = V + (size_t)k * N;
+// partial[block][k] = sum over this block's share of i of V[k][i] w[i]; columns
+// are taken eight at a time so w is read once per eight basis vectors.
+__device__ inline double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+__global__ void __launch_bounds__(256) k_multidot(const double* __restrict__ V, int ncols, long long N,
+                                                  const double* __restrict__ w, double* __restrict__ partial) {
+  __shared__ double sh[4][8];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int k0 = 0; k0 < ncols; k0 += 8) {
+    const int kc = min(8, ncols - k0);
+    double s[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) s[q] = 0.0;
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < N;
-         i += (long long)gridDim.x * blockDim.x)
-      s += v[i] * w[i];
-    sh[threadIdx.x] = s;
-    __syncthreads();
-    for (int st = blockDim.x / 2; st > 0; st >>= 1) {
-      if (threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
-      __syncthreads();
+         i += (long long)gridDim.x * blockDim.x) {
+      const double wi = w[i];
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        if (q < kc) s[q] += V[(size_t)(k0 + q) * N + i] * wi;
     }
-    if (threadIdx.x == 0) partial[(size_t)blockIdx.x * ncols + k] = sh[0];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const double t = wave_sum(s[q]);
+      if (lane == 0) sh[wave][q] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x < kc)
+      partial[(size_t)blockIdx.x * ncols + k0 + threadIdx.x] =
+          sh[0][threadIdx.x] + sh[1][threadIdx.x] + sh[2][threadIdx.x] + sh[3][threadIdx.x];
     __syncthreads();
   }
 }
 
-__global__ void k_reduce_partial(const double* __restrict__ partial, int nblocks, int ncols,
-                                 double* __restrict__ out) {
-  const int k = threadIdx.x;
-  if (k >= ncols) return;
+// out[k] = sum over blocks of partial[b][k]; one block per column.
+__global__ void __launch_bounds__(256) k_reduce_partial(const double* __restrict__ partial, int nblocks,
+                                                        int ncols, double* __restrict__ out) {
+  __shared__ double sh[4];
+  const int k = blockIdx.x;
   double s = 0.0;
-  for (int b = 0; b < nblocks; ++b) s += partial[(size_t)b * ncols + k];
-  out[k] = s;
+  for (int b = threadIdx.x; b < nblocks; b += blockDim.x) s += partial[(size_t)b * ncols + k];
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) out[k] = sh[0] + sh[1] + sh[2] + sh[3];
 }
-
-// w -= sum_k h[k] V_k
 __global__ void k_multiaxpy(const double* __restrict__ V, int ncols, long long N,
                             const double* __restrict__ h, double* __restrict__ w) {
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < N;
@@ -93,36 +111,6 @@ namespace {
 
 constexpr int kBlocks = 512;
 
-struct Blas {
-  trap_ctx* ctx;
-  long long N;
-  double* partial;     // [kBlocks * maxcols]
-  double* dres;        // [maxcols]
-  std::vector<double> hbuf;
-  int dots(const double* V, int ncols, const double* w, double* host_out) {
-    hipLaunchKernelGGL(k_multidot, dim3(kBlocks), dim3(256), 0, ctx->stream, V, ncols, N, w, partial);
-    TRAP_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_reduce_partial, dim3(1), dim3(std::max(64, ncols)), 0, ctx->stream, partial,
-                       kBlocks, ncols, dres);
-    TRAP_HIP(hipGetLastError());
-    TRAP_HIP(hipMemcpyAsync(host_out, dres, ncols * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
-    TRAP_HIP(hipStreamSynchronize(ctx->stream));
-    return TRAP_OK;
-  }
-  int axpy_many(const double* V, int ncols, const double* host_h, double* w) {
-    TRAP_HIP(hipMemcpyAsync(dres, host_h, ncols * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
-    hipLaunchKernelGGL(k_multiaxpy, dim3(kBlocks), dim3(256), 0, ctx->stream, V, ncols, N, dres, w);
-    TRAP_HIP(hipGetLastError());
-    return TRAP_OK;
-  }
-  int norm(const double* x, double* out) {
-    double v;
-    TRAP_TRY(dots(x, 1, x, &v));
-    *out = std::sqrt(std::max(v, 0.0));
-    return TRAP_OK;
-  }
-};
-
 // y = A x with the operator in precision `prec` (x, y FP64)
 int op_apply(trap_ctx* ctx, int prec, const double* x, double* y, trap_solve_stats* st) {
   Work& K = ctx->wk;
@@ -141,97 +129,70 @@ int op_apply(trap_ctx* ctx, int prec, const double* x, double* y, trap_solve_sta
   return TRAP_OK;
 }
 
-// One GMRES run on A d = r (r FP64 device, not modified), d accumulated into x.
-// Stops when the estimated residual falls below target or after max_it steps.
-int gmres_core(trap_ctx* ctx, Blas& B, int prec, int m, const double* r, double rnorm, double target,
-               int max_it, double* x, int* iters, trap_solve_stats* st) {
-  Work& K = ctx->wk;
-  const long long N = B.N;
-  double* V = K.V;
-  std::vector<double> H((m + 1) * m, 0.0), cs(m), sn(m), g(m + 1), h(m + 1), h2(m + 1);
-  double beta = rnorm;
-  int total = 0;
-  // V0 = r / beta
-  hipLaunchKernelGGL(k_scale_copy, dim3(kBlocks), dim3(256), 0, ctx->stream, N, 1.0 / beta, r, V);
+}  // namespace
+
+// ---------------------------------------------------------------- GMRES state machine
+// One run of the (mixed-precision) restarted GMRES of a context, advanced in
+// units that end at a host synchronisation point, so that many contexts can be
+// advanced together with one wait per phase (trap_gmres_step_batch):
+//   RESID_OUTER    r = b - A64 x and its norm             (one sync)
+//   RESID_RESTART  r_k = r - A_p d and its norm           (one sync)
+//   ARNOLDI        w = A_p v_j; h = V^T w                  (sync 1)
+//                  w -= V h; h2 = [V, w]^T w               (sync 2)
+//                  w -= V h2, |w| from h2, Givens update    (no sync)
+// The norm after the second projection follows from ||w - V h2||^2 =
+// ||w||^2 - ||h2||^2 (V orthonormal); when that difference is small against
+// ||w||^2 it is recomputed with one more reduction.
+enum GmresPhase { GP_RESID_OUTER = 0, GP_RESID_RESTART = 1, GP_ARNOLDI = 2, GP_DONE = 3 };
+
+struct GmresRun {
+  trap_solve_opts opts{};
+  trap_solve_stats st{};
+  double* x = nullptr;
+  long long N = 0;
+  int m = 0, prec = TRAP_FP64, phase = GP_DONE, status = TRAP_OK;
+  int outer = 0, j = 0, max_outer = 1;
+  bool p2 = false;            // an Arnoldi step waits for its second reduction
+  double bnorm = 0, beta = 0, target = 0, res = 0, rel = 0;
+  std::vector<double> H, cs, sn, g, h;
+  double* hbuf = nullptr;     // pinned host copy of the reductions, 2 (m + 2)
+  double* partial = nullptr;  // device reduction scratch
+  double* dres = nullptr;
+  std::chrono::steady_clock::time_point t0;
+};
+
+namespace {
+
+int dots_async(trap_ctx* ctx, GmresRun& R, const double* V, int ncols, const double* w, double* host_out) {
+  hipLaunchKernelGGL(k_multidot, dim3(kBlocks), dim3(256), 0, ctx->stream, V, ncols, R.N, w, R.partial);
   TRAP_HIP(hipGetLastError());
-  // restarts: residual of the correction problem is recomputed with the same operator
-  double* wres = K.tmp64;
-  while (true) {
-    std::fill(g.begin(), g.end(), 0.0);
-    g[0] = beta;
-    int j = 0;
-    double res = beta;
-    for (; j < m && total < max_it; ++j) {
-      double* w = V + (size_t)(j + 1) * N;
-      TRAP_TRY(op_apply(ctx, prec, V + (size_t)j * N, w, st));
-      ++total;
-      TRAP_TRY(B.dots(V, j + 1, w, h.data()));
-      TRAP_TRY(B.axpy_many(V, j + 1, h.data(), w));
-      TRAP_TRY(B.dots(V, j + 1, w, h2.data()));
-      TRAP_TRY(B.axpy_many(V, j + 1, h2.data(), w));
-      for (int i = 0; i <= j; ++i) h[i] += h2[i];
-      double hn;
-      TRAP_TRY(B.norm(w, &hn));
-      if (!std::isfinite(hn)) return fail(TRAP_ENAN, "non-finite Arnoldi vector");
-      for (int i = 0; i <= j; ++i) H[i * m + j] = h[i];
-      H[(j + 1) * m + j] = hn;
-      if (hn > 0.0) {
-        hipLaunchKernelGGL(k_scale_copy, dim3(kBlocks), dim3(256), 0, ctx->stream, N, 1.0 / hn, w, w);
-        TRAP_HIP(hipGetLastError());
-      }
-      // apply previous rotations
-      for (int i = 0; i < j; ++i) {
-        const double a = H[i * m + j], b = H[(i + 1) * m + j];
-        H[i * m + j] = cs[i] * a + sn[i] * b;
-        H[(i + 1) * m + j] = -sn[i] * a + cs[i] * b;
-      }
-      const double a = H[j * m + j], b = H[(j + 1) * m + j];
-      const double den = std::hypot(a, b);
-      cs[j] = den > 0 ? a / den : 1.0;
-      sn[j] = den > 0 ? b / den : 0.0;
-      H[j * m + j] = den;
-      H[(j + 1) * m + j] = 0.0;
-      g[j + 1] = -sn[j] * g[j];
-      g[j] = cs[j] * g[j];
-      res = std::fabs(g[j + 1]);
-      if (res <= target || hn == 0.0) {
-        ++j;
-        break;
-      }
-    }
-    // solve H y = g (upper triangular j x j) and update x += V y
-    std::vector<double> y(j, 0.0);
-    for (int i = j - 1; i >= 0; --i) {
-      double v = g[i];
-      for (int k = i + 1; k < j; ++k) v -= H[i * m + k] * y[k];
-      y[i] = v / H[i * m + i];
-    }
-    for (int i = 0; i < j; ++i) y[i] = -y[i];
-    TRAP_TRY(B.axpy_many(V, j, y.data(), x));        // x -= (-y) V  ==  x += V y
-    if (res <= target || total >= max_it) {
-      *iters = total;
-      return TRAP_OK;
-    }
-    // restart: new residual r - A (x - x_start) is not tracked separately; the
-    // caller passes r for a zero start, so recompute r_new = r - A x_acc
-    TRAP_TRY(op_apply(ctx, prec, x, wres, st));
-    hipLaunchKernelGGL(k_axpby, dim3(kBlocks), dim3(256), 0, ctx->stream, N, 1.0, r, -1.0, wres);
-    TRAP_HIP(hipGetLastError());
-    TRAP_TRY(B.norm(wres, &beta));
-    if (beta <= target) {
-      *iters = total;
-      return TRAP_OK;
-    }
-    hipLaunchKernelGGL(k_scale_copy, dim3(kBlocks), dim3(256), 0, ctx->stream, N, 1.0 / beta, wres, V);
-    TRAP_HIP(hipGetLastError());
-    std::fill(H.begin(), H.end(), 0.0);
-  }
+  hipLaunchKernelGGL(k_reduce_partial, dim3(ncols), dim3(256), 0, ctx->stream, R.partial, kBlocks, ncols,
+                     R.dres);
+  TRAP_HIP(hipGetLastError());
+  TRAP_HIP(hipMemcpyAsync(host_out, R.dres, ncols * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  return TRAP_OK;
+}
+
+// w -= sum_k coef[k] V_k (coefficients from the host; copied through the
+// second half of the pinned buffer so the copy is ordered on the stream)
+int axpy_async(trap_ctx* ctx, GmresRun& R, const double* V, int ncols, const double* coef, double* w,
+               double* dcoef) {
+  TRAP_HIP(hipMemcpyAsync(dcoef, coef, ncols * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+  hipLaunchKernelGGL(k_multiaxpy, dim3(kBlocks), dim3(256), 0, ctx->stream, V, ncols, R.N, dcoef, w);
+  TRAP_HIP(hipGetLastError());
+  return TRAP_OK;
 }
 
 }  // namespace
 
-int gmres_solve(trap_ctx* ctx, const trap_solve_opts* opts, double* I, trap_solve_stats* st) {
-  auto t0 = std::chrono::steady_clock::now();
+static void run_finish(GmresRun& R, int status) {
+  R.phase = GP_DONE;
+  R.status = status;
+  R.st.final_rel_res = R.rel;
+  R.st.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - R.t0).count();
+}
+
+int gmres_begin(trap_ctx* ctx, const trap_solve_opts* opts, double* I) {
   if (!ctx->has_problem || !ctx->pre.done) return fail(TRAP_ESTATE, "precompute not run");
   if (!opts || !I) return fail(TRAP_EINVAL, "null argument");
   if (!(opts->tol > 0) || opts->restart < 1 || opts->max_iters < 0)
@@ -239,9 +200,6 @@ int gmres_solve(trap_ctx* ctx, const trap_solve_opts* opts, double* I, trap_solv
   const int inner = opts->inner;
   if (inner != TRAP_FP64 && inner != TRAP_FP32) return fail(TRAP_EINVAL, "bad inner precision");
   if (inner == TRAP_FP32 && !ctx->pre.d_M32) return fail(TRAP_ESTATE, "FP32 kernels not stored");
-  trap_solve_stats local{};
-  if (!st) st = &local;
-  *st = trap_solve_stats{};
   Work& K = ctx->wk;
   const long long N = 4LL * ctx->pb.nz * ctx->pb.nd * ctx->pb.nn;
   TRAP_TRY(ensure_work(ctx, TRAP_FP64));
@@ -249,79 +207,304 @@ int gmres_solve(trap_ctx* ctx, const trap_solve_opts* opts, double* I, trap_solv
   const int m = opts->restart;
   if (K.V_cols < m + 1) {
     TRAP_TRY(dalloc_t(ctx, &K.V, (size_t)(m + 1) * N));
-    TRAP_TRY(dalloc_t(ctx, &K.dots, (size_t)kBlocks * (m + 2) + (m + 2)));
+    TRAP_TRY(dalloc_t(ctx, &K.dots, (size_t)kBlocks * (m + 2) + 2 * (m + 2)));
     K.V_cols = m + 1;
   }
   if (inner == TRAP_FP32 && !K.v32a) {
     TRAP_TRY(dalloc_t(ctx, &K.v32a, N));
     TRAP_TRY(dalloc_t(ctx, &K.v32b, N));
   }
-  Blas B{ctx, N, nullptr, nullptr, {}};
-  static_assert(sizeof(double) == 8, "double");
-  // scratch for reductions: kBlocks * (m+2) partials + (m+2) results
-  B.partial = K.dots;
-  B.dres = K.dots + (size_t)kBlocks * (K.V_cols + 1);
+  if (!ctx->run) ctx->run = new (std::nothrow) GmresRun();
+  if (!ctx->run) return fail(TRAP_ENOMEM, "host allocation failed");
+  GmresRun& R = *ctx->run;
+  if (R.hbuf && R.m < m) {
+    (void)hipHostFree(R.hbuf);
+    R.hbuf = nullptr;
+  }
+  if (!R.hbuf) TRAP_HIP(hipHostMalloc(reinterpret_cast<void**>(&R.hbuf), 4 * (m + 2) * sizeof(double)));
+  R.opts = *opts;
+  R.st = trap_solve_stats{};
+  R.x = I;
+  R.N = N;
+  R.m = m;
+  R.prec = inner;
+  R.outer = 0;
+  R.p2 = false;
+  R.max_outer = inner == TRAP_FP64 ? 1 : std::max(1, opts->max_outer);
+  R.H.assign((size_t)(m + 1) * m, 0.0);
+  R.cs.assign(m, 0.0);
+  R.sn.assign(m, 0.0);
+  R.g.assign(m + 1, 0.0);
+  R.h.assign(m + 2, 0.0);
+  R.partial = K.dots;
+  R.dres = K.dots + (size_t)kBlocks * (m + 2);
+  R.t0 = std::chrono::steady_clock::now();
+  // initial guess must be finite; ||b|| (one synchronisation)
   int* dflag = reinterpret_cast<int*>(K.red);
   TRAP_HIP(hipMemsetAsync(dflag, 0, sizeof(int), ctx->stream));
   hipLaunchKernelGGL(k_nonfinite, dim3(kBlocks), dim3(256), 0, ctx->stream, N, I, dflag);
-  int hflag = 0;
-  TRAP_HIP(hipMemcpyAsync(&hflag, dflag, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  TRAP_HIP(hipGetLastError());
+  int* hflag = reinterpret_cast<int*>(R.hbuf + 2 * (m + 2));
+  *hflag = 0;
+  TRAP_HIP(hipMemcpyAsync(hflag, dflag, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  TRAP_TRY(dots_async(ctx, R, ctx->pre.d_b, 1, ctx->pre.d_b, R.hbuf));
   TRAP_HIP(hipStreamSynchronize(ctx->stream));
-  if (hflag) return fail(TRAP_ENAN, "non-finite initial guess");
-  const double* b = ctx->pre.d_b;
-  double bnorm;
-  TRAP_TRY(B.norm(b, &bnorm));
-  if (!(bnorm > 0)) return fail(TRAP_EINVAL, "zero right-hand side");
-  double* r = K.r;
-  double* d = K.x;
-  int status = TRAP_OK;
-  double rel = 0.0;
-  const int max_outer = inner == TRAP_FP64 ? 1 : std::max(1, opts->max_outer);
-  for (int outer = 0;; ++outer) {
-    // r = b - A64 I
-    TRAP_TRY(op_apply(ctx, TRAP_FP64, I, r, st));
-    hipLaunchKernelGGL(k_axpby, dim3(kBlocks), dim3(256), 0, ctx->stream, N, 1.0, b, -1.0, r);
+  if (*hflag) {
+    run_finish(R, fail(TRAP_ENAN, "non-finite initial guess"));
+    return R.status;
+  }
+  R.bnorm = std::sqrt(std::max(R.hbuf[0], 0.0));
+  if (!(R.bnorm > 0)) {
+    run_finish(R, fail(TRAP_EINVAL, "zero right-hand side"));
+    return R.status;
+  }
+  R.phase = GP_RESID_OUTER;
+  R.status = 1;
+  return TRAP_OK;
+}
+
+namespace {
+
+// phase-1 work of one unit (everything up to its first synchronisation)
+int unit_issue1(trap_ctx* ctx, GmresRun& R) {
+  Work& K = ctx->wk;
+  const long long N = R.N;
+  switch (R.phase) {
+    case GP_RESID_OUTER:
+      TRAP_TRY(op_apply(ctx, TRAP_FP64, R.x, K.r, &R.st));
+      hipLaunchKernelGGL(k_axpby, dim3(kBlocks), dim3(256), 0, ctx->stream, N, 1.0, ctx->pre.d_b, -1.0, K.r);
+      TRAP_HIP(hipGetLastError());
+      return dots_async(ctx, R, K.r, 1, K.r, R.hbuf);
+    case GP_RESID_RESTART:
+      TRAP_TRY(op_apply(ctx, R.prec, K.x, K.tmp64, &R.st));
+      hipLaunchKernelGGL(k_axpby, dim3(kBlocks), dim3(256), 0, ctx->stream, N, 1.0, K.r, -1.0, K.tmp64);
+      TRAP_HIP(hipGetLastError());
+      return dots_async(ctx, R, K.tmp64, 1, K.tmp64, R.hbuf);
+    case GP_ARNOLDI: {
+      double* w = K.V + (size_t)(R.j + 1) * N;
+      TRAP_TRY(op_apply(ctx, R.prec, K.V + (size_t)R.j * N, w, &R.st));
+      return dots_async(ctx, R, K.V, R.j + 1, w, R.hbuf);
+    }
+    default:
+      return TRAP_OK;
+  }
+}
+
+// start an Arnoldi cycle from the (unnormalised) residual vector src of norm beta
+int start_cycle(trap_ctx* ctx, GmresRun& R, const double* src, double beta) {
+  R.beta = beta;
+  std::fill(R.g.begin(), R.g.end(), 0.0);
+  std::fill(R.H.begin(), R.H.end(), 0.0);
+  R.g[0] = beta;
+  R.j = 0;
+  hipLaunchKernelGGL(k_scale_copy, dim3(kBlocks), dim3(256), 0, ctx->stream, R.N, 1.0 / beta, src, ctx->wk.V);
+  TRAP_HIP(hipGetLastError());
+  R.phase = GP_ARNOLDI;
+  return TRAP_OK;
+}
+
+// end of an Arnoldi cycle: d += V y with H y = g; then either restart or refine
+int end_cycle(trap_ctx* ctx, GmresRun& R, bool converged) {
+  Work& K = ctx->wk;
+  const int m = R.m, j = R.j;
+  std::vector<double> y(j, 0.0);
+  for (int i = j - 1; i >= 0; --i) {
+    double v = R.g[i];
+    for (int k = i + 1; k < j; ++k) v -= R.H[(size_t)i * m + k] * y[k];
+    y[i] = v / R.H[(size_t)i * m + i];
+  }
+  for (int i = 0; i < j; ++i) y[i] = -y[i];
+  double* hc = R.hbuf + 2 * (m + 2) + 2;   // staging of the coefficients, past the flag
+  std::copy(y.begin(), y.end(), hc);
+  TRAP_TRY(axpy_async(ctx, R, K.V, j, hc, K.x, R.dres));    // d -= (-y) V
+  const bool out_of_iters = R.st.inner_iters >= R.opts.max_iters;
+  if (converged || out_of_iters) {
+    hipLaunchKernelGGL(k_axpby, dim3(kBlocks), dim3(256), 0, ctx->stream, R.N, 1.0, K.x, 1.0, R.x);
     TRAP_HIP(hipGetLastError());
-    double rn;
-    TRAP_TRY(B.norm(r, &rn));
-    rel = rn / bnorm;
-    if (!std::isfinite(rel)) {
-      status = fail(TRAP_ENAN, "non-finite residual");
-      break;
+    R.phase = GP_RESID_OUTER;
+  } else {
+    R.phase = GP_RESID_RESTART;
+  }
+  return TRAP_OK;
+}
+
+// host work after sync 1; issues phase-2 work of Arnoldi units
+int unit_after1(trap_ctx* ctx, GmresRun& R) {
+  Work& K = ctx->wk;
+  const long long N = R.N;
+  switch (R.phase) {
+    case GP_RESID_OUTER: {
+      const double rn = std::sqrt(std::max(R.hbuf[0], 0.0));
+      R.rel = rn / R.bnorm;
+      if (!std::isfinite(R.rel)) {
+        run_finish(R, fail(TRAP_ENAN, "non-finite residual"));
+        return TRAP_OK;
+      }
+      if (R.rel < R.opts.tol) {
+        run_finish(R, TRAP_OK);
+        return TRAP_OK;
+      }
+      if (R.outer >= R.max_outer || R.st.inner_iters >= R.opts.max_iters) {
+        run_finish(R, fail(TRAP_ENOCONV, "tolerance not reached"));
+        return TRAP_OK;
+      }
+      R.outer++;
+      R.st.outer_steps = R.outer;
+      TRAP_HIP(hipMemsetAsync(K.x, 0, N * sizeof(double), ctx->stream));
+      R.target = R.prec == TRAP_FP64 ? 0.999 * R.opts.tol * R.bnorm
+                                     : std::max(R.opts.inner_tol * rn, 0.5 * R.opts.tol * R.bnorm);
+      return start_cycle(ctx, R, K.r, rn);
     }
-    if (rel < opts->tol) break;
-    if (outer >= max_outer || st->inner_iters >= opts->max_iters) {
-      status = fail(TRAP_ENOCONV, "tolerance not reached");
-      break;
+    case GP_RESID_RESTART: {
+      const double beta = std::sqrt(std::max(R.hbuf[0], 0.0));
+      if (beta <= R.target) {
+        hipLaunchKernelGGL(k_axpby, dim3(kBlocks), dim3(256), 0, ctx->stream, N, 1.0, K.x, 1.0, R.x);
+        TRAP_HIP(hipGetLastError());
+        R.phase = GP_RESID_OUTER;
+        return TRAP_OK;
+      }
+      return start_cycle(ctx, R, K.tmp64, beta);
     }
-    st->outer_steps = outer + 1;
-    // correction solve A d = r from d = 0
-    TRAP_HIP(hipMemsetAsync(d, 0, N * sizeof(double), ctx->stream));
-    double target;
-    if (inner == TRAP_FP64) {
-      target = 0.999 * opts->tol * bnorm;
-    } else {
-      target = std::max(opts->inner_tol * rn, 0.5 * opts->tol * bnorm);
+    case GP_ARNOLDI: {
+      const int j = R.j;
+      double* w = K.V + (size_t)(j + 1) * N;
+      for (int i = 0; i <= j; ++i) R.h[i] = R.hbuf[i];
+      TRAP_TRY(axpy_async(ctx, R, K.V, j + 1, R.hbuf, w, R.dres + (R.m + 2)));
+      // second projection and ||w||^2 in one reduction (w is basis column j + 1)
+      R.p2 = true;
+      return dots_async(ctx, R, K.V, j + 2, w, R.hbuf + (R.m + 2));
     }
-    int it = 0;
-    TRAP_TRY(gmres_core(ctx, B, inner, m, r, rn, target, opts->max_iters - st->inner_iters, d, &it, st));
-    st->inner_iters += it;
-    hipLaunchKernelGGL(k_axpby, dim3(kBlocks), dim3(256), 0, ctx->stream, N, 1.0, d, 1.0, I);
+    default:
+      return TRAP_OK;
+  }
+}
+
+// host work after sync 2 (Arnoldi units only)
+int unit_after2(trap_ctx* ctx, GmresRun& R) {
+  if (R.phase != GP_ARNOLDI || !R.p2) return TRAP_OK;
+  R.p2 = false;
+  Work& K = ctx->wk;
+  const long long N = R.N;
+  const int j = R.j, m = R.m;
+  double* w = K.V + (size_t)(j + 1) * N;
+  const double* h2 = R.hbuf + (m + 2);
+  double s2 = 0.0;
+  for (int i = 0; i <= j; ++i) s2 += h2[i] * h2[i];
+  const double wn2 = h2[j + 1];
+  for (int i = 0; i <= j; ++i) R.h[i] += h2[i];
+  TRAP_TRY(axpy_async(ctx, R, K.V, j + 1, h2, w, R.dres));
+  double hn2 = wn2 - s2;
+  if (!(hn2 > 1e-6 * wn2)) {
+    // cancellation: measure the norm directly
+    TRAP_TRY(dots_async(ctx, R, w, 1, w, R.hbuf));
+    TRAP_HIP(hipStreamSynchronize(ctx->stream));
+    hn2 = R.hbuf[0];
+  }
+  const double hn = std::sqrt(std::max(hn2, 0.0));
+  if (!std::isfinite(hn)) {
+    run_finish(R, fail(TRAP_ENAN, "non-finite Arnoldi vector"));
+    return TRAP_OK;
+  }
+  for (int i = 0; i <= j; ++i) R.H[(size_t)i * m + j] = R.h[i];
+  R.H[(size_t)(j + 1) * m + j] = hn;
+  if (hn > 0.0) {
+    hipLaunchKernelGGL(k_scale_copy, dim3(kBlocks), dim3(256), 0, ctx->stream, N, 1.0 / hn, w, w);
     TRAP_HIP(hipGetLastError());
-    if (inner == TRAP_FP64) {
-      // plain GMRES: one final true residual check
-      TRAP_TRY(op_apply(ctx, TRAP_FP64, I, r, st));
-      hipLaunchKernelGGL(k_axpby, dim3(kBlocks), dim3(256), 0, ctx->stream, N, 1.0, b, -1.0, r);
-      TRAP_TRY(B.norm(r, &rn));
-      rel = rn / bnorm;
-      if (!(rel < opts->tol)) status = fail(TRAP_ENOCONV, "tolerance not reached");
-      break;
+  }
+  for (int i = 0; i < j; ++i) {
+    const double a = R.H[(size_t)i * m + j], b = R.H[(size_t)(i + 1) * m + j];
+    R.H[(size_t)i * m + j] = R.cs[i] * a + R.sn[i] * b;
+    R.H[(size_t)(i + 1) * m + j] = -R.sn[i] * a + R.cs[i] * b;
+  }
+  const double a = R.H[(size_t)j * m + j], b = R.H[(size_t)(j + 1) * m + j];
+  const double den = std::hypot(a, b);
+  R.cs[j] = den > 0 ? a / den : 1.0;
+  R.sn[j] = den > 0 ? b / den : 0.0;
+  R.H[(size_t)j * m + j] = den;
+  R.H[(size_t)(j + 1) * m + j] = 0.0;
+  R.g[j + 1] = -R.sn[j] * R.g[j];
+  R.g[j] = R.cs[j] * R.g[j];
+  R.res = std::fabs(R.g[j + 1]);
+  R.j = j + 1;
+  R.st.inner_iters++;
+  const bool conv = R.res <= R.target || hn == 0.0;
+  if (conv || R.j == m || R.st.inner_iters >= R.opts.max_iters) return end_cycle(ctx, R, conv);
+  return TRAP_OK;
+}
+
+}  // namespace
+
+int gmres_step_batch(trap_ctx** ctxs, int n, int* status) {
+  // phase 1
+  for (int i = 0; i < n; ++i) {
+    GmresRun& R = *ctxs[i]->run;
+    if (R.phase == GP_DONE) continue;
+    DeviceGuard g(ctxs[i]->device);
+    const int rc = unit_issue1(ctxs[i], R);
+    if (rc < 0) run_finish(R, rc);
+  }
+  for (int i = 0; i < n; ++i) {
+    GmresRun& R = *ctxs[i]->run;
+    if (R.phase == GP_DONE) continue;
+    DeviceGuard g(ctxs[i]->device);
+    if (hipStreamSynchronize(ctxs[i]->stream) != hipSuccess) run_finish(R, fail(TRAP_EDEVICE, "stream error"));
+  }
+  bool any2 = false;
+  for (int i = 0; i < n; ++i) {
+    GmresRun& R = *ctxs[i]->run;
+    if (R.phase == GP_DONE) continue;
+    DeviceGuard g(ctxs[i]->device);
+    const int rc = unit_after1(ctxs[i], R);
+    if (rc < 0) run_finish(R, rc);
+    any2 = any2 || (R.phase == GP_ARNOLDI && R.p2);
+  }
+  if (any2) {
+    for (int i = 0; i < n; ++i) {
+      GmresRun& R = *ctxs[i]->run;
+      if (R.phase != GP_ARNOLDI || !R.p2) continue;
+      DeviceGuard g(ctxs[i]->device);
+      if (hipStreamSynchronize(ctxs[i]->stream) != hipSuccess) run_finish(R, fail(TRAP_EDEVICE, "stream error"));
+    }
+    for (int i = 0; i < n; ++i) {
+      GmresRun& R = *ctxs[i]->run;
+      DeviceGuard g(ctxs[i]->device);
+      const int rc = unit_after2(ctxs[i], R);
+      if (rc < 0) run_finish(R, rc);
     }
   }
+  if (status)
+    for (int i = 0; i < n; ++i) status[i] = ctxs[i]->run->phase == GP_DONE ? ctxs[i]->run->status : 1;
+  return TRAP_OK;
+}
+
+int gmres_end(trap_ctx* ctx, trap_solve_stats* st) {
+  if (!ctx->run) return fail(TRAP_ESTATE, "no solve started");
+  GmresRun& R = *ctx->run;
+  if (R.phase != GP_DONE) return fail(TRAP_ESTATE, "solve still running");
   TRAP_HIP(hipStreamSynchronize(ctx->stream));
-  st->final_rel_res = rel;
-  st->ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-  return status;
+  if (st) *st = R.st;
+  return R.status;
+}
+
+void gmres_release(trap_ctx* ctx) {
+  if (!ctx->run) return;
+  if (ctx->run->hbuf) (void)hipHostFree(ctx->run->hbuf);
+  delete ctx->run;
+  ctx->run = nullptr;
+}
+
+int gmres_solve(trap_ctx* ctx, const trap_solve_opts* opts, double* I, trap_solve_stats* st) {
+  const int rc = gmres_begin(ctx, opts, I);
+  if (rc < 0) {
+    if (st && ctx->run) *st = ctx->run->st;
+    return rc;
+  }
+  if (ctx->run->phase != GP_DONE) {
+    int s = 1;
+    while (s == 1) gmres_step_batch(&ctx, 1, &s);
+  }
+  const int r = gmres_end(ctx, st);
+  return r == 1 ? TRAP_OK : r;
 }
 
 }  // namespace trap

@@ -53,6 +53,8 @@ struct DevBuf {
 //                  (row stride ldm >= nn, zero padded)
 //   W intermediate W[zc][t][slot][c][n][s]   (height chunk zc)
 //   eps_bar        Eb[z][l][l'][o][n][s]
+//   coefficients   cf[z][p][t][c][l'][i][j]  p = pair index in slot-major order; c = 0 multiplies
+//                  Re W, c = 1 multiplies Im W
 //   E table        E[z][o][i][u'][u][l']   = d_{u'l'}^T Acart_i(o) d^*_{u l'}
 //   A table        A[z][o'][j][u][u'][l]   = d_{u l}^T Acart_j(o')/2 d^*_{u' l}
 //   transitions    t = u * n_lo + l
@@ -67,8 +69,15 @@ struct Problem {
   std::vector<double> theta;               // [nth]
   std::vector<int> slot_off;               // [nth+1]
   std::vector<int> slot_dir;               // [nslot]
+  std::vector<int> slot_theta;             // [nslot]
   std::vector<int> pair_slot;              // [nd][nd] slot of (theta(o,i), i)
   std::vector<int> pair_theta;             // [nd][nd]
+  std::vector<int> pair_off;               // [nslot+1] pairs (o, o') of each slot, slot-major
+  std::vector<int> pair_o;                 // [nd*nd]   outgoing direction of each pair
+  std::vector<int> pair_dir;               // [nd*nd]   incoming direction of each pair
+  // slot groups for the fused Sigma kernel: {theta, first slot, slot count}
+  std::vector<int> grp[2];                 // [0] FP64 (8 slots), [1] FP32 (16 slots)
+  int grp_maxpairs[2] = {0, 0};            // most pairs in one group
   // device copies
   double *d_x = nullptr, *d_P = nullptr, *d_mu = nullptr, *d_w = nullptr, *d_tau = nullptr;
   double *d_Sig = nullptr;                 // [nn][nn] second-derivative map of the spline
@@ -79,6 +88,8 @@ struct Problem {
   double *d_sll = nullptr;                 // [nz][nl][nl] lower-level shifts
   double *d_theta = nullptr;               // [nth]
   int *d_slot_theta = nullptr, *d_slot_dir = nullptr, *d_slot_off = nullptr, *d_pair_slot = nullptr;
+  int *d_pair_off = nullptr, *d_pair_o = nullptr, *d_pair_dir = nullptr;
+  int *d_grp[2] = {nullptr, nullptr};
   double2 *d_E = nullptr, *d_A = nullptr;  // see above
   double2 *d_alpha = nullptr, *d_bma = nullptr; // [nz][nu][nu]
   double *d_g = nullptr;                   // [nz][nt][nd][4] geometric factors of K
@@ -95,6 +106,8 @@ struct Precomp {
   double2 *d_r3 = nullptr;    // [z][t][n] R_III incoming weights
   double2 *d_prof = nullptr;  // [z][t][n] outgoing profiles on the comoving grid
   double *d_b = nullptr;      // right-hand side, FP64 vector
+  double *d_cf64 = nullptr;   // angular coefficients [z][pair][t][c][l'][i][j], FP64
+  float *d_cf32 = nullptr;    //   and FP32
   double *d_Gt = nullptr;     // Gaussian factor table of the kernel precompute (uniform grids)
   double2 *d_Vt = nullptr;    // Faddeeva factor table of the kernel precompute (uniform grids)
   double *d_Lrow = nullptr;   // local part of the kernel rows, [rows][ldm] (height chunk)
@@ -126,6 +139,8 @@ struct ProfRec {
   double flops, bytes;
 };
 
+struct GmresRun;   // solver state of one context (solver.hip)
+
 struct Prof {
   bool on = false;
   std::vector<ProfRec> rec;      // records [0, used) are live; events are reused
@@ -142,6 +157,9 @@ struct trap_ctx {
   trap::Precomp pre;
   trap::Work wk;
   trap::Prof prof;
+  trap::GmresRun* run = nullptr;    // state of the current GMRES solve
+  int path = 0;                     // TRAP_PATH_* of trap.h
+  int max_lds = 64 * 1024;          // device limit of LDS bytes per block
   std::vector<trap::DevBuf> bufs;   // every allocation the context made
 };
 
@@ -176,6 +194,22 @@ int ensure_work(trap_ctx* ctx, int prec);
 
 // solver (solver.hip)
 int gmres_solve(trap_ctx* ctx, const trap_solve_opts* opts, double* I, trap_solve_stats* st);
+int gmres_begin(trap_ctx* ctx, const trap_solve_opts* opts, double* I);
+int gmres_step_batch(trap_ctx** ctxs, int n, int* status);
+int gmres_end(trap_ctx* ctx, trap_solve_stats* st);
+void gmres_release(trap_ctx* ctx);
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
 
 inline int ceil_div(long long a, long long b) { return static_cast<int>((a + b - 1) / b); }
 

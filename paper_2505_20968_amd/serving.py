@@ -1,0 +1,181 @@
+"""Continuous-batching serving loop for forward Stokes solves.
+
+Requests (an atom, grids and a seeded atmosphere) arrive over time.  The
+server admits queued requests in arrival order while the device-memory budget
+(computed per request by ``trap_footprint``) and the slot limit allow; each
+admitted request gets its own context and HIP stream, runs its precompute, and
+starts a GMRES solve.  All admitted solves then advance together through
+``trap_gmres_step_batch``: one step enqueues the next unit of every request's
+solve on that request's stream before waiting, so their device work overlaps,
+and the host synchronises at most twice per step for the whole batch.  A
+finished request releases its memory at once, so requests that arrived while
+others were on the GPU join the batch as soon as memory frees up.  Krylov
+state stays on the device for the whole solve.
+
+The scheduling policy lives in :class:`Scheduler`, which drives an abstract
+backend; :class:`DeviceBackend` is the GPU backend over the C ABI.
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import time
+from typing import Any, Callable, List, Optional, Sequence
+
+TRAP_ENOMEM = -2
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    arrival: float            # seconds after the start of the run
+    problem: Any
+    admitted: Optional[float] = None
+    done: Optional[float] = None
+    status: Optional[int] = None
+    stats: Optional[dict] = None
+    result: Any = None        # backend result (the emergent Stokes profiles on the device backend)
+
+    @property
+    def latency(self) -> Optional[float]:
+        return None if self.done is None else self.done - self.arrival
+
+
+class Scheduler:
+    """Arrival-order admission under a memory budget and a slot limit, one
+    batched step per iteration, immediate release of finished requests.
+
+    backend must provide ``footprint(problem) -> bytes``, ``admit(problem) ->
+    handle``, ``step(handles) -> list of status`` (1 running, else final status)
+    and ``finish(handle) -> (status, stats, result)``."""
+
+    def __init__(self, backend, mem_budget: int, max_active: int = 16,
+                 clock: Callable[[], float] = time.perf_counter,
+                 sleep: Callable[[float], None] = time.sleep):
+        self.backend = backend
+        self.mem_budget = int(mem_budget)
+        self.max_active = int(max_active)
+        self.clock = clock
+        self.sleep = sleep
+        self.peak_used = 0
+        self.peak_active = 0
+        self.steps = 0
+
+    def run(self, requests: Sequence[Request]) -> List[Request]:
+        pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
+        queue: collections.deque = collections.deque()
+        active = []               # (request, handle, bytes)
+        used = 0
+        t0 = self.clock()
+        while pending or queue or active:
+            now = self.clock() - t0
+            while pending and pending[0].arrival <= now:
+                queue.append(pending.popleft())
+            while queue and len(active) < self.max_active:
+                req = queue[0]
+                need = int(self.backend.footprint(req.problem))
+                if need > self.mem_budget:            # can never fit: reject
+                    queue.popleft()
+                    req.status = TRAP_ENOMEM
+                    req.admitted = req.done = self.clock() - t0
+                    continue
+                if used + need > self.mem_budget:     # wait for memory (arrival order is kept)
+                    break
+                queue.popleft()
+                req.admitted = self.clock() - t0
+                handle = self.backend.admit(req.problem)
+                active.append((req, handle, need))
+                used += need
+                self.peak_used = max(self.peak_used, used)
+            self.peak_active = max(self.peak_active, len(active))
+            if not active:
+                if pending:
+                    self.sleep(max(0.0, min(pending[0].arrival - (self.clock() - t0), 0.01)))
+                continue
+            status = self.backend.step([h for _, h, _ in active])
+            self.steps += 1
+            keep = []
+            for (req, handle, need), s in zip(active, status):
+                if s == 1:
+                    keep.append((req, handle, need))
+                    continue
+                req.status, req.stats, req.result = self.backend.finish(handle)
+                req.done = self.clock() - t0
+                used -= need
+            active = keep
+        return list(requests)
+
+
+class DeviceBackend:
+    """GPU backend: one context and HIP stream per request, batched GMRES steps."""
+
+    def __init__(self, device: int = 0, precision: str = "mixed", tol: float = 1e-8, restart: int = 40,
+                 inner_tol: float = 1e-4, max_outer: int = 10, max_iters: int = 2000):
+        import torch
+        from .trap import TRAP_FP32, TRAP_FP64, footprint
+        self.torch = torch
+        self.device = device
+        self.mixed = precision == "mixed"
+        self.store = 3 if self.mixed else 1
+        self.opts = dict(tol=tol, restart=restart, max_iters=max_iters, max_outer=max_outer,
+                         inner=TRAP_FP32 if self.mixed else TRAP_FP64, inner_tol=inner_tol)
+        self._footprint = footprint
+
+    def footprint(self, problem) -> int:
+        # library allocations plus the solution vector held by the caller
+        n = 4 * problem.n_z * problem.n_dir * problem.n_nu
+        return self._footprint(problem, self.store) + 8 * n
+
+    def admit(self, problem):
+        from .trap import Context
+        torch = self.torch
+        stream = torch.cuda.Stream(self.device)
+        ctx = Context(self.device, stream)
+        ctx.set_problem(problem)
+        ctx.precompute(self.store)
+        with torch.cuda.stream(stream):
+            x = torch.zeros(ctx.shape, dtype=torch.float64, device=f"cuda:{self.device}")
+        stream.synchronize()
+        ctx.gmres_begin(x, **self.opts)
+        return (ctx, x, stream)
+
+    def step(self, handles):
+        from .trap import gmres_step_batch
+        return gmres_step_batch([h[0] for h in handles])
+
+    def finish(self, handle):
+        ctx, x, _ = handle
+        stats = ctx.gmres_end(raise_on_noconv=False)
+        em = ctx.emergent(x)
+        ctx.close()
+        return stats["status"], stats, em
+
+
+def serve(requests: Sequence[Request], precision: str = "mixed", mem_budget: Optional[int] = None,
+          max_active: int = 16, device: int = 0, **solver) -> dict:
+    """Run a request stream on the device; returns the requests and summary figures."""
+    import torch
+    backend = DeviceBackend(device, precision, **solver)
+    if mem_budget is None:
+        free, _ = torch.cuda.mem_get_info(device)
+        mem_budget = int(0.8 * free)
+    sched = Scheduler(backend, mem_budget, max_active)
+    t0 = time.perf_counter()
+    out = sched.run(requests)
+    wall = time.perf_counter() - t0
+    ok = [r for r in out if r.status == 0]
+    lat = sorted(r.latency for r in ok)
+
+    def pct(q):
+        if not lat:
+            return None
+        k = (len(lat) - 1) * q
+        lo = int(k)
+        hi = min(lo + 1, len(lat) - 1)
+        return lat[lo] + (lat[hi] - lat[lo]) * (k - lo)
+
+    return {"requests": out, "wall_s": wall, "solves_per_s": len(ok) / wall if wall > 0 else 0.0,
+            "n_ok": len(ok), "n_rejected": sum(1 for r in out if r.status == TRAP_ENOMEM),
+            "n_failed": sum(1 for r in out if r.status not in (0, TRAP_ENOMEM)),
+            "p50_s": pct(0.5), "p99_s": pct(0.99), "peak_active": sched.peak_active,
+            "peak_bytes": sched.peak_used, "steps": sched.steps}

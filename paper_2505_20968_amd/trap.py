@@ -18,13 +18,15 @@ LIB_PATH = os.path.join(HERE, "libtrap.so")
 
 TRAP_FP64 = 0
 TRAP_FP32 = 1
+TRAP_PATH_AUTO, TRAP_PATH_FUSED, TRAP_PATH_CHUNKED = 0, 1, 2
 STATUS = {0: "TRAP_OK", -1: "TRAP_EINVAL", -2: "TRAP_ENOMEM", -3: "TRAP_EDEVICE",
           -4: "TRAP_ENOCONV", -5: "TRAP_ESTATE", -6: "TRAP_ENAN"}
 
 EXPORTED = ["trap_create", "trap_destroy", "trap_set_problem", "trap_precompute",
             "trap_apply_sigma", "trap_formal_solve", "trap_apply_operator", "trap_rhs",
             "trap_gmres_solve", "trap_emergent", "trap_get_info", "trap_footprint",
-            "trap_profile", "trap_stage_times", "trap_last_error"]
+            "trap_profile", "trap_stage_times", "trap_set_path", "trap_gmres_begin",
+            "trap_gmres_step_batch", "trap_gmres_end", "trap_last_error"]
 STAGES = ["comoving", "contract_fp32", "r3", "angular", "backinterp", "formal", "kernel_rows",
           "contract_fp64"]
 
@@ -97,6 +99,10 @@ def load_library(path: str = LIB_PATH):
     lib.trap_footprint.argtypes = [ctypes.POINTER(AtomDesc), ctypes.POINTER(ProblemDesc), ctypes.c_int,
                                    ctypes.POINTER(ctypes.c_size_t)]
     lib.trap_profile.argtypes = [vp, ctypes.c_int]
+    lib.trap_set_path.argtypes = [vp, ctypes.c_int]
+    lib.trap_gmres_begin.argtypes = [vp, ctypes.POINTER(SolveOpts), vp]
+    lib.trap_gmres_step_batch.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
+    lib.trap_gmres_end.argtypes = [vp, ctypes.POINTER(SolveStats)]
     lib.trap_stage_times.argtypes = [vp, ctypes.POINTER(StageStats)]
     lib.trap_last_error.restype = ctypes.c_char_p
     for name in EXPORTED:
@@ -140,6 +146,17 @@ def footprint(prob, store_mask: int = 3) -> int:
     _check(lib.trap_footprint(ctypes.byref(_atom_desc(prob.atom)), ctypes.byref(d), store_mask,
                               ctypes.byref(out)))
     return int(out.value)
+
+
+def gmres_step_batch(contexts) -> list:
+    """Advance every context's solve by one step (trap_gmres_step_batch);
+    returns per context 1 while running, else its final status."""
+    lib = load_library()
+    n = len(contexts)
+    arr = (ctypes.c_void_p * n)(*[c.h.value for c in contexts])
+    st = (ctypes.c_int * n)()
+    _check(lib.trap_gmres_step_batch(arr, n, st))
+    return list(st)
 
 
 def _prec_of(t) -> int:
@@ -224,11 +241,33 @@ class Context:
                 "applies_fp64": st.applies_fp64, "applies_fp32": st.applies_fp32,
                 "final_rel_res": st.final_rel_res, "ms_total": st.ms_total, "status": code}
 
+    def gmres_begin(self, I, tol: float = 1e-8, restart: int = 40, max_iters: int = 2000,
+                    inner: int = TRAP_FP64, max_outer: int = 8, inner_tol: float = 1e-5):
+        """Start a solve that trap_gmres_step_batch advances (see gmres_step_batch)."""
+        o = SolveOpts(tol=tol, restart=restart, max_iters=max_iters, max_outer=max_outer, inner=inner,
+                      inner_tol=inner_tol)
+        self._solution = I           # the library writes into I until the solve ends
+        _check(self.lib.trap_gmres_begin(self.h, ctypes.byref(o), self._vec(I, TRAP_FP64)))
+
+    def gmres_end(self, raise_on_noconv: bool = True) -> dict:
+        st = SolveStats()
+        code = self.lib.trap_gmres_end(self.h, ctypes.byref(st))
+        if code != 0 and (raise_on_noconv or code != -4):
+            _check(code)
+        self._solution = None
+        return {"outer_steps": st.outer_steps, "inner_iters": st.inner_iters,
+                "applies_fp64": st.applies_fp64, "applies_fp32": st.applies_fp32,
+                "final_rel_res": st.final_rel_res, "ms_total": st.ms_total, "status": code}
+
     def emergent(self, I) -> np.ndarray:
         n_up = self.shape[1] // 2
         out = np.zeros((n_up, self.shape[2], 4))
         _check(self.lib.trap_emergent(self.h, self._vec(I, TRAP_FP64), out.ctypes.data_as(_dp)))
         return out
+
+    def set_path(self, path: int):
+        """Sigma implementation: TRAP_PATH_AUTO, TRAP_PATH_FUSED or TRAP_PATH_CHUNKED."""
+        _check(self.lib.trap_set_path(self.h, int(path)))
 
     def profile(self, enable: bool = True):
         _check(self.lib.trap_profile(self.h, int(enable)))

@@ -57,30 +57,58 @@ def _rel(a, b):
     return np.linalg.norm(a - b) / np.linalg.norm(b)
 
 
-def test_sigma_apply_fp64(case):
+PATHS = {"auto": 0, "fused": 1, "chunked": 2}
+
+
+@pytest.mark.parametrize("path", ["auto", "chunked"])
+def test_sigma_apply_fp64(case, path):
     name, prob, op, ctx, I, torch = case
     from oracle import transfer as T
     ref = T.sigma_apply(op, I)
     It = torch.tensor(I, dtype=torch.float64, device="cuda")
     e = torch.empty_like(It)
-    ctx.apply_sigma(It, e)
-    torch.cuda.synchronize()
+    ctx.set_path(PATHS[path])
+    try:
+        ctx.apply_sigma(It, e)
+        torch.cuda.synchronize()
+    finally:
+        ctx.set_path(0)
     got = e.cpu().numpy()
     r = _rel(got, ref)
-    print(f"[{name}] sigma fp64 rel {r:.3e} maxabs {np.abs(got - ref).max():.3e}", flush=True)
+    print(f"[{name}] sigma fp64 {path} rel {r:.3e} maxabs {np.abs(got - ref).max():.3e}", flush=True)
     assert r < 1e-10
 
 
-def test_sigma_apply_fp32(case):
+def test_fused_path_is_fp32_only(case):
+    """The FP64 operator keeps the height-chunked path; forcing the fused
+    kernel for it is an error, not a silent fallback."""
+    name, prob, op, ctx, I, torch = case
+    from paper_2505_20968_amd import TrapError
+    It = torch.tensor(I, dtype=torch.float64, device="cuda")
+    e = torch.empty_like(It)
+    ctx.set_path(PATHS["fused"])
+    try:
+        with pytest.raises(TrapError):
+            ctx.apply_sigma(It, e)
+    finally:
+        ctx.set_path(0)
+
+
+@pytest.mark.parametrize("path", ["fused", "chunked"])
+def test_sigma_apply_fp32(case, path):
     name, prob, op, ctx, I, torch = case
     from oracle import transfer as T
     ref = T.sigma_apply(op, I)
     It = torch.tensor(I, dtype=torch.float32, device="cuda")
     e = torch.empty_like(It)
-    ctx.apply_sigma(It, e)
-    torch.cuda.synchronize()
+    ctx.set_path(PATHS[path])
+    try:
+        ctx.apply_sigma(It, e)
+        torch.cuda.synchronize()
+    finally:
+        ctx.set_path(0)
     r = _rel(e.double().cpu().numpy(), ref)
-    print(f"[{name}] sigma fp32 rel {r:.3e}", flush=True)
+    print(f"[{name}] sigma fp32 {path} rel {r:.3e}", flush=True)
     assert r < 2e-5
 
 

@@ -1,0 +1,92 @@
+"""Host logic of the serving loop (no GPU): admission in arrival order under a
+memory budget and a slot limit, rejection of requests that can never fit,
+release on completion, latency accounting."""
+from paper_2505_20968_amd.serving import Request, Scheduler, TRAP_ENOMEM
+
+
+class FakeClock:
+    def __init__(self):
+        self.t = 0.0
+
+    def __call__(self):
+        return self.t
+
+    def sleep(self, dt):
+        self.t += max(dt, 1e-3)
+
+
+class FakeBackend:
+    """Each request needs problem['steps'] batched steps; a step costs 1 s."""
+
+    def __init__(self, clock):
+        self.clock = clock
+        self.live = {}
+        self.log = []
+
+    def footprint(self, p):
+        return p["mem"]
+
+    def admit(self, p):
+        h = len(self.log)
+        self.live[h] = p["steps"]
+        self.log.append(("admit", p["id"], self.clock()))
+        return h
+
+    def step(self, handles):
+        self.clock.t += 1.0
+        out = []
+        for h in handles:
+            self.live[h] -= 1
+            out.append(1 if self.live[h] > 0 else 0)
+        return out
+
+    def finish(self, h):
+        del self.live[h]
+        return 0, {"steps": "done"}, h
+
+
+def _run(reqs, budget, max_active):
+    clock = FakeClock()
+    be = FakeBackend(clock)
+    s = Scheduler(be, budget, max_active, clock=clock, sleep=clock.sleep)
+    out = s.run(reqs)
+    return s, be, out
+
+
+def test_budget_and_slots_are_respected():
+    reqs = [Request(i, 0.0, {"id": i, "mem": 40, "steps": 3}) for i in range(6)]
+    s, be, out = _run(reqs, budget=100, max_active=4)
+    assert all(r.status == 0 for r in out)
+    assert s.peak_used <= 100 and s.peak_active == 2          # memory allows two at a time
+    s, be, out = _run([Request(i, 0.0, {"id": i, "mem": 10, "steps": 3}) for i in range(6)], 100, 4)
+    assert s.peak_active == 4
+
+
+def test_never_fitting_request_is_rejected_and_others_run():
+    reqs = [Request(0, 0.0, {"id": 0, "mem": 500, "steps": 2}),
+            Request(1, 0.0, {"id": 1, "mem": 50, "steps": 2})]
+    s, be, out = _run(reqs, budget=100, max_active=4)
+    assert out[0].status == TRAP_ENOMEM and out[0].result is None
+    assert out[1].status == 0
+
+
+def test_late_arrivals_join_running_batch_when_memory_frees():
+    reqs = [Request(0, 0.0, {"id": 0, "mem": 60, "steps": 10}),
+            Request(1, 0.0, {"id": 1, "mem": 40, "steps": 2}),
+            Request(2, 1.5, {"id": 2, "mem": 40, "steps": 2})]
+    s, be, out = _run(reqs, budget=100, max_active=8)
+    r0, r1, r2 = out
+    # request 2 arrives while 0 and 1 run, waits for 1 to free its memory,
+    # and finishes before the long request 0
+    assert r2.admitted >= r1.done and r2.admitted >= r2.arrival
+    assert r2.done < r0.done
+    assert s.peak_used <= 100
+
+
+def test_arrival_order_is_kept_and_latency_is_measured():
+    reqs = [Request(i, 0.5 * i, {"id": i, "mem": 30, "steps": 1 + i % 3}) for i in range(8)]
+    s, be, out = _run(reqs, budget=60, max_active=8)
+    adm = [r.admitted for r in sorted(out, key=lambda r: r.arrival)]
+    assert adm == sorted(adm)
+    for r in out:
+        assert r.status == 0 and r.latency == r.done - r.arrival and r.latency > 0

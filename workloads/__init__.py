@@ -232,17 +232,23 @@ def tiny(n_z: int = 6, n_nu: int = 13, x_max: float = 6.0, n_mu: int = 2, n_chi:
                    v=v, B=Bz, meta={"seed": seed})
 
 
-def serving_stream(n_requests: int = 1024, seed: int = 5, rate_hz: float = 10.0):
+def serving_stream(n_requests: int = 1024, seed: int = 5, rate_hz: float = 10.0,
+                   n_z_range=(40, 100), nu_choices=None, angle_sets=None):
     """Request stream: each request picks one of the four configurations'
-    generators with its own seed and resized grids; arrivals are Poisson."""
+    generators with its own seed and resized grids; arrivals are Poisson.
+    Defaults span N_z 40-100, N_nu 31-301 and N_dir 16-128; the ranges can be
+    narrowed (a bounded stream for short runs)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     t = np.cumsum(rng.exponential(1.0 / rate_hz, n_requests))
-    angle_sets = [(4, 4), (8, 4), (8, 8), (12, 8), (16, 8)]
+    if angle_sets is None:
+        angle_sets = [(4, 4), (8, 4), (8, 8), (12, 8), (16, 8)]
+    if nu_choices is None:
+        nu_choices = np.arange(31, 302, 30)
     reqs = []
     for i in range(n_requests):
         kind = int(rng.integers(0, 4))
-        n_z = int(rng.integers(40, 101))
-        n_nu = int(rng.choice(np.arange(31, 302, 30)))
+        n_z = int(rng.integers(n_z_range[0], n_z_range[1] + 1))
+        n_nu = int(rng.choice(np.asarray(nu_choices)))
         n_mu, n_chi = angle_sets[int(rng.integers(0, len(angle_sets)))]
         s = 5000 + i
         if kind <= 1:
