@@ -457,6 +457,24 @@ static void angular_setup(Problem& P, std::vector<double>& dirs, std::vector<dou
   P.pair_dir.assign(nd * nd, 0);
   for (int sl = 0; sl < P.nslot; ++sl)
     for (int q = P.pair_off[sl]; q < P.pair_off[sl + 1]; ++q) P.pair_dir[q] = P.slot_dir[sl];
+  P.pair_index.assign(nd * nd, 0);
+  for (int q = 0; q < nd * nd; ++q) P.pair_index[P.pair_o[q] * nd + P.pair_dir[q]] = q;
+  // contraction column groups: the slots of one theta in groups of at most 32
+  // (FP32) or 16 (FP64); FP32 groups are split into two classes by size so
+  // each class runs with its own number of column tiles
+  for (int pi = 0; pi < 2; ++pi) {
+    const int cg = pi == 0 ? 16 : 32;
+    P.cgrp[pi][0].clear();
+    P.cgrp[pi][1].clear();
+    for (int t = 0; t < P.nth; ++t)
+      for (int s0 = P.slot_off[t]; s0 < P.slot_off[t + 1]; s0 += cg) {
+        const int cnt = std::min(cg, P.slot_off[t + 1] - s0);
+        auto& dst = P.cgrp[pi][(pi == 1 && cnt > 16) ? 1 : 0];
+        dst.push_back(t);
+        dst.push_back(s0);
+        dst.push_back(cnt);
+      }
+  }
   // a group holds at most sg slots of one theta and at most 2 sg pairs
   for (int pi = 0; pi < 2; ++pi) {
     const int sg = pi == 0 ? 8 : 16;
@@ -675,8 +693,11 @@ int build_problem(trap_ctx* ctx, const trap_atom_desc* at, const trap_problem_de
   TRAP_TRY(upload_t(ctx, &P.d_pair_off, P.pair_off));
   TRAP_TRY(upload_t(ctx, &P.d_pair_o, P.pair_o));
   TRAP_TRY(upload_t(ctx, &P.d_pair_dir, P.pair_dir));
+  TRAP_TRY(upload_t(ctx, &P.d_pair_index, P.pair_index));
   TRAP_TRY(upload_t(ctx, &P.d_grp[0], P.grp[0]));
   TRAP_TRY(upload_t(ctx, &P.d_grp[1], P.grp[1]));
+  for (int pi = 0; pi < 2; ++pi)
+    for (int c = 0; c < 2; ++c) TRAP_TRY(upload_t(ctx, &P.d_cgrp[pi][c], P.cgrp[pi][c]));
   TRAP_TRY(upload_t(ctx, &P.d_E, E));
   TRAP_TRY(upload_t(ctx, &P.d_A, A));
   TRAP_TRY(upload_t(ctx, &P.d_alpha, alpha));

@@ -113,8 +113,6 @@ __global__ void __launch_bounds__(128) k_spline_shift(
 // v_mfma_{f32,f64}_16x16x4 with the operands swapped (A_in = B^T, B_in = M^T)
 // so that each lane's four accumulators are the four Stokes components of one
 // (row, slot) entry of W -- one contiguous 16/32-byte store.
-// Block: 4 waves, 64 rows (16 per wave) x up to 256 columns (16 column tiles
-// held in registers), K staged through LDS in chunks of KC.
 typedef float floatx4_t __attribute__((ext_vector_type(4)));
 typedef double doublex4_t __attribute__((ext_vector_type(4)));
 
@@ -125,7 +123,6 @@ template <typename T> struct MfmaOp;
 // both end up with one slot's four Stokes values per lane.
 template <> struct MfmaOp<float> {
   typedef floatx4_t acc_t;
-  static constexpr int KC = 32;
   static constexpr bool kInterleavedRows = false;
   __device__ static inline acc_t run(float a, float b, acc_t c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
@@ -133,141 +130,170 @@ template <> struct MfmaOp<float> {
 };
 template <> struct MfmaOp<double> {
   typedef doublex4_t acc_t;
-  static constexpr int KC = 16;
   static constexpr bool kInterleavedRows = true;
   __device__ static inline acc_t run(double a, double b, acc_t c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
 };
 
-constexpr int kMaxColTiles = 16;   // 256 columns = 64 slots per column group
 constexpr int kRowsPerBlock = 128; // 8 waves x 16 rows
 
 template <typename T> struct Vec4;
 template <> struct Vec4<float> { typedef float4 type; };
 template <> struct Vec4<double> { typedef double4 type; };
+template <typename T> struct T2of;
+template <> struct T2of<float> { typedef float2 type; };
+template <> struct T2of<double> { typedef double2 type; };
 
-// Block: 8 waves = 128 rows (16 per wave) x up to 256 columns (16 column tiles in
-// registers).  K is staged through LDS in chunks of KC with the next chunk's
-// global loads issued before the current chunk's matrix-core work (register
-// double buffering).  LDS row strides are 16 (mod 64) elements so the four
-// k-rows of a fragment read fall in different bank groups.
-template <typename T>
-__global__ void __launch_bounds__(512) k_contract(int z0, int nth, int nt, int nn, int ldm, int nd,
-                                                  const T* __restrict__ M, const T* __restrict__ Ibar,
-                                                  const int* __restrict__ slot_off,
-                                                  const int* __restrict__ slot_dir, T* __restrict__ W,
-                                                  int nslot) {
+// Block: 8 waves = 128 rows (16 per wave) x one column group (up to 4 NCT
+// slots of one Theta, 16 NCT columns).  K is taken in chunks of 8 NH: each
+// lane loads its kernel-row fragment straight into registers with two-element
+// vector loads, using the permuted K order k = k0 + 2 (4 h + lk) + jj for step
+// (h, jj) of the matrix-core chain; the column group's comoving field for the
+// chunk is staged once in LDS and read with the same k.  With one chunk
+// (padded N_nu <= 128) a block synchronises once before its products.
+template <typename T> struct ContractCfg;
+template <> struct ContractCfg<float> { static constexpr int BST = 136; };   // 128 columns + pad
+template <> struct ContractCfg<double> { static constexpr int BST = 72; };   // 64 columns + pad
+
+template <typename T, int NH, int NCT>
+__global__ void __launch_bounds__(512, 2) k_contract(int z0, int nth, int nt, int nn, int ldm, int nd, int nkc,
+                                                     const T* __restrict__ M, const T* __restrict__ Ibar,
+                                                     const int* __restrict__ cgrp,
+                                                     const int* __restrict__ slot_dir, T* __restrict__ W,
+                                                     int nslot) {
   using Op = MfmaOp<T>;
   using acc_t = typename Op::acc_t;
   using V4 = typename Vec4<T>::type;
-  constexpr int KC = Op::KC;
-  constexpr int NCOL = kMaxColTiles * 16;
-  constexpr int AST = kRowsPerBlock + 16;   // As[k][row]
-  constexpr int BST = NCOL + 16;            // Bs[k][col]
-  constexpr int APT = KC / 4;               // A elements per thread per chunk (row, 4 threads per row)
-  constexpr int BPT = KC / 8;               // B k-rows per thread per chunk (8 k-lanes)
-  __shared__ T As[KC * AST];
-  __shared__ T Bs[KC * BST];
-  const int th = blockIdx.y;
+  using T2 = typename T2of<T>::type;
+  constexpr int KCH = 8 * NH;
+  constexpr int BST = ContractCfg<T>::BST;
+  constexpr int CG = 4 * NCT;                       // slots per column group
+  extern __shared__ __align__(16) unsigned char csh[];
+  T* Bs = reinterpret_cast<T*>(csh);
+  const int g = blockIdx.y;
+  const int th = cgrp[3 * g], s0 = cgrp[3 * g + 1], cnt = cgrp[3 * g + 2];
   const int zl = blockIdx.z;
   const int z = z0 + zl;
   const int R = 2 * nt * nn;
   const int row0 = blockIdx.x * kRowsPerBlock;
-  if (row0 >= R) return;
-  const int s0 = slot_off[th], ns = slot_off[th + 1] - s0;
   const T* Mb = M + ((size_t)z * nth + th) * (size_t)R * ldm;
   const T* Ib = Ibar + (size_t)zl * nd * nn * 4;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int lr = lane & 15, lk = lane >> 4;
-  // loader roles
-  const int a_row = tid >> 2, a_kq = tid & 3;          // A: 4 threads per row, APT consecutive k each
-  const int b_sl = tid & 63, b_ky = tid >> 6;          // B: one slot per lane, k rows b_ky + 8 i
-  const int ga_row = row0 + a_row;
-  const T* a_src = Mb + (size_t)min(ga_row, R - 1) * ldm;
-  // output coordinates of this lane's row
   const int grow = row0 + wave * 16 + lr;
-  const int rt = grow / (2 * nn), rc = (grow / nn) & 1, rn = grow % nn;
-  const int nchunks = (nn + KC - 1) / KC;
-  for (int sg0 = 0; sg0 < ns; sg0 += NCOL / 4) {
-    const int nsg = min(NCOL / 4, ns - sg0);      // slots in this column group
-    const int nsub = (4 * nsg + 15) >> 4;
-    const bool b_live = b_sl < nsg;
-    const int b_dir = b_live ? slot_dir[s0 + sg0 + b_sl] : 0;
-    const T* b_src = Ib + (size_t)b_dir * nn * 4;
-    const bool b_store = b_sl < 4 * nsub;        // zero-fill padded columns of the last tile
-    acc_t acc[kMaxColTiles];
+  const T* arow = Mb + (size_t)min(grow, R - 1) * ldm;
+  acc_t acc[NCT];
 #pragma unroll
-    for (int j = 0; j < kMaxColTiles; ++j)
-      for (int r = 0; r < 4; ++r) acc[j][r] = T(0);
-    T ra[APT];
-    V4 rb[BPT];
-    auto load = [&](int k0) {
+  for (int j = 0; j < NCT; ++j)
+    for (int r = 0; r < 4; ++r) acc[j][r] = T(0);
+  for (int kc = 0; kc < nkc; ++kc) {
+    const int k0 = kc * KCH;
+    T2 mf[NH];
 #pragma unroll
-      for (int i = 0; i < APT; ++i) {
-        const int gk = k0 + a_kq * APT + i;
-        ra[i] = (ga_row < R && gk < ldm) ? a_src[gk] : T(0);
+    for (int h = 0; h < NH; ++h) {
+      const int k = k0 + 2 * (4 * h + lk);
+      if (grow < R && k < ldm) {
+        mf[h] = *reinterpret_cast<const T2*>(arow + k);
+      } else {
+        mf[h].x = T(0);
+        mf[h].y = T(0);
       }
-#pragma unroll
-      for (int i = 0; i < BPT; ++i) {
-        const int gk = k0 + b_ky + 8 * i;
-        if (b_live && gk < nn) {
-          rb[i] = *reinterpret_cast<const V4*>(b_src + (size_t)gk * 4);
-        } else {
-          rb[i].x = T(0); rb[i].y = T(0); rb[i].z = T(0); rb[i].w = T(0);
-        }
+    }
+    if (kc > 0) __syncthreads();
+    for (int e = tid; e < KCH * CG; e += 512) {
+      const int sl = e / KCH, kk = e - sl * KCH, k = k0 + kk;
+      V4 v;
+      if (sl < cnt && k < nn) {
+        v = *reinterpret_cast<const V4*>(Ib + ((size_t)slot_dir[s0 + sl] * nn + k) * 4);
+      } else {
+        v.x = T(0); v.y = T(0); v.z = T(0); v.w = T(0);
       }
-    };
-    load(0);
-    for (int c = 0; c < nchunks; ++c) {
-      const int k0 = c * KC;
-      if (c > 0) __syncthreads();
-#pragma unroll
-      for (int i = 0; i < APT; ++i) As[(a_kq * APT + i) * AST + a_row] = ra[i];
-      if (b_store) {
-#pragma unroll
-        for (int i = 0; i < BPT; ++i) {
-          T* dst = Bs + (b_ky + 8 * i) * BST;
-          const T v[4] = {rb[i].x, rb[i].y, rb[i].z, rb[i].w};
-          if (Op::kInterleavedRows) {
-            const int base = (b_sl >> 2) * 16 + (b_sl & 3);
-            for (int q = 0; q < 4; ++q) dst[base + 4 * q] = v[q];
-          } else {
-            for (int q = 0; q < 4; ++q) dst[4 * b_sl + q] = v[q];
-          }
-        }
-      }
-      __syncthreads();
-      if (c + 1 < nchunks) load(k0 + KC);
-      const int ksteps = (min(KC, nn - k0) + 3) >> 2;
-#pragma unroll
-      for (int ks = 0; ks < KC / 4; ++ks) {
-        if (ks < ksteps) {
-          const T bf = As[(ks * 4 + lk) * AST + wave * 16 + lr];
-#pragma unroll
-          for (int j = 0; j < kMaxColTiles; ++j) {
-            if (j < nsub) {
-              const T af = Bs[(ks * 4 + lk) * BST + j * 16 + lr];
-              acc[j] = Op::run(af, bf, acc[j]);
-            }
-          }
-        }
+      T* dst = Bs + (size_t)kk * BST;
+      if (Op::kInterleavedRows) {
+        const int base = (sl >> 2) * 16 + (sl & 3);
+        dst[base] = v.x;
+        dst[base + 4] = v.y;
+        dst[base + 8] = v.z;
+        dst[base + 12] = v.w;
+      } else {
+        *reinterpret_cast<V4*>(dst + 4 * sl) = v;
       }
     }
     __syncthreads();
-    // lane holds C[grow][16 j + 4 lk + r], r = 0..3 -> slot 4 j + lk, Stokes r
-    if (grow < R) {
+    // step st = 2 h + jj; the B operands of step st + 1 are read from LDS
+    // before the products of step st are issued
+    const T* bcol = Bs + 2 * lk * BST + lr;
+    T af[2][NCT];
 #pragma unroll
-      for (int j = 0; j < kMaxColTiles; ++j) {
-        const int sl = 4 * j + lk;
-        if (j < nsub && sl < nsg) {
-          V4 o;
-          o.x = acc[j][0]; o.y = acc[j][1]; o.z = acc[j][2]; o.w = acc[j][3];
-          *reinterpret_cast<V4*>(W + (((((size_t)zl * nt + rt) * nslot + s0 + sg0 + sl) * 2 + rc) * nn + rn) * 4) = o;
-        }
+    for (int jt = 0; jt < NCT; ++jt) af[0][jt] = bcol[jt * 16];
+#pragma unroll
+    for (int st = 0; st < 2 * NH; ++st) {
+      const int cur = st & 1;
+      if (st + 1 < 2 * NH) {
+        const int kn = 8 * ((st + 1) >> 1) + ((st + 1) & 1);   // 2 (4 h + lk) + jj minus 2 lk
+#pragma unroll
+        for (int jt = 0; jt < NCT; ++jt) af[cur ^ 1][jt] = bcol[kn * BST + jt * 16];
+      }
+      const T bf = (st & 1) ? mf[st >> 1].y : mf[st >> 1].x;
+#pragma unroll
+      for (int jt = 0; jt < NCT; ++jt) acc[jt] = Op::run(af[cur][jt], bf, acc[jt]);
+    }
+  }
+  // lane holds C[grow][slot s0 + 4 jt + lk][Stokes r]
+  if (grow < R) {
+    const int rt = grow / (2 * nn), rc = (grow / nn) & 1, rn = grow % nn;
+#pragma unroll
+    for (int jt = 0; jt < NCT; ++jt) {
+      const int sl = 4 * jt + lk;
+      if (sl < cnt) {
+        V4 o;
+        o.x = acc[jt][0]; o.y = acc[jt][1]; o.z = acc[jt][2]; o.w = acc[jt][3];
+        *reinterpret_cast<V4*>(W + (((((size_t)zl * nt + rt) * nslot + s0 + sl) * 2 + rc) * nn + rn) * 4) = o;
       }
     }
   }
+}
+
+// chunking of K: the fewest chunks of at most 128 columns, NH = chunk / 8
+static void contract_chunks(int ldm, int* nkc, int* nh) {
+  *nkc = (ldm + 127) / 128;
+  *nh = (ldm + 8 * *nkc - 1) / (8 * *nkc);
+}
+
+template <typename T, int NCT>
+static int launch_contract_nct(trap_ctx* ctx, int zc, int z0, const T* Mk, const T* Ibar, T* W, int cls) {
+  Problem& P = ctx->pb;
+  const int pi = sizeof(T) == 8 ? 0 : 1;
+  const int ngrp = (int)P.cgrp[pi][cls].size() / 3;
+  if (ngrp == 0) return TRAP_OK;
+  int nkc, nh;
+  contract_chunks(P.ldm, &nkc, &nh);
+  const size_t lds = (size_t)8 * nh * ContractCfg<T>::BST * sizeof(T);
+  dim3 grid(ceil_div(2LL * P.nt * P.nn, kRowsPerBlock), ngrp, zc);
+  switch (nh) {
+#define TRAP_CONTRACT_CASE(NHV)                                                                               \
+  case NHV:                                                                                                   \
+    hipLaunchKernelGGL((k_contract<T, NHV, NCT>), grid, dim3(512), lds, ctx->stream, z0, P.nth, P.nt, P.nn,     \
+                       P.ldm, P.nd, nkc, Mk, Ibar, P.d_cgrp[pi][cls], P.d_slot_dir, W, P.nslot);              \
+    break;
+    TRAP_CONTRACT_CASE(1) TRAP_CONTRACT_CASE(2) TRAP_CONTRACT_CASE(3) TRAP_CONTRACT_CASE(4)
+    TRAP_CONTRACT_CASE(5) TRAP_CONTRACT_CASE(6) TRAP_CONTRACT_CASE(7) TRAP_CONTRACT_CASE(8)
+    TRAP_CONTRACT_CASE(9) TRAP_CONTRACT_CASE(10) TRAP_CONTRACT_CASE(11) TRAP_CONTRACT_CASE(12)
+    TRAP_CONTRACT_CASE(13) TRAP_CONTRACT_CASE(14) TRAP_CONTRACT_CASE(15) TRAP_CONTRACT_CASE(16)
+#undef TRAP_CONTRACT_CASE
+    default:
+      return fail(TRAP_EINVAL, "internal: bad contraction chunk");
+  }
+  TRAP_HIP(hipGetLastError());
+  return TRAP_OK;
+}
+
+template <typename T>
+static int launch_contract(trap_ctx* ctx, int zc, int z0, const T* Mk, const T* Ibar, T* W) {
+  TRAP_TRY((launch_contract_nct<T, 4>(ctx, zc, z0, Mk, Ibar, W, 0)));
+  if (sizeof(T) == sizeof(float)) TRAP_TRY((launch_contract_nct<T, 8>(ctx, zc, z0, Mk, Ibar, W, 1)));
+  return TRAP_OK;
 }
 
 // ------------------------------------------------------------------ R_III factors
@@ -330,128 +356,83 @@ __global__ void k_r3_X(int z0, int nu, int nl, int nd, const double* __restrict_
 }
 
 // ------------------------------------------------------------------ angular / sublevel sum
-// One block per (zl, mu index, block of 32 frequencies); thread (k, n) handles
-// outgoing direction (mu, chi_k) at one frequency, so the mirror directions
-// that read the same W slot sit in one block.  For a chunk of incoming
-// directions the 4x4 coefficients
-//   C^{u' l, l'}_ij(o, o') = (c_sc w_o'/pi) sum_u alpha_{u u'} E_i(o; u', u, l') A_j(o'; u, u', l)
-// are built in LDS by the whole block; the accumulation Re sum_j C_ij W_j then
-// runs without barriers.
+// eps_bar[z][l][l'][o][n][i] = sum_{o'} sum_{u'} sum_c sum_j cf[z][p(o,o')][(u',l)][c][l'][i][j]
+//                                  W[z][(u',l)][slot(o,o')][c][n][j]  +  R_III term
+// with the angular coefficients precomputed per pair (c = 0 multiplies Re W,
+// c = 1 multiplies Im W).  One thread per (o, n): a block covers the n_chi
+// azimuths of one mu ring and 32 frequencies, so the waves read W for 32
+// consecutive frequencies (contiguous 16-byte vectors) and each coefficient
+// is shared by the 32 threads of one direction.
 constexpr int kAngN = 32;
 
-template <typename T>
+template <typename T, int kAngMaxNl>
 __global__ void __launch_bounds__(512) k_angular(
-    int z0, int nd, int nchi, int nn, int nu, int nl, int nslot, int oc_max, double c_sc,
-    const double* __restrict__ w, const double2* __restrict__ E, const double2* __restrict__ A,
-    const double2* __restrict__ alpha, const double2* __restrict__ bma, const int* __restrict__ pair_slot,
-    const T* __restrict__ W, const double2* __restrict__ X, const double2* __restrict__ prof,
-    T* __restrict__ Eb) {
-  extern __shared__ double2 sh[];
+    int z0, int nd, int nchi, int nn, int nu, int nl, int nslot, const int* __restrict__ pair_slot,
+    const int* __restrict__ pair_index, const T* __restrict__ cf, const T* __restrict__ W, double c_sc,
+    const double2* __restrict__ E, const double2* __restrict__ bma, const double2* __restrict__ X,
+    const double2* __restrict__ prof, T* __restrict__ Eb) {
+  using V4 = typename Vec4<T>::type;
   const int nmu = nd / nchi;
   const int zl = blockIdx.x / nmu, imu = blockIdx.x % nmu;
   const int z = z0 + zl;
   const int nt = nu * nl;
-  const int o_first = imu * nchi;
+  const int np = nd * nd;
   const int k = threadIdx.x / kAngN;
   const int n = blockIdx.y * kAngN + (threadIdx.x % kAngN);
-  const bool active = n < nn && k < nchi;
-  const int o = o_first + k;
-  double2* Cs = sh;
-  int* slots = reinterpret_cast<int*>(sh + (size_t)oc_max * nu * nchi * nl * 16);
-  double2* Ds = sh;
+  if (n >= nn || k >= nchi) return;
+  const int o = imu * nchi + k;
+  const size_t pstride = (size_t)nt * 2 * nl * 16;
+  const T* cfz = cf + (size_t)z * np * pstride;
+  const double sc3 = c_sc * 0.25 * kInvPi;
+  const double2* Ez = E + ((size_t)z * nd + o) * 4 * nu * nu * nl;
   for (int l = 0; l < nl; ++l) {
-    double acc[8][4];
-    for (int a = 0; a < 8; ++a)
-      for (int i = 0; i < 4; ++i) acc[a][i] = 0.0;
-    for (int o0 = 0; o0 < nd; o0 += oc_max) {
-      const int oc_n = min(oc_max, nd - o0);
-      __syncthreads();
-      const int nC = oc_n * nu * nchi * nl * 16;
-      for (int e = threadIdx.x; e < nC; e += blockDim.x) {
-        const int j = e & 3, i = (e >> 2) & 3;
-        int r = e >> 4;
-        const int lp = r % nl; r /= nl;
-        const int kk = r % nchi; r /= nchi;
-        const int upr = r % nu; r /= nu;
-        const int oc = r;
-        const int oo = o_first + kk, op = o0 + oc;
-        const double2* Ez = E + ((size_t)z * nd + oo) * 4 * nu * nu * nl;
-        const double2* Az = A + ((size_t)z * nd + op) * 4 * nu * nu * nl;
-        double re = 0.0, im = 0.0;
-        for (int u = 0; u < nu; ++u) {
-          const double2 al = alpha[((size_t)z * nu + u) * nu + upr];
-          const double2 ee = Ez[((size_t)(i * nu + upr) * nu + u) * nl + lp];
-          const double2 aa = Az[((size_t)(j * nu + u) * nu + upr) * nl + l];
-          const double2 v = cmul(al, cmul(ee, aa));
-          re += v.x;
-          im += v.y;
-        }
-        const double sc = c_sc * w[op] * kInvPi;
-        Cs[e] = make_double2(sc * re, sc * im);
-      }
-      for (int e = threadIdx.x; e < oc_n * nchi; e += blockDim.x) {
-        const int oc = e / nchi, kk = e % nchi;
-        slots[e] = pair_slot[(o_first + kk) * nd + o0 + oc];
-      }
-      __syncthreads();
-      if (!active) continue;
-      for (int oc = 0; oc < oc_n; ++oc) {
-        const int sl = slots[oc * nchi + k];
-        for (int upr = 0; upr < nu; ++upr) {
-          const int t = upr * nl + l;
-          const T* Wp = W + (((size_t)zl * nt + t) * nslot + sl) * 2 * (size_t)nn * 4;
-          typedef typename Vec4<T>::type V4;
-          const V4 a = *reinterpret_cast<const V4*>(Wp + (size_t)n * 4);
-          const V4 b = *reinterpret_cast<const V4*>(Wp + (size_t)nn * 4 + (size_t)n * 4);
-          const double wr[4] = {(double)a.x, (double)a.y, (double)a.z, (double)a.w};
-          const double wi[4] = {(double)b.x, (double)b.y, (double)b.z, (double)b.w};
-          const double2* Cb = Cs + (((size_t)oc * nu + upr) * nchi + k) * nl * 16;
-          for (int lp = 0; lp < nl; ++lp)
+    T acc[kAngMaxNl][4];
+#pragma unroll
+    for (int a = 0; a < kAngMaxNl; ++a)
+      for (int i = 0; i < 4; ++i) acc[a][i] = T(0);
+    for (int op = 0; op < nd; ++op) {
+      const int slot = pair_slot[o * nd + op];
+      const T* cp = cfz + (size_t)pair_index[o * nd + op] * pstride;
+      for (int upr = 0; upr < nu; ++upr) {
+        const int t = upr * nl + l;
+        const T* Wp = W + (((size_t)zl * nt + t) * nslot + slot) * 2 * (size_t)nn * 4 + (size_t)n * 4;
+        const V4 wr = *reinterpret_cast<const V4*>(Wp);
+        const V4 wi = *reinterpret_cast<const V4*>(Wp + (size_t)nn * 4);
+        const T* c0 = cp + (size_t)t * 2 * nl * 16;
+        const T* c1 = c0 + (size_t)nl * 16;
+#pragma unroll
+        for (int lp = 0; lp < kAngMaxNl; ++lp) {
+          if (lp < nl) {
+#pragma unroll
             for (int i = 0; i < 4; ++i) {
-              double v = 0.0;
-              for (int jj = 0; jj < 4; ++jj) {
-                const double2 c = Cb[(lp * 4 + i) * 4 + jj];
-                v += c.x * wr[jj] - c.y * wi[jj];
-              }
-              acc[lp][i] += v;
+              const V4 a = *reinterpret_cast<const V4*>(c0 + lp * 16 + i * 4);
+              const V4 b = *reinterpret_cast<const V4*>(c1 + lp * 16 + i * 4);
+              acc[lp][i] += a.x * wr.x + a.y * wr.y + a.z * wr.z + a.w * wr.w +
+                            b.x * wi.x + b.y * wi.y + b.z * wi.z + b.w * wi.w;
             }
+          }
         }
       }
     }
-    // R_III: D[k][l'][i][u][u'] = c_sc/(4 pi) (beta-alpha)_{u u'} E_i(o; u', u, l') X[u][u'][l]
-    __syncthreads();
-    const int nD = nchi * nl * 4 * nu * nu;
-    for (int e = threadIdx.x; e < nD; e += blockDim.x) {
-      const int upr = e % nu, u = (e / nu) % nu, i = (e / (nu * nu)) % 4;
-      const int lp = (e / (4 * nu * nu)) % nl, kk = e / (4 * nu * nu * nl);
-      const double2* Ez = E + ((size_t)z * nd + o_first + kk) * 4 * nu * nu * nl;
-      const double2 b = bma[((size_t)z * nu + u) * nu + upr];
-      const double2 ee = Ez[((size_t)(i * nu + upr) * nu + u) * nl + lp];
-      const double2 xx = X[(((size_t)z * nu + u) * nu + upr) * nl + l];
-      const double2 v = cmul(b, cmul(ee, xx));
-      const double sc = c_sc * 0.25 * kInvPi;
-      Ds[e] = make_double2(sc * v.x, sc * v.y);
-    }
-    __syncthreads();
-    if (active) {
-      for (int lp = 0; lp < nl; ++lp)
-        for (int i = 0; i < 4; ++i) {
-          double v = 0.0;
-          for (int u = 0; u < nu; ++u)
-            for (int upr = 0; upr < nu; ++upr) {
-              const double2 d = Ds[(((k * nl + lp) * 4 + i) * nu + u) * nu + upr];
-              const double2 p1 = prof[((size_t)z * nt + upr * nl + l) * nn + n];
-              const double2 p2 = prof[((size_t)z * nt + u * nl + l) * nn + n];
-              v += d.x * (p1.x + p2.x) - d.y * (p1.y - p2.y);
+    // R_III:  D_i(o, l', u, u') = c_sc/(4 pi) (beta - alpha)_{u u'} E_i(o; u', u, l') X[u][u'][l]
+#pragma unroll
+    for (int lp = 0; lp < kAngMaxNl; ++lp) {
+      if (lp < nl) {
+        double r3[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int u = 0; u < nu; ++u)
+          for (int upr = 0; upr < nu; ++upr) {
+            const double2 bx = cmul(bma[((size_t)z * nu + u) * nu + upr], X[(((size_t)z * nu + u) * nu + upr) * nl + l]);
+            const double2 pa = prof[((size_t)z * nt + upr * nl + l) * nn + n];
+            const double2 pb = prof[((size_t)z * nt + u * nl + l) * nn + n];
+            for (int i = 0; i < 4; ++i) {
+              const double2 d = cmul(Ez[((size_t)(i * nu + upr) * nu + u) * nl + lp], bx);
+              r3[i] += d.x * (pa.x + pb.x) - d.y * (pa.y - pb.y);
             }
-          acc[lp][i] += v;
-        }
-      for (int lp = 0; lp < nl; ++lp) {
+          }
         T* dst = Eb + ((((size_t)zl * nl + l) * nl + lp) * nd + o) * (size_t)nn * 4 + (size_t)n * 4;
-        for (int i = 0; i < 4; ++i) dst[i] = (T)acc[lp][i];
+        for (int i = 0; i < 4; ++i) dst[i] = (T)((double)acc[lp][i] + sc3 * r3[i]);
       }
     }
-    __syncthreads();
   }
 }
 
@@ -472,10 +453,6 @@ __global__ void __launch_bounds__(512) k_angular(
 // plane c), TPW each.  The kernel-row fragments use a permuted K order: step
 // (h, jj) takes k = 2 (4 h + lk) + jj in lane group lk, so each lane loads its
 // fragment with two-element vector loads; the B tile is read with the same k.
-template <typename T> struct T2of;
-template <> struct T2of<float> { typedef float2 type; };
-template <> struct T2of<double> { typedef double2 type; };
-
 template <typename T> struct FusedCfg;
 template <> struct FusedCfg<float> { static constexpr int SG = 16, BST = 72; };
 template <> struct FusedCfg<double> { static constexpr int SG = 8, BST = 40; };
@@ -884,7 +861,6 @@ static int sigma_apply_t(trap_ctx* ctx, const T* I, T* eps, int prec, int add_th
     TRAP_HIP(hipGetLastError());
     prof_end(ctx, pr);
     // 2. contraction
-    dim3 grid(ceil_div(2LL * nt * nn, kRowsPerBlock), nth, zc);
     {
       const double kel = (double)zc * nth * nt * 2.0 * nn * P.ldm;
       const double flops = 16.0 * zc * nt * (double)nn * nn * P.nslot;
@@ -895,9 +871,7 @@ static int sigma_apply_t(trap_ctx* ctx, const T* I, T* eps, int prec, int add_th
       TRAP_TRY(dalloc(ctx, &K.W[pi], (size_t)K.zchunk * nt * P.nslot * 2 * nn * 4 * sizeof(T)));
       W = static_cast<T*>(K.W[pi]);
     }
-    hipLaunchKernelGGL(k_contract<T>, grid, dim3(512), 0, s, z0, nth, nt, nn, P.ldm, nd, Mk, Ibar,
-                       P.d_slot_off, P.d_slot_dir, W, P.nslot);
-    TRAP_HIP(hipGetLastError());
+    TRAP_TRY(launch_contract<T>(ctx, zc, z0, Mk, Ibar, W));
     prof_end(ctx, pr);
     // 3. R_III factors
     pr = prof_begin(ctx, TRAP_STAGE_R3);
@@ -912,14 +886,10 @@ static int sigma_apply_t(trap_ctx* ctx, const T* I, T* eps, int prec, int add_th
     // 4. angular / sublevel sum into Eb (chunk-local heights)
     pr = prof_begin(ctx, TRAP_STAGE_ANGULAR);
     {
-      const int nchi = P.nchi;
-      const size_t per_oc = (size_t)nu * nchi * nl * 16 * sizeof(double2) + nchi * sizeof(int);
-      const int oc_max = (int)std::max<size_t>(1, std::min<size_t>(nd, (48u << 10) / per_oc));
-      const size_t shb = std::max((size_t)oc_max * per_oc + 64,
-                                  (size_t)nchi * nl * 4 * nu * nu * sizeof(double2));
-      hipLaunchKernelGGL(k_angular<T>, dim3(zc * (nd / nchi), ceil_div(nn, kAngN)), dim3(kAngN * nchi), shb, s, z0, nd,
-                         nchi, nn, nu, nl, P.nslot, oc_max, P.c_sc, P.d_w, P.d_E, P.d_A, P.d_alpha, P.d_bma,
-                         P.d_pair_slot, W, K.X, C.d_prof, Eb + (size_t)z0 * ncls * nd * nn * 4);
+      auto kern = nl == 1 ? k_angular<T, 1> : nl == 2 ? k_angular<T, 2> : nl <= 4 ? k_angular<T, 4> : k_angular<T, 8>;
+      hipLaunchKernelGGL(kern, dim3(zc * (nd / P.nchi), ceil_div(nn, kAngN)), dim3(kAngN * P.nchi), 0, s, z0, nd,
+                         P.nchi, nn, nu, nl, P.nslot, P.d_pair_slot, P.d_pair_index, cf, W, P.c_sc, P.d_E, P.d_bma,
+                         K.X, C.d_prof, Eb + (size_t)z0 * ncls * nd * nn * 4);
     }
     TRAP_HIP(hipGetLastError());
     prof_end(ctx, pr);
