@@ -242,7 +242,8 @@ def main():
                      "frac": achieved / PEAK[key], "traffic": measured_traffic() if mixed else None,
                      "algorithmic_bytes_per_launch": cbytes / max(cstage["launches"], 1),
                      "algorithmic_flops_per_launch": flops / max(cstage["launches"], 1),
-                     "kernel": "k_contract<float>" if mixed else "k_contract<double>"},
+                     "kernel": ("k_contract<float, NH, 4|8> (two column classes per launch)" if mixed
+                                else "k_contract<double, NH, 4>")},
     }
     if args.serve_requests > 0:
         out["serving"] = serving_bench(args.serve_requests, seed=5)

@@ -24,7 +24,7 @@ SIGMA_SRC = os.path.join(HERE, "csrc", "sigma.hip")
 CONTRACT_BEGIN = "// ------------------------------------------------------------------ R_II contraction"
 CONTRACT_END = "// ------------------------------------------------------------------ R_III factors"
 COPY_BYTES = 256 << 20
-CONTRACT_NAME = "k_contract<float>"
+CONTRACT_NAME = "k_contract<float"     # both column classes (<float, NH, 4> and <float, NH, 8>)
 COPY_NAME = "neg"
 
 
@@ -74,19 +74,29 @@ def _pick(vals, needle):
     return [x for v in hits.values() for x in v]
 
 
+def _per_launch(vals, needle):
+    """Mean counter value of one launch of the stage: the stage issues one
+    dispatch of each matching kernel, so the per-kernel means add up."""
+    hits = {k: v for k, v in vals.items() if needle in k}
+    if not hits:
+        raise SystemExit(f"no dispatch of a kernel named like {needle!r}")
+    return sum(statistics.mean(v) for v in hits.values()), {k.split("(")[0]: len(v) for k, v in hits.items()}
+
+
 def traffic(fetch_csv: str, write_csv: str, out: str, command: str) -> None:
     fv = _counter_by_kernel(fetch_csv, "FETCH_SIZE")
     wv = _counter_by_kernel(write_csv, "WRITE_SIZE")
     copy_kib = COPY_BYTES / 1024.0
     f_copy, w_copy = statistics.mean(_pick(fv, COPY_NAME)), statistics.mean(_pick(wv, COPY_NAME))
     f_scale, w_scale = copy_kib / f_copy, copy_kib / w_copy
-    fc, wc = _pick(fv, CONTRACT_NAME), _pick(wv, CONTRACT_NAME)
-    f_bytes = statistics.mean(fc) * f_scale * 1024.0
-    w_bytes = statistics.mean(wc) * w_scale * 1024.0
+    fmean, fn = _per_launch(fv, CONTRACT_NAME)
+    wmean, wn = _per_launch(wv, CONTRACT_NAME)
+    f_bytes = fmean * f_scale * 1024.0
+    w_bytes = wmean * w_scale * 1024.0
     lines = [f"command: {command}",
              f"calibration kernel: elementwise negation over {COPY_BYTES} bytes "
              f"(FETCH_SIZE {f_copy:.0f} KiB -> scale {f_scale:.4f}; WRITE_SIZE {w_copy:.0f} KiB -> scale {w_scale:.4f})",
-             f"kernel: {CONTRACT_NAME}, {len(fc)} dispatches with FETCH_SIZE, {len(wc)} with WRITE_SIZE",
+             f"kernels of one contraction launch (dispatch counts, FETCH_SIZE pass): {fn}; WRITE_SIZE pass: {wn}",
              f"fetch_bytes_per_launch: {f_bytes:.6e}",
              f"write_bytes_per_launch: {w_bytes:.6e}",
              f"traffic_bytes_per_launch: {f_bytes + w_bytes:.6e}",
