@@ -161,9 +161,9 @@ int trap_set_problem(trap_ctx* ctx, const trap_atom_desc* atom, const trap_probl
     free_all(ctx);
     return fail(s, msg);
   }
-  if (ctx->pb.nl > 8 || ctx->pb.nu > 16 || ctx->pb.nchi > 16) {
+  if (ctx->pb.nl > 8 || ctx->pb.nu > 16 || ctx->pb.nchi > 16 || ctx->pb.nchi * ctx->pb.nl > 32) {
     free_all(ctx);
-    return fail(TRAP_EINVAL, "too many sublevels or azimuths (n_lower <= 8, n_upper <= 16, n_chi <= 16)");
+    return fail(TRAP_EINVAL, "too many sublevels or azimuths (n_lower <= 8, n_upper <= 16, n_chi <= 16, n_chi * n_lower <= 32)");
   }
   hipError_t e = hipStreamSynchronize(ctx->stream);
   if (e != hipSuccess) {

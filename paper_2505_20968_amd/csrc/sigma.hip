@@ -359,28 +359,30 @@ __global__ void k_r3_X(int z0, int nu, int nl, int nd, const double* __restrict_
 // eps_bar[z][l][l'][o][n][i] = sum_{o'} sum_{u'} sum_c sum_j cf[z][p(o,o')][(u',l)][c][l'][i][j]
 //                                  W[z][(u',l)][slot(o,o')][c][n][j]  +  R_III term
 // with the angular coefficients precomputed per pair (c = 0 multiplies Re W,
-// c = 1 multiplies Im W).  One thread per (o, n): a block covers the n_chi
-// azimuths of one mu ring and 32 frequencies, so the waves read W for 32
-// consecutive frequencies (contiguous 16-byte vectors) and each coefficient
-// is shared by the 32 threads of one direction.
-constexpr int kAngN = 32;
+// c = 1 multiplies Im W).  A block covers one outgoing direction o and 64
+// frequencies (one per lane); its kAngQ waves split the incoming directions
+// (o' = q, q + kAngQ, ...), so within a wave the slot, the pair and hence the
+// coefficients are uniform (scalar loads) and each W load is 64 consecutive
+// frequencies.  The partial sums meet in LDS.
+constexpr int kAngQ = 4;
 
 template <typename T, int kAngMaxNl>
-__global__ void __launch_bounds__(512) k_angular(
-    int z0, int nd, int nchi, int nn, int nu, int nl, int nslot, const int* __restrict__ pair_slot,
+__global__ void __launch_bounds__(64 * kAngQ) k_angular(
+    int z0, int nd, int nn, int nu, int nl, int nslot, const int* __restrict__ pair_slot,
     const int* __restrict__ pair_index, const T* __restrict__ cf, const T* __restrict__ W, double c_sc,
     const double2* __restrict__ E, const double2* __restrict__ bma, const double2* __restrict__ X,
     const double2* __restrict__ prof, T* __restrict__ Eb) {
   using V4 = typename Vec4<T>::type;
-  const int nmu = nd / nchi;
-  const int zl = blockIdx.x / nmu, imu = blockIdx.x % nmu;
+  __shared__ T red[kAngQ][64][kAngMaxNl][4];
+  const int zl = blockIdx.x / nd, o = blockIdx.x % nd;
   const int z = z0 + zl;
   const int nt = nu * nl;
   const int np = nd * nd;
-  const int k = threadIdx.x / kAngN;
-  const int n = blockIdx.y * kAngN + (threadIdx.x % kAngN);
-  if (n >= nn || k >= nchi) return;
-  const int o = imu * nchi + k;
+  const int lane = threadIdx.x & 63;
+  const int q = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int n = blockIdx.y * 64 + lane;
+  const bool live = n < nn;
+  const int nc = min(n, nn - 1);
   const size_t pstride = (size_t)nt * 2 * nl * 16;
   const T* cfz = cf + (size_t)z * np * pstride;
   const double sc3 = c_sc * 0.25 * kInvPi;
@@ -390,12 +392,12 @@ __global__ void __launch_bounds__(512) k_angular(
 #pragma unroll
     for (int a = 0; a < kAngMaxNl; ++a)
       for (int i = 0; i < 4; ++i) acc[a][i] = T(0);
-    for (int op = 0; op < nd; ++op) {
+    for (int op = q; op < nd; op += kAngQ) {
       const int slot = pair_slot[o * nd + op];
       const T* cp = cfz + (size_t)pair_index[o * nd + op] * pstride;
       for (int upr = 0; upr < nu; ++upr) {
         const int t = upr * nl + l;
-        const T* Wp = W + (((size_t)zl * nt + t) * nslot + slot) * 2 * (size_t)nn * 4 + (size_t)n * 4;
+        const T* Wp = W + (((size_t)zl * nt + t) * nslot + slot) * 2 * (size_t)nn * 4 + (size_t)nc * 4;
         const V4 wr = *reinterpret_cast<const V4*>(Wp);
         const V4 wi = *reinterpret_cast<const V4*>(Wp + (size_t)nn * 4);
         const T* c0 = cp + (size_t)t * 2 * nl * 16;
@@ -405,15 +407,22 @@ __global__ void __launch_bounds__(512) k_angular(
           if (lp < nl) {
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-              const V4 a = *reinterpret_cast<const V4*>(c0 + lp * 16 + i * 4);
-              const V4 b = *reinterpret_cast<const V4*>(c1 + lp * 16 + i * 4);
-              acc[lp][i] += a.x * wr.x + a.y * wr.y + a.z * wr.z + a.w * wr.w +
-                            b.x * wi.x + b.y * wi.y + b.z * wi.z + b.w * wi.w;
+              const T* a = c0 + lp * 16 + i * 4;
+              const T* b = c1 + lp * 16 + i * 4;
+              acc[lp][i] += a[0] * wr.x + a[1] * wr.y + a[2] * wr.z + a[3] * wr.w +
+                            b[0] * wi.x + b[1] * wi.y + b[2] * wi.z + b[3] * wi.w;
             }
           }
         }
       }
     }
+    if (l > 0) __syncthreads();                        // previous class's partial sums consumed
+#pragma unroll
+    for (int lp = 0; lp < kAngMaxNl; ++lp)
+      if (lp < nl)
+        for (int i = 0; i < 4; ++i) red[q][lane][lp][i] = acc[lp][i];
+    __syncthreads();
+    if (q != 0 || !live) continue;
     // R_III:  D_i(o, l', u, u') = c_sc/(4 pi) (beta - alpha)_{u u'} E_i(o; u', u, l') X[u][u'][l]
 #pragma unroll
     for (int lp = 0; lp < kAngMaxNl; ++lp) {
@@ -430,7 +439,11 @@ __global__ void __launch_bounds__(512) k_angular(
             }
           }
         T* dst = Eb + ((((size_t)zl * nl + l) * nl + lp) * nd + o) * (size_t)nn * 4 + (size_t)n * 4;
-        for (int i = 0; i < 4; ++i) dst[i] = (T)((double)acc[lp][i] + sc3 * r3[i]);
+        for (int i = 0; i < 4; ++i) {
+          T sum = T(0);
+          for (int qq = 0; qq < kAngQ; ++qq) sum += red[qq][lane][lp][i];
+          dst[i] = (T)((double)sum + sc3 * r3[i]);
+        }
       }
     }
   }
@@ -887,9 +900,9 @@ static int sigma_apply_t(trap_ctx* ctx, const T* I, T* eps, int prec, int add_th
     pr = prof_begin(ctx, TRAP_STAGE_ANGULAR);
     {
       auto kern = nl == 1 ? k_angular<T, 1> : nl == 2 ? k_angular<T, 2> : nl <= 4 ? k_angular<T, 4> : k_angular<T, 8>;
-      hipLaunchKernelGGL(kern, dim3(zc * (nd / P.nchi), ceil_div(nn, kAngN)), dim3(kAngN * P.nchi), 0, s, z0, nd,
-                         P.nchi, nn, nu, nl, P.nslot, P.d_pair_slot, P.d_pair_index, cf, W, P.c_sc, P.d_E, P.d_bma,
-                         K.X, C.d_prof, Eb + (size_t)z0 * ncls * nd * nn * 4);
+      hipLaunchKernelGGL(kern, dim3(zc * nd, ceil_div(nn, 64)), dim3(64 * kAngQ), 0, s, z0, nd, nn, nu, nl,
+                         P.nslot, P.d_pair_slot, P.d_pair_index, cf, W, P.c_sc, P.d_E, P.d_bma, K.X, C.d_prof,
+                         Eb + (size_t)z0 * ncls * nd * nn * 4);
     }
     TRAP_HIP(hipGetLastError());
     prof_end(ctx, pr);
