@@ -167,13 +167,22 @@ def main():
     mixed = args.precision == "mixed"
     ctx = Context(0)
 
+    phases = {"set_problem": [], "precompute": [], "solve": []}
+
     def one_step(seed):
         prob = cfg2(seed)
+        t0 = time.perf_counter()
         ctx.set_problem(prob)
+        t1 = time.perf_counter()
         ctx.precompute(3 if mixed else 1)
+        t2 = time.perf_counter()
         x = torch.zeros(ctx.shape, dtype=torch.float64, device="cuda")
         st = ctx.gmres_solve(x, tol=args.tol, restart=args.restart, max_iters=2000,
                              inner=TRAP_FP32 if mixed else TRAP_FP64, max_outer=10, inner_tol=1e-4)
+        t3 = time.perf_counter()
+        phases["set_problem"].append(t1 - t0)
+        phases["precompute"].append(t2 - t1)
+        phases["solve"].append(t3 - t2)
         return st
 
     if args.copy_probe:
@@ -184,6 +193,8 @@ def main():
         del xs, ys
     for i in range(args.warmup):
         one_step(1000 + i)
+    for v in phases.values():
+        v.clear()
     torch.cuda.synchronize()
     ctx.profile(True)
     lat, stats = [], []
@@ -230,6 +241,7 @@ def main():
                    "n_unknowns": info["n_unknowns"], "n_theta": info["n_theta"],
                    "n_slots": info["n_slots"], "restart": args.restart},
         "latency_ms": {"p50": 1e3 * _pct(lat, 0.5), "p99": 1e3 * _pct(lat, 0.99)},
+        "phase_ms": {k: 1e3 * sum(v) / len(v) for k, v in phases.items()},
         "solver": {"inner_iters_mean": sum(s["inner_iters"] for s in stats) / len(stats),
                    "outer_steps_mean": sum(s["outer_steps"] for s in stats) / len(stats),
                    "applies_mean": n_applies,

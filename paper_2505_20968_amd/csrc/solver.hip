@@ -137,12 +137,14 @@ int op_apply(trap_ctx* ctx, int prec, const double* x, double* y, trap_solve_sta
 // advanced together with one wait per phase (trap_gmres_step_batch):
 //   RESID_OUTER    r = b - A64 x and its norm             (one sync)
 //   RESID_RESTART  r_k = r - A_p d and its norm           (one sync)
-//   ARNOLDI        w = A_p v_j; h = V^T w                  (sync 1)
-//                  w -= V h; h2 = [V, w]^T w               (sync 2)
-//                  w -= V h2, |w| from h2, Givens update    (no sync)
-// The norm after the second projection follows from ||w - V h2||^2 =
-// ||w||^2 - ||h2||^2 (V orthonormal); when that difference is small against
-// ||w||^2 it is recomputed with one more reduction.
+//   ARNOLDI        w = A_p v_j; [h, |w|^2] = [V, w]^T w    (sync 1)
+//                  w -= V h; if the projection removed more than half of
+//                  |w|^2, a second pass: h2 = [V, w]^T w    (sync 2)
+//                  and w -= V h2; |w| and the Givens update (no sync)
+// Classical Gram-Schmidt with the reorthogonalisation pass taken only when
+// ||w - V h|| < ||w|| / sqrt(2) (the Daniel-Gragg-Kaufman-Stewart test).  The
+// norm after a projection follows from ||w - V h||^2 = ||w||^2 - ||h||^2 (V
+// orthonormal); when that difference is small it is measured directly.
 enum GmresPhase { GP_RESID_OUTER = 0, GP_RESID_RESTART = 1, GP_ARNOLDI = 2, GP_DONE = 3 };
 
 struct GmresRun {
@@ -283,7 +285,7 @@ int unit_issue1(trap_ctx* ctx, GmresRun& R) {
     case GP_ARNOLDI: {
       double* w = K.V + (size_t)(R.j + 1) * N;
       TRAP_TRY(op_apply(ctx, R.prec, K.V + (size_t)R.j * N, w, &R.st));
-      return dots_async(ctx, R, K.V, R.j + 1, w, R.hbuf);
+      return dots_async(ctx, R, K.V, R.j + 2, w, R.hbuf);   // last entry: |w|^2 (w is column j + 1)
     }
     default:
       return TRAP_OK;
@@ -328,6 +330,8 @@ int end_cycle(trap_ctx* ctx, GmresRun& R, bool converged) {
   return TRAP_OK;
 }
 
+int arnoldi_finish(trap_ctx* ctx, GmresRun& R, double hn);
+
 // host work after sync 1; issues phase-2 work of Arnoldi units
 int unit_after1(trap_ctx* ctx, GmresRun& R) {
   Work& K = ctx->wk;
@@ -368,8 +372,14 @@ int unit_after1(trap_ctx* ctx, GmresRun& R) {
     case GP_ARNOLDI: {
       const int j = R.j;
       double* w = K.V + (size_t)(j + 1) * N;
-      for (int i = 0; i <= j; ++i) R.h[i] = R.hbuf[i];
+      double s1 = 0.0;
+      for (int i = 0; i <= j; ++i) {
+        R.h[i] = R.hbuf[i];
+        s1 += R.hbuf[i] * R.hbuf[i];
+      }
+      const double wn2 = R.hbuf[j + 1];
       TRAP_TRY(axpy_async(ctx, R, K.V, j + 1, R.hbuf, w, R.dres + (R.m + 2)));
+      if (wn2 - s1 > 0.5 * wn2) return arnoldi_finish(ctx, R, std::sqrt(wn2 - s1));
       // second projection and ||w||^2 in one reduction (w is basis column j + 1)
       R.p2 = true;
       return dots_async(ctx, R, K.V, j + 2, w, R.hbuf + (R.m + 2));
@@ -400,7 +410,15 @@ int unit_after2(trap_ctx* ctx, GmresRun& R) {
     TRAP_HIP(hipStreamSynchronize(ctx->stream));
     hn2 = R.hbuf[0];
   }
-  const double hn = std::sqrt(std::max(hn2, 0.0));
+  return arnoldi_finish(ctx, R, std::sqrt(std::max(hn2, 0.0)));
+}
+
+// |w| known: normalise w, append the Hessenberg column, rotate, test
+int arnoldi_finish(trap_ctx* ctx, GmresRun& R, double hn) {
+  Work& K = ctx->wk;
+  const long long N = R.N;
+  const int j = R.j, m = R.m;
+  double* w = K.V + (size_t)(j + 1) * N;
   if (!std::isfinite(hn)) {
     run_finish(R, fail(TRAP_ENAN, "non-finite Arnoldi vector"));
     return TRAP_OK;
