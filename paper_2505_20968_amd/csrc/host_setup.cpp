@@ -541,13 +541,11 @@ size_t estimate_bytes(const trap_atom_desc* atom, const trap_problem_desc* pd, i
   b += N * 4 * 2;                                       // FP32 solver vectors
   b += nz * nd * nd * nt * 16 * 2 + nz * nt * nd * 4 * 8;  // E/A tables, geometric factors
   b += nd * nd * 4 * 4 + nslot * 8;                     // pair and slot tables
-  // the height-chunked Sigma path (problems beyond the fused kernel's limits)
-  // materialises W for one chunk of heights (at most ~1 GiB in FP64)
-  const size_t fused_f64 = ldm * 40 * 8 + nl * nd * 64 * 8, fused_f32 = ldm * 72 * 4 + nl * nd * 64 * 4;
-  const bool fits = ldm <= 128 && 2 * nu <= 16 && fused_f64 <= 65536 && fused_f32 <= 65536;
-  if (!fits) {
+  // the height-chunked Sigma path materialises W for one chunk of heights
+  // (at most ~512 MiB in FP64, half that in FP32)
+  {
     const size_t per_z = nt * nslot * 2 * nn * 4 * 8;
-    const size_t zc = std::max<size_t>(1, std::min<size_t>(nz, (size_t(1) << 30) / std::max<size_t>(per_z, 1)));
+    const size_t zc = std::max<size_t>(1, std::min<size_t>(nz, (size_t(1) << 29) / std::max<size_t>(per_z, 1)));
     b += zc * per_z * ((mask & 2) ? 3 : 2) / 2;
   }
   return b;

@@ -152,6 +152,8 @@ template <> struct T2of<double> { typedef double2 type; };
 // (h, jj) of the matrix-core chain; the column group's comoving field for the
 // chunk is staged once in LDS and read with the same k.  With one chunk
 // (padded N_nu <= 128) a block synchronises once before its products.
+// LDS row strides are padded so that the four k rows read by one matrix-core
+// step (rows 2 apart) fall in different bank groups.
 template <typename T> struct ContractCfg;
 template <> struct ContractCfg<float> { static constexpr int BST = 136; };   // 128 columns + pad
 template <> struct ContractCfg<double> { static constexpr int BST = 72; };   // 64 columns + pad
@@ -221,23 +223,17 @@ __global__ void __launch_bounds__(512, 2) k_contract(int z0, int nth, int nt, in
       }
     }
     __syncthreads();
-    // step st = 2 h + jj; the B operands of step st + 1 are read from LDS
-    // before the products of step st are issued
     const T* bcol = Bs + 2 * lk * BST + lr;
-    T af[2][NCT];
 #pragma unroll
-    for (int jt = 0; jt < NCT; ++jt) af[0][jt] = bcol[jt * 16];
+    for (int h = 0; h < NH; ++h) {
 #pragma unroll
-    for (int st = 0; st < 2 * NH; ++st) {
-      const int cur = st & 1;
-      if (st + 1 < 2 * NH) {
-        const int kn = 8 * ((st + 1) >> 1) + ((st + 1) & 1);   // 2 (4 h + lk) + jj minus 2 lk
+      for (int jj = 0; jj < 2; ++jj) {
+        const T bf = jj ? mf[h].y : mf[h].x;
+        const T* brow = bcol + (8 * h + jj) * BST;
 #pragma unroll
-        for (int jt = 0; jt < NCT; ++jt) af[cur ^ 1][jt] = bcol[kn * BST + jt * 16];
+        for (int jt = 0; jt < NCT; ++jt)
+          acc[jt] = Op::run(brow[jt * 16], bf, acc[jt]);
       }
-      const T bf = (st & 1) ? mf[st >> 1].y : mf[st >> 1].x;
-#pragma unroll
-      for (int jt = 0; jt < NCT; ++jt) acc[jt] = Op::run(af[cur][jt], bf, acc[jt]);
     }
   }
   // lane holds C[grow][slot s0 + 4 jt + lk][Stokes r]
@@ -361,7 +357,7 @@ __global__ void k_r3_X(int z0, int nu, int nl, int nd, const double* __restrict_
 // with the angular coefficients precomputed per pair (c = 0 multiplies Re W,
 // c = 1 multiplies Im W).  A block covers one outgoing direction o and 64
 // frequencies (one per lane); its kAngQ waves split the incoming directions
-// (o' = q, q + kAngQ, ...), so within a wave the slot, the pair and hence the
+// into contiguous ranges, so within a wave the slot, the pair and hence the
 // coefficients are uniform (scalar loads) and each W load is 64 consecutive
 // frequencies.  The partial sums meet in LDS.
 constexpr int kAngQ = 4;
@@ -392,7 +388,10 @@ __global__ void __launch_bounds__(64 * kAngQ) k_angular(
 #pragma unroll
     for (int a = 0; a < kAngMaxNl; ++a)
       for (int i = 0; i < 4; ++i) acc[a][i] = T(0);
-    for (int op = q; op < nd; op += kAngQ) {
+    const int chunk = (nd + kAngQ - 1) / kAngQ;
+    const int op1 = min(nd, (q + 1) * chunk);
+#pragma unroll 4
+    for (int op = q * chunk; op < op1; ++op) {
       const int slot = pair_slot[o * nd + op];
       const T* cp = cfz + (size_t)pair_index[o * nd + op] * pstride;
       for (int upr = 0; upr < nu; ++upr) {
@@ -793,9 +792,11 @@ int ensure_work(trap_ctx* ctx, int prec) {
     TRAP_TRY(dalloc_t(ctx, &K.Y, nz * P.nt * nd * 4));
     TRAP_TRY(dalloc_t(ctx, &K.X, nz * P.nu * P.nu * P.nl));
     TRAP_TRY(dalloc_t(ctx, &K.red, 4096));
-    // height chunk: keep one chunk of W (FP64) within ~1 GiB
+    // height chunk: one chunk of W within 512 MiB in FP64 (half that in FP32),
+    // so that the FP32 intermediate written by the contraction is still in the
+    // 256 MB last-level cache when the angular sum reads it
     const size_t per_z = (size_t)P.nt * P.nslot * 2 * nn * 4 * sizeof(double);
-    K.zchunk = (int)std::max<size_t>(1, std::min<size_t>(nz, (size_t(1) << 30) / std::max<size_t>(per_z, 1)));
+    K.zchunk = (int)std::max<size_t>(1, std::min<size_t>(nz, (size_t(1) << 29) / std::max<size_t>(per_z, 1)));
   }
   const int pi = prec == TRAP_FP64 ? 0 : 1;
   if (!K.Ibar[pi]) {
@@ -862,17 +863,28 @@ static int sigma_apply_t(trap_ctx* ctx, const T* I, T* eps, int prec, int add_th
     }
     prof_end(ctx, pr);
   }
-  for (int z0 = 0; z0 < nz && !(flds && cf); z0 += K.zchunk) {
-    const int zc = std::min(K.zchunk, nz - z0);
-    const long long npts = (long long)zc * nd * nn;
-    // 1. comoving interpolation
+  if (!(flds && cf)) {
+    // 1. comoving interpolation and R_III factors, all heights
     int pr = prof_begin(ctx, TRAP_STAGE_COMOVING);
-    hipLaunchKernelGGL(k_spline_shift<T>, dim3(zc * nd), dim3(128), spl_lds, s, z0, zc, nd, nn, P.d_x,
-                       P.d_SigT, P.d_lam, P.d_ub, -1.0, (const double*)nullptr, 1, 0,
-                       I + (size_t)z0 * nd * nn * 4, (long long)nd * nn * 4, (long long)nn * 4, Ibar, 0,
-                       (const double*)nullptr, (const double*)nullptr);
+    hipLaunchKernelGGL(k_spline_shift<T>, dim3(nz * nd), dim3(128), spl_lds, s, 0, nz, nd, nn, P.d_x,
+                       P.d_SigT, P.d_lam, P.d_ub, -1.0, (const double*)nullptr, 1, 0, I,
+                       (long long)nd * nn * 4, (long long)nn * 4, Ibar, 0, (const double*)nullptr,
+                       (const double*)nullptr);
     TRAP_HIP(hipGetLastError());
     prof_end(ctx, pr);
+    pr = prof_begin(ctx, TRAP_STAGE_R3);
+    const long long ny = (long long)nz * nt * nd * 4;
+    hipLaunchKernelGGL(k_r3_Y<T>, dim3(ceil_div(ny, 256)), dim3(256), 0, s, 0, nz, nt, nd, nn, C.d_r3, Ibar,
+                       K.Y);
+    TRAP_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_r3_X, dim3(nz * nu * nu * nl), dim3(256), 0, s, 0, nu, nl, nd, P.d_w, P.d_A, K.Y,
+                       K.X);
+    TRAP_HIP(hipGetLastError());
+    prof_end(ctx, pr);
+  }
+  for (int z0 = 0; z0 < nz && !(flds && cf); z0 += K.zchunk) {
+    const int zc = std::min(K.zchunk, nz - z0);
+    int pr;
     // 2. contraction
     {
       const double kel = (double)zc * nth * nt * 2.0 * nn * P.ldm;
@@ -884,17 +896,7 @@ static int sigma_apply_t(trap_ctx* ctx, const T* I, T* eps, int prec, int add_th
       TRAP_TRY(dalloc(ctx, &K.W[pi], (size_t)K.zchunk * nt * P.nslot * 2 * nn * 4 * sizeof(T)));
       W = static_cast<T*>(K.W[pi]);
     }
-    TRAP_TRY(launch_contract<T>(ctx, zc, z0, Mk, Ibar, W));
-    prof_end(ctx, pr);
-    // 3. R_III factors
-    pr = prof_begin(ctx, TRAP_STAGE_R3);
-    const long long ny = (long long)zc * nt * nd * 4;
-    hipLaunchKernelGGL(k_r3_Y<T>, dim3(ceil_div(ny, 256)), dim3(256), 0, s, z0, zc, nt, nd, nn, C.d_r3,
-                       Ibar, K.Y);
-    TRAP_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_r3_X, dim3(zc * nu * nu * nl), dim3(256), 0, s, z0, nu, nl, nd, P.d_w, P.d_A,
-                       K.Y, K.X);
-    TRAP_HIP(hipGetLastError());
+    TRAP_TRY(launch_contract<T>(ctx, zc, z0, Mk, Ibar + (size_t)z0 * nd * nn * 4, W));
     prof_end(ctx, pr);
     // 4. angular / sublevel sum into Eb (chunk-local heights)
     pr = prof_begin(ctx, TRAP_STAGE_ANGULAR);

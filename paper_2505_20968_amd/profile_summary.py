@@ -8,8 +8,8 @@
 that also launched the calibration kernel (an elementwise negation reading and
 writing COPY_BYTES), scales both counters by what they read for that kernel,
 and records HBM bytes per launch of the FP32 contraction together with a hash
-of the contraction's source, so that a stale figure is not reported after the
-kernel changes.
+of the source file that holds the kernel and its launch configuration, so that
+a stale figure is not reported after either changes.
 """
 from __future__ import annotations
 
@@ -21,18 +21,18 @@ import statistics
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SIGMA_SRC = os.path.join(HERE, "csrc", "sigma.hip")
-CONTRACT_BEGIN = "// ------------------------------------------------------------------ R_II contraction"
-CONTRACT_END = "// ------------------------------------------------------------------ R_III factors"
 COPY_BYTES = 256 << 20
 CONTRACT_NAME = "k_contract<float"     # both column classes (<float, NH, 4> and <float, NH, 8>)
 COPY_NAME = "neg"
 
 
 def contraction_source_hash() -> str:
+    """Hash of the file holding the contraction kernel and its launch
+    configuration (height chunking, column groups): any change there makes a
+    stored traffic figure stale."""
     with open(SIGMA_SRC) as f:
         src = f.read()
-    i, j = src.index(CONTRACT_BEGIN), src.index(CONTRACT_END)
-    return hashlib.sha256(src[i:j].encode()).hexdigest()
+    return hashlib.sha256(src.encode()).hexdigest()
 
 
 def _short(name: str, width: int = 72) -> str:
