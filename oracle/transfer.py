@@ -256,16 +256,22 @@ def sigma_height(op, z, Iz, normalize=True):
     return out
 
 
+def normalization_height(op, z):
+    """App. E at height z: f = (1 - eps) W_T eta_I / eps^sc_I[I = (W_T, 0, 0, 0)], Stokes I only."""
+    prob = op.prob
+    Iz = np.zeros((prob.n_dir, prob.n_nu, 4))
+    Iz[..., 0] = prob.W_T[z]
+    num = sigma_height(op, z, Iz, normalize=False)[..., 0]
+    ref = (1.0 - prob.eps[z]) * prob.W_T[z] * op.K[z, :, :, 0, 0]
+    return ref / num
+
+
 def normalization(op):
-    """App. E: f = (1 - eps) W_T eta_I / eps^sc_I[I = (W_T, 0, 0, 0)], Stokes I only."""
+    """App. E normalisation factor for every height."""
     prob = op.prob
     f = np.ones((prob.n_z, prob.n_dir, prob.n_nu))
     for z in range(prob.n_z):
-        Iz = np.zeros((prob.n_dir, prob.n_nu, 4))
-        Iz[..., 0] = prob.W_T[z]
-        num = sigma_height(op, z, Iz, normalize=False)[..., 0]
-        ref = (1.0 - prob.eps[z]) * prob.W_T[z] * op.K[z, :, :, 0, 0]
-        f[z] = ref / num
+        f[z] = normalization_height(op, z)
     return f
 
 

@@ -1,0 +1,100 @@
+"""Edge cases through the C ABI: the degenerate field-free static atmosphere
+(all Zeeman components coincide, no Doppler shifts), the smallest grids the
+library accepts (two heights, four frequencies, one azimuth, one mu per
+hemisphere; a ragged frequency count), the largest azimuth count, and invalid
+descriptions, which must fail with TRAP_EINVAL and leave the context usable."""
+import numpy as np
+import pytest
+
+from workloads import tiny, two_term_atom
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+CASES = {
+    "field_free_static": dict(n_z=5, n_nu=19, x_max=6, n_mu=4, n_chi=4, B=(0.0, 0.0, 0.0), a=1e-2, eps=5e-2),
+    "field_free_two_term": dict(n_z=4, n_nu=29, x_max=14, n_mu=4, n_chi=3, B=(0.0, 0.0, 0.0), a=1e-2,
+                                eps=5e-2, atom=two_term_atom(2800.0, 24.305, 20.0)),
+    "smallest_grids": dict(n_z=2, n_nu=4, x_max=3, n_mu=2, n_chi=1, B=(15.0, 0.7, 0.2), a=2e-2, eps=1e-1),
+    "ragged_odd_chi": dict(n_z=3, n_nu=11, x_max=5, n_mu=2, n_chi=7, B=(50.0, 1.3, 2.2), a=1e-2, eps=3e-2,
+                           v_z=3.0, seed=4),
+    "sixteen_azimuths": dict(n_z=2, n_nu=9, x_max=5, n_mu=2, n_chi=16, B=(30.0, 0.5, 1.0), a=1e-2, eps=5e-2),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_edge_case_matches_oracle(name):
+    torch = _torch()
+    from oracle import transfer as T
+    from paper_2505_20968_amd import Context, TRAP_FP32, TRAP_FP64
+    prob = tiny(**CASES[name])
+    op = T.setup(prob)
+    ctx = Context(0)
+    ctx.set_problem(prob)
+    ctx.precompute(3)
+    rng = np.random.default_rng(11)
+    I = rng.random((prob.n_z, prob.n_dir, prob.n_nu, 4))
+    It = torch.tensor(I, device="cuda")
+    e = torch.empty_like(It)
+    ctx.apply_sigma(It, e)
+    torch.cuda.synchronize()
+    r = _rel(e.cpu().numpy(), T.sigma_apply(op, I))
+    ref = T.solve(op, tol=1e-12)
+    up = op.ang["mu"] > 0
+    for inner in (TRAP_FP64, TRAP_FP32):
+        x = torch.zeros(ctx.shape, dtype=torch.float64, device="cuda")
+        st = ctx.gmres_solve(x, tol=1e-11, restart=30, max_iters=600, inner=inner, inner_tol=1e-4)
+        em, emr = ctx.emergent(x), ref[-1][up]
+        relI = (np.abs(em[..., 0] - emr[..., 0]) / np.abs(emr[..., 0])).max()
+        print(f"[{name}] sigma rel {r:.2e}; inner {inner}: {st['inner_iters']} iters, emergent I rel {relI:.2e}",
+              flush=True)
+        assert relI < 1e-6
+        for s in (1, 2, 3):
+            assert np.abs(em[..., s] / em[..., 0] - emr[..., s] / emr[..., 0]).max() < 1e-4
+    ctx.close()
+    assert r < 1e-10
+
+
+def test_invalid_descriptions_fail_cleanly():
+    torch = _torch()
+    from paper_2505_20968_amd import Context, TrapError
+    good = tiny(n_z=3, n_nu=9, x_max=4, n_mu=2, n_chi=2)
+    ctx = Context(0)
+    bad = [
+        good.with_(x=good.x[::-1].copy()),                         # frequencies must increase
+        good.with_(x=np.linspace(0.5, 4.0, 9)),                     # grid must bracket 0
+        good.with_(x=np.linspace(-1.0, 1.0, 3)),                    # fewer than 4 nodes
+        good.with_(n_mu=3),                                         # odd mu count
+        good.with_(n_chi=17),                                       # more than 16 azimuths
+        good.with_(tau_line=np.array([1.0, -1.0, 1e-3])),           # optical depth must be positive
+    ]
+    for p in bad:
+        with pytest.raises(TrapError) as ei:
+            ctx.set_problem(p)
+        assert ei.value.code == -1, ei.value
+    # the context still works after the failures
+    ctx.set_problem(good)
+    ctx.precompute(3)
+    x = torch.zeros(ctx.shape, dtype=torch.float64, device="cuda")
+    st = ctx.gmres_solve(x, tol=1e-9, restart=20, max_iters=300, inner=0)
+    assert st["final_rel_res"] < 1e-9
+    # calls out of order are state errors (TRAP_ESTATE)
+    ctx2 = Context(0)
+    ctx2.set_problem(good)
+    v = torch.zeros(ctx2.shape, device="cuda", dtype=torch.float64)
+    with pytest.raises(TrapError) as ei:
+        ctx2.apply_sigma(v, torch.empty_like(v))
+    assert ei.value.code == -5
+    ctx2.close()
+    ctx.close()

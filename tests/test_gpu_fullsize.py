@@ -1,0 +1,130 @@
+"""Parity at the benchmark sizes, in the launch configuration bench.py times.
+
+* cfg1 (two-level slab, N = 79 360): full FP64 and mixed-precision solves
+  against the oracle's emergent profiles (tests/golden/cfg1_emergent.txt,
+  written by tests/golden/make_cfg1_emergent.py from the oracle alone).
+* cfg2 (chromosphere column, N = 1 809 920): Sigma is height-local, so the
+  full-size GPU apply is compared with the oracle's Sigma at sampled heights
+  (the oracle builds those heights' kernels itself); Lambda is compared for
+  every ray; the mixed solve's FP64 residual and its agreement with the FP64
+  solve are checked.
+Tolerances as in the small-case parity tests: FP64 operator 1e-10, FP32
+operator 2e-5 (relative 2-norm), FP32 formal solution 1e-6, emergent I 1e-6
+relative and Q/I, U/I, V/I 1e-4 absolute.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from workloads import cfg1, cfg2
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("inner", ["fp64", "fp32"])
+def test_cfg1_full_solve_matches_oracle(inner):
+    torch = _torch()
+    from paper_2505_20968_amd import Context, TRAP_FP32, TRAP_FP64
+    g = np.loadtxt(os.path.join(HERE, "golden", "cfg1_emergent.txt"))
+    prob = cfg1()
+    ctx = Context(0)
+    ctx.set_problem(prob)
+    ctx.precompute(3)
+    x = torch.zeros(ctx.shape, dtype=torch.float64, device="cuda")
+    st = ctx.gmres_solve(x, tol=1e-10, restart=40, max_iters=2000,
+                         inner=TRAP_FP64 if inner == "fp64" else TRAP_FP32, inner_tol=1e-4, max_outer=10)
+    em = ctx.emergent(x)
+    ctx.close()
+    ref = g[:, 2:].reshape(em.shape)
+    relI = np.abs(em[..., 0] - ref[..., 0]) / np.abs(ref[..., 0])
+    print(f"[cfg1 {inner}] {st['inner_iters']} iters, res {st['final_rel_res']:.2e}, max rel I {relI.max():.2e}",
+          flush=True)
+    assert st["final_rel_res"] < 1e-10
+    assert relI.max() < 1e-6
+    for s in (1, 2, 3):
+        assert np.abs(em[..., s] / em[..., 0] - ref[..., s] / ref[..., 0]).max() < 1e-4
+
+
+@pytest.fixture(scope="module")
+def big():
+    torch = _torch()
+    from paper_2505_20968_amd import Context
+    prob = cfg2(2)
+    ctx = Context(0)
+    ctx.set_problem(prob)
+    ctx.precompute(3)
+    rng = np.random.default_rng(7)
+    I = rng.random((prob.n_z, prob.n_dir, prob.n_nu, 4))
+    I[..., 1:] = 0.2 * (I[..., 1:] - 0.5) * I[..., :1]
+    print(f"\n[cfg2] N={prob.n_unknowns}", flush=True)
+    yield prob, ctx, I, torch
+    ctx.close()
+
+
+SAMPLED_HEIGHTS = (0, 52)
+
+
+def test_cfg2_sigma_at_sampled_heights(big):
+    prob, ctx, I, torch = big
+    from oracle import transfer as T
+    It64 = torch.tensor(I, dtype=torch.float64, device="cuda")
+    e64 = torch.empty_like(It64)
+    ctx.apply_sigma(It64, e64)
+    It32 = It64.float()
+    e32 = torch.empty_like(It32)
+    ctx.apply_sigma(It32, e32)
+    torch.cuda.synchronize()
+    g64, g32 = e64.cpu().numpy(), e32.double().cpu().numpy()
+    op = T.setup(prob, {"normalize": False})
+    for z in SAMPLED_HEIGHTS:
+        ref = T.sigma_height(op, z, I[z], normalize=False)
+        ref[..., 0] *= T.normalization_height(op, z)
+        r64, r32 = _rel(g64[z], ref), _rel(g32[z], ref)
+        print(f"[cfg2] height {z}: sigma fp64 rel {r64:.2e}, fp32 rel {r32:.2e}", flush=True)
+        assert r64 < 1e-10
+        assert r32 < 2e-5
+
+
+def test_cfg2_formal_solution_every_ray(big):
+    prob, ctx, I, torch = big
+    from oracle import transfer as T
+    op = T.setup(prob, {"normalize": False})
+    eps = np.abs(I) * 0.3
+    ref = T.formal_solve(op, eps, boundary=True)
+    for dt, tol in ((torch.float64, 1e-12), (torch.float32, 1e-6)):
+        et = torch.tensor(eps, dtype=dt, device="cuda")
+        out = torch.empty_like(et)
+        ctx.formal_solve(et, out, with_boundary=True)
+        torch.cuda.synchronize()
+        r = _rel(out.double().cpu().numpy(), ref)
+        print(f"[cfg2] formal {dt} rel {r:.2e}", flush=True)
+        assert r < tol
+
+
+def test_cfg2_mixed_solve_agrees_with_fp64_solve(big):
+    prob, ctx, I, torch = big
+    from paper_2505_20968_amd import TRAP_FP32, TRAP_FP64
+    out = {}
+    for name, inner in (("mixed", TRAP_FP32), ("fp64", TRAP_FP64)):
+        x = torch.zeros(ctx.shape, dtype=torch.float64, device="cuda")
+        st = ctx.gmres_solve(x, tol=1e-10, restart=40, max_iters=2000, inner=inner, inner_tol=1e-4, max_outer=10)
+        print(f"[cfg2] {name} solve: {st}", flush=True)
+        assert st["final_rel_res"] < 1e-10
+        out[name] = ctx.emergent(x)
+    a, b = out["mixed"], out["fp64"]
+    assert (np.abs(a[..., 0] - b[..., 0]) / np.abs(b[..., 0])).max() < 1e-6
+    for s in (1, 2, 3):
+        assert np.abs(a[..., s] / a[..., 0] - b[..., s] / b[..., 0]).max() < 1e-4
