@@ -33,9 +33,9 @@ function that implements it.
 """
 from .grids import angular_grid, theta_table, SplineBasis
 from .atom import AtomModel, build_atom
-from .redistribution import faddeeva, F_function, kernel_matrix, r3_weights
+from .redistribution import faddeeva, F_function, kernel_matrix, kernel_matrix_aa, r3_weights
 from .transfer import OracleProblem, setup, sigma_apply, formal_solve, apply_operator, solve
 
 __all__ = ["angular_grid", "theta_table", "SplineBasis", "AtomModel", "build_atom",
-           "faddeeva", "F_function", "kernel_matrix", "r3_weights",
+           "faddeeva", "F_function", "kernel_matrix", "kernel_matrix_aa", "r3_weights",
            "OracleProblem", "setup", "sigma_apply", "formal_solve", "apply_operator", "solve"]

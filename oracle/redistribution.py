@@ -151,6 +151,19 @@ def kernel_matrix(theta: float, s: float, a: float, lam: float, basis, n_gl: int
     return M
 
 
+def kernel_matrix_aa(s: float, a: float, lam: float, basis, n_theta: int = 25):
+    """Angle-averaged R_II kernel (Sect. 5.2, Eq. R_AA): the scattering-angle
+    average (1/2) int_0^pi sin(Theta) M(Theta) dTheta of the kernel matrix, with
+    the Gauss-Legendre rule of n_theta nodes on [0, pi] that App. C uses for it."""
+    t, w = np.polynomial.legendre.leggauss(n_theta)
+    th = 0.5 * np.pi * (t + 1.0)
+    wt = 0.5 * np.pi * w * 0.5 * np.sin(th)
+    M = np.zeros((basis.x.size, basis.x.size), complex)
+    for thk, wk in zip(th, wt):
+        M += wk * kernel_matrix(float(thk), s, a, lam, basis)
+    return M
+
+
 def _tail_integral(fun, start, direction):
     """int from start to +-inf of a complex function, with scipy quad."""
     if direction > 0:

@@ -57,7 +57,7 @@ from scipy.sparse.linalg import LinearOperator, gmres
 
 from .atom import build_atom
 from .grids import angular_grid, theta_table, SplineBasis
-from .redistribution import SQRT_PI, faddeeva, kernel_matrix, r3_weights
+from .redistribution import SQRT_PI, faddeeva, kernel_matrix, kernel_matrix_aa, r3_weights
 
 C_CGS = 2.99792458e10
 K_B = 1.380649e-16
@@ -110,6 +110,8 @@ def setup(prob, opts=None) -> OracleProblem:
       zero_profile_shifts: transitions at the zero-field frequency in all
                     profiles while alpha/beta keep the sublevel splittings
       normalize:    apply the App. E factor f (default True)
+      aa:           angle-averaged R_II (Sect. 5.2, Eq. R_AA) in place of the
+                    angle-dependent kernel (default False)
     """
     opts = dict({"normalize": True}, **(opts or {}))
     atom = prob.atom
@@ -176,7 +178,13 @@ def setup(prob, opts=None) -> OracleProblem:
 
 
 def _kernel(op, z, th, u, l):
-    # heights with identical (Theta, shift, damping, grid scale) share a kernel
+    # heights with identical (Theta, shift, damping, grid scale) share a kernel;
+    # the angle-averaged kernel is the same for every pair
+    if op.opts.get("aa"):
+        key = ("aa", float(op.s_ul[z, u, l]), float(op.prob.a[z]), float(op.lam[z]))
+        if key not in op.M:
+            op.M[key] = kernel_matrix_aa(op.s_ul[z, u, l], op.prob.a[z], op.lam[z], op.basis)
+        return op.M[key]
     key = (float(op.theta[th]), float(op.s_ul[z, u, l]), float(op.prob.a[z]), float(op.lam[z]))
     if key not in op.M:
         op.M[key] = kernel_matrix(op.theta[th], op.s_ul[z, u, l], op.prob.a[z],

@@ -437,3 +437,51 @@ def test_gmres_matches_dense_solve():
     assert np.abs(Ig - Id).max() < 1e-11 * np.abs(Id).max()
     r = T.rhs(op) - T.apply_operator(op, Id)
     assert np.linalg.norm(r) < 1e-12 * np.linalg.norm(T.rhs(op))
+
+
+# ---------------------------------------------------------------- angle-averaged PRD (Sect. 5.2, Eq. R_AA)
+
+def test_aa_kernel_theta_rule_matches_adaptive_integral():
+    """The angle-averaged kernel (1/2) int_0^pi sin(Theta) M(Theta) dTheta,
+    evaluated with the 25-node Gauss-Legendre rule of App. C, equals an
+    adaptive Theta integral of the angle-dependent kernel."""
+    from scipy.integrate import quad_vec
+    from oracle.redistribution import kernel_matrix_aa
+    b = SplineBasis(np.linspace(-4.0, 4.0, 9))
+    for a, s in ((1e-2, 0.3), (5e-2, -1.0)):
+        Mg = kernel_matrix_aa(s, a, 1.1, b)
+        Mq, _ = quad_vec(lambda th: (0.5 * np.sin(th) * kernel_matrix(th, s, a, 1.1, b)).ravel(),
+                         0.0, np.pi, epsrel=1e-10, epsabs=1e-13)
+        assert np.abs(Mg - Mq.reshape(Mg.shape)).max() < 1e-8 * np.abs(Mg).max()
+
+
+def test_aa_and_ad_agree_on_a_flat_field():
+    """For a flat incident field every kernel row integrates to sqrt(pi) W
+    whatever Theta is, so the angle-averaged and angle-dependent emissivities
+    coincide (moving, magnetised, seeded atmosphere; unnormalised Sigma)."""
+    p = tiny(n_z=3, n_nu=13, x_max=6, n_mu=4, n_chi=4, B=(40.0, 1.0, 0.4), a=2e-2, eps=3e-2,
+             v_z=1.5, seed=5)
+    ad = T.sigma_apply(T.setup(p, {"normalize": False}), _flat(p), normalize=False)
+    aa = T.sigma_apply(T.setup(p, {"normalize": False, "aa": True}), _flat(p), normalize=False)
+    assert np.abs(aa - ad).max() < 1e-10 * np.abs(ad).max()
+
+
+def test_aa_and_ad_solutions_identical_without_rII():
+    """With alpha = 0 only R_III scatters, which does not depend on Theta:
+    angle-averaged and angle-dependent solutions are the same."""
+    p = tiny(n_z=3, n_nu=9, x_max=5, n_mu=4, n_chi=3, B=(25.0, 1.2, 0.3), a=2e-2, eps=0.05, seed=11)
+    s_ad = T.solve(T.setup(p, {"alpha_zero": True}), tol=1e-13)
+    s_aa = T.solve(T.setup(p, {"alpha_zero": True, "aa": True}), tol=1e-13)
+    assert np.abs(s_aa - s_ad).max() < 1e-12 * np.abs(s_ad).max()
+
+
+def test_aa_differs_from_ad_for_an_anisotropic_field():
+    """Guard against an AA switch that changes nothing: for a strongly
+    anisotropic, frequency-structured field the two kernels give different
+    emissivities."""
+    p = tiny(n_z=2, n_nu=13, x_max=6, n_mu=4, n_chi=4, B=(0.0, 0.0, 0.0), a=1e-2, eps=3e-2)
+    rng = np.random.default_rng(3)
+    I = rng.random((p.n_z, p.n_dir, p.n_nu, 4))
+    ad = T.sigma_apply(T.setup(p, {"normalize": False}), I, normalize=False)
+    aa = T.sigma_apply(T.setup(p, {"normalize": False, "aa": True}), I, normalize=False)
+    assert np.abs(aa - ad).max() > 1e-3 * np.abs(ad).max()
