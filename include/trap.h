@@ -224,6 +224,15 @@ typedef struct {
 int trap_profile(trap_ctx* ctx, int enable);
 int trap_stage_times(trap_ctx* ctx, trap_stage_stats* out);
 
+/* Angle-dependent (default) or angle-averaged partial frequency redistribution
+ * for R_II (Sect. 5.2, Eq. R_AA): in the AA mode every pair of directions uses
+ * the kernel (1/2) int_0^pi sin(Theta) M(Theta) dTheta, evaluated with the
+ * 25-node Gauss-Legendre rule in Theta of App. C.  The mode takes effect at
+ * the next trap_set_problem.  trap_footprint sizes the AD layout, which bounds
+ * the AA one from above for Theta tables of 25 angles or more. */
+enum { TRAP_PRD_AD = 0, TRAP_PRD_AA = 1 };
+int trap_set_prd_mode(trap_ctx* ctx, int mode);
+
 /* Choice of Sigma implementation (both compute the same operator):
  * TRAP_PATH_AUTO (default) and TRAP_PATH_CHUNKED materialise the R_II
  * intermediate W per chunk of heights (contraction, then angular sum).

@@ -290,6 +290,13 @@ int trap_gmres_end(trap_ctx* ctx, trap_solve_stats* stats) {
   return gmres_end(ctx, stats);
 }
 
+int trap_set_prd_mode(trap_ctx* ctx, int mode) {
+  if (!ctx) return fail(TRAP_EINVAL, "null context");
+  if (mode != TRAP_PRD_AD && mode != TRAP_PRD_AA) return fail(TRAP_EINVAL, "unknown PRD mode");
+  ctx->prd_mode = mode;
+  return TRAP_OK;
+}
+
 int trap_set_path(trap_ctx* ctx, int path) {
   if (!ctx) return fail(TRAP_EINVAL, "null context");
   if (path != TRAP_PATH_AUTO && path != TRAP_PATH_FUSED && path != TRAP_PATH_CHUNKED)

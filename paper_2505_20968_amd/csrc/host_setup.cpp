@@ -361,6 +361,7 @@ std::vector<double> spline_map(const std::vector<double>& x, std::vector<double>
 static void angular_setup(Problem& P, std::vector<double>& dirs, std::vector<double>& ea,
                           std::vector<double>& eb) {
   const int nd = P.nd;
+  const bool aa = P.prd_mode == TRAP_PRD_AA;
   std::vector<double> gt, gw;
   gauss_legendre01(P.nmu / 2, gt, gw);
   std::vector<double> mu1, wmu1;
@@ -409,6 +410,10 @@ static void angular_setup(Problem& P, std::vector<double>& dirs, std::vector<dou
   std::vector<double> reps{sorted[0]};
   for (size_t k = 1; k < sorted.size(); ++k)
     if (reps.back() - sorted[k] > 1e-10) reps.push_back(sorted[k]);
+  // angle-averaged PRD (Sect. 5.2, Eq. R_AA): one kernel for every pair, so a
+  // single "angle" class holds every incoming direction as a slot; its kernel
+  // is the average of the rows at the 25 Gauss-Legendre angles of App. C
+  if (aa) reps.assign(1, 1.0);
   P.nth = static_cast<int>(reps.size());
   P.theta.resize(P.nth);
   for (int t = 0; t < P.nth; ++t) {
@@ -421,6 +426,20 @@ static void angular_setup(Problem& P, std::vector<double>& dirs, std::vector<dou
       if (std::fabs(reps[t] - cosv[k]) < std::fabs(reps[best] - cosv[k])) best = t;
     P.pair_theta[k] = best;
   }
+  if (aa) {
+    std::vector<double> gt, gw;
+    gauss_legendre01(25, gt, gw);
+    P.theta_rows.resize(25);
+    P.theta_rw.resize(25);
+    for (int g = 0; g < 25; ++g) {
+      P.theta_rows[g] = kPi * gt[g];
+      P.theta_rw[g] = kPi * gw[g] * 0.5 * std::sin(P.theta_rows[g]);
+    }
+  } else {
+    P.theta_rows = P.theta;
+    P.theta_rw.clear();
+  }
+  P.nth_rows = static_cast<int>(P.theta_rows.size());
   // slots: for each theta the incoming directions that occur with it
   std::vector<std::vector<int>> used(P.nth, std::vector<int>(nd, -1));
   for (int o = 0; o < nd; ++o)
@@ -604,6 +623,7 @@ int build_problem(trap_ctx* ctx, const trap_atom_desc* at, const trap_problem_de
     P.eta0[z] = std::exp(P.a[z] * P.a[z]) * std::erfc(P.a[z]) / std::sqrt(kPi);
   }
   // ---- angular grid, scattering angles, slots
+  P.prd_mode = ctx->prd_mode;
   std::vector<double> dirs, ea, eb;
   angular_setup(P, dirs, ea, eb);
   // ---- sublevels per height
@@ -684,6 +704,8 @@ int build_problem(trap_ctx* ctx, const trap_atom_desc* at, const trap_problem_de
   TRAP_TRY(upload_t(ctx, &P.d_st, st));
   TRAP_TRY(upload_t(ctx, &P.d_sll, sll));
   TRAP_TRY(upload_t(ctx, &P.d_theta, P.theta));
+  TRAP_TRY(upload_t(ctx, &P.d_theta_rows, P.theta_rows));
+  TRAP_TRY(upload_t(ctx, &P.d_theta_rw, P.theta_rw));
   TRAP_TRY(upload_t(ctx, &P.d_slot_theta, P.slot_theta));
   TRAP_TRY(upload_t(ctx, &P.d_slot_dir, P.slot_dir));
   TRAP_TRY(upload_t(ctx, &P.d_slot_off, P.slot_off));

@@ -536,6 +536,20 @@ __global__ void k_coef_table(int nd, int nu, int nl, double c_sc, const double* 
   }
 }
 
+// Angle-averaged kernels (Sect. 5.2, Eq. R_AA): M[z][0][t][c][n][m] =
+// sum_g w_g Mg[z][g][t][c][n][m] over the Theta nodes of one height chunk.
+__global__ void k_theta_average(long long per_z_out, int ng, int zc, const double* __restrict__ w,
+                                const double* __restrict__ Mg, double* __restrict__ M64, float* __restrict__ M32,
+                                long long out_offset) {
+  const long long id = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (id >= per_z_out * zc) return;
+  const long long zl = id / per_z_out, r = id % per_z_out;
+  double v = 0.0;
+  for (int g = 0; g < ng; ++g) v += w[g] * Mg[(zl * ng + g) * per_z_out + r];
+  if (M64) M64[out_offset + id] = v;
+  if (M32) M32[out_offset + id] = (float)v;
+}
+
 int run_precompute(trap_ctx* ctx, int store_mask) {
   Problem& P = ctx->pb;
   Precomp& C = ctx->pre;
@@ -577,6 +591,8 @@ int run_precompute(trap_ctx* ctx, int store_mask) {
   TRAP_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_gl_t), gt, sizeof(gt)));
   TRAP_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_gl_w), gw, sizeof(gw)));
   const int nz = P.nz, nd = P.nd, nn = P.nn, nt = P.nt, nth = P.nth;
+  const int nthr = P.nth_rows;                    // angles at which rows are computed
+  const bool aa = P.prd_mode == TRAP_PRD_AA;
   const long long npt = (long long)nz * nd * nn;
   if (!C.d_K) {
     TRAP_TRY(dalloc_t(ctx, &C.d_K, npt * 8));
@@ -603,44 +619,57 @@ int run_precompute(trap_ctx* ctx, int store_mask) {
   for (int k = 0; k + 1 < nn; ++k)
     if (std::fabs(P.x[k + 1] - P.x[k] - h) > 1e-12 * std::fabs(h)) uniform = false;
   const int nd2 = 2 * nn - 1;
-  const size_t tab_per_z = (size_t)nth * nd2 * 16 * (sizeof(double) + nt * sizeof(double2));
-  const size_t rows_per_z = (size_t)nth * nt * 2 * nn;
-  const size_t lg_per_z = rows_per_z * P.ldm * sizeof(double) * 2;
+  const size_t tab_per_z = (size_t)nthr * nd2 * 16 * (sizeof(double) + nt * sizeof(double2));
+  const size_t rows_per_z = (size_t)nthr * nt * 2 * nn;
+  const size_t lg_per_z = rows_per_z * P.ldm * sizeof(double) * (aa ? 3 : 2);
   size_t zc_lim = std::max<size_t>(1, (size_t(1) << 30) / lg_per_z);
   if (uniform) zc_lim = std::min(zc_lim, std::max<size_t>(1, (size_t(192) << 20) / tab_per_z));
   const int zc_tab = (int)std::min<size_t>(nz, zc_lim);
   if (uniform && !C.d_Gt) {
-    TRAP_TRY(dalloc_t(ctx, &C.d_Gt, (size_t)zc_tab * nth * nd2 * 16));
-    TRAP_TRY(dalloc_t(ctx, &C.d_Vt, (size_t)zc_tab * nth * nt * nd2 * 16));
+    TRAP_TRY(dalloc_t(ctx, &C.d_Gt, (size_t)zc_tab * nthr * nd2 * 16));
+    TRAP_TRY(dalloc_t(ctx, &C.d_Vt, (size_t)zc_tab * nthr * nt * nd2 * 16));
   }
   if (!C.d_Lrow || C.zc_rows < zc_tab) {
     TRAP_TRY(dalloc_t(ctx, &C.d_Lrow, (size_t)zc_tab * rows_per_z * P.ldm));
     TRAP_TRY(dalloc_t(ctx, &C.d_Grow, (size_t)zc_tab * rows_per_z * P.ldm));
+    if (aa) TRAP_TRY(dalloc_t(ctx, &C.d_Mtmp, (size_t)zc_tab * rows_per_z * P.ldm));
     C.zc_rows = zc_tab;
   }
   const int pr = prof_begin(ctx, TRAP_STAGE_KERNEL_ROWS);
   for (int z0 = 0; z0 < nz; z0 += zc_tab) {
     const int zc = std::min(zc_tab, nz - z0);
     if (uniform) {
-      hipLaunchKernelGGL(k_kernel_tables, dim3(zc * nth * nt), dim3(256), 0, s, z0, nth, nt, nn, P.x[0], h,
-                         P.d_lam, P.d_a, P.d_st, P.d_theta, C.d_Gt, C.d_Vt);
+      hipLaunchKernelGGL(k_kernel_tables, dim3(zc * nthr * nt), dim3(256), 0, s, z0, nthr, nt, nn, P.x[0], h,
+                         P.d_lam, P.d_a, P.d_st, P.d_theta_rows, C.d_Gt, C.d_Vt);
       TRAP_HIP(hipGetLastError());
     }
-    const long long nrows = (long long)zc * nth * nt * nn;      // complex rows of this chunk
+    const long long nrows = (long long)zc * nthr * nt * nn;     // complex rows of this chunk
     const long long chunk = 1 << 20;
     for (long long r0 = 0; r0 < nrows; r0 += chunk) {
       const long long nr = std::min(chunk, nrows - r0);
-      hipLaunchKernelGGL(k_kernel_rows, dim3((unsigned)nr), dim3(64), lds, s, nth, nt, nn, P.ldm, P.d_x,
-                         P.d_lam, P.d_a, P.d_st, P.d_theta, C.d_Lrow, C.d_Grow, r0, z0, h,
+      hipLaunchKernelGGL(k_kernel_rows, dim3((unsigned)nr), dim3(64), lds, s, nthr, nt, nn, P.ldm, P.d_x,
+                         P.d_lam, P.d_a, P.d_st, P.d_theta_rows, C.d_Lrow, C.d_Grow, r0, z0, h,
                          uniform ? C.d_Gt : nullptr, uniform ? C.d_Vt : nullptr);
       TRAP_HIP(hipGetLastError());
     }
     const long long rrows = 2 * nrows;                           // real rows (both planes)
     dim3 gg(ceil_div(rrows, 64), ceil_div(P.ldm, kSigColTiles * 16));
-    hipLaunchKernelGGL(k_sig_gemm, gg, dim3(256), 0, s, rrows, nn, P.ldm, C.d_Grow, C.d_Lrow, P.d_Sig,
-                       (mask & 1) ? C.d_M64 : nullptr, (mask & 2) ? C.d_M32 : nullptr,
-                       (long long)z0 * nth * nt * 2 * nn);
-    TRAP_HIP(hipGetLastError());
+    if (!aa) {
+      hipLaunchKernelGGL(k_sig_gemm, gg, dim3(256), 0, s, rrows, nn, P.ldm, C.d_Grow, C.d_Lrow, P.d_Sig,
+                         (mask & 1) ? C.d_M64 : nullptr, (mask & 2) ? C.d_M32 : nullptr,
+                         (long long)z0 * nth * nt * 2 * nn);
+      TRAP_HIP(hipGetLastError());
+    } else {
+      // rows at the Gauss-Legendre angles into the scratch store, then their weighted sum
+      hipLaunchKernelGGL(k_sig_gemm, gg, dim3(256), 0, s, rrows, nn, P.ldm, C.d_Grow, C.d_Lrow, P.d_Sig,
+                         C.d_Mtmp, (float*)nullptr, 0LL);
+      TRAP_HIP(hipGetLastError());
+      const long long per_z_out = (long long)nt * 2 * nn * P.ldm;
+      hipLaunchKernelGGL(k_theta_average, dim3(ceil_div(per_z_out * zc, 256)), dim3(256), 0, s, per_z_out, nthr,
+                         zc, P.d_theta_rw, C.d_Mtmp, (mask & 1) ? C.d_M64 : nullptr, (mask & 2) ? C.d_M32 : nullptr,
+                         (long long)z0 * per_z_out);
+      TRAP_HIP(hipGetLastError());
+    }
   }
   prof_end(ctx, pr);
   hipLaunchKernelGGL(k_r3_rows, dim3(nz * nt), dim3(64), lds, s, nt, nn, P.d_x, P.d_P, P.d_lam, P.d_a,

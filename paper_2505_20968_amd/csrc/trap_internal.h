@@ -67,6 +67,11 @@ struct Problem {
   // host copies used by host-side logic
   std::vector<double> x, mu, w, tau, lam, a, eps, WT, eta0, dnuD;
   std::vector<double> theta;               // [nth]
+  int prd_mode = 0;                        // TRAP_PRD_AD or TRAP_PRD_AA
+  // scattering angles at which kernel rows are computed: the Theta table (AD)
+  // or the Gauss-Legendre nodes of the angle average (AA, weights theta_rw)
+  std::vector<double> theta_rows, theta_rw;
+  int nth_rows = 0;
   std::vector<int> slot_off;               // [nth+1]
   std::vector<int> slot_dir;               // [nslot]
   std::vector<int> slot_theta;             // [nslot]
@@ -91,6 +96,8 @@ struct Problem {
   double *d_st = nullptr;                  // [nz][nt] reduced transition shifts
   double *d_sll = nullptr;                 // [nz][nl][nl] lower-level shifts
   double *d_theta = nullptr;               // [nth]
+  double *d_theta_rows = nullptr;          // [nth_rows]
+  double *d_theta_rw = nullptr;            // [nth_rows] AA weights
   int *d_slot_theta = nullptr, *d_slot_dir = nullptr, *d_slot_off = nullptr, *d_pair_slot = nullptr;
   int *d_pair_off = nullptr, *d_pair_o = nullptr, *d_pair_dir = nullptr, *d_pair_index = nullptr;
   int *d_grp[2] = {nullptr, nullptr};
@@ -111,6 +118,7 @@ struct Precomp {
   double2 *d_r3 = nullptr;    // [z][t][n] R_III incoming weights
   double2 *d_prof = nullptr;  // [z][t][n] outgoing profiles on the comoving grid
   double *d_b = nullptr;      // right-hand side, FP64 vector
+  double *d_Mtmp = nullptr;   // AA: kernels at the Theta nodes of one height chunk, FP64
   double *d_cf64 = nullptr;   // angular coefficients [z][pair][t][c][l'][i][j], FP64
   float *d_cf32 = nullptr;    //   and FP32
   double *d_Gt = nullptr;     // Gaussian factor table of the kernel precompute (uniform grids)
@@ -164,6 +172,7 @@ struct trap_ctx {
   trap::Prof prof;
   trap::GmresRun* run = nullptr;    // state of the current GMRES solve
   int path = 0;                     // TRAP_PATH_* of trap.h
+  int prd_mode = 0;                 // TRAP_PRD_* of trap.h, applied at trap_set_problem
   int max_lds = 64 * 1024;          // device limit of LDS bytes per block
   std::vector<trap::DevBuf> bufs;   // every allocation the context made
 };

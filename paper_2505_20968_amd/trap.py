@@ -19,13 +19,14 @@ LIB_PATH = os.path.join(HERE, "libtrap.so")
 TRAP_FP64 = 0
 TRAP_FP32 = 1
 TRAP_PATH_AUTO, TRAP_PATH_FUSED, TRAP_PATH_CHUNKED = 0, 1, 2
+TRAP_PRD_AD, TRAP_PRD_AA = 0, 1
 STATUS = {0: "TRAP_OK", -1: "TRAP_EINVAL", -2: "TRAP_ENOMEM", -3: "TRAP_EDEVICE",
           -4: "TRAP_ENOCONV", -5: "TRAP_ESTATE", -6: "TRAP_ENAN"}
 
 EXPORTED = ["trap_create", "trap_destroy", "trap_set_problem", "trap_precompute",
             "trap_apply_sigma", "trap_formal_solve", "trap_apply_operator", "trap_rhs",
             "trap_gmres_solve", "trap_emergent", "trap_get_info", "trap_footprint",
-            "trap_profile", "trap_stage_times", "trap_set_path", "trap_gmres_begin",
+            "trap_profile", "trap_stage_times", "trap_set_path", "trap_set_prd_mode", "trap_gmres_begin",
             "trap_gmres_step_batch", "trap_gmres_end", "trap_last_error"]
 STAGES = ["comoving", "contract_fp32", "r3", "angular", "backinterp", "formal", "kernel_rows",
           "contract_fp64"]
@@ -100,6 +101,7 @@ def load_library(path: str = LIB_PATH):
                                    ctypes.POINTER(ctypes.c_size_t)]
     lib.trap_profile.argtypes = [vp, ctypes.c_int]
     lib.trap_set_path.argtypes = [vp, ctypes.c_int]
+    lib.trap_set_prd_mode.argtypes = [vp, ctypes.c_int]
     lib.trap_gmres_begin.argtypes = [vp, ctypes.POINTER(SolveOpts), vp]
     lib.trap_gmres_step_batch.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
     lib.trap_gmres_end.argtypes = [vp, ctypes.POINTER(SolveStats)]
@@ -264,6 +266,10 @@ class Context:
         out = np.zeros((n_up, self.shape[2], 4))
         _check(self.lib.trap_emergent(self.h, self._vec(I, TRAP_FP64), out.ctypes.data_as(_dp)))
         return out
+
+    def set_prd_mode(self, mode: int):
+        """TRAP_PRD_AD or TRAP_PRD_AA; takes effect at the next set_problem."""
+        _check(self.lib.trap_set_prd_mode(self.h, int(mode)))
 
     def set_path(self, path: int):
         """Sigma implementation: TRAP_PATH_AUTO, TRAP_PATH_FUSED or TRAP_PATH_CHUNKED."""
