@@ -183,20 +183,21 @@ def _cfg3_grid() -> np.ndarray:
     return x[:200] if x.size > 200 else x
 
 
-def cfg3(seed: int = 3) -> Problem:
+def cfg3(seed: int = 3, n_z: int = 80) -> Problem:
     """Two-term Mg II h&k-like doublet, components at x=+-10, N_z=80, N_nu=200,
-    6+6 mu x 8 chi."""
+    6+6 mu x 8 chi.  n_z < 80 gives the same generator on fewer heights."""
     atom = two_term_atom(2800.0, 24.305, 20.0)
-    return _chromosphere("cfg3_two_term_doublet", atom, _cfg3_grid(), 12, 8, 80, seed)
+    return _chromosphere("cfg3_two_term_doublet", atom, _cfg3_grid(), 12, 8, n_z, seed)
 
 
-def cfg4(seed: int = 4) -> Problem:
+def cfg4(seed: int = 4, n_z: int = 100) -> Problem:
     """Two-term H I Ly-alpha-like line (fine structure 0.3 Doppler widths), wide
-    damping, N_z=100, N_nu=301 on a sinh grid to +-1000, 8+8 mu x 8 chi."""
+    damping, N_z=100, N_nu=301 on a sinh grid to +-1000, 8+8 mu x 8 chi.
+    n_z < 100 gives the same generator on fewer heights."""
     atom = two_term_atom(1215.67, 1.008, 0.3)
     s = np.linspace(-1.0, 1.0, 301)
     x = 1000.0 * np.sinh(6.0 * s) / np.sinh(6.0)
-    return _chromosphere("cfg4_two_term_wide_wings", atom, x, 16, 8, 100, seed,
+    return _chromosphere("cfg4_two_term_wide_wings", atom, x, 16, 8, n_z, seed,
                          a_range=(1e-2, 1e-1), B_range=(1.0, 300.0))
 
 
