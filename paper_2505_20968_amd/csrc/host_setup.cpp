@@ -483,16 +483,18 @@ static void angular_setup(Problem& P, std::vector<double>& dirs, std::vector<dou
   // each class runs with its own number of column tiles
   for (int pi = 0; pi < 2; ++pi) {
     const int cg = pi == 0 ? 16 : 32;
-    P.cgrp[pi][0].clear();
-    P.cgrp[pi][1].clear();
+    std::vector<int> wide, narrow;
     for (int t = 0; t < P.nth; ++t)
       for (int s0 = P.slot_off[t]; s0 < P.slot_off[t + 1]; s0 += cg) {
         const int cnt = std::min(cg, P.slot_off[t + 1] - s0);
-        auto& dst = P.cgrp[pi][(pi == 1 && cnt > 16) ? 1 : 0];
+        auto& dst = cnt > 16 ? wide : narrow;
         dst.push_back(t);
         dst.push_back(s0);
         dst.push_back(cnt);
       }
+    P.cgrp_n8[pi] = static_cast<int>(wide.size() / 3);
+    P.cgrp[pi] = wide;
+    P.cgrp[pi].insert(P.cgrp[pi].end(), narrow.begin(), narrow.end());
   }
   // a group holds at most sg slots of one theta and at most 2 sg pairs
   for (int pi = 0; pi < 2; ++pi) {
@@ -716,8 +718,7 @@ int build_problem(trap_ctx* ctx, const trap_atom_desc* at, const trap_problem_de
   TRAP_TRY(upload_t(ctx, &P.d_pair_index, P.pair_index));
   TRAP_TRY(upload_t(ctx, &P.d_grp[0], P.grp[0]));
   TRAP_TRY(upload_t(ctx, &P.d_grp[1], P.grp[1]));
-  for (int pi = 0; pi < 2; ++pi)
-    for (int c = 0; c < 2; ++c) TRAP_TRY(upload_t(ctx, &P.d_cgrp[pi][c], P.cgrp[pi][c]));
+  for (int pi = 0; pi < 2; ++pi) TRAP_TRY(upload_t(ctx, &P.d_cgrp[pi], P.cgrp[pi]));
   TRAP_TRY(upload_t(ctx, &P.d_E, E));
   TRAP_TRY(upload_t(ctx, &P.d_A, A));
   TRAP_TRY(upload_t(ctx, &P.d_alpha, alpha));

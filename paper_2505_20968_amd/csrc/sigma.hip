@@ -159,11 +159,10 @@ template <> struct ContractCfg<float> { static constexpr int BST = 136; };   // 
 template <> struct ContractCfg<double> { static constexpr int BST = 72; };   // 64 columns + pad
 
 template <typename T, int NH, int NCT>
-__global__ void __launch_bounds__(512, 2) k_contract(int z0, int nth, int nt, int nn, int ldm, int nd, int nkc,
-                                                     const T* __restrict__ M, const T* __restrict__ Ibar,
-                                                     const int* __restrict__ cgrp,
-                                                     const int* __restrict__ slot_dir, T* __restrict__ W,
-                                                     int nslot) {
+__device__ __forceinline__ void contract_block(int g, int zl, int z0, int nth, int nt, int nn, int ldm, int nd,
+                                               int nkc, const T* __restrict__ M, const T* __restrict__ Ibar,
+                                               const int* __restrict__ cgrp, const int* __restrict__ slot_dir,
+                                               T* __restrict__ W, int nslot, T* Bs) {
   using Op = MfmaOp<T>;
   using acc_t = typename Op::acc_t;
   using V4 = typename Vec4<T>::type;
@@ -171,11 +170,7 @@ __global__ void __launch_bounds__(512, 2) k_contract(int z0, int nth, int nt, in
   constexpr int KCH = 8 * NH;
   constexpr int BST = ContractCfg<T>::BST;
   constexpr int CG = 4 * NCT;                       // slots per column group
-  extern __shared__ __align__(16) unsigned char csh[];
-  T* Bs = reinterpret_cast<T*>(csh);
-  const int g = blockIdx.y;
   const int th = cgrp[3 * g], s0 = cgrp[3 * g + 1], cnt = cgrp[3 * g + 2];
-  const int zl = blockIdx.z;
   const int z = z0 + zl;
   const int R = 2 * nt * nn;
   const int row0 = blockIdx.x * kRowsPerBlock;
@@ -251,27 +246,51 @@ __global__ void __launch_bounds__(512, 2) k_contract(int z0, int nth, int nt, in
   }
 }
 
+
+// One launch covers both column classes: groups [0, n8) have up to 32 slots
+// (8 column tiles, FP32 only), groups [n8, ngrp) up to 16 (4 tiles); the wider
+// groups come first in the dispatch order (the group index is the slowest grid
+// dimension).
+template <typename T, int NH>
+__global__ void __launch_bounds__(512, 2) k_contract(int z0, int nth, int nt, int nn, int ldm, int nd, int nkc,
+                                                     const T* __restrict__ M, const T* __restrict__ Ibar,
+                                                     const int* __restrict__ cgrp, int n8,
+                                                     const int* __restrict__ slot_dir, T* __restrict__ W,
+                                                     int nslot) {
+  extern __shared__ __align__(16) unsigned char csh[];
+  T* Bs = reinterpret_cast<T*>(csh);
+  const int g = blockIdx.z, zl = blockIdx.y;
+  if constexpr (sizeof(T) == sizeof(float)) {
+    if (g < n8) {
+      contract_block<T, NH, 8>(g, zl, z0, nth, nt, nn, ldm, nd, nkc, M, Ibar, cgrp, slot_dir, W, nslot, Bs);
+      return;
+    }
+  }
+  contract_block<T, NH, 4>(g, zl, z0, nth, nt, nn, ldm, nd, nkc, M, Ibar, cgrp, slot_dir, W, nslot, Bs);
+}
+
 // chunking of K: the fewest chunks of at most 128 columns, NH = chunk / 8
 static void contract_chunks(int ldm, int* nkc, int* nh) {
   *nkc = (ldm + 127) / 128;
   *nh = (ldm + 8 * *nkc - 1) / (8 * *nkc);
 }
 
-template <typename T, int NCT>
-static int launch_contract_nct(trap_ctx* ctx, int zc, int z0, const T* Mk, const T* Ibar, T* W, int cls) {
+template <typename T>
+static int launch_contract(trap_ctx* ctx, int zc, int z0, const T* Mk, const T* Ibar, T* W) {
   Problem& P = ctx->pb;
   const int pi = sizeof(T) == 8 ? 0 : 1;
-  const int ngrp = (int)P.cgrp[pi][cls].size() / 3;
+  const int ngrp = (int)P.cgrp[pi].size() / 3;
   if (ngrp == 0) return TRAP_OK;
   int nkc, nh;
   contract_chunks(P.ldm, &nkc, &nh);
   const size_t lds = (size_t)8 * nh * ContractCfg<T>::BST * sizeof(T);
-  dim3 grid(ceil_div(2LL * P.nt * P.nn, kRowsPerBlock), ngrp, zc);
+  dim3 grid(ceil_div(2LL * P.nt * P.nn, kRowsPerBlock), zc, ngrp);
+  const int n8 = P.cgrp_n8[pi];
   switch (nh) {
 #define TRAP_CONTRACT_CASE(NHV)                                                                               \
   case NHV:                                                                                                   \
-    hipLaunchKernelGGL((k_contract<T, NHV, NCT>), grid, dim3(512), lds, ctx->stream, z0, P.nth, P.nt, P.nn,     \
-                       P.ldm, P.nd, nkc, Mk, Ibar, P.d_cgrp[pi][cls], P.d_slot_dir, W, P.nslot);              \
+    hipLaunchKernelGGL((k_contract<T, NHV>), grid, dim3(512), lds, ctx->stream, z0, P.nth, P.nt, P.nn, P.ldm,  \
+                       P.nd, nkc, Mk, Ibar, P.d_cgrp[pi], n8, P.d_slot_dir, W, P.nslot);                     \
     break;
     TRAP_CONTRACT_CASE(1) TRAP_CONTRACT_CASE(2) TRAP_CONTRACT_CASE(3) TRAP_CONTRACT_CASE(4)
     TRAP_CONTRACT_CASE(5) TRAP_CONTRACT_CASE(6) TRAP_CONTRACT_CASE(7) TRAP_CONTRACT_CASE(8)
@@ -282,13 +301,6 @@ static int launch_contract_nct(trap_ctx* ctx, int zc, int z0, const T* Mk, const
       return fail(TRAP_EINVAL, "internal: bad contraction chunk");
   }
   TRAP_HIP(hipGetLastError());
-  return TRAP_OK;
-}
-
-template <typename T>
-static int launch_contract(trap_ctx* ctx, int zc, int z0, const T* Mk, const T* Ibar, T* W) {
-  TRAP_TRY((launch_contract_nct<T, 4>(ctx, zc, z0, Mk, Ibar, W, 0)));
-  if (sizeof(T) == sizeof(float)) TRAP_TRY((launch_contract_nct<T, 8>(ctx, zc, z0, Mk, Ibar, W, 1)));
   return TRAP_OK;
 }
 

@@ -84,9 +84,10 @@ struct Problem {
   // slot groups for the fused Sigma kernel: {theta, first slot, slot count}
   std::vector<int> grp[2];                 // [0] FP64 (8 slots), [1] FP32 (16 slots)
   int grp_maxpairs[2] = {0, 0};            // most pairs in one group
-  // column groups of the R_II contraction {theta, first slot, slot count}:
-  // [precision][class]; FP64: <= 16 slots (class 0); FP32: <= 16 (class 0) or 17..32 (class 1)
-  std::vector<int> cgrp[2][2];
+  // column groups of the R_II contraction {theta, first slot, slot count} per
+  // precision: FP64 <= 16 slots; FP32 <= 32, the cgrp_n8 groups of 17..32 slots first
+  std::vector<int> cgrp[2];
+  int cgrp_n8[2] = {0, 0};
   // device copies
   double *d_x = nullptr, *d_P = nullptr, *d_mu = nullptr, *d_w = nullptr, *d_tau = nullptr;
   double *d_Sig = nullptr;                 // [nn][nn] second-derivative map of the spline
@@ -101,7 +102,7 @@ struct Problem {
   int *d_slot_theta = nullptr, *d_slot_dir = nullptr, *d_slot_off = nullptr, *d_pair_slot = nullptr;
   int *d_pair_off = nullptr, *d_pair_o = nullptr, *d_pair_dir = nullptr, *d_pair_index = nullptr;
   int *d_grp[2] = {nullptr, nullptr};
-  int *d_cgrp[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+  int *d_cgrp[2] = {nullptr, nullptr};
   double2 *d_E = nullptr, *d_A = nullptr;  // see above
   double2 *d_alpha = nullptr, *d_bma = nullptr; // [nz][nu][nu]
   double *d_g = nullptr;                   // [nz][nt][nd][4] geometric factors of K
