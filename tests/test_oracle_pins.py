@@ -485,3 +485,68 @@ def test_aa_differs_from_ad_for_an_anisotropic_field():
     ad = T.sigma_apply(T.setup(p, {"normalize": False}), I, normalize=False)
     aa = T.sigma_apply(T.setup(p, {"normalize": False, "aa": True}), I, normalize=False)
     assert np.abs(aa - ad).max() > 1e-3 * np.abs(ad).max()
+
+
+# ---------------------------------------------------------------- limits the transfer problem fixes
+
+def _unpolarisable_atom():
+    """J_l = 1/2 -> J_u = 1/2: no alignment can be carried (W_2 = 0)."""
+    import dataclasses
+    return dataclasses.replace(two_level_atom(), J_l=0.5, J_u=0.5, g_l=2.0, g_u=2.0 / 3.0)
+
+
+def test_unpolarisable_line_scatters_no_polarisation():
+    """Unpolarised limit: for a J 1/2 -> 1/2 line without a magnetic field the
+    scattered radiation from any unpolarised, anisotropic, frequency-dependent
+    field has Q = U = V = 0, and so has the solution."""
+    p = tiny(n_z=3, n_nu=11, x_max=5, n_mu=4, n_chi=4, B=(0.0, 0.0, 0.0), a=1e-2, eps=3e-2,
+             atom=_unpolarisable_atom())
+    op = T.setup(p)
+    rng = np.random.default_rng(1)
+    I = np.zeros((p.n_z, p.n_dir, p.n_nu, 4))
+    I[..., 0] = rng.random(I.shape[:-1])
+    e = T.sigma_apply(op, I)
+    assert np.abs(e[..., 1:]).max() < 1e-14 * np.abs(e[..., 0]).max()
+    sol = T.solve(op, tol=1e-12)
+    assert np.abs(sol[..., 1:]).max() < 1e-13 * np.abs(sol[..., 0]).max()
+
+
+def _flux_above(nz, nn):
+    p = tiny(n_z=nz, n_nu=nn, x_max=8, n_mu=4, n_chi=2, B=(0.0, 0.0, 0.0), a=1e-3, eps=1e-9,
+             tau_top=1e-3, tau_bot=1e2, atom=_unpolarisable_atom())
+    op = T.setup(p)
+    I = T.solve(op, tol=1e-12)
+    wx = np.full(p.n_nu, p.x[1] - p.x[0])
+    wx[[0, -1]] *= 0.5
+    F = np.einsum("o,o,zon,n->z", op.ang["w"], op.ang["mu"], I[..., 0], wx)
+    top = nz // 2                                   # heights above the bottom boundary layer
+    return np.abs(F[top:] / F[-1] - 1.0).max()
+
+
+def test_pure_scattering_conserves_flux():
+    """Energy conservation: with no photon destruction and no thermal source
+    the frequency- and angle-integrated net flux is constant in height up to
+    discretisation error, which falls when the grids are refined (above the
+    boundary layer at the illuminated bottom)."""
+    coarse, fine = _flux_above(8, 21), _flux_above(16, 41)
+    assert fine < 1e-4
+    assert fine < 0.5 * coarse
+
+
+def test_sqrt_eps_law_for_complete_redistribution():
+    """Semi-infinite isothermal atmosphere, constant destruction probability,
+    complete redistribution (alpha = 0, an unpolarisable line): the surface
+    source function tends to sqrt(eps) B; the error falls under depth-grid
+    refinement."""
+    errs = []
+    for nz in (24, 40):
+        p = tiny(n_z=nz, n_nu=13, x_max=4.0, n_mu=4, n_chi=1, B=(0.0, 0.0, 0.0), a=1e-3, eps=0.04,
+                 tau_top=1e-4, tau_bot=1e4, atom=_unpolarisable_atom())
+        op = T.setup(p, {"alpha_zero": True})
+        I = T.solve(op, tol=1e-12)
+        e = T.sigma_apply(op, I) + op.eps_th
+        S = e[-1, :, :, 0] / op.K[-1, :, :, 0, 0]
+        assert np.ptp(S) < 1e-10 * S.mean()          # CRD: frequency- and angle-independent
+        errs.append(abs(S.mean() / np.sqrt(0.04) - 1.0))
+    assert errs[1] < 0.05
+    assert errs[1] < errs[0] / 1.8
