@@ -125,6 +125,7 @@ typedef struct {
   int inner_iters;
   int applies_fp64;
   int applies_fp32;
+  int applies_grouped;    /* FP32 applies made in launches shared with other contexts */
   double final_rel_res;   /* FP64 true residual at exit */
   double ms_total;
 } trap_solve_stats;
@@ -185,8 +186,14 @@ int trap_gmres_solve(trap_ctx* ctx, const trap_solve_opts* opts, double* I, trap
  * may stay in the batch (they are skipped).
  * trap_gmres_end returns the final status and statistics of a finished solve
  * (TRAP_ESTATE while it is still running).
+ * Contexts of one device whose step applies the FP32 operator, whose
+ * problem fits in one height chunk and that do not record stage times share
+ * the launches of that apply: each stage of the operator is one launch over
+ * all of them, on a stream the library keeps per device (ordered after each
+ * context's earlier work and before its later work through events).
  * The arithmetic of a context does not depend on the other contexts of the
- * batch: a request's solution is the same alone and in any mix. */
+ * batch: each block of a shared launch runs the single-context code on one
+ * context's data, so a request's solution is the same alone and in any mix. */
 int trap_gmres_begin(trap_ctx* ctx, const trap_solve_opts* opts, double* I);
 int trap_gmres_step_batch(trap_ctx** ctxs, int n, int* status);
 int trap_gmres_end(trap_ctx* ctx, trap_solve_stats* stats);

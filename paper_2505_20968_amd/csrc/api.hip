@@ -138,6 +138,7 @@ int trap_create(trap_ctx** out, int device, void* stream) {
     ctx->max_lds = std::min(lds, 160 * 1024);
   else
     (void)hipGetLastError();
+  batch_arena_acquire(device);
   *out = ctx;
   return TRAP_OK;
 }
@@ -147,6 +148,7 @@ int trap_destroy(trap_ctx* ctx) {
   DeviceGuard g(ctx->device);
   prof_clear(ctx, true);
   free_all(ctx);
+  batch_arena_release(ctx->device);
   delete ctx;
   return TRAP_OK;
 }

@@ -80,11 +80,11 @@ __device__ inline void delo_solve(const T* k, T p, const T* b, T* xout) {
 }
 
 template <typename T>
-__global__ void k_formal(int nz, int nd, int nn, const double* __restrict__ mu,
-                         const double* __restrict__ tau, const double* __restrict__ K8,
-                         const double* __restrict__ WT, const T* __restrict__ eps, T* __restrict__ I,
-                         int with_boundary) {
-  const int id = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void formal_body(int bx, int nz, int nd, int nn, const double* __restrict__ mu,
+                                            const double* __restrict__ tau, const double* __restrict__ K8,
+                                            const double* __restrict__ WT, const T* __restrict__ eps,
+                                            T* __restrict__ I, int with_boundary) {
+  const int id = bx * blockDim.x + threadIdx.x;
   if (id >= nd * nn) return;
   const int o = id / nn, n = id % nn;
   const double m = mu[o];
@@ -132,6 +132,31 @@ __global__ void k_formal(int nz, int nd, int nn, const double* __restrict__ mu,
     ru = rc;
     z = zc;
   }
+}
+
+template <typename T>
+__global__ void k_formal(int nz, int nd, int nn, const double* __restrict__ mu,
+                         const double* __restrict__ tau, const double* __restrict__ K8,
+                         const double* __restrict__ WT, const T* __restrict__ eps, T* __restrict__ I,
+                         int with_boundary) {
+  formal_body<T>(blockIdx.x, nz, nd, nn, mu, tau, K8, WT, eps, I, with_boundary);
+}
+
+// one launch over several contexts: block b is context r's block b - off[r]
+__global__ void k_formal_grouped(const GFormal* __restrict__ A, const int* __restrict__ off, int n) {
+  int lo = 0, hi = n;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (off[mid] <= (int)blockIdx.x) lo = mid; else hi = mid;
+  }
+  const GFormal& a = A[lo];
+  formal_body<float>(blockIdx.x - off[lo], a.nz, a.nd, a.nn, a.mu, a.tau, a.K8, a.WT, a.eps, a.I, 0);
+}
+
+int launch_formal_grouped(hipStream_t s, const GFormal* args, const int* off, int n, int blocks) {
+  hipLaunchKernelGGL(k_formal_grouped, dim3(blocks), dim3(64), 0, s, args, off, n);
+  TRAP_HIP(hipGetLastError());
+  return TRAP_OK;
 }
 
 int formal_apply(trap_ctx* ctx, const void* eps, void* I, int with_boundary, int prec) {

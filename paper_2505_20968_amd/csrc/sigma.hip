@@ -14,6 +14,9 @@
 // bounded (and cache resident on the 256 MB Infinity Cache for small chunks).
 #include <algorithm>
 #include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
 
 #include "trap_internal.h"
 
@@ -30,16 +33,15 @@ static constexpr double kInvPi = 0.31830988618379067154;
 //   S(x) = (1-t) v_k + t v_{k+1} + h^2 [((1-t)^3 - (1-t)) s_k + (t^3 - t) s_{k+1}] / 6.
 // Optionally multiplies Stokes I by f and adds eps_th.
 template <typename T>
-__global__ void __launch_bounds__(128) k_spline_shift(
-    int nz0, int nzc, int nd, int nn, const double* __restrict__ x, const double* __restrict__ SigT,
+__device__ __forceinline__ void spline_shift_body(
+    int bx, double* spl, int nz0, int nd, int nn, const double* __restrict__ x, const double* __restrict__ SigT,
     const double* __restrict__ lam, const double* __restrict__ ub, double ub_sign,
     const double* __restrict__ sll, int ncls, int cls, const T* __restrict__ in, long long in_z_stride,
     long long in_o_stride, T* __restrict__ out, int accumulate, const double* __restrict__ f,
     const double* __restrict__ epsth) {
-  extern __shared__ double spl[];
   double* v = spl;               // [nn][4]
   double* sd = spl + 4 * nn;     // [nn][4]
-  const int zl = blockIdx.x / nd, o = blockIdx.x % nd;
+  const int zl = bx / nd, o = bx % nd;
   const int z = nz0 + zl;
   const double L = lam[z];
   double sh = ub_sign * ub[(long long)z * nd + o];
@@ -105,6 +107,19 @@ __global__ void __launch_bounds__(128) k_spline_shift(
   }
 }
 
+template <typename T>
+__global__ void __launch_bounds__(128) k_spline_shift(
+    int nz0, int nzc, int nd, int nn, const double* __restrict__ x, const double* __restrict__ SigT,
+    const double* __restrict__ lam, const double* __restrict__ ub, double ub_sign,
+    const double* __restrict__ sll, int ncls, int cls, const T* __restrict__ in, long long in_z_stride,
+    long long in_o_stride, T* __restrict__ out, int accumulate, const double* __restrict__ f,
+    const double* __restrict__ epsth) {
+  extern __shared__ double spl[];
+  (void)nzc;
+  spline_shift_body<T>(blockIdx.x, spl, nz0, nd, nn, x, SigT, lam, ub, ub_sign, sll, ncls, cls, in, in_z_stride,
+                       in_o_stride, out, accumulate, f, epsth);
+}
+
 // ------------------------------------------------------------------ R_II contraction
 // One GEMM per (z, theta) over every transition at once:
 //   C[(t, c, n), (sl, s)] = sum_m M[z][theta][(t, c, n)][m] * Ibar[z][dir(sl)][m][s]
@@ -159,7 +174,7 @@ template <> struct ContractCfg<float> { static constexpr int BST = 136; };   // 
 template <> struct ContractCfg<double> { static constexpr int BST = 72; };   // 64 columns + pad
 
 template <typename T, int NH, int NCT>
-__device__ __forceinline__ void contract_block(int g, int zl, int z0, int nth, int nt, int nn, int ldm, int nd,
+__device__ __forceinline__ void contract_block(int rb, int g, int zl, int z0, int nth, int nt, int nn, int ldm, int nd,
                                                int nkc, const T* __restrict__ M, const T* __restrict__ Ibar,
                                                const int* __restrict__ cgrp, const int* __restrict__ slot_dir,
                                                T* __restrict__ W, int nslot, T* Bs) {
@@ -173,7 +188,7 @@ __device__ __forceinline__ void contract_block(int g, int zl, int z0, int nth, i
   const int th = cgrp[3 * g], s0 = cgrp[3 * g + 1], cnt = cgrp[3 * g + 2];
   const int z = z0 + zl;
   const int R = 2 * nt * nn;
-  const int row0 = blockIdx.x * kRowsPerBlock;
+  const int row0 = rb * kRowsPerBlock;
   const T* Mb = M + ((size_t)z * nth + th) * (size_t)R * ldm;
   const T* Ib = Ibar + (size_t)zl * nd * nn * 4;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -262,11 +277,12 @@ __global__ void __launch_bounds__(512, 2) k_contract(int z0, int nth, int nt, in
   const int g = blockIdx.z, zl = blockIdx.y;
   if constexpr (sizeof(T) == sizeof(float)) {
     if (g < n8) {
-      contract_block<T, NH, 8>(g, zl, z0, nth, nt, nn, ldm, nd, nkc, M, Ibar, cgrp, slot_dir, W, nslot, Bs);
+      contract_block<T, NH, 8>(blockIdx.x, g, zl, z0, nth, nt, nn, ldm, nd, nkc, M, Ibar, cgrp, slot_dir, W, nslot,
+                               Bs);
       return;
     }
   }
-  contract_block<T, NH, 4>(g, zl, z0, nth, nt, nn, ldm, nd, nkc, M, Ibar, cgrp, slot_dir, W, nslot, Bs);
+  contract_block<T, NH, 4>(blockIdx.x, g, zl, z0, nth, nt, nn, ldm, nd, nkc, M, Ibar, cgrp, slot_dir, W, nslot, Bs);
 }
 
 // chunking of K: the fewest chunks of at most 128 columns, NH = chunk / 8
@@ -307,9 +323,10 @@ static int launch_contract(trap_ctx* ctx, int zc, int z0, const T* Mk, const T* 
 // ------------------------------------------------------------------ R_III factors
 // Y[z][t][o][s] = sum_m r3[z][t][m] Ibar[z][o][m][s]
 template <typename T>
-__global__ void k_r3_Y(int z0, int nzc, int nt, int nd, int nn, const double2* __restrict__ r3,
-                       const T* __restrict__ Ibar, double2* __restrict__ Y) {
-  const long long id = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+__device__ __forceinline__ void r3_Y_body(int bx, int z0, int nzc, int nt, int nd, int nn,
+                                          const double2* __restrict__ r3, const T* __restrict__ Ibar,
+                                          double2* __restrict__ Y) {
+  const long long id = bx * (long long)blockDim.x + threadIdx.x;
   const long long total = (long long)nzc * nt * nd * 4;
   if (id >= total) return;
   const int s = id & 3;
@@ -328,11 +345,17 @@ __global__ void k_r3_Y(int z0, int nzc, int nt, int nd, int nn, const double2* _
   Y[(((size_t)z * nt + t) * nd + o) * 4 + s] = make_double2(re, im);
 }
 
+template <typename T>
+__global__ void k_r3_Y(int z0, int nzc, int nt, int nd, int nn, const double2* __restrict__ r3,
+                       const T* __restrict__ Ibar, double2* __restrict__ Y) {
+  r3_Y_body<T>(blockIdx.x, z0, nzc, nt, nd, nn, r3, Ibar, Y);
+}
+
 // X[z][u][u'][l] = sum_o' w_o' sum_j A[z][o'][j][u][u'][l] (Y[(u',l)][o'][j] + conj Y[(u,l)][o'][j])
-__global__ void k_r3_X(int z0, int nu, int nl, int nd, const double* __restrict__ w,
-                       const double2* __restrict__ A, const double2* __restrict__ Y,
-                       double2* __restrict__ X) {
-  const int e = blockIdx.x;   // (zl, u, up, l)
+__device__ __forceinline__ void r3_X_body(int bx, int z0, int nu, int nl, int nd, const double* __restrict__ w,
+                                          const double2* __restrict__ A, const double2* __restrict__ Y,
+                                          double2* __restrict__ X) {
+  const int e = bx;   // (zl, u, up, l)
   const int l = e % nl;
   const int up = (e / nl) % nu;
   const int u = (e / (nl * nu)) % nu;
@@ -363,6 +386,12 @@ __global__ void k_r3_X(int z0, int nu, int nl, int nd, const double* __restrict_
   if (threadIdx.x == 0) X[((((size_t)z * nu + u) * nu + up) * nl) + l] = make_double2(sr[0], si[0]);
 }
 
+__global__ void k_r3_X(int z0, int nu, int nl, int nd, const double* __restrict__ w,
+                       const double2* __restrict__ A, const double2* __restrict__ Y,
+                       double2* __restrict__ X) {
+  r3_X_body(blockIdx.x, z0, nu, nl, nd, w, A, Y, X);
+}
+
 // ------------------------------------------------------------------ angular / sublevel sum
 // eps_bar[z][l][l'][o][n][i] = sum_{o'} sum_{u'} sum_c sum_j cf[z][p(o,o')][(u',l)][c][l'][i][j]
 //                                  W[z][(u',l)][slot(o,o')][c][n][j]  +  R_III term
@@ -375,20 +404,19 @@ __global__ void k_r3_X(int z0, int nu, int nl, int nd, const double* __restrict_
 constexpr int kAngQ = 4;
 
 template <typename T, int kAngMaxNl>
-__global__ void __launch_bounds__(64 * kAngQ) k_angular(
-    int z0, int nd, int nn, int nu, int nl, int nslot, const int* __restrict__ pair_slot,
-    const int* __restrict__ pair_index, const T* __restrict__ cf, const T* __restrict__ W, double c_sc,
-    const double2* __restrict__ E, const double2* __restrict__ bma, const double2* __restrict__ X,
-    const double2* __restrict__ prof, T* __restrict__ Eb) {
+__device__ __forceinline__ void angular_body(
+    int bx, int by, T (&red)[kAngQ][64][kAngMaxNl][4], int z0, int nd, int nn, int nu, int nl, int nslot,
+    const int* __restrict__ pair_slot, const int* __restrict__ pair_index, const T* __restrict__ cf,
+    const T* __restrict__ W, double c_sc, const double2* __restrict__ E, const double2* __restrict__ bma,
+    const double2* __restrict__ X, const double2* __restrict__ prof, T* __restrict__ Eb) {
   using V4 = typename Vec4<T>::type;
-  __shared__ T red[kAngQ][64][kAngMaxNl][4];
-  const int zl = blockIdx.x / nd, o = blockIdx.x % nd;
+  const int zl = bx / nd, o = bx % nd;
   const int z = z0 + zl;
   const int nt = nu * nl;
   const int np = nd * nd;
   const int lane = threadIdx.x & 63;
   const int q = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int n = blockIdx.y * 64 + lane;
+  const int n = by * 64 + lane;
   const bool live = n < nn;
   const int nc = min(n, nn - 1);
   const size_t pstride = (size_t)nt * 2 * nl * 16;
@@ -458,6 +486,17 @@ __global__ void __launch_bounds__(64 * kAngQ) k_angular(
       }
     }
   }
+}
+
+template <typename T, int kAngMaxNl>
+__global__ void __launch_bounds__(64 * kAngQ) k_angular(
+    int z0, int nd, int nn, int nu, int nl, int nslot, const int* __restrict__ pair_slot,
+    const int* __restrict__ pair_index, const T* __restrict__ cf, const T* __restrict__ W, double c_sc,
+    const double2* __restrict__ E, const double2* __restrict__ bma, const double2* __restrict__ X,
+    const double2* __restrict__ prof, T* __restrict__ Eb) {
+  __shared__ T red[kAngQ][64][kAngMaxNl][4];
+  angular_body<T, kAngMaxNl>(blockIdx.x, blockIdx.y, red, z0, nd, nn, nu, nl, nslot, pair_slot, pair_index, cf,
+                             W, c_sc, E, bma, X, prof, Eb);
 }
 
 // ------------------------------------------------------------------ fused R_II contraction + angular sum
@@ -965,6 +1004,443 @@ int sigma_apply(trap_ctx* ctx, const void* I, void* eps, int prec, int add_therm
   if (!ctx->pre.d_M32) return fail(TRAP_ESTATE, "FP32 kernels not stored (store_mask bit 1)");
   return sigma_apply_t<float>(ctx, static_cast<const float*>(I), static_cast<float*>(eps), prec,
                               add_thermal, normalize, ctx->pre.d_M32);
+}
+
+}  // namespace trap
+
+// ------------------------------------------------------------------ grouped launches across contexts
+// A serving step applies the FP32 operator of many contexts (requests) at
+// once: each stage below is one launch whose blocks cover every context's
+// work, with the same per-block code as the single-context kernels above, so a
+// context's result does not depend on the others in the launch.  Block b
+// belongs to context r with off[r] <= b < off[r + 1]; the context's sizes and
+// pointers come from an argument record in device memory.
+
+namespace trap {
+
+__device__ __forceinline__ int find_req(int b, const int* __restrict__ off, int n) {
+  int lo = 0, hi = n;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (off[mid] <= b) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+__global__ void __launch_bounds__(128) k_spline_shift_grouped(const GSpline* __restrict__ A,
+                                                              const int* __restrict__ off, int n) {
+  extern __shared__ double spl[];
+  const int r = find_req(blockIdx.x, off, n);
+  const GSpline& a = A[r];
+  spline_shift_body<float>(blockIdx.x - off[r], spl, a.nz0, a.nd, a.nn, a.x, a.SigT, a.lam, a.ub, a.ub_sign, a.sll,
+                           a.ncls, a.cls, a.in, a.in_z_stride, a.in_o_stride, a.out, a.accumulate, a.f, a.epsth);
+}
+
+__global__ void __launch_bounds__(256) k_r3_Y_grouped(const GR3Y* __restrict__ A, const int* __restrict__ off,
+                                                      int n) {
+  const int r = find_req(blockIdx.x, off, n);
+  const GR3Y& a = A[r];
+  r3_Y_body<float>(blockIdx.x - off[r], a.z0, a.nzc, a.nt, a.nd, a.nn, a.r3, a.Ibar, a.Y);
+}
+
+__global__ void __launch_bounds__(256) k_r3_X_grouped(const GR3X* __restrict__ A, const int* __restrict__ off,
+                                                      int n) {
+  const int r = find_req(blockIdx.x, off, n);
+  const GR3X& a = A[r];
+  r3_X_body(blockIdx.x - off[r], a.z0, a.nu, a.nl, a.nd, a.w, a.A, a.Y, a.X);
+}
+
+template <int NH>
+__global__ void __launch_bounds__(512, 2) k_contract_grouped(const GContract* __restrict__ A,
+                                                             const int* __restrict__ off, int n) {
+  extern __shared__ __align__(16) unsigned char csh[];
+  float* Bs = reinterpret_cast<float*>(csh);
+  const int r = find_req(blockIdx.x, off, n);
+  const GContract& a = A[r];
+  const int local = blockIdx.x - off[r];
+  const int rb = local % a.rb_n, rest = local / a.rb_n;
+  const int zl = rest % a.zc, g = rest / a.zc;     // column group slowest, as in k_contract
+  if (g < a.n8)
+    contract_block<float, NH, 8>(rb, g, zl, a.z0, a.nth, a.nt, a.nn, a.ldm, a.nd, a.nkc, a.M, a.Ibar, a.cgrp,
+                                 a.slot_dir, a.W, a.nslot, Bs);
+  else
+    contract_block<float, NH, 4>(rb, g, zl, a.z0, a.nth, a.nt, a.nn, a.ldm, a.nd, a.nkc, a.M, a.Ibar, a.cgrp,
+                                 a.slot_dir, a.W, a.nslot, Bs);
+}
+
+template <int NLM>
+__global__ void __launch_bounds__(64 * kAngQ) k_angular_grouped(const GAngular* __restrict__ A,
+                                                                const int* __restrict__ off, int n) {
+  __shared__ float red[kAngQ][64][NLM][4];
+  const int r = find_req(blockIdx.x, off, n);
+  const GAngular& a = A[r];
+  const int local = blockIdx.x - off[r];
+  angular_body<float, NLM>(local % a.nbx, local / a.nbx, red, a.z0, a.nd, a.nn, a.nu, a.nl, a.nslot, a.pair_slot,
+                           a.pair_index, a.cf, a.W, a.c_sc, a.E, a.bma, a.X, a.prof, a.Eb);
+}
+
+// x32 = (float) x64 (the conversion of the single-context path)
+__global__ void __launch_bounds__(256) k_to_f32_grouped(const GVec* __restrict__ A, const int* __restrict__ off,
+                                                        int n) {
+  const int r = find_req(blockIdx.x, off, n);
+  const GVec& a = A[r];
+  for (long long i = (blockIdx.x - off[r]) * 256LL + threadIdx.x; i < a.N; i += (long long)a.nb * 256)
+    a.x32[i] = (float)a.x64[i];
+}
+
+// y64 = (double)(x32 - f32): the FP32 difference, then the exact widening
+__global__ void __launch_bounds__(256) k_finish_grouped(const GVec* __restrict__ A, const int* __restrict__ off,
+                                                        int n) {
+  const int r = find_req(blockIdx.x, off, n);
+  const GVec& a = A[r];
+  for (long long i = (blockIdx.x - off[r]) * 256LL + threadIdx.x; i < a.N; i += (long long)a.nb * 256) {
+    const float d = a.x32[i] - a.f32[i];
+    a.y64[i] = (double)d;
+  }
+}
+
+// ---- per-device arena
+namespace {
+
+std::mutex g_arena_mu;
+std::map<int, BatchArena> g_arena;
+
+void arena_free(BatchArena& a) {
+  if (a.stream) (void)hipStreamSynchronize(a.stream);
+  for (hipEvent_t e : a.ev) (void)hipEventDestroy(e);
+  a.ev.clear();
+  if (a.copied) (void)hipEventDestroy(a.copied);
+  if (a.done) (void)hipEventDestroy(a.done);
+  if (a.host) (void)hipHostFree(a.host);
+  if (a.dev) (void)hipFree(a.dev);
+  if (a.stream) (void)hipStreamDestroy(a.stream);
+  a = BatchArena();
+}
+
+// stream, events and a staging buffer of at least `bytes` (device current)
+int arena_ready(BatchArena& a, size_t bytes, int nev) {
+  if (!a.stream) {
+    TRAP_HIP(hipStreamCreateWithFlags(&a.stream, hipStreamNonBlocking));
+    TRAP_HIP(hipEventCreateWithFlags(&a.copied, hipEventDisableTiming));
+    TRAP_HIP(hipEventCreateWithFlags(&a.done, hipEventDisableTiming));
+  }
+  while ((int)a.ev.size() < nev) {
+    hipEvent_t e;
+    TRAP_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    a.ev.push_back(e);
+  }
+  // the previous batch's upload must have left the staging buffer
+  TRAP_HIP(hipEventSynchronize(a.copied));
+  if (a.cap < bytes) {
+    if (a.host) TRAP_HIP(hipHostFree(a.host));
+    a.host = nullptr;
+    if (a.dev) {
+      TRAP_HIP(hipStreamSynchronize(a.stream));
+      TRAP_HIP(hipFree(a.dev));
+    }
+    a.dev = nullptr;
+    a.cap = 0;
+    const size_t cap = std::max<size_t>(bytes, 64 << 10);
+    TRAP_HIP(hipHostMalloc(reinterpret_cast<void**>(&a.host), cap));
+    const hipError_t e = hipMalloc(&a.dev, cap);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(TRAP_ENOMEM, "device allocation of the batch argument buffer failed");
+    }
+    a.cap = cap;
+  }
+  return TRAP_OK;
+}
+
+struct Blob {
+  std::vector<unsigned char> h;
+  template <typename S>
+  size_t put(const std::vector<S>& v) {
+    const size_t at = (h.size() + 63) & ~size_t(63);
+    h.resize(at + std::max<size_t>(1, v.size()) * sizeof(S));
+    if (!v.empty()) std::memcpy(h.data() + at, v.data(), v.size() * sizeof(S));
+    return at;
+  }
+};
+
+enum StageKind { SK_TO32, SK_SPLINE, SK_R3Y, SK_R3X, SK_CONTRACT, SK_ANGULAR, SK_COPY, SK_FORMAL, SK_FINISH };
+
+struct Stage {
+  int kind;
+  int cls;            // NH of the contraction, sublevel class of the angular sum
+  size_t args, off;   // blob offsets of the records and of the block offsets
+  int n, blocks;
+  size_t lds;
+};
+
+int nl_class(int nl) { return nl == 1 ? 1 : nl == 2 ? 2 : nl <= 4 ? 4 : 8; }
+
+}  // namespace
+
+void batch_arena_acquire(int device) {
+  std::lock_guard<std::mutex> lk(g_arena_mu);
+  g_arena[device].users++;
+}
+
+void batch_arena_release(int device) {
+  std::lock_guard<std::mutex> lk(g_arena_mu);
+  auto it = g_arena.find(device);
+  if (it == g_arena.end()) return;
+  if (--it->second.users > 0) return;
+  arena_free(it->second);
+  g_arena.erase(it);
+}
+
+int sigma_batch_ready(trap_ctx* ctx) {
+  Problem& P = ctx->pb;
+  Work& K = ctx->wk;
+  if (!ctx->has_problem || !ctx->pre.done || !ctx->pre.d_M32 || !ctx->pre.d_cf32) return 0;
+  if (ctx->path == TRAP_PATH_FUSED || ctx->prof.on) return 0;
+  if (K.zchunk < P.nz) return 0;
+  TRAP_TRY(ensure_work(ctx, TRAP_FP32));
+  if (!K.W[1]) TRAP_TRY(dalloc(ctx, &K.W[1], (size_t)K.zchunk * P.nt * P.nslot * 2 * P.nn * 4 * sizeof(float)));
+  return (K.v32a && K.v32b) ? 1 : 0;
+}
+
+int op_apply_batch_f32(trap_ctx** ctxs, int n, const double* const* x, double* const* y) {
+  if (n <= 0) return TRAP_OK;
+  const int device = ctxs[0]->device;
+  Blob blob;
+  std::vector<Stage> stages;
+  auto add_stage = [&](int kind, int cls, size_t args, const std::vector<int>& cnt, size_t lds) {
+    std::vector<int> off(cnt.size() + 1, 0);
+    for (size_t i = 0; i < cnt.size(); ++i) off[i + 1] = off[i] + cnt[i];
+    if (off.back() == 0) return;
+    stages.push_back(Stage{kind, cls, args, blob.put(off), (int)cnt.size(), off.back(), lds});
+  };
+  auto spl_lds = [](const Problem& P) { return (size_t)8 * P.nn * sizeof(double); };
+  // 0. operands to FP32
+  std::vector<GVec> vec;
+  std::vector<int> vcnt;
+  for (int i = 0; i < n; ++i) {
+    const Problem& P = ctxs[i]->pb;
+    const long long N = 4LL * P.nz * P.nd * P.nn;
+    const int nb = std::min(ceil_div(N, 256), 1024);
+    vec.push_back(GVec{N, nb, x[i], ctxs[i]->wk.v32a, nullptr,
+                       y[i]});
+    vcnt.push_back(nb);
+  }
+  const size_t vec_at = blob.put(vec);
+  add_stage(SK_TO32, 0, vec_at, vcnt, 0);
+  // 1. comoving interpolation, every height
+  {
+    std::vector<GSpline> a;
+    std::vector<int> cnt;
+    size_t lds = 0;
+    for (int i = 0; i < n; ++i) {
+      const Problem& P = ctxs[i]->pb;
+      a.push_back(GSpline{0, P.nd, P.nn, P.d_x, P.d_SigT, P.d_lam, P.d_ub, -1.0, nullptr, 1, 0, ctxs[i]->wk.v32a,
+                          (long long)P.nd * P.nn * 4, (long long)P.nn * 4, static_cast<float*>(ctxs[i]->wk.Ibar[1]),
+                          0, nullptr, nullptr});
+      cnt.push_back(P.nz * P.nd);
+      lds = std::max(lds, spl_lds(P));
+    }
+    add_stage(SK_SPLINE, 0, blob.put(a), cnt, lds);
+  }
+  // 2. R_III incoming factors
+  {
+    std::vector<GR3Y> ay;
+    std::vector<GR3X> ax;
+    std::vector<int> cy, cx;
+    for (int i = 0; i < n; ++i) {
+      const Problem& P = ctxs[i]->pb;
+      Work& K = ctxs[i]->wk;
+      ay.push_back(GR3Y{0, P.nz, P.nt, P.nd, P.nn, ctxs[i]->pre.d_r3, static_cast<const float*>(K.Ibar[1]), K.Y});
+      ax.push_back(GR3X{0, P.nu, P.nl, P.nd, P.d_w, P.d_A, K.Y, K.X});
+      cy.push_back(ceil_div((long long)P.nz * P.nt * P.nd * 4, 256));
+      cx.push_back(P.nz * P.nu * P.nu * P.nl);
+    }
+    add_stage(SK_R3Y, 0, blob.put(ay), cy, 0);
+    add_stage(SK_R3X, 0, blob.put(ax), cx, 0);
+  }
+  // 3. R_II contraction, one launch per K-chunk class
+  {
+    std::map<int, std::vector<int>> by_nh;
+    for (int i = 0; i < n; ++i) {
+      int nkc, nh;
+      contract_chunks(ctxs[i]->pb.ldm, &nkc, &nh);
+      by_nh[nh].push_back(i);
+    }
+    for (auto& kv : by_nh) {
+      std::vector<GContract> a;
+      std::vector<int> cnt;
+      for (int i : kv.second) {
+        const Problem& P = ctxs[i]->pb;
+        int nkc, nh;
+        contract_chunks(P.ldm, &nkc, &nh);
+        const int rb_n = ceil_div(2LL * P.nt * P.nn, kRowsPerBlock);
+        const int ngrp = (int)P.cgrp[1].size() / 3;
+        a.push_back(GContract{0, P.nth, P.nt, P.nn, P.ldm, P.nd, nkc, P.cgrp_n8[1], P.nslot, rb_n, P.nz,
+                              ctxs[i]->pre.d_M32, static_cast<const float*>(ctxs[i]->wk.Ibar[1]), P.d_cgrp[1],
+                              P.d_slot_dir, static_cast<float*>(ctxs[i]->wk.W[1])});
+        cnt.push_back(rb_n * P.nz * ngrp);
+      }
+      add_stage(SK_CONTRACT, kv.first, blob.put(a), cnt,
+                (size_t)8 * kv.first * ContractCfg<float>::BST * sizeof(float));
+    }
+  }
+  // 4. angular / sublevel sum, one launch per sublevel class
+  {
+    std::map<int, std::vector<int>> by_nl;
+    for (int i = 0; i < n; ++i) by_nl[nl_class(ctxs[i]->pb.nl)].push_back(i);
+    for (auto& kv : by_nl) {
+      std::vector<GAngular> a;
+      std::vector<int> cnt;
+      for (int i : kv.second) {
+        const Problem& P = ctxs[i]->pb;
+        Work& K = ctxs[i]->wk;
+        a.push_back(GAngular{0, P.nd, P.nn, P.nu, P.nl, P.nslot, P.nz * P.nd, P.d_pair_slot, P.d_pair_index,
+                             ctxs[i]->pre.d_cf32, static_cast<const float*>(K.W[1]), P.c_sc, P.d_E, P.d_bma, K.X,
+                             ctxs[i]->pre.d_prof, static_cast<float*>(K.Eb[1])});
+        cnt.push_back(P.nz * P.nd * ceil_div(P.nn, 64));
+      }
+      add_stage(SK_ANGULAR, kv.first, blob.put(a), cnt, 0);
+    }
+  }
+  // 5. back to the observer frame, class by class in the single-context order;
+  //    f on Stokes I in the same launch for one class, in a pass of its own over
+  //    a copy for several
+  int maxcls = 0;
+  for (int i = 0; i < n; ++i) maxcls = std::max(maxcls, ctxs[i]->pb.nl * ctxs[i]->pb.nl);
+  for (int c = 0; c < maxcls; ++c) {
+    std::vector<GSpline> a;
+    std::vector<int> cnt;
+    size_t lds = 0;
+    for (int i = 0; i < n; ++i) {
+      const Problem& P = ctxs[i]->pb;
+      const int ncls = P.nl * P.nl;
+      if (c >= ncls) continue;
+      const float* Eb = static_cast<const float*>(ctxs[i]->wk.Eb[1]);
+      a.push_back(GSpline{0, P.nd, P.nn, P.d_x, P.d_SigT, P.d_lam, P.d_ub, 1.0, P.d_sll, ncls, c,
+                          Eb + (size_t)c * P.nd * P.nn * 4, (long long)ncls * P.nd * P.nn * 4, (long long)P.nn * 4,
+                          static_cast<float*>(ctxs[i]->wk.opeps[1]), c == 0 ? 0 : 1,
+                          ncls == 1 ? ctxs[i]->pre.d_f : nullptr, nullptr});
+      cnt.push_back(P.nz * P.nd);
+      lds = std::max(lds, spl_lds(P));
+    }
+    add_stage(SK_SPLINE, 0, blob.put(a), cnt, lds);
+  }
+  {
+    std::vector<GSpline> a;
+    std::vector<int> cnt;
+    size_t lds = 0;
+    for (int i = 0; i < n; ++i) {
+      const Problem& P = ctxs[i]->pb;
+      if (P.nl == 1) continue;
+      a.push_back(GSpline{0, P.nd, P.nn, P.d_x, P.d_SigT, P.d_lam, P.d_ub, 0.0, nullptr, 1, 0,
+                          static_cast<const float*>(ctxs[i]->wk.tmp[1]), (long long)P.nd * P.nn * 4,
+                          (long long)P.nn * 4, static_cast<float*>(ctxs[i]->wk.opeps[1]), 0, ctxs[i]->pre.d_f,
+                          nullptr});
+      cnt.push_back(P.nz * P.nd);
+      lds = std::max(lds, spl_lds(P));
+    }
+    if (!a.empty()) {
+      stages.push_back(Stage{SK_COPY, 0, 0, 0, 0, 0, 0});
+      add_stage(SK_SPLINE, 0, blob.put(a), cnt, lds);
+    }
+  }
+  // 6. formal solution Lambda of the emissivity, then y = x - Lambda Sigma x
+  {
+    std::vector<GFormal> a;
+    std::vector<int> cnt;
+    for (int i = 0; i < n; ++i) {
+      const Problem& P = ctxs[i]->pb;
+      a.push_back(GFormal{P.nz, P.nd, P.nn, P.d_mu, P.d_tau, ctxs[i]->pre.d_K, P.d_WT,
+                          static_cast<const float*>(ctxs[i]->wk.opeps[1]), ctxs[i]->wk.v32b});
+      cnt.push_back(ceil_div((long long)P.nd * P.nn, 64));
+    }
+    add_stage(SK_FORMAL, 0, blob.put(a), cnt, 0);
+  }
+  for (int i = 0; i < n; ++i) vec[i].f32 = ctxs[i]->wk.v32b;
+  add_stage(SK_FINISH, 0, blob.put(vec), vcnt, 0);
+
+  std::lock_guard<std::mutex> lk(g_arena_mu);
+  auto it = g_arena.find(device);
+  if (it == g_arena.end()) return fail(TRAP_ESTATE, "internal: no batch arena for the device");
+  BatchArena& ar = it->second;
+  TRAP_TRY(arena_ready(ar, blob.h.size(), n));
+  // the batch starts after each context's pending work ...
+  for (int i = 0; i < n; ++i) {
+    TRAP_HIP(hipEventRecord(ar.ev[i], ctxs[i]->stream));
+    TRAP_HIP(hipStreamWaitEvent(ar.stream, ar.ev[i], 0));
+  }
+  std::memcpy(ar.host, blob.h.data(), blob.h.size());
+  TRAP_HIP(hipMemcpyAsync(ar.dev, ar.host, blob.h.size(), hipMemcpyHostToDevice, ar.stream));
+  TRAP_HIP(hipEventRecord(ar.copied, ar.stream));
+  const unsigned char* base = static_cast<const unsigned char*>(ar.dev);
+  for (const Stage& st : stages) {
+    const int* off = reinterpret_cast<const int*>(base + st.off);
+    const void* args = base + st.args;
+    switch (st.kind) {
+      case SK_TO32:
+        hipLaunchKernelGGL(k_to_f32_grouped, dim3(st.blocks), dim3(256), 0, ar.stream,
+                           static_cast<const GVec*>(args), off, st.n);
+        break;
+      case SK_FINISH:
+        hipLaunchKernelGGL(k_finish_grouped, dim3(st.blocks), dim3(256), 0, ar.stream,
+                           static_cast<const GVec*>(args), off, st.n);
+        break;
+      case SK_SPLINE:
+        hipLaunchKernelGGL(k_spline_shift_grouped, dim3(st.blocks), dim3(128), st.lds, ar.stream,
+                           static_cast<const GSpline*>(args), off, st.n);
+        break;
+      case SK_R3Y:
+        hipLaunchKernelGGL(k_r3_Y_grouped, dim3(st.blocks), dim3(256), 0, ar.stream,
+                           static_cast<const GR3Y*>(args), off, st.n);
+        break;
+      case SK_R3X:
+        hipLaunchKernelGGL(k_r3_X_grouped, dim3(st.blocks), dim3(256), 0, ar.stream,
+                           static_cast<const GR3X*>(args), off, st.n);
+        break;
+      case SK_CONTRACT: {
+        const GContract* a = static_cast<const GContract*>(args);
+        switch (st.cls) {
+#define TRAP_GCONTRACT_CASE(NHV)                                                                              \
+  case NHV:                                                                                                   \
+    hipLaunchKernelGGL(k_contract_grouped<NHV>, dim3(st.blocks), dim3(512), st.lds, ar.stream, a, off, st.n); \
+    break;
+          TRAP_GCONTRACT_CASE(1) TRAP_GCONTRACT_CASE(2) TRAP_GCONTRACT_CASE(3) TRAP_GCONTRACT_CASE(4)
+          TRAP_GCONTRACT_CASE(5) TRAP_GCONTRACT_CASE(6) TRAP_GCONTRACT_CASE(7) TRAP_GCONTRACT_CASE(8)
+          TRAP_GCONTRACT_CASE(9) TRAP_GCONTRACT_CASE(10) TRAP_GCONTRACT_CASE(11) TRAP_GCONTRACT_CASE(12)
+          TRAP_GCONTRACT_CASE(13) TRAP_GCONTRACT_CASE(14) TRAP_GCONTRACT_CASE(15) TRAP_GCONTRACT_CASE(16)
+#undef TRAP_GCONTRACT_CASE
+          default:
+            return fail(TRAP_EINVAL, "internal: bad contraction chunk");
+        }
+        break;
+      }
+      case SK_ANGULAR: {
+        const GAngular* a = static_cast<const GAngular*>(args);
+        auto kern = st.cls == 1 ? k_angular_grouped<1>
+                  : st.cls == 2 ? k_angular_grouped<2>
+                  : st.cls == 4 ? k_angular_grouped<4> : k_angular_grouped<8>;
+        hipLaunchKernelGGL(kern, dim3(st.blocks), dim3(64 * kAngQ), 0, ar.stream, a, off, st.n);
+        break;
+      }
+      case SK_COPY:
+        for (int i = 0; i < n; ++i) {
+          const Problem& P = ctxs[i]->pb;
+          if (P.nl == 1) continue;
+          TRAP_HIP(hipMemcpyAsync(ctxs[i]->wk.tmp[1], ctxs[i]->wk.opeps[1],
+                                  (size_t)4 * P.nz * P.nd * P.nn * sizeof(float), hipMemcpyDeviceToDevice,
+                                  ar.stream));
+        }
+        break;
+      case SK_FORMAL:
+        TRAP_TRY(launch_formal_grouped(ar.stream, static_cast<const GFormal*>(args), off, st.n, st.blocks));
+        break;
+    }
+    TRAP_HIP(hipGetLastError());
+  }
+  // ... and each context's later work waits for the batch
+  TRAP_HIP(hipEventRecord(ar.done, ar.stream));
+  for (int i = 0; i < n; ++i) TRAP_HIP(hipStreamWaitEvent(ctxs[i]->stream, ar.done, 0));
+  return TRAP_OK;
 }
 
 }  // namespace trap

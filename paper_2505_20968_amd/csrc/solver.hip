@@ -267,29 +267,58 @@ int gmres_begin(trap_ctx* ctx, const trap_solve_opts* opts, double* I) {
 
 namespace {
 
-// phase-1 work of one unit (everything up to its first synchronisation)
-int unit_issue1(trap_ctx* ctx, GmresRun& R) {
+// the operator apply that opens a unit: y = A_prec x (false when none)
+bool unit_operand(trap_ctx* ctx, GmresRun& R, int* prec, const double** x, double** y) {
+  Work& K = ctx->wk;
+  switch (R.phase) {
+    case GP_RESID_OUTER:
+      *prec = TRAP_FP64;
+      *x = R.x;
+      *y = K.r;
+      return true;
+    case GP_RESID_RESTART:
+      *prec = R.prec;
+      *x = K.x;
+      *y = K.tmp64;
+      return true;
+    case GP_ARNOLDI:
+      *prec = R.prec;
+      *x = K.V + (size_t)R.j * R.N;
+      *y = K.V + (size_t)(R.j + 1) * R.N;
+      return true;
+    default:
+      return false;
+  }
+}
+
+// phase-1 work of one unit after its operator apply, up to the first synchronisation
+int unit_issue1_rest(trap_ctx* ctx, GmresRun& R) {
   Work& K = ctx->wk;
   const long long N = R.N;
   switch (R.phase) {
     case GP_RESID_OUTER:
-      TRAP_TRY(op_apply(ctx, TRAP_FP64, R.x, K.r, &R.st));
       hipLaunchKernelGGL(k_axpby, dim3(kBlocks), dim3(256), 0, ctx->stream, N, 1.0, ctx->pre.d_b, -1.0, K.r);
       TRAP_HIP(hipGetLastError());
       return dots_async(ctx, R, K.r, 1, K.r, R.hbuf);
     case GP_RESID_RESTART:
-      TRAP_TRY(op_apply(ctx, R.prec, K.x, K.tmp64, &R.st));
       hipLaunchKernelGGL(k_axpby, dim3(kBlocks), dim3(256), 0, ctx->stream, N, 1.0, K.r, -1.0, K.tmp64);
       TRAP_HIP(hipGetLastError());
       return dots_async(ctx, R, K.tmp64, 1, K.tmp64, R.hbuf);
-    case GP_ARNOLDI: {
-      double* w = K.V + (size_t)(R.j + 1) * N;
-      TRAP_TRY(op_apply(ctx, R.prec, K.V + (size_t)R.j * N, w, &R.st));
-      return dots_async(ctx, R, K.V, R.j + 2, w, R.hbuf);   // last entry: |w|^2 (w is column j + 1)
-    }
+    case GP_ARNOLDI:
+      return dots_async(ctx, R, K.V, R.j + 2, K.V + (size_t)(R.j + 1) * N, R.hbuf);   // last entry: |w|^2
     default:
       return TRAP_OK;
   }
+}
+
+// phase-1 work of one unit (everything up to its first synchronisation)
+int unit_issue1(trap_ctx* ctx, GmresRun& R) {
+  int prec;
+  const double* x;
+  double* y;
+  if (!unit_operand(ctx, R, &prec, &x, &y)) return TRAP_OK;
+  TRAP_TRY(op_apply(ctx, prec, x, y, &R.st));
+  return unit_issue1_rest(ctx, R);
 }
 
 // start an Arnoldi cycle from the (unnormalised) residual vector src of norm beta
@@ -453,13 +482,58 @@ int arnoldi_finish(trap_ctx* ctx, GmresRun& R, double hn) {
 }  // namespace
 
 int gmres_step_batch(trap_ctx** ctxs, int n, int* status) {
-  // phase 1
+  // phase 1: the FP32 operator applies of contexts on one device go through
+  // shared launches; every other unit is issued on its own
+  std::vector<int> grp;
+  std::vector<trap_ctx*> gctx;
+  std::vector<const double*> gx;
+  std::vector<double*> gy;
+  int gdev = -1;
   for (int i = 0; i < n; ++i) {
     GmresRun& R = *ctxs[i]->run;
     if (R.phase == GP_DONE) continue;
     DeviceGuard g(ctxs[i]->device);
+    int prec;
+    const double* x;
+    double* y;
+    if (unit_operand(ctxs[i], R, &prec, &x, &y) && prec == TRAP_FP32 &&
+        (gdev < 0 || gdev == ctxs[i]->device)) {
+      const int ok = sigma_batch_ready(ctxs[i]);
+      if (ok < 0) {
+        run_finish(R, ok);
+        continue;
+      }
+      if (ok) {
+        gdev = ctxs[i]->device;
+        grp.push_back(i);
+        gctx.push_back(ctxs[i]);
+        gx.push_back(x);
+        gy.push_back(y);
+        continue;
+      }
+    }
     const int rc = unit_issue1(ctxs[i], R);
     if (rc < 0) run_finish(R, rc);
+  }
+  if (grp.size() == 1) {
+    GmresRun& R = *ctxs[grp[0]]->run;
+    DeviceGuard g(gdev);
+    const int rc = unit_issue1(ctxs[grp[0]], R);
+    if (rc < 0) run_finish(R, rc);
+  } else if (grp.size() > 1) {
+    DeviceGuard g(gdev);
+    const int rc = op_apply_batch_f32(gctx.data(), (int)gctx.size(), gx.data(), gy.data());
+    for (int i : grp) {
+      GmresRun& R = *ctxs[i]->run;
+      if (rc < 0) {
+        run_finish(R, rc);
+        continue;
+      }
+      R.st.applies_fp32++;
+      R.st.applies_grouped++;
+      const int rc2 = unit_issue1_rest(ctxs[i], R);
+      if (rc2 < 0) run_finish(R, rc2);
+    }
   }
   for (int i = 0; i < n; ++i) {
     GmresRun& R = *ctxs[i]->run;

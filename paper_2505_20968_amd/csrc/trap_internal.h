@@ -214,6 +214,89 @@ int gmres_step_batch(trap_ctx** ctxs, int n, int* status);
 int gmres_end(trap_ctx* ctx, trap_solve_stats* st);
 void gmres_release(trap_ctx* ctx);
 
+// ---------------------------------------------------------------- grouped launches
+// Arguments of one context in a launch that covers several contexts (one
+// record per context, in device memory; blocks [off[r], off[r + 1]) are
+// context r's).
+struct GSpline {
+  int nz0, nd, nn;
+  const double *x, *SigT, *lam, *ub;
+  double ub_sign;
+  const double* sll;
+  int ncls, cls;
+  const float* in;
+  long long in_z_stride, in_o_stride;
+  float* out;
+  int accumulate;
+  const double *f, *epsth;
+};
+struct GR3Y {
+  int z0, nzc, nt, nd, nn;
+  const double2* r3;
+  const float* Ibar;
+  double2* Y;
+};
+struct GR3X {
+  int z0, nu, nl, nd;
+  const double* w;
+  const double2* A;
+  const double2* Y;
+  double2* X;
+};
+struct GContract {
+  int z0, nth, nt, nn, ldm, nd, nkc, n8, nslot, rb_n, zc;
+  const float* M;
+  const float* Ibar;
+  const int* cgrp;
+  const int* slot_dir;
+  float* W;
+};
+struct GAngular {
+  int z0, nd, nn, nu, nl, nslot, nbx;
+  const int *pair_slot, *pair_index;
+  const float* cf;
+  const float* W;
+  double c_sc;
+  const double2 *E, *bma, *X, *prof;
+  float* Eb;
+};
+struct GFormal {
+  int nz, nd, nn;
+  const double *mu, *tau, *K8, *WT;
+  const float* eps;
+  float* I;
+};
+struct GVec {              // FP64 <-> FP32 conversions around the FP32 operator
+  long long N;
+  int nb;
+  const double* x64;       // in: operand
+  float* x32;              // operand in FP32
+  const float* f32;        // Lambda Sigma x in FP32
+  double* y64;             // out: x - Lambda Sigma x
+};
+
+// Per-device state of grouped launches: a stream, a pinned staging buffer and
+// its device copy for the argument records, and events.  Created with the
+// first context on a device and released with the last.
+struct BatchArena {
+  hipStream_t stream = nullptr;
+  unsigned char* host = nullptr;
+  void* dev = nullptr;
+  size_t cap = 0;
+  hipEvent_t copied = nullptr, done = nullptr;
+  std::vector<hipEvent_t> ev;
+  int users = 0;
+};
+void batch_arena_acquire(int device);
+void batch_arena_release(int device);
+// 1 when the context's FP32 operator can join a grouped apply (W allocated
+// for all heights at once), 0 when it cannot, < 0 on error
+int sigma_batch_ready(trap_ctx* ctx);
+// y_i = x_i - Lambda Sigma x_i in FP32 for every context (operands FP64), on
+// the device's batch stream, ordered after and before each context's stream
+int op_apply_batch_f32(trap_ctx** ctxs, int n, const double* const* x, double* const* y);
+int launch_formal_grouped(hipStream_t s, const GFormal* args, const int* off, int n, int blocks);
+
 struct DeviceGuard {
   int prev = -1;
   explicit DeviceGuard(int dev) {

@@ -65,7 +65,7 @@ class SolveOpts(ctypes.Structure):
 class SolveStats(ctypes.Structure):
     _fields_ = [("outer_steps", ctypes.c_int), ("inner_iters", ctypes.c_int),
                 ("applies_fp64", ctypes.c_int), ("applies_fp32", ctypes.c_int),
-                ("final_rel_res", ctypes.c_double), ("ms_total", ctypes.c_double)]
+                ("applies_grouped", ctypes.c_int), ("final_rel_res", ctypes.c_double), ("ms_total", ctypes.c_double)]
 
 
 class StageStats(ctypes.Structure):
@@ -240,7 +240,7 @@ class Context:
         if code != 0 and (raise_on_noconv or code != -4):
             _check(code)
         return {"outer_steps": st.outer_steps, "inner_iters": st.inner_iters,
-                "applies_fp64": st.applies_fp64, "applies_fp32": st.applies_fp32,
+                "applies_fp64": st.applies_fp64, "applies_fp32": st.applies_fp32, "applies_grouped": st.applies_grouped,
                 "final_rel_res": st.final_rel_res, "ms_total": st.ms_total, "status": code}
 
     def gmres_begin(self, I, tol: float = 1e-8, restart: int = 40, max_iters: int = 2000,
@@ -258,7 +258,7 @@ class Context:
             _check(code)
         self._solution = None
         return {"outer_steps": st.outer_steps, "inner_iters": st.inner_iters,
-                "applies_fp64": st.applies_fp64, "applies_fp32": st.applies_fp32,
+                "applies_fp64": st.applies_fp64, "applies_fp32": st.applies_fp32, "applies_grouped": st.applies_grouped,
                 "final_rel_res": st.final_rel_res, "ms_total": st.ms_total, "status": code}
 
     def emergent(self, I) -> np.ndarray:

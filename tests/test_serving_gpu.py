@@ -69,6 +69,17 @@ def test_every_request_converges_and_slots_were_shared(served, precision):
         assert r.admitted >= r.arrival - 1e-9 and r.done >= r.admitted
 
 
+def test_fp32_applies_shared_launches(served):
+    """Requests running together apply their FP32 operators in shared launches
+    (one launch per stage over all of them); FP64 applies are never grouped."""
+    grouped = [r.stats["applies_grouped"] for r in served["mixed"]["requests"]]
+    print(f"[serving mixed] grouped FP32 applies per request: {grouped}", flush=True)
+    assert sum(grouped) > 0
+    for r in served["mixed"]["requests"]:
+        assert r.stats["applies_grouped"] <= r.stats["applies_fp32"]
+    assert all(r.stats["applies_grouped"] == 0 for r in served["fp64"]["requests"])
+
+
 @pytest.mark.parametrize("precision", ["mixed", "fp64"])
 def test_result_is_the_same_alone_and_in_the_mix(served, precision):
     for r in served[precision]["requests"]:
