@@ -206,7 +206,10 @@ int trap_emergent(trap_ctx* ctx, const double* I, double* host_out);
 int trap_get_info(const trap_ctx* ctx, trap_info* info);
 
 /* Device bytes a context needs for this problem with the given kernel store
- * mask (for admission control); does not touch the device. */
+ * mask (for admission control): every allocation of trap_set_problem,
+ * trap_precompute (including its scratch) and a solve with restart <= 40,
+ * in the angle-dependent layout.  Host arithmetic only; does not touch the
+ * device. */
 int trap_footprint(const trap_atom_desc* atom, const trap_problem_desc* prob, int store_mask,
                    size_t* bytes);
 

@@ -519,10 +519,34 @@ static void angular_setup(Problem& P, std::vector<double>& dirs, std::vector<dou
   }
 }
 
+PrecompLayout precomp_layout(int nz, int nn, int ldm, int nt, int nthr, bool aa, const double* x,
+                             const double* lam) {
+  PrecompLayout L;
+  L.h = (x[nn - 1] - x[0]) / (nn - 1);
+  L.uniform = true;
+  for (int k = 0; k + 1 < nn; ++k)
+    if (std::fabs(x[k + 1] - x[k] - L.h) > 1e-12 * std::fabs(L.h)) L.uniform = false;
+  // the widest kernel support has half-width 6.6 * 2 sin(Theta/2) / lam <= 13.2 / lam
+  if (L.uniform) {
+    double lmin = lam[0];
+    for (int z = 1; z < nz; ++z) lmin = std::min(lmin, lam[z]);
+    L.ntail = (int)std::min<double>(std::ceil(13.2 / (lmin * L.h)) + 2.0, 8.0 * nn);
+  }
+  L.nd2 = 2 * nn - 1 + 2 * L.ntail;
+  const size_t tab_per_z = (size_t)nthr * L.nd2 * 16 * (sizeof(double) + nt * 2 * sizeof(double));
+  const size_t rows_per_z = (size_t)nthr * nt * 2 * nn;
+  const size_t lg_per_z = rows_per_z * ldm * sizeof(double) * (aa ? 3 : 2);
+  size_t zc_lim = std::max<size_t>(1, (size_t(1) << 30) / lg_per_z);
+  if (L.uniform) zc_lim = std::min(zc_lim, std::max<size_t>(1, (size_t(192) << 20) / tab_per_z));
+  L.zc_tab = (int)std::min<size_t>(nz, zc_lim);
+  L.bytes = (size_t)L.zc_tab * (lg_per_z + (L.uniform ? tab_per_z : 0));
+  return L;
+}
+
 size_t estimate_bytes(const trap_atom_desc* atom, const trap_problem_desc* pd, int store_mask, int* err) {
   *err = 0;
   if (!atom || !pd || pd->n_z < 2 || pd->n_nu < 4 || pd->n_mu < 2 || pd->n_mu % 2 || pd->n_chi < 1 ||
-      (atom->kind != 0 && atom->kind != 1)) {
+      (atom->kind != 0 && atom->kind != 1) || !pd->x || !pd->T || !(atom->mass_amu > 0)) {
     *err = 1;
     return 0;
   }
@@ -550,24 +574,90 @@ size_t estimate_bytes(const trap_atom_desc* atom, const trap_problem_desc* pd, i
   const size_t ker = nz * nth * nt * 2 * nn * ldm;       // stored kernel entries per precision
   const size_t cfe = nz * nd * nd * nt * 2 * nl * 16;    // angular coefficients per precision
   size_t b = 0;
+  auto add = [&b](size_t bytes) { b += bytes ? bytes : 16; };   // one allocation
+  auto add_vec = [&add](const auto& v) { add(v.size() * sizeof(v[0])); };
   for (int pi = 0; pi < 2; ++pi) {
     if (!(mask & (1 << pi))) continue;
     const size_t es = pi == 0 ? 8 : 4;
-    b += (ker + cfe) * es;
-    b += (N * 4 + nz * nl * nl * nd * nn * 4) * es;     // comoving field, eps_bar, two work vectors
+    add(ker * es);
+    add(cfe * es);
+    for (int k = 0; k < 3; ++k) add(N * es);           // comoving field, two work vectors
+    add(nz * nl * nl * nd * nn * 4 * es);               // eps_bar
   }
-  b += nz * nd * nn * (8 + 4 + 1 + 4) * 8;               // K, eps_th, f, b
-  b += nz * nt * nn * 2 * 16;                           // R_III weights and profiles
-  b += N * 8 * (41 + 3);                                // Krylov basis (restart <= 40) and solver vectors
-  b += N * 4 * 2;                                       // FP32 solver vectors
-  b += nz * nd * nd * nt * 16 * 2 + nz * nt * nd * 4 * 8;  // E/A tables, geometric factors
-  b += nd * nd * 4 * 4 + nslot * 8;                     // pair and slot tables
+  // precompute outputs: K, eps_th, f, b; R_III weights and profiles
+  add(nz * nd * nn * 8 * 8);
+  add(nz * nd * nn * 4 * 8);
+  add(nz * nd * nn * 8);
+  add(nz * nd * nn * 4 * 8);
+  add(nz * nt * nn * 16);
+  add(nz * nt * nn * 16);
+  // solver: Krylov basis (restart <= 40), r, x, scratch, reductions, FP32 vectors
+  add(N * 8 * 41);
+  for (int k = 0; k < 3; ++k) add(N * 8);
+  add(nz * nt * nd * 4 * 16);                           // R_III factors Y, X
+  add(nz * nu * nu * nl * 16);
+  add(4096 * 8);
+  add((1024 * 42 + 2 * 42) * 8);                       // reduction scratch (1024 blocks)
+  add(N * 4);
+  add(N * 4);
+  // problem tables: grid and spline maps, per-height scalars, angular tables,
+  // sublevel shifts, branching ratios, dipole tables
+  add(nn * 8);
+  add((nn - 1) * 4 * nn * 8);
+  add(nn * nn * 8);
+  add(nn * nn * 8);
+  for (int k = 0; k < 2; ++k) add(nd * 8);              // mu, w
+  for (int k = 0; k < 6; ++k) add(nz * 8);              // tau, lam, a, eps, W_T, eta0
+  add(nz * nd * 8);                                     // u_b
+  add(nz * nt * 8);                                     // transition shifts
+  add(nz * nl * nl * 8);                                // lower-level shifts
+  add_vec(P.theta);
+  add_vec(P.theta_rows);
+  add_vec(P.theta_rw);
+  add_vec(P.slot_theta);
+  add_vec(P.slot_dir);
+  add_vec(P.slot_off);
+  add_vec(P.pair_slot);
+  add_vec(P.pair_off);
+  add_vec(P.pair_o);
+  add_vec(P.pair_dir);
+  add_vec(P.pair_index);
+  add_vec(P.grp[0]);
+  add_vec(P.grp[1]);
+  add_vec(P.cgrp[0]);
+  add_vec(P.cgrp[1]);
+  add(nz * nd * 4 * nu * nu * nl * 16);                 // E
+  add(nz * nd * 4 * nu * nu * nl * 16);                 // A
+  add(nz * nu * nu * 16);                               // alpha
+  add(nz * nu * nu * 16);                               // beta - alpha
+  add(nz * nt * nd * 4 * 8);                            // g
+  // precompute scratch (factor tables, row stores of one height chunk)
+  {
+    const double mass = atom->mass_amu * kAMU;
+    const double Tref = pd->T_ref > 0 ? pd->T_ref : 6000.0;
+    const double vref = std::sqrt(2.0 * kKB * Tref / mass);
+    std::vector<double> lam(nz);
+    for (size_t z = 0; z < nz; ++z) {
+      const double xi = pd->xi ? pd->xi[z] * 1e5 : 0.0;
+      lam[z] = vref / std::sqrt(2.0 * kKB * pd->T[z] / mass + xi * xi);
+    }
+    const PrecompLayout lay =
+        precomp_layout((int)nz, (int)nn, (int)ldm, (int)nt, P.nth_rows, false, pd->x, lam.data());
+    const size_t rows = (size_t)lay.zc_tab * P.nth_rows * nt * 2 * nn * ldm * 8;
+    add(rows);                                          // L and Gamma row stores
+    add(rows);
+    if (lay.uniform) {
+      add((size_t)lay.zc_tab * P.nth_rows * lay.nd2 * 16 * 8);        // Gaussian factors
+      add((size_t)lay.zc_tab * P.nth_rows * nt * lay.nd2 * 16 * 16);  // Faddeeva factors
+    }
+  }
   // the height-chunked Sigma path materialises W for one chunk of heights
   // (at most ~512 MiB in FP64, half that in FP32)
   {
-    const size_t per_z = nt * nslot * 2 * nn * 4 * 8;
-    const size_t zc = std::max<size_t>(1, std::min<size_t>(nz, (size_t(1) << 29) / std::max<size_t>(per_z, 1)));
-    b += zc * per_z * ((mask & 2) ? 3 : 2) / 2;
+    const size_t per_z = nt * nslot * 2 * nn * 4;
+    const size_t zc = std::max<size_t>(1, std::min<size_t>(nz, (size_t(1) << 29) / std::max<size_t>(per_z * 8, 1)));
+    add(zc * per_z * 8);
+    if (mask & 2) add(zc * per_z * 4);
   }
   return b;
 }

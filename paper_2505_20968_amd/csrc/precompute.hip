@@ -159,10 +159,13 @@ __device__ inline int upper_interval(const double* x, int nn, double v) {
 // The Gaussian factor of F therefore depends on (d = n - k, i) only and the
 // Faddeeva factor on (p = n + k, i) only; both are tabulated per (height,
 // Theta[, transition]) so the row integration needs no transcendental calls.
-//   G[d + nn - 1][i] = exp(-(lam h (d - t_i) / (2 sin(Theta/2)))^2)
-//   V[p][i]          = W(a/cos(Theta/2), (lam (2 x_0 + h (p + t_i)) + 2 s)/(2 cos(Theta/2)))
+//   G[d + nn - 1 + ntail][i] = exp(-(lam h (d - t_i) / (2 sin(Theta/2)))^2)
+//   V[p + ntail][i]          = W(a/cos(Theta/2), (lam (2 x_0 + h (p + t_i)) + 2 s)/(2 cos(Theta/2)))
 // (Theta = pi: exp(-(lam h (d - t_i)/2)^2) and i/(2 sqrt(pi)(m + i a)), m = half the sum.)
-__global__ void k_kernel_tables(int z0, int nth, int nt, int nn, double x0, double h,
+// The index ranges reach ntail intervals past either end of the grid, so the
+// tails of a row's support (where the spline is extended flat) are integrated
+// with the same rule over virtual intervals x_0 + k h, k < 0 or k >= nn - 1.
+__global__ void k_kernel_tables(int z0, int nth, int nt, int nn, int ntail, double x0, double h,
                                 const double* __restrict__ lam, const double* __restrict__ av,
                                 const double* __restrict__ st, const double* __restrict__ theta,
                                 double* __restrict__ Gt, double2* __restrict__ Vt) {
@@ -174,10 +177,10 @@ __global__ void k_kernel_tables(int z0, int nth, int nt, int nn, double x0, doub
   if (Th == 0.0) return;
   const bool pil = Th >= kPiD;
   const double sG = pil ? 1.0 : sin(0.5 * Th), cG = pil ? 0.0 : cos(0.5 * Th);
-  const int nd2 = 2 * nn - 1;
+  const int nd2 = 2 * nn - 1 + 2 * ntail;
   double2* V = Vt + ((size_t)(zl * nth + th) * nt + t) * nd2 * 16;
   for (int e = threadIdx.x; e < nd2 * 16; e += blockDim.x) {
-    const int p = e >> 4, i = e & 15;
+    const int p = (e >> 4) - ntail, i = e & 15;
     const double xs = 2.0 * x0 + h * (p + c_gl_t[i]);
     if (pil) {
       const double m = 0.5 * (L * xs + 2.0 * s);
@@ -190,7 +193,7 @@ __global__ void k_kernel_tables(int z0, int nth, int nt, int nn, double x0, doub
   if (t == 0) {
     double* G = Gt + (size_t)(zl * nth + th) * nd2 * 16;
     for (int e = threadIdx.x; e < nd2 * 16; e += blockDim.x) {
-      const int dd = (e >> 4) - (nn - 1), i = e & 15;
+      const int dd = (e >> 4) - (nn - 1) - ntail, i = e & 15;
       const double q = L * h * (dd - c_gl_t[i]) / (2.0 * sG);
       G[e] = exp(-q * q);
     }
@@ -207,15 +210,22 @@ __global__ void k_kernel_tables(int z0, int nth, int nt, int nn, double x0, doub
 //   M[n][m] = L[m] + sum_j Gam[j] Sig[j][m]
 // with Sig = d s / d v the spline's second-derivative map; L and Gam are
 // written here, the dense product is one batched GEMM (k_sig_gemm).
-__global__ void __launch_bounds__(64) k_kernel_rows(
-    int nth, int nt, int nn, int ldm, const double* __restrict__ x,
+constexpr int kRowWavesMax = 2;       // rows (one per wave) per block of the kernel-row precompute
+
+__global__ void __launch_bounds__(64 * kRowWavesMax) k_kernel_rows(
+    long long nrows, int nth, int nt, int nn, int ldm, const double* __restrict__ x,
     const double* __restrict__ lam, const double* __restrict__ av, const double* __restrict__ st,
     const double* __restrict__ theta, double* __restrict__ Lout, double* __restrict__ Gout,
     long long row0, int z0, double h_uniform, const double* __restrict__ Gt,
-    const double2* __restrict__ Vt) {
-  extern __shared__ double2 mom[];     // [(nn+1)][4], piece index shifted by one
-  const long long row = row0 + blockIdx.x;
-  const int lane = threadIdx.x;
+    const double2* __restrict__ Vt, int ntail) {
+  extern __shared__ double2 smem[];    // per wave: [(nn+1)][4], piece index shifted by one
+  __shared__ double2 tred[kRowWavesMax][2][64];
+  const int waves = blockDim.x >> 6;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  double2* mom = smem + (size_t)wave * (nn + 1) * 4;
+  const long long rl = (long long)blockIdx.x * waves + wave;     // row within this launch
+  const bool live = rl < nrows;
+  const long long row = row0 + (live ? rl : 0);
   const int n = row % nn;
   const int t = (row / nn) % nt;
   const int th = (row / ((long long)nn * nt)) % nth;
@@ -224,7 +234,7 @@ __global__ void __launch_bounds__(64) k_kernel_rows(
   // chunk-local row index of the real plane; the imaginary plane follows nn rows later
   const size_t cbase = (size_t)((((size_t)(z - z0) * nth + th) * nt + t) * 2) * nn * ldm;
   const size_t rre = cbase + (size_t)n * ldm, rim = cbase + (size_t)nn * ldm + (size_t)n * ldm;
-  if (Th == 0.0) {
+  if (live && Th == 0.0) {
     const double2 w = wz(L * x[n] + s, a);
     for (int m = lane; m < ldm; m += 64) {
       Lout[rre + m] = (m == n) ? kSqrtPi * w.x : 0.0;
@@ -232,8 +242,9 @@ __global__ void __launch_bounds__(64) k_kernel_rows(
       Gout[rre + m] = 0.0;
       Gout[rim + m] = 0.0;
     }
-    return;
   }
+  // every wave of the block reaches the barriers below; only `work` rows integrate
+  const bool work = live && Th != 0.0;
   FParams fp;
   fp.pi_limit = (Th >= kPiD);
   fp.sG = fp.pi_limit ? 1.0 : sin(0.5 * Th);
@@ -260,63 +271,155 @@ __global__ void __launch_bounds__(64) k_kernel_rows(
   };
   // table fast path: uniform grid, Gaussian resolved by the interval nodes
   const bool fast = (Gt != nullptr) && (sigma >= 0.5 * h_uniform);
-  const int nd2 = 2 * nn - 1;
+  const int nd2 = 2 * nn - 1 + 2 * ntail;
   const double* Grow = fast ? Gt + (size_t)((z - z0) * nth + th) * nd2 * 16 : nullptr;
   const double2* Vrow = fast ? Vt + ((size_t)((z - z0) * nth + th) * nt + t) * nd2 * 16 : nullptr;
+  const int g_off = n + nn - 1 + ntail, v_off = n + ntail;     // table row = g_off - k, v_off + k
   const double fscale = L * h_uniform * (fp.pi_limit ? 1.0 : fp.inv_sinT);
   const bool sharp = wc < h_uniform;      // Voigt core narrower than an interval
-  // knot intervals inside the support: one lane per interval
-  const int ilo = max(plo, 0), ihi = min(phi, nn - 2);
-  for (int p = ilo + lane; p <= ihi; p += 64) {
-    double2 acc[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
-    const bool near_core = sharp && xc > x[p] - h_uniform && xc < x[p + 1] + h_uniform;
-    if (fast && !near_core) {
-      const double* g = Grow + (size_t)(n - p + nn - 1) * 16;
-      const double2* v = Vrow + (size_t)(n + p) * 16;
-      for (int i = 0; i < 16; ++i) {
-        const double f = fscale * c_gl_w[i] * g[i];
-        const double2 vv = v[i];
-        double tp = f;
-        const double ti = c_gl_t[i];
-        for (int q = 0; q < 4; ++q) {
-          acc[q].x += tp * vv.x;
-          acc[q].y += tp * vv.y;
-          tp *= ti;
+  // Graded region: where the 16-node rule per interval does not resolve F --
+  // the whole support when the Gaussian is narrower than half an interval or
+  // the grid is not uniform, else the intervals next to a sharp Voigt core.
+  // It is split into 64 equal pieces, one per lane; each lane integrates its
+  // piece with panels graded towards the core, interval by interval, and adds
+  // the moments into LDS.  Every other interval of the support takes the
+  // table rule, one lane per interval (virtual intervals of width h past the
+  // grid ends for the tails, where the spline is extended flat).
+  const double x0 = x[0];
+  auto xk = [&](int k) { return (k >= 0 && k < nn) ? x[k] : x0 + h_uniform * k; };
+  const int kmin = fast ? (int)floor((lo - x0) / h_uniform) : 0;
+  const int kmax = fast ? (int)floor((hi - x0) / h_uniform) : 0;
+  const bool tail_tab = fast && kmin >= -ntail && kmax <= nn - 2 + ntail;
+  // near-core intervals k (real or virtual): x_k - h < xc < x_{k+1} + h
+  auto near_core = [&](int k) { return sharp && xc > xk(k) - h_uniform && xc < xk(k + 1) + h_uniform; };
+  bool graded = false;
+  int kA = 1, kB = 0;                  // table-rule intervals skip [kA, kB]
+  double ga = 0.0, gb = 0.0;
+  if (work) {
+    if (!fast || !tail_tab) {
+      graded = true;
+      ga = lo;
+      gb = hi;
+      kA = -(1 << 30);
+      kB = 1 << 30;
+    } else if (sharp) {
+      const int kc = (int)floor((xc - x0) / h_uniform);
+      kA = 1 << 30;
+      kB = -(1 << 30);
+      for (int k = kc - 3; k <= kc + 2; ++k)
+        if (k >= kmin && k <= kmax && near_core(k)) {
+          kA = min(kA, k);
+          kB = max(kB, k);
         }
+      if (kA <= kB) {
+        graded = true;
+        ga = fmax(xk(kA), lo);
+        gb = fmin(xk(kB + 1), hi);
       }
-    } else {
-      const double pa = fmax(x[p], lo), pb = fmin(x[p + 1], hi);
-      graded_integrate(pa, pb, xc, wc, Lg, x[p], 1.0 / (x[p + 1] - x[p]), 4, integrand, acc);
+    }
+  }
+  // table rule: knot intervals inside the support, one lane per interval
+  const int ilo = max(plo, 0), ihi = min(phi, nn - 2);
+  for (int p = ilo + lane; work && fast && p <= ihi; p += 64) {
+    if (p >= kA && p <= kB) continue;
+    double2 acc[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+    const double* g = Grow + (size_t)(g_off - p) * 16;
+    const double2* v = Vrow + (size_t)(v_off + p) * 16;
+    for (int i = 0; i < 16; ++i) {
+      const double f = fscale * c_gl_w[i] * g[i];
+      const double2 vv = v[i];
+      double tp = f;
+      const double ti = c_gl_t[i];
+      for (int q = 0; q < 4; ++q) {
+        acc[q].x += tp * vv.x;
+        acc[q].y += tp * vv.y;
+        tp *= ti;
+      }
     }
     for (int q = 0; q < 4; ++q) mom[(p + 1) * 4 + q] = acc[q];
   }
-  // tails beyond the grid (flat extension: they weigh the edge nodes); each
-  // tail is split into 64 equal pieces, one per lane, then reduced
-  __shared__ double2 tred[2][64];
+  // graded pieces: moments of knot intervals into mom[k + 1], tails (q = 0)
+  // into mom[0] and mom[nn]
+  if (graded && gb > ga) {
+    const double wpiece = (gb - ga) / 64.0;
+    const double pe = (lane == 63) ? gb : ga + wpiece * (lane + 1);
+    double pa = ga + wpiece * lane;
+    int guard = 0;
+    while (pa < pe && guard < 2 * nn + 4) {
+      ++guard;
+      const int k = upper_interval(x, nn, pa);       // -1: left of the grid, nn - 1: right
+      double pb;
+      int slot, nq;
+      double xl, invh;
+      if (k < 0) {
+        pb = fmin(pe, x0);
+        slot = 0;
+        nq = 1;
+        xl = 0.0;
+        invh = 0.0;
+      } else if (k >= nn - 1) {
+        pb = pe;
+        slot = nn * 4;
+        nq = 1;
+        xl = 0.0;
+        invh = 0.0;
+      } else {
+        pb = fmin(pe, x[k + 1]);
+        slot = (k + 1) * 4;
+        nq = 4;
+        xl = x[k];
+        invh = 1.0 / (x[k + 1] - x[k]);
+      }
+      if (pb > pa) {
+        // four moments always (constant trip counts keep acc in registers);
+        // a tail has invh = 0 and uses the zeroth only
+        double2 acc[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+        graded_integrate(pa, pb, xc, wc, Lg, xl, invh, 4, integrand, acc);
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (q < nq) {
+            atomicAdd(&mom[slot + q].x, acc[q].x);
+            atomicAdd(&mom[slot + q].y, acc[q].y);
+          }
+      }
+      pa = fmax(pb, pa);
+      if (pb <= pa && k >= nn - 1) break;
+    }
+  }
+  // table rule on the tails: virtual intervals past the ends, reduced over lanes
   for (int side = 0; side < 2; ++side) {
-    const bool present = side == 0 ? (plo < 0) : (phi >= nn - 1);
+    const bool present = work && tail_tab && (side == 0 ? (plo < 0) : (phi >= nn - 1));
     double2 acc = make_double2(0.0, 0.0);
     if (present) {
-      const double ta = side == 0 ? lo : x[nn - 1];
-      const double tb = side == 0 ? x[0] : hi;
-      const double wpiece = (tb - ta) / 64.0;
-      const double pa = ta + wpiece * lane, pb = (lane == 63) ? tb : ta + wpiece * (lane + 1);
-      graded_integrate(pa, pb, xc, wc, Lg, 0.0, 0.0, 1, integrand, &acc);
+      const int ka = side == 0 ? kmin : nn - 1, kb = side == 0 ? -1 : kmax;
+      for (int k = ka + lane; k <= kb; k += 64) {
+        if (k >= kA && k <= kB) continue;
+        const double* g = Grow + (size_t)(g_off - k) * 16;
+        const double2* v = Vrow + (size_t)(v_off + k) * 16;
+        for (int i = 0; i < 16; ++i) {
+          const double f = fscale * c_gl_w[i] * g[i];
+          const double2 vv = v[i];
+          acc.x += f * vv.x;
+          acc.y += f * vv.y;
+        }
+      }
     }
-    tred[side][lane] = acc;
+    tred[wave][side][lane] = acc;
   }
   __syncthreads();
-  if (lane < 2) {
+  if (work && lane < 2) {
     double2 tot = make_double2(0.0, 0.0);
     for (int i = 0; i < 64; ++i) {
-      tot.x += tred[lane][i].x;
-      tot.y += tred[lane][i].y;
+      tot.x += tred[wave][lane][i].x;
+      tot.y += tred[wave][lane][i].y;
     }
-    mom[(lane == 0 ? 0 : nn) * 4] = tot;
+    const int slot = (lane == 0 ? 0 : nn) * 4;
+    mom[slot].x += tot.x;
+    mom[slot].y += tot.y;
   }
   __syncthreads();
   // per node m: L[m] = (mu0 - mu1)_m + (mu1)_{m-1} (+ tails), Gam[m] = g_m + e_{m-1}
-  for (int m = lane; m < ldm; m += 64) {
+  for (int m = lane; work && m < ldm; m += 64) {
     double lr = 0.0, li = 0.0, gr = 0.0, gi = 0.0;
     if (m < nn) {
       if (m <= nn - 2) {          // interval m starts at node m
@@ -613,18 +716,15 @@ int run_precompute(trap_ctx* ctx, int store_mask) {
   C.store_mask = mask;
   const size_t lds = (size_t)(nn + 1) * 4 * sizeof(double2);
   if (lds > 64 * 1024) return fail(TRAP_EINVAL, "frequency grid too large for the kernel precompute");
+  // rows per block of k_kernel_rows: two when their moments and lane partial
+  // sums fit in 64 KB
+  const int rw = (int)std::max<size_t>(1, std::min<size_t>(kRowWavesMax, (56 * 1024) / lds));
   // uniform grid -> factor tables, heights in chunks so the tables stay cache sized
-  const double h = (P.x[nn - 1] - P.x[0]) / (nn - 1);
-  bool uniform = true;
-  for (int k = 0; k + 1 < nn; ++k)
-    if (std::fabs(P.x[k + 1] - P.x[k] - h) > 1e-12 * std::fabs(h)) uniform = false;
-  const int nd2 = 2 * nn - 1;
-  const size_t tab_per_z = (size_t)nthr * nd2 * 16 * (sizeof(double) + nt * sizeof(double2));
+  const PrecompLayout lay = precomp_layout(nz, nn, P.ldm, nt, nthr, aa, P.x.data(), P.lam.data());
+  const bool uniform = lay.uniform;
+  const double h = lay.h;
+  const int ntail = lay.ntail, nd2 = lay.nd2, zc_tab = lay.zc_tab;
   const size_t rows_per_z = (size_t)nthr * nt * 2 * nn;
-  const size_t lg_per_z = rows_per_z * P.ldm * sizeof(double) * (aa ? 3 : 2);
-  size_t zc_lim = std::max<size_t>(1, (size_t(1) << 30) / lg_per_z);
-  if (uniform) zc_lim = std::min(zc_lim, std::max<size_t>(1, (size_t(192) << 20) / tab_per_z));
-  const int zc_tab = (int)std::min<size_t>(nz, zc_lim);
   if (uniform && !C.d_Gt) {
     TRAP_TRY(dalloc_t(ctx, &C.d_Gt, (size_t)zc_tab * nthr * nd2 * 16));
     TRAP_TRY(dalloc_t(ctx, &C.d_Vt, (size_t)zc_tab * nthr * nt * nd2 * 16));
@@ -639,17 +739,18 @@ int run_precompute(trap_ctx* ctx, int store_mask) {
   for (int z0 = 0; z0 < nz; z0 += zc_tab) {
     const int zc = std::min(zc_tab, nz - z0);
     if (uniform) {
-      hipLaunchKernelGGL(k_kernel_tables, dim3(zc * nthr * nt), dim3(256), 0, s, z0, nthr, nt, nn, P.x[0], h,
+      hipLaunchKernelGGL(k_kernel_tables, dim3(zc * nthr * nt), dim3(256), 0, s, z0, nthr, nt, nn, ntail, P.x[0], h,
                          P.d_lam, P.d_a, P.d_st, P.d_theta_rows, C.d_Gt, C.d_Vt);
       TRAP_HIP(hipGetLastError());
     }
     const long long nrows = (long long)zc * nthr * nt * nn;     // complex rows of this chunk
-    const long long chunk = 1 << 20;
+    const long long chunk = 1 << 22;
     for (long long r0 = 0; r0 < nrows; r0 += chunk) {
       const long long nr = std::min(chunk, nrows - r0);
-      hipLaunchKernelGGL(k_kernel_rows, dim3((unsigned)nr), dim3(64), lds, s, nthr, nt, nn, P.ldm, P.d_x,
+      hipLaunchKernelGGL(k_kernel_rows, dim3((unsigned)ceil_div(nr, rw)), dim3(64 * rw), rw * lds, s, nr, nthr, nt,
+                         nn, P.ldm, P.d_x,
                          P.d_lam, P.d_a, P.d_st, P.d_theta_rows, C.d_Lrow, C.d_Grow, r0, z0, h,
-                         uniform ? C.d_Gt : nullptr, uniform ? C.d_Vt : nullptr);
+                         uniform ? C.d_Gt : nullptr, uniform ? C.d_Vt : nullptr, ntail);
       TRAP_HIP(hipGetLastError());
     }
     const long long rrows = 2 * nrows;                           // real rows (both planes)

@@ -25,21 +25,29 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
+// Vectors have N = 4 n_z n_dir n_nu entries (a multiple of four), so every
+// column of the basis is 16-byte aligned and is streamed as double2.
 __global__ void __launch_bounds__(256) k_multidot(const double* __restrict__ V, int ncols, long long N,
                                                   const double* __restrict__ w, double* __restrict__ partial) {
   __shared__ double sh[4][8];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const long long N2 = N >> 1;
+  const double2* w2 = reinterpret_cast<const double2*>(w);
   for (int k0 = 0; k0 < ncols; k0 += 8) {
     const int kc = min(8, ncols - k0);
+    const double2* V2 = reinterpret_cast<const double2*>(V + (size_t)k0 * N);
     double s[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) s[q] = 0.0;
-    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < N;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < N2;
          i += (long long)gridDim.x * blockDim.x) {
-      const double wi = w[i];
+      const double2 wi = w2[i];
 #pragma unroll
       for (int q = 0; q < 8; ++q)
-        if (q < kc) s[q] += V[(size_t)(k0 + q) * N + i] * wi;
+        if (q < kc) {
+          const double2 v = V2[(size_t)q * N2 + i];
+          s[q] += v.x * wi.x + v.y * wi.y;
+        }
     }
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
@@ -66,13 +74,34 @@ __global__ void __launch_bounds__(256) k_reduce_partial(const double* __restrict
   __syncthreads();
   if (threadIdx.x == 0) out[k] = sh[0] + sh[1] + sh[2] + sh[3];
 }
-__global__ void k_multiaxpy(const double* __restrict__ V, int ncols, long long N,
-                            const double* __restrict__ h, double* __restrict__ w) {
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < N;
+// w -= sum_k h[k] V_k, four columns per step
+__global__ void __launch_bounds__(256) k_multiaxpy(const double* __restrict__ V, int ncols, long long N,
+                                                   const double* __restrict__ h, double* __restrict__ w) {
+  const long long N2 = N >> 1;
+  const double2* V2 = reinterpret_cast<const double2*>(V);
+  double2* w2 = reinterpret_cast<double2*>(w);
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < N2;
        i += (long long)gridDim.x * blockDim.x) {
-    double s = w[i];
-    for (int k = 0; k < ncols; ++k) s -= h[k] * V[(size_t)k * N + i];
-    w[i] = s;
+    double2 s = w2[i];
+    int k = 0;
+    for (; k + 4 <= ncols; k += 4) {
+      const double2 a0 = V2[(size_t)k * N2 + i], a1 = V2[(size_t)(k + 1) * N2 + i];
+      const double2 a2 = V2[(size_t)(k + 2) * N2 + i], a3 = V2[(size_t)(k + 3) * N2 + i];
+      s.x -= h[k] * a0.x;
+      s.y -= h[k] * a0.y;
+      s.x -= h[k + 1] * a1.x;
+      s.y -= h[k + 1] * a1.y;
+      s.x -= h[k + 2] * a2.x;
+      s.y -= h[k + 2] * a2.y;
+      s.x -= h[k + 3] * a3.x;
+      s.y -= h[k + 3] * a3.y;
+    }
+    for (; k < ncols; ++k) {
+      const double2 a = V2[(size_t)k * N2 + i];
+      s.x -= h[k] * a.x;
+      s.y -= h[k] * a.y;
+    }
+    w2[i] = s;
   }
 }
 
@@ -109,7 +138,7 @@ __global__ void k_nonfinite(long long N, const double* __restrict__ x, int* __re
 
 namespace {
 
-constexpr int kBlocks = 512;
+constexpr int kBlocks = 1024;
 
 // y = A x with the operator in precision `prec` (x, y FP64)
 int op_apply(trap_ctx* ctx, int prec, const double* x, double* y, trap_solve_stats* st) {

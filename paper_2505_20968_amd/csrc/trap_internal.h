@@ -198,7 +198,17 @@ int build_problem(trap_ctx* ctx, const trap_atom_desc* atom, const trap_problem_
 size_t estimate_bytes(const trap_atom_desc* atom, const trap_problem_desc* pd, int store_mask,
                       int* err);
 
-// precompute (precompute.hip)
+// precompute (precompute.hip) and the layout of its scratch (host_setup.cpp):
+// factor tables on uniform grids reaching ntail virtual intervals past the grid
+// ends, and the height chunk zc_tab of the row scratch
+struct PrecompLayout {
+  bool uniform = false;
+  double h = 0.0;
+  int ntail = 0, nd2 = 0, zc_tab = 1;
+  size_t bytes = 0;     // device scratch: tables and the row stores of one chunk
+};
+PrecompLayout precomp_layout(int nz, int nn, int ldm, int nt, int nthr, bool aa, const double* x,
+                             const double* lam);
 int run_precompute(trap_ctx* ctx, int store_mask);
 
 // applies (sigma.hip, formal.hip)

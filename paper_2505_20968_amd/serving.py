@@ -60,6 +60,9 @@ class Scheduler:
         self.peak_used = 0
         self.peak_active = 0
         self.steps = 0
+        self.time_admit = 0.0     # host seconds spent in backend.admit / step / finish
+        self.time_step = 0.0
+        self.time_finish = 0.0
 
     def run(self, requests: Sequence[Request]) -> List[Request]:
         pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
@@ -83,7 +86,9 @@ class Scheduler:
                     break
                 queue.popleft()
                 req.admitted = self.clock() - t0
+                ta = self.clock()
                 handle = self.backend.admit(req.problem)
+                self.time_admit += self.clock() - ta
                 active.append((req, handle, need))
                 used += need
                 self.peak_used = max(self.peak_used, used)
@@ -92,14 +97,18 @@ class Scheduler:
                 if pending:
                     self.sleep(max(0.0, min(pending[0].arrival - (self.clock() - t0), 0.01)))
                 continue
+            ta = self.clock()
             status = self.backend.step([h for _, h, _ in active])
+            self.time_step += self.clock() - ta
             self.steps += 1
             keep = []
             for (req, handle, need), s in zip(active, status):
                 if s == 1:
                     keep.append((req, handle, need))
                     continue
+                ta = self.clock()
                 req.status, req.stats, req.result = self.backend.finish(handle)
+                self.time_finish += self.clock() - ta
                 req.done = self.clock() - t0
                 used -= need
             active = keep
@@ -178,4 +187,5 @@ def serve(requests: Sequence[Request], precision: str = "mixed", mem_budget: Opt
             "n_ok": len(ok), "n_rejected": sum(1 for r in out if r.status == TRAP_ENOMEM),
             "n_failed": sum(1 for r in out if r.status not in (0, TRAP_ENOMEM)),
             "p50_s": pct(0.5), "p99_s": pct(0.99), "peak_active": sched.peak_active,
-            "peak_bytes": sched.peak_used, "steps": sched.steps}
+            "peak_bytes": sched.peak_used, "steps": sched.steps,
+            "host_s": {"admit": sched.time_admit, "step": sched.time_step, "finish": sched.time_finish}}

@@ -98,3 +98,28 @@ def test_invalid_descriptions_fail_cleanly():
     assert ei.value.code == -5
     ctx2.close()
     ctx.close()
+
+
+@pytest.mark.parametrize("store", [1, 3])
+def test_footprint_bounds_what_a_solve_allocates(store):
+    """Admission sizing: trap_footprint (host arithmetic) is at least what a
+    context holds on the device after set-up, precompute and a solve, and
+    not wildly more."""
+    torch = _torch()
+    from paper_2505_20968_amd import Context, TRAP_FP32, TRAP_FP64, footprint
+    from workloads import cfg1
+    for prob in (cfg1(), tiny(n_z=6, n_nu=25, x_max=7, n_mu=4, n_chi=5, B=(60.0, 0.8, 2.0), a=2e-2,
+                              eps=3e-2, v_z=2.0, seed=21),
+                 tiny(n_z=4, n_nu=33, x_max=16, n_mu=4, n_chi=4, B=(40.0, 1.0, 0.3), a=1e-2, eps=5e-2,
+                      atom=two_term_atom(2800.0, 24.305, 20.0))):
+        est = footprint(prob, store)
+        ctx = Context(0)
+        ctx.set_problem(prob)
+        ctx.precompute(store)
+        x = torch.zeros(ctx.shape, dtype=torch.float64, device="cuda")
+        ctx.gmres_solve(x, tol=1e-9, restart=40, inner=TRAP_FP32 if store == 3 else TRAP_FP64,
+                        inner_tol=1e-4, max_outer=10)
+        used = ctx.info()["bytes_device_total"]
+        ctx.close()
+        print(f"store {store}: footprint {est} B, held {used} B", flush=True)
+        assert used <= est <= 1.5 * used + (1 << 20)
