@@ -29,9 +29,10 @@
  *   descriptor arrays are read during the call only.  The context owns every
  *   allocation it makes and frees it in trap_destroy.
  * Streams: work is enqueued on the stream given to trap_create (a hipStream_t,
- *   NULL = default stream).  trap_apply_sigma, trap_formal_solve and
- *   trap_apply_operator are asynchronous; trap_set_problem, trap_precompute,
- *   trap_gmres_solve and trap_emergent synchronise the stream.
+ *   NULL = default stream).  trap_set_problem (after its host work),
+ *   trap_precompute, trap_apply_sigma, trap_formal_solve, trap_apply_operator
+ *   and trap_gmres_begin are asynchronous; trap_gmres_solve, trap_gmres_end
+ *   and trap_emergent synchronise the stream.
  * Errors: every call returns a trap_status; negative values are failures and
  *   trap_last_error() returns a thread-local message.  A failed call leaves the
  *   context usable.  No call aborts or throws.
@@ -138,8 +139,10 @@ int trap_destroy(trap_ctx* ctx);
 /* Load a problem: per-height physics on the host in FP64 (Doppler widths,
  * damping split, branching ratios alpha/beta of App. B, sublevel energies and
  * dipole vectors, angular tables, scattering-angle table of Sect. 4.2, cubic-
- * spline coefficient maps of Sect. 6.2), uploaded to the device.  Replaces any
- * previous problem of the context.  Synchronises. */
+ * spline coefficient maps of Sect. 6.2), uploaded to the device with one copy
+ * enqueued on the context's stream (the call returns once the host work is
+ * done).  Replaces any previous problem of the context (waiting for the work
+ * still queued on it). */
 int trap_set_problem(trap_ctx* ctx, const trap_atom_desc* atom, const trap_problem_desc* prob);
 
 /* Device-side precompute (Sect. 4.3, App. C-E): the propagation matrix and
@@ -147,7 +150,9 @@ int trap_set_problem(trap_ctx* ctx, const trap_atom_desc* atom, const trap_probl
  * integration over frequency) stored in FP64 and/or FP32, the R_III weights,
  * the normalisation factor f (one Sigma apply on a flat field) and the right-
  * hand side b = Lambda eps_th + t.  store_mask: bit 0 = FP64 kernels, bit 1 =
- * FP32 kernels (FP64 is always built for f and b).  Synchronises. */
+ * FP32 kernels (FP64 is always built for f and b).  Asynchronous: the work is
+ * enqueued on the context's stream, and later calls on the context are
+ * ordered after it. */
 int trap_precompute(trap_ctx* ctx, int store_mask);
 
 /* eps = Sigma I (Eq. matrix_form_2 without eps_th): comoving interpolation,
@@ -174,9 +179,11 @@ int trap_gmres_solve(trap_ctx* ctx, const trap_solve_opts* opts, double* I, trap
 
 /* Batched solving for a serving loop: the solve of trap_gmres_solve split into
  * steps so that many contexts (requests) advance together.
- * trap_gmres_begin checks the options and the initial guess I (FP64 device
- * memory, overwritten with the solution; must stay valid until the solve ends)
- * and computes ||b|| (synchronises the context's stream).
+ * trap_gmres_begin checks the options and enqueues the check of the initial
+ * guess I (FP64 device memory, overwritten with the solution; must stay valid
+ * until the solve ends) and the computation of ||b||; it does not wait.  A
+ * non-finite initial guess (TRAP_ENAN) or a zero right-hand side
+ * (TRAP_EINVAL) ends the solve at its first step.
  * trap_gmres_step_batch advances each of the n distinct contexts by one unit
  * (one Arnoldi iteration, or one FP64 residual of the refinement loop): the
  * device work of all contexts is enqueued on their own streams before the call

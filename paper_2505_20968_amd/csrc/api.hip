@@ -44,10 +44,16 @@ void free_all(trap_ctx* ctx) {
   ctx->has_problem = false;
 }
 
-int upload(trap_ctx* ctx, void** dst, const void* src, size_t bytes) {
-  TRAP_TRY(dalloc(ctx, dst, bytes));
-  if (bytes) TRAP_HIP(hipMemcpyAsync(*dst, src, bytes, hipMemcpyHostToDevice, ctx->stream));
-  return TRAP_OK;
+int UploadBatch::commit(trap_ctx* ctx) {
+  if (items.empty()) return TRAP_OK;
+  void* base = nullptr;
+  TRAP_TRY(dalloc(ctx, &base, total));
+  std::vector<unsigned char> h(total, 0);
+  for (const Item& it : items) {
+    if (it.bytes) std::memcpy(h.data() + it.off, it.src, it.bytes);
+    if (it.dst) *it.dst = static_cast<unsigned char*>(base) + it.off;
+  }
+  return stage_upload(ctx, h.data(), total, base);
 }
 
 template <typename T>
@@ -167,11 +173,8 @@ int trap_set_problem(trap_ctx* ctx, const trap_atom_desc* atom, const trap_probl
     free_all(ctx);
     return fail(TRAP_EINVAL, "too many sublevels or azimuths (n_lower <= 8, n_upper <= 16, n_chi <= 16, n_chi * n_lower <= 32)");
   }
-  hipError_t e = hipStreamSynchronize(ctx->stream);
-  if (e != hipSuccess) {
-    free_all(ctx);
-    return fail(TRAP_EDEVICE, std::string("upload: ") + hipGetErrorString(e));
-  }
+  // the upload is in flight on the context's stream (from a pinned buffer the
+  // device's pool keeps until the copy has finished); later work is ordered after it
   ctx->has_problem = true;
   return TRAP_OK;
 }

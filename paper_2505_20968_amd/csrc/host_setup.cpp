@@ -600,37 +600,44 @@ size_t estimate_bytes(const trap_atom_desc* atom, const trap_problem_desc* pd, i
   add((1024 * 42 + 2 * 42) * 8);                       // reduction scratch (1024 blocks)
   add(N * 4);
   add(N * 4);
-  // problem tables: grid and spline maps, per-height scalars, angular tables,
-  // sublevel shifts, branching ratios, dipole tables
-  add(nn * 8);
-  add((nn - 1) * 4 * nn * 8);
-  add(nn * nn * 8);
-  add(nn * nn * 8);
-  for (int k = 0; k < 2; ++k) add(nd * 8);              // mu, w
-  for (int k = 0; k < 6; ++k) add(nz * 8);              // tau, lam, a, eps, W_T, eta0
-  add(nz * nd * 8);                                     // u_b
-  add(nz * nt * 8);                                     // transition shifts
-  add(nz * nl * nl * 8);                                // lower-level shifts
-  add_vec(P.theta);
-  add_vec(P.theta_rows);
-  add_vec(P.theta_rw);
-  add_vec(P.slot_theta);
-  add_vec(P.slot_dir);
-  add_vec(P.slot_off);
-  add_vec(P.pair_slot);
-  add_vec(P.pair_off);
-  add_vec(P.pair_o);
-  add_vec(P.pair_dir);
-  add_vec(P.pair_index);
-  add_vec(P.grp[0]);
-  add_vec(P.grp[1]);
-  add_vec(P.cgrp[0]);
-  add_vec(P.cgrp[1]);
-  add(nz * nd * 4 * nu * nu * nl * 16);                 // E
-  add(nz * nd * 4 * nu * nu * nl * 16);                 // A
-  add(nz * nu * nu * 16);                               // alpha
-  add(nz * nu * nu * 16);                               // beta - alpha
-  add(nz * nt * nd * 4 * 8);                            // g
+  // problem tables: one batch (grid and spline maps, per-height scalars,
+  // angular tables, sublevel shifts, branching ratios, dipole tables) in the
+  // order and alignment of build_problem's upload
+  {
+    UploadBatch up;
+    auto item = [&up](size_t bytes) { up.add(nullptr, nullptr, bytes); };
+    auto item_vec = [&item](const auto& v) { item(v.size() * sizeof(v[0])); };
+    item(nn * 8);
+    item((nn - 1) * 4 * nn * 8);
+    item(nn * nn * 8);
+    item(nn * nn * 8);
+    for (int k = 0; k < 2; ++k) item(nd * 8);            // mu, w
+    for (int k = 0; k < 6; ++k) item(nz * 8);            // tau, lam, a, eps, W_T, eta0
+    item(nz * nd * 8);                                   // u_b
+    item(nz * nt * 8);                                   // transition shifts
+    item(nz * nl * nl * 8);                              // lower-level shifts
+    item_vec(P.theta);
+    item_vec(P.theta_rows);
+    item_vec(P.theta_rw);
+    item_vec(P.slot_theta);
+    item_vec(P.slot_dir);
+    item_vec(P.slot_off);
+    item_vec(P.pair_slot);
+    item_vec(P.pair_off);
+    item_vec(P.pair_o);
+    item_vec(P.pair_dir);
+    item_vec(P.pair_index);
+    item_vec(P.grp[0]);
+    item_vec(P.grp[1]);
+    item_vec(P.cgrp[0]);
+    item_vec(P.cgrp[1]);
+    item(nz * nd * 4 * nu * nu * nl * 16);               // E
+    item(nz * nd * 4 * nu * nu * nl * 16);               // A
+    item(nz * nu * nu * 16);                             // alpha
+    item(nz * nu * nu * 16);                             // beta - alpha
+    item(nz * nt * nd * 4 * 8);                          // g
+    add(up.total);
+  }
   // precompute scratch (factor tables, row stores of one height chunk)
   {
     const double mass = atom->mass_amu * kAMU;
@@ -775,45 +782,48 @@ int build_problem(trap_ctx* ctx, const trap_atom_desc* at, const trap_problem_de
   // ---- upload
   std::vector<double> sig;
   auto spl = spline_map(P.x, &sig);
-  int nsl = P.nslot;
-  (void)nsl;
-  TRAP_TRY(upload_t(ctx, &P.d_x, P.x));
-  TRAP_TRY(upload_t(ctx, &P.d_P, spl));
-  TRAP_TRY(upload_t(ctx, &P.d_Sig, sig));
   std::vector<double> sigT(sig.size());
   for (int i = 0; i < nn; ++i)
     for (int j = 0; j < nn; ++j) sigT[(size_t)j * nn + i] = sig[(size_t)i * nn + j];
-  TRAP_TRY(upload_t(ctx, &P.d_SigT, sigT));
-  TRAP_TRY(upload_t(ctx, &P.d_mu, P.mu));
-  TRAP_TRY(upload_t(ctx, &P.d_w, P.w));
-  TRAP_TRY(upload_t(ctx, &P.d_tau, P.tau));
-  TRAP_TRY(upload_t(ctx, &P.d_lam, P.lam));
-  TRAP_TRY(upload_t(ctx, &P.d_a, P.a));
-  TRAP_TRY(upload_t(ctx, &P.d_eps, P.eps));
-  TRAP_TRY(upload_t(ctx, &P.d_WT, P.WT));
-  TRAP_TRY(upload_t(ctx, &P.d_eta0, P.eta0));
-  TRAP_TRY(upload_t(ctx, &P.d_ub, ub));
-  TRAP_TRY(upload_t(ctx, &P.d_st, st));
-  TRAP_TRY(upload_t(ctx, &P.d_sll, sll));
-  TRAP_TRY(upload_t(ctx, &P.d_theta, P.theta));
-  TRAP_TRY(upload_t(ctx, &P.d_theta_rows, P.theta_rows));
-  TRAP_TRY(upload_t(ctx, &P.d_theta_rw, P.theta_rw));
-  TRAP_TRY(upload_t(ctx, &P.d_slot_theta, P.slot_theta));
-  TRAP_TRY(upload_t(ctx, &P.d_slot_dir, P.slot_dir));
-  TRAP_TRY(upload_t(ctx, &P.d_slot_off, P.slot_off));
-  TRAP_TRY(upload_t(ctx, &P.d_pair_slot, P.pair_slot));
-  TRAP_TRY(upload_t(ctx, &P.d_pair_off, P.pair_off));
-  TRAP_TRY(upload_t(ctx, &P.d_pair_o, P.pair_o));
-  TRAP_TRY(upload_t(ctx, &P.d_pair_dir, P.pair_dir));
-  TRAP_TRY(upload_t(ctx, &P.d_pair_index, P.pair_index));
-  TRAP_TRY(upload_t(ctx, &P.d_grp[0], P.grp[0]));
-  TRAP_TRY(upload_t(ctx, &P.d_grp[1], P.grp[1]));
-  for (int pi = 0; pi < 2; ++pi) TRAP_TRY(upload_t(ctx, &P.d_cgrp[pi], P.cgrp[pi]));
-  TRAP_TRY(upload_t(ctx, &P.d_E, E));
-  TRAP_TRY(upload_t(ctx, &P.d_A, A));
-  TRAP_TRY(upload_t(ctx, &P.d_alpha, alpha));
-  TRAP_TRY(upload_t(ctx, &P.d_bma, bma));
-  TRAP_TRY(upload_t(ctx, &P.d_g, g));
+  // one device allocation and one pinned copy for every table (the layout of
+  // the batch is mirrored by estimate_bytes)
+  UploadBatch up;
+  up.add(&P.d_x, P.x);
+  up.add(&P.d_P, spl);
+  up.add(&P.d_Sig, sig);
+  up.add(&P.d_SigT, sigT);
+  up.add(&P.d_mu, P.mu);
+  up.add(&P.d_w, P.w);
+  up.add(&P.d_tau, P.tau);
+  up.add(&P.d_lam, P.lam);
+  up.add(&P.d_a, P.a);
+  up.add(&P.d_eps, P.eps);
+  up.add(&P.d_WT, P.WT);
+  up.add(&P.d_eta0, P.eta0);
+  up.add(&P.d_ub, ub);
+  up.add(&P.d_st, st);
+  up.add(&P.d_sll, sll);
+  up.add(&P.d_theta, P.theta);
+  up.add(&P.d_theta_rows, P.theta_rows);
+  up.add(&P.d_theta_rw, P.theta_rw);
+  up.add(&P.d_slot_theta, P.slot_theta);
+  up.add(&P.d_slot_dir, P.slot_dir);
+  up.add(&P.d_slot_off, P.slot_off);
+  up.add(&P.d_pair_slot, P.pair_slot);
+  up.add(&P.d_pair_off, P.pair_off);
+  up.add(&P.d_pair_o, P.pair_o);
+  up.add(&P.d_pair_dir, P.pair_dir);
+  up.add(&P.d_pair_index, P.pair_index);
+  up.add(&P.d_grp[0], P.grp[0]);
+  up.add(&P.d_grp[1], P.grp[1]);
+  up.add(&P.d_cgrp[0], P.cgrp[0]);
+  up.add(&P.d_cgrp[1], P.cgrp[1]);
+  up.add(&P.d_E, E);
+  up.add(&P.d_A, A);
+  up.add(&P.d_alpha, alpha);
+  up.add(&P.d_bma, bma);
+  up.add(&P.d_g, g);
+  TRAP_TRY(up.commit(ctx));
   return TRAP_OK;
 }
 

@@ -13,9 +13,12 @@
 // half the Gaussian width 2 sin(Theta/2); the Gaussian factor is cut where
 // it falls below e^-43.
 #include <cmath>
+#include <mutex>
+#include <set>
 #include <vector>
 
 #include "faddeeva.h"
+
 #include "trap_internal.h"
 
 namespace trap {
@@ -653,13 +656,15 @@ __global__ void k_theta_average(long long per_z_out, int ng, int zc, const doubl
   if (M32) M32[out_offset + id] = (float)v;
 }
 
-int run_precompute(trap_ctx* ctx, int store_mask) {
-  Problem& P = ctx->pb;
-  Precomp& C = ctx->pre;
-  hipStream_t s = ctx->stream;
+// The Faddeeva and quadrature constants: computed once per process, copied to
+// each device's constant memory once (the copy waits for the device).
+static int load_constants(int device) {
+  static std::mutex mu;
   static bool coef_ready = false;
   static FaddeevaCoef hc;
   static double gt[16], gw[16];
+  static std::set<int> devices_loaded;
+  std::lock_guard<std::mutex> lk(mu);
   if (!coef_ready) {
     faddeeva_coefficients(&hc);
     // Gauss-Legendre 16 on [0,1] (Newton on P_16)
@@ -690,9 +695,20 @@ int run_precompute(trap_ctx* ctx, int store_mask) {
     }
     coef_ready = true;
   }
-  TRAP_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_fad), &hc, sizeof(hc)));
-  TRAP_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_gl_t), gt, sizeof(gt)));
-  TRAP_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_gl_w), gw, sizeof(gw)));
+  if (!devices_loaded.count(device)) {
+    TRAP_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_fad), &hc, sizeof(hc)));
+    TRAP_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_gl_t), gt, sizeof(gt)));
+    TRAP_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_gl_w), gw, sizeof(gw)));
+    devices_loaded.insert(device);
+  }
+  return TRAP_OK;
+}
+
+int run_precompute(trap_ctx* ctx, int store_mask) {
+  Problem& P = ctx->pb;
+  Precomp& C = ctx->pre;
+  hipStream_t s = ctx->stream;
+  TRAP_TRY(load_constants(ctx->device));
   const int nz = P.nz, nd = P.nd, nn = P.nn, nt = P.nt, nth = P.nth;
   const int nthr = P.nth_rows;                    // angles at which rows are computed
   const bool aa = P.prd_mode == TRAP_PRD_AA;
@@ -798,7 +814,6 @@ int run_precompute(trap_ctx* ctx, int store_mask) {
   TRAP_HIP(hipGetLastError());
   // right-hand side b = Lambda eps_th + t
   TRAP_TRY(formal_apply(ctx, C.d_epsth, C.d_b, 1, TRAP_FP64));
-  TRAP_HIP(hipStreamSynchronize(s));
   return TRAP_OK;
 }
 

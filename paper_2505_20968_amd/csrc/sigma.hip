@@ -1106,6 +1106,14 @@ std::mutex g_arena_mu;
 std::map<int, BatchArena> g_arena;
 
 void arena_free(BatchArena& a) {
+  for (StagingBuf& b : a.staging) {
+    if (b.ev) {
+      (void)hipEventSynchronize(b.ev);
+      (void)hipEventDestroy(b.ev);
+    }
+    if (b.host) (void)hipHostFree(b.host);
+  }
+  a.staging.clear();
   if (a.stream) (void)hipStreamSynchronize(a.stream);
   for (hipEvent_t e : a.ev) (void)hipEventDestroy(e);
   a.ev.clear();
@@ -1189,6 +1197,41 @@ void batch_arena_release(int device) {
   if (--it->second.users > 0) return;
   arena_free(it->second);
   g_arena.erase(it);
+}
+
+int stage_upload(trap_ctx* ctx, const void* host, size_t bytes, void* dev) {
+  if (bytes == 0) return TRAP_OK;
+  std::lock_guard<std::mutex> lk(g_arena_mu);
+  auto it = g_arena.find(ctx->device);
+  if (it == g_arena.end()) return fail(TRAP_ESTATE, "internal: no shared state for the device");
+  BatchArena& a = it->second;
+  StagingBuf* pick = nullptr;
+  for (StagingBuf& b : a.staging) {
+    if (b.cap < bytes) continue;
+    if (b.used) {
+      const hipError_t q = hipEventQuery(b.ev);
+      if (q == hipErrorNotReady) {
+        (void)hipGetLastError();         // not an error: the buffer is still being read
+        continue;
+      }
+      TRAP_HIP(q);
+    }
+    pick = &b;
+    break;
+  }
+  if (!pick) {
+    StagingBuf b;
+    b.cap = std::max<size_t>(bytes, size_t(1) << 20);
+    TRAP_HIP(hipHostMalloc(&b.host, b.cap));
+    TRAP_HIP(hipEventCreateWithFlags(&b.ev, hipEventDisableTiming));
+    a.staging.push_back(b);
+    pick = &a.staging.back();
+  }
+  std::memcpy(pick->host, host, bytes);
+  TRAP_HIP(hipMemcpyAsync(dev, pick->host, bytes, hipMemcpyHostToDevice, ctx->stream));
+  TRAP_HIP(hipEventRecord(pick->ev, ctx->stream));
+  pick->used = true;
+  return TRAP_OK;
 }
 
 int sigma_batch_ready(trap_ctx* ctx) {

@@ -184,6 +184,7 @@ struct GmresRun {
   int m = 0, prec = TRAP_FP64, phase = GP_DONE, status = TRAP_OK;
   int outer = 0, j = 0, max_outer = 1;
   bool p2 = false;            // an Arnoldi step waits for its second reduction
+  bool begin_pending = false; // ||b|| and the initial-guess check are read at the first step
   double bnorm = 0, beta = 0, target = 0, res = 0, rel = 0;
   std::vector<double> H, cs, sn, g, h;
   double* hbuf = nullptr;     // pinned host copy of the reductions, 2 (m + 2)
@@ -215,6 +216,16 @@ int axpy_async(trap_ctx* ctx, GmresRun& R, const double* V, int ncols, const dou
 }
 
 }  // namespace
+
+// pinned host buffer layout (4 (m + 2) doubles): [0, m + 2) first reduction,
+// [m + 2, 2 (m + 2)) second reduction, then the initial-guess flag, the
+// update coefficients, and ||b||^2 in the last slot
+static int* begin_flag(GmresRun& R) { return reinterpret_cast<int*>(R.hbuf + 2 * (R.m + 2)); }
+static double* begin_bnorm2(GmresRun& R) { return R.hbuf + 4 * (R.m + 2) - 1; }
+
+__global__ void k_fill_int(int* p, int v) {
+  if (threadIdx.x == 0) p[0] = v;
+}
 
 static void run_finish(GmresRun& R, int status) {
   R.phase = GP_DONE;
@@ -270,28 +281,36 @@ int gmres_begin(trap_ctx* ctx, const trap_solve_opts* opts, double* I) {
   R.partial = K.dots;
   R.dres = K.dots + (size_t)kBlocks * (m + 2);
   R.t0 = std::chrono::steady_clock::now();
-  // initial guess must be finite; ||b|| (one synchronisation)
+  // the initial guess must be finite, and ||b||: enqueued here, read by the
+  // first step after its synchronisation (so beginning a solve never waits)
   int* dflag = reinterpret_cast<int*>(K.red);
-  TRAP_HIP(hipMemsetAsync(dflag, 0, sizeof(int), ctx->stream));
+  hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, ctx->stream, dflag, 0);
   hipLaunchKernelGGL(k_nonfinite, dim3(kBlocks), dim3(256), 0, ctx->stream, N, I, dflag);
   TRAP_HIP(hipGetLastError());
-  int* hflag = reinterpret_cast<int*>(R.hbuf + 2 * (m + 2));
+  int* hflag = begin_flag(R);
   *hflag = 0;
   TRAP_HIP(hipMemcpyAsync(hflag, dflag, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
-  TRAP_TRY(dots_async(ctx, R, ctx->pre.d_b, 1, ctx->pre.d_b, R.hbuf));
-  TRAP_HIP(hipStreamSynchronize(ctx->stream));
-  if (*hflag) {
-    run_finish(R, fail(TRAP_ENAN, "non-finite initial guess"));
-    return R.status;
-  }
-  R.bnorm = std::sqrt(std::max(R.hbuf[0], 0.0));
-  if (!(R.bnorm > 0)) {
-    run_finish(R, fail(TRAP_EINVAL, "zero right-hand side"));
-    return R.status;
-  }
+  TRAP_TRY(dots_async(ctx, R, ctx->pre.d_b, 1, ctx->pre.d_b, begin_bnorm2(R)));
+  R.begin_pending = true;
   R.phase = GP_RESID_OUTER;
   R.status = 1;
   return TRAP_OK;
+}
+
+// the deferred checks of gmres_begin; false when they ended the run
+static bool begin_checks(GmresRun& R) {
+  if (!R.begin_pending) return true;
+  R.begin_pending = false;
+  if (*begin_flag(R)) {
+    run_finish(R, fail(TRAP_ENAN, "non-finite initial guess"));
+    return false;
+  }
+  R.bnorm = std::sqrt(std::max(*begin_bnorm2(R), 0.0));
+  if (!(R.bnorm > 0)) {
+    run_finish(R, fail(TRAP_EINVAL, "zero right-hand side"));
+    return false;
+  }
+  return true;
 }
 
 namespace {
@@ -394,6 +413,7 @@ int arnoldi_finish(trap_ctx* ctx, GmresRun& R, double hn);
 int unit_after1(trap_ctx* ctx, GmresRun& R) {
   Work& K = ctx->wk;
   const long long N = R.N;
+  if (!begin_checks(R)) return TRAP_OK;
   switch (R.phase) {
     case GP_RESID_OUTER: {
       const double rn = std::sqrt(std::max(R.hbuf[0], 0.0));

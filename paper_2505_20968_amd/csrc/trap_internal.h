@@ -182,16 +182,37 @@ namespace trap {
 // allocation helper (records into ctx->bufs)
 int dalloc(trap_ctx* ctx, void** p, size_t bytes);
 void free_all(trap_ctx* ctx);
-int upload(trap_ctx* ctx, void** dst, const void* src, size_t bytes);
 
 template <typename T>
 int dalloc_t(trap_ctx* ctx, T** p, size_t count) {
   return dalloc(ctx, reinterpret_cast<void**>(p), count * sizeof(T));
 }
-template <typename T>
-int upload_t(trap_ctx* ctx, T** dst, const std::vector<T>& v) {
-  return upload(ctx, reinterpret_cast<void**>(dst), v.data(), v.size() * sizeof(T));
-}
+// Host -> device copy of `bytes` from pageable host memory through a pinned
+// staging buffer of the device's pool (sigma.hip): returns once the data is in
+// the staging buffer; the copy itself is enqueued on the context's stream.
+int stage_upload(trap_ctx* ctx, const void* host, size_t bytes, void* dev);
+
+// Many host arrays uploaded as one device allocation (256-byte aligned items,
+// at least 16 bytes each) with one staged copy.
+struct UploadBatch {
+  struct Item {
+    void** dst;
+    const void* src;
+    size_t bytes, off;
+  };
+  std::vector<Item> items;
+  size_t total = 0;
+  void add(void** dst, const void* src, size_t bytes) {
+    const size_t off = (total + 255) & ~size_t(255);
+    items.push_back(Item{dst, src, bytes, off});
+    total = off + (bytes ? bytes : 16);
+  }
+  template <typename T>
+  void add(T** dst, const std::vector<T>& v) {
+    add(reinterpret_cast<void**>(dst), v.data(), v.size() * sizeof(T));
+  }
+  int commit(trap_ctx* ctx);
+};
 
 // host setup (host_setup.cpp)
 int build_problem(trap_ctx* ctx, const trap_atom_desc* atom, const trap_problem_desc* pd);
@@ -285,9 +306,17 @@ struct GVec {              // FP64 <-> FP32 conversions around the FP32 operator
   double* y64;             // out: x - Lambda Sigma x
 };
 
-// Per-device state of grouped launches: a stream, a pinned staging buffer and
-// its device copy for the argument records, and events.  Created with the
-// first context on a device and released with the last.
+// Per-device state shared by the contexts of a device: for grouped launches a
+// stream, a pinned staging buffer and its device copy for the argument records,
+// and events; pinned buffers for host-to-device uploads.  Created with the
+// first context on a device and released with the last (freeing pinned
+// memory waits for the device, so it is not done per context).
+struct StagingBuf {
+  void* host = nullptr;       // pinned
+  size_t cap = 0;
+  hipEvent_t ev = nullptr;    // recorded after the copy out of the buffer
+  bool used = false;
+};
 struct BatchArena {
   hipStream_t stream = nullptr;
   unsigned char* host = nullptr;
@@ -295,6 +324,7 @@ struct BatchArena {
   size_t cap = 0;
   hipEvent_t copied = nullptr, done = nullptr;
   std::vector<hipEvent_t> ev;
+  std::vector<StagingBuf> staging;   // pinned buffers of stage_upload
   int users = 0;
 };
 void batch_arena_acquire(int device);

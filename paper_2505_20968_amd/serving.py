@@ -3,11 +3,13 @@
 Requests (an atom, grids and a seeded atmosphere) arrive over time.  The
 server admits queued requests in arrival order while the device-memory budget
 (computed per request by ``trap_footprint``) and the slot limit allow; each
-admitted request gets its own context and HIP stream, runs its precompute, and
-starts a GMRES solve.  All admitted solves then advance together through
-``trap_gmres_step_batch``: one step enqueues the next unit of every request's
-solve on that request's stream before waiting, so their device work overlaps,
-and the host synchronises at most twice per step for the whole batch.  A
+admitted request gets its own context and HIP stream, on which its precompute
+and the start of its GMRES solve are enqueued without waiting.  Requests whose
+precompute has finished advance together through ``trap_gmres_step_batch``:
+one step enqueues the next unit of every such request's solve before waiting,
+so their device work overlaps (and their FP32 operator applies share
+launches), and the host synchronises at most twice per step for the whole
+batch; precomputes of newly admitted requests run on the device meanwhile.  A
 finished request releases its memory at once, so requests that arrived while
 others were on the GPU join the batch as soon as memory frees up.  Krylov
 state stays on the device for the whole solve.
@@ -129,6 +131,7 @@ class DeviceBackend:
         self.opts = dict(tol=tol, restart=restart, max_iters=max_iters, max_outer=max_outer,
                          inner=TRAP_FP32 if self.mixed else TRAP_FP64, inner_tol=inner_tol)
         self._footprint = footprint
+        self.admit_parts = {"context": 0.0, "set_problem": 0.0, "precompute": 0.0, "begin": 0.0}
 
     def footprint(self, problem) -> int:
         # library allocations plus the solution vector held by the caller
@@ -136,24 +139,45 @@ class DeviceBackend:
         return self._footprint(problem, self.store) + 8 * n
 
     def admit(self, problem):
+        """Set up the request and enqueue its precompute and the start of its
+        solve on its own stream; returns without waiting for the device."""
         from .trap import Context
         torch = self.torch
+        t0 = time.perf_counter()
         stream = torch.cuda.Stream(self.device)
         ctx = Context(self.device, stream)
+        t1 = time.perf_counter()
         ctx.set_problem(problem)
+        t2 = time.perf_counter()
         ctx.precompute(self.store)
+        t3 = time.perf_counter()
         with torch.cuda.stream(stream):
             x = torch.zeros(ctx.shape, dtype=torch.float64, device=f"cuda:{self.device}")
-        stream.synchronize()
         ctx.gmres_begin(x, **self.opts)
-        return (ctx, x, stream)
+        ready = torch.cuda.Event()
+        ready.record(stream)
+        t4 = time.perf_counter()
+        for k, dt in zip(self.admit_parts, (t1 - t0, t2 - t1, t3 - t2, t4 - t3)):
+            self.admit_parts[k] += dt
+        return {"ctx": ctx, "x": x, "stream": stream, "ready": ready, "is_ready": False}
 
     def step(self, handles):
+        """One batched GMRES step over the requests whose precompute has
+        finished; the others keep running on the device meanwhile (status 1).
+        When none has finished, wait for the oldest."""
         from .trap import gmres_step_batch
-        return gmres_step_batch([h[0] for h in handles])
+        for h in handles:
+            if not h["is_ready"] and h["ready"].query():
+                h["is_ready"] = True
+        if not any(h["is_ready"] for h in handles):
+            handles[0]["ready"].synchronize()
+            handles[0]["is_ready"] = True
+        live = [h for h in handles if h["is_ready"]]
+        st = iter(gmres_step_batch([h["ctx"] for h in live]))
+        return [next(st) if h["is_ready"] else 1 for h in handles]
 
     def finish(self, handle):
-        ctx, x, _ = handle
+        ctx, x = handle["ctx"], handle["x"]
         stats = ctx.gmres_end(raise_on_noconv=False)
         em = ctx.emergent(x)
         ctx.close()
@@ -188,4 +212,5 @@ def serve(requests: Sequence[Request], precision: str = "mixed", mem_budget: Opt
             "n_failed": sum(1 for r in out if r.status not in (0, TRAP_ENOMEM)),
             "p50_s": pct(0.5), "p99_s": pct(0.99), "peak_active": sched.peak_active,
             "peak_bytes": sched.peak_used, "steps": sched.steps,
-            "host_s": {"admit": sched.time_admit, "step": sched.time_step, "finish": sched.time_finish}}
+            "host_s": {"admit": sched.time_admit, "step": sched.time_step, "finish": sched.time_finish,
+                       "admit_parts": dict(backend.admit_parts)}}
