@@ -144,6 +144,11 @@ int trap_create(trap_ctx** out, int device, void* stream) {
     ctx->max_lds = std::min(lds, 160 * 1024);
   else
     (void)hipGetLastError();
+  int ncu = 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && ncu > 0)
+    ctx->n_cu = ncu;
+  else
+    (void)hipGetLastError();
   batch_arena_acquire(device);
   *out = ctx;
   return TRAP_OK;

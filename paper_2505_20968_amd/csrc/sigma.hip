@@ -173,6 +173,47 @@ template <typename T> struct ContractCfg;
 template <> struct ContractCfg<float> { static constexpr int BST = 136; };   // 128 columns + pad
 template <> struct ContractCfg<double> { static constexpr int BST = 72; };   // 64 columns + pad
 
+// The products of one K chunk: for step (h, jj) every column tile jt takes
+// its B value from LDS (row 8 h + jj of the lane's k group) and the lane's
+// kernel-row fragment.  The B values of step h + 1 are read into registers
+// before the products of step h are issued, so LDS latency overlaps the
+// matrix cores.
+template <typename T, int NH, int NCT>
+__device__ __forceinline__ void mfma_chunk(const T* bcol, int bst, const typename T2of<T>::type (&mf)[NH],
+                                           typename MfmaOp<T>::acc_t (&acc)[NCT]) {
+  using Op = MfmaOp<T>;
+  T bc[2][NCT], bx[2][NCT];
+#pragma unroll
+  for (int jj = 0; jj < 2; ++jj)
+#pragma unroll
+    for (int jt = 0; jt < NCT; ++jt) bc[jj][jt] = bcol[jj * bst + jt * 16];
+#pragma unroll
+  for (int h = 0; h < NH; ++h) {
+    if (h + 1 < NH) {
+#pragma unroll
+      for (int jj = 0; jj < 2; ++jj)
+#pragma unroll
+        for (int jt = 0; jt < NCT; ++jt) bx[jj][jt] = bcol[(8 * (h + 1) + jj) * bst + jt * 16];
+    }
+    // keep the reads of step h + 1 ahead of the products of step h (the
+    // scheduler would otherwise sink each read next to its use)
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int jj = 0; jj < 2; ++jj) {
+      const T bf = jj ? mf[h].y : mf[h].x;
+#pragma unroll
+      for (int jt = 0; jt < NCT; ++jt) acc[jt] = Op::run(bc[jj][jt], bf, acc[jt]);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    if (h + 1 < NH) {
+#pragma unroll
+      for (int jj = 0; jj < 2; ++jj)
+#pragma unroll
+        for (int jt = 0; jt < NCT; ++jt) bc[jj][jt] = bx[jj][jt];
+    }
+  }
+}
+
 template <typename T, int NH, int NCT>
 __device__ __forceinline__ void contract_block(int rb, int g, int zl, int z0, int nth, int nt, int nn, int ldm, int nd,
                                                int nkc, const T* __restrict__ M, const T* __restrict__ Ibar,
@@ -233,18 +274,7 @@ __device__ __forceinline__ void contract_block(int rb, int g, int zl, int z0, in
       }
     }
     __syncthreads();
-    const T* bcol = Bs + 2 * lk * BST + lr;
-#pragma unroll
-    for (int h = 0; h < NH; ++h) {
-#pragma unroll
-      for (int jj = 0; jj < 2; ++jj) {
-        const T bf = jj ? mf[h].y : mf[h].x;
-        const T* brow = bcol + (8 * h + jj) * BST;
-#pragma unroll
-        for (int jt = 0; jt < NCT; ++jt)
-          acc[jt] = Op::run(brow[jt * 16], bf, acc[jt]);
-      }
-    }
+    mfma_chunk<T, NH, NCT>(Bs + 2 * lk * BST + lr, BST, mf, acc);
   }
   // lane holds C[grow][slot s0 + 4 jt + lk][Stokes r]
   if (grow < R) {
@@ -289,6 +319,223 @@ __global__ void __launch_bounds__(512, 2) k_contract(int z0, int nth, int nt, in
 static void contract_chunks(int ldm, int* nkc, int* nh) {
   *nkc = (ldm + 127) / 128;
   *nh = (ldm + 8 * *nkc - 1) / (8 * *nkc);
+}
+
+// ---- persistent, software-pipelined FP32 contraction
+// The same products as k_contract, with one block per compute unit looping
+// over the tiles (row block, height, column group) x K chunks.  While the
+// matrix cores work on stage s (kernel-row fragments in registers, comoving
+// tile in LDS buffer s % 2), the block already has the loads of stage s + 1 in
+// flight: its kernel-row fragments into a second register set and its
+// comoving tile into registers, written to the other LDS buffer once the
+// products are issued.  One barrier per stage.  The slot -> direction table is
+// copied to LDS at the start so the comoving gather has no dependent global
+// load.  Groups with up to 32 slots (8 column tiles) are processed first, then
+// those with up to 16.
+template <int NH, int NCT>
+__device__ __forceinline__ void contract_pipe_class(
+    int first, int count, int step, int gbase, int zc, int z0, int nth, int nt, int nn, int ldm, int nd, int nkc,
+    int rb_n, const float* __restrict__ M, const float* __restrict__ Ibar, const int* __restrict__ cgrp,
+    const int* sdir, float* __restrict__ W, int nslot, float* Bs0, float* Bs1) {
+  using acc_t = floatx4_t;
+  constexpr int KCH = 8 * NH;
+  constexpr int BST = ContractCfg<float>::BST;
+  constexpr int CG = 4 * NCT;
+  constexpr int NB = (KCH * CG + 511) / 512;
+  const int ntile = count > first ? (count - first + step - 1) / step : 0;
+  const int nst = ntile * nkc;
+  if (nst == 0) return;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int R = 2 * nt * nn;
+  const int per_g = zc * rb_n;
+  struct St {
+    int rb, zl, g, kc;
+  };
+  auto decode = [&](int s) {
+    St d;
+    const int t = first + (s / nkc) * step;
+    d.kc = s % nkc;
+    d.g = gbase + t / per_g;
+    const int r = t % per_g;
+    d.zl = r / rb_n;
+    d.rb = r % rb_n;
+    return d;
+  };
+  // Loads read a valid clamped address and keep the raw values; the masks
+  // (zero past the last k, zero past the last slot or frequency of the tile)
+  // are applied when the values are consumed, after the products of the
+  // current stage are issued, so no load of the next stage is waited for early.
+  // Rows past the end need no mask: their outputs are not stored.
+  unsigned amask = 0;
+  auto load_a = [&](const St& d, float2 (&dst)[NH]) {
+    const int th = cgrp[3 * d.g];
+    const int grow = d.rb * kRowsPerBlock + wave * 16 + lr;
+    const float* arow = M + (((size_t)(z0 + d.zl) * nth + th) * (size_t)R + min(grow, R - 1)) * ldm;
+    const int k0 = d.kc * KCH;
+    amask = 0;
+#pragma unroll
+    for (int h = 0; h < NH; ++h) {
+      const int k = k0 + 2 * (4 * h + lk);
+      dst[h] = *reinterpret_cast<const float2*>(arow + min(k, ldm - 2));
+      amask |= (k < ldm ? 1u : 0u) << h;
+    }
+  };
+  float4 bn[NB];
+  unsigned bmask = 0;
+  auto load_b = [&](const St& d) {
+    const int s0 = cgrp[3 * d.g + 1], cnt = cgrp[3 * d.g + 2];
+    const float* Ib = Ibar + (size_t)d.zl * nd * nn * 4;
+    const int k0 = d.kc * KCH;
+    int dir[NB];
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      const int sl = (tid + 512 * q) / KCH;
+      dir[q] = sdir[s0 + min(sl, cnt - 1)];
+    }
+    bmask = 0;
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      const int e = tid + 512 * q;
+      const int sl = e / KCH, kk = e - sl * KCH, k = k0 + kk;
+      bn[q] = *reinterpret_cast<const float4*>(Ib + ((size_t)dir[q] * nn + min(k, nn - 1)) * 4);
+      bmask |= (e < KCH * CG && sl < cnt && k < nn ? 1u : 0u) << q;
+    }
+  };
+  auto store_b = [&](float* Bs) {
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      const int e = tid + 512 * q;
+      if (e < KCH * CG) {
+        const int sl = e / KCH, kk = e - sl * KCH;
+        const bool ok = (bmask >> q) & 1u;
+        const float4 v = ok ? bn[q] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        *reinterpret_cast<float4*>(Bs + (size_t)kk * BST + 4 * sl) = v;
+      }
+    }
+  };
+  auto take_a = [&](float2 (&dst)[NH], const float2 (&src)[NH]) {
+#pragma unroll
+    for (int h = 0; h < NH; ++h) {
+      const bool ok = (amask >> h) & 1u;
+      dst[h].x = ok ? src[h].x : 0.0f;
+      dst[h].y = ok ? src[h].y : 0.0f;
+    }
+  };
+  float2 mf[NH], mfn[NH];
+  acc_t acc[NCT];
+#pragma unroll
+  for (int j = 0; j < NCT; ++j)
+    for (int r = 0; r < 4; ++r) acc[j][r] = 0.0f;
+  {
+    const St d0 = decode(0);
+    load_a(d0, mfn);
+    load_b(d0);
+    store_b(Bs0);
+    take_a(mf, mfn);
+  }
+  __syncthreads();
+  for (int s = 0; s < nst; ++s) {
+    const St d = decode(s);
+    const bool more = s + 1 < nst;
+    if (more) {
+      const St dn = decode(s + 1);
+      load_a(dn, mfn);
+      load_b(dn);
+    }
+    mfma_chunk<float, NH, NCT>(((s & 1) ? Bs1 : Bs0) + 2 * lk * BST + lr, BST, mf, acc);
+    if (d.kc == nkc - 1) {
+      // lane holds C[grow][slot s0 + 4 jt + lk][Stokes r]
+      const int s0 = cgrp[3 * d.g + 1], cnt = cgrp[3 * d.g + 2];
+      const int grow = d.rb * kRowsPerBlock + wave * 16 + lr;
+      if (grow < R) {
+        const int rt = grow / (2 * nn), rc = (grow / nn) & 1, rn = grow % nn;
+#pragma unroll
+        for (int jt = 0; jt < NCT; ++jt) {
+          const int sl = 4 * jt + lk;
+          if (sl < cnt) {
+            float4 o;
+            o.x = acc[jt][0]; o.y = acc[jt][1]; o.z = acc[jt][2]; o.w = acc[jt][3];
+            *reinterpret_cast<float4*>(W + (((((size_t)d.zl * nt + rt) * nslot + s0 + sl) * 2 + rc) * nn + rn) * 4) = o;
+          }
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < NCT; ++j)
+        for (int r = 0; r < 4; ++r) acc[j][r] = 0.0f;
+    }
+    if (more) {
+      store_b((s & 1) ? Bs0 : Bs1);
+      take_a(mf, mfn);
+    }
+    __syncthreads();
+  }
+}
+
+template <int NH>
+__global__ void __launch_bounds__(512, 1) k_contract_pipe(int z0, int zc, int nth, int nt, int nn, int ldm, int nd,
+                                                          int nkc, int rb_n, const float* __restrict__ M,
+                                                          const float* __restrict__ Ibar,
+                                                          const int* __restrict__ cgrp, int ngrp, int n8,
+                                                          const int* __restrict__ slot_dir, float* __restrict__ W,
+                                                          int nslot) {
+  extern __shared__ __align__(16) unsigned char psh[];
+  constexpr int KCH = 8 * NH;
+  float* Bs0 = reinterpret_cast<float*>(psh);
+  float* Bs1 = Bs0 + KCH * ContractCfg<float>::BST;
+  int* sdir = reinterpret_cast<int*>(Bs1 + KCH * ContractCfg<float>::BST);
+  for (int i = threadIdx.x; i < nslot; i += blockDim.x) sdir[i] = slot_dir[i];
+  __syncthreads();
+  const int per_g = zc * rb_n;
+  contract_pipe_class<NH, 8>(blockIdx.x, n8 * per_g, gridDim.x, 0, zc, z0, nth, nt, nn, ldm, nd, nkc, rb_n, M,
+                             Ibar, cgrp, sdir, W, nslot, Bs0, Bs1);
+  contract_pipe_class<NH, 4>(blockIdx.x, (ngrp - n8) * per_g, gridDim.x, n8, zc, z0, nth, nt, nn, ldm, nd, nkc,
+                             rb_n, M, Ibar, cgrp, sdir, W, nslot, Bs0, Bs1);
+}
+
+static size_t contract_pipe_lds(int nh, int nslot) {
+  return (size_t)2 * 8 * nh * ContractCfg<float>::BST * sizeof(float) + (size_t)nslot * sizeof(int);
+}
+
+template <int NH>
+static int launch_contract_pipe_nh(trap_ctx* ctx, int zc, int z0, const float* Mk, const float* Ibar, float* W,
+                                   size_t lds, int nkc) {
+  Problem& P = ctx->pb;
+  const int ngrp = (int)P.cgrp[1].size() / 3;
+  const int rb_n = ceil_div(2LL * P.nt * P.nn, kRowsPerBlock);
+  const long long ntiles = (long long)ngrp * zc * rb_n;
+  const int grid = (int)std::min<long long>(ntiles, ctx->n_cu);
+  auto kern = k_contract_pipe<NH>;
+  if (lds > 64 * 1024)
+    TRAP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)lds));
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(512), lds, ctx->stream, z0, zc, P.nth, P.nt, P.nn, P.ldm, P.nd, nkc,
+                     rb_n, Mk, Ibar, P.d_cgrp[1], ngrp, P.cgrp_n8[1], P.d_slot_dir, W, P.nslot);
+  TRAP_HIP(hipGetLastError());
+  return TRAP_OK;
+}
+
+// 1 when launched, 0 when the problem does not fit the pipelined kernel's LDS
+static int launch_contract_pipe(trap_ctx* ctx, int zc, int z0, const float* Mk, const float* Ibar, float* W) {
+  Problem& P = ctx->pb;
+  if ((int)P.cgrp[1].size() / 3 == 0) return 1;
+  int nkc, nh;
+  contract_chunks(P.ldm, &nkc, &nh);
+  const size_t lds = contract_pipe_lds(nh, P.nslot);
+  if (lds > (size_t)ctx->max_lds) return 0;
+  switch (nh) {
+#define TRAP_PIPE_CASE(NHV) \
+  case NHV:                 \
+    TRAP_TRY(launch_contract_pipe_nh<NHV>(ctx, zc, z0, Mk, Ibar, W, lds, nkc)); \
+    return 1;
+    TRAP_PIPE_CASE(1) TRAP_PIPE_CASE(2) TRAP_PIPE_CASE(3) TRAP_PIPE_CASE(4)
+    TRAP_PIPE_CASE(5) TRAP_PIPE_CASE(6) TRAP_PIPE_CASE(7) TRAP_PIPE_CASE(8)
+    TRAP_PIPE_CASE(9) TRAP_PIPE_CASE(10) TRAP_PIPE_CASE(11) TRAP_PIPE_CASE(12)
+    TRAP_PIPE_CASE(13) TRAP_PIPE_CASE(14) TRAP_PIPE_CASE(15) TRAP_PIPE_CASE(16)
+#undef TRAP_PIPE_CASE
+    default:
+      return fail(TRAP_EINVAL, "internal: bad contraction chunk");
+  }
 }
 
 template <typename T>
@@ -947,7 +1194,13 @@ static int sigma_apply_t(trap_ctx* ctx, const T* I, T* eps, int prec, int add_th
       TRAP_TRY(dalloc(ctx, &K.W[pi], (size_t)K.zchunk * nt * P.nslot * 2 * nn * 4 * sizeof(T)));
       W = static_cast<T*>(K.W[pi]);
     }
-    TRAP_TRY(launch_contract<T>(ctx, zc, z0, Mk, Ibar + (size_t)z0 * nd * nn * 4, W));
+    if constexpr (sizeof(T) == sizeof(float)) {
+      const int launched = launch_contract_pipe(ctx, zc, z0, Mk, Ibar + (size_t)z0 * nd * nn * 4, W);
+      if (launched < 0) return launched;
+      if (!launched) TRAP_TRY(launch_contract<T>(ctx, zc, z0, Mk, Ibar + (size_t)z0 * nd * nn * 4, W));
+    } else {
+      TRAP_TRY(launch_contract<T>(ctx, zc, z0, Mk, Ibar + (size_t)z0 * nd * nn * 4, W));
+    }
     prof_end(ctx, pr);
     // 4. angular / sublevel sum into Eb (chunk-local heights)
     pr = prof_begin(ctx, TRAP_STAGE_ANGULAR);

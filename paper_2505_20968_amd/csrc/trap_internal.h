@@ -175,6 +175,7 @@ struct trap_ctx {
   int path = 0;                     // TRAP_PATH_* of trap.h
   int prd_mode = 0;                 // TRAP_PRD_* of trap.h, applied at trap_set_problem
   int max_lds = 64 * 1024;          // device limit of LDS bytes per block
+  int n_cu = 256;                   // compute units of the device
   std::vector<trap::DevBuf> bufs;   // every allocation the context made
 };
 

@@ -8,6 +8,10 @@ cost grows with the heights; the GPU path is the same at any height count).
   of the chromosphere-like generator.  Reference: tests/golden/cfg3_nz3_emergent.txt
   (every 4th frequency), written by tests/golden/make_reduced_emergent.py from
   the oracle alone, solved to 1e-11.
+* The Ly-alpha-like line (fine-structure splitting of 0.3 Doppler width,
+  damping 1e-2 - 1e-1, B up to 300 G): 301 frequencies on a sinh-spaced grid
+  to +-1000 Doppler widths, 16 mu x 8 azimuths, 2 heights.  Reference:
+  tests/golden/cfg4_nz2_emergent.txt (every 4th frequency), same script.
 Both the plain FP64 GMRES and the mixed-precision solve (FP32 operator inside
 FP64 iterative refinement) are checked to the parity contract: 1e-6 relative
 on I, 1e-4 absolute on Q/I, U/I, V/I; the FP64 solve also to 1e-8 relative.
@@ -17,7 +21,7 @@ import os
 import numpy as np
 import pytest
 
-from workloads import cfg3
+from workloads import cfg3, cfg4
 
 pytestmark = pytest.mark.gpu
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -30,13 +34,19 @@ def _golden(name, shape):
     return ref, g[:, 0].astype(int), g[:, 1].astype(int)
 
 
+CASES = {"doublet": (lambda: cfg3(n_z=3), "cfg3_nz3_emergent.txt"),
+         "lyman_alpha": (lambda: cfg4(n_z=2), "cfg4_nz2_emergent.txt")}
+
+
 @pytest.mark.parametrize("inner", ["fp64", "mixed"])
-def test_doublet_reduced_heights_matches_oracle(inner):
+@pytest.mark.parametrize("case", list(CASES))
+def test_two_term_reduced_heights_matches_oracle(case, inner):
     import torch
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     from paper_2505_20968_amd import Context, TRAP_FP32, TRAP_FP64
-    prob = cfg3(n_z=3)
+    make, golden = CASES[case]
+    prob = make()
     ctx = Context(0)
     ctx.set_problem(prob)
     ctx.precompute(3 if inner == "mixed" else 1)
@@ -45,11 +55,11 @@ def test_doublet_reduced_heights_matches_oracle(inner):
                          inner=TRAP_FP32 if inner == "mixed" else TRAP_FP64, inner_tol=1e-4, max_outer=10)
     em = ctx.emergent(x)
     ctx.close()
-    ref, o, n = _golden("cfg3_nz3_emergent.txt", em.shape)
+    ref, o, n = _golden(golden, em.shape)
     got, want = em[o, n], ref[o, n]
     relI = np.abs(got[:, 0] - want[:, 0]) / np.abs(want[:, 0])
     pol = max(np.abs(got[:, s] / got[:, 0] - want[:, s] / want[:, 0]).max() for s in (1, 2, 3))
-    print(f"[doublet {inner}] {st['inner_iters']} iters, res {st['final_rel_res']:.2e}, "
+    print(f"[{case} {inner}] {st['inner_iters']} iters, res {st['final_rel_res']:.2e}, "
           f"max rel I {relI.max():.2e}, max pol {pol:.2e}", flush=True)
     assert st["final_rel_res"] < 1e-10
     assert relI.max() < (1e-8 if inner == "fp64" else 1e-6)
