@@ -121,7 +121,7 @@ class DeviceBackend:
     """GPU backend: one context and HIP stream per request, batched GMRES steps."""
 
     def __init__(self, device: int = 0, precision: str = "mixed", tol: float = 1e-8, restart: int = 40,
-                 inner_tol: float = 1e-4, max_outer: int = 10, max_iters: int = 2000):
+                 inner_tol: float = 1e-7, max_outer: int = 10, max_iters: int = 2000):
         import torch
         from .trap import TRAP_FP32, TRAP_FP64, footprint
         self.torch = torch

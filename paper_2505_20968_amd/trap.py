@@ -231,7 +231,7 @@ class Context:
         _check(self.lib.trap_rhs(self.h, self._vec(b, TRAP_FP64)))
 
     def gmres_solve(self, I, tol: float = 1e-8, restart: int = 40, max_iters: int = 2000,
-                    inner: int = TRAP_FP64, max_outer: int = 8, inner_tol: float = 1e-5,
+                    inner: int = TRAP_FP64, max_outer: int = 8, inner_tol: float = 1e-7,
                     raise_on_noconv: bool = True):
         o = SolveOpts(tol=tol, restart=restart, max_iters=max_iters, max_outer=max_outer, inner=inner,
                       inner_tol=inner_tol)
@@ -244,7 +244,7 @@ class Context:
                 "final_rel_res": st.final_rel_res, "ms_total": st.ms_total, "status": code}
 
     def gmres_begin(self, I, tol: float = 1e-8, restart: int = 40, max_iters: int = 2000,
-                    inner: int = TRAP_FP64, max_outer: int = 8, inner_tol: float = 1e-5):
+                    inner: int = TRAP_FP64, max_outer: int = 8, inner_tol: float = 1e-7):
         """Start a solve that trap_gmres_step_batch advances (see gmres_step_batch)."""
         o = SolveOpts(tol=tol, restart=restart, max_iters=max_iters, max_outer=max_outer, inner=inner,
                       inner_tol=inner_tol)
