@@ -142,7 +142,9 @@ int trap_destroy(trap_ctx* ctx);
  * spline coefficient maps of Sect. 6.2), uploaded to the device with one copy
  * enqueued on the context's stream (the call returns once the host work is
  * done).  Replaces any previous problem of the context (waiting for the work
- * still queued on it). */
+ * still queued on it); the previous problem's device allocations are kept and
+ * reused by size for the new one, those left over are freed at the next
+ * trap_set_problem or at trap_destroy (trap_get_info counts them). */
 int trap_set_problem(trap_ctx* ctx, const trap_atom_desc* atom, const trap_problem_desc* prob);
 
 /* Device-side precompute (Sect. 4.3, App. C-E): the propagation matrix and

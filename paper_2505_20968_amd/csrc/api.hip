@@ -22,6 +22,14 @@ int fail(int code, const std::string& msg) {
 int dalloc(trap_ctx* ctx, void** p, size_t bytes) {
   void* q = nullptr;
   if (bytes == 0) bytes = 16;
+  // a buffer of the same size kept from the context's previous problem
+  for (size_t i = 0; i < ctx->spare.size(); ++i)
+    if (ctx->spare[i].bytes == bytes) {
+      ctx->bufs.push_back(ctx->spare[i]);
+      ctx->spare.erase(ctx->spare.begin() + i);
+      *p = ctx->bufs.back().p;
+      return TRAP_OK;
+    }
   hipError_t e = hipMalloc(&q, bytes);
   if (e != hipSuccess) {
     (void)hipGetLastError();
@@ -33,11 +41,20 @@ int dalloc(trap_ctx* ctx, void** p, size_t bytes) {
   return TRAP_OK;
 }
 
+// Releasing device memory waits for the whole device, so a context keeps the
+// allocations of its previous problem and hands them out again by exact size
+// (same-shaped problems in a row allocate and free nothing); spares not
+// reused by the next problem are freed when that one is replaced.
+void release_spare(trap_ctx* ctx) {
+  for (auto& b : ctx->spare) (void)hipFree(b.p);
+  ctx->spare.clear();
+}
+
 void free_all(trap_ctx* ctx) {
   if (!ctx->bufs.empty()) (void)hipStreamSynchronize(ctx->stream);
   gmres_release(ctx);
-  for (auto& b : ctx->bufs) (void)hipFree(b.p);
-  ctx->bufs.clear();
+  release_spare(ctx);
+  ctx->spare.swap(ctx->bufs);
   ctx->pb = Problem();
   ctx->pre = Precomp();
   ctx->wk = Work();
@@ -48,12 +65,9 @@ int UploadBatch::commit(trap_ctx* ctx) {
   if (items.empty()) return TRAP_OK;
   void* base = nullptr;
   TRAP_TRY(dalloc(ctx, &base, total));
-  std::vector<unsigned char> h(total, 0);
-  for (const Item& it : items) {
-    if (it.bytes) std::memcpy(h.data() + it.off, it.src, it.bytes);
+  for (const Item& it : items)
     if (it.dst) *it.dst = static_cast<unsigned char*>(base) + it.off;
-  }
-  return stage_upload(ctx, h.data(), total, base);
+  return stage_upload_batch(ctx, *this, base);
 }
 
 template <typename T>
@@ -159,6 +173,7 @@ int trap_destroy(trap_ctx* ctx) {
   DeviceGuard g(ctx->device);
   prof_clear(ctx, true);
   free_all(ctx);
+  release_spare(ctx);
   batch_arena_release(ctx->device);
   delete ctx;
   return TRAP_OK;
@@ -266,6 +281,7 @@ int trap_get_info(const trap_ctx* ctx, trap_info* info) {
   info->bytes_kernel_fp32 = (size_t)((double)P.nz * P.nth * P.nt * 2.0 * P.nn * P.ldm * 4);
   size_t tot = 0;
   for (auto& b : ctx->bufs) tot += b.bytes;
+  for (auto& b : ctx->spare) tot += b.bytes;
   info->bytes_device_total = tot;
   // per complex kernel entry: 4 Stokes columns x (real, imag) multiply-adds = 16 flops per slot
   info->flops_contraction = 16.0 * P.nz * P.nt * (double)P.nn * P.nn * P.nslot;

@@ -15,11 +15,13 @@
 #include <cmath>
 #include <complex>
 #include <numeric>
+#include <vector>
 
 #include "faddeeva.h"
 #include "trap_internal.h"
 
 namespace trap {
+
 
 namespace {
 
@@ -69,7 +71,15 @@ void gauss_legendre01(int n, std::vector<double>& t, std::vector<double>& w) {
 }
 
 // ---------------------------------------------------------------- Wigner 3j (Racah formula)
-double lfact(int n) { return std::lgamma(n + 1.0); }
+// log n!, tabulated once
+double lfact(int n) {
+  static const std::vector<double> tab = [] {
+    std::vector<double> t(256);
+    for (int k = 0; k < 256; ++k) t[k] = std::lgamma(k + 1.0);
+    return t;
+  }();
+  return n < 256 ? tab[n] : std::lgamma(n + 1.0);
+}
 
 double wigner3j(double j1, double j2, double j3, double m1, double m2, double m3) {
   auto I = [](double v) { return static_cast<int>(std::lround(v)); };
@@ -268,14 +278,21 @@ Sublevels sublevels(const trap_atom_desc& at, double Bg, double thB, double chB,
 }
 
 // d1^T Acart_j d2^* with Acart_j = sum_ab (A_j)_ab e_a e_b^T
-cd stokes_form(int j, const cd* d1, const cd* d2, const double* ea, const double* eb) {
-  cd pa1(0, 0), pb1(0, 0), pa2(0, 0), pb2(0, 0);
+// projections of a dipole vector on the two polarisation axes of a direction
+void stokes_proj(const cd* d, const double* ea, const double* eb, cd* pa, cd* pb) {
+  cd a(0, 0), b(0, 0);
   for (int k = 0; k < 3; ++k) {
-    pa1 += d1[k] * ea[k];
-    pb1 += d1[k] * eb[k];
-    pa2 += std::conj(d2[k]) * ea[k];
-    pb2 += std::conj(d2[k]) * eb[k];
+    a += d[k] * ea[k];
+    b += d[k] * eb[k];
   }
+  *pa = a;
+  *pb = b;
+}
+
+// Stokes component j of the pair (d1, d2) from the projections of d1 and the
+// conjugated projections of d2 (ea, eb real, so those are the conjugates of
+// d2's projections, exactly)
+cd stokes_pair(int j, cd pa1, cd pb1, cd pa2, cd pb2) {
   const cd I(0.0, 1.0);
   switch (j) {
     case 0: return pa1 * pa2 + pb1 * pb2;
@@ -309,9 +326,17 @@ std::vector<double> spline_map(const std::vector<double>& x, std::vector<double>
   A[(n - 1) * n + n - 3] = -h[n - 2];
   A[(n - 1) * n + n - 2] = h[n - 3] + h[n - 2];
   A[(n - 1) * n + n - 1] = -h[n - 3];
-  // solve A S = R by Gaussian elimination with partial pivoting
+  // solve A S = R by Gaussian elimination with partial pivoting.  A is banded
+  // (tridiagonal plus the two not-a-knot rows), so each row operation only
+  // runs to the pivot row's last nonzero column: the skipped terms are exact
+  // zeros, the result is the same as the dense elimination.
   std::vector<double> S = R;
   std::vector<double> M = A;
+  auto last_nz = [&](int r) {
+    int k = n - 1;
+    while (k > 0 && M[r * n + k] == 0.0) --k;
+    return k;
+  };
   for (int c = 0; c < n; ++c) {
     int piv = c;
     for (int r = c + 1; r < n; ++r)
@@ -321,17 +346,19 @@ std::vector<double> spline_map(const std::vector<double>& x, std::vector<double>
         std::swap(M[c * n + k], M[piv * n + k]);
         std::swap(S[c * n + k], S[piv * n + k]);
       }
+    const int hi = last_nz(c);
     for (int r = c + 1; r < n; ++r) {
       double f = M[r * n + c] / M[c * n + c];
       if (f == 0.0) continue;
-      for (int k = c; k < n; ++k) M[r * n + k] -= f * M[c * n + k];
+      for (int k = c; k <= hi; ++k) M[r * n + k] -= f * M[c * n + k];
       for (int k = 0; k < n; ++k) S[r * n + k] -= f * S[c * n + k];
     }
   }
   for (int c = n - 1; c >= 0; --c) {
+    const int hi = last_nz(c);
     for (int k = 0; k < n; ++k) {
       double v = S[c * n + k];
-      for (int j = c + 1; j < n; ++j) v -= M[c * n + j] * S[j * n + k];
+      for (int j = c + 1; j <= hi; ++j) v -= M[c * n + j] * S[j * n + k];
       S[c * n + k] = v / M[c * n + c];
     }
   }
@@ -735,10 +762,19 @@ int build_problem(trap_ctx* ctx, const trap_atom_desc* at, const trap_problem_de
   P.c_abs = sub[0].c_abs;
   P.c_sc = sub[0].c_sc;
   const int nu = P.nu, nl = P.nl, nt = P.nt;
-  std::vector<double> st(nz * nt), sll(nz * nl * nl), ub(nz * nd), g(nz * nt * nd * 4);
+  std::vector<double> st(nz * nt), sll(nz * nl * nl), ub(nz * nd);
   std::vector<double2> alpha(nz * nu * nu), bma(nz * nu * nu);
-  std::vector<double2> E(static_cast<size_t>(nz) * nd * 4 * nu * nu * nl);
-  std::vector<double2> A(static_cast<size_t>(nz) * nd * 4 * nu * nu * nl);
+  // the large tables are written in full below: per-thread buffers that keep
+  // their pages between calls (no zero fill, no first-touch faults per problem)
+  static thread_local std::vector<double> g_buf;
+  static thread_local std::vector<double2> E_buf, A_buf;
+  const size_t n_g = (size_t)nz * nt * nd * 4, n_e = static_cast<size_t>(nz) * nd * 4 * nu * nu * nl;
+  if (g_buf.size() < n_g) g_buf.resize(n_g);
+  if (E_buf.size() < n_e) E_buf.resize(n_e);
+  if (A_buf.size() < n_e) A_buf.resize(n_e);
+  double* g = g_buf.data();
+  double2* E = E_buf.data();
+  double2* A = A_buf.data();
   const double rE = at->r_E;
   for (int z = 0; z < nz; ++z) {
     const Sublevels& s = sub[z];
@@ -761,20 +797,22 @@ int build_problem(trap_ctx* ctx, const trap_atom_desc* at, const trap_problem_de
       const double vdot = pd->v[3 * z] * dirs[3 * o] + pd->v[3 * z + 1] * dirs[3 * o + 1] +
                           pd->v[3 * z + 2] * dirs[3 * o + 2];
       ub[z * nd + o] = vdot * 1e5 / vth[z];
+      // projections of every transition's dipole vector on this direction's axes
+      std::vector<cd> pa(nt), pb(nt);
+      for (int t = 0; t < nt; ++t) stokes_proj(&s.d[t * 3], &ea[3 * o], &eb[3 * o], &pa[t], &pb[t]);
       for (int t = 0; t < nt; ++t)
-        for (int j = 0; j < 4; ++j) {
-          const cd* dt = &s.d[t * 3];
-          g[((z * nt + t) * nd + o) * 4 + j] = stokes_form(j, dt, dt, &ea[3 * o], &eb[3 * o]).real();
-        }
+        for (int j = 0; j < 4; ++j)
+          g[((z * nt + t) * nd + o) * 4 + j] = stokes_pair(j, pa[t], pb[t], std::conj(pa[t]), std::conj(pb[t])).real();
       for (int i = 0; i < 4; ++i)
         for (int up = 0; up < nu; ++up)
           for (int u = 0; u < nu; ++u)
             for (int l = 0; l < nl; ++l) {
+              const int t1 = up * nl + l, t2 = u * nl + l;
               // E[z][o][i][u'][u][l'] with l' = l here
-              const cd e = stokes_form(i, &s.d[(up * nl + l) * 3], &s.d[(u * nl + l) * 3], &ea[3 * o], &eb[3 * o]);
+              const cd e = stokes_pair(i, pa[t1], pb[t1], std::conj(pa[t2]), std::conj(pb[t2]));
               E[((((static_cast<size_t>(z) * nd + o) * 4 + i) * nu + up) * nu + u) * nl + l] = make_double2(e.real(), e.imag());
               // A[z][o][j][u][u'][l] with (u, u') = (up, u) index order: first upper index u
-              const cd aa = 0.5 * stokes_form(i, &s.d[(up * nl + l) * 3], &s.d[(u * nl + l) * 3], &ea[3 * o], &eb[3 * o]);
+              const cd aa = 0.5 * e;
               A[((((static_cast<size_t>(z) * nd + o) * 4 + i) * nu + up) * nu + u) * nl + l] = make_double2(aa.real(), aa.imag());
             }
     }
@@ -818,11 +856,11 @@ int build_problem(trap_ctx* ctx, const trap_atom_desc* at, const trap_problem_de
   up.add(&P.d_grp[1], P.grp[1]);
   up.add(&P.d_cgrp[0], P.cgrp[0]);
   up.add(&P.d_cgrp[1], P.cgrp[1]);
-  up.add(&P.d_E, E);
-  up.add(&P.d_A, A);
+  up.add(reinterpret_cast<void**>(&P.d_E), E, n_e * sizeof(double2));
+  up.add(reinterpret_cast<void**>(&P.d_A), A, n_e * sizeof(double2));
   up.add(&P.d_alpha, alpha);
   up.add(&P.d_bma, bma);
-  up.add(&P.d_g, g);
+  up.add(reinterpret_cast<void**>(&P.d_g), g, n_g * sizeof(double));
   TRAP_TRY(up.commit(ctx));
   return TRAP_OK;
 }

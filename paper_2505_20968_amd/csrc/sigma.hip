@@ -1454,6 +1454,14 @@ void batch_arena_release(int device) {
 
 int stage_upload(trap_ctx* ctx, const void* host, size_t bytes, void* dev) {
   if (bytes == 0) return TRAP_OK;
+  UploadBatch one;
+  one.add(nullptr, host, bytes);
+  return stage_upload_batch(ctx, one, dev);
+}
+
+int stage_upload_batch(trap_ctx* ctx, const UploadBatch& up, void* dev) {
+  const size_t bytes = up.total;
+  if (bytes == 0) return TRAP_OK;
   std::lock_guard<std::mutex> lk(g_arena_mu);
   auto it = g_arena.find(ctx->device);
   if (it == g_arena.end()) return fail(TRAP_ESTATE, "internal: no shared state for the device");
@@ -1480,7 +1488,9 @@ int stage_upload(trap_ctx* ctx, const void* host, size_t bytes, void* dev) {
     a.staging.push_back(b);
     pick = &a.staging.back();
   }
-  std::memcpy(pick->host, host, bytes);
+  unsigned char* h = static_cast<unsigned char*>(pick->host);
+  for (const UploadBatch::Item& it : up.items)
+    if (it.bytes) std::memcpy(h + it.off, it.src, it.bytes);
   TRAP_HIP(hipMemcpyAsync(dev, pick->host, bytes, hipMemcpyHostToDevice, ctx->stream));
   TRAP_HIP(hipEventRecord(pick->ev, ctx->stream));
   pick->used = true;

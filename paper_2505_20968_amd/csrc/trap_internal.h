@@ -176,13 +176,15 @@ struct trap_ctx {
   int prd_mode = 0;                 // TRAP_PRD_* of trap.h, applied at trap_set_problem
   int max_lds = 64 * 1024;          // device limit of LDS bytes per block
   int n_cu = 256;                   // compute units of the device
-  std::vector<trap::DevBuf> bufs;   // every allocation the context made
+  std::vector<trap::DevBuf> bufs;   // every allocation of the current problem
+  std::vector<trap::DevBuf> spare;  // the previous problem's allocations, reused by size
 };
 
 namespace trap {
 // allocation helper (records into ctx->bufs)
 int dalloc(trap_ctx* ctx, void** p, size_t bytes);
-void free_all(trap_ctx* ctx);
+void free_all(trap_ctx* ctx);        // current allocations become spares (older spares are freed)
+void release_spare(trap_ctx* ctx);
 
 template <typename T>
 int dalloc_t(trap_ctx* ctx, T** p, size_t count) {
@@ -192,6 +194,10 @@ int dalloc_t(trap_ctx* ctx, T** p, size_t count) {
 // staging buffer of the device's pool (sigma.hip): returns once the data is in
 // the staging buffer; the copy itself is enqueued on the context's stream.
 int stage_upload(trap_ctx* ctx, const void* host, size_t bytes, void* dev);
+struct UploadBatch;
+// the same for every item of a batch, gathered into one staging buffer at the
+// batch's offsets and copied to dev with one transfer
+int stage_upload_batch(trap_ctx* ctx, const UploadBatch& up, void* dev);
 
 // Many host arrays uploaded as one device allocation (256-byte aligned items,
 // at least 16 bytes each) with one staged copy.
