@@ -182,7 +182,8 @@ def main():
         t2 = time.perf_counter()
         x = torch.zeros(ctx.shape, dtype=torch.float64, device="cuda")
         st = ctx.gmres_solve(x, tol=args.tol, restart=args.restart, max_iters=2000,
-                             inner=TRAP_FP32 if mixed else TRAP_FP64, max_outer=10, inner_tol=1e-7)
+                             inner=TRAP_FP32 if mixed else TRAP_FP64, max_outer=10, inner_tol=1e-7,
+                             zero_guess=True)
         t3 = time.perf_counter()
         phases["set_problem"].append(t1 - t0)
         phases["precompute"].append(t2 - t1)

@@ -119,6 +119,9 @@ typedef struct {
   int max_outer;       /* iterative-refinement steps (mixed precision) */
   trap_prec inner;     /* precision of the inner operator (FP64 = plain GMRES) */
   double inner_tol;    /* relative reduction asked of each inner solve */
+  int zero_guess;      /* nonzero: I holds zeros on entry, so the first residual is b
+                          itself and its operator apply is skipped (TRAP_EINVAL at the
+                          first step if I is not zero) */
 } trap_solve_opts;
 
 typedef struct {

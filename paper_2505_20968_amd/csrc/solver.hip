@@ -130,10 +130,13 @@ __global__ void k_from_f32(long long N, double scale, const float* __restrict__ 
     y[i] = scale * (double)x[i];
 }
 
-__global__ void k_nonfinite(long long N, const double* __restrict__ x, int* __restrict__ flag) {
+// flag bit 0: a non-finite entry; bit 1 (when asked): a nonzero entry
+__global__ void k_nonfinite(long long N, const double* __restrict__ x, int* __restrict__ flag, int want_zero) {
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < N;
-       i += (long long)gridDim.x * blockDim.x)
+       i += (long long)gridDim.x * blockDim.x) {
     if (!isfinite(x[i])) atomicOr(flag, 1);
+    if (want_zero && x[i] != 0.0) atomicOr(flag, 2);
+  }
 }
 
 namespace {
@@ -285,7 +288,7 @@ int gmres_begin(trap_ctx* ctx, const trap_solve_opts* opts, double* I) {
   // first step after its synchronisation (so beginning a solve never waits)
   int* dflag = reinterpret_cast<int*>(K.red);
   hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, ctx->stream, dflag, 0);
-  hipLaunchKernelGGL(k_nonfinite, dim3(kBlocks), dim3(256), 0, ctx->stream, N, I, dflag);
+  hipLaunchKernelGGL(k_nonfinite, dim3(kBlocks), dim3(256), 0, ctx->stream, N, I, dflag, opts->zero_guess ? 1 : 0);
   TRAP_HIP(hipGetLastError());
   int* hflag = begin_flag(R);
   *hflag = 0;
@@ -301,8 +304,12 @@ int gmres_begin(trap_ctx* ctx, const trap_solve_opts* opts, double* I) {
 static bool begin_checks(GmresRun& R) {
   if (!R.begin_pending) return true;
   R.begin_pending = false;
-  if (*begin_flag(R)) {
+  if (*begin_flag(R) & 1) {
     run_finish(R, fail(TRAP_ENAN, "non-finite initial guess"));
+    return false;
+  }
+  if (*begin_flag(R) & 2) {
+    run_finish(R, fail(TRAP_EINVAL, "initial guess declared zero is not zero"));
     return false;
   }
   R.bnorm = std::sqrt(std::max(*begin_bnorm2(R), 0.0));
@@ -365,7 +372,13 @@ int unit_issue1(trap_ctx* ctx, GmresRun& R) {
   const double* x;
   double* y;
   if (!unit_operand(ctx, R, &prec, &x, &y)) return TRAP_OK;
-  TRAP_TRY(op_apply(ctx, prec, x, y, &R.st));
+  if (R.phase == GP_RESID_OUTER && R.outer == 0 && R.opts.zero_guess) {
+    // A 0 = 0: the first residual is b itself
+    hipLaunchKernelGGL(k_scale_copy, dim3(kBlocks), dim3(256), 0, ctx->stream, R.N, 0.0, ctx->pre.d_b, y);
+    TRAP_HIP(hipGetLastError());
+  } else {
+    TRAP_TRY(op_apply(ctx, prec, x, y, &R.st));
+  }
   return unit_issue1_rest(ctx, R);
 }
 

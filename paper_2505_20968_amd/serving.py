@@ -129,7 +129,7 @@ class DeviceBackend:
         self.mixed = precision == "mixed"
         self.store = 3 if self.mixed else 1
         self.opts = dict(tol=tol, restart=restart, max_iters=max_iters, max_outer=max_outer,
-                         inner=TRAP_FP32 if self.mixed else TRAP_FP64, inner_tol=inner_tol)
+                         inner=TRAP_FP32 if self.mixed else TRAP_FP64, inner_tol=inner_tol, zero_guess=True)
         self._footprint = footprint
         self.admit_parts = {"context": 0.0, "set_problem": 0.0, "precompute": 0.0, "begin": 0.0}
 

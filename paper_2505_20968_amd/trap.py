@@ -59,7 +59,8 @@ class Info(ctypes.Structure):
 
 class SolveOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("restart", ctypes.c_int), ("max_iters", ctypes.c_int),
-                ("max_outer", ctypes.c_int), ("inner", ctypes.c_int), ("inner_tol", ctypes.c_double)]
+                ("max_outer", ctypes.c_int), ("inner", ctypes.c_int), ("inner_tol", ctypes.c_double),
+                ("zero_guess", ctypes.c_int)]
 
 
 class SolveStats(ctypes.Structure):
@@ -232,9 +233,9 @@ class Context:
 
     def gmres_solve(self, I, tol: float = 1e-8, restart: int = 40, max_iters: int = 2000,
                     inner: int = TRAP_FP64, max_outer: int = 8, inner_tol: float = 1e-7,
-                    raise_on_noconv: bool = True):
+                    raise_on_noconv: bool = True, zero_guess: bool = False):
         o = SolveOpts(tol=tol, restart=restart, max_iters=max_iters, max_outer=max_outer, inner=inner,
-                      inner_tol=inner_tol)
+                      inner_tol=inner_tol, zero_guess=int(zero_guess))
         st = SolveStats()
         code = self.lib.trap_gmres_solve(self.h, ctypes.byref(o), self._vec(I, TRAP_FP64), ctypes.byref(st))
         if code != 0 and (raise_on_noconv or code != -4):
@@ -244,10 +245,11 @@ class Context:
                 "final_rel_res": st.final_rel_res, "ms_total": st.ms_total, "status": code}
 
     def gmres_begin(self, I, tol: float = 1e-8, restart: int = 40, max_iters: int = 2000,
-                    inner: int = TRAP_FP64, max_outer: int = 8, inner_tol: float = 1e-7):
+                    inner: int = TRAP_FP64, max_outer: int = 8, inner_tol: float = 1e-7,
+                    zero_guess: bool = False):
         """Start a solve that trap_gmres_step_batch advances (see gmres_step_batch)."""
         o = SolveOpts(tol=tol, restart=restart, max_iters=max_iters, max_outer=max_outer, inner=inner,
-                      inner_tol=inner_tol)
+                      inner_tol=inner_tol, zero_guess=int(zero_guess))
         self._solution = I           # the library writes into I until the solve ends
         _check(self.lib.trap_gmres_begin(self.h, ctypes.byref(o), self._vec(I, TRAP_FP64)))
 

@@ -123,3 +123,30 @@ def test_footprint_bounds_what_a_solve_allocates(store):
         ctx.close()
         print(f"store {store}: footprint {est} B, held {used} B", flush=True)
         assert used <= est <= 1.5 * used + (1 << 20)
+
+
+@pytest.mark.parametrize("inner", ["fp64", "mixed"])
+def test_zero_guess_skips_the_first_apply_and_changes_nothing(inner):
+    """Declaring the initial guess zero replaces the first residual's operator
+    apply by r = b (A 0 = 0 exactly): same iterations, same solution bitwise,
+    one FP64 apply fewer; a nonzero guess declared zero is rejected."""
+    torch = _torch()
+    from paper_2505_20968_amd import Context, TRAP_FP32, TRAP_FP64, TrapError
+    prob = tiny(n_z=6, n_nu=25, x_max=7, n_mu=4, n_chi=5, B=(60.0, 0.8, 2.0), a=2e-2, eps=3e-2, v_z=2.0, seed=21)
+    ctx = Context(0)
+    ctx.set_problem(prob)
+    ctx.precompute(3)
+    opts = dict(tol=1e-10, restart=30, max_iters=500, inner=TRAP_FP32 if inner == "mixed" else TRAP_FP64,
+                inner_tol=1e-7, max_outer=10)
+    xa = torch.zeros(ctx.shape, dtype=torch.float64, device="cuda")
+    sa = ctx.gmres_solve(xa, **opts)
+    xb = torch.zeros(ctx.shape, dtype=torch.float64, device="cuda")
+    sb = ctx.gmres_solve(xb, zero_guess=True, **opts)
+    print(f"[{inner}] applies fp64 {sa['applies_fp64']} -> {sb['applies_fp64']}", flush=True)
+    assert torch.equal(xa, xb)
+    assert sb["inner_iters"] == sa["inner_iters"]
+    assert sb["applies_fp64"] == sa["applies_fp64"] - 1
+    xc = torch.full(ctx.shape, 1e-3, dtype=torch.float64, device="cuda")
+    with pytest.raises(TrapError):
+        ctx.gmres_solve(xc, zero_guess=True, **opts)
+    ctx.close()
