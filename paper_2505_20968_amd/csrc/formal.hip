@@ -55,25 +55,41 @@ __device__ inline void delo_solve(const T* k, T p, const T* b, T* xout) {
   A[1][0] = p * k[0]; A[1][1] = T(1); A[1][2] = p * k[5]; A[1][3] = -p * k[4];
   A[2][0] = p * k[1]; A[2][1] = -p * k[5]; A[2][2] = T(1); A[2][3] = p * k[3];
   A[3][0] = p * k[2]; A[3][1] = p * k[4]; A[3][2] = -p * k[3]; A[3][3] = T(1);
+#pragma unroll
   for (int i = 0; i < 4; ++i) A[i][4] = b[i];
+  // every index below is a compile-time constant (the pivot row is swapped in
+  // by comparison, not by indexing), so the matrix stays in registers
+#pragma unroll
   for (int c = 0; c < 4; ++c) {
     int piv = c;
+    T best = fabs(A[c][c]);
+#pragma unroll
     for (int r = c + 1; r < 4; ++r)
-      if (fabs(A[r][c]) > fabs(A[piv][c])) piv = r;
-    if (piv != c)
-      for (int j = 0; j < 5; ++j) {
-        const T tmp = A[c][j];
-        A[c][j] = A[piv][j];
-        A[piv][j] = tmp;
+      if (fabs(A[r][c]) > best) {
+        best = fabs(A[r][c]);
+        piv = r;
       }
+#pragma unroll
+    for (int r = c + 1; r < 4; ++r)
+      if (piv == r)
+#pragma unroll
+        for (int j = 0; j < 5; ++j) {
+          const T tmp = A[c][j];
+          A[c][j] = A[r][j];
+          A[r][j] = tmp;
+        }
     const T inv = T(1) / A[c][c];
+#pragma unroll
     for (int r = c + 1; r < 4; ++r) {
       const T fct = A[r][c] * inv;
+#pragma unroll
       for (int j = c; j < 5; ++j) A[r][j] -= fct * A[c][j];
     }
   }
+#pragma unroll
   for (int i = 3; i >= 0; --i) {
     T v = A[i][4];
+#pragma unroll
     for (int j = i + 1; j < 4; ++j) v -= A[i][j] * xout[j];
     xout[i] = v / A[i][i];
   }
@@ -97,6 +113,7 @@ __device__ __forceinline__ void formal_body(int bx, int nz, int nd, int nn, cons
   T Icur[4] = {T(0), T(0), T(0), T(0)};
   if (up && with_boundary) Icur[0] = T(WT[0]);
   T ku[6], Su[4], ru;
+  double tz = tau[z];
   {
     const long long p = pidx(z);
     const double* k = K8 + p * 8;
@@ -106,16 +123,37 @@ __device__ __forceinline__ void formal_body(int bx, int nz, int nd, int nn, cons
     for (int s = 0; s < 4; ++s) Su[s] = eps[p * 4 + s] * inv;
     for (int s = 0; s < 4; ++s) I[p * 4 + s] = Icur[s];
   }
+  // the raw data of the next height are loaded one step ahead, so their
+  // latency overlaps the current step's arithmetic
+  double kn[8], tn = 0.0;
+  T en[4];
+  auto fetch = [&](int zz) {
+    const long long p = pidx(zz);
+    const double* k = K8 + p * 8;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) kn[i] = k[i];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) en[s] = eps[p * 4 + s];
+    tn = tau[zz];
+  };
+  if (nz > 1) fetch(z + dz);
   for (int step = 1; step < nz; ++step) {
     const int zc = z + dz;
     const long long p = pidx(zc);
-    const double* k = K8 + p * 8;
+    double kr[8];
+    T er[4];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) kr[i] = kn[i];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) er[s] = en[s];
+    const double tzc = tn;
+    if (step + 1 < nz) fetch(zc + dz);
     T kc[6], Sc[4];
-    for (int i = 0; i < 6; ++i) kc[i] = T(k[i]);
-    const T inv = T(k[6]);
-    const T rc = T(k[7]);
-    for (int s = 0; s < 4; ++s) Sc[s] = eps[p * 4 + s] * inv;
-    const T x = T(0.5) * (ru + rc) * T(fabs(tau[z] - tau[zc])) / amu;
+    for (int i = 0; i < 6; ++i) kc[i] = T(kr[i]);
+    const T inv = T(kr[6]);
+    const T rc = T(kr[7]);
+    for (int s = 0; s < 4; ++s) Sc[s] = er[s] * inv;
+    const T x = T(0.5) * (ru + rc) * T(fabs(tz - tzc)) / amu;
     T pu, pc, ex;
     delo_weights<T>(x, pu, pc, ex);
     T kv[4], b[4];
@@ -131,11 +169,12 @@ __device__ __forceinline__ void formal_body(int bx, int nz, int nd, int nn, cons
     for (int i = 0; i < 6; ++i) ku[i] = kc[i];
     ru = rc;
     z = zc;
+    tz = tzc;
   }
 }
 
 template <typename T>
-__global__ void k_formal(int nz, int nd, int nn, const double* __restrict__ mu,
+__global__ void __launch_bounds__(64) k_formal(int nz, int nd, int nn, const double* __restrict__ mu,
                          const double* __restrict__ tau, const double* __restrict__ K8,
                          const double* __restrict__ WT, const T* __restrict__ eps, T* __restrict__ I,
                          int with_boundary) {
@@ -143,7 +182,7 @@ __global__ void k_formal(int nz, int nd, int nn, const double* __restrict__ mu,
 }
 
 // one launch over several contexts: block b is context r's block b - off[r]
-__global__ void k_formal_grouped(const GFormal* __restrict__ A, const int* __restrict__ off, int n) {
+__global__ void __launch_bounds__(64) k_formal_grouped(const GFormal* __restrict__ A, const int* __restrict__ off, int n) {
   int lo = 0, hi = n;
   while (hi - lo > 1) {
     const int mid = (lo + hi) >> 1;
