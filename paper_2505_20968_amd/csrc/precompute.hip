@@ -181,8 +181,12 @@ __global__ void k_kernel_tables(int z0, int nth, int nt, int nn, int ntail, doub
   const bool pil = Th >= kPiD;
   const double sG = pil ? 1.0 : sin(0.5 * Th), cG = pil ? 0.0 : cos(0.5 * Th);
   const int nd2 = 2 * nn - 1 + 2 * ntail;
+  // this height's rows reach at most ntz intervals past the grid ends (support
+  // half-width 13.2 / lam); entries beyond are never read and not computed
+  const int ntz = min(ntail, (int)ceil(13.2 / (L * h)) + 2);
+  const int e0 = (ntail - ntz) * 16, e1 = nd2 * 16 - e0;
   double2* V = Vt + ((size_t)(zl * nth + th) * nt + t) * nd2 * 16;
-  for (int e = threadIdx.x; e < nd2 * 16; e += blockDim.x) {
+  for (int e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
     const int p = (e >> 4) - ntail, i = e & 15;
     const double xs = 2.0 * x0 + h * (p + c_gl_t[i]);
     if (pil) {
@@ -195,7 +199,7 @@ __global__ void k_kernel_tables(int z0, int nth, int nt, int nn, int ntail, doub
   }
   if (t == 0) {
     double* G = Gt + (size_t)(zl * nth + th) * nd2 * 16;
-    for (int e = threadIdx.x; e < nd2 * 16; e += blockDim.x) {
+    for (int e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
       const int dd = (e >> 4) - (nn - 1) - ntail, i = e & 15;
       const double q = L * h * (dd - c_gl_t[i]) / (2.0 * sG);
       G[e] = exp(-q * q);
