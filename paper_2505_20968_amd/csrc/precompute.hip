@@ -517,6 +517,153 @@ __global__ void __launch_bounds__(256) k_sig_gemm(long long nrows, int nn, int l
   }
 }
 
+// Persistent form for grids whose Sig fits in LDS: each block stages Sig once
+// (rows k padded with zeros to 8 NH, columns to whole 16-column tiles) and its
+// 8 waves then stream 16-row tiles of Gam independently (no barrier in the
+// loop, so the waves drift apart and one's loads overlap another's products):
+// the kernel-row fragments are loaded straight into registers in the permuted
+// K order k = 2 (4 h + lk) + jj (two-element vector loads).
+template <int NH, int NCT>
+__global__ void __launch_bounds__(512, 1) k_sig_gemm_lds(long long nrows, int nn, int ldm,
+                                                         const double* __restrict__ Gam,
+                                                         const double* __restrict__ Lrow,
+                                                         const double* __restrict__ Sig,
+                                                         double* __restrict__ M64, float* __restrict__ M32,
+                                                         long long out_row0) {
+  constexpr int KP = 8 * NH, CP = 16 * NCT, BST = CP + 4;
+  extern __shared__ double sgs[];      // [KP][BST]
+  for (int e = threadIdx.x; e < KP * CP; e += blockDim.x) {
+    const int k = e / CP, c = e - k * CP;
+    sgs[k * BST + c] = (k < nn && c < nn) ? Sig[(size_t)k * nn + c] : 0.0;
+  }
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
+  const long long ntile = (nrows + 15) / 16;
+  const long long step = (long long)gridDim.x * 8;
+  auto load = [&](long long tile, double2 (&f)[NH]) {
+    const long long row = min(tile * 16 + lr, nrows - 1);
+    const double* g = Gam + row * ldm;
+#pragma unroll
+    for (int h = 0; h < NH; ++h) {
+      const int k = 2 * (4 * h + lk);
+      f[h] = *reinterpret_cast<const double2*>(g + min(k, ldm - 2));
+      if (k >= ldm) f[h] = make_double2(0.0, 0.0);
+    }
+  };
+  double2 fa[NH];
+  const double* bcol = sgs + 2 * lk * BST + lr;
+  for (long long tile = (long long)blockIdx.x * 8 + wave; tile < ntile; tile += step) {
+    load(tile, fa);
+    doublex4_g acc[NCT];
+#pragma unroll
+    for (int j = 0; j < NCT; ++j)
+      for (int r = 0; r < 4; ++r) acc[j][r] = 0.0;
+    // the B values of step h + 1 are read before step h's products are
+    // issued; the scheduling barriers keep that order and stop the compiler
+    // from hoisting every read of the unrolled loop
+    double bc[2][NCT], bx[2][NCT];
+#pragma unroll
+    for (int jj = 0; jj < 2; ++jj)
+#pragma unroll
+      for (int j = 0; j < NCT; ++j) bc[jj][j] = bcol[jj * BST + j * 16];
+#pragma unroll
+    for (int h = 0; h < NH; ++h) {
+      if (h + 1 < NH) {
+#pragma unroll
+        for (int jj = 0; jj < 2; ++jj)
+#pragma unroll
+          for (int j = 0; j < NCT; ++j) bx[jj][j] = bcol[(8 * (h + 1) + jj) * BST + j * 16];
+      }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int jj = 0; jj < 2; ++jj) {
+        const double af = jj ? fa[h].y : fa[h].x;
+#pragma unroll
+        for (int j = 0; j < NCT; ++j) acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af, bc[jj][j], acc[j], 0, 0, 0);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      if (h + 1 < NH) {
+#pragma unroll
+        for (int jj = 0; jj < 2; ++jj)
+#pragma unroll
+          for (int j = 0; j < NCT; ++j) bc[jj][j] = bx[jj][j];
+      }
+    }
+    // lane holds D[row lk + 4 r][column 16 j + lr]
+#pragma unroll
+    for (int j = 0; j < NCT; ++j) {
+      const int col = j * 16 + lr;
+      if (col >= ldm) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const long long gr = tile * 16 + lk + 4 * r;
+        if (gr >= nrows) continue;
+        const double v = (col < nn) ? acc[j][r] + Lrow[gr * ldm + col] : 0.0;
+        const size_t o = (size_t)(out_row0 + gr) * ldm + col;
+        if (M64) M64[o] = v;
+        if (M32) M32[o] = (float)v;
+      }
+    }
+  }
+}
+
+// M = L + Gam Sig for `rrows` real rows; the persistent form when Sig fits
+int launch_sig_gemm(trap_ctx* ctx, long long rrows, const double* Gam, const double* Lrow, double* M64,
+                    float* M32, long long out_row0) {
+  Problem& P = ctx->pb;
+  const int nn = P.nn, ldm = P.ldm;
+  const int nh = ldm / 8, nct = (nn + 15) / 16;
+  const size_t lds = (size_t)8 * nh * (16 * nct + 4) * sizeof(double);
+  auto fallback = [&]() -> int {
+    dim3 gg(ceil_div(rrows, 64), ceil_div(ldm, kSigColTiles * 16));
+    hipLaunchKernelGGL(k_sig_gemm, gg, dim3(256), 0, ctx->stream, rrows, nn, ldm, Gam, Lrow, P.d_Sig, M64, M32,
+                       out_row0);
+    TRAP_HIP(hipGetLastError());
+    return TRAP_OK;
+  };
+  if (lds > (size_t)ctx->max_lds || nh < 1 || nh > 16 || nct > 8) return fallback();
+  const int grid = (int)std::min<long long>(ctx->n_cu, ceil_div((rrows + 15) / 16, 8));
+  auto launch = [&](auto kern) -> int {
+    if (lds > 64 * 1024)
+      TRAP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)lds));
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(512), lds, ctx->stream, rrows, nn, ldm, Gam, Lrow, P.d_Sig, M64, M32,
+                       out_row0);
+    TRAP_HIP(hipGetLastError());
+    return TRAP_OK;
+  };
+#define TRAP_SIG_NCT(NHV)                                              \
+  switch (nct) {                                                       \
+    case 1: return launch(k_sig_gemm_lds<NHV, 1>);                     \
+    case 2: return launch(k_sig_gemm_lds<NHV, 2>);                     \
+    case 3: return launch(k_sig_gemm_lds<NHV, 3>);                     \
+    case 4: return launch(k_sig_gemm_lds<NHV, 4>);                     \
+    case 5: return launch(k_sig_gemm_lds<NHV, 5>);                     \
+    case 6: return launch(k_sig_gemm_lds<NHV, 6>);                     \
+    case 7: return launch(k_sig_gemm_lds<NHV, 7>);                     \
+    default: return launch(k_sig_gemm_lds<NHV, 8>);                    \
+  }
+  switch (nh) {
+    case 1: TRAP_SIG_NCT(1)
+    case 2: TRAP_SIG_NCT(2)
+    case 3: TRAP_SIG_NCT(3)
+    case 4: TRAP_SIG_NCT(4)
+    case 5: TRAP_SIG_NCT(5)
+    case 6: TRAP_SIG_NCT(6)
+    case 7: TRAP_SIG_NCT(7)
+    case 8: TRAP_SIG_NCT(8)
+    case 9: TRAP_SIG_NCT(9)
+    case 10: TRAP_SIG_NCT(10)
+    case 11: TRAP_SIG_NCT(11)
+    case 12: TRAP_SIG_NCT(12)
+    case 13: TRAP_SIG_NCT(13)
+    case 14: TRAP_SIG_NCT(14)
+    case 15: TRAP_SIG_NCT(15)
+    default: TRAP_SIG_NCT(16)
+  }
+#undef TRAP_SIG_NCT
+}
+
 // ------------------------------------------------------------------ R_III weights
 __global__ void __launch_bounds__(64) k_r3_rows(int nt, int nn, const double* __restrict__ x,
                                                 const double* __restrict__ P, const double* __restrict__ lam,
@@ -774,17 +921,12 @@ int run_precompute(trap_ctx* ctx, int store_mask) {
       TRAP_HIP(hipGetLastError());
     }
     const long long rrows = 2 * nrows;                           // real rows (both planes)
-    dim3 gg(ceil_div(rrows, 64), ceil_div(P.ldm, kSigColTiles * 16));
     if (!aa) {
-      hipLaunchKernelGGL(k_sig_gemm, gg, dim3(256), 0, s, rrows, nn, P.ldm, C.d_Grow, C.d_Lrow, P.d_Sig,
-                         (mask & 1) ? C.d_M64 : nullptr, (mask & 2) ? C.d_M32 : nullptr,
-                         (long long)z0 * nth * nt * 2 * nn);
-      TRAP_HIP(hipGetLastError());
+      TRAP_TRY(launch_sig_gemm(ctx, rrows, C.d_Grow, C.d_Lrow, (mask & 1) ? C.d_M64 : nullptr,
+                               (mask & 2) ? C.d_M32 : nullptr, (long long)z0 * nth * nt * 2 * nn));
     } else {
       // rows at the Gauss-Legendre angles into the scratch store, then their weighted sum
-      hipLaunchKernelGGL(k_sig_gemm, gg, dim3(256), 0, s, rrows, nn, P.ldm, C.d_Grow, C.d_Lrow, P.d_Sig,
-                         C.d_Mtmp, (float*)nullptr, 0LL);
-      TRAP_HIP(hipGetLastError());
+      TRAP_TRY(launch_sig_gemm(ctx, rrows, C.d_Grow, C.d_Lrow, C.d_Mtmp, (float*)nullptr, 0LL));
       const long long per_z_out = (long long)nt * 2 * nn * P.ldm;
       hipLaunchKernelGGL(k_theta_average, dim3(ceil_div(per_z_out * zc, 256)), dim3(256), 0, s, per_z_out, nthr,
                          zc, P.d_theta_rw, C.d_Mtmp, (mask & 1) ? C.d_M64 : nullptr, (mask & 2) ? C.d_M32 : nullptr,
