@@ -198,8 +198,8 @@ int trap_gmres_solve(trap_ctx* ctx, const trap_solve_opts* opts, double* I, trap
  * may stay in the batch (they are skipped).
  * trap_gmres_end returns the final status and statistics of a finished solve
  * (TRAP_ESTATE while it is still running).
- * Contexts of one device whose step applies the FP32 operator, whose
- * problem fits in one height chunk and that do not record stage times share
+ * Contexts of one device whose step applies the FP32 operator and that do
+ * not record stage times share
  * the launches of that apply: each stage of the operator is one launch over
  * all of them, on a stream the library keeps per device (ordered after each
  * context's earlier work and before its later work through events).

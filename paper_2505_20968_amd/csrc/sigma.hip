@@ -1502,7 +1502,6 @@ int sigma_batch_ready(trap_ctx* ctx) {
   Work& K = ctx->wk;
   if (!ctx->has_problem || !ctx->pre.done || !ctx->pre.d_M32 || !ctx->pre.d_cf32) return 0;
   if (ctx->path == TRAP_PATH_FUSED || ctx->prof.on) return 0;
-  if (K.zchunk < P.nz) return 0;
   TRAP_TRY(ensure_work(ctx, TRAP_FP32));
   if (!K.W[1]) TRAP_TRY(dalloc(ctx, &K.W[1], (size_t)K.zchunk * P.nt * P.nslot * 2 * P.nn * 4 * sizeof(float)));
   return (K.v32a && K.v32b) ? 1 : 0;
@@ -1564,46 +1563,53 @@ int op_apply_batch_f32(trap_ctx** ctxs, int n, const double* const* x, double* c
     add_stage(SK_R3Y, 0, blob.put(ay), cy, 0);
     add_stage(SK_R3X, 0, blob.put(ax), cx, 0);
   }
-  // 3. R_II contraction, one launch per K-chunk class
-  {
-    std::map<int, std::vector<int>> by_nh;
+  // 3-4. per height chunk (W holds one chunk of each context): the R_II
+  //      contraction, one launch per K-chunk class, then the angular /
+  //      sublevel sum, one launch per sublevel class, over every context that
+  //      has that chunk
+  int maxch = 0;
+  for (int i = 0; i < n; ++i) maxch = std::max(maxch, ceil_div(ctxs[i]->pb.nz, ctxs[i]->wk.zchunk));
+  for (int ch = 0; ch < maxch; ++ch) {
+    std::map<int, std::vector<int>> by_nh, by_nl;
     for (int i = 0; i < n; ++i) {
+      if (ch * ctxs[i]->wk.zchunk >= ctxs[i]->pb.nz) continue;
       int nkc, nh;
       contract_chunks(ctxs[i]->pb.ldm, &nkc, &nh);
       by_nh[nh].push_back(i);
+      by_nl[nl_class(ctxs[i]->pb.nl)].push_back(i);
     }
     for (auto& kv : by_nh) {
       std::vector<GContract> a;
       std::vector<int> cnt;
       for (int i : kv.second) {
         const Problem& P = ctxs[i]->pb;
+        const int z0 = ch * ctxs[i]->wk.zchunk, zc = std::min(ctxs[i]->wk.zchunk, P.nz - z0);
         int nkc, nh;
         contract_chunks(P.ldm, &nkc, &nh);
         const int rb_n = ceil_div(2LL * P.nt * P.nn, kRowsPerBlock);
         const int ngrp = (int)P.cgrp[1].size() / 3;
-        a.push_back(GContract{0, P.nth, P.nt, P.nn, P.ldm, P.nd, nkc, P.cgrp_n8[1], P.nslot, rb_n, P.nz,
-                              ctxs[i]->pre.d_M32, static_cast<const float*>(ctxs[i]->wk.Ibar[1]), P.d_cgrp[1],
-                              P.d_slot_dir, static_cast<float*>(ctxs[i]->wk.W[1])});
-        cnt.push_back(rb_n * P.nz * ngrp);
+        a.push_back(GContract{z0, P.nth, P.nt, P.nn, P.ldm, P.nd, nkc, P.cgrp_n8[1], P.nslot, rb_n, zc,
+                              ctxs[i]->pre.d_M32,
+                              static_cast<const float*>(ctxs[i]->wk.Ibar[1]) + (size_t)z0 * P.nd * P.nn * 4,
+                              P.d_cgrp[1], P.d_slot_dir, static_cast<float*>(ctxs[i]->wk.W[1])});
+        cnt.push_back(rb_n * zc * ngrp);
       }
       add_stage(SK_CONTRACT, kv.first, blob.put(a), cnt,
                 (size_t)8 * kv.first * ContractCfg<float>::BST * sizeof(float));
     }
-  }
-  // 4. angular / sublevel sum, one launch per sublevel class
-  {
-    std::map<int, std::vector<int>> by_nl;
-    for (int i = 0; i < n; ++i) by_nl[nl_class(ctxs[i]->pb.nl)].push_back(i);
     for (auto& kv : by_nl) {
       std::vector<GAngular> a;
       std::vector<int> cnt;
       for (int i : kv.second) {
         const Problem& P = ctxs[i]->pb;
         Work& K = ctxs[i]->wk;
-        a.push_back(GAngular{0, P.nd, P.nn, P.nu, P.nl, P.nslot, P.nz * P.nd, P.d_pair_slot, P.d_pair_index,
+        const int z0 = ch * K.zchunk, zc = std::min(K.zchunk, P.nz - z0);
+        const int ncls = P.nl * P.nl;
+        a.push_back(GAngular{z0, P.nd, P.nn, P.nu, P.nl, P.nslot, zc * P.nd, P.d_pair_slot, P.d_pair_index,
                              ctxs[i]->pre.d_cf32, static_cast<const float*>(K.W[1]), P.c_sc, P.d_E, P.d_bma, K.X,
-                             ctxs[i]->pre.d_prof, static_cast<float*>(K.Eb[1])});
-        cnt.push_back(P.nz * P.nd * ceil_div(P.nn, 64));
+                             ctxs[i]->pre.d_prof,
+                             static_cast<float*>(K.Eb[1]) + (size_t)z0 * ncls * P.nd * P.nn * 4});
+        cnt.push_back(zc * P.nd * ceil_div(P.nn, 64));
       }
       add_stage(SK_ANGULAR, kv.first, blob.put(a), cnt, 0);
     }

@@ -21,8 +21,12 @@ def _requests():
         tiny(n_z=4, n_nu=33, x_max=16, n_mu=4, n_chi=4, B=(40.0, 1.0, 0.3), a=1e-2, eps=5e-2,
              atom=two_term_atom(2800.0, 24.305, 20.0)),
         tiny(n_z=8, n_nu=17, x_max=5, n_mu=4, n_chi=4, B=(10.0, 0.3, 1.0), a=5e-3, eps=1e-2, seed=7),
+        # two-term atom on 64 directions: W of one height is ~80 MB, so its
+        # Sigma runs in two height chunks, also inside the shared launches
+        tiny(n_z=8, n_nu=41, x_max=16, n_mu=8, n_chi=8, B=(40.0, 1.0, 0.3), a=1e-2, eps=5e-2,
+             atom=two_term_atom(2800.0, 24.305, 20.0), seed=11),
     ]
-    arrivals = [0.0, 0.0, 0.01, 0.02, 0.03]
+    arrivals = [0.0, 0.0, 0.01, 0.02, 0.03, 0.0]
     return [Request(i, t, p) for i, (t, p) in enumerate(zip(arrivals, probs))]
 
 
@@ -57,7 +61,7 @@ def served():
 @pytest.mark.parametrize("precision", ["mixed", "fp64"])
 def test_every_request_converges_and_slots_were_shared(served, precision):
     res = served[precision]
-    assert res["n_ok"] == 5 and res["n_rejected"] == 0 and res["n_failed"] == 0
+    assert res["n_ok"] == len(res["requests"]) and res["n_rejected"] == 0 and res["n_failed"] == 0
     # the first two arrive together and share the batch; whether the later ones
     # find it still running depends on timing (the host-side test pins that)
     assert res["peak_active"] >= 2
@@ -71,10 +75,23 @@ def test_every_request_converges_and_slots_were_shared(served, precision):
 
 def test_fp32_applies_shared_launches(served):
     """Requests running together apply their FP32 operators in shared launches
-    (one launch per stage over all of them); FP64 applies are never grouped."""
+    (one launch per stage over all of them), also a request whose Sigma runs in
+    several height chunks; FP64 applies are never grouped."""
+    from paper_2505_20968_amd import Context
+    chunks = []
+    for r in served["mixed"]["requests"]:
+        ctx = Context(0)
+        ctx.set_problem(r.problem)
+        i = ctx.info()
+        ctx.close()
+        per_z = i["n_trans"] * i["n_slots"] * 2 * i["n_nu"] * 4 * 8      # one height of W in FP64
+        chunks.append(-(-i["n_z"] // max(1, min(i["n_z"], (1 << 29) // per_z))))
+    print(f"[serving mixed] height chunks per request: {chunks}", flush=True)
+    assert max(chunks) > 1
     grouped = [r.stats["applies_grouped"] for r in served["mixed"]["requests"]]
     print(f"[serving mixed] grouped FP32 applies per request: {grouped}", flush=True)
     assert sum(grouped) > 0
+    assert grouped[chunks.index(max(chunks))] > 0
     for r in served["mixed"]["requests"]:
         assert r.stats["applies_grouped"] <= r.stats["applies_fp32"]
     assert all(r.stats["applies_grouped"] == 0 for r in served["fp64"]["requests"])
