@@ -198,11 +198,13 @@ int trap_gmres_solve(trap_ctx* ctx, const trap_solve_opts* opts, double* I, trap
  * may stay in the batch (they are skipped).
  * trap_gmres_end returns the final status and statistics of a finished solve
  * (TRAP_ESTATE while it is still running).
- * Contexts of one device whose step applies the FP32 operator and that do
- * not record stage times share
- * the launches of that apply: each stage of the operator is one launch over
- * all of them, on a stream the library keeps per device (ordered after each
- * context's earlier work and before its later work through events).
+ * Contexts of one device whose step applies the FP32 operator, that do not
+ * record stage times and whose Sigma runs in one height chunk share the
+ * launches of that apply (a context with several chunks applies on its own
+ * stream, so it does not hold the shared applies of smaller ones): each
+ * stage of the operator is one launch over all of them, on a stream the
+ * library keeps per device (ordered after each context's earlier work and
+ * before its later work through events).
  * The arithmetic of a context does not depend on the other contexts of the
  * batch: each block of a shared launch runs the single-context code on one
  * context's data, so a request's solution is the same alone and in any mix. */
