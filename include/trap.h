@@ -122,6 +122,12 @@ typedef struct {
   int zero_guess;      /* nonzero: I holds zeros on entry, so the first residual is b
                           itself and its operator apply is skipped (TRAP_EINVAL at the
                           first step if I is not zero) */
+  int precond_sweeps;  /* 0: no preconditioner; k in [1, 64]: left preconditioning with
+                          k block-Jacobi steps on P (trap_apply_preconditioner; needs
+                          trap_precompute_preconditioner).  The inner solves then stop on
+                          the preconditioned residual, refined in FP64 as with an FP32
+                          inner operator (also for FP64: up to max_outer steps) until
+                          the true residual meets tol */
 } trap_solve_opts;
 
 typedef struct {
@@ -130,6 +136,7 @@ typedef struct {
   int applies_fp64;
   int applies_fp32;
   int applies_grouped;    /* FP32 applies made in launches shared with other contexts */
+  int applies_precond;    /* preconditioner applications */
   double final_rel_res;   /* FP64 true residual at exit */
   double ms_total;
 } trap_solve_stats;
@@ -159,6 +166,34 @@ int trap_set_problem(trap_ctx* ctx, const trap_atom_desc* atom, const trap_probl
  * enqueued on the context's stream, and later calls on the context are
  * ordered after it. */
 int trap_precompute(trap_ctx* ctx, int store_mask);
+
+/* Physics-based preconditioner (Sect. 5.3) with the block-diagonal local
+ * inverse of App. F.  P = Id - Lambda* Sigma* in the unmagnetised,
+ * unpolarised, angle-averaged setting, multipole K = Q = 0: Sigma* maps Stokes
+ * I to a Stokes-I emissivity through the comoving interpolation per
+ * direction, the angular mean, a comoving frequency coupling Phi_z (N_nu x
+ * N_nu, zero-field R_II averaged over Theta with 25 Gauss-Legendre nodes, plus
+ * R_III) and the interpolation back; Lambda* is the DELO-linear solution of
+ * Stokes I with the problem's eta_I and no polarisation terms.  P is the
+ * identity on Q, U, V.
+ * trap_precompute_preconditioner builds, after trap_precompute, per height
+ * Phi_z, the local Lambda (the diagonal of Lambda* at the height) and
+ * C_z = Phi_z (Id - A_z)^-1 with A_z of App. F (FP64, Gauss-Jordan with
+ * partial pivoting; a singular Id - A_z gives non-finite tables, which a
+ * solve reports as TRAP_ENAN).  Asynchronous; once per problem (later calls
+ * return at once).  Device memory: about 5 n_z N_nu^2 + n_z n_dir N_nu doubles
+ * plus the kernel scratch, not counted by trap_footprint.
+ * trap_apply_preconditioner: out = M r for FP64 device vectors
+ * [z][Omega][n][4] (out may equal r): x_1 = P^^-1 r_I,
+ * x_{k+1} = x_k + P^^-1 (r_I - P x_k), `sweeps` in [1, 64] steps, then
+ * out_I = x_sweeps and out_{Q,U,V} = r_{Q,U,V}.  The scalar formal solutions
+ * inside run in `prec`, the rest in FP64.  Asynchronous.
+ * trap_preconditioner_tables copies Phi [n_z][N_nu][N_nu], C [n_z][N_nu][N_nu]
+ * and the local Lambda [n_z][n_dir][N_nu] to host arrays (any may be NULL);
+ * synchronises. */
+int trap_precompute_preconditioner(trap_ctx* ctx);
+int trap_apply_preconditioner(trap_ctx* ctx, const double* r, double* out, int sweeps, int prec);
+int trap_preconditioner_tables(trap_ctx* ctx, double* phi, double* c, double* lloc);
 
 /* eps = Sigma I (Eq. matrix_form_2 without eps_th): comoving interpolation,
  * R_II contraction with the stored kernels, angular/sublevel sum, R_III,

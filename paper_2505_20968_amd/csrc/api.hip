@@ -207,6 +207,33 @@ int trap_precompute(trap_ctx* ctx, int store_mask) {
   return run_precompute(ctx, store_mask);
 }
 
+int trap_precompute_preconditioner(trap_ctx* ctx) {
+  if (!ctx) return fail(TRAP_EINVAL, "null context");
+  if (!ctx->has_problem || !ctx->pre.done) return fail(TRAP_ESTATE, "precompute not run");
+  if (ctx->pre.pc_done) return TRAP_OK;
+  DeviceGuard g(ctx->device);
+  return run_precompute_precond(ctx);
+}
+
+int trap_apply_preconditioner(trap_ctx* ctx, const double* r, double* out, int sweeps, int prec) {
+  if (!ctx) return fail(TRAP_EINVAL, "null context");
+  DeviceGuard g(ctx->device);
+  return precond_apply(ctx, r, out, sweeps, prec);
+}
+
+int trap_preconditioner_tables(trap_ctx* ctx, double* phi, double* c, double* lloc) {
+  if (!ctx) return fail(TRAP_EINVAL, "null context");
+  if (!ctx->has_problem || !ctx->pre.pc_done) return fail(TRAP_ESTATE, "preconditioner tables not computed");
+  DeviceGuard g(ctx->device);
+  const Problem& P = ctx->pb;
+  const size_t nmat = (size_t)P.nz * P.nn * P.nn, nloc = (size_t)P.nz * P.nd * P.nn;
+  if (phi) TRAP_HIP(hipMemcpyAsync(phi, ctx->pre.d_pcPhi, nmat * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  if (c) TRAP_HIP(hipMemcpyAsync(c, ctx->pre.d_pcC, nmat * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  if (lloc) TRAP_HIP(hipMemcpyAsync(lloc, ctx->pre.d_pcL, nloc * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  TRAP_HIP(hipStreamSynchronize(ctx->stream));
+  return TRAP_OK;
+}
+
 int trap_apply_sigma(trap_ctx* ctx, const void* I, void* eps, int prec, int add_thermal) {
   if (!ctx) return fail(TRAP_EINVAL, "null context");
   DeviceGuard g(ctx->device);

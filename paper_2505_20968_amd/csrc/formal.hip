@@ -198,6 +198,98 @@ int launch_formal_grouped(hipStream_t s, const GFormal* args, const int* off, in
   return TRAP_OK;
 }
 
+// ------------------------------------------------------------------ preconditioner (Sect. 5.3, App. F)
+// Local Lambda of the unpolarised formal solution: along each ray the
+// response of I at a height to the emissivity at that height is psi_c/eta_I
+// of the step that ends there; zero at the first point of the sweep.
+__global__ void __launch_bounds__(64) k_pc_local_lambda(int nz, int nd, int nn, const double* __restrict__ mu,
+                                                        const double* __restrict__ tau, const double* __restrict__ K8,
+                                                        double* __restrict__ L) {
+  const int id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= nd * nn) return;
+  const int o = id / nn, n = id % nn;
+  const double m = mu[o];
+  const bool up = m > 0.0;
+  const double amu = fabs(m);
+  const long long zs = (long long)nd * nn;
+  int z = up ? 0 : nz - 1;
+  const int dz = up ? 1 : -1;
+  L[(long long)z * zs + id] = 0.0;
+  double ru = K8[((long long)z * zs + id) * 8 + 7];
+  for (int step = 1; step < nz; ++step) {
+    const int zc = z + dz;
+    const long long p = (long long)zc * zs + id;
+    const double rc = K8[p * 8 + 7];
+    const double x = 0.5 * (ru + rc) * fabs(tau[z] - tau[zc]) / amu;
+    double pu, pc, ex;
+    delo_weights<double>(x, pu, pc, ex);
+    L[p] = pc * K8[p * 8 + 6];
+    ru = rc;
+    z = zc;
+  }
+}
+
+int launch_pc_local_lambda(trap_ctx* ctx) {
+  Problem& P = ctx->pb;
+  hipLaunchKernelGGL(k_pc_local_lambda, dim3(ceil_div((long long)P.nd * P.nn, 64)), dim3(64), 0, ctx->stream, P.nz,
+                     P.nd, P.nn, P.d_mu, P.d_tau, ctx->pre.d_K, ctx->pre.d_pcL);
+  TRAP_HIP(hipGetLastError());
+  return TRAP_OK;
+}
+
+// Lambda* e for the Stokes-I emissivity e[z][o][n] (scalar DELO-linear steps,
+// K' = 0, no incoming radiation) in precision T, with the block-Jacobi
+// residual fused: res = y - x + Lambda* e (y read with stride y_stride).
+template <typename T>
+__global__ void __launch_bounds__(64) k_formal_scalar(int nz, int nd, int nn, const double* __restrict__ mu,
+                                                      const double* __restrict__ tau, const double* __restrict__ K8,
+                                                      const double* __restrict__ e, const double* __restrict__ y,
+                                                      int y_stride, const double* __restrict__ x,
+                                                      double* __restrict__ res) {
+  const int id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= nd * nn) return;
+  const int o = id / nn;
+  const double m = mu[o];
+  const bool up = m > 0.0;
+  const T amu = T(fabs(m));
+  const long long zs = (long long)nd * nn;
+  int z = up ? 0 : nz - 1;
+  const int dz = up ? 1 : -1;
+  long long p = (long long)z * zs + id;
+  T I = T(0);
+  T Su = T(e[p]) * T(K8[p * 8 + 6]);
+  T ru = T(K8[p * 8 + 7]);
+  res[p] = y[p * y_stride] - x[p];
+  for (int step = 1; step < nz; ++step) {
+    const int zc = z + dz;
+    p = (long long)zc * zs + id;
+    const T rc = T(K8[p * 8 + 7]);
+    const T Sc = T(e[p]) * T(K8[p * 8 + 6]);
+    const T xx = T(0.5) * (ru + rc) * T(fabs(tau[z] - tau[zc])) / amu;
+    T pu, pc, ex;
+    delo_weights<T>(xx, pu, pc, ex);
+    I = ex * I + pu * Su + pc * Sc;
+    res[p] = y[p * y_stride] - x[p] + (double)I;
+    Su = Sc;
+    ru = rc;
+    z = zc;
+  }
+}
+
+int launch_formal_scalar(trap_ctx* ctx, int prec, const double* e, const double* y, int y_stride, const double* x,
+                         double* res) {
+  Problem& P = ctx->pb;
+  const dim3 grid(ceil_div((long long)P.nd * P.nn, 64));
+  if (prec == TRAP_FP64)
+    hipLaunchKernelGGL(k_formal_scalar<double>, grid, dim3(64), 0, ctx->stream, P.nz, P.nd, P.nn, P.d_mu, P.d_tau,
+                       ctx->pre.d_K, e, y, y_stride, x, res);
+  else
+    hipLaunchKernelGGL(k_formal_scalar<float>, grid, dim3(64), 0, ctx->stream, P.nz, P.nd, P.nn, P.d_mu, P.d_tau,
+                       ctx->pre.d_K, e, y, y_stride, x, res);
+  TRAP_HIP(hipGetLastError());
+  return TRAP_OK;
+}
+
 int formal_apply(trap_ctx* ctx, const void* eps, void* I, int with_boundary, int prec) {
   if (!ctx->has_problem) return fail(TRAP_ESTATE, "no problem loaded");
   if (!ctx->pre.d_K) return fail(TRAP_ESTATE, "precompute not run");

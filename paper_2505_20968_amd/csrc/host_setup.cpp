@@ -382,6 +382,8 @@ std::vector<double> spline_map(const std::vector<double>& x, std::vector<double>
 
 }  // namespace
 
+void gauss_legendre_unit(int n, std::vector<double>& t, std::vector<double>& w) { gauss_legendre01(n, t, w); }
+
 // Angular grid (double Gauss-Legendre mu x trapezoidal chi, Sect. 4.2), the
 // distinct scattering angles, the (incoming direction, Theta) slots, the pair
 // lists per slot and the slot groups of the fused Sigma kernel.
@@ -696,6 +698,94 @@ size_t estimate_bytes(const trap_atom_desc* atom, const trap_problem_desc* pd, i
   return b;
 }
 
+// Weights of the preconditioner's comoving coupling (Sect. 5.3, App. F): the
+// comoving Stokes-I emissivity of the zero-field atom for an isotropic,
+// unpolarised comoving field J (K = Q = 0).  With the angle-averaged kernels
+// M_k and R_III rows R_k / profiles P_k of the zero-field transition classes k,
+//   Phi J = sum_k (cr_k Re M_k + ci_k Im M_k) J
+//         + sum_{a,b} Re[X1 P_a (R_b.J) + X2 conj(P_a) (R_b.J) + X3 P_a (conj R_b.J) + X4 conj(P_a) (conj R_b.J)].
+// They follow from the scattering sums of Sigma (App. D) with the incoming
+// factor summed over directions, which an isotropic field allows; the total
+// is then the same for every outgoing direction, so direction 0 is used.
+static void precond_weights(Problem& P, const trap_atom_desc& at, double dnuD_ref, const std::vector<double>& ea,
+                            const std::vector<double>& eb, const std::vector<double>& ub, double rE) {
+  const int nz = P.nz, nd = P.nd;
+  const Sublevels s0 = sublevels(at, 0.0, 0.0, 0.0, dnuD_ref);
+  const int nu = static_cast<int>(s0.Eu.size()), nl = static_cast<int>(s0.El.size()), nt = nu * nl;
+  std::vector<int> cls(nt);
+  P.pc_dE.clear();
+  for (int u = 0; u < nu; ++u)
+    for (int l = 0; l < nl; ++l) {
+      const double e = s0.Eu[u] - s0.El[l];
+      int k = 0;
+      while (k < (int)P.pc_dE.size() && std::fabs(P.pc_dE[k] - e) > 1e-9 * std::max(1.0, std::fabs(e))) ++k;
+      if (k == (int)P.pc_dE.size()) P.pc_dE.push_back(e);
+      cls[u * nl + l] = k;
+    }
+  const int nk = P.pc_nk = static_cast<int>(P.pc_dE.size());
+  // incoming factor summed over directions, SA[q][p][l] = sum_x w_x d_ql^T Acart_0(x)/2 d_pl^*,
+  // and the outgoing factor of direction 0, E0[p][q][l'] = d_pl'^T Acart_0(0) d_ql'^*
+  std::vector<cd> SA((size_t)nu * nu * nl, cd(0, 0)), E0((size_t)nu * nu * nl);
+  std::vector<cd> pa(nt), pb(nt);
+  for (int o = 0; o < nd; ++o) {
+    for (int t = 0; t < nt; ++t) stokes_proj(&s0.d[t * 3], &ea[3 * o], &eb[3 * o], &pa[t], &pb[t]);
+    for (int q = 0; q < nu; ++q)
+      for (int p = 0; p < nu; ++p)
+        for (int l = 0; l < nl; ++l) {
+          const int tq = q * nl + l, tp = p * nl + l;
+          SA[((size_t)q * nu + p) * nl + l] +=
+              P.w[o] * 0.5 * stokes_pair(0, pa[tq], pb[tq], std::conj(pa[tp]), std::conj(pb[tp]));
+          if (o == 0) E0[((size_t)p * nu + q) * nl + l] = stokes_pair(0, pa[tp], pb[tp], std::conj(pa[tq]), std::conj(pb[tq]));
+        }
+  }
+  P.pc_cr.assign((size_t)nz * nk, 0.0);
+  P.pc_ci.assign((size_t)nz * nk, 0.0);
+  P.pc_X.assign((size_t)nz * 4 * nk * nk, make_double2(0.0, 0.0));
+  for (int z = 0; z < nz; ++z) {
+    const double gtot = 4.0 * kPi * P.a[z] * P.dnuD[z];
+    const double gri = gtot / (1.0 + rE);
+    const double gr = (1.0 - P.eps[z]) * gri;
+    std::vector<cd> X(4 * nk * nk, cd(0, 0));
+    for (int l = 0; l < nl; ++l)
+      for (int lp = 0; lp < nl; ++lp)
+        for (int q = 0; q < nu; ++q)
+          for (int p = 0; p < nu; ++p) {
+            const double nuqp = s0.Eu[q] - s0.Eu[p];
+            const cd al = gr / cd(gtot, 2.0 * kPi * nuqp);
+            const cd bma = gr / cd(gri, 2.0 * kPi * nuqp) - al;
+            const cd C = P.c_sc * E0[((size_t)p * nu + q) * nl + lp] * SA[((size_t)q * nu + p) * nl + l];
+            const cd g = C * al / (2.0 * kPi), h = C * bma / (4.0 * kPi);
+            const int kp = cls[p * nl + l], kq = cls[q * nl + l];
+            // R_II: g W_{p l} + g conj(W_{q l})
+            P.pc_cr[z * nk + kp] += g.real();
+            P.pc_ci[z * nk + kp] -= g.imag();
+            P.pc_cr[z * nk + kq] += g.real();
+            P.pc_ci[z * nk + kq] += g.imag();
+            // R_III: h (y_p + conj y_q)(P_p + conj P_q)
+            X[(0 * nk + kp) * nk + kp] += h;
+            X[(1 * nk + kq) * nk + kp] += h;
+            X[(2 * nk + kp) * nk + kq] += h;
+            X[(3 * nk + kq) * nk + kq] += h;
+          }
+    for (int i = 0; i < 4 * nk * nk; ++i) P.pc_X[(size_t)z * 4 * nk * nk + i] = make_double2(X[i].real(), X[i].imag());
+  }
+  // directions of equal Doppler shift share the interpolation maps
+  P.pc_dcls.assign((size_t)nz * nd, 0);
+  P.pc_cub.assign((size_t)nz * nd, 0.0);
+  P.pc_ncls.assign(nz, 0);
+  for (int z = 0; z < nz; ++z) {
+    int nc = 0;
+    for (int o = 0; o < nd; ++o) {
+      const double v = ub[(size_t)z * nd + o];
+      int c = 0;
+      while (c < nc && P.pc_cub[(size_t)z * nd + c] != v) ++c;
+      if (c == nc) P.pc_cub[(size_t)z * nd + nc++] = v;
+      P.pc_dcls[(size_t)z * nd + o] = c;
+    }
+    P.pc_ncls[z] = nc;
+  }
+}
+
 int build_problem(trap_ctx* ctx, const trap_atom_desc* at, const trap_problem_desc* pd) {
   if (!at || !pd) return fail(TRAP_EINVAL, "null descriptor");
   if (pd->n_z < 2 || pd->n_nu < 4 || pd->n_mu < 2 || (pd->n_mu & 1) || pd->n_chi < 1)
@@ -817,6 +907,7 @@ int build_problem(trap_ctx* ctx, const trap_atom_desc* at, const trap_problem_de
             }
     }
   }
+  precond_weights(P, *at, dnuD_ref, ea, eb, ub, rE);
   // ---- upload
   std::vector<double> sig;
   auto spl = spline_map(P.x, &sig);

@@ -963,6 +963,249 @@ int run_precompute(trap_ctx* ctx, int store_mask) {
   return TRAP_OK;
 }
 
+// ------------------------------------------------------------------ preconditioner tables
+// Comoving coupling of the preconditioner (Sect. 5.3): for height z and row n,
+//   Phi[z][n][m] = sum_k (cr_k M_k^re[n][m] + ci_k M_k^im[n][m])
+//                + sum_{a,b} Re[X1_ab P_a(n) R_b(m) + X2_ab conj(P_a(n)) R_b(m)
+//                               + X3_ab P_a(n) conj(R_b(m)) + X4_ab conj(P_a(n)) conj(R_b(m))]
+// with the angle-averaged kernels M_k, R_III rows R_k and profiles P_k of the
+// zero-field transition classes.
+__global__ void __launch_bounds__(128) k_pc_phi(int nk, int nn, int ldm, const double* __restrict__ M,
+                                                const double* __restrict__ cr, const double* __restrict__ ci,
+                                                const double2* __restrict__ X, const double2* __restrict__ R3,
+                                                const double2* __restrict__ prof, double* __restrict__ Phi) {
+  const int z = blockIdx.x / nn, n = blockIdx.x % nn;
+  for (int m = threadIdx.x; m < nn; m += blockDim.x) {
+    double v = 0.0;
+    for (int k = 0; k < nk; ++k) {
+      const size_t base = ((size_t)(z * nk + k) * 2) * nn * ldm + (size_t)n * ldm + m;
+      v += cr[z * nk + k] * M[base] + ci[z * nk + k] * M[base + (size_t)nn * ldm];
+    }
+    const double2* Xz = X + (size_t)z * 4 * nk * nk;
+    for (int a = 0; a < nk; ++a) {
+      const double2 pa = prof[((size_t)z * nk + a) * nn + n];
+      for (int b = 0; b < nk; ++b) {
+        const double2 rb = R3[((size_t)z * nk + b) * nn + m];
+        const int ab = a * nk + b;
+        v += cmul(Xz[ab], cmul(pa, rb)).x + cmul(Xz[nk * nk + ab], cmul(cconj(pa), rb)).x +
+             cmul(Xz[2 * nk * nk + ab], cmul(pa, cconj(rb))).x +
+             cmul(Xz[3 * nk * nk + ab], cmul(cconj(pa), cconj(rb))).x;
+      }
+    }
+    Phi[((size_t)z * nn + n) * nn + m] = v;
+  }
+}
+
+// Column m of A_z = sum_Omega w_Omega U_Omega Lambda_zz(Omega) V_Omega Phi_z,
+// directions of equal Doppler shift taken together: the column of Phi is
+// interpolated to the class's observer grid (x_n + u_b/lam), weighted by the
+// summed w Lambda_zz of the class, interpolated back to the comoving grid
+// (x_m - u_b/lam) and accumulated.  One block per (z, m).
+__global__ void __launch_bounds__(128) k_pc_A(int nd, int nn, const double* __restrict__ x,
+                                              const double* __restrict__ SigT, const double* __restrict__ lam,
+                                              const double* __restrict__ w, const int* __restrict__ dcls,
+                                              const int* __restrict__ ncls, const double* __restrict__ cub,
+                                              const double* __restrict__ L, const double* __restrict__ Phi,
+                                              double* __restrict__ A) {
+  extern __shared__ double sh[];
+  double* ph = sh;
+  double* sp = sh + nn;
+  double* g = sh + 2 * nn;
+  double* sg = sh + 3 * nn;
+  double* acc = sh + 4 * nn;
+  const int z = blockIdx.x / nn, m = blockIdx.x % nn;
+  const double* Pz = Phi + (size_t)z * nn * nn;
+  for (int j = threadIdx.x; j < nn; j += blockDim.x) {
+    ph[j] = Pz[(size_t)j * nn + m];
+    acc[j] = 0.0;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < nn; i += blockDim.x) {
+    double a = 0.0;
+    for (int j = 0; j < nn; ++j) a += SigT[(size_t)j * nn + i] * ph[j];
+    sp[i] = a;
+  }
+  __syncthreads();
+  const double Lz = lam[z];
+  for (int c = 0; c < ncls[z]; ++c) {
+    const double shf = cub[(size_t)z * nd + c] / Lz;
+    for (int n = threadIdx.x; n < nn; n += blockDim.x) {
+      double d = 0.0;
+      for (int o = 0; o < nd; ++o)
+        if (dcls[(size_t)z * nd + o] == c) d += w[o] * L[((size_t)z * nd + o) * nn + n];
+      g[n] = d * spline_at(x, nn, ph, sp, x[n] + shf);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < nn; i += blockDim.x) {
+      double a = 0.0;
+      for (int j = 0; j < nn; ++j) a += SigT[(size_t)j * nn + i] * g[j];
+      sg[i] = a;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < nn; i += blockDim.x) acc[i] += spline_at(x, nn, g, sg, x[i] - shf);
+    __syncthreads();
+  }
+  for (int i = threadIdx.x; i < nn; i += blockDim.x) A[((size_t)z * nn + i) * nn + m] = acc[i];
+}
+
+// C_z = Phi_z (Id - A_z)^-1 from (Id - A_z)^T C_z^T = Phi_z^T: Gauss-Jordan
+// elimination with partial pivoting on [ (Id - A_z)^T | Phi_z^T ] (rows of
+// 2 nn entries in global scratch), one block per height.
+constexpr int kInvThreads = 1024;
+
+__global__ void __launch_bounds__(kInvThreads) k_pc_invert(int nn, const double* __restrict__ A,
+                                                           const double* __restrict__ Phi, double* __restrict__ aug,
+                                                           double* __restrict__ C) {
+  __shared__ double rv[kInvThreads];
+  __shared__ int ri[kInvThreads];
+  __shared__ double fac[1024];
+  const int z = blockIdx.x, tid = threadIdx.x;
+  const int w2 = 2 * nn;
+  double* G = aug + (size_t)z * nn * w2;
+  const double* Az = A + (size_t)z * nn * nn;
+  const double* Pz = Phi + (size_t)z * nn * nn;
+  for (int e = tid; e < nn * w2; e += blockDim.x) {
+    const int i = e / w2, j = e % w2;
+    G[e] = j < nn ? (i == j ? 1.0 : 0.0) - Az[(size_t)j * nn + i] : Pz[(size_t)(j - nn) * nn + i];
+  }
+  __syncthreads();
+  for (int k = 0; k < nn; ++k) {
+    // pivot: the largest |G[i][k]|, i >= k
+    double best = -1.0;
+    int bi = k;
+    for (int i = k + tid; i < nn; i += blockDim.x) {
+      const double v = fabs(G[(size_t)i * w2 + k]);
+      if (v > best) {
+        best = v;
+        bi = i;
+      }
+    }
+    rv[tid] = best;
+    ri[tid] = bi;
+    __syncthreads();
+    for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+      if (tid < st && (rv[tid + st] > rv[tid] || (rv[tid + st] == rv[tid] && ri[tid + st] < ri[tid]))) {
+        rv[tid] = rv[tid + st];
+        ri[tid] = ri[tid + st];
+      }
+      __syncthreads();
+    }
+    const int p = ri[0];
+    if (p != k)
+      for (int j = k + tid; j < w2; j += blockDim.x) {
+        const double t = G[(size_t)k * w2 + j];
+        G[(size_t)k * w2 + j] = G[(size_t)p * w2 + j];
+        G[(size_t)p * w2 + j] = t;
+      }
+    __syncthreads();
+    const double inv = 1.0 / G[(size_t)k * w2 + k];
+    __syncthreads();
+    for (int j = k + tid; j < w2; j += blockDim.x) G[(size_t)k * w2 + j] *= inv;
+    for (int i = tid; i < nn; i += blockDim.x) fac[i] = (i == k) ? 0.0 : G[(size_t)i * w2 + k];
+    __syncthreads();
+    const int wk = w2 - k - 1;
+    for (long long e = tid; e < (long long)nn * wk; e += blockDim.x) {
+      const int i = (int)(e / wk), j = k + 1 + (int)(e % wk);
+      if (i != k) G[(size_t)i * w2 + j] -= fac[i] * G[(size_t)k * w2 + j];
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < nn * nn; e += blockDim.x) {
+    const int n = e / nn, m = e % nn;
+    C[(size_t)z * nn * nn + e] = G[(size_t)m * w2 + nn + n];
+  }
+}
+
+int run_precompute_precond(trap_ctx* ctx) {
+  Problem& P = ctx->pb;
+  Precomp& C = ctx->pre;
+  hipStream_t s = ctx->stream;
+  if (!ctx->has_problem || !C.done) return fail(TRAP_ESTATE, "precompute not run");
+  const int nz = P.nz, nd = P.nd, nn = P.nn, ldm = P.ldm, nk = P.pc_nk, ng = 25;
+  if (nn > 1024) return fail(TRAP_EINVAL, "frequency grid too large for the preconditioner (n_nu > 1024)");
+  if (nk < 1) return fail(TRAP_ESTATE, "no zero-field transitions");
+  TRAP_TRY(load_constants(ctx->device));
+  const size_t lds_row = (size_t)(nn + 1) * 4 * sizeof(double2);
+  if (lds_row > 64 * 1024) return fail(TRAP_EINVAL, "frequency grid too large for the kernel precompute");
+  const PrecompLayout lay = precomp_layout(nz, nn, ldm, nk, ng, true, P.x.data(), P.lam.data());
+  const size_t rows_per_z = (size_t)ng * nk * 2 * nn;
+  // row scratch in height chunks of at most 32 MB per buffer
+  const int zc_max = (int)std::max<size_t>(1, std::min<size_t>(nz, (size_t(32) << 20) / (rows_per_z * ldm * 8)));
+  if (!C.d_pcPhi) {
+    std::vector<double> st((size_t)nz * nk), gt, gw, th(ng), rw(ng);
+    for (int z = 0; z < nz; ++z)
+      for (int k = 0; k < nk; ++k) st[(size_t)z * nk + k] = P.pc_dE[k] / P.dnuD[z];
+    gauss_legendre_unit(ng, gt, gw);
+    for (int g = 0; g < ng; ++g) {
+      th[g] = kPiD * gt[g];
+      rw[g] = kPiD * gw[g] * 0.5 * std::sin(th[g]);
+    }
+    UploadBatch up;
+    up.add(&C.d_pcSt, st);
+    up.add(&C.d_pcCr, P.pc_cr);
+    up.add(&C.d_pcCi, P.pc_ci);
+    up.add(&C.d_pcX, P.pc_X);
+    up.add(&C.d_pcDcls, P.pc_dcls);
+    up.add(&C.d_pcNcls, P.pc_ncls);
+    up.add(&C.d_pcCub, P.pc_cub);
+    up.add(&C.d_pcTheta, th);
+    up.add(&C.d_pcRw, rw);
+    TRAP_TRY(up.commit(ctx));
+    TRAP_TRY(dalloc_t(ctx, &C.d_pcPhi, (size_t)nz * nn * nn));
+    TRAP_TRY(dalloc_t(ctx, &C.d_pcC, (size_t)nz * nn * nn));
+    TRAP_TRY(dalloc_t(ctx, &C.d_pcL, (size_t)nz * nd * nn));
+    TRAP_TRY(dalloc_t(ctx, &C.d_pcA, (size_t)nz * nn * nn * 3));
+    TRAP_TRY(dalloc_t(ctx, &C.d_pcM, (size_t)nz * nk * 2 * nn * ldm));
+    TRAP_TRY(dalloc_t(ctx, &C.d_pcR3, (size_t)nz * nk * nn));
+    TRAP_TRY(dalloc_t(ctx, &C.d_pcProf, (size_t)nz * nk * nn));
+  }
+  // angle-averaged kernels of the zero-field classes: rows at the
+  // Gauss-Legendre angles, then their weighted sum (as the AA precompute)
+  double *Gt = nullptr, *Lrow = nullptr, *Grow = nullptr, *Mtmp = nullptr;
+  double2* Vt = nullptr;
+  if (lay.uniform) {
+    TRAP_TRY(dalloc_t(ctx, &Gt, (size_t)zc_max * ng * lay.nd2 * 16));
+    TRAP_TRY(dalloc_t(ctx, &Vt, (size_t)zc_max * ng * nk * lay.nd2 * 16));
+  }
+  TRAP_TRY(dalloc_t(ctx, &Lrow, (size_t)zc_max * rows_per_z * ldm));
+  TRAP_TRY(dalloc_t(ctx, &Grow, (size_t)zc_max * rows_per_z * ldm));
+  TRAP_TRY(dalloc_t(ctx, &Mtmp, (size_t)zc_max * rows_per_z * ldm));
+  const int rw = (int)std::max<size_t>(1, std::min<size_t>(kRowWavesMax, (56 * 1024) / lds_row));
+  const long long per_z_out = (long long)nk * 2 * nn * ldm;
+  for (int z0 = 0; z0 < nz; z0 += zc_max) {
+    const int zc = std::min(zc_max, nz - z0);
+    if (lay.uniform) {
+      hipLaunchKernelGGL(k_kernel_tables, dim3(zc * ng * nk), dim3(256), 0, s, z0, ng, nk, nn, lay.ntail, P.x[0],
+                         lay.h, P.d_lam, P.d_a, C.d_pcSt, C.d_pcTheta, Gt, Vt);
+      TRAP_HIP(hipGetLastError());
+    }
+    const long long nrows = (long long)zc * ng * nk * nn;
+    hipLaunchKernelGGL(k_kernel_rows, dim3((unsigned)ceil_div(nrows, rw)), dim3(64 * rw), rw * lds_row, s, nrows, ng,
+                       nk, nn, ldm, P.d_x, P.d_lam, P.d_a, C.d_pcSt, C.d_pcTheta, Lrow, Grow, 0LL, z0, lay.h,
+                       lay.uniform ? Gt : nullptr, lay.uniform ? Vt : nullptr, lay.ntail);
+    TRAP_HIP(hipGetLastError());
+    TRAP_TRY(launch_sig_gemm(ctx, 2 * nrows, Grow, Lrow, Mtmp, (float*)nullptr, 0LL));
+    hipLaunchKernelGGL(k_theta_average, dim3(ceil_div(per_z_out * zc, 256)), dim3(256), 0, s, per_z_out, ng, zc,
+                       C.d_pcRw, Mtmp, C.d_pcM, (float*)nullptr, (long long)z0 * per_z_out);
+    TRAP_HIP(hipGetLastError());
+  }
+  hipLaunchKernelGGL(k_r3_rows, dim3(nz * nk), dim3(64), lds_row, s, nk, nn, P.d_x, P.d_P, P.d_lam, P.d_a, C.d_pcSt,
+                     C.d_pcR3, C.d_pcProf);
+  TRAP_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_pc_phi, dim3(nz * nn), dim3(128), 0, s, nk, nn, ldm, C.d_pcM, C.d_pcCr, C.d_pcCi, C.d_pcX,
+                     C.d_pcR3, C.d_pcProf, C.d_pcPhi);
+  TRAP_HIP(hipGetLastError());
+  TRAP_TRY(launch_pc_local_lambda(ctx));
+  hipLaunchKernelGGL(k_pc_A, dim3(nz * nn), dim3(128), 5 * nn * sizeof(double), s, nd, nn, P.d_x, P.d_SigT, P.d_lam,
+                     P.d_w, C.d_pcDcls, C.d_pcNcls, C.d_pcCub, C.d_pcL, C.d_pcPhi, C.d_pcA);
+  TRAP_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_pc_invert, dim3(nz), dim3(kInvThreads), 0, s, nn, C.d_pcA, C.d_pcPhi,
+                     C.d_pcA + (size_t)nz * nn * nn, C.d_pcC);
+  TRAP_HIP(hipGetLastError());
+  C.pc_done = true;
+  return TRAP_OK;
+}
+
 void faddeeva_coefficients(FaddeevaCoef* out) {
   const int N = kWeidemanN, M = 2 * N;
   const double L = sqrt(N / sqrt(2.0));

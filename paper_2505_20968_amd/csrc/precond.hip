@@ -1,0 +1,153 @@
+// Physics-based preconditioner (paper Sect. 5.3) with the block-diagonal
+// local inverse of App. F, applied as a fixed number of block-Jacobi steps.
+//
+// P = Id - Lambda* Sigma* acts on Stokes I only (Q, U, V pass through):
+// Sigma* = Ups^{nubar->nu} Phi Phi^Omega Ups^{nu->nubar} per height
+// (interpolation to the comoving grid per direction, angular mean, comoving
+// coupling Phi_z, interpolation back) and Lambda* the scalar DELO-linear
+// formal solution with the problem's eta_I.  The local blocks
+// Id - Lambda_zz Sigma*_z are inverted in closed form,
+//   P^_z^-1 r = r + Lambda_zz Ups^{nubar->nu} C_z Phi^Omega Ups^{nu->nubar} r,
+//   C_z = Phi_z (Id - A_z)^-1 (tables from the precompute),
+// and M r = x_k with x_1 = P^^-1 r, x_{j+1} = x_j + P^^-1 (r - P x_j): a
+// fixed linear map, so left-preconditioned GMRES stays plain GMRES.
+//
+// Per step two kinds of kernels: a per-height one (angular mean of the
+// comoving field, one N_nu x N_nu matrix-vector product, spline second
+// derivatives of the result) and a per-point one (interpolation back to every
+// direction, combined with the local Lambda and the running iterate); the
+// sweeps add the scalar formal solution with the residual fused into it.
+#include "trap_internal.h"
+
+namespace trap {
+
+// hz = Mat_z sum_c Ups_c (sum_{o in c} w_o src_o) for every height z, where
+// class c holds the directions of one Doppler shift; hz and its spline second
+// derivatives go to h[z][0][.] and h[z][1][.].  One block per height.
+__global__ void __launch_bounds__(256) k_pc_gather(int nd, int nn, const double* __restrict__ x,
+                                                   const double* __restrict__ SigT, const double* __restrict__ lam,
+                                                   const double* __restrict__ w, const int* __restrict__ dcls,
+                                                   const int* __restrict__ ncls, const double* __restrict__ cub,
+                                                   const double* __restrict__ src, int stride,
+                                                   const double* __restrict__ Mat, double* __restrict__ h) {
+  extern __shared__ double sh[];
+  double* v = sh;
+  double* sd = sh + nn;
+  double* G = sh + 2 * nn;
+  double* hv = sh + 3 * nn;
+  const int z = blockIdx.x;
+  for (int m = threadIdx.x; m < nn; m += blockDim.x) G[m] = 0.0;
+  const double Lz = lam[z];
+  for (int c = 0; c < ncls[z]; ++c) {
+    const double shf = cub[(size_t)z * nd + c] / Lz;
+    for (int n = threadIdx.x; n < nn; n += blockDim.x) {
+      double a = 0.0;
+      for (int o = 0; o < nd; ++o)
+        if (dcls[(size_t)z * nd + o] == c) a += w[o] * src[(((size_t)z * nd + o) * nn + n) * stride];
+      v[n] = a;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < nn; i += blockDim.x) {
+      double a = 0.0;
+      for (int j = 0; j < nn; ++j) a += SigT[(size_t)j * nn + i] * v[j];
+      sd[i] = a;
+    }
+    __syncthreads();
+    for (int m = threadIdx.x; m < nn; m += blockDim.x) G[m] += spline_at(x, nn, v, sd, x[m] - shf);
+    __syncthreads();
+  }
+  const double* Mz = Mat + (size_t)z * nn * nn;
+  for (int n = threadIdx.x; n < nn; n += blockDim.x) {
+    double a = 0.0;
+    for (int m = 0; m < nn; ++m) a += Mz[(size_t)n * nn + m] * G[m];
+    hv[n] = a;
+  }
+  __syncthreads();
+  double* hz = h + (size_t)z * 2 * nn;
+  for (int i = threadIdx.x; i < nn; i += blockDim.x) {
+    double a = 0.0;
+    for (int j = 0; j < nn; ++j) a += SigT[(size_t)j * nn + i] * hv[j];
+    hz[i] = hv[i];
+    hz[nn + i] = a;
+  }
+}
+
+enum PcScatter { PC_FIRST = 0, PC_SIGMA = 1, PC_UPDATE = 2 };
+
+// per point p = (z, o, n), with v = S[h_z](x_n + u_b(z, o)/lam_z):
+//   PC_FIRST:  dst = src + L v            (x_1 = P^^-1 y)
+//   PC_SIGMA:  dst = v                    (Sigma* x)
+//   PC_UPDATE: dst = xin + res + L v      (x += P^^-1 res)
+__global__ void __launch_bounds__(256) k_pc_scatter(int mode, int nz, int nd, int nn, const double* __restrict__ x,
+                                                    const double* __restrict__ lam, const double* __restrict__ ub,
+                                                    const double* __restrict__ h, const double* __restrict__ L,
+                                                    const double* src, int src_stride, const double* xin,
+                                                    const double* __restrict__ res, double* dst, int dst_stride) {
+  const long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (p >= (long long)nz * nd * nn) return;
+  const int n = (int)(p % nn);
+  const long long zo = p / nn;
+  const int z = (int)(zo / nd);
+  const double* hz = h + (size_t)z * 2 * nn;
+  const double v = spline_at(x, nn, hz, hz + nn, x[n] + ub[zo] / lam[z]);
+  double out;
+  if (mode == PC_FIRST) out = src[p * src_stride] + L[p] * v;
+  else if (mode == PC_SIGMA) out = v;
+  else out = xin[p] + res[p] + L[p] * v;
+  dst[p * dst_stride] = out;
+}
+
+static int pc_gather(trap_ctx* ctx, const double* src, int stride, const double* Mat) {
+  Problem& P = ctx->pb;
+  Precomp& C = ctx->pre;
+  hipLaunchKernelGGL(k_pc_gather, dim3(P.nz), dim3(256), 4 * P.nn * sizeof(double), ctx->stream, P.nd, P.nn, P.d_x,
+                     P.d_SigT, P.d_lam, P.d_w, C.d_pcDcls, C.d_pcNcls, C.d_pcCub, src, stride, Mat, ctx->wk.pc_h);
+  TRAP_HIP(hipGetLastError());
+  return TRAP_OK;
+}
+
+static int pc_scatter(trap_ctx* ctx, int mode, const double* src, int src_stride, const double* xin,
+                      const double* res, double* dst, int dst_stride) {
+  Problem& P = ctx->pb;
+  const long long ns = (long long)P.nz * P.nd * P.nn;
+  hipLaunchKernelGGL(k_pc_scatter, dim3(ceil_div(ns, 256)), dim3(256), 0, ctx->stream, mode, P.nz, P.nd, P.nn,
+                     P.d_x, P.d_lam, P.d_ub, ctx->wk.pc_h, ctx->pre.d_pcL, src, src_stride, xin, res, dst,
+                     dst_stride);
+  TRAP_HIP(hipGetLastError());
+  return TRAP_OK;
+}
+
+int precond_apply(trap_ctx* ctx, const double* r, double* out, int sweeps, int prec) {
+  if (!ctx->has_problem || !ctx->pre.pc_done) return fail(TRAP_ESTATE, "preconditioner tables not computed");
+  if (!r || !out) return fail(TRAP_EINVAL, "null vector");
+  if (sweeps < 1 || sweeps > 64) return fail(TRAP_EINVAL, "preconditioner sweeps must be in [1, 64]");
+  if (prec != TRAP_FP64 && prec != TRAP_FP32) return fail(TRAP_EINVAL, "unknown precision");
+  Problem& P = ctx->pb;
+  Precomp& C = ctx->pre;
+  Work& K = ctx->wk;
+  const long long ns = (long long)P.nz * P.nd * P.nn;
+  if (!K.pc_h) {
+    TRAP_TRY(dalloc_t(ctx, &K.pc_x, ns));
+    TRAP_TRY(dalloc_t(ctx, &K.pc_e, ns));
+    TRAP_TRY(dalloc_t(ctx, &K.pc_res, ns));
+    TRAP_TRY(dalloc_t(ctx, &K.pc_h, (size_t)P.nz * 2 * P.nn));
+  }
+  if (out != r) TRAP_HIP(hipMemcpyAsync(out, r, 4 * ns * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+  // x_1 = P^^-1 y with y the Stokes I of `out` (read until the last write)
+  TRAP_TRY(pc_gather(ctx, out, 4, C.d_pcC));
+  if (sweeps == 1) return pc_scatter(ctx, PC_FIRST, out, 4, nullptr, nullptr, out, 4);
+  TRAP_TRY(pc_scatter(ctx, PC_FIRST, out, 4, nullptr, nullptr, K.pc_x, 1));
+  for (int k = 2; k <= sweeps; ++k) {
+    // res = y - P x = y - x + Lambda* Sigma* x
+    TRAP_TRY(pc_gather(ctx, K.pc_x, 1, C.d_pcPhi));
+    TRAP_TRY(pc_scatter(ctx, PC_SIGMA, nullptr, 0, nullptr, nullptr, K.pc_e, 1));
+    TRAP_TRY(launch_formal_scalar(ctx, prec, K.pc_e, out, 4, K.pc_x, K.pc_res));
+    // x += P^^-1 res
+    TRAP_TRY(pc_gather(ctx, K.pc_res, 1, C.d_pcC));
+    const bool last = k == sweeps;
+    TRAP_TRY(pc_scatter(ctx, PC_UPDATE, nullptr, 0, K.pc_x, K.pc_res, last ? out : K.pc_x, last ? 4 : 1));
+  }
+  return TRAP_OK;
+}
+
+}  // namespace trap

@@ -186,6 +186,7 @@ struct GmresRun {
   long long N = 0;
   int m = 0, prec = TRAP_FP64, phase = GP_DONE, status = TRAP_OK;
   int outer = 0, j = 0, max_outer = 1;
+  int pc = 0;                 // preconditioner sweeps (0: none)
   bool p2 = false;            // an Arnoldi step waits for its second reduction
   bool begin_pending = false; // ||b|| and the initial-guess check are read at the first step
   double bnorm = 0, beta = 0, target = 0, res = 0, rel = 0;
@@ -245,6 +246,10 @@ int gmres_begin(trap_ctx* ctx, const trap_solve_opts* opts, double* I) {
   const int inner = opts->inner;
   if (inner != TRAP_FP64 && inner != TRAP_FP32) return fail(TRAP_EINVAL, "bad inner precision");
   if (inner == TRAP_FP32 && !ctx->pre.d_M32) return fail(TRAP_ESTATE, "FP32 kernels not stored");
+  if (opts->precond_sweeps < 0 || opts->precond_sweeps > 64)
+    return fail(TRAP_EINVAL, "preconditioner sweeps must be in [0, 64]");
+  if (opts->precond_sweeps > 0 && !ctx->pre.pc_done)
+    return fail(TRAP_ESTATE, "preconditioner tables not computed");
   Work& K = ctx->wk;
   const long long N = 4LL * ctx->pb.nz * ctx->pb.nd * ctx->pb.nn;
   TRAP_TRY(ensure_work(ctx, TRAP_FP64));
@@ -275,7 +280,10 @@ int gmres_begin(trap_ctx* ctx, const trap_solve_opts* opts, double* I) {
   R.prec = inner;
   R.outer = 0;
   R.p2 = false;
-  R.max_outer = inner == TRAP_FP64 ? 1 : std::max(1, opts->max_outer);
+  R.pc = opts->precond_sweeps;
+  // the preconditioned inner solves stop on the preconditioned residual, so
+  // the true residual is refined in an outer loop in either precision
+  R.max_outer = (inner == TRAP_FP64 && R.pc == 0) ? 1 : std::max(1, opts->max_outer);
   R.H.assign((size_t)(m + 1) * m, 0.0);
   R.cs.assign(m, 0.0);
   R.sn.assign(m, 0.0);
@@ -354,12 +362,28 @@ int unit_issue1_rest(trap_ctx* ctx, GmresRun& R) {
     case GP_RESID_OUTER:
       hipLaunchKernelGGL(k_axpby, dim3(kBlocks), dim3(256), 0, ctx->stream, N, 1.0, ctx->pre.d_b, -1.0, K.r);
       TRAP_HIP(hipGetLastError());
+      if (R.pc) {
+        // M r into tmp64; ||r||^2 and ||M r||^2 in the first two slots
+        TRAP_TRY(precond_apply(ctx, K.r, K.tmp64, R.pc, R.prec));
+        R.st.applies_precond++;
+        TRAP_TRY(dots_async(ctx, R, K.r, 1, K.r, R.hbuf));
+        return dots_async(ctx, R, K.tmp64, 1, K.tmp64, R.hbuf + 1);
+      }
       return dots_async(ctx, R, K.r, 1, K.r, R.hbuf);
     case GP_RESID_RESTART:
       hipLaunchKernelGGL(k_axpby, dim3(kBlocks), dim3(256), 0, ctx->stream, N, 1.0, K.r, -1.0, K.tmp64);
       TRAP_HIP(hipGetLastError());
+      if (R.pc) {
+        TRAP_TRY(precond_apply(ctx, K.tmp64, K.tmp64, R.pc, R.prec));
+        R.st.applies_precond++;
+      }
       return dots_async(ctx, R, K.tmp64, 1, K.tmp64, R.hbuf);
     case GP_ARNOLDI:
+      if (R.pc) {
+        double* w = K.V + (size_t)(R.j + 1) * N;
+        TRAP_TRY(precond_apply(ctx, w, w, R.pc, R.prec));
+        R.st.applies_precond++;
+      }
       return dots_async(ctx, R, K.V, R.j + 2, K.V + (size_t)(R.j + 1) * N, R.hbuf);   // last entry: |w|^2
     default:
       return TRAP_OK;
@@ -446,6 +470,19 @@ int unit_after1(trap_ctx* ctx, GmresRun& R) {
       R.outer++;
       R.st.outer_steps = R.outer;
       TRAP_HIP(hipMemsetAsync(K.x, 0, N * sizeof(double), ctx->stream));
+      if (R.pc) {
+        // the inner solve sees the preconditioned residual M r; its goal
+        // scales with ||M r|| / ||r||
+        const double pn = std::sqrt(std::max(R.hbuf[1], 0.0));
+        if (!std::isfinite(pn) || !(pn > 0.0)) {
+          run_finish(R, fail(TRAP_ENAN, "non-finite or zero preconditioned residual"));
+          return TRAP_OK;
+        }
+        // (an FP64 inner operator has no precision floor: it aims at tol at once)
+        const double goal = 0.5 * R.opts.tol * R.bnorm * (pn / rn);
+        R.target = R.prec == TRAP_FP64 ? goal : std::max(R.opts.inner_tol * pn, goal);
+        return start_cycle(ctx, R, K.tmp64, pn);
+      }
       R.target = R.prec == TRAP_FP64 ? 0.999 * R.opts.tol * R.bnorm
                                      : std::max(R.opts.inner_tol * rn, 0.5 * R.opts.tol * R.bnorm);
       return start_cycle(ctx, R, K.r, rn);

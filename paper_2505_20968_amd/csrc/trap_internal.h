@@ -106,6 +106,18 @@ struct Problem {
   double2 *d_E = nullptr, *d_A = nullptr;  // see above
   double2 *d_alpha = nullptr, *d_bma = nullptr; // [nz][nu][nu]
   double *d_g = nullptr;                   // [nz][nt][nd][4] geometric factors of K
+  // physics-based preconditioner (unmagnetised, unpolarised, angle-averaged,
+  // K = Q = 0): transitions of the zero-field atom grouped by frequency
+  // (pc_nk classes, energy differences pc_dE in Hz); per height the weights
+  // of the class kernels in the comoving coupling (R_II: real and imaginary
+  // planes, pc_cr / pc_ci [nz][nk]; R_III: four complex [nk][nk] blocks
+  // pc_X [nz][4][nk][nk]); directions grouped by Doppler shift per height
+  // (pc_dcls [nz][nd] class of each direction, pc_cub [nz][nd] class shifts
+  // in u units, pc_ncls [nz] class count)
+  int pc_nk = 0;
+  std::vector<double> pc_dE, pc_cr, pc_ci, pc_cub;
+  std::vector<double2> pc_X;
+  std::vector<int> pc_dcls, pc_ncls;
 };
 
 struct Precomp {
@@ -127,6 +139,21 @@ struct Precomp {
   double *d_Lrow = nullptr;   // local part of the kernel rows, [rows][ldm] (height chunk)
   double *d_Grow = nullptr;   // second-derivative weights of the kernel rows, [rows][ldm]
   int zc_rows = 0;            // heights per precompute chunk
+  // preconditioner tables (FP64), present once pc_done
+  bool pc_done = false;
+  double *d_pcPhi = nullptr;  // [z][n][m] comoving coupling Phi_z
+  double *d_pcC = nullptr;    // [z][n][m] Phi_z (Id - A_z)^-1
+  double *d_pcL = nullptr;    // [z][o][n] local Lambda (diagonal of the scalar formal solution)
+  double *d_pcA = nullptr;    // [z][m'][m] A_z, then the Gauss-Jordan scratch [z][nn][2 nn]
+  double *d_pcM = nullptr;    // [z][k][c][n][ldm] angle-averaged kernels of the zero-field classes
+  double2 *d_pcR3 = nullptr;  // [z][k][n] R_III weights of the classes
+  double2 *d_pcProf = nullptr;// [z][k][n] profiles of the classes on the comoving grid
+  double *d_pcSt = nullptr;   // [z][k] class shifts (u units)
+  double *d_pcCr = nullptr, *d_pcCi = nullptr;
+  double2 *d_pcX = nullptr;
+  int *d_pcDcls = nullptr, *d_pcNcls = nullptr;
+  double *d_pcCub = nullptr;
+  double *d_pcTheta = nullptr, *d_pcRw = nullptr;   // Gauss-Legendre angles and weights of the average
 };
 
 struct Work {
@@ -145,6 +172,9 @@ struct Work {
   double *r = nullptr, *x = nullptr, *tmp64 = nullptr, *red = nullptr;
   double *dots = nullptr;     // reduction scratch for the block dot-products
   int V_cols = 0;
+  // preconditioner sweeps: Stokes-I fields [z][o][n] and per-height vectors
+  double *pc_x = nullptr, *pc_e = nullptr, *pc_res = nullptr;
+  double *pc_h = nullptr;     // [z][2][nn]: comoving vector and its spline second derivatives
 };
 
 struct ProfRec {
@@ -220,6 +250,27 @@ struct UploadBatch {
   }
   int commit(trap_ctx* ctx);
 };
+
+// Gauss-Legendre nodes and weights on [0, 1] (host_setup.cpp)
+void gauss_legendre_unit(int n, std::vector<double>& t, std::vector<double>& w);
+
+// Value at xs of the not-a-knot spline through v on the nodes x (second
+// derivatives sd from the spline's second-derivative map), extended flat
+// beyond the end nodes.
+__device__ inline double spline_at(const double* __restrict__ x, int nn, const double* v, const double* sd,
+                                   double xs) {
+  if (xs <= x[0]) return v[0];
+  if (xs >= x[nn - 1]) return v[nn - 1];
+  int lo = 0, hi = nn - 1;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (x[mid] <= xs) lo = mid; else hi = mid;
+  }
+  const double h = x[lo + 1] - x[lo];
+  const double t = (xs - x[lo]) / h, u = 1.0 - t;
+  const double cs = h * h / 6.0;
+  return u * v[lo] + t * v[lo + 1] + cs * (u * u * u - u) * sd[lo] + cs * (t * t * t - t) * sd[lo + 1];
+}
 
 // host setup (host_setup.cpp)
 int build_problem(trap_ctx* ctx, const trap_atom_desc* atom, const trap_problem_desc* pd);
@@ -343,6 +394,18 @@ int sigma_batch_ready(trap_ctx* ctx);
 // the device's batch stream, ordered after and before each context's stream
 int op_apply_batch_f32(trap_ctx** ctxs, int n, const double* const* x, double* const* y);
 int launch_formal_grouped(hipStream_t s, const GFormal* args, const int* off, int n, int blocks);
+
+// physics-based preconditioner (Sect. 5.3, App. F): tables after the kernel
+// precompute (precompute.hip); out = M r for FP64 vectors, `sweeps`
+// block-Jacobi steps, the scalar formal solution in precision prec
+// (precond.hip; out may equal r)
+int run_precompute_precond(trap_ctx* ctx);
+int precond_apply(trap_ctx* ctx, const double* r, double* out, int sweeps, int prec);
+// local Lambda of the scalar formal solution, and the sweep of Lambda* with
+// the fused residual res = y - x + Lambda* e (formal.hip)
+int launch_pc_local_lambda(trap_ctx* ctx);
+int launch_formal_scalar(trap_ctx* ctx, int prec, const double* e, const double* y, int y_stride,
+                         const double* x, double* res);
 
 struct DeviceGuard {
   int prev = -1;

@@ -27,7 +27,8 @@ EXPORTED = ["trap_create", "trap_destroy", "trap_set_problem", "trap_precompute"
             "trap_apply_sigma", "trap_formal_solve", "trap_apply_operator", "trap_rhs",
             "trap_gmres_solve", "trap_emergent", "trap_get_info", "trap_footprint",
             "trap_profile", "trap_stage_times", "trap_set_path", "trap_set_prd_mode", "trap_gmres_begin",
-            "trap_gmres_step_batch", "trap_gmres_end", "trap_last_error"]
+            "trap_gmres_step_batch", "trap_gmres_end", "trap_precompute_preconditioner",
+            "trap_apply_preconditioner", "trap_preconditioner_tables", "trap_last_error"]
 STAGES = ["comoving", "contract_fp32", "r3", "angular", "backinterp", "formal", "kernel_rows",
           "contract_fp64"]
 
@@ -60,13 +61,14 @@ class Info(ctypes.Structure):
 class SolveOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("restart", ctypes.c_int), ("max_iters", ctypes.c_int),
                 ("max_outer", ctypes.c_int), ("inner", ctypes.c_int), ("inner_tol", ctypes.c_double),
-                ("zero_guess", ctypes.c_int)]
+                ("zero_guess", ctypes.c_int), ("precond_sweeps", ctypes.c_int)]
 
 
 class SolveStats(ctypes.Structure):
     _fields_ = [("outer_steps", ctypes.c_int), ("inner_iters", ctypes.c_int),
                 ("applies_fp64", ctypes.c_int), ("applies_fp32", ctypes.c_int),
-                ("applies_grouped", ctypes.c_int), ("final_rel_res", ctypes.c_double), ("ms_total", ctypes.c_double)]
+                ("applies_grouped", ctypes.c_int), ("applies_precond", ctypes.c_int),
+                ("final_rel_res", ctypes.c_double), ("ms_total", ctypes.c_double)]
 
 
 class StageStats(ctypes.Structure):
@@ -107,6 +109,9 @@ def load_library(path: str = LIB_PATH):
     lib.trap_gmres_step_batch.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
     lib.trap_gmres_end.argtypes = [vp, ctypes.POINTER(SolveStats)]
     lib.trap_stage_times.argtypes = [vp, ctypes.POINTER(StageStats)]
+    lib.trap_precompute_preconditioner.argtypes = [vp]
+    lib.trap_apply_preconditioner.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.c_int]
+    lib.trap_preconditioner_tables.argtypes = [vp, _dp, _dp, _dp]
     lib.trap_last_error.restype = ctypes.c_char_p
     for name in EXPORTED:
         if name != "trap_last_error":
@@ -216,6 +221,22 @@ class Context:
     def precompute(self, store_mask: int = 3):
         _check(self.lib.trap_precompute(self.h, store_mask))
 
+    def precompute_preconditioner(self):
+        _check(self.lib.trap_precompute_preconditioner(self.h))
+
+    def apply_preconditioner(self, r, out, sweeps: int, prec: int = TRAP_FP64):
+        _check(self.lib.trap_apply_preconditioner(self.h, self._vec(r, TRAP_FP64), self._vec(out, TRAP_FP64),
+                                                  int(sweeps), int(prec)))
+
+    def preconditioner_tables(self) -> dict:
+        nz, nd, nn = self.shape[0], self.shape[1], self.shape[2]
+        phi = np.zeros((nz, nn, nn))
+        c = np.zeros((nz, nn, nn))
+        lloc = np.zeros((nz, nd, nn))
+        _check(self.lib.trap_preconditioner_tables(self.h, phi.ctypes.data_as(_dp), c.ctypes.data_as(_dp),
+                                                   lloc.ctypes.data_as(_dp)))
+        return {"Phi": phi, "C": c, "L": lloc}
+
     def apply_sigma(self, I, eps, add_thermal: bool = False):
         p = _prec_of(I)
         _check(self.lib.trap_apply_sigma(self.h, self._vec(I, p), self._vec(eps, p), p, int(add_thermal)))
@@ -233,23 +254,24 @@ class Context:
 
     def gmres_solve(self, I, tol: float = 1e-8, restart: int = 40, max_iters: int = 2000,
                     inner: int = TRAP_FP64, max_outer: int = 8, inner_tol: float = 1e-7,
-                    raise_on_noconv: bool = True, zero_guess: bool = False):
+                    raise_on_noconv: bool = True, zero_guess: bool = False, precond_sweeps: int = 0):
         o = SolveOpts(tol=tol, restart=restart, max_iters=max_iters, max_outer=max_outer, inner=inner,
-                      inner_tol=inner_tol, zero_guess=int(zero_guess))
+                      inner_tol=inner_tol, zero_guess=int(zero_guess), precond_sweeps=int(precond_sweeps))
         st = SolveStats()
         code = self.lib.trap_gmres_solve(self.h, ctypes.byref(o), self._vec(I, TRAP_FP64), ctypes.byref(st))
         if code != 0 and (raise_on_noconv or code != -4):
             _check(code)
         return {"outer_steps": st.outer_steps, "inner_iters": st.inner_iters,
                 "applies_fp64": st.applies_fp64, "applies_fp32": st.applies_fp32, "applies_grouped": st.applies_grouped,
+                "applies_precond": st.applies_precond,
                 "final_rel_res": st.final_rel_res, "ms_total": st.ms_total, "status": code}
 
     def gmres_begin(self, I, tol: float = 1e-8, restart: int = 40, max_iters: int = 2000,
                     inner: int = TRAP_FP64, max_outer: int = 8, inner_tol: float = 1e-7,
-                    zero_guess: bool = False):
+                    zero_guess: bool = False, precond_sweeps: int = 0):
         """Start a solve that trap_gmres_step_batch advances (see gmres_step_batch)."""
         o = SolveOpts(tol=tol, restart=restart, max_iters=max_iters, max_outer=max_outer, inner=inner,
-                      inner_tol=inner_tol, zero_guess=int(zero_guess))
+                      inner_tol=inner_tol, zero_guess=int(zero_guess), precond_sweeps=int(precond_sweeps))
         self._solution = I           # the library writes into I until the solve ends
         _check(self.lib.trap_gmres_begin(self.h, ctypes.byref(o), self._vec(I, TRAP_FP64)))
 
@@ -261,6 +283,7 @@ class Context:
         self._solution = None
         return {"outer_steps": st.outer_steps, "inner_iters": st.inner_iters,
                 "applies_fp64": st.applies_fp64, "applies_fp32": st.applies_fp32, "applies_grouped": st.applies_grouped,
+                "applies_precond": st.applies_precond,
                 "final_rel_res": st.final_rel_res, "ms_total": st.ms_total, "status": code}
 
     def emergent(self, I) -> np.ndarray:
