@@ -5,9 +5,11 @@ widths, 4+4 Gauss-Legendre mu x 8 azimuths, seeded atmosphere, tolerance 1e-8).
 
 One step = one whole pass of the method on a fresh seeded atmosphere:
 per-height setup, device precompute (R_II kernels by product integration,
-R_III weights, propagation matrix, normalisation, right-hand side) and the
-GMRES solve to tolerance (mixed precision: FP32 inner operator, FP64 Arnoldi,
-residual and iterative refinement; or plain FP64 with --precision fp64).
+R_III weights, propagation matrix, normalisation, right-hand side), the
+tables of the physics-based preconditioner (Sect. 5.3, App. F) and the
+left-preconditioned GMRES solve to tolerance (mixed precision: FP32 inner
+operator, FP64 Arnoldi, residual and iterative refinement; or plain FP64 with
+--precision fp64; --precond-sweeps 0 solves without the preconditioner).
 
 Prints one JSON line.  `value` is solves/s; `roofline` covers the dominant
 kernel (the FP32 R_II contraction), timed with HIP events on the library's
@@ -99,7 +101,8 @@ def cpu_baseline(n_applies: float, seed: int, budget_heights: int = 1):
             "sample": (f"oracle on seed {seed}: setup, R_II/R_III kernels and one Sigma apply "
                        f"at {k} of {prob.n_z} heights (scaled by N_z; Sigma is height-local), "
                        f"one full Lambda; scaled to {n_applies:.1f} operator applies per solve "
-                       f"as measured on the GPU; single BLAS thread"),
+                       f"(the oracle's unpreconditioned GMRES; apply count of an unpreconditioned "
+                       f"GPU solve of the same atmosphere); single BLAS thread"),
             "seconds_measured": t_setup + t_first + t_second + t_formal,
             "seconds_per_solve_est": t_solve}
 
@@ -107,7 +110,7 @@ def cpu_baseline(n_applies: float, seed: int, budget_heights: int = 1):
 SERVE_STREAM = dict(n_z_range=(40, 70), nu_choices=(51, 71, 101), angle_sets=[(8, 4), (8, 8)])
 
 
-def serving_bench(n_requests: int, seed: int):
+def serving_bench(n_requests: int, seed: int, precond_sweeps: int):
     """Continuous-batching serving of a bounded request stream (all four atom/grid
     generators, N_z 40-70, N_nu 51-101, N_dir 32-64): saturated runs (all
     requests at t = 0) in mixed precision and in plain FP64; the mixed one fixes
@@ -116,7 +119,8 @@ def serving_bench(n_requests: int, seed: int):
     from workloads import serving_stream
     from paper_2505_20968_amd.serving import Request, serve
     base = serving_stream(n_requests, seed=seed, rate_hz=1.0, **SERVE_STREAM)
-    solver = dict(tol=1e-8, restart=40, inner_tol=1e-7, max_outer=10, max_iters=2000)
+    solver = dict(tol=1e-8, restart=40, inner_tol=1e-7, max_outer=10, max_iters=2000,
+                  precond_sweeps=precond_sweeps)
 
     def summary(res):
         return {"solves_per_s": res["solves_per_s"], "p50_ms": 1e3 * res["p50_s"], "p99_ms": 1e3 * res["p99_s"],
@@ -133,7 +137,7 @@ def serving_bench(n_requests: int, seed: int):
     return {"requests": n_requests, "stream": "seeded mix of the four generators, N_z 40-70, N_nu 51-101, "
                                               "N_dir 32-64, tol 1e-8",
             "saturated_solves_per_s": {"mixed": sat["solves_per_s"], "fp64": sat64["solves_per_s"]},
-            "arrival_rate_hz": lam,
+            "arrival_rate_hz": lam, "precond_sweeps": precond_sweeps,
             "mixed": runs["mixed"], "fp64": runs["fp64"],
             "mixed_over_fp64_throughput": runs["mixed"]["solves_per_s"] / max(runs["fp64"]["solves_per_s"], 1e-30)}
 
@@ -146,6 +150,8 @@ def main():
     ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--restart", type=int, default=40)
+    ap.add_argument("--precond-sweeps", type=int, default=2,
+                    help="block-Jacobi steps of the physics-based preconditioner (0: none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=16,
                     help="requests in the serving measurement (0 skips it)")
@@ -170,9 +176,11 @@ def main():
     mixed = args.precision == "mixed"
     ctx = Context(0)
 
-    phases = {"set_problem": [], "precompute": [], "solve": []}
+    phases = {"set_problem": [], "precompute": [], "precond_tables": [], "solve": []}
+    sweeps = args.precond_sweeps
 
-    def one_step(seed):
+    def one_step(seed, sw=None, record=True):
+        sw = sweeps if sw is None else sw
         prob = cfg2(seed)
         t0 = time.perf_counter()
         ctx.set_problem(prob)
@@ -180,14 +188,21 @@ def main():
         ctx.precompute(3 if mixed else 1)
         torch.cuda.synchronize()         # precompute is asynchronous: attribute its time here
         t2 = time.perf_counter()
+        if sw:
+            ctx.precompute_preconditioner()
+            torch.cuda.synchronize()
+        t3 = time.perf_counter()
         x = torch.zeros(ctx.shape, dtype=torch.float64, device="cuda")
         st = ctx.gmres_solve(x, tol=args.tol, restart=args.restart, max_iters=2000,
                              inner=TRAP_FP32 if mixed else TRAP_FP64, max_outer=10, inner_tol=1e-7,
-                             zero_guess=True)
-        t3 = time.perf_counter()
+                             zero_guess=True, precond_sweeps=sw)
+        t4 = time.perf_counter()
+        if not record:
+            return st
         phases["set_problem"].append(t1 - t0)
         phases["precompute"].append(t2 - t1)
-        phases["solve"].append(t3 - t2)
+        phases["precond_tables"].append(t3 - t2)
+        phases["solve"].append(t4 - t3)
         return st
 
     if args.copy_probe:
@@ -216,6 +231,10 @@ def main():
     stage = ctx.stage_times()
     ctx.profile(False)
     info = ctx.info()
+    # the oracle solves without a preconditioner: its CPU estimate is scaled
+    # to the applies of an unpreconditioned solve of the same atmosphere
+    # (outside the timed region)
+    plain = one_step(2, sw=0, record=False) if sweeps else stats[0]
     ctx.close()
 
     key = "fp32" if mixed else "fp64"
@@ -225,6 +244,7 @@ def main():
     ms_c = cstage["ms"]
     achieved = flops / (ms_c * 1e-3) / 1e12 if ms_c > 0 else 0.0
     n_applies = sum(s["applies_fp32"] + s["applies_fp64"] for s in stats) / len(stats)
+    plain_applies = plain["applies_fp32"] + plain["applies_fp64"]
     apply_ms = {k: v["ms"] / max(v["launches"], 1) for k, v in stage.items() if isinstance(v, dict) and "ms" in v}
     out = {
         "metric": METRIC,
@@ -244,12 +264,16 @@ def main():
                    "precision": ("FP32 inner operator, FP64 Arnoldi/residual/refinement" if mixed
                                  else "FP64 throughout"),
                    "n_unknowns": info["n_unknowns"], "n_theta": info["n_theta"],
-                   "n_slots": info["n_slots"], "restart": args.restart},
+                   "n_slots": info["n_slots"], "restart": args.restart,
+                   "preconditioner": (f"physics-based P = Id - Lambda* Sigma* (unmagnetised, unpolarised, "
+                                      f"angle-averaged), {sweeps} block-Jacobi steps with the App. F "
+                                      f"local inverse" if sweeps else "none")},
         "latency_ms": {"p50": 1e3 * _pct(lat, 0.5), "p99": 1e3 * _pct(lat, 0.99)},
         "phase_ms": {k: 1e3 * sum(v) / len(v) for k, v in phases.items()},
         "solver": {"inner_iters_mean": sum(s["inner_iters"] for s in stats) / len(stats),
                    "outer_steps_mean": sum(s["outer_steps"] for s in stats) / len(stats),
                    "applies_mean": n_applies,
+                   "precond_applies_mean": sum(s["applies_precond"] for s in stats) / len(stats),
                    "max_final_rel_res": max(s["final_rel_res"] for s in stats)},
         "emissivity_apply": {"contraction_tflops": achieved,
                              "contraction_ms_per_launch": ms_c / max(cstage["launches"], 1),
@@ -263,9 +287,9 @@ def main():
                                 if mixed else "k_contract<double, NH>")},
     }
     if args.serve_requests > 0:
-        out["serving"] = serving_bench(args.serve_requests, seed=5)
+        out["serving"] = serving_bench(args.serve_requests, seed=5, precond_sweeps=sweeps)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(n_applies, seed=2)
+        out["cpu_baseline"] = cpu_baseline(plain_applies, seed=2)
     print(json.dumps(out))
 
 

@@ -181,8 +181,8 @@ int trap_precompute(trap_ctx* ctx, int store_mask);
  * C_z = Phi_z (Id - A_z)^-1 with A_z of App. F (FP64, Gauss-Jordan with
  * partial pivoting; a singular Id - A_z gives non-finite tables, which a
  * solve reports as TRAP_ENAN).  Asynchronous; once per problem (later calls
- * return at once).  Device memory: about 5 n_z N_nu^2 + n_z n_dir N_nu doubles
- * plus the kernel scratch, not counted by trap_footprint.
+ * return at once).  Device memory: about 5 n_z N_nu^2 + 4 n_z n_dir N_nu
+ * doubles plus the kernel scratch (trap_footprint with store_mask bit 2).
  * trap_apply_preconditioner: out = M r for FP64 device vectors
  * [z][Omega][n][4] (out may equal r): x_1 = P^^-1 r_I,
  * x_{k+1} = x_k + P^^-1 (r_I - P x_k), `sweeps` in [1, 64] steps, then
@@ -257,7 +257,8 @@ int trap_get_info(const trap_ctx* ctx, trap_info* info);
 /* Device bytes a context needs for this problem with the given kernel store
  * mask (for admission control): every allocation of trap_set_problem,
  * trap_precompute (including its scratch) and a solve with restart <= 40,
- * in the angle-dependent layout.  Host arithmetic only; does not touch the
+ * in the angle-dependent layout; with store_mask bit 2 also those of
+ * trap_precompute_preconditioner and of preconditioned solves.  Host arithmetic only; does not touch the
  * device. */
 int trap_footprint(const trap_atom_desc* atom, const trap_problem_desc* prob, int store_mask,
                    size_t* bytes);

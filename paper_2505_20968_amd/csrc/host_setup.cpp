@@ -572,6 +572,9 @@ PrecompLayout precomp_layout(int nz, int nn, int ldm, int nt, int nthr, bool aa,
   return L;
 }
 
+static int zero_field_classes(const trap_atom_desc& at, double dnuD_ref, std::vector<double>* dE,
+                              std::vector<int>* cls);
+
 size_t estimate_bytes(const trap_atom_desc* atom, const trap_problem_desc* pd, int store_mask, int* err) {
   *err = 0;
   if (!atom || !pd || pd->n_z < 2 || pd->n_nu < 4 || pd->n_mu < 2 || pd->n_mu % 2 || pd->n_chi < 1 ||
@@ -687,6 +690,51 @@ size_t estimate_bytes(const trap_atom_desc* atom, const trap_problem_desc* pd, i
       add((size_t)lay.zc_tab * P.nth_rows * nt * lay.nd2 * 16 * 16);  // Faddeeva factors
     }
   }
+  // the preconditioner (store_mask bit 2): its table upload, tables, kernel
+  // scratch and sweep vectors, as run_precompute_precond and precond_apply
+  // allocate them
+  if (store_mask & 4) {
+    const double mass = atom->mass_amu * kAMU;
+    const double Tref = pd->T_ref > 0 ? pd->T_ref : 6000.0;
+    const double nu0 = kC / (atom->lambda0_A * 1e-8);
+    const double vref = std::sqrt(2.0 * kKB * Tref / mass);
+    std::vector<double> lam(nz);
+    for (size_t z = 0; z < nz; ++z) {
+      const double xi = pd->xi ? pd->xi[z] * 1e5 : 0.0;
+      lam[z] = vref / std::sqrt(2.0 * kKB * pd->T[z] / mass + xi * xi);
+    }
+    const size_t nk = (size_t)zero_field_classes(*atom, nu0 * vref / kC, nullptr, nullptr);
+    const size_t ng = 25;
+    UploadBatch up;
+    auto item = [&up](size_t bytes) { up.add(nullptr, nullptr, bytes); };
+    item(nz * nk * 8);                                   // class shifts
+    item(nz * nk * 8);                                   // R_II weights (real plane)
+    item(nz * nk * 8);                                   //   (imaginary plane)
+    item(nz * 4 * nk * nk * 16);                         // R_III weights
+    item(nz * nd * 4);                                   // direction classes
+    item(nz * 4);                                        // class counts
+    item(nz * nd * 8);                                   // class shifts
+    item(ng * 8);                                        // angles
+    item(ng * 8);                                        // weights
+    add(up.total);
+    add(nz * nn * nn * 8);                               // Phi
+    add(nz * nn * nn * 8);                               // C
+    add(nz * nd * nn * 8);                               // local Lambda
+    add(nz * nn * nn * 3 * 8);                           // A and the elimination scratch
+    add(nz * nk * 2 * nn * ldm * 8);                     // class kernels
+    add(nz * nk * nn * 16);                              // R_III rows
+    add(nz * nk * nn * 16);                              // profiles
+    const PrecompLayout lay = precomp_layout((int)nz, (int)nn, (int)ldm, (int)nk, (int)ng, true, pd->x, lam.data());
+    const size_t rows_per_z = ng * nk * 2 * nn;
+    const size_t zc = std::max<size_t>(1, std::min<size_t>(nz, (size_t(32) << 20) / (rows_per_z * ldm * 8)));
+    if (lay.uniform) {
+      add(zc * ng * lay.nd2 * 16 * 8);
+      add(zc * ng * nk * lay.nd2 * 16 * 16);
+    }
+    for (int k = 0; k < 3; ++k) add(zc * rows_per_z * ldm * 8);
+    for (int k = 0; k < 3; ++k) add(nz * nd * nn * 8);  // sweep vectors
+    add(nz * 2 * nn * 8);
+  }
   // the height-chunked Sigma path materialises W for one chunk of heights
   // (at most ~512 MiB in FP64, half that in FP32)
   {
@@ -696,6 +744,27 @@ size_t estimate_bytes(const trap_atom_desc* atom, const trap_problem_desc* pd, i
     if (mask & 2) add(zc * per_z * 4);
   }
   return b;
+}
+
+// Transitions of the zero-field atom grouped by frequency: class energy
+// differences (Hz) and the class of each transition (u, l) at u nl + l; the
+// class count is returned.
+static int zero_field_classes(const trap_atom_desc& at, double dnuD_ref, std::vector<double>* dE,
+                              std::vector<int>* cls) {
+  const Sublevels s0 = sublevels(at, 0.0, 0.0, 0.0, dnuD_ref);
+  const int nu = static_cast<int>(s0.Eu.size()), nl = static_cast<int>(s0.El.size());
+  std::vector<double> e_k;
+  if (cls) cls->assign((size_t)nu * nl, 0);
+  for (int u = 0; u < nu; ++u)
+    for (int l = 0; l < nl; ++l) {
+      const double e = s0.Eu[u] - s0.El[l];
+      int k = 0;
+      while (k < (int)e_k.size() && std::fabs(e_k[k] - e) > 1e-9 * std::max(1.0, std::fabs(e))) ++k;
+      if (k == (int)e_k.size()) e_k.push_back(e);
+      if (cls) (*cls)[(size_t)u * nl + l] = k;
+    }
+  if (dE) *dE = e_k;
+  return static_cast<int>(e_k.size());
 }
 
 // Weights of the preconditioner's comoving coupling (Sect. 5.3, App. F): the
@@ -713,16 +782,7 @@ static void precond_weights(Problem& P, const trap_atom_desc& at, double dnuD_re
   const Sublevels s0 = sublevels(at, 0.0, 0.0, 0.0, dnuD_ref);
   const int nu = static_cast<int>(s0.Eu.size()), nl = static_cast<int>(s0.El.size()), nt = nu * nl;
   std::vector<int> cls(nt);
-  P.pc_dE.clear();
-  for (int u = 0; u < nu; ++u)
-    for (int l = 0; l < nl; ++l) {
-      const double e = s0.Eu[u] - s0.El[l];
-      int k = 0;
-      while (k < (int)P.pc_dE.size() && std::fabs(P.pc_dE[k] - e) > 1e-9 * std::max(1.0, std::fabs(e))) ++k;
-      if (k == (int)P.pc_dE.size()) P.pc_dE.push_back(e);
-      cls[u * nl + l] = k;
-    }
-  const int nk = P.pc_nk = static_cast<int>(P.pc_dE.size());
+  const int nk = P.pc_nk = zero_field_classes(at, dnuD_ref, &P.pc_dE, &cls);
   // incoming factor summed over directions, SA[q][p][l] = sum_x w_x d_ql^T Acart_0(x)/2 d_pl^*,
   // and the outgoing factor of direction 0, E0[p][q][l'] = d_pl'^T Acart_0(0) d_ql'^*
   std::vector<cd> SA((size_t)nu * nu * nl, cd(0, 0)), E0((size_t)nu * nu * nl);

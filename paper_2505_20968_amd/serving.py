@@ -121,22 +121,24 @@ class DeviceBackend:
     """GPU backend: one context and HIP stream per request, batched GMRES steps."""
 
     def __init__(self, device: int = 0, precision: str = "mixed", tol: float = 1e-8, restart: int = 40,
-                 inner_tol: float = 1e-7, max_outer: int = 10, max_iters: int = 2000):
+                 inner_tol: float = 1e-7, max_outer: int = 10, max_iters: int = 2000, precond_sweeps: int = 0):
         import torch
         from .trap import TRAP_FP32, TRAP_FP64, footprint
         self.torch = torch
         self.device = device
         self.mixed = precision == "mixed"
         self.store = 3 if self.mixed else 1
+        self.precond = int(precond_sweeps)
         self.opts = dict(tol=tol, restart=restart, max_iters=max_iters, max_outer=max_outer,
-                         inner=TRAP_FP32 if self.mixed else TRAP_FP64, inner_tol=inner_tol, zero_guess=True)
+                         inner=TRAP_FP32 if self.mixed else TRAP_FP64, inner_tol=inner_tol, zero_guess=True,
+                         precond_sweeps=self.precond)
         self._footprint = footprint
         self.admit_parts = {"context": 0.0, "set_problem": 0.0, "precompute": 0.0, "begin": 0.0}
 
     def footprint(self, problem) -> int:
         # library allocations plus the solution vector held by the caller
         n = 4 * problem.n_z * problem.n_dir * problem.n_nu
-        return self._footprint(problem, self.store) + 8 * n
+        return self._footprint(problem, self.store | (4 if self.precond else 0)) + 8 * n
 
     def admit(self, problem):
         """Set up the request and enqueue its precompute and the start of its
@@ -150,6 +152,8 @@ class DeviceBackend:
         ctx.set_problem(problem)
         t2 = time.perf_counter()
         ctx.precompute(self.store)
+        if self.precond:
+            ctx.precompute_preconditioner()
         t3 = time.perf_counter()
         with torch.cuda.stream(stream):
             x = torch.zeros(ctx.shape, dtype=torch.float64, device=f"cuda:{self.device}")

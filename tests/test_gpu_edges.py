@@ -125,6 +125,33 @@ def test_footprint_bounds_what_a_solve_allocates(store):
         assert used <= est <= 1.5 * used + (1 << 20)
 
 
+@pytest.mark.parametrize("store", [1, 3])
+def test_footprint_with_preconditioner(store):
+    """With store_mask bit 2 the footprint also covers the preconditioner's
+    tables, scratch and sweep vectors: exactly what a context holds after a
+    preconditioned solve when both kernel stores are kept."""
+    torch = _torch()
+    from paper_2505_20968_amd import Context, TRAP_FP32, TRAP_FP64, footprint
+    for prob in (tiny(n_z=6, n_nu=25, x_max=7, n_mu=4, n_chi=5, B=(60.0, 0.8, 2.0), a=2e-2, eps=3e-2, v_z=2.0,
+                      seed=21),
+                 tiny(n_z=4, n_nu=33, x_max=16, n_mu=4, n_chi=4, B=(40.0, 1.0, 0.3), a=1e-2, eps=5e-2,
+                      atom=two_term_atom(2800.0, 24.305, 20.0))):
+        est = footprint(prob, store | 4)
+        ctx = Context(0)
+        ctx.set_problem(prob)
+        ctx.precompute(store)
+        ctx.precompute_preconditioner()
+        x = torch.zeros(ctx.shape, dtype=torch.float64, device="cuda")
+        ctx.gmres_solve(x, tol=1e-9, restart=40, inner=TRAP_FP32 if store == 3 else TRAP_FP64,
+                        inner_tol=1e-4, max_outer=10, precond_sweeps=2, zero_guess=True)
+        used = ctx.info()["bytes_device_total"]
+        ctx.close()
+        print(f"store {store} + preconditioner: footprint {est} B, held {used} B", flush=True)
+        assert used <= est <= 1.5 * used + (1 << 20)
+        if store == 3:
+            assert est == used
+
+
 @pytest.mark.parametrize("inner", ["fp64", "mixed"])
 def test_zero_guess_skips_the_first_apply_and_changes_nothing(inner):
     """Declaring the initial guess zero replaces the first residual's operator
