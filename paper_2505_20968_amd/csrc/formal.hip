@@ -204,7 +204,7 @@ int launch_formal_grouped(hipStream_t s, const GFormal* args, const int* off, in
 // of the step that ends there; zero at the first point of the sweep.
 __global__ void __launch_bounds__(64) k_pc_local_lambda(int nz, int nd, int nn, const double* __restrict__ mu,
                                                         const double* __restrict__ tau, const double* __restrict__ K8,
-                                                        double* __restrict__ L) {
+                                                        double* __restrict__ L, double2* __restrict__ F) {
   const int id = blockIdx.x * blockDim.x + threadIdx.x;
   if (id >= nd * nn) return;
   const int o = id / nn, n = id % nn;
@@ -215,16 +215,20 @@ __global__ void __launch_bounds__(64) k_pc_local_lambda(int nz, int nd, int nn, 
   int z = up ? 0 : nz - 1;
   const int dz = up ? 1 : -1;
   L[(long long)z * zs + id] = 0.0;
+  F[(long long)z * zs + id] = make_double2(0.0, 0.0);
   double ru = K8[((long long)z * zs + id) * 8 + 7];
+  double iu = K8[((long long)z * zs + id) * 8 + 6];
   for (int step = 1; step < nz; ++step) {
     const int zc = z + dz;
     const long long p = (long long)zc * zs + id;
-    const double rc = K8[p * 8 + 7];
+    const double rc = K8[p * 8 + 7], ic = K8[p * 8 + 6];
     const double x = 0.5 * (ru + rc) * fabs(tau[z] - tau[zc]) / amu;
     double pu, pc, ex;
     delo_weights<double>(x, pu, pc, ex);
-    L[p] = pc * K8[p * 8 + 6];
+    L[p] = pc * ic;
+    F[p] = make_double2(ex, pu * iu);
     ru = rc;
+    iu = ic;
     z = zc;
   }
 }
@@ -232,60 +236,66 @@ __global__ void __launch_bounds__(64) k_pc_local_lambda(int nz, int nd, int nn, 
 int launch_pc_local_lambda(trap_ctx* ctx) {
   Problem& P = ctx->pb;
   hipLaunchKernelGGL(k_pc_local_lambda, dim3(ceil_div((long long)P.nd * P.nn, 64)), dim3(64), 0, ctx->stream, P.nz,
-                     P.nd, P.nn, P.d_mu, P.d_tau, ctx->pre.d_K, ctx->pre.d_pcL);
+                     P.nd, P.nn, P.d_mu, P.d_tau, ctx->pre.d_K, ctx->pre.d_pcL, ctx->pre.d_pcF);
   TRAP_HIP(hipGetLastError());
   return TRAP_OK;
 }
 
 // Lambda* e for the Stokes-I emissivity e[z][o][n] (scalar DELO-linear steps,
-// K' = 0, no incoming radiation) in precision T, with the block-Jacobi
-// residual fused: res = y - x + Lambda* e (y read with stride y_stride).
-template <typename T>
-__global__ void __launch_bounds__(64) k_formal_scalar(int nz, int nd, int nn, const double* __restrict__ mu,
-                                                      const double* __restrict__ tau, const double* __restrict__ K8,
-                                                      const double* __restrict__ e, const double* __restrict__ y,
-                                                      int y_stride, const double* __restrict__ x,
-                                                      double* __restrict__ res) {
+// K' = 0, no incoming radiation) with the block-Jacobi residual fused:
+// res = y - x + Lambda* e (y read with stride y_stride).  The step
+// coefficients depend on the atmosphere only and are tabulated with the local
+// Lambda: I_c = ex I_u + (psi_u/eta_u) e_u + (psi_c/eta_c) e_c, F = (ex,
+// psi_u/eta_u), L = psi_c/eta_c.  Nothing but I itself depends on the
+// previous step, so the loads of kSweepAhead steps are issued together.
+constexpr int kSweepAhead = 4;
+
+__global__ void __launch_bounds__(64) k_pc_lambda_sweep(int nz, int nd, int nn, const double* __restrict__ mu,
+                                                        const double2* __restrict__ F, const double* __restrict__ L,
+                                                        const double* __restrict__ e, const double* __restrict__ y,
+                                                        int y_stride, const double* __restrict__ x,
+                                                        double* __restrict__ res) {
   const int id = blockIdx.x * blockDim.x + threadIdx.x;
   if (id >= nd * nn) return;
   const int o = id / nn;
-  const double m = mu[o];
-  const bool up = m > 0.0;
-  const T amu = T(fabs(m));
+  const bool up = mu[o] > 0.0;
   const long long zs = (long long)nd * nn;
-  int z = up ? 0 : nz - 1;
+  const int z0 = up ? 0 : nz - 1;
   const int dz = up ? 1 : -1;
-  long long p = (long long)z * zs + id;
-  T I = T(0);
-  T Su = T(e[p]) * T(K8[p * 8 + 6]);
-  T ru = T(K8[p * 8 + 7]);
+  long long p = (long long)z0 * zs + id;
+  double I = 0.0;
+  double eu = e[p];
   res[p] = y[p * y_stride] - x[p];
-  for (int step = 1; step < nz; ++step) {
-    const int zc = z + dz;
-    p = (long long)zc * zs + id;
-    const T rc = T(K8[p * 8 + 7]);
-    const T Sc = T(e[p]) * T(K8[p * 8 + 6]);
-    const T xx = T(0.5) * (ru + rc) * T(fabs(tau[z] - tau[zc])) / amu;
-    T pu, pc, ex;
-    delo_weights<T>(xx, pu, pc, ex);
-    I = ex * I + pu * Su + pc * Sc;
-    res[p] = y[p * y_stride] - x[p] + (double)I;
-    Su = Sc;
-    ru = rc;
-    z = zc;
+  for (int s0 = 1; s0 < nz; s0 += kSweepAhead) {
+    double2 f[kSweepAhead];
+    double lc[kSweepAhead], ec[kSweepAhead], yr[kSweepAhead];
+    long long pp[kSweepAhead];
+#pragma unroll
+    for (int j = 0; j < kSweepAhead; ++j) {
+      const int st = min(s0 + j, nz - 1);
+      pp[j] = (long long)(z0 + dz * st) * zs + id;
+      f[j] = F[pp[j]];
+      lc[j] = L[pp[j]];
+      ec[j] = e[pp[j]];
+      yr[j] = y[pp[j] * y_stride] - x[pp[j]];
+    }
+#pragma unroll
+    for (int j = 0; j < kSweepAhead; ++j) {
+      if (s0 + j < nz) {
+        I = f[j].x * I + f[j].y * eu + lc[j] * ec[j];
+        res[pp[j]] = yr[j] + I;
+        eu = ec[j];
+      }
+    }
   }
 }
 
 int launch_formal_scalar(trap_ctx* ctx, int prec, const double* e, const double* y, int y_stride, const double* x,
                          double* res) {
+  (void)prec;      // the tabulated step coefficients are FP64
   Problem& P = ctx->pb;
-  const dim3 grid(ceil_div((long long)P.nd * P.nn, 64));
-  if (prec == TRAP_FP64)
-    hipLaunchKernelGGL(k_formal_scalar<double>, grid, dim3(64), 0, ctx->stream, P.nz, P.nd, P.nn, P.d_mu, P.d_tau,
-                       ctx->pre.d_K, e, y, y_stride, x, res);
-  else
-    hipLaunchKernelGGL(k_formal_scalar<float>, grid, dim3(64), 0, ctx->stream, P.nz, P.nd, P.nn, P.d_mu, P.d_tau,
-                       ctx->pre.d_K, e, y, y_stride, x, res);
+  hipLaunchKernelGGL(k_pc_lambda_sweep, dim3(ceil_div((long long)P.nd * P.nn, 64)), dim3(64), 0, ctx->stream, P.nz,
+                     P.nd, P.nn, P.d_mu, ctx->pre.d_pcF, ctx->pre.d_pcL, e, y, y_stride, x, res);
   TRAP_HIP(hipGetLastError());
   return TRAP_OK;
 }

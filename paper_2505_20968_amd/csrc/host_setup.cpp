@@ -711,7 +711,8 @@ size_t estimate_bytes(const trap_atom_desc* atom, const trap_problem_desc* pd, i
     item(nz * nk * 8);                                   // R_II weights (real plane)
     item(nz * nk * 8);                                   //   (imaginary plane)
     item(nz * 4 * nk * nk * 16);                         // R_III weights
-    item(nz * nd * 4);                                   // direction classes
+    item(nz * nd * 4);                                   // directions by class
+    item(nz * (nd + 1) * 4);                             // class offsets
     item(nz * 4);                                        // class counts
     item(nz * nd * 8);                                   // class shifts
     item(ng * 8);                                        // angles
@@ -720,6 +721,7 @@ size_t estimate_bytes(const trap_atom_desc* atom, const trap_problem_desc* pd, i
     add(nz * nn * nn * 8);                               // Phi
     add(nz * nn * nn * 8);                               // C
     add(nz * nd * nn * 8);                               // local Lambda
+    add(nz * nd * nn * 16);                              // scalar step coefficients
     add(nz * nn * nn * 3 * 8);                           // A and the elimination scratch
     add(nz * nk * 2 * nn * ldm * 8);                     // class kernels
     add(nz * nk * nn * 16);                              // R_III rows
@@ -830,9 +832,11 @@ static void precond_weights(Problem& P, const trap_atom_desc& at, double dnuD_re
     for (int i = 0; i < 4 * nk * nk; ++i) P.pc_X[(size_t)z * 4 * nk * nk + i] = make_double2(X[i].real(), X[i].imag());
   }
   // directions of equal Doppler shift share the interpolation maps
-  P.pc_dcls.assign((size_t)nz * nd, 0);
+  P.pc_mem.assign((size_t)nz * nd, 0);
+  P.pc_moff.assign((size_t)nz * (nd + 1), 0);
   P.pc_cub.assign((size_t)nz * nd, 0.0);
   P.pc_ncls.assign(nz, 0);
+  std::vector<int> dcls(nd);
   for (int z = 0; z < nz; ++z) {
     int nc = 0;
     for (int o = 0; o < nd; ++o) {
@@ -840,9 +844,16 @@ static void precond_weights(Problem& P, const trap_atom_desc& at, double dnuD_re
       int c = 0;
       while (c < nc && P.pc_cub[(size_t)z * nd + c] != v) ++c;
       if (c == nc) P.pc_cub[(size_t)z * nd + nc++] = v;
-      P.pc_dcls[(size_t)z * nd + o] = c;
+      dcls[o] = c;
     }
     P.pc_ncls[z] = nc;
+    int k = 0;
+    for (int c = 0; c < nc; ++c) {
+      P.pc_moff[(size_t)z * (nd + 1) + c] = k;
+      for (int o = 0; o < nd; ++o)
+        if (dcls[o] == c) P.pc_mem[(size_t)z * nd + k++] = o;
+    }
+    for (int c = nc; c <= nd; ++c) P.pc_moff[(size_t)z * (nd + 1) + c] = k;
   }
 }
 

@@ -1003,8 +1003,9 @@ __global__ void __launch_bounds__(128) k_pc_phi(int nk, int nn, int ldm, const d
 // (x_m - u_b/lam) and accumulated.  One block per (z, m).
 __global__ void __launch_bounds__(128) k_pc_A(int nd, int nn, const double* __restrict__ x,
                                               const double* __restrict__ SigT, const double* __restrict__ lam,
-                                              const double* __restrict__ w, const int* __restrict__ dcls,
-                                              const int* __restrict__ ncls, const double* __restrict__ cub,
+                                              const double* __restrict__ w, const int* __restrict__ mem,
+                                              const int* __restrict__ moff, const int* __restrict__ ncls,
+                                              const double* __restrict__ cub,
                                               const double* __restrict__ L, const double* __restrict__ Phi,
                                               double* __restrict__ A) {
   extern __shared__ double sh[];
@@ -1029,10 +1030,13 @@ __global__ void __launch_bounds__(128) k_pc_A(int nd, int nn, const double* __re
   const double Lz = lam[z];
   for (int c = 0; c < ncls[z]; ++c) {
     const double shf = cub[(size_t)z * nd + c] / Lz;
+    const int k0 = moff[(size_t)z * (nd + 1) + c], k1 = moff[(size_t)z * (nd + 1) + c + 1];
     for (int n = threadIdx.x; n < nn; n += blockDim.x) {
       double d = 0.0;
-      for (int o = 0; o < nd; ++o)
-        if (dcls[(size_t)z * nd + o] == c) d += w[o] * L[((size_t)z * nd + o) * nn + n];
+      for (int k = k0; k < k1; ++k) {
+        const int o = mem[(size_t)z * nd + k];
+        d += w[o] * L[((size_t)z * nd + o) * nn + n];
+      }
       g[n] = d * spline_at(x, nn, ph, sp, x[n] + shf);
     }
     __syncthreads();
@@ -1145,7 +1149,8 @@ int run_precompute_precond(trap_ctx* ctx) {
     up.add(&C.d_pcCr, P.pc_cr);
     up.add(&C.d_pcCi, P.pc_ci);
     up.add(&C.d_pcX, P.pc_X);
-    up.add(&C.d_pcDcls, P.pc_dcls);
+    up.add(&C.d_pcMem, P.pc_mem);
+    up.add(&C.d_pcMoff, P.pc_moff);
     up.add(&C.d_pcNcls, P.pc_ncls);
     up.add(&C.d_pcCub, P.pc_cub);
     up.add(&C.d_pcTheta, th);
@@ -1154,6 +1159,7 @@ int run_precompute_precond(trap_ctx* ctx) {
     TRAP_TRY(dalloc_t(ctx, &C.d_pcPhi, (size_t)nz * nn * nn));
     TRAP_TRY(dalloc_t(ctx, &C.d_pcC, (size_t)nz * nn * nn));
     TRAP_TRY(dalloc_t(ctx, &C.d_pcL, (size_t)nz * nd * nn));
+    TRAP_TRY(dalloc_t(ctx, &C.d_pcF, (size_t)nz * nd * nn));
     TRAP_TRY(dalloc_t(ctx, &C.d_pcA, (size_t)nz * nn * nn * 3));
     TRAP_TRY(dalloc_t(ctx, &C.d_pcM, (size_t)nz * nk * 2 * nn * ldm));
     TRAP_TRY(dalloc_t(ctx, &C.d_pcR3, (size_t)nz * nk * nn));
@@ -1197,7 +1203,7 @@ int run_precompute_precond(trap_ctx* ctx) {
   TRAP_HIP(hipGetLastError());
   TRAP_TRY(launch_pc_local_lambda(ctx));
   hipLaunchKernelGGL(k_pc_A, dim3(nz * nn), dim3(128), 5 * nn * sizeof(double), s, nd, nn, P.d_x, P.d_SigT, P.d_lam,
-                     P.d_w, C.d_pcDcls, C.d_pcNcls, C.d_pcCub, C.d_pcL, C.d_pcPhi, C.d_pcA);
+                     P.d_w, C.d_pcMem, C.d_pcMoff, C.d_pcNcls, C.d_pcCub, C.d_pcL, C.d_pcPhi, C.d_pcA);
   TRAP_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_pc_invert, dim3(nz), dim3(kInvThreads), 0, s, nn, C.d_pcA, C.d_pcPhi,
                      C.d_pcA + (size_t)nz * nn * nn, C.d_pcC);

@@ -21,15 +21,36 @@
 
 namespace trap {
 
+// sd = Sig v for one vector of N_nu values in LDS (SigT = Sig^T, so that
+// consecutive threads read consecutive entries); four independent partial
+// sums keep several loads in flight per thread.
+__device__ inline void pc_second_derivs(int nn, const double* __restrict__ SigT, const double* v, double* sd) {
+  for (int i = threadIdx.x; i < nn; i += blockDim.x) {
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int j = 0;
+    for (; j + 4 <= nn; j += 4) {
+      a0 += SigT[(size_t)j * nn + i] * v[j];
+      a1 += SigT[(size_t)(j + 1) * nn + i] * v[j + 1];
+      a2 += SigT[(size_t)(j + 2) * nn + i] * v[j + 2];
+      a3 += SigT[(size_t)(j + 3) * nn + i] * v[j + 3];
+    }
+    for (; j < nn; ++j) a0 += SigT[(size_t)j * nn + i] * v[j];
+    sd[i] = (a0 + a1) + (a2 + a3);
+  }
+}
+
 // hz = Mat_z sum_c Ups_c (sum_{o in c} w_o src_o) for every height z, where
-// class c holds the directions of one Doppler shift; hz and its spline second
-// derivatives go to h[z][0][.] and h[z][1][.].  One block per height.
+// class c holds the directions of one Doppler shift (members mem[moff[c] ..
+// moff[c + 1]) of the height); hz and its spline second derivatives go to
+// h[z][0][.] and h[z][1][.].  One block per height; the matrix-vector product
+// takes one wave per row.
 __global__ void __launch_bounds__(256) k_pc_gather(int nd, int nn, const double* __restrict__ x,
                                                    const double* __restrict__ SigT, const double* __restrict__ lam,
-                                                   const double* __restrict__ w, const int* __restrict__ dcls,
-                                                   const int* __restrict__ ncls, const double* __restrict__ cub,
-                                                   const double* __restrict__ src, int stride,
-                                                   const double* __restrict__ Mat, double* __restrict__ h) {
+                                                   const double* __restrict__ w, const int* __restrict__ mem,
+                                                   const int* __restrict__ moff, const int* __restrict__ ncls,
+                                                   const double* __restrict__ cub, const double* __restrict__ src,
+                                                   int stride, const double* __restrict__ Mat,
+                                                   double* __restrict__ h) {
   extern __shared__ double sh[];
   double* v = sh;
   double* sd = sh + nn;
@@ -38,38 +59,40 @@ __global__ void __launch_bounds__(256) k_pc_gather(int nd, int nn, const double*
   const int z = blockIdx.x;
   for (int m = threadIdx.x; m < nn; m += blockDim.x) G[m] = 0.0;
   const double Lz = lam[z];
+  const int* mz = mem + (size_t)z * nd;
+  const int* oz = moff + (size_t)z * (nd + 1);
   for (int c = 0; c < ncls[z]; ++c) {
     const double shf = cub[(size_t)z * nd + c] / Lz;
+    const int k0 = oz[c], k1 = oz[c + 1];
     for (int n = threadIdx.x; n < nn; n += blockDim.x) {
-      double a = 0.0;
-      for (int o = 0; o < nd; ++o)
-        if (dcls[(size_t)z * nd + o] == c) a += w[o] * src[(((size_t)z * nd + o) * nn + n) * stride];
-      v[n] = a;
+      double a0 = 0.0, a1 = 0.0;
+      int k = k0;
+      for (; k + 2 <= k1; k += 2) {
+        const int o0 = mz[k], o1 = mz[k + 1];
+        a0 += w[o0] * src[(((size_t)z * nd + o0) * nn + n) * stride];
+        a1 += w[o1] * src[(((size_t)z * nd + o1) * nn + n) * stride];
+      }
+      if (k < k1) a0 += w[mz[k]] * src[(((size_t)z * nd + mz[k]) * nn + n) * stride];
+      v[n] = a0 + a1;
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < nn; i += blockDim.x) {
-      double a = 0.0;
-      for (int j = 0; j < nn; ++j) a += SigT[(size_t)j * nn + i] * v[j];
-      sd[i] = a;
-    }
+    pc_second_derivs(nn, SigT, v, sd);
     __syncthreads();
     for (int m = threadIdx.x; m < nn; m += blockDim.x) G[m] += spline_at(x, nn, v, sd, x[m] - shf);
     __syncthreads();
   }
   const double* Mz = Mat + (size_t)z * nn * nn;
-  for (int n = threadIdx.x; n < nn; n += blockDim.x) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int n = wave; n < nn; n += nw) {
     double a = 0.0;
-    for (int m = 0; m < nn; ++m) a += Mz[(size_t)n * nn + m] * G[m];
-    hv[n] = a;
+    for (int m = lane; m < nn; m += 64) a += Mz[(size_t)n * nn + m] * G[m];
+    for (int off = 32; off > 0; off >>= 1) a += __shfl_down(a, off, 64);
+    if (lane == 0) hv[n] = a;
   }
   __syncthreads();
   double* hz = h + (size_t)z * 2 * nn;
-  for (int i = threadIdx.x; i < nn; i += blockDim.x) {
-    double a = 0.0;
-    for (int j = 0; j < nn; ++j) a += SigT[(size_t)j * nn + i] * hv[j];
-    hz[i] = hv[i];
-    hz[nn + i] = a;
-  }
+  pc_second_derivs(nn, SigT, hv, hz + nn);
+  for (int i = threadIdx.x; i < nn; i += blockDim.x) hz[i] = hv[i];
 }
 
 enum PcScatter { PC_FIRST = 0, PC_SIGMA = 1, PC_UPDATE = 2 };
@@ -101,7 +124,8 @@ static int pc_gather(trap_ctx* ctx, const double* src, int stride, const double*
   Problem& P = ctx->pb;
   Precomp& C = ctx->pre;
   hipLaunchKernelGGL(k_pc_gather, dim3(P.nz), dim3(256), 4 * P.nn * sizeof(double), ctx->stream, P.nd, P.nn, P.d_x,
-                     P.d_SigT, P.d_lam, P.d_w, C.d_pcDcls, C.d_pcNcls, C.d_pcCub, src, stride, Mat, ctx->wk.pc_h);
+                     P.d_SigT, P.d_lam, P.d_w, C.d_pcMem, C.d_pcMoff, C.d_pcNcls, C.d_pcCub, src, stride, Mat,
+                     ctx->wk.pc_h);
   TRAP_HIP(hipGetLastError());
   return TRAP_OK;
 }

@@ -112,12 +112,13 @@ struct Problem {
   // of the class kernels in the comoving coupling (R_II: real and imaginary
   // planes, pc_cr / pc_ci [nz][nk]; R_III: four complex [nk][nk] blocks
   // pc_X [nz][4][nk][nk]); directions grouped by Doppler shift per height
-  // (pc_dcls [nz][nd] class of each direction, pc_cub [nz][nd] class shifts
-  // in u units, pc_ncls [nz] class count)
+  // (pc_mem [nz][nd] directions ordered by class, class c holding
+  // pc_mem[pc_moff[c] .. pc_moff[c + 1]) of its height, pc_moff [nz][nd + 1];
+  // pc_cub [nz][nd] class shifts in u units, pc_ncls [nz] class count)
   int pc_nk = 0;
   std::vector<double> pc_dE, pc_cr, pc_ci, pc_cub;
   std::vector<double2> pc_X;
-  std::vector<int> pc_dcls, pc_ncls;
+  std::vector<int> pc_mem, pc_moff, pc_ncls;
 };
 
 struct Precomp {
@@ -144,6 +145,7 @@ struct Precomp {
   double *d_pcPhi = nullptr;  // [z][n][m] comoving coupling Phi_z
   double *d_pcC = nullptr;    // [z][n][m] Phi_z (Id - A_z)^-1
   double *d_pcL = nullptr;    // [z][o][n] local Lambda (diagonal of the scalar formal solution)
+  double2 *d_pcF = nullptr;   // [z][o][n] scalar DELO step into z: (exp(-dtau), psi_u / eta_I upwind)
   double *d_pcA = nullptr;    // [z][m'][m] A_z, then the Gauss-Jordan scratch [z][nn][2 nn]
   double *d_pcM = nullptr;    // [z][k][c][n][ldm] angle-averaged kernels of the zero-field classes
   double2 *d_pcR3 = nullptr;  // [z][k][n] R_III weights of the classes
@@ -151,7 +153,7 @@ struct Precomp {
   double *d_pcSt = nullptr;   // [z][k] class shifts (u units)
   double *d_pcCr = nullptr, *d_pcCi = nullptr;
   double2 *d_pcX = nullptr;
-  int *d_pcDcls = nullptr, *d_pcNcls = nullptr;
+  int *d_pcMem = nullptr, *d_pcMoff = nullptr, *d_pcNcls = nullptr;
   double *d_pcCub = nullptr;
   double *d_pcTheta = nullptr, *d_pcRw = nullptr;   // Gauss-Legendre angles and weights of the average
 };
@@ -401,8 +403,9 @@ int launch_formal_grouped(hipStream_t s, const GFormal* args, const int* off, in
 // (precond.hip; out may equal r)
 int run_precompute_precond(trap_ctx* ctx);
 int precond_apply(trap_ctx* ctx, const double* r, double* out, int sweeps, int prec);
-// local Lambda of the scalar formal solution, and the sweep of Lambda* with
-// the fused residual res = y - x + Lambda* e (formal.hip)
+// local Lambda and step coefficients of the scalar formal solution, and the
+// sweep of Lambda* with the fused residual res = y - x + Lambda* e
+// (formal.hip; the sweep's arithmetic is FP64 whatever prec)
 int launch_pc_local_lambda(trap_ctx* ctx);
 int launch_formal_scalar(trap_ctx* ctx, int prec, const double* e, const double* y, int y_stride,
                          const double* x, double* res);
