@@ -1060,8 +1060,8 @@ constexpr int kInvThreads = 1024;
 __global__ void __launch_bounds__(kInvThreads) k_pc_invert(int nn, const double* __restrict__ A,
                                                            const double* __restrict__ Phi, double* __restrict__ aug,
                                                            double* __restrict__ C) {
-  __shared__ double rv[kInvThreads];
-  __shared__ int ri[kInvThreads];
+  __shared__ double rv[kInvThreads / 64];
+  __shared__ int ri[kInvThreads / 64];
   __shared__ double fac[1024];
   const int z = blockIdx.x, tid = threadIdx.x;
   const int w2 = 2 * nn;
@@ -1073,8 +1073,10 @@ __global__ void __launch_bounds__(kInvThreads) k_pc_invert(int nn, const double*
     G[e] = j < nn ? (i == j ? 1.0 : 0.0) - Az[(size_t)j * nn + i] : Pz[(size_t)(j - nn) * nn + i];
   }
   __syncthreads();
+  const int lane = tid & 63, wv = tid >> 6, nwv = blockDim.x >> 6;
   for (int k = 0; k < nn; ++k) {
-    // pivot: the largest |G[i][k]|, i >= k
+    // pivot: the largest |G[i][k]|, i >= k (smallest i on ties): within each
+    // wave by shuffles, then across the waves
     double best = -1.0;
     int bi = k;
     for (int i = k + tid; i < nn; i += blockDim.x) {
@@ -1084,17 +1086,26 @@ __global__ void __launch_bounds__(kInvThreads) k_pc_invert(int nn, const double*
         bi = i;
       }
     }
-    rv[tid] = best;
-    ri[tid] = bi;
-    __syncthreads();
-    for (int st = blockDim.x / 2; st > 0; st >>= 1) {
-      if (tid < st && (rv[tid + st] > rv[tid] || (rv[tid + st] == rv[tid] && ri[tid + st] < ri[tid]))) {
-        rv[tid] = rv[tid + st];
-        ri[tid] = ri[tid + st];
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ov = __shfl_xor(best, off, 64);
+      const int oi = __shfl_xor(bi, off, 64);
+      if (ov > best || (ov == best && oi < bi)) {
+        best = ov;
+        bi = oi;
       }
-      __syncthreads();
     }
-    const int p = ri[0];
+    if (lane == 0) {
+      rv[wv] = best;
+      ri[wv] = bi;
+    }
+    __syncthreads();
+    int p = ri[0];
+    double pb = rv[0];
+    for (int r = 1; r < nwv; ++r)
+      if (rv[r] > pb || (rv[r] == pb && ri[r] < p)) {
+        pb = rv[r];
+        p = ri[r];
+      }
     if (p != k)
       for (int j = k + tid; j < w2; j += blockDim.x) {
         const double t = G[(size_t)k * w2 + j];

@@ -21,22 +21,35 @@
 
 namespace trap {
 
+constexpr int kGatherThreads = 512;
+constexpr int kGatherParts = 4;       // partial sums per output of the spline products
+
 // sd = Sig v for one vector of N_nu values in LDS (SigT = Sig^T, so that
-// consecutive threads read consecutive entries); four independent partial
-// sums keep several loads in flight per thread.
-__device__ inline void pc_second_derivs(int nn, const double* __restrict__ SigT, const double* v, double* sd) {
-  for (int i = threadIdx.x; i < nn; i += blockDim.x) {
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-    int j = 0;
-    for (; j + 4 <= nn; j += 4) {
+// consecutive threads read consecutive entries).  The block splits the sum
+// over j into kGatherParts ranges (partial sums in part[kGatherParts][nn]),
+// which shortens each thread's chain of dependent loads.  Ends synchronised.
+__device__ inline void pc_second_derivs(int nn, const double* __restrict__ SigT, const double* v, double* part,
+                                        double* sd) {
+  const int per = (kGatherThreads / kGatherParts);
+  const int q = threadIdx.x / per, i0 = threadIdx.x % per;
+  const int j0 = q * nn / kGatherParts, j1 = (q + 1) * nn / kGatherParts;
+  for (int i = i0; i < nn; i += per) {
+    double a0 = 0.0, a1 = 0.0;
+    int j = j0;
+    for (; j + 2 <= j1; j += 2) {
       a0 += SigT[(size_t)j * nn + i] * v[j];
       a1 += SigT[(size_t)(j + 1) * nn + i] * v[j + 1];
-      a2 += SigT[(size_t)(j + 2) * nn + i] * v[j + 2];
-      a3 += SigT[(size_t)(j + 3) * nn + i] * v[j + 3];
     }
-    for (; j < nn; ++j) a0 += SigT[(size_t)j * nn + i] * v[j];
-    sd[i] = (a0 + a1) + (a2 + a3);
+    if (j < j1) a0 += SigT[(size_t)j * nn + i] * v[j];
+    part[q * nn + i] = a0 + a1;
   }
+  __syncthreads();
+  for (int i = threadIdx.x; i < nn; i += blockDim.x) {
+    double a = 0.0;
+    for (int r = 0; r < kGatherParts; ++r) a += part[r * nn + i];
+    sd[i] = a;
+  }
+  __syncthreads();
 }
 
 // hz = Mat_z sum_c Ups_c (sum_{o in c} w_o src_o) for every height z, where
@@ -44,7 +57,7 @@ __device__ inline void pc_second_derivs(int nn, const double* __restrict__ SigT,
 // moff[c + 1]) of the height); hz and its spline second derivatives go to
 // h[z][0][.] and h[z][1][.].  One block per height; the matrix-vector product
 // takes one wave per row.
-__global__ void __launch_bounds__(256) k_pc_gather(int nd, int nn, const double* __restrict__ x,
+__global__ void __launch_bounds__(kGatherThreads) k_pc_gather(int nd, int nn, const double* __restrict__ x,
                                                    const double* __restrict__ SigT, const double* __restrict__ lam,
                                                    const double* __restrict__ w, const int* __restrict__ mem,
                                                    const int* __restrict__ moff, const int* __restrict__ ncls,
@@ -56,6 +69,7 @@ __global__ void __launch_bounds__(256) k_pc_gather(int nd, int nn, const double*
   double* sd = sh + nn;
   double* G = sh + 2 * nn;
   double* hv = sh + 3 * nn;
+  double* part = sh + 4 * nn;       // [kGatherParts][nn]
   const int z = blockIdx.x;
   for (int m = threadIdx.x; m < nn; m += blockDim.x) G[m] = 0.0;
   const double Lz = lam[z];
@@ -76,8 +90,7 @@ __global__ void __launch_bounds__(256) k_pc_gather(int nd, int nn, const double*
       v[n] = a0 + a1;
     }
     __syncthreads();
-    pc_second_derivs(nn, SigT, v, sd);
-    __syncthreads();
+    pc_second_derivs(nn, SigT, v, part, sd);
     for (int m = threadIdx.x; m < nn; m += blockDim.x) G[m] += spline_at(x, nn, v, sd, x[m] - shf);
     __syncthreads();
   }
@@ -91,7 +104,7 @@ __global__ void __launch_bounds__(256) k_pc_gather(int nd, int nn, const double*
   }
   __syncthreads();
   double* hz = h + (size_t)z * 2 * nn;
-  pc_second_derivs(nn, SigT, hv, hz + nn);
+  pc_second_derivs(nn, SigT, hv, part, hz + nn);
   for (int i = threadIdx.x; i < nn; i += blockDim.x) hz[i] = hv[i];
 }
 
@@ -123,7 +136,8 @@ __global__ void __launch_bounds__(256) k_pc_scatter(int mode, int nz, int nd, in
 static int pc_gather(trap_ctx* ctx, const double* src, int stride, const double* Mat) {
   Problem& P = ctx->pb;
   Precomp& C = ctx->pre;
-  hipLaunchKernelGGL(k_pc_gather, dim3(P.nz), dim3(256), 4 * P.nn * sizeof(double), ctx->stream, P.nd, P.nn, P.d_x,
+  hipLaunchKernelGGL(k_pc_gather, dim3(P.nz), dim3(kGatherThreads), (4 + kGatherParts) * P.nn * sizeof(double),
+                     ctx->stream, P.nd, P.nn, P.d_x,
                      P.d_SigT, P.d_lam, P.d_w, C.d_pcMem, C.d_pcMoff, C.d_pcNcls, C.d_pcCub, src, stride, Mat,
                      ctx->wk.pc_h);
   TRAP_HIP(hipGetLastError());
