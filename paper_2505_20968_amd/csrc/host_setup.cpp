@@ -736,6 +736,21 @@ size_t estimate_bytes(const trap_atom_desc* atom, const trap_problem_desc* pd, i
     for (int k = 0; k < 3; ++k) add(zc * rows_per_z * ldm * 8);
     for (int k = 0; k < 3; ++k) add(nz * nd * nn * 8);  // sweep vectors
     add(nz * 2 * nn * 8);
+    // per-class comoving sums: Doppler-shift classes per height as build_problem forms them
+    int ncmax = 1;
+    for (size_t z = 0; z < nz; ++z) {
+      const double xi = pd->xi ? pd->xi[z] * 1e5 : 0.0;
+      const double vth = std::sqrt(2.0 * kKB * pd->T[z] / mass + xi * xi);
+      std::vector<double> cub;
+      for (size_t o = 0; o < nd && pd->v; ++o) {
+        const double vdot = pd->v[3 * z] * dirs[3 * o] + pd->v[3 * z + 1] * dirs[3 * o + 1] +
+                            pd->v[3 * z + 2] * dirs[3 * o + 2];
+        const double v = vdot * 1e5 / vth;
+        if (std::find(cub.begin(), cub.end(), v) == cub.end()) cub.push_back(v);
+      }
+      ncmax = std::max(ncmax, (int)cub.size());
+    }
+    add(nz * (size_t)ncmax * nn * 8);
   }
   // the height-chunked Sigma path materialises W for one chunk of heights
   // (at most ~512 MiB in FP64, half that in FP32)

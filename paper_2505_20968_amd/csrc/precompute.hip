@@ -686,25 +686,30 @@ __global__ void __launch_bounds__(64) k_r3_rows(int nt, int nn, const double* __
     graded_integrate(x[p], x[p + 1], xc, wc, Lg, x[p], 1.0 / (x[p + 1] - x[p]), 4, integrand, acc);
     for (int q = 0; q < 4; ++q) mom[(p + 1) * 4 + q] = acc[q];
   }
-  // tails in u units: int [w(u'+s+ia) - i/(sqrt(pi) u')] du' over (-inf, u0] and [u1, inf)
-  if (lane < 2) {
-    const double uedge = (lane == 0) ? L * x[0] : L * x[nn - 1];
-    const double sgn = (lane == 0) ? -1.0 : 1.0;
+  // tails in u units: int [w(u'+s+ia) - i/(sqrt(pi) u')] du' over (-inf, u0]
+  // (lanes 0-31) and [u1, inf) (lanes 32-63), u' = u_edge +- |u_edge| tau/(1 - tau),
+  // 32 panels of 16 Gauss-Legendre nodes in tau, one panel per lane
+  {
+    const int side = lane >> 5, pnl = lane & 31;
+    const double uedge = side == 0 ? L * x[0] : L * x[nn - 1];
+    const double sgn = side == 0 ? -1.0 : 1.0;
     const double sc = fabs(uedge);
     double2 acc = make_double2(0.0, 0.0);
-    for (int pnl = 0; pnl < 32; ++pnl) {
-      const double ta = pnl / 32.0, tb = (pnl + 1) / 32.0;
-      for (int i = 0; i < 16; ++i) {
-        const double tau = ta + (tb - ta) * c_gl_t[i];
-        const double om = 1.0 - tau;
-        const double up = uedge + sgn * sc * tau / om;
-        const double2 w = wz(up + s, a);
-        const double jac = sc / (om * om) * (tb - ta) * c_gl_w[i];
-        acc.x += jac * w.x;
-        acc.y += jac * (w.y - kInvSqrtPi / up);
-      }
+    const double ta = pnl / 32.0, tb = (pnl + 1) / 32.0;
+    for (int i = 0; i < 16; ++i) {
+      const double tau = ta + (tb - ta) * c_gl_t[i];
+      const double om = 1.0 - tau;
+      const double up = uedge + sgn * sc * tau / om;
+      const double2 w = wz(up + s, a);
+      const double jac = sc / (om * om) * (tb - ta) * c_gl_w[i];
+      acc.x += jac * w.x;
+      acc.y += jac * (w.y - kInvSqrtPi / up);
     }
-    mom[(lane == 0 ? 0 : nn) * 4] = acc;
+    for (int off = 16; off > 0; off >>= 1) {
+      acc.x += __shfl_xor(acc.x, off, 64);
+      acc.y += __shfl_xor(acc.y, off, 64);
+    }
+    if (pnl == 0) mom[(side == 0 ? 0 : nn) * 4] = acc;
   }
   __syncthreads();
   for (int m = lane; m < nn; m += 64) {
@@ -1219,6 +1224,8 @@ int run_precompute_precond(trap_ctx* ctx) {
   hipLaunchKernelGGL(k_pc_invert, dim3(nz), dim3(kInvThreads), 0, s, nn, C.d_pcA, C.d_pcPhi,
                      C.d_pcA + (size_t)nz * nn * nn, C.d_pcC);
   TRAP_HIP(hipGetLastError());
+  C.pc_ncmax = 1;
+  for (int z = 0; z < nz; ++z) C.pc_ncmax = std::max(C.pc_ncmax, P.pc_ncls[z]);
   C.pc_done = true;
   return TRAP_OK;
 }

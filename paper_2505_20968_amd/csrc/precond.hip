@@ -52,48 +52,68 @@ __device__ inline void pc_second_derivs(int nn, const double* __restrict__ SigT,
   __syncthreads();
 }
 
-// hz = Mat_z sum_c Ups_c (sum_{o in c} w_o src_o) for every height z, where
-// class c holds the directions of one Doppler shift (members mem[moff[c] ..
-// moff[c + 1]) of the height); hz and its spline second derivatives go to
-// h[z][0][.] and h[z][1][.].  One block per height; the matrix-vector product
-// takes one wave per row.
-__global__ void __launch_bounds__(kGatherThreads) k_pc_gather(int nd, int nn, const double* __restrict__ x,
-                                                   const double* __restrict__ SigT, const double* __restrict__ lam,
-                                                   const double* __restrict__ w, const int* __restrict__ mem,
-                                                   const int* __restrict__ moff, const int* __restrict__ ncls,
-                                                   const double* __restrict__ cub, const double* __restrict__ src,
-                                                   int stride, const double* __restrict__ Mat,
-                                                   double* __restrict__ h) {
+// gc[z][c][.] = Ups_c (sum_{o in c} w_o src_o): the angular sum of Doppler
+// class c of height z (members mem[moff[c] .. moff[c + 1])) interpolated to
+// the comoving grid.  One block per (z, c); blocks past the height's class
+// count return at once.
+__global__ void __launch_bounds__(kGatherThreads) k_pc_gather_cls(int nd, int nn, int ncmax,
+                                                                  const double* __restrict__ x,
+                                                                  const double* __restrict__ SigT,
+                                                                  const double* __restrict__ lam,
+                                                                  const double* __restrict__ w,
+                                                                  const int* __restrict__ mem,
+                                                                  const int* __restrict__ moff,
+                                                                  const int* __restrict__ ncls,
+                                                                  const double* __restrict__ cub,
+                                                                  const double* __restrict__ src, int stride,
+                                                                  double* __restrict__ gc) {
   extern __shared__ double sh[];
   double* v = sh;
   double* sd = sh + nn;
-  double* G = sh + 2 * nn;
-  double* hv = sh + 3 * nn;
-  double* part = sh + 4 * nn;       // [kGatherParts][nn]
-  const int z = blockIdx.x;
-  for (int m = threadIdx.x; m < nn; m += blockDim.x) G[m] = 0.0;
-  const double Lz = lam[z];
+  double* part = sh + 2 * nn;       // [kGatherParts][nn]
+  const int z = blockIdx.x / ncmax, c = blockIdx.x % ncmax;
+  if (c >= ncls[z]) return;
+  const double shf = cub[(size_t)z * nd + c] / lam[z];
   const int* mz = mem + (size_t)z * nd;
-  const int* oz = moff + (size_t)z * (nd + 1);
-  for (int c = 0; c < ncls[z]; ++c) {
-    const double shf = cub[(size_t)z * nd + c] / Lz;
-    const int k0 = oz[c], k1 = oz[c + 1];
-    for (int n = threadIdx.x; n < nn; n += blockDim.x) {
-      double a0 = 0.0, a1 = 0.0;
-      int k = k0;
-      for (; k + 2 <= k1; k += 2) {
-        const int o0 = mz[k], o1 = mz[k + 1];
-        a0 += w[o0] * src[(((size_t)z * nd + o0) * nn + n) * stride];
-        a1 += w[o1] * src[(((size_t)z * nd + o1) * nn + n) * stride];
-      }
-      if (k < k1) a0 += w[mz[k]] * src[(((size_t)z * nd + mz[k]) * nn + n) * stride];
-      v[n] = a0 + a1;
+  const int k0 = moff[(size_t)z * (nd + 1) + c], k1 = moff[(size_t)z * (nd + 1) + c + 1];
+  for (int n = threadIdx.x; n < nn; n += blockDim.x) {
+    double a0 = 0.0, a1 = 0.0;
+    int k = k0;
+    for (; k + 2 <= k1; k += 2) {
+      const int o0 = mz[k], o1 = mz[k + 1];
+      a0 += w[o0] * src[(((size_t)z * nd + o0) * nn + n) * stride];
+      a1 += w[o1] * src[(((size_t)z * nd + o1) * nn + n) * stride];
     }
-    __syncthreads();
-    pc_second_derivs(nn, SigT, v, part, sd);
-    for (int m = threadIdx.x; m < nn; m += blockDim.x) G[m] += spline_at(x, nn, v, sd, x[m] - shf);
-    __syncthreads();
+    if (k < k1) a0 += w[mz[k]] * src[(((size_t)z * nd + mz[k]) * nn + n) * stride];
+    v[n] = a0 + a1;
   }
+  __syncthreads();
+  pc_second_derivs(nn, SigT, v, part, sd);
+  double* g = gc + ((size_t)z * ncmax + c) * nn;
+  for (int m = threadIdx.x; m < nn; m += blockDim.x) g[m] = spline_at(x, nn, v, sd, x[m] - shf);
+}
+
+// hz = Mat_z sum_c gc[z][c] with one wave per row of Mat_z, then the spline
+// second derivatives of hz; hz and them go to h[z][0][.] and h[z][1][.].
+// One block per height.
+__global__ void __launch_bounds__(kGatherThreads) k_pc_gather_fin(int nn, int ncmax,
+                                                                  const double* __restrict__ SigT,
+                                                                  const int* __restrict__ ncls,
+                                                                  const double* __restrict__ gc,
+                                                                  const double* __restrict__ Mat,
+                                                                  double* __restrict__ h) {
+  extern __shared__ double sh[];
+  double* G = sh;
+  double* hv = sh + nn;
+  double* part = sh + 2 * nn;       // [kGatherParts][nn]
+  const int z = blockIdx.x, nc = ncls[z];
+  const double* gz = gc + (size_t)z * ncmax * nn;
+  for (int m = threadIdx.x; m < nn; m += blockDim.x) {
+    double a = 0.0;
+    for (int c = 0; c < nc; ++c) a += gz[(size_t)c * nn + m];
+    G[m] = a;
+  }
+  __syncthreads();
   const double* Mz = Mat + (size_t)z * nn * nn;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   for (int n = wave; n < nn; n += nw) {
@@ -136,10 +156,13 @@ __global__ void __launch_bounds__(256) k_pc_scatter(int mode, int nz, int nd, in
 static int pc_gather(trap_ctx* ctx, const double* src, int stride, const double* Mat) {
   Problem& P = ctx->pb;
   Precomp& C = ctx->pre;
-  hipLaunchKernelGGL(k_pc_gather, dim3(P.nz), dim3(kGatherThreads), (4 + kGatherParts) * P.nn * sizeof(double),
-                     ctx->stream, P.nd, P.nn, P.d_x,
-                     P.d_SigT, P.d_lam, P.d_w, C.d_pcMem, C.d_pcMoff, C.d_pcNcls, C.d_pcCub, src, stride, Mat,
-                     ctx->wk.pc_h);
+  hipLaunchKernelGGL(k_pc_gather_cls, dim3(P.nz * C.pc_ncmax), dim3(kGatherThreads),
+                     (2 + kGatherParts) * P.nn * sizeof(double), ctx->stream, P.nd, P.nn, C.pc_ncmax, P.d_x,
+                     P.d_SigT, P.d_lam, P.d_w, C.d_pcMem, C.d_pcMoff, C.d_pcNcls, C.d_pcCub, src, stride,
+                     ctx->wk.pc_gc);
+  TRAP_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_pc_gather_fin, dim3(P.nz), dim3(kGatherThreads), (2 + kGatherParts) * P.nn * sizeof(double),
+                     ctx->stream, P.nn, C.pc_ncmax, P.d_SigT, C.d_pcNcls, ctx->wk.pc_gc, Mat, ctx->wk.pc_h);
   TRAP_HIP(hipGetLastError());
   return TRAP_OK;
 }
@@ -169,6 +192,7 @@ int precond_apply(trap_ctx* ctx, const double* r, double* out, int sweeps, int p
     TRAP_TRY(dalloc_t(ctx, &K.pc_e, ns));
     TRAP_TRY(dalloc_t(ctx, &K.pc_res, ns));
     TRAP_TRY(dalloc_t(ctx, &K.pc_h, (size_t)P.nz * 2 * P.nn));
+    TRAP_TRY(dalloc_t(ctx, &K.pc_gc, (size_t)P.nz * C.pc_ncmax * P.nn));
   }
   if (out != r) TRAP_HIP(hipMemcpyAsync(out, r, 4 * ns * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
   // x_1 = P^^-1 y with y the Stokes I of `out` (read until the last write)

@@ -156,6 +156,7 @@ struct Precomp {
   int *d_pcMem = nullptr, *d_pcMoff = nullptr, *d_pcNcls = nullptr;
   double *d_pcCub = nullptr;
   double *d_pcTheta = nullptr, *d_pcRw = nullptr;   // Gauss-Legendre angles and weights of the average
+  int pc_ncmax = 0;            // most Doppler-shift classes at one height
 };
 
 struct Work {
@@ -177,6 +178,7 @@ struct Work {
   // preconditioner sweeps: Stokes-I fields [z][o][n] and per-height vectors
   double *pc_x = nullptr, *pc_e = nullptr, *pc_res = nullptr;
   double *pc_h = nullptr;     // [z][2][nn]: comoving vector and its spline second derivatives
+  double *pc_gc = nullptr;    // [z][class][nn]: comoving interpolation of each Doppler class's angular sum
 };
 
 struct ProfRec {
