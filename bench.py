@@ -152,6 +152,9 @@ def main():
     ap.add_argument("--restart", type=int, default=40)
     ap.add_argument("--precond-sweeps", type=int, default=4,
                     help="block-Jacobi steps of the physics-based preconditioner (0: none)")
+    ap.add_argument("--serve-precond-sweeps", type=int, default=1,
+                    help="the same for the serving measurement (its requests are smaller and its host "
+                         "loop issues every request's preconditioner launches, so fewer steps pay)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=16,
                     help="requests in the serving measurement (0 skips it)")
@@ -289,7 +292,7 @@ def main():
                                 if mixed else "k_contract<double, NH>")},
     }
     if args.serve_requests > 0:
-        out["serving"] = serving_bench(args.serve_requests, seed=5, precond_sweeps=sweeps)
+        out["serving"] = serving_bench(args.serve_requests, seed=5, precond_sweeps=args.serve_precond_sweeps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(plain_applies, seed=2)
     print(json.dumps(out))
