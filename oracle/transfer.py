@@ -112,6 +112,7 @@ def setup(prob, opts=None) -> OracleProblem:
       normalize:    apply the App. E factor f (default True)
       aa:           angle-averaged R_II (Sect. 5.2, Eq. R_AA) in place of the
                     angle-dependent kernel (default False)
+      formal:       'linear' (DELO-linear, default) or 'delopar' formal solver
     """
     opts = dict({"normalize": True}, **(opts or {}))
     atom = prob.atom
@@ -315,8 +316,52 @@ def _psi(x):
     return psi_u, psi_c, ex
 
 
-def formal_solve(op, eps, boundary=True, I_bottom=None):
-    """Lambda eps (+ t if boundary): DELO-linear sweeps along every ray."""
+def _exp_moments(m):
+    """E_k = int_0^m t^k e^{-t} dt for k = 0, 1, 2 (power series below m = 0.5,
+    where the closed forms cancel)."""
+    m = np.asarray(m, float)
+    ex = np.exp(-m)
+    E0 = -np.expm1(-m)
+    E1 = E0 - m * ex
+    E2 = 2.0 * E1 - m * m * ex
+    small = m < 0.5
+    if np.any(small):
+        ms = m[small]
+        s = [np.zeros_like(ms) for _ in range(3)]
+        term = np.ones_like(ms)              # (-1)^j m^j / j!
+        for j in range(30):
+            for k in range(3):
+                s[k] += term * ms ** (k + 1) / (k + j + 1)
+            term = -term * ms / (j + 1)
+        E0 = np.where(small, 0.0, E0)
+        E1 = np.where(small, 0.0, E1)
+        E2 = np.where(small, 0.0, E2)
+        E0[small], E1[small], E2[small] = s
+    return E0, E1, E2
+
+
+def _psi_parabolic(m, p):
+    """Weights of S at the upwind (M), current (O) and downwind (P) points for
+    int_0^m e^{-t} S(t) dt with S the parabola through the three points, t
+    measured from O back along the ray (M at t = m, P at t = -p)."""
+    E0, E1, E2 = _exp_moments(m)
+    wM = (E2 + p * E1) / (m * (m + p))
+    wO = -(E2 + (p - m) * E1 - m * p * E0) / (m * p)
+    wP = (E2 - m * E1) / (p * (m + p))
+    return wM, wO, wP
+
+
+def formal_solve(op, eps, boundary=True, I_bottom=None, scheme=None):
+    """Lambda eps (+ t if boundary): DELO sweeps along every ray.
+
+    scheme 'linear' (default, or op.opts['formal']): DELO-linear, S and K'I
+    linear between the upwind and current points.  'delopar': S parabolic
+    through the upwind, current and downwind points, K'I linear (the
+    DELOPAR integrator named in Sect. 3); the last point of a ray, which has
+    no downwind point, takes the DELO-linear step."""
+    scheme = scheme or op.opts.get("formal", "linear")
+    if scheme not in ("linear", "delopar"):
+        raise ValueError(f"unknown formal scheme {scheme}")
     prob = op.prob
     nz, nd, nn = prob.n_z, prob.n_dir, prob.n_nu
     K = op.K
@@ -344,7 +389,14 @@ def formal_solve(op, eps, boundary=True, I_bottom=None):
             pu, pc, ex = _psi(x)
             lhs = np.eye(4)[None] + pc[:, None, None] * Kp[zc, o]
             rhs = (ex[:, None, None] * np.eye(4)[None] - pu[:, None, None] * Kp[zu, o])
-            b = np.einsum("nij,nj->ni", rhs, Icur) + pu[:, None] * S[zu, o] + pc[:, None] * S[zc, o]
+            if scheme == "delopar" and k + 1 < nz:
+                zd = order[k + 1]
+                xd = 0.5 * (ratio[zc, o] + ratio[zd, o]) * dtl[min(zc, zd)] / abs(mu[o])
+                wM, wO, wP = _psi_parabolic(x, xd)
+                src = wM[:, None] * S[zu, o] + wO[:, None] * S[zc, o] + wP[:, None] * S[zd, o]
+            else:
+                src = pu[:, None] * S[zu, o] + pc[:, None] * S[zc, o]
+            b = np.einsum("nij,nj->ni", rhs, Icur) + src
             Icur = np.linalg.solve(lhs, b[..., None])[..., 0]
             I[zc, o] = Icur
     return I

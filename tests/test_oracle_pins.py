@@ -550,3 +550,67 @@ def test_sqrt_eps_law_for_complete_redistribution():
         errs.append(abs(S.mean() / np.sqrt(0.04) - 1.0))
     assert errs[1] < 0.05
     assert errs[1] < errs[0] / 1.8
+
+
+def test_delopar_weights_reproduce_the_exponential_moments():
+    """The parabolic weights integrate e^{-t} times 1, t and t^2 exactly over
+    [0, m] with the nodes t = m (upwind), 0 (current), -p (downwind)."""
+    from scipy.integrate import quad
+    for m, p in ((1e-4, 2e-4), (0.05, 0.3), (0.49, 0.51), (0.7, 0.2), (3.0, 5.0), (40.0, 1.0)):
+        wM, wO, wP = T._psi_parabolic(np.array([m]), np.array([p]))
+        for k, nodes in ((0, (1.0, 1.0, 1.0)), (1, (m, 0.0, -p)), (2, (m * m, 0.0, p * p))):
+            ref = quad(lambda t: t ** k * np.exp(-t), 0.0, m, epsabs=0.0, epsrel=1e-13)[0]
+            got = wM[0] * nodes[0] + wO[0] * nodes[1] + wP[0] * nodes[2]
+            assert abs(got - ref) <= 1e-12 * max(abs(ref), 1e-300) + 1e-18
+
+
+def test_delopar_exact_for_a_quadratic_source():
+    """Static, field-free atmosphere (K' = 0) with eta_I / eta_0 constant in
+    height and the source W = B0 + B1 tau + B2 tau^2: the emerging intensity of
+    a semi-infinite medium is S + mu dS/dtau_v + mu^2 d2S/dtau_v^2.  Entered at
+    the bottom with that value, DELOPAR reproduces it at every point that has a
+    downwind neighbour (the last point takes the linear step); DELO-linear does
+    not."""
+    p = tiny(n_z=12, n_nu=9, x_max=4, n_mu=4, n_chi=2, B=(0.0, 0.0, 0.0), a=2e-2, eps=0.1,
+             tau_top=1e-2, tau_bot=20.0)
+    op = T.setup(p, {"normalize": False})
+    B0, B1, B2 = 0.4, 0.3, 0.05
+    tl = p.tau_line
+    Wt = B0 + B1 * tl + B2 * tl * tl
+    eps = Wt[:, None, None, None] * op.K[:, :, :, :, 0]
+    r = op.K[..., 0, 0] / op.eta0[:, None, None]
+    assert np.abs(r - r[0:1]).max() < 1e-12 * np.abs(r).max()
+    mu = op.ang["mu"]
+    Iex = np.zeros_like(eps)
+    Iex[..., 0] = (Wt[:, None, None] + mu[None, :, None] * (B1 + 2 * B2 * tl)[:, None, None] / r
+                   + 2 * B2 * (mu[None, :, None] / r) ** 2)
+    up = mu > 0
+    Ip = T.formal_solve(op, eps, boundary=True, I_bottom=Iex[0], scheme="delopar")
+    Il = T.formal_solve(op, eps, boundary=True, I_bottom=Iex[0], scheme="linear")
+    rel_p = np.abs(Ip[:-1, up, :, 0] - Iex[:-1, up, :, 0]) / np.abs(Iex[:-1, up, :, 0])
+    rel_l = np.abs(Il[:-1, up, :, 0] - Iex[:-1, up, :, 0]) / np.abs(Iex[:-1, up, :, 0])
+    assert rel_p.max() < 1e-12
+    assert rel_l.max() > 1e-4
+    assert np.abs(Ip[..., 1:]).max() < 1e-12 * np.abs(Ip[..., 0]).max()
+
+
+def test_delopar_exact_for_milne_eddington():
+    """The Milne-Eddington case above (constant K/eta_I with dichroism and
+    dispersion, linear source) is integrated exactly by DELOPAR too: the
+    parabola through a linear source is the line, and K'I is linear along the
+    ray."""
+    p = tiny(n_z=9, n_nu=15, x_max=5, n_mu=4, n_chi=4, B=(800.0, 0.8, 0.4), a=2e-2, eps=0.1,
+             tau_top=1e-2, tau_bot=30.0)
+    op = T.setup(p, {"normalize": False})
+    B0, B1 = 0.7, 0.35
+    Wt = B0 + B1 * p.tau_line
+    eps = Wt[:, None, None, None] * op.K[:, :, :, :, 0]
+    ratio = op.K[..., 0, 0] / op.eta0[:, None, None]
+    Khat = op.K / op.K[..., 0:1, 0:1]
+    e0 = np.array([1.0, 0, 0, 0])
+    mu = op.ang["mu"]
+    part = np.einsum("zonij,j->zoni", np.linalg.inv(Khat), e0)
+    Iex = Wt[:, None, None, None] * e0 + (B1 * mu[None, :, None, None] / ratio[..., None]) * part
+    I = T.formal_solve(op, eps, boundary=True, I_bottom=Iex[0], scheme="delopar")
+    up = mu > 0
+    assert np.abs(I[:, up] - Iex[:, up]).max() < 1e-12
