@@ -204,6 +204,17 @@ int trap_apply_sigma(trap_ctx* ctx, const void* I, void* eps, int prec, int add_
 /* I = Lambda eps (+ t if with_boundary): DELO-linear sweeps (Sect. 3). */
 int trap_formal_solve(trap_ctx* ctx, const void* eps, void* I, int with_boundary, int prec);
 
+/* Formal solver of Lambda (Sect. 3).  TRAP_FORMAL_DELO_LINEAR (default): S and
+ * K'I linear between the upwind and current points.  TRAP_FORMAL_DELOPAR: S
+ * integrated with the parabola through the upwind, current and downwind
+ * points (weights from the moments int_0^m t^k e^{-t} dt, FP64), K'I linear;
+ * a ray's last point takes the DELO-linear step.  Applies to trap_formal_solve,
+ * the operator and the right-hand side, so it is set before trap_precompute
+ * (TRAP_ESTATE when changed after it for the loaded problem; a new problem
+ * frees it again).  The preconditioner's scalar sweep stays DELO-linear. */
+enum { TRAP_FORMAL_DELO_LINEAR = 0, TRAP_FORMAL_DELOPAR = 1 };
+int trap_set_formal_scheme(trap_ctx* ctx, int scheme);
+
 /* y = (Id - Lambda Sigma) x, the operator of Eq. linear_system. */
 int trap_apply_operator(trap_ctx* ctx, const void* x, void* y, int prec);
 

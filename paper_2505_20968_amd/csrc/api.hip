@@ -350,6 +350,15 @@ int trap_set_prd_mode(trap_ctx* ctx, int mode) {
   return TRAP_OK;
 }
 
+int trap_set_formal_scheme(trap_ctx* ctx, int scheme) {
+  if (!ctx) return fail(TRAP_EINVAL, "null context");
+  if (scheme != TRAP_FORMAL_DELO_LINEAR && scheme != TRAP_FORMAL_DELOPAR) return fail(TRAP_EINVAL, "unknown formal scheme");
+  if (ctx->pre.done && scheme != ctx->formal_scheme)
+    return fail(TRAP_ESTATE, "the formal scheme is fixed once trap_precompute has run for the problem");
+  ctx->formal_scheme = scheme;
+  return TRAP_OK;
+}
+
 int trap_set_path(trap_ctx* ctx, int path) {
   if (!ctx) return fail(TRAP_EINVAL, "null context");
   if (path != TRAP_PATH_AUTO && path != TRAP_PATH_FUSED && path != TRAP_PATH_CHUNKED)

@@ -95,11 +95,44 @@ __device__ inline void delo_solve(const T* k, T p, const T* b, T* xout) {
   }
 }
 
+// DELOPAR (Sect. 3): the source S integrated against e^{-t} over the upwind
+// interval [0, m] (t from the current point O back to the upwind point M)
+// with the parabola through M (t = m), O (t = 0) and the downwind point P
+// (t = -p).  With E_k = int_0^m t^k e^{-t} dt:
+//   w_M = (E2 + p E1) / (m (m + p)),   w_O = -(E2 + (p - m) E1 - m p E0) / (m p),
+//   w_P = (E2 - m E1) / (p (m + p)).
+// E_k from the closed forms, or below m = 0.5 (where they cancel) from
+// sum_j (-1)^j m^(k+j+1) / (j! (k+j+1)).  Always FP64.
+__device__ inline void parabolic_weights(double m, double p, double& wM, double& wO, double& wP) {
+  double E0, E1, E2;
+  if (m < 0.5) {
+    // E_k = m^(k+1) sum_j t_j / (k + j + 1), t_j = (-m)^j / j!
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, t = 1.0;
+    for (int j = 0; j < 24; ++j) {
+      s0 += t / (j + 1);
+      s1 += t / (j + 2);
+      s2 += t / (j + 3);
+      t *= -m / (j + 1);
+    }
+    E0 = m * s0;
+    E1 = m * m * s1;
+    E2 = m * m * m * s2;
+  } else {
+    const double ex = exp(-m);
+    E0 = 1.0 - ex;
+    E1 = E0 - m * ex;
+    E2 = 2.0 * E1 - m * m * ex;
+  }
+  wM = (E2 + p * E1) / (m * (m + p));
+  wO = -(E2 + (p - m) * E1 - m * p * E0) / (m * p);
+  wP = (E2 - m * E1) / (p * (m + p));
+}
+
 template <typename T>
 __device__ __forceinline__ void formal_body(int bx, int nz, int nd, int nn, const double* __restrict__ mu,
                                             const double* __restrict__ tau, const double* __restrict__ K8,
                                             const double* __restrict__ WT, const T* __restrict__ eps,
-                                            T* __restrict__ I, int with_boundary) {
+                                            T* __restrict__ I, int with_boundary, int scheme) {
   const int id = bx * blockDim.x + threadIdx.x;
   if (id >= nd * nn) return;
   const int o = id / nn, n = id % nn;
@@ -158,7 +191,17 @@ __device__ __forceinline__ void formal_body(int bx, int nz, int nd, int nn, cons
     delo_weights<T>(x, pu, pc, ex);
     T kv[4], b[4];
     kprime_mul<T>(ku, Icur, kv);
-    for (int s = 0; s < 4; ++s) b[s] = ex * Icur[s] - pu * kv[s] + pu * Su[s] + pc * Sc[s];
+    if (scheme == TRAP_FORMAL_DELOPAR && step + 1 < nz) {
+      // the downwind point's data are the ones just prefetched
+      const double xd = 0.5 * (kr[7] + kn[7]) * fabs(tzc - tn) / fabs(m);
+      double wM, wO, wP;
+      parabolic_weights(0.5 * (double(ru) + kr[7]) * fabs(tz - tzc) / fabs(m), xd, wM, wO, wP);
+      const T inP = T(kn[6]);
+      for (int s = 0; s < 4; ++s)
+        b[s] = ex * Icur[s] - pu * kv[s] + T(wM) * Su[s] + T(wO) * Sc[s] + T(wP) * (en[s] * inP);
+    } else {
+      for (int s = 0; s < 4; ++s) b[s] = ex * Icur[s] - pu * kv[s] + pu * Su[s] + pc * Sc[s];
+    }
     T Inew[4];
     delo_solve<T>(kc, pc, b, Inew);
     for (int s = 0; s < 4; ++s) {
@@ -177,8 +220,8 @@ template <typename T>
 __global__ void __launch_bounds__(64) k_formal(int nz, int nd, int nn, const double* __restrict__ mu,
                          const double* __restrict__ tau, const double* __restrict__ K8,
                          const double* __restrict__ WT, const T* __restrict__ eps, T* __restrict__ I,
-                         int with_boundary) {
-  formal_body<T>(blockIdx.x, nz, nd, nn, mu, tau, K8, WT, eps, I, with_boundary);
+                         int with_boundary, int scheme) {
+  formal_body<T>(blockIdx.x, nz, nd, nn, mu, tau, K8, WT, eps, I, with_boundary, scheme);
 }
 
 // one launch over several contexts: block b is context r's block b - off[r]
@@ -189,7 +232,7 @@ __global__ void __launch_bounds__(64) k_formal_grouped(const GFormal* __restrict
     if (off[mid] <= (int)blockIdx.x) lo = mid; else hi = mid;
   }
   const GFormal& a = A[lo];
-  formal_body<float>(blockIdx.x - off[lo], a.nz, a.nd, a.nn, a.mu, a.tau, a.K8, a.WT, a.eps, a.I, 0);
+  formal_body<float>(blockIdx.x - off[lo], a.nz, a.nd, a.nn, a.mu, a.tau, a.K8, a.WT, a.eps, a.I, 0, a.scheme);
 }
 
 int launch_formal_grouped(hipStream_t s, const GFormal* args, const int* off, int n, int blocks) {
@@ -310,11 +353,11 @@ int formal_apply(trap_ctx* ctx, const void* eps, void* I, int with_boundary, int
   if (prec == TRAP_FP64) {
     hipLaunchKernelGGL(k_formal<double>, dim3(ceil_div(rays, 64)), dim3(64), 0, ctx->stream, P.nz, P.nd,
                        P.nn, P.d_mu, P.d_tau, ctx->pre.d_K, P.d_WT, static_cast<const double*>(eps),
-                       static_cast<double*>(I), with_boundary);
+                       static_cast<double*>(I), with_boundary, ctx->formal_scheme);
   } else if (prec == TRAP_FP32) {
     hipLaunchKernelGGL(k_formal<float>, dim3(ceil_div(rays, 64)), dim3(64), 0, ctx->stream, P.nz, P.nd,
                        P.nn, P.d_mu, P.d_tau, ctx->pre.d_K, P.d_WT, static_cast<const float*>(eps),
-                       static_cast<float*>(I), with_boundary);
+                       static_cast<float*>(I), with_boundary, ctx->formal_scheme);
   } else {
     return fail(TRAP_EINVAL, "unknown precision");
   }

@@ -1680,7 +1680,7 @@ int op_apply_batch_f32(trap_ctx** ctxs, int n, const double* const* x, double* c
     std::vector<int> cnt;
     for (int i = 0; i < n; ++i) {
       const Problem& P = ctxs[i]->pb;
-      a.push_back(GFormal{P.nz, P.nd, P.nn, P.d_mu, P.d_tau, ctxs[i]->pre.d_K, P.d_WT,
+      a.push_back(GFormal{P.nz, P.nd, P.nn, ctxs[i]->formal_scheme, P.d_mu, P.d_tau, ctxs[i]->pre.d_K, P.d_WT,
                           static_cast<const float*>(ctxs[i]->wk.opeps[1]), ctxs[i]->wk.v32b});
       cnt.push_back(ceil_div((long long)P.nd * P.nn, 64));
     }

@@ -208,6 +208,7 @@ struct trap_ctx {
   trap::GmresRun* run = nullptr;    // state of the current GMRES solve
   int path = 0;                     // TRAP_PATH_* of trap.h
   int prd_mode = 0;                 // TRAP_PRD_* of trap.h, applied at trap_set_problem
+  int formal_scheme = 0;            // TRAP_FORMAL_* of trap.h
   int max_lds = 64 * 1024;          // device limit of LDS bytes per block
   int n_cu = 256;                   // compute units of the device
   std::vector<trap::DevBuf> bufs;   // every allocation of the current problem
@@ -354,7 +355,7 @@ struct GAngular {
   float* Eb;
 };
 struct GFormal {
-  int nz, nd, nn;
+  int nz, nd, nn, scheme;
   const double *mu, *tau, *K8, *WT;
   const float* eps;
   float* I;

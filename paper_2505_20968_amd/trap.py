@@ -20,6 +20,7 @@ TRAP_FP64 = 0
 TRAP_FP32 = 1
 TRAP_PATH_AUTO, TRAP_PATH_FUSED, TRAP_PATH_CHUNKED = 0, 1, 2
 TRAP_PRD_AD, TRAP_PRD_AA = 0, 1
+TRAP_FORMAL_DELO_LINEAR, TRAP_FORMAL_DELOPAR = 0, 1
 STATUS = {0: "TRAP_OK", -1: "TRAP_EINVAL", -2: "TRAP_ENOMEM", -3: "TRAP_EDEVICE",
           -4: "TRAP_ENOCONV", -5: "TRAP_ESTATE", -6: "TRAP_ENAN"}
 
@@ -28,7 +29,8 @@ EXPORTED = ["trap_create", "trap_destroy", "trap_set_problem", "trap_precompute"
             "trap_gmres_solve", "trap_emergent", "trap_get_info", "trap_footprint",
             "trap_profile", "trap_stage_times", "trap_set_path", "trap_set_prd_mode", "trap_gmres_begin",
             "trap_gmres_step_batch", "trap_gmres_end", "trap_precompute_preconditioner",
-            "trap_apply_preconditioner", "trap_preconditioner_tables", "trap_last_error"]
+            "trap_apply_preconditioner", "trap_preconditioner_tables", "trap_set_formal_scheme",
+            "trap_last_error"]
 STAGES = ["comoving", "contract_fp32", "r3", "angular", "backinterp", "formal", "kernel_rows",
           "contract_fp64"]
 
@@ -110,6 +112,7 @@ def load_library(path: str = LIB_PATH):
     lib.trap_gmres_end.argtypes = [vp, ctypes.POINTER(SolveStats)]
     lib.trap_stage_times.argtypes = [vp, ctypes.POINTER(StageStats)]
     lib.trap_precompute_preconditioner.argtypes = [vp]
+    lib.trap_set_formal_scheme.argtypes = [vp, ctypes.c_int]
     lib.trap_apply_preconditioner.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.c_int]
     lib.trap_preconditioner_tables.argtypes = [vp, _dp, _dp, _dp]
     lib.trap_last_error.restype = ctypes.c_char_p
@@ -220,6 +223,10 @@ class Context:
 
     def precompute(self, store_mask: int = 3):
         _check(self.lib.trap_precompute(self.h, store_mask))
+
+    def set_formal_scheme(self, scheme: int):
+        """TRAP_FORMAL_DELO_LINEAR (0) or TRAP_FORMAL_DELOPAR (1), before precompute."""
+        _check(self.lib.trap_set_formal_scheme(self.h, int(scheme)))
 
     def precompute_preconditioner(self):
         _check(self.lib.trap_precompute_preconditioner(self.h))
