@@ -21,7 +21,9 @@ here is the one App. F builds its local blocks from:
   v = 0 and the angle-averaged kernel, one unit field per column, without
   the App. E factor.
 * Lambda*: the DELO-linear formal solution of Stokes I with the problem's
-  own eta_I and no dichroism or dispersion (K' = 0), no incoming radiation.
+  own eta_I (continuum opacity included) and no dichroism or dispersion
+  (K' = 0), no incoming radiation, whatever formal solver the problem uses.
+  Sigma* leaves the continuum scattering out, as App. F does.
 * App. F: the local blocks P^_z = Id - Lambda_zz Sigma*_z with Lambda_zz the
   diagonal of Lambda* at height z (the response of I at z to the emissivity
   at z on the same ray) are inverted in closed form,
@@ -47,7 +49,7 @@ def comoving_coupling(op) -> np.ndarray:
     unpolarised comoving field, unmagnetised, angle-averaged R_II + R_III."""
     prob = op.prob
     nz, nd, nn = prob.n_z, prob.n_dir, prob.n_nu
-    plain = prob.with_(B=np.zeros_like(prob.B), v=np.zeros_like(prob.v))
+    plain = prob.with_(B=np.zeros_like(prob.B), v=np.zeros_like(prob.v), kappa_c=None, sigma_c=None)
     opts = {k: v for k, v in op.opts.items() if k not in ("aa", "normalize")}
     op0 = T.setup(plain, dict(opts, aa=True, normalize=False))
     Phi = np.zeros((nz, nn, nn))
@@ -142,7 +144,7 @@ def lambda_star(op, eps):
     op_ = T.OracleProblem(**{**op.__dict__, "K": K})
     e4 = np.zeros(eps.shape + (4,))
     e4[..., 0] = eps
-    return T.formal_solve(op_, e4, boundary=False)[..., 0]
+    return T.formal_solve(op_, e4, boundary=False, scheme="linear")[..., 0]
 
 
 def p_apply(op, tab, x):

@@ -40,6 +40,16 @@ App. D Eq. eps_sc_II_exp, in the comoving frame of Sect. 4.1):
   eps^sc_i(Omega, u_n) = sum_{l,l'} S[eps_bar_i(Omega, .; l, l')](u_n + u_b(Omega) + u_{l,l'});
   eps^sc_I *= f (App. E normalisation).
 
+Continuum (App. A), optional: true absorption kappa_c and scattering sigma_c
+(given relative to the field-free line-centre absorption eta_0 of each
+height) add kappa_c + sigma_c to the diagonal of K only; the thermal
+continuum emission is kappa_c W_T (LTE, Stokes I); the scattering is
+coherent in the observer frame with the dipole (Rayleigh) phase matrix,
+  eps^c_i(Omega, nu) = sigma_c sum_{Omega'} w_{Omega'} sum_j R_ij(Omega, Omega') I_j(Omega', nu),
+  R_ij = (3/4) Re Tr(Acart_i(Omega) Acart_j(Omega')),
+which is the K = 0, 1, 2 multipole sum of App. A with unit weights; it joins
+the normalised Sigma (the App. E factor f is computed from the line alone).
+
 Formal solution (Sect. 3): trapezoidal ray optical depth
   dtau = (eta_I/eta_0 (z_k) + eta_I/eta_0 (z_k+1))/2 |dtau_line| / |mu|,
 eta_0 = field-free line-centre value, and DELO-linear steps
@@ -93,6 +103,8 @@ class OracleProblem:
     M: dict = field(default_factory=dict)
     r3: dict = field(default_factory=dict)
     f: np.ndarray = None      # [z, Omega, n]
+    sigma_c: np.ndarray = None  # [z, n] continuum scattering coefficient (K units)
+    cont: np.ndarray = None     # [z, n] continuum opacity kappa_c + sigma_c on the diagonal of K
 
 
 def _acart(ang):
@@ -168,9 +180,19 @@ def setup(prob, opts=None) -> OracleProblem:
         t2 = np.einsum("kab,onbc,jca->onjk", A_STOKES, Ndag, A_STOKES)
         K[z] = 0.25 * (t1 + t2).real
     eps_th = (prob.eps * prob.W_T)[:, None, None, None] * K[:, :, :, 0, :]
+    kc = np.zeros((nz, nn))
+    sc = np.zeros((nz, nn))
+    if getattr(prob, "kappa_c", None) is not None:
+        kc = np.asarray(prob.kappa_c, float) * eta0[:, None]
+    if getattr(prob, "sigma_c", None) is not None:
+        sc = np.asarray(prob.sigma_c, float) * eta0[:, None]
+    for s in range(4):
+        K[:, :, :, s, s] += (kc + sc)[:, None, :]
+    eps_th[..., 0] += (kc * prob.W_T[:, None])[:, None, :]
     op = OracleProblem(prob=prob, ang=ang, theta=theta, pair=pair, basis=basis, lam=lam,
                        dnuD=dnuD, ub=ub, atoms=atoms, s_ul=s_ul, s_ll=s_ll, alpha=alpha,
-                       beta=beta, K=K, eta0=eta0, eps_th=eps_th, Acart=Acart, opts=opts)
+                       beta=beta, K=K, eta0=eta0, eps_th=eps_th, Acart=Acart, opts=opts,
+                       sigma_c=sc, cont=kc + sc)
     if opts["normalize"]:
         op.f = normalization(op)
     else:
@@ -262,17 +284,38 @@ def sigma_height(op, z, Iz, normalize=True):
                 out[o] += op.basis.interpolate(eps_bar[l, lp, o], y, axis=0)
     if normalize:
         out[..., 0] *= op.f[z]
+        if op.sigma_c is not None and np.any(op.sigma_c[z] != 0.0):
+            out += continuum_scattering(op, z, Iz)
     return out
 
 
+def rayleigh_matrix(Acart, o, x):
+    """R[i, j] = (3/4) Re Tr(Acart_i(Omega_o) Acart_j(Omega_x)): the dipole
+    scattering phase matrix from direction x into direction o."""
+    return 0.75 * np.einsum("iab,jba->ij", Acart[o], Acart[x]).real
+
+
+def continuum_scattering(op, z, Iz):
+    """Coherent continuum scattering at height z (App. A) for the field Iz[Omega, n, 4]."""
+    nd = op.prob.n_dir
+    w = op.ang["w"]
+    out = np.zeros_like(Iz)
+    for o in range(nd):
+        for x in range(nd):
+            out[o] += w[x] * (Iz[x] @ rayleigh_matrix(op.Acart, o, x).T)
+    return op.sigma_c[z][None, :, None] * out
+
+
 def normalization_height(op, z):
-    """App. E at height z: f = (1 - eps) W_T eta_I / eps^sc_I[I = (W_T, 0, 0, 0)], Stokes I only."""
+    """App. E at height z: f = (1 - eps) W_T eta_I / eps^sc_I[I = (W_T, 0, 0, 0)], Stokes I only,
+    with the line's own eta_I (the continuum takes no part in it)."""
     prob = op.prob
     Iz = np.zeros((prob.n_dir, prob.n_nu, 4))
     Iz[..., 0] = prob.W_T[z]
     num = sigma_height(op, z, Iz, normalize=False)[..., 0]
-    ref = (1.0 - prob.eps[z]) * prob.W_T[z] * op.K[z, :, :, 0, 0]
-    return ref / num
+    ref = (1.0 - prob.eps[z]) * prob.W_T[z] * (op.K[z, :, :, 0, 0] - op.cont[z][None, :])
+    # no line scattering (eps = 1): nothing to normalise
+    return np.where(num != 0.0, ref / np.where(num != 0.0, num, 1.0), 1.0)
 
 
 def normalization(op):

@@ -614,3 +614,57 @@ def test_delopar_exact_for_milne_eddington():
     I = T.formal_solve(op, eps, boundary=True, I_bottom=Iex[0], scheme="delopar")
     up = mu > 0
     assert np.abs(I[:, up] - Iex[:, up]).max() < 1e-12
+
+
+def test_rayleigh_phase_matrix_closed_forms():
+    """The continuum scattering matrix R = (3/4) Re Tr(Acart_i Acart_j) is the
+    dipole (Rayleigh) phase matrix: R_II = 3/4 (1 + cos^2 Theta), linear
+    polarisation sqrt(R_QI^2 + R_UI^2) = 3/4 sin^2 Theta, no circular
+    polarisation from linear and back, R_VV = 3/2 cos Theta, and an isotropic
+    unpolarised field scatters into itself (sum_x w_x R_II = 1)."""
+    ang = angular_grid(6, 5)
+    acart = T._acart(ang)
+    dirs, w = ang["dirs"], ang["w"]
+    for o in range(dirs.shape[0]):
+        tot = 0.0
+        for x in range(dirs.shape[0]):
+            R = T.rayleigh_matrix(acart, o, x)
+            c = float(dirs[o] @ dirs[x])
+            assert abs(R[0, 0] - 0.75 * (1 + c * c)) < 1e-14
+            assert abs(np.hypot(R[1, 0], R[2, 0]) - 0.75 * (1 - c * c)) < 1e-14
+            assert abs(R[3, 0]) < 1e-14 and abs(R[0, 3]) < 1e-14
+            assert abs(R[3, 1]) < 1e-14 and abs(R[3, 2]) < 1e-14
+            assert abs(R[3, 3] - 1.5 * c) < 1e-14
+            tot += w[x] * R[0, 0]
+        assert abs(tot - 1.0) < 1e-14
+
+
+def test_continuum_flat_field():
+    """With a continuum, the normalised Sigma of the flat field (W_T, 0, 0, 0)
+    is the line's (1 - eps) W_T eta (App. E) plus sigma_c W_T on Stokes I: the
+    continuum scatters an isotropic unpolarised field into itself."""
+    p = tiny(n_z=3, n_nu=13, n_mu=4, n_chi=4, B=(0.0, 0.0, 0.0), a=1e-2, eps=3e-2, cont=(0.2, 0.4))
+    op = T.setup(p)
+    e = T.sigma_apply(op, _flat(p))
+    kc = p.kappa_c * op.eta0[:, None]
+    sc = p.sigma_c * op.eta0[:, None]
+    eta_line = op.K[:, :, :, 0, :].copy()
+    eta_line[..., 0] -= (kc + sc)[:, None, :]
+    ref = ((1 - p.eps) * p.W_T)[:, None, None, None] * eta_line
+    ref[..., 0] += (sc * p.W_T[:, None])[:, None, :]
+    assert np.abs(e - ref).max() < 1e-12 * np.abs(ref).max()
+
+
+def test_continuum_lte_column_keeps_the_planck_value():
+    """A pure-absorption line (eps = 1) with continuum absorption and a
+    constant W_T: the emissivity W_T (eta_line + kappa_c e_0) is K W_T e_0, so
+    the exact solution on upward rays is I = W_T e_0, which the right-hand side
+    (the formal solution of the thermal emissivity with the bottom boundary)
+    reproduces for every field geometry."""
+    p = tiny(n_z=7, n_nu=11, n_mu=4, n_chi=3, B=(300.0, 0.7, 1.1), a=1e-2, eps=1.0, cont=(0.5, 0.0))
+    op = T.setup(p)
+    b = T.rhs(op)
+    up = op.ang["mu"] > 0
+    ref = np.zeros_like(b[:, up])
+    ref[..., 0] = p.W_T[:, None, None]
+    assert np.abs(b[:, up] - ref).max() < 1e-12

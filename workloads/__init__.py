@@ -83,6 +83,11 @@ class Problem:
     v: np.ndarray              # [n_z, 3] bulk velocity, km/s, cartesian, z up
     B: np.ndarray              # [n_z, 3] (|B| in G, theta_B rad, chi_B rad)
     z_km: Optional[np.ndarray] = None
+    # continuum (App. A): true absorption and scattering coefficients per height
+    # and frequency, [n_z, n_nu], in units of the height's field-free
+    # line-centre absorption coefficient; None = no continuum
+    kappa_c: Optional[np.ndarray] = None
+    sigma_c: Optional[np.ndarray] = None
     T_ref: float = 6000.0      # temperature that defines dnu_D_ref
     tol: float = 1e-8
     meta: dict = field(default_factory=dict)
@@ -204,9 +209,12 @@ def cfg4(seed: int = 4, n_z: int = 100) -> Problem:
 def tiny(n_z: int = 6, n_nu: int = 13, x_max: float = 6.0, n_mu: int = 2, n_chi: int = 4,
          atom: Optional[Atom] = None, B=(20.0, np.pi / 2, 0.0), v_z: float = 0.0,
          a: float = 1e-2, eps: float = 1e-2, tau_top: float = 1e-3, tau_bot: float = 1e2,
-         seed: Optional[int] = None, T: float = 6000.0) -> Problem:
+         seed: Optional[int] = None, T: float = 6000.0, cont: Optional[tuple] = None) -> Problem:
     """Small problems for oracle pins and GPU parity.  With ``seed`` set, the
-    damping, destruction probability, field and velocity vary with height."""
+    damping, destruction probability, field and velocity vary with height.
+    ``cont = (kappa, sigma)`` adds a continuum whose coefficients (relative to
+    the line-centre absorption) change linearly by 25 % across the grid
+    (kappa rising to the red end, sigma to the blue end) and vary with height."""
     atom = atom or two_level_atom()
     tau = np.logspace(np.log10(tau_bot), np.log10(tau_top), n_z)
     Tz = np.full(n_z, float(T))
@@ -227,10 +235,18 @@ def tiny(n_z: int = 6, n_nu: int = 13, x_max: float = 6.0, n_mu: int = 2, n_chi:
         v[:, 2] = v_z * np.sin(np.linspace(0.0, 2.0 * np.pi, n_z) + rng.uniform(0, 6.28))
         W_T = np.exp(rng.uniform(-0.2, 0.2, n_z))
         W_T /= W_T[0]
+    kc = sc = None
+    if cont is not None:
+        x = np.linspace(-x_max, x_max, n_nu)
+        tilt = 1.0 + 0.25 * (x - x[0]) / (x[-1] - x[0])
+        hz = np.exp(np.linspace(-0.3, 0.3, n_z)) if seed is None else np.exp(
+            np.random.Generator(np.random.PCG64(seed + 1)).uniform(-0.5, 0.5, n_z))
+        kc = cont[0] * hz[:, None] * tilt[None, :]
+        sc = cont[1] * hz[::-1, None] * tilt[None, ::-1]
     return Problem(name=f"tiny_{atom.kind}", atom=atom,
                    x=np.linspace(-x_max, x_max, n_nu), n_mu=n_mu, n_chi=n_chi,
                    tau_line=tau, T=Tz, xi=np.zeros(n_z), a=az, eps=epsz, W_T=W_T,
-                   v=v, B=Bz, meta={"seed": seed})
+                   v=v, B=Bz, kappa_c=kc, sigma_c=sc, meta={"seed": seed})
 
 
 def serving_stream(n_requests: int = 1024, seed: int = 5, rate_hz: float = 10.0,
