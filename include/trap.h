@@ -85,7 +85,14 @@ typedef struct {
  *    > 0.  T (K), xi (km/s), a (damping), eps (photon destruction), W_T (Wien
  *    function) have n_z entries; v is [n_z][3] km/s cartesian (z up); B is
  *    [n_z][3] = (|B| in G, theta_B, chi_B) in the atmospheric frame.
- * n_mu (even, >= 2) Gauss-Legendre mu nodes in total, n_chi >= 1 azimuths. */
+ * n_mu (even, >= 2) Gauss-Legendre mu nodes in total, n_chi >= 1 azimuths.
+ * kappa_c, sigma_c (optional, NULL = none; either may be NULL alone):
+ *    continuum true absorption and scattering coefficients (App. A),
+ *    [n_z][n_nu], >= 0, in units of the height's field-free line-centre
+ *    absorption coefficient.  They add kappa_c + sigma_c to the diagonal of
+ *    the propagation matrix, kappa_c W_T to the thermal emissivity of Stokes I
+ *    (LTE) and coherent dipole scattering sigma_c sum_j R_ij I_j (observer
+ *    frame, R the Rayleigh phase matrix) to the normalised Sigma. */
 typedef struct {
   int n_z, n_nu, n_mu, n_chi;
   const double* x;
@@ -98,6 +105,8 @@ typedef struct {
   const double* v;
   const double* B;
   double T_ref;
+  const double* kappa_c;
+  const double* sigma_c;
 } trap_problem_desc;
 
 /* Sizes of the discrete problem (filled by trap_get_info). */

@@ -668,6 +668,12 @@ size_t estimate_bytes(const trap_atom_desc* atom, const trap_problem_desc* pd, i
     item(nz * nu * nu * 16);                             // alpha
     item(nz * nu * nu * 16);                             // beta - alpha
     item(nz * nt * nd * 4 * 8);                          // g
+    if (pd->kappa_c || pd->sigma_c) {
+      item(nz * nn * 8);                                 // kappa_c
+      item(nz * nn * 8);                                 // sigma_c
+      item(nd * 3 * 8);                                  // polarisation axes e_a
+      item(nd * 3 * 8);                                  //   and e_b
+    }
     add(up.total);
   }
   // precompute scratch (factor tables, row stores of one height chunk)
@@ -905,6 +911,18 @@ int build_problem(trap_ctx* ctx, const trap_atom_desc* at, const trap_problem_de
       if (!std::isfinite(pd->v[3 * z + k]) || !std::isfinite(pd->B[3 * z + k]))
         return fail(TRAP_EINVAL, "velocity/field not finite");
   }
+  // ---- continuum
+  P.has_cont = pd->kappa_c || pd->sigma_c;
+  if (P.has_cont) {
+    P.kc.assign((size_t)nz * nn, 0.0);
+    P.sc.assign((size_t)nz * nn, 0.0);
+    for (size_t i = 0; i < (size_t)nz * nn; ++i) {
+      if (pd->kappa_c) P.kc[i] = pd->kappa_c[i];
+      if (pd->sigma_c) P.sc[i] = pd->sigma_c[i];
+      if (!(P.kc[i] >= 0.0) || !(P.sc[i] >= 0.0) || !std::isfinite(P.kc[i]) || !std::isfinite(P.sc[i]))
+        return fail(TRAP_EINVAL, "continuum coefficients must be finite and >= 0");
+    }
+  }
   // ---- per-height scalars
   const double nu0 = kC / (at->lambda0_A * 1e-8);
   const double mass = at->mass_amu * kAMU;
@@ -1038,6 +1056,12 @@ int build_problem(trap_ctx* ctx, const trap_atom_desc* at, const trap_problem_de
   up.add(&P.d_alpha, alpha);
   up.add(&P.d_bma, bma);
   up.add(reinterpret_cast<void**>(&P.d_g), g, n_g * sizeof(double));
+  if (P.has_cont) {
+    up.add(&P.d_kc, P.kc);
+    up.add(&P.d_sc, P.sc);
+    up.add(&P.d_ea, ea);
+    up.add(&P.d_eb, eb);
+  }
   TRAP_TRY(up.commit(ctx));
   return TRAP_OK;
 }

@@ -60,7 +60,8 @@ __global__ void k_profiles(int nz, int nd, int nn, int nt, const double* __restr
                            const double* __restrict__ ub, const double* __restrict__ st,
                            const double* __restrict__ g, const double* __restrict__ eta0,
                            const double* __restrict__ eps, const double* __restrict__ WT,
-                           double c_abs, double* __restrict__ K8, double* __restrict__ epsth) {
+                           double c_abs, const double* __restrict__ kc, const double* __restrict__ scc,
+                           double* __restrict__ K8, double* __restrict__ epsth) {
   const long long id = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   const long long total = (long long)nz * nd * nn;
   if (id >= total) return;
@@ -82,7 +83,11 @@ __global__ void k_profiles(int nz, int nd, int nn, int nt, const double* __restr
     eta[j] *= sc;
     rho[j] *= sc;
   }
-  const double inv = 1.0 / eta[0];
+  // continuum opacity on the diagonal (App. A), relative to the line centre
+  const double kz = kc ? kc[(long long)z * nn + n] * eta0[z] : 0.0;
+  const double sz = scc ? scc[(long long)z * nn + n] * eta0[z] : 0.0;
+  const double etot = eta[0] + kz + sz;
+  const double inv = 1.0 / etot;
   double* k = K8 + id * 8;
   k[0] = eta[1] * inv;
   k[1] = eta[2] * inv;
@@ -91,9 +96,10 @@ __global__ void k_profiles(int nz, int nd, int nn, int nt, const double* __restr
   k[4] = rho[2] * inv;
   k[5] = rho[3] * inv;
   k[6] = inv;
-  k[7] = eta[0] / eta0[z];
+  k[7] = etot / eta0[z];
   const double th = eps[z] * WT[z];
   for (int j = 0; j < 4; ++j) epsth[id * 4 + j] = th * eta[j];
+  epsth[id * 4] += kz * WT[z];          // LTE continuum emission
 }
 
 // ------------------------------------------------------------------ panel integration helper
@@ -742,14 +748,21 @@ __global__ void k_flat_field(long long total, int nd, int nn, const double* __re
   v[3] = 0.0;
 }
 
+// f = (1 - eps) W_T eta_I / num with the line's own eta_I (the continuum takes
+// no part in the App. E factor); 1 where the line scatters nothing (eps = 1)
 __global__ void k_norm_factor(long long total, int nd, int nn, const double* __restrict__ eps,
                               const double* __restrict__ WT, const double* __restrict__ K8,
-                              const double* __restrict__ num, double* __restrict__ f) {
+                              const double* __restrict__ num, const double* __restrict__ kc,
+                              const double* __restrict__ scc, const double* __restrict__ eta0,
+                              double* __restrict__ f) {
   const long long id = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   if (id >= total) return;
   const int z = id / ((long long)nd * nn);
-  const double etaI = 1.0 / K8[id * 8 + 6];
-  f[id] = (1.0 - eps[z]) * WT[z] * etaI / num[id * 4];
+  const long long zn = (long long)z * nn + id % nn;
+  const double cont = ((kc ? kc[zn] : 0.0) + (scc ? scc[zn] : 0.0)) * eta0[z];
+  const double etaI = 1.0 / K8[id * 8 + 6] - cont;
+  const double d = num[id * 4];
+  f[id] = d != 0.0 ? (1.0 - eps[z]) * WT[z] * etaI / d : 1.0;
 }
 
 // ------------------------------------------------------------------ driver
@@ -878,8 +891,8 @@ int run_precompute(trap_ctx* ctx, int store_mask) {
     TRAP_TRY(dalloc_t(ctx, &C.d_b, npt * 4));
   }
   hipLaunchKernelGGL(k_profiles, dim3(ceil_div(npt, 256)), dim3(256), 0, s, nz, nd, nn, nt, P.d_x,
-                     P.d_lam, P.d_a, P.d_ub, P.d_st, P.d_g, P.d_eta0, P.d_eps, P.d_WT, P.c_abs, C.d_K,
-                     C.d_epsth);
+                     P.d_lam, P.d_a, P.d_ub, P.d_st, P.d_g, P.d_eta0, P.d_eps, P.d_WT, P.c_abs, P.d_kc, P.d_sc,
+                     C.d_K, C.d_epsth);
   TRAP_HIP(hipGetLastError());
   const size_t kelems = (size_t)nz * nth * nt * 2 * nn * P.ldm;
   const int mask = store_mask | 1;     // FP64 kernels always exist (residual, f, b)
@@ -961,7 +974,7 @@ int run_precompute(trap_ctx* ctx, int store_mask) {
   TRAP_HIP(hipGetLastError());
   TRAP_TRY(sigma_apply(ctx, flat, num, TRAP_FP64, 0, 0));
   hipLaunchKernelGGL(k_norm_factor, dim3(ceil_div(npt, 256)), dim3(256), 0, s, npt, nd, nn, P.d_eps,
-                     P.d_WT, C.d_K, num, C.d_f);
+                     P.d_WT, C.d_K, num, P.d_kc, P.d_sc, P.d_eta0, C.d_f);
   TRAP_HIP(hipGetLastError());
   // right-hand side b = Lambda eps_th + t
   TRAP_TRY(formal_apply(ctx, C.d_epsth, C.d_b, 1, TRAP_FP64));

@@ -1244,7 +1244,94 @@ static int sigma_apply_t(trap_ctx* ctx, const T* I, T* eps, int prec, int add_th
   return TRAP_OK;
 }
 
+// ------------------------------------------------------------------ continuum scattering (App. A)
+// Coherent dipole scattering in the observer frame: for height z and
+// frequency n, M = sum_x w_x sum_j I_j(x) Acart_j(x) (a 3 x 3 complex tensor,
+// Acart_j = sum_cd (A_j)_cd e_c e_d^T on the direction's axes e_a, e_b), then
+//   eps_i(o) += (3/4) sigma_c Re Tr(Acart_i(o) M),
+// the Rayleigh phase matrix summed over incoming directions.  One 64-lane
+// block per (z, n): lanes over directions, M reduced across the wave in FP64.
+__device__ inline void acart_entry(int j, const double* ea, const double* eb, int r, int c, double& re, double& im) {
+  const double aa = ea[r] * ea[c], bb = eb[r] * eb[c], ab = ea[r] * eb[c], ba = eb[r] * ea[c];
+  switch (j) {
+    case 0: re = aa + bb; im = 0.0; break;
+    case 1: re = aa - bb; im = 0.0; break;
+    case 2: re = ab + ba; im = 0.0; break;
+    default: re = 0.0; im = ab - ba; break;      // A_V = [[0, i], [-i, 0]]
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(64) k_cont_scatter(int nz, int nd, int nn, const double* __restrict__ ea,
+                                                     const double* __restrict__ eb, const double* __restrict__ w,
+                                                     const double* __restrict__ sc, const double* __restrict__ eta0,
+                                                     const T* __restrict__ I, T* __restrict__ eps) {
+  __shared__ double Mr[9], Mi[9];
+  const int z = blockIdx.x / nn, n = blockIdx.x % nn, lane = threadIdx.x;
+  double mr[9], mi[9];
+#pragma unroll
+  for (int e = 0; e < 9; ++e) mr[e] = mi[e] = 0.0;
+  for (int x = lane; x < nd; x += 64) {
+    const T* ix = I + (((size_t)z * nd + x) * nn + n) * 4;
+    const double* a = ea + 3 * x;
+    const double* b = eb + 3 * x;
+    for (int j = 0; j < 4; ++j) {
+      const double v = w[x] * (double)ix[j];
+#pragma unroll
+      for (int e = 0; e < 9; ++e) {
+        double re, im;
+        acart_entry(j, a, b, e / 3, e % 3, re, im);
+        mr[e] += v * re;
+        mi[e] += v * im;
+      }
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < 9; ++e)
+    for (int off = 32; off > 0; off >>= 1) {
+      mr[e] += __shfl_xor(mr[e], off, 64);
+      mi[e] += __shfl_xor(mi[e], off, 64);
+    }
+  if (lane == 0)
+    for (int e = 0; e < 9; ++e) {
+      Mr[e] = mr[e];
+      Mi[e] = mi[e];
+    }
+  __syncthreads();
+  const double s = 0.75 * sc[(size_t)z * nn + n] * eta0[z];
+  for (int o = lane; o < nd; o += 64) {
+    T* eo = eps + (((size_t)z * nd + o) * nn + n) * 4;
+    const double* a = ea + 3 * o;
+    const double* b = eb + 3 * o;
+    for (int i = 0; i < 4; ++i) {
+      // Re Tr(X M) = sum_rc Re(X_rc M_cr)
+      double t = 0.0;
+      for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) {
+          double xr, xi;
+          acart_entry(i, a, b, r, c, xr, xi);
+          t += xr * Mr[c * 3 + r] - xi * Mi[c * 3 + r];
+        }
+      eo[i] = (T)((double)eo[i] + s * t);
+    }
+  }
+}
+
 int sigma_apply(trap_ctx* ctx, const void* I, void* eps, int prec, int add_thermal, int normalize) {
+  TRAP_TRY(sigma_apply_line(ctx, I, eps, prec, add_thermal, normalize));
+  Problem& P = ctx->pb;
+  if (!normalize || !P.has_cont || !P.d_sc) return TRAP_OK;
+  if (prec == TRAP_FP64)
+    hipLaunchKernelGGL(k_cont_scatter<double>, dim3(P.nz * P.nn), dim3(64), 0, ctx->stream, P.nz, P.nd, P.nn, P.d_ea,
+                       P.d_eb, P.d_w, P.d_sc, P.d_eta0, static_cast<const double*>(I), static_cast<double*>(eps));
+  else
+    hipLaunchKernelGGL(k_cont_scatter<float>, dim3(P.nz * P.nn), dim3(64), 0, ctx->stream, P.nz, P.nd, P.nn, P.d_ea,
+                       P.d_eb, P.d_w, P.d_sc, P.d_eta0, static_cast<const float*>(I), static_cast<float*>(eps));
+  TRAP_HIP(hipGetLastError());
+  return TRAP_OK;
+}
+
+int sigma_apply_line(trap_ctx* ctx, const void* I, void* eps, int prec, int add_thermal, int normalize) {
   if (!ctx->has_problem) return fail(TRAP_ESTATE, "no problem loaded");
   if (!ctx->pre.done) return fail(TRAP_ESTATE, "precompute not run");
   if (prec != TRAP_FP64 && prec != TRAP_FP32) return fail(TRAP_EINVAL, "unknown precision");
@@ -1504,6 +1591,8 @@ int sigma_batch_ready(trap_ctx* ctx) {
   Work& K = ctx->wk;
   if (!ctx->has_problem || !ctx->pre.done || !ctx->pre.d_M32 || !ctx->pre.d_cf32) return 0;
   if (ctx->path == TRAP_PATH_FUSED || ctx->prof.on) return 0;
+  // the shared launches carry no continuum term
+  if (P.has_cont) return 0;
   // a context whose Sigma runs in several height chunks costs several small
   // applies: in lockstep with the others it would hold every shared apply of
   // the batch, so it applies on its own stream and overlaps the shared work

@@ -106,6 +106,11 @@ struct Problem {
   double2 *d_E = nullptr, *d_A = nullptr;  // see above
   double2 *d_alpha = nullptr, *d_bma = nullptr; // [nz][nu][nu]
   double *d_g = nullptr;                   // [nz][nt][nd][4] geometric factors of K
+  // continuum (App. A): kappa_c, sigma_c [nz][nn] relative to the line-centre
+  // absorption, and the polarisation axes of each direction for its scattering
+  bool has_cont = false;
+  std::vector<double> kc, sc;
+  double *d_kc = nullptr, *d_sc = nullptr, *d_ea = nullptr, *d_eb = nullptr;
   // physics-based preconditioner (unmagnetised, unpolarised, angle-averaged,
   // K = Q = 0): transitions of the zero-field atom grouped by frequency
   // (pc_nk classes, energy differences pc_dE in Hz); per height the weights
@@ -296,7 +301,10 @@ PrecompLayout precomp_layout(int nz, int nn, int ldm, int nt, int nthr, bool aa,
 int run_precompute(trap_ctx* ctx, int store_mask);
 
 // applies (sigma.hip, formal.hip)
+// (normalize != 0: the App. E factor on the line part and, with a continuum,
+// its coherent scattering; sigma_apply_line is the line part alone)
 int sigma_apply(trap_ctx* ctx, const void* I, void* eps, int prec, int add_thermal, int normalize);
+int sigma_apply_line(trap_ctx* ctx, const void* I, void* eps, int prec, int add_thermal, int normalize);
 int formal_apply(trap_ctx* ctx, const void* eps, void* I, int with_boundary, int prec);
 int operator_apply(trap_ctx* ctx, const void* x, void* y, int prec);
 int ensure_work(trap_ctx* ctx, int prec);

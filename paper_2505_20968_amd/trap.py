@@ -48,7 +48,7 @@ class ProblemDesc(ctypes.Structure):
     _fields_ = [("n_z", ctypes.c_int), ("n_nu", ctypes.c_int), ("n_mu", ctypes.c_int),
                 ("n_chi", ctypes.c_int), ("x", _dp), ("tau_line", _dp), ("T", _dp), ("xi", _dp),
                 ("a", _dp), ("eps", _dp), ("W_T", _dp), ("v", _dp), ("B", _dp),
-                ("T_ref", ctypes.c_double)]
+                ("T_ref", ctypes.c_double), ("kappa_c", _dp), ("sigma_c", _dp)]
 
 
 class Info(ctypes.Structure):
@@ -144,6 +144,13 @@ def _atom_desc(atom) -> AtomDesc:
 def _problem_desc(prob):
     keep = {k: np.ascontiguousarray(getattr(prob, k), dtype=np.float64)
             for k in ("x", "tau_line", "T", "xi", "a", "eps", "W_T", "v", "B")}
+    for k in ("kappa_c", "sigma_c"):
+        v = getattr(prob, k, None)
+        if v is not None:
+            v = np.ascontiguousarray(v, dtype=np.float64)
+            if v.shape != (prob.n_z, prob.n_nu):
+                raise ValueError(f"{k} must have shape (n_z, n_nu)")
+            keep[k] = v
     ptr = {k: v.ctypes.data_as(_dp) for k, v in keep.items()}
     d = ProblemDesc(n_z=prob.n_z, n_nu=prob.n_nu, n_mu=prob.n_mu, n_chi=prob.n_chi,
                     T_ref=float(prob.T_ref), **ptr)
