@@ -2,6 +2,8 @@
 // context's allocation bookkeeping and the operator apply y = x - Lambda Sigma x.
 #include <cmath>
 #include <cstring>
+#include <mutex>
+#include <set>
 #include <string>
 
 #include "trap_internal.h"
@@ -19,6 +21,37 @@ int fail(int code, const std::string& msg) {
   return code;
 }
 
+// Device memory comes from the device's stream-ordered pool, allocated and
+// returned on the context's stream: a freed buffer stays in the pool (its
+// release threshold is raised once per device) and serves the next context
+// without a device-wide synchronisation or a new mapping.  Devices whose
+// runtime has no pool take hipMalloc / hipFree.
+namespace {
+std::mutex g_pool_mu;
+std::set<int> g_pool_ready, g_pool_absent;
+}  // namespace
+
+void device_pool_setup(int device) {
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  if (g_pool_ready.count(device) || g_pool_absent.count(device)) return;
+  hipMemPool_t pool;
+  int supported = 0;
+  if (hipDeviceGetAttribute(&supported, hipDeviceAttributeMemoryPoolsSupported, device) != hipSuccess ||
+      !supported || hipDeviceGetDefaultMemPool(&pool, device) != hipSuccess) {
+    (void)hipGetLastError();
+    g_pool_absent.insert(device);
+    return;
+  }
+  uint64_t keep = UINT64_MAX;
+  if (hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep) != hipSuccess) (void)hipGetLastError();
+  g_pool_ready.insert(device);
+}
+
+static bool device_pooled(int device) {
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  return g_pool_ready.count(device) > 0;
+}
+
 int dalloc(trap_ctx* ctx, void** p, size_t bytes) {
   void* q = nullptr;
   if (bytes == 0) bytes = 16;
@@ -30,23 +63,27 @@ int dalloc(trap_ctx* ctx, void** p, size_t bytes) {
       *p = ctx->bufs.back().p;
       return TRAP_OK;
     }
-  hipError_t e = hipMalloc(&q, bytes);
+  const bool pooled = device_pooled(ctx->device);
+  hipError_t e = pooled ? hipMallocAsync(&q, bytes, ctx->stream) : hipMalloc(&q, bytes);
   if (e != hipSuccess) {
     (void)hipGetLastError();
     return fail(TRAP_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed: " +
                                  hipGetErrorString(e));
   }
-  ctx->bufs.push_back(DevBuf{q, bytes});
+  ctx->bufs.push_back(DevBuf{q, bytes, pooled});
   *p = q;
   return TRAP_OK;
 }
 
-// Releasing device memory waits for the whole device, so a context keeps the
-// allocations of its previous problem and hands them out again by exact size
-// (same-shaped problems in a row allocate and free nothing); spares not
-// reused by the next problem are freed when that one is replaced.
+// A context keeps the allocations of its previous problem and hands them out
+// again by exact size (same-shaped problems in a row allocate and free
+// nothing); spares not reused by the next problem go back when that one is
+// replaced, in stream order after the context's work.
 void release_spare(trap_ctx* ctx) {
-  for (auto& b : ctx->spare) (void)hipFree(b.p);
+  for (auto& b : ctx->spare) {
+    if (b.pooled) (void)hipFreeAsync(b.p, ctx->stream);
+    else (void)hipFree(b.p);
+  }
   ctx->spare.clear();
 }
 
@@ -164,6 +201,7 @@ int trap_create(trap_ctx** out, int device, void* stream) {
   else
     (void)hipGetLastError();
   batch_arena_acquire(device);
+  device_pool_setup(device);
   *out = ctx;
   return TRAP_OK;
 }

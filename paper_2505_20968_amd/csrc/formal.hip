@@ -131,7 +131,8 @@ __device__ inline void parabolic_weights(double m, double p, double& wM, double&
   wP = (E2 - m * E1) / (p * (m + p));
 }
 
-template <typename T>
+// PAR: 0 = DELO-linear only, 1 = DELOPAR only, -1 = the scheme argument decides
+template <typename T, int PAR>
 __device__ __forceinline__ void formal_body(int bx, int nz, int nd, int nn, const double* __restrict__ mu,
                                             const double* __restrict__ tau, const double* __restrict__ K8,
                                             const double* __restrict__ WT, const T* __restrict__ eps,
@@ -194,7 +195,8 @@ __device__ __forceinline__ void formal_body(int bx, int nz, int nd, int nn, cons
     delo_weights<T>(x, pu, pc, ex);
     T kv[4], b[4];
     kprime_mul<T>(ku, Icur, kv);
-    if (scheme == TRAP_FORMAL_DELOPAR && step + 1 < nz) {
+    const bool par = PAR == 1 || (PAR < 0 && scheme == TRAP_FORMAL_DELOPAR);
+    if (PAR != 0 && par && step + 1 < nz) {
       // the downwind point's data are the ones just prefetched
       const double xd = 0.5 * (kr[7] + kn[7]) * fabs(tzc - tn) / fabs(m);
       double wM, wO, wP;
@@ -219,12 +221,12 @@ __device__ __forceinline__ void formal_body(int bx, int nz, int nd, int nn, cons
   }
 }
 
-template <typename T>
+template <typename T, int PAR>
 __global__ void __launch_bounds__(64) k_formal(int nz, int nd, int nn, const double* __restrict__ mu,
                          const double* __restrict__ tau, const double* __restrict__ K8,
                          const double* __restrict__ WT, const T* __restrict__ eps, T* __restrict__ I,
-                         int with_boundary, int scheme) {
-  formal_body<T>(blockIdx.x, nz, nd, nn, mu, tau, K8, WT, eps, I, with_boundary, scheme);
+                         int with_boundary) {
+  formal_body<T, PAR>(blockIdx.x, nz, nd, nn, mu, tau, K8, WT, eps, I, with_boundary, PAR);
 }
 
 // one launch over several contexts: block b is context r's block b - off[r]
@@ -235,7 +237,7 @@ __global__ void __launch_bounds__(64) k_formal_grouped(const GFormal* __restrict
     if (off[mid] <= (int)blockIdx.x) lo = mid; else hi = mid;
   }
   const GFormal& a = A[lo];
-  formal_body<float>(blockIdx.x - off[lo], a.nz, a.nd, a.nn, a.mu, a.tau, a.K8, a.WT, a.eps, a.I, 0, a.scheme);
+  formal_body<float, -1>(blockIdx.x - off[lo], a.nz, a.nd, a.nn, a.mu, a.tau, a.K8, a.WT, a.eps, a.I, 0, a.scheme);
 }
 
 int launch_formal_grouped(hipStream_t s, const GFormal* args, const int* off, int n, int blocks) {
@@ -296,12 +298,12 @@ int launch_pc_local_lambda(trap_ctx* ctx) {
 // previous step, so the loads of kSweepAhead steps are issued together.
 constexpr int kSweepAhead = 4;
 
-__global__ void __launch_bounds__(64) k_pc_lambda_sweep(int nz, int nd, int nn, const double* __restrict__ mu,
-                                                        const double2* __restrict__ F, const double* __restrict__ L,
-                                                        const double* __restrict__ e, const double* __restrict__ y,
-                                                        int y_stride, const double* __restrict__ x,
-                                                        double* __restrict__ res) {
-  const int id = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void pc_lambda_sweep_body(int bx, int nz, int nd, int nn, const double* __restrict__ mu,
+                                                     const double2* __restrict__ F, const double* __restrict__ L,
+                                                     const double* __restrict__ e, const double* __restrict__ y,
+                                                     int y_stride, const double* __restrict__ x,
+                                                     double* __restrict__ res) {
+  const int id = bx * blockDim.x + threadIdx.x;
   if (id >= nd * nn) return;
   const int o = id / nn;
   const bool up = mu[o] > 0.0;
@@ -336,6 +338,32 @@ __global__ void __launch_bounds__(64) k_pc_lambda_sweep(int nz, int nd, int nn, 
   }
 }
 
+__global__ void __launch_bounds__(64) k_pc_lambda_sweep(int nz, int nd, int nn, const double* __restrict__ mu,
+                                                        const double2* __restrict__ F, const double* __restrict__ L,
+                                                        const double* __restrict__ e, const double* __restrict__ y,
+                                                        int y_stride, const double* __restrict__ x,
+                                                        double* __restrict__ res) {
+  pc_lambda_sweep_body(blockIdx.x, nz, nd, nn, mu, F, L, e, y, y_stride, x, res);
+}
+
+// one launch over several contexts: block b is context r's block b - off[r]
+__global__ void __launch_bounds__(64) k_pc_lambda_sweep_grouped(const GPcSweep* __restrict__ A,
+                                                                const int* __restrict__ off, int n) {
+  int lo = 0, hi = n;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (off[mid] <= (int)blockIdx.x) lo = mid; else hi = mid;
+  }
+  const GPcSweep& a = A[lo];
+  pc_lambda_sweep_body(blockIdx.x - off[lo], a.nz, a.nd, a.nn, a.mu, a.F, a.L, a.e, a.y, a.y_stride, a.x, a.res);
+}
+
+int launch_pc_sweep_grouped(hipStream_t s, const GPcSweep* args, const int* off, int n, int blocks) {
+  hipLaunchKernelGGL(k_pc_lambda_sweep_grouped, dim3(blocks), dim3(64), 0, s, args, off, n);
+  TRAP_HIP(hipGetLastError());
+  return TRAP_OK;
+}
+
 int launch_formal_scalar(trap_ctx* ctx, int prec, const double* e, const double* y, int y_stride, const double* x,
                          double* res) {
   (void)prec;      // the tabulated step coefficients are FP64
@@ -353,14 +381,17 @@ int formal_apply(trap_ctx* ctx, const void* eps, void* I, int with_boundary, int
   Problem& P = ctx->pb;
   const int rays = P.nd * P.nn;
   const int pr = prof_begin(ctx, TRAP_STAGE_FORMAL);
+  const bool par = ctx->formal_scheme == TRAP_FORMAL_DELOPAR;
   if (prec == TRAP_FP64) {
-    hipLaunchKernelGGL(k_formal<double>, dim3(ceil_div(rays, 64)), dim3(64), 0, ctx->stream, P.nz, P.nd,
-                       P.nn, P.d_mu, P.d_tau, ctx->pre.d_K, P.d_WT, static_cast<const double*>(eps),
-                       static_cast<double*>(I), with_boundary, ctx->formal_scheme);
+    auto kern = par ? k_formal<double, 1> : k_formal<double, 0>;
+    hipLaunchKernelGGL(kern, dim3(ceil_div(rays, 64)), dim3(64), 0, ctx->stream, P.nz, P.nd, P.nn, P.d_mu,
+                       P.d_tau, ctx->pre.d_K, P.d_WT, static_cast<const double*>(eps), static_cast<double*>(I),
+                       with_boundary);
   } else if (prec == TRAP_FP32) {
-    hipLaunchKernelGGL(k_formal<float>, dim3(ceil_div(rays, 64)), dim3(64), 0, ctx->stream, P.nz, P.nd,
-                       P.nn, P.d_mu, P.d_tau, ctx->pre.d_K, P.d_WT, static_cast<const float*>(eps),
-                       static_cast<float*>(I), with_boundary, ctx->formal_scheme);
+    auto kern = par ? k_formal<float, 1> : k_formal<float, 0>;
+    hipLaunchKernelGGL(kern, dim3(ceil_div(rays, 64)), dim3(64), 0, ctx->stream, P.nz, P.nd, P.nn, P.d_mu,
+                       P.d_tau, ctx->pre.d_K, P.d_WT, static_cast<const float*>(eps), static_cast<float*>(I),
+                       with_boundary);
   } else {
     return fail(TRAP_EINVAL, "unknown precision");
   }

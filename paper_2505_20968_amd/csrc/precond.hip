@@ -56,22 +56,17 @@ __device__ inline void pc_second_derivs(int nn, const double* __restrict__ SigT,
 // class c of height z (members mem[moff[c] .. moff[c + 1])) interpolated to
 // the comoving grid.  One block per (z, c); blocks past the height's class
 // count return at once.
-__global__ void __launch_bounds__(kGatherThreads) k_pc_gather_cls(int nd, int nn, int ncmax,
-                                                                  const double* __restrict__ x,
-                                                                  const double* __restrict__ SigT,
-                                                                  const double* __restrict__ lam,
-                                                                  const double* __restrict__ w,
-                                                                  const int* __restrict__ mem,
-                                                                  const int* __restrict__ moff,
-                                                                  const int* __restrict__ ncls,
-                                                                  const double* __restrict__ cub,
-                                                                  const double* __restrict__ src, int stride,
-                                                                  double* __restrict__ gc) {
+__device__ __forceinline__ void pc_gather_cls_body(int bx, int nd, int nn, int ncmax, const double* __restrict__ x,
+                                                   const double* __restrict__ SigT, const double* __restrict__ lam,
+                                                   const double* __restrict__ w, const int* __restrict__ mem,
+                                                   const int* __restrict__ moff, const int* __restrict__ ncls,
+                                                   const double* __restrict__ cub, const double* __restrict__ src,
+                                                   int stride, double* __restrict__ gc) {
   extern __shared__ double sh[];
   double* v = sh;
   double* sd = sh + nn;
   double* part = sh + 2 * nn;       // [kGatherParts][nn]
-  const int z = blockIdx.x / ncmax, c = blockIdx.x % ncmax;
+  const int z = bx / ncmax, c = bx % ncmax;
   if (c >= ncls[z]) return;
   const double shf = cub[(size_t)z * nd + c] / lam[z];
   const int* mz = mem + (size_t)z * nd;
@@ -93,20 +88,31 @@ __global__ void __launch_bounds__(kGatherThreads) k_pc_gather_cls(int nd, int nn
   for (int m = threadIdx.x; m < nn; m += blockDim.x) g[m] = spline_at(x, nn, v, sd, x[m] - shf);
 }
 
+__global__ void __launch_bounds__(kGatherThreads) k_pc_gather_cls(int nd, int nn, int ncmax,
+                                                                  const double* __restrict__ x,
+                                                                  const double* __restrict__ SigT,
+                                                                  const double* __restrict__ lam,
+                                                                  const double* __restrict__ w,
+                                                                  const int* __restrict__ mem,
+                                                                  const int* __restrict__ moff,
+                                                                  const int* __restrict__ ncls,
+                                                                  const double* __restrict__ cub,
+                                                                  const double* __restrict__ src, int stride,
+                                                                  double* __restrict__ gc) {
+  pc_gather_cls_body(blockIdx.x, nd, nn, ncmax, x, SigT, lam, w, mem, moff, ncls, cub, src, stride, gc);
+}
+
 // hz = Mat_z sum_c gc[z][c] with one wave per row of Mat_z, then the spline
 // second derivatives of hz; hz and them go to h[z][0][.] and h[z][1][.].
 // One block per height.
-__global__ void __launch_bounds__(kGatherThreads) k_pc_gather_fin(int nn, int ncmax,
-                                                                  const double* __restrict__ SigT,
-                                                                  const int* __restrict__ ncls,
-                                                                  const double* __restrict__ gc,
-                                                                  const double* __restrict__ Mat,
-                                                                  double* __restrict__ h) {
+__device__ __forceinline__ void pc_gather_fin_body(int bx, int nn, int ncmax, const double* __restrict__ SigT,
+                                                   const int* __restrict__ ncls, const double* __restrict__ gc,
+                                                   const double* __restrict__ Mat, double* __restrict__ h) {
   extern __shared__ double sh[];
   double* G = sh;
   double* hv = sh + nn;
   double* part = sh + 2 * nn;       // [kGatherParts][nn]
-  const int z = blockIdx.x, nc = ncls[z];
+  const int z = bx, nc = ncls[z];
   const double* gz = gc + (size_t)z * ncmax * nn;
   for (int m = threadIdx.x; m < nn; m += blockDim.x) {
     double a = 0.0;
@@ -128,18 +134,27 @@ __global__ void __launch_bounds__(kGatherThreads) k_pc_gather_fin(int nn, int nc
   for (int i = threadIdx.x; i < nn; i += blockDim.x) hz[i] = hv[i];
 }
 
+__global__ void __launch_bounds__(kGatherThreads) k_pc_gather_fin(int nn, int ncmax,
+                                                                  const double* __restrict__ SigT,
+                                                                  const int* __restrict__ ncls,
+                                                                  const double* __restrict__ gc,
+                                                                  const double* __restrict__ Mat,
+                                                                  double* __restrict__ h) {
+  pc_gather_fin_body(blockIdx.x, nn, ncmax, SigT, ncls, gc, Mat, h);
+}
+
 enum PcScatter { PC_FIRST = 0, PC_SIGMA = 1, PC_UPDATE = 2 };
 
 // per point p = (z, o, n), with v = S[h_z](x_n + u_b(z, o)/lam_z):
 //   PC_FIRST:  dst = src + L v            (x_1 = P^^-1 y)
 //   PC_SIGMA:  dst = v                    (Sigma* x)
 //   PC_UPDATE: dst = xin + res + L v      (x += P^^-1 res)
-__global__ void __launch_bounds__(256) k_pc_scatter(int mode, int nz, int nd, int nn, const double* __restrict__ x,
-                                                    const double* __restrict__ lam, const double* __restrict__ ub,
-                                                    const double* __restrict__ h, const double* __restrict__ L,
-                                                    const double* src, int src_stride, const double* xin,
-                                                    const double* __restrict__ res, double* dst, int dst_stride) {
-  const long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+__device__ __forceinline__ void pc_scatter_body(int bx, int mode, int nz, int nd, int nn, const double* __restrict__ x,
+                                                const double* __restrict__ lam, const double* __restrict__ ub,
+                                                const double* __restrict__ h, const double* __restrict__ L,
+                                                const double* src, int src_stride, const double* xin,
+                                                const double* __restrict__ res, double* dst, int dst_stride) {
+  const long long p = bx * (long long)blockDim.x + threadIdx.x;
   if (p >= (long long)nz * nd * nn) return;
   const int n = (int)(p % nn);
   const long long zo = p / nn;
@@ -151,6 +166,80 @@ __global__ void __launch_bounds__(256) k_pc_scatter(int mode, int nz, int nd, in
   else if (mode == PC_SIGMA) out = v;
   else out = xin[p] + res[p] + L[p] * v;
   dst[p * dst_stride] = out;
+}
+
+__global__ void __launch_bounds__(256) k_pc_scatter(int mode, int nz, int nd, int nn, const double* __restrict__ x,
+                                                    const double* __restrict__ lam, const double* __restrict__ ub,
+                                                    const double* __restrict__ h, const double* __restrict__ L,
+                                                    const double* src, int src_stride, const double* xin,
+                                                    const double* __restrict__ res, double* dst, int dst_stride) {
+  pc_scatter_body(blockIdx.x, mode, nz, nd, nn, x, lam, ub, h, L, src, src_stride, xin, res, dst, dst_stride);
+}
+
+// ------------------------------------------------------------------ shared launches across contexts
+// block b of a grouped launch is context r's block b - off[r]
+__device__ inline int pc_group_of(const int* __restrict__ off, int n) {
+  int lo = 0, hi = n;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (off[mid] <= (int)blockIdx.x) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+__global__ void __launch_bounds__(kGatherThreads) k_pc_gather_cls_grouped(const GPcCls* __restrict__ A,
+                                                                          const int* __restrict__ off, int n) {
+  const int r = pc_group_of(off, n);
+  const GPcCls& a = A[r];
+  pc_gather_cls_body(blockIdx.x - off[r], a.nd, a.nn, a.ncmax, a.x, a.SigT, a.lam, a.w, a.mem, a.moff, a.ncls,
+                     a.cub, a.src, a.stride, a.gc);
+}
+
+__global__ void __launch_bounds__(kGatherThreads) k_pc_gather_fin_grouped(const GPcFin* __restrict__ A,
+                                                                          const int* __restrict__ off, int n) {
+  const int r = pc_group_of(off, n);
+  const GPcFin& a = A[r];
+  pc_gather_fin_body(blockIdx.x - off[r], a.nn, a.ncmax, a.SigT, a.ncls, a.gc, a.Mat, a.h);
+}
+
+__global__ void __launch_bounds__(256) k_pc_scatter_grouped(const GPcScat* __restrict__ A,
+                                                            const int* __restrict__ off, int n) {
+  const int r = pc_group_of(off, n);
+  const GPcScat& a = A[r];
+  pc_scatter_body(blockIdx.x - off[r], a.mode, a.nz, a.nd, a.nn, a.x, a.lam, a.ub, a.h, a.L, a.src, a.src_stride,
+                  a.xin, a.res, a.dst, a.dst_stride);
+}
+
+int launch_pc_grouped(hipStream_t s, int stage, const void* args, const int* off, int n, int blocks, size_t lds) {
+  switch (stage) {
+    case 0:
+      hipLaunchKernelGGL(k_pc_gather_cls_grouped, dim3(blocks), dim3(kGatherThreads), lds, s,
+                         static_cast<const GPcCls*>(args), off, n);
+      break;
+    case 1:
+      hipLaunchKernelGGL(k_pc_gather_fin_grouped, dim3(blocks), dim3(kGatherThreads), lds, s,
+                         static_cast<const GPcFin*>(args), off, n);
+      break;
+    default:
+      hipLaunchKernelGGL(k_pc_scatter_grouped, dim3(blocks), dim3(256), 0, s, static_cast<const GPcScat*>(args),
+                         off, n);
+      break;
+  }
+  TRAP_HIP(hipGetLastError());
+  return TRAP_OK;
+}
+
+int precond_ensure(trap_ctx* ctx) {
+  Problem& P = ctx->pb;
+  Work& K = ctx->wk;
+  if (K.pc_h) return TRAP_OK;
+  const long long ns = (long long)P.nz * P.nd * P.nn;
+  TRAP_TRY(dalloc_t(ctx, &K.pc_x, ns));
+  TRAP_TRY(dalloc_t(ctx, &K.pc_e, ns));
+  TRAP_TRY(dalloc_t(ctx, &K.pc_res, ns));
+  TRAP_TRY(dalloc_t(ctx, &K.pc_h, (size_t)P.nz * 2 * P.nn));
+  TRAP_TRY(dalloc_t(ctx, &K.pc_gc, (size_t)P.nz * ctx->pre.pc_ncmax * P.nn));
+  return TRAP_OK;
 }
 
 static int pc_gather(trap_ctx* ctx, const double* src, int stride, const double* Mat) {
@@ -187,13 +276,7 @@ int precond_apply(trap_ctx* ctx, const double* r, double* out, int sweeps, int p
   Precomp& C = ctx->pre;
   Work& K = ctx->wk;
   const long long ns = (long long)P.nz * P.nd * P.nn;
-  if (!K.pc_h) {
-    TRAP_TRY(dalloc_t(ctx, &K.pc_x, ns));
-    TRAP_TRY(dalloc_t(ctx, &K.pc_e, ns));
-    TRAP_TRY(dalloc_t(ctx, &K.pc_res, ns));
-    TRAP_TRY(dalloc_t(ctx, &K.pc_h, (size_t)P.nz * 2 * P.nn));
-    TRAP_TRY(dalloc_t(ctx, &K.pc_gc, (size_t)P.nz * C.pc_ncmax * P.nn));
-  }
+  TRAP_TRY(precond_ensure(ctx));
   if (out != r) TRAP_HIP(hipMemcpyAsync(out, r, 4 * ns * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
   // x_1 = P^^-1 y with y the Stokes I of `out` (read until the last write)
   TRAP_TRY(pc_gather(ctx, out, 4, C.d_pcC));

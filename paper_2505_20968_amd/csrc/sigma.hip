@@ -1513,7 +1513,7 @@ struct Blob {
 };
 
 enum StageKind { SK_TO32, SK_SPLINE, SK_R3Y, SK_R3X, SK_CONTRACT, SK_CONTRACT_ONE, SK_ANGULAR, SK_COPY, SK_FORMAL,
-                 SK_FINISH };
+                 SK_FINISH, SK_PC_CLS, SK_PC_FIN, SK_PC_SCAT, SK_PC_SWEEP };
 
 struct Stage {
   int kind;
@@ -1603,7 +1603,7 @@ int sigma_batch_ready(trap_ctx* ctx) {
   return (K.v32a && K.v32b) ? 1 : 0;
 }
 
-int op_apply_batch_f32(trap_ctx** ctxs, int n, const double* const* x, double* const* y) {
+int op_apply_batch_f32(trap_ctx** ctxs, int n, const double* const* x, double* const* y, const int* pc) {
   if (n <= 0) return TRAP_OK;
   const int device = ctxs[0]->device;
   Blob blob;
@@ -1777,6 +1777,85 @@ int op_apply_batch_f32(trap_ctx** ctxs, int n, const double* const* x, double* c
   }
   for (int i = 0; i < n; ++i) vec[i].f32 = ctxs[i]->wk.v32b;
   add_stage(SK_FINISH, 0, blob.put(vec), vcnt, 0);
+  // 7. the preconditioner of the contexts that ask for it, in place on y_i:
+  //    the block-Jacobi steps of precond_apply, each kernel one launch over
+  //    the contexts that still have that step
+  int maxk = 0;
+  for (int i = 0; pc && i < n; ++i)
+    if (pc[i] > 0) {
+      TRAP_TRY(precond_ensure(ctxs[i]));
+      maxk = std::max(maxk, pc[i]);
+    }
+  auto pc_gather = [&](int step, auto src_of, int stride, bool phi) {
+    std::vector<GPcCls> a;
+    std::vector<GPcFin> b;
+    std::vector<int> ca, cb;
+    size_t lds = 0;
+    for (int i = 0; i < n; ++i) {
+      if (pc[i] < step) continue;
+      const Problem& P = ctxs[i]->pb;
+      const Precomp& C = ctxs[i]->pre;
+      Work& K = ctxs[i]->wk;
+      a.push_back(GPcCls{P.nd, P.nn, C.pc_ncmax, stride, P.d_x, P.d_SigT, P.d_lam, P.d_w, C.d_pcMem, C.d_pcMoff,
+                         C.d_pcNcls, C.d_pcCub, src_of(i), K.pc_gc});
+      b.push_back(GPcFin{P.nn, C.pc_ncmax, P.d_SigT, C.d_pcNcls, K.pc_gc, phi ? C.d_pcPhi : C.d_pcC, K.pc_h});
+      ca.push_back(P.nz * C.pc_ncmax);
+      cb.push_back(P.nz);
+      lds = std::max(lds, (size_t)6 * P.nn * sizeof(double));
+    }
+    add_stage(SK_PC_CLS, 0, blob.put(a), ca, lds);
+    add_stage(SK_PC_FIN, 0, blob.put(b), cb, lds);
+  };
+  auto pc_scatter = [&](int step, int mode, auto fill) {
+    std::vector<GPcScat> a;
+    std::vector<int> cnt;
+    for (int i = 0; i < n; ++i) {
+      if (pc[i] < step) continue;
+      const Problem& P = ctxs[i]->pb;
+      GPcScat g{mode, P.nz, P.nd, P.nn, 0, 1, P.d_x, P.d_lam, P.d_ub, ctxs[i]->wk.pc_h, ctxs[i]->pre.d_pcL,
+                nullptr, nullptr, nullptr, nullptr};
+      fill(i, g);
+      a.push_back(g);
+      cnt.push_back(ceil_div((long long)P.nz * P.nd * P.nn, 256));
+    }
+    add_stage(SK_PC_SCAT, 0, blob.put(a), cnt, 0);
+  };
+  for (int step = 1; step <= maxk; ++step) {
+    if (step == 1) {
+      pc_gather(1, [&](int i) { return (const double*)y[i]; }, 4, false);
+      pc_scatter(1, 0, [&](int i, GPcScat& g) {       // x_1 = P^^-1 y
+        g.src = y[i];
+        g.src_stride = 4;
+        const bool last = pc[i] == 1;
+        g.dst = last ? y[i] : ctxs[i]->wk.pc_x;
+        g.dst_stride = last ? 4 : 1;
+      });
+      continue;
+    }
+    pc_gather(step, [&](int i) { return (const double*)ctxs[i]->wk.pc_x; }, 1, true);
+    pc_scatter(step, 1, [&](int i, GPcScat& g) { g.dst = ctxs[i]->wk.pc_e; });   // Sigma* x
+    {
+      std::vector<GPcSweep> a;
+      std::vector<int> cnt;
+      for (int i = 0; i < n; ++i) {
+        if (pc[i] < step) continue;
+        const Problem& P = ctxs[i]->pb;
+        Work& K = ctxs[i]->wk;
+        a.push_back(GPcSweep{P.nz, P.nd, P.nn, 4, P.d_mu, ctxs[i]->pre.d_pcF, ctxs[i]->pre.d_pcL, K.pc_e, y[i],
+                             K.pc_x, K.pc_res});
+        cnt.push_back(ceil_div((long long)P.nd * P.nn, 64));
+      }
+      add_stage(SK_PC_SWEEP, 0, blob.put(a), cnt, 0);
+    }
+    pc_gather(step, [&](int i) { return (const double*)ctxs[i]->wk.pc_res; }, 1, false);
+    pc_scatter(step, 2, [&](int i, GPcScat& g) {      // x += P^^-1 res
+      g.xin = ctxs[i]->wk.pc_x;
+      g.res = ctxs[i]->wk.pc_res;
+      const bool last = pc[i] == step;
+      g.dst = last ? y[i] : ctxs[i]->wk.pc_x;
+      g.dst_stride = last ? 4 : 1;
+    });
+  }
 
   std::lock_guard<std::mutex> lk(g_arena_mu);
   auto it = g_arena.find(device);
@@ -1864,6 +1943,14 @@ int op_apply_batch_f32(trap_ctx** ctxs, int n, const double* const* x, double* c
       }
       case SK_FORMAL:
         TRAP_TRY(launch_formal_grouped(ar.stream, static_cast<const GFormal*>(args), off, st.n, st.blocks));
+        break;
+      case SK_PC_CLS:
+      case SK_PC_FIN:
+      case SK_PC_SCAT:
+        TRAP_TRY(launch_pc_grouped(ar.stream, st.kind - SK_PC_CLS, args, off, st.n, st.blocks, st.lds));
+        break;
+      case SK_PC_SWEEP:
+        TRAP_TRY(launch_pc_sweep_grouped(ar.stream, static_cast<const GPcSweep*>(args), off, st.n, st.blocks));
         break;
     }
     TRAP_HIP(hipGetLastError());

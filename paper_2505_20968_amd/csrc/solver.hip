@@ -354,8 +354,10 @@ bool unit_operand(trap_ctx* ctx, GmresRun& R, int* prec, const double** x, doubl
   }
 }
 
-// phase-1 work of one unit after its operator apply, up to the first synchronisation
-int unit_issue1_rest(trap_ctx* ctx, GmresRun& R) {
+// phase-1 work of one unit after its operator apply, up to the first
+// synchronisation (pc_done: the Arnoldi vector was preconditioned in the
+// shared apply already)
+int unit_issue1_rest(trap_ctx* ctx, GmresRun& R, bool pc_done = false) {
   Work& K = ctx->wk;
   const long long N = R.N;
   switch (R.phase) {
@@ -379,7 +381,7 @@ int unit_issue1_rest(trap_ctx* ctx, GmresRun& R) {
       }
       return dots_async(ctx, R, K.tmp64, 1, K.tmp64, R.hbuf);
     case GP_ARNOLDI:
-      if (R.pc) {
+      if (R.pc && !pc_done) {
         double* w = K.V + (size_t)(R.j + 1) * N;
         TRAP_TRY(precond_apply(ctx, w, w, R.pc, R.prec));
         R.st.applies_precond++;
@@ -621,16 +623,24 @@ int gmres_step_batch(trap_ctx** ctxs, int n, int* status) {
     if (rc < 0) run_finish(R, rc);
   } else if (grp.size() > 1) {
     DeviceGuard g(gdev);
-    const int rc = op_apply_batch_f32(gctx.data(), (int)gctx.size(), gx.data(), gy.data());
-    for (int i : grp) {
-      GmresRun& R = *ctxs[i]->run;
+    // Arnoldi vectors are preconditioned in place right after the apply, so
+    // their preconditioner joins the shared launches
+    std::vector<int> pcs(grp.size(), 0);
+    for (size_t k = 0; k < grp.size(); ++k) {
+      const GmresRun& R = *ctxs[grp[k]]->run;
+      if (R.phase == GP_ARNOLDI && R.pc > 0) pcs[k] = R.pc;
+    }
+    const int rc = op_apply_batch_f32(gctx.data(), (int)gctx.size(), gx.data(), gy.data(), pcs.data());
+    for (size_t k = 0; k < grp.size(); ++k) {
+      GmresRun& R = *ctxs[grp[k]]->run;
       if (rc < 0) {
         run_finish(R, rc);
         continue;
       }
       R.st.applies_fp32++;
       R.st.applies_grouped++;
-      const int rc2 = unit_issue1_rest(ctxs[i], R);
+      if (pcs[k]) R.st.applies_precond++;
+      const int rc2 = unit_issue1_rest(ctxs[grp[k]], R, pcs[k] > 0);
       if (rc2 < 0) run_finish(R, rc2);
     }
   }

@@ -43,6 +43,7 @@ __host__ __device__ inline double2 cadd(double2 a, double2 b) { return make_doub
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  bool pooled = false;     // from the device's stream-ordered pool (freed with hipFreeAsync)
 };
 
 // ---------------------------------------------------------------- context
@@ -368,6 +369,37 @@ struct GFormal {
   const float* eps;
   float* I;
 };
+// preconditioner stages of a shared apply (precond.hip, formal.hip)
+struct GPcCls {
+  int nd, nn, ncmax, stride;
+  const double *x, *SigT, *lam, *w;
+  const int *mem, *moff, *ncls;
+  const double *cub, *src;
+  double* gc;
+};
+struct GPcFin {
+  int nn, ncmax;
+  const double* SigT;
+  const int* ncls;
+  const double *gc, *Mat;
+  double* h;
+};
+struct GPcScat {
+  int mode, nz, nd, nn, src_stride, dst_stride;
+  const double *x, *lam, *ub, *h, *L, *src, *xin, *res;
+  double* dst;
+};
+struct GPcSweep {
+  int nz, nd, nn, y_stride;
+  const double* mu;
+  const double2* F;
+  const double *L, *e, *y, *x;
+  double* res;
+};
+// stage 0: class sums, 1: per-height finish, 2: per-point scatter
+int launch_pc_grouped(hipStream_t s, int stage, const void* args, const int* off, int n, int blocks, size_t lds);
+int launch_pc_sweep_grouped(hipStream_t s, const GPcSweep* args, const int* off, int n, int blocks);
+int precond_ensure(trap_ctx* ctx);     // the sweep buffers of a context
 struct GVec {              // FP64 <-> FP32 conversions around the FP32 operator
   long long N;
   int nb;
@@ -405,7 +437,9 @@ void batch_arena_release(int device);
 int sigma_batch_ready(trap_ctx* ctx);
 // y_i = x_i - Lambda Sigma x_i in FP32 for every context (operands FP64), on
 // the device's batch stream, ordered after and before each context's stream
-int op_apply_batch_f32(trap_ctx** ctxs, int n, const double* const* x, double* const* y);
+// pc[i] > 0: apply context i's preconditioner with pc[i] block-Jacobi steps to
+// y_i in place (shared launches as well); pc may be null
+int op_apply_batch_f32(trap_ctx** ctxs, int n, const double* const* x, double* const* y, const int* pc = nullptr);
 int launch_formal_grouped(hipStream_t s, const GFormal* args, const int* off, int n, int blocks);
 
 // physics-based preconditioner (Sect. 5.3, App. F): tables after the kernel

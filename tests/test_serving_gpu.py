@@ -117,3 +117,34 @@ def test_mixed_and_fp64_serving_agree(served):
         assert (np.abs(a[..., 0] - b[..., 0]) / np.abs(b[..., 0])).max() < 1e-6
         for s in (1, 2, 3):
             assert np.abs(a[..., s] / a[..., 0] - b[..., s] / b[..., 0]).max() < 1e-4
+
+
+def test_preconditioned_requests_share_launches_and_match_alone():
+    """With the preconditioner (2 block-Jacobi steps) the Arnoldi vectors of
+    requests running together are preconditioned in the shared launches too;
+    each result is still bitwise the one the request gives alone."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2505_20968_amd.serving import Request, serve
+    from paper_2505_20968_amd import Context, TRAP_FP32
+    probs = [cfg1(),
+             tiny(n_z=6, n_nu=25, x_max=7, n_mu=4, n_chi=5, B=(60.0, 0.8, 2.0), a=2e-2, eps=3e-2, v_z=2.0, seed=21),
+             tiny(n_z=4, n_nu=33, x_max=16, n_mu=4, n_chi=4, B=(40.0, 1.0, 0.3), a=1e-2, eps=5e-2,
+                  atom=two_term_atom(2800.0, 24.305, 20.0))]
+    solver = dict(SOLVER, precond_sweeps=2)
+    res = serve([Request(i, 0.0, p) for i, p in enumerate(probs)], precision="mixed", max_active=3, **solver)
+    assert res["n_ok"] == len(probs)
+    for r in res["requests"]:
+        print(f"[serving preconditioned] request {r.rid}: {r.stats}", flush=True)
+        assert r.stats["applies_grouped"] > 0 and r.stats["applies_precond"] > 0
+        ctx = Context(0)
+        ctx.set_problem(r.problem)
+        ctx.precompute(3)
+        ctx.precompute_preconditioner()
+        x = torch.zeros(ctx.shape, dtype=torch.float64, device="cuda")
+        st = ctx.gmres_solve(x, inner=TRAP_FP32, zero_guess=True, **solver)
+        em = ctx.emergent(x)
+        ctx.close()
+        assert st["inner_iters"] == r.stats["inner_iters"]
+        assert np.array_equal(em, r.result)
