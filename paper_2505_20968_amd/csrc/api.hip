@@ -212,6 +212,12 @@ int trap_destroy(trap_ctx* ctx) {
   prof_clear(ctx, true);
   free_all(ctx);
   release_spare(ctx);
+  if (ctx->side) {
+    (void)hipStreamSynchronize(ctx->side);
+    (void)hipStreamDestroy(ctx->side);
+  }
+  if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
+  if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
   batch_arena_release(ctx->device);
   delete ctx;
   return TRAP_OK;

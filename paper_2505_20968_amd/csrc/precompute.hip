@@ -894,6 +894,10 @@ int run_precompute(trap_ctx* ctx, int store_mask) {
                      P.d_lam, P.d_a, P.d_ub, P.d_st, P.d_g, P.d_eta0, P.d_eps, P.d_WT, P.c_abs, P.d_kc, P.d_sc,
                      C.d_K, C.d_epsth);
   TRAP_HIP(hipGetLastError());
+  // everything the preconditioner tables read exists from here on
+  if (!ctx->ev_fork) TRAP_HIP(hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming));
+  TRAP_HIP(hipEventRecord(ctx->ev_fork, s));
+  ctx->fork_recorded = true;
   const size_t kelems = (size_t)nz * nth * nt * 2 * nn * P.ldm;
   const int mask = store_mask | 1;     // FP64 kernels always exist (residual, f, b)
   if ((mask & 1) && !C.d_M64) TRAP_TRY(dalloc_t(ctx, &C.d_M64, kelems));
@@ -1149,7 +1153,7 @@ __global__ void __launch_bounds__(kInvThreads) k_pc_invert(int nn, const double*
   }
 }
 
-int run_precompute_precond(trap_ctx* ctx) {
+static int precompute_precond_body(trap_ctx* ctx) {
   Problem& P = ctx->pb;
   Precomp& C = ctx->pre;
   hipStream_t s = ctx->stream;
@@ -1241,6 +1245,26 @@ int run_precompute_precond(trap_ctx* ctx) {
   for (int z = 0; z < nz; ++z) C.pc_ncmax = std::max(C.pc_ncmax, P.pc_ncls[z]);
   C.pc_done = true;
   return TRAP_OK;
+}
+
+// The tables need the problem tables and the propagation matrix only, so
+// they are built on the context's side stream from the fork event of the
+// precompute on, overlapping its kernel rows and normalisation; the
+// context's stream waits for them before anything enqueued later.
+int run_precompute_precond(trap_ctx* ctx) {
+  if (!ctx->has_problem || !ctx->pre.done || !ctx->fork_recorded) return fail(TRAP_ESTATE, "precompute not run");
+  if (!ctx->side) {
+    TRAP_HIP(hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
+    TRAP_HIP(hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming));
+  }
+  TRAP_HIP(hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0));
+  hipStream_t main = ctx->stream;
+  ctx->stream = ctx->side;
+  const int rc = precompute_precond_body(ctx);
+  ctx->stream = main;
+  TRAP_HIP(hipEventRecord(ctx->ev_join, ctx->side));
+  TRAP_HIP(hipStreamWaitEvent(main, ctx->ev_join, 0));
+  return rc;
 }
 
 void faddeeva_coefficients(FaddeevaCoef* out) {

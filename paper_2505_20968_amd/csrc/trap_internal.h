@@ -217,6 +217,12 @@ struct trap_ctx {
   int formal_scheme = 0;            // TRAP_FORMAL_* of trap.h
   int max_lds = 64 * 1024;          // device limit of LDS bytes per block
   int n_cu = 256;                   // compute units of the device
+  // the preconditioner tables are built on a stream of the library's own
+  // (default priority), forked after the propagation matrix of the precompute
+  // and joined back before the context's later work
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  bool fork_recorded = false;
   std::vector<trap::DevBuf> bufs;   // every allocation of the current problem
   std::vector<trap::DevBuf> spare;  // the previous problem's allocations, reused by size
 };
