@@ -225,7 +225,9 @@ __global__ void k_kernel_tables(int z0, int nth, int nt, int nn, int ntail, doub
 // written here, the dense product is one batched GEMM (k_sig_gemm).
 constexpr int kRowWavesMax = 2;       // rows (one per wave) per block of the kernel-row precompute
 
-__global__ void __launch_bounds__(64 * kRowWavesMax) k_kernel_rows(
+// The kernel is latency bound; a register cap for three waves per SIMD (a few
+// bytes of spill) measured faster than the uncapped two or a four-wave cap.
+__global__ void __launch_bounds__(64 * kRowWavesMax, 3) k_kernel_rows(
     long long nrows, int nth, int nt, int nn, int ldm, const double* __restrict__ x,
     const double* __restrict__ lam, const double* __restrict__ av, const double* __restrict__ st,
     const double* __restrict__ theta, double* __restrict__ Lout, double* __restrict__ Gout,
