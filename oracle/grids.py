@@ -17,13 +17,19 @@ import numpy as np
 from scipy.interpolate import CubicSpline
 
 
-def angular_grid(n_mu: int, n_chi: int):
+def angular_grid(n_mu: int, n_chi: int, los_mu=None):
     """Directions ordered mu-major (mu ascending from -1 to 1), chi-minor.
 
     Returns dict with mu, chi, w (sum 1), dirs [N,3], e_a, e_b [N,3].
     e_a is the positive-Q reference direction: perpendicular to the vertical
     plane that contains the ray, i.e. parallel to the limb (Sect. 6.3, Fig. 2
     caption); (e_a, e_b, Omega) is right-handed.
+
+    ``los_mu`` (optional, each in (0, 1]): lines of sight off the quadrature
+    (the emergent profiles of Sect. 6 are shown at such mu values).  Each
+    adds a ring of the n_chi azimuths after the quadrature directions with
+    zero weight: the rays are solved like any other but take no part in the
+    angular integrals.  "n_grid" counts the quadrature directions.
     """
     if n_mu < 2 or n_mu % 2:
         raise ValueError("n_mu must be even and >= 2 (double Gauss-Legendre)")
@@ -35,16 +41,22 @@ def angular_grid(n_mu: int, n_chi: int):
     w_p = 0.5 * wt
     mu1 = np.concatenate([-mu_p[::-1], mu_p])
     wmu = np.concatenate([w_p[::-1], w_p])
+    los = np.zeros(0) if los_mu is None else np.asarray(los_mu, float).ravel()
+    if np.any(~(los > 0.0)) or np.any(los > 1.0):
+        raise ValueError("line-of-sight mu must lie in (0, 1]")
+    mu1 = np.concatenate([mu1, los])
+    wmu = np.concatenate([wmu, np.zeros_like(los)])
     chi1 = 2.0 * np.pi * np.arange(n_chi) / n_chi
+    n_ring = mu1.size
     mu = np.repeat(mu1, n_chi)
-    chi = np.tile(chi1, n_mu)
+    chi = np.tile(chi1, n_ring)
     w = np.repeat(wmu, n_chi) / (2.0 * n_chi)
     st = np.sqrt(1.0 - mu * mu)
     dirs = np.stack([st * np.cos(chi), st * np.sin(chi), mu], axis=1)
     e_a = np.stack([-np.sin(chi), np.cos(chi), np.zeros_like(chi)], axis=1)
     e_b = np.cross(dirs, e_a)
     return {"mu": mu, "chi": chi, "w": w, "dirs": dirs, "e_a": e_a, "e_b": e_b,
-            "n_mu": n_mu, "n_chi": n_chi}
+            "n_mu": n_mu, "n_chi": n_chi, "n_grid": n_mu * n_chi, "n_los": los.size}
 
 
 def theta_table(dirs: np.ndarray, tol: float = 1e-10):

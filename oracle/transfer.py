@@ -135,7 +135,7 @@ def setup(prob, opts=None) -> OracleProblem:
     dnuD = nu0 * vth / C_CGS
     dnuD_ref = nu0 * vth_ref / C_CGS
     lam = dnuD_ref / dnuD
-    ang = angular_grid(prob.n_mu, prob.n_chi)
+    ang = angular_grid(prob.n_mu, prob.n_chi, getattr(prob, "los_mu", None))
     theta, pair = theta_table(ang["dirs"])
     basis = SplineBasis(prob.x)
     nz, nd, nn = prob.n_z, prob.n_dir, prob.n_nu
@@ -477,6 +477,27 @@ def solve(op, tol=1e-12, method="gmres", restart=200, maxiter=4000):
 
 
 def emergent(op, I):
-    """Stokes vectors at z_max for every outgoing (mu > 0) direction: [o, n, 4]."""
-    up = op.ang["mu"] > 0
-    return I[-1][up]
+    """Stokes vectors at z_max for every outgoing (mu > 0) quadrature direction: [o, n, 4]."""
+    ng = op.ang["n_grid"]
+    up = op.ang["mu"][:ng] > 0
+    return I[-1][:ng][up]
+
+
+def los_emergent(op, I_grid):
+    """Emergent Stokes vectors along the off-grid lines of sight, [los, chi, n, 4].
+
+    Given the radiation field on the quadrature directions (I_grid[z, o, n, 4],
+    o < n_grid; a converged solution), the emissivity eps = Sigma I + eps_th
+    is evaluated for every direction, the lines of sight included, and one
+    formal solution with the boundary radiation gives I = Lambda eps + t along
+    them (the extra formal solution after convergence, Sect. 6).  The lines of
+    sight carry zero quadrature weight, so whatever stands there in the input
+    does not matter; they are set to zero."""
+    prob = op.prob
+    ng, nl, nc = op.ang["n_grid"], op.ang["n_los"], prob.n_chi
+    if nl == 0:
+        raise ValueError("the problem has no off-grid lines of sight")
+    x = np.zeros((prob.n_z, prob.n_dir, prob.n_nu, 4))
+    x[:, :ng] = np.asarray(I_grid)[:, :ng]
+    full = formal_solve(op, sigma_apply(op, x) + op.eps_th, boundary=True)
+    return full[-1, ng:].reshape(nl, nc, prob.n_nu, 4)

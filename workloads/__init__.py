@@ -88,6 +88,9 @@ class Problem:
     # line-centre absorption coefficient; None = no continuum
     kappa_c: Optional[np.ndarray] = None
     sigma_c: Optional[np.ndarray] = None
+    # off-grid lines of sight: mu values in (0, 1], each a ring of the n_chi
+    # azimuths after the quadrature directions, with zero quadrature weight
+    los_mu: Optional[np.ndarray] = None
     T_ref: float = 6000.0      # temperature that defines dnu_D_ref
     tol: float = 1e-8
     meta: dict = field(default_factory=dict)
@@ -101,8 +104,16 @@ class Problem:
         return int(self.x.shape[0])
 
     @property
-    def n_dir(self) -> int:
+    def n_los(self) -> int:
+        return 0 if self.los_mu is None else int(np.asarray(self.los_mu).size)
+
+    @property
+    def n_dir_grid(self) -> int:
         return self.n_mu * self.n_chi
+
+    @property
+    def n_dir(self) -> int:
+        return (self.n_mu + self.n_los) * self.n_chi
 
     @property
     def n_unknowns(self) -> int:
@@ -209,12 +220,14 @@ def cfg4(seed: int = 4, n_z: int = 100) -> Problem:
 def tiny(n_z: int = 6, n_nu: int = 13, x_max: float = 6.0, n_mu: int = 2, n_chi: int = 4,
          atom: Optional[Atom] = None, B=(20.0, np.pi / 2, 0.0), v_z: float = 0.0,
          a: float = 1e-2, eps: float = 1e-2, tau_top: float = 1e-3, tau_bot: float = 1e2,
-         seed: Optional[int] = None, T: float = 6000.0, cont: Optional[tuple] = None) -> Problem:
+         seed: Optional[int] = None, T: float = 6000.0, cont: Optional[tuple] = None,
+         los_mu=None) -> Problem:
     """Small problems for oracle pins and GPU parity.  With ``seed`` set, the
     damping, destruction probability, field and velocity vary with height.
     ``cont = (kappa, sigma)`` adds a continuum whose coefficients (relative to
     the line-centre absorption) change linearly by 25 % across the grid
-    (kappa rising to the red end, sigma to the blue end) and vary with height."""
+    (kappa rising to the red end, sigma to the blue end) and vary with height.
+    ``los_mu`` adds off-grid lines of sight (rings of zero weight)."""
     atom = atom or two_level_atom()
     tau = np.logspace(np.log10(tau_bot), np.log10(tau_top), n_z)
     Tz = np.full(n_z, float(T))
@@ -246,7 +259,8 @@ def tiny(n_z: int = 6, n_nu: int = 13, x_max: float = 6.0, n_mu: int = 2, n_chi:
     return Problem(name=f"tiny_{atom.kind}", atom=atom,
                    x=np.linspace(-x_max, x_max, n_nu), n_mu=n_mu, n_chi=n_chi,
                    tau_line=tau, T=Tz, xi=np.zeros(n_z), a=az, eps=epsz, W_T=W_T,
-                   v=v, B=Bz, kappa_c=kc, sigma_c=sc, meta={"seed": seed})
+                   v=v, B=Bz, kappa_c=kc, sigma_c=sc,
+                   los_mu=None if los_mu is None else np.asarray(los_mu, float), meta={"seed": seed})
 
 
 def serving_stream(n_requests: int = 1024, seed: int = 5, rate_hz: float = 10.0,
