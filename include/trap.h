@@ -92,7 +92,16 @@ typedef struct {
  *    absorption coefficient.  They add kappa_c + sigma_c to the diagonal of
  *    the propagation matrix, kappa_c W_T to the thermal emissivity of Stokes I
  *    (LTE) and coherent dipole scattering sigma_c sum_j R_ij I_j (observer
- *    frame, R the Rayleigh phase matrix) to the normalised Sigma. */
+ *    frame, R the Rayleigh phase matrix) to the normalised Sigma.
+ * n_los, los_mu (optional, n_los = 0 / NULL = none; n_los <= 16): lines of
+ *    sight off the quadrature, each mu in (0, 1] (the emergent profiles of
+ *    Sect. 6 are shown at such mu values).  Each adds a ring of the n_chi
+ *    azimuths after the n_mu * n_chi quadrature directions, with zero
+ *    quadrature weight: the rays carry their own propagation matrix,
+ *    emissivity and formal solution but take no part in the angular
+ *    integrals, so the solution on the quadrature directions is the one
+ *    without them.  Every device vector then holds
+ *    n_dir = (n_mu + n_los) * n_chi directions. */
 typedef struct {
   int n_z, n_nu, n_mu, n_chi;
   const double* x;
@@ -107,6 +116,8 @@ typedef struct {
   double T_ref;
   const double* kappa_c;
   const double* sigma_c;
+  int n_los;
+  const double* los_mu;
 } trap_problem_desc;
 
 /* Sizes of the discrete problem (filled by trap_get_info). */
@@ -267,9 +278,29 @@ int trap_gmres_begin(trap_ctx* ctx, const trap_solve_opts* opts, double* I);
 int trap_gmres_step_batch(trap_ctx** ctxs, int n, int* status);
 int trap_gmres_end(trap_ctx* ctx, trap_solve_stats* stats);
 
-/* Emergent Stokes vectors at z_max for the mu > 0 directions:
- * host_out[o_up][n][4] (FP64, n_dir/2 x n_nu x 4).  Synchronises. */
+/* Emergent Stokes vectors at z_max for the mu > 0 quadrature directions:
+ * host_out[o_up][n][4] (FP64, n_mu/2 * n_chi x n_nu x 4).  Synchronises. */
 int trap_emergent(trap_ctx* ctx, const double* I, double* host_out);
+
+/* The formal solution of a given radiation field's emissivity (FP64):
+ * out = Lambda (Sigma I + eps_th) + t on every ray, as in the iteration of
+ * Eq. linear_system; for a converged solution this is the extra formal
+ * solution that gives the emergent profiles along the off-grid lines of
+ * sight (Sect. 6).  I is FP64 device memory holding n_dir_in directions per
+ * height: either all n_dir, or only the n_mu * n_chi quadrature directions
+ * (the solution of a context of the same problem without lines of sight;
+ * the line-of-sight rings carry zero weight, so they are read as zero).
+ * out is FP64 device memory of the full layout (n_dir directions); it may
+ * not overlap I.  TRAP_EINVAL for another n_dir_in, TRAP_ESTATE before
+ * trap_precompute.  Asynchronous on the context's stream. */
+int trap_formal_from_field(trap_ctx* ctx, const double* I, int n_dir_in, double* out);
+
+/* Emergent Stokes vectors at z_max along the lines of sight:
+ * host_out[los][chi][n][4] (FP64, n_los x n_chi x n_nu x 4) read from the
+ * full-layout FP64 device vector I (a solution of the problem with its
+ * rings, or the output of trap_formal_from_field).  TRAP_EINVAL when the
+ * problem has no lines of sight.  Synchronises. */
+int trap_emergent_los(trap_ctx* ctx, const double* I, double* host_out);
 
 /* Sizes and algorithmic work of the loaded problem. */
 int trap_get_info(const trap_ctx* ctx, trap_info* info);

@@ -323,12 +323,56 @@ int trap_emergent(trap_ctx* ctx, const double* I, double* host_out) {
   const size_t rec = (size_t)P.nn * 4;
   const double* top = I + (size_t)(P.nz - 1) * P.nd * rec;
   size_t k = 0;
-  for (int o = 0; o < P.nd; ++o) {
+  for (int o = 0; o < P.ngrid; ++o) {
     if (P.mu[o] <= 0.0) continue;
     TRAP_HIP(hipMemcpyAsync(host_out + k * rec, top + (size_t)o * rec, rec * sizeof(double),
                             hipMemcpyDeviceToHost, ctx->stream));
     ++k;
   }
+  TRAP_HIP(hipStreamSynchronize(ctx->stream));
+  return TRAP_OK;
+}
+
+int trap_formal_from_field(trap_ctx* ctx, const double* I, int n_dir_in, double* out) {
+  if (!ctx) return fail(TRAP_EINVAL, "null context");
+  if (!ctx->has_problem || !ctx->pre.done) return fail(TRAP_ESTATE, "precompute not run");
+  if (!I || !out) return fail(TRAP_EINVAL, "null vector");
+  const Problem& P = ctx->pb;
+  if (n_dir_in != P.nd && n_dir_in != P.ngrid)
+    return fail(TRAP_EINVAL, "n_dir_in must be n_dir or the quadrature count n_mu * n_chi");
+  const size_t rec = (size_t)P.nn * 4 * sizeof(double);
+  const size_t N = (size_t)P.nz * P.nd * rec;
+  const char* ib = reinterpret_cast<const char*>(I);
+  const char* ob = reinterpret_cast<const char*>(out);
+  if (ib < ob + N && ob < ib + (size_t)P.nz * n_dir_in * rec) return fail(TRAP_EINVAL, "out overlaps I");
+  DeviceGuard g(ctx->device);
+  TRAP_TRY(ensure_work(ctx, TRAP_FP64));
+  const double* x = I;
+  if (n_dir_in != P.nd) {
+    // the quadrature directions per height into the full layout, the rings zero
+    TRAP_HIP(hipMemcpy2DAsync(out, P.nd * rec, I, P.ngrid * rec, P.ngrid * rec, P.nz, hipMemcpyDeviceToDevice,
+                              ctx->stream));
+    TRAP_HIP(hipMemset2DAsync(reinterpret_cast<char*>(out) + P.ngrid * rec, P.nd * rec, 0, (P.nd - P.ngrid) * rec,
+                              P.nz, ctx->stream));
+    x = out;
+  }
+  void* e = ctx->wk.opeps[0];
+  TRAP_TRY(sigma_apply(ctx, x, e, TRAP_FP64, 1, 1));   // Sigma I + eps_th
+  TRAP_TRY(formal_apply(ctx, e, out, 1, TRAP_FP64));   // Lambda (...) + t
+  return TRAP_OK;
+}
+
+int trap_emergent_los(trap_ctx* ctx, const double* I, double* host_out) {
+  if (!ctx) return fail(TRAP_EINVAL, "null context");
+  if (!ctx->has_problem) return fail(TRAP_ESTATE, "no problem loaded");
+  if (!I || !host_out) return fail(TRAP_EINVAL, "null pointer");
+  const Problem& P = ctx->pb;
+  if (P.nlos == 0) return fail(TRAP_EINVAL, "the problem has no lines of sight");
+  DeviceGuard g(ctx->device);
+  const size_t rec = (size_t)P.nn * 4;
+  const double* top = I + ((size_t)(P.nz - 1) * P.nd + P.ngrid) * rec;   // the rings follow the quadrature
+  TRAP_HIP(hipMemcpyAsync(host_out, top, (size_t)(P.nd - P.ngrid) * rec * sizeof(double), hipMemcpyDeviceToHost,
+                          ctx->stream));
   TRAP_HIP(hipStreamSynchronize(ctx->stream));
   return TRAP_OK;
 }

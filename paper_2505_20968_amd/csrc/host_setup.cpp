@@ -402,12 +402,17 @@ static void angular_setup(Problem& P, std::vector<double>& dirs, std::vector<dou
     mu1.push_back(gt[i]);
     wmu1.push_back(gw[i]);
   }
+  // off-grid lines of sight: rings of zero weight after the quadrature
+  for (double m : P.los_mu) {
+    mu1.push_back(m);
+    wmu1.push_back(0.0);
+  }
   P.mu.resize(nd);
   P.w.resize(nd);
   dirs.assign(3 * nd, 0.0);
   ea.assign(3 * nd, 0.0);
   eb.assign(3 * nd, 0.0);
-  for (int i = 0; i < P.nmu; ++i)
+  for (int i = 0; i < P.nmu + P.nlos; ++i)
     for (int k = 0; k < P.nchi; ++k) {
       const int o = i * P.nchi + k;
       const double chi = 2.0 * kPi * k / P.nchi, mu = mu1[i], st = std::sqrt(1.0 - mu * mu);
@@ -575,6 +580,22 @@ PrecompLayout precomp_layout(int nz, int nn, int ldm, int nt, int nthr, bool aa,
 static int zero_field_classes(const trap_atom_desc& at, double dnuD_ref, std::vector<double>* dE,
                               std::vector<int>* cls);
 
+// Direction counts: the n_mu x n_chi quadrature plus the zero-weight
+// line-of-sight rings.  Returns an error message, or nullptr.
+static const char* set_directions(Problem& P, const trap_problem_desc* pd) {
+  if (pd->n_los < 0 || pd->n_los > 16) return "n_los must lie in [0, 16]";
+  if (pd->n_los > 0 && !pd->los_mu) return "los_mu is NULL";
+  P.nmu = pd->n_mu;
+  P.nchi = pd->n_chi;
+  P.nlos = pd->n_los;
+  P.los_mu.assign(pd->los_mu, pd->los_mu + pd->n_los);
+  for (double m : P.los_mu)
+    if (!(m > 0.0 && m <= 1.0)) return "line-of-sight mu must lie in (0, 1]";
+  P.ngrid = P.nmu * P.nchi;
+  P.nd = (P.nmu + P.nlos) * P.nchi;
+  return nullptr;
+}
+
 size_t estimate_bytes(const trap_atom_desc* atom, const trap_problem_desc* pd, int store_mask, int* err) {
   *err = 0;
   if (!atom || !pd || pd->n_z < 2 || pd->n_nu < 4 || pd->n_mu < 2 || pd->n_mu % 2 || pd->n_chi < 1 ||
@@ -585,9 +606,10 @@ size_t estimate_bytes(const trap_atom_desc* atom, const trap_problem_desc* pd, i
   Problem P;
   P.nz = pd->n_z;
   P.nn = pd->n_nu;
-  P.nmu = pd->n_mu;
-  P.nchi = pd->n_chi;
-  P.nd = P.nmu * P.nchi;
+  if (set_directions(P, pd)) {
+    *err = 1;
+    return 0;
+  }
   P.ldm = (P.nn + 7) / 8 * 8;
   std::vector<double> dirs, ea, eb;
   angular_setup(P, dirs, ea, eb);
@@ -890,9 +912,7 @@ int build_problem(trap_ctx* ctx, const trap_atom_desc* at, const trap_problem_de
   P = Problem();
   P.nz = pd->n_z;
   P.nn = pd->n_nu;
-  P.nmu = pd->n_mu;
-  P.nchi = pd->n_chi;
-  P.nd = P.nmu * P.nchi;
+  if (const char* why = set_directions(P, pd)) return fail(TRAP_EINVAL, why);
   P.ldm = (P.nn + 7) / 8 * 8;
   const int nz = P.nz, nn = P.nn, nd = P.nd;
   P.x.assign(pd->x, pd->x + nn);

@@ -61,6 +61,8 @@ struct DevBuf {
 //   transitions    t = u * n_lo + l
 struct Problem {
   int nz = 0, nn = 0, nmu = 0, nchi = 0, nd = 0;
+  int nlos = 0, ngrid = 0;                 // line-of-sight rings; quadrature directions nmu * nchi
+  std::vector<double> los_mu;              // [nlos] mu of each zero-weight ring
   int nth = 0, nslot = 0, nu = 0, nl = 0, nt = 0;
   int max_slots_per_theta = 0;
   int ldm = 0;                             // padded row length of the stored kernels (multiple of 8)

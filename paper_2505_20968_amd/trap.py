@@ -30,7 +30,7 @@ EXPORTED = ["trap_create", "trap_destroy", "trap_set_problem", "trap_precompute"
             "trap_profile", "trap_stage_times", "trap_set_path", "trap_set_prd_mode", "trap_gmres_begin",
             "trap_gmres_step_batch", "trap_gmres_end", "trap_precompute_preconditioner",
             "trap_apply_preconditioner", "trap_preconditioner_tables", "trap_set_formal_scheme",
-            "trap_last_error"]
+            "trap_formal_from_field", "trap_emergent_los", "trap_last_error"]
 STAGES = ["comoving", "contract_fp32", "r3", "angular", "backinterp", "formal", "kernel_rows",
           "contract_fp64"]
 
@@ -48,7 +48,8 @@ class ProblemDesc(ctypes.Structure):
     _fields_ = [("n_z", ctypes.c_int), ("n_nu", ctypes.c_int), ("n_mu", ctypes.c_int),
                 ("n_chi", ctypes.c_int), ("x", _dp), ("tau_line", _dp), ("T", _dp), ("xi", _dp),
                 ("a", _dp), ("eps", _dp), ("W_T", _dp), ("v", _dp), ("B", _dp),
-                ("T_ref", ctypes.c_double), ("kappa_c", _dp), ("sigma_c", _dp)]
+                ("T_ref", ctypes.c_double), ("kappa_c", _dp), ("sigma_c", _dp),
+                ("n_los", ctypes.c_int), ("los_mu", _dp)]
 
 
 class Info(ctypes.Structure):
@@ -115,6 +116,8 @@ def load_library(path: str = LIB_PATH):
     lib.trap_set_formal_scheme.argtypes = [vp, ctypes.c_int]
     lib.trap_apply_preconditioner.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.c_int]
     lib.trap_preconditioner_tables.argtypes = [vp, _dp, _dp, _dp]
+    lib.trap_formal_from_field.argtypes = [vp, vp, ctypes.c_int, vp]
+    lib.trap_emergent_los.argtypes = [vp, vp, _dp]
     lib.trap_last_error.restype = ctypes.c_char_p
     for name in EXPORTED:
         if name != "trap_last_error":
@@ -151,9 +154,12 @@ def _problem_desc(prob):
             if v.shape != (prob.n_z, prob.n_nu):
                 raise ValueError(f"{k} must have shape (n_z, n_nu)")
             keep[k] = v
+    los = getattr(prob, "los_mu", None)
+    if los is not None:
+        keep["los_mu"] = np.ascontiguousarray(np.ravel(los), dtype=np.float64)
     ptr = {k: v.ctypes.data_as(_dp) for k, v in keep.items()}
     d = ProblemDesc(n_z=prob.n_z, n_nu=prob.n_nu, n_mu=prob.n_mu, n_chi=prob.n_chi,
-                    T_ref=float(prob.T_ref), **ptr)
+                    T_ref=float(prob.T_ref), n_los=0 if los is None else int(keep["los_mu"].size), **ptr)
     return d, keep
 
 
@@ -226,7 +232,10 @@ class Context:
         d, keep = _problem_desc(prob)
         _check(self.lib.trap_set_problem(self.h, ctypes.byref(_atom_desc(prob.atom)), ctypes.byref(d)))
         self.prob = prob
-        self.shape = (prob.n_z, prob.n_mu * prob.n_chi, prob.n_nu, 4)
+        n_los = 0 if getattr(prob, "los_mu", None) is None else int(np.size(prob.los_mu))
+        self.n_dir_grid = prob.n_mu * prob.n_chi
+        self.n_los = n_los
+        self.shape = (prob.n_z, (prob.n_mu + n_los) * prob.n_chi, prob.n_nu, 4)
 
     def precompute(self, store_mask: int = 3):
         _check(self.lib.trap_precompute(self.h, store_mask))
@@ -301,9 +310,26 @@ class Context:
                 "final_rel_res": st.final_rel_res, "ms_total": st.ms_total, "status": code}
 
     def emergent(self, I) -> np.ndarray:
-        n_up = self.shape[1] // 2
+        n_up = self.n_dir_grid // 2
         out = np.zeros((n_up, self.shape[2], 4))
         _check(self.lib.trap_emergent(self.h, self._vec(I, TRAP_FP64), out.ctypes.data_as(_dp)))
+        return out
+
+    def formal_from_field(self, I, out):
+        """out = Lambda (Sigma I + eps_th) + t (FP64, trap_formal_from_field).  I has
+        either every direction of this context or only its quadrature directions."""
+        if _prec_of(I) != TRAP_FP64 or not I.is_contiguous() or I.dim() != 4:
+            raise TypeError("I must be a contiguous FP64 [z][dir][n][4] tensor")
+        if I.shape[1] not in (self.shape[1], self.n_dir_grid) or (I.shape[0], I.shape[2]) != (
+                self.shape[0], self.shape[2]):
+            raise ValueError(f"I shape {tuple(I.shape)} does not fit {self.shape}")
+        _check(self.lib.trap_formal_from_field(self.h, ctypes.c_void_p(I.data_ptr()), int(I.shape[1]),
+                                               self._vec(out, TRAP_FP64)))
+
+    def emergent_los(self, I) -> np.ndarray:
+        """Emergent Stokes vectors along the lines of sight, [los][chi][n][4]."""
+        out = np.zeros((self.n_los, self.prob.n_chi, self.shape[2], 4))
+        _check(self.lib.trap_emergent_los(self.h, self._vec(I, TRAP_FP64), out.ctypes.data_as(_dp)))
         return out
 
     def set_prd_mode(self, mode: int):
