@@ -35,9 +35,9 @@ from .grids import angular_grid, theta_table, SplineBasis
 from .atom import AtomModel, build_atom
 from .redistribution import faddeeva, F_function, kernel_matrix, kernel_matrix_aa, r3_weights
 from .transfer import (OracleProblem, setup, sigma_apply, formal_solve, apply_operator, solve, emergent,
-                       los_emergent)
+                       los_emergent, fixed_point_map, solve_aar)
 
 __all__ = ["angular_grid", "theta_table", "SplineBasis", "AtomModel", "build_atom",
            "faddeeva", "F_function", "kernel_matrix", "kernel_matrix_aa", "r3_weights",
            "OracleProblem", "setup", "sigma_apply", "formal_solve", "apply_operator", "solve", "emergent",
-           "los_emergent"]
+           "los_emergent", "fixed_point_map", "solve_aar"]

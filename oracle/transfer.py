@@ -124,7 +124,7 @@ def setup(prob, opts=None) -> OracleProblem:
       normalize:    apply the App. E factor f (default True)
       aa:           angle-averaged R_II (Sect. 5.2, Eq. R_AA) in place of the
                     angle-dependent kernel (default False)
-      formal:       'linear' (DELO-linear, default) or 'delopar' formal solver
+      formal:       'linear' (DELO-linear, default), 'delopar' or 'besser' formal solver
     """
     opts = dict({"normalize": True}, **(opts or {}))
     atom = prob.atom
@@ -394,16 +394,46 @@ def _psi_parabolic(m, p):
     return wM, wO, wP
 
 
+def _bezier_weights(m):
+    """Weights of the upwind value, the control point and the current value for
+    int_0^m e^{-t} B(t) dt, t the optical distance back from the current point
+    and B the quadratic Bezier curve from the upwind point (t = m) to the
+    current point (t = 0): its Bernstein factors are (t/m)^2, 2 (t/m)(1 - t/m)
+    and (1 - t/m)^2, integrated through the moments E_k of the exponential."""
+    E0, E1, E2 = _exp_moments(m)
+    wM = E2 / (m * m)
+    wC = 2.0 * (E1 / m - E2 / (m * m))
+    wO = E0 - 2.0 * E1 / m + E2 / (m * m)
+    return wM, wC, wO
+
+
+def _besser_control(SM, SO, SP, hM, hP):
+    """Control point of the Bezier source between the upwind (M) and current
+    (O) points: the tangent at O of the parabola through M, O, P (zero where O
+    is a local extremum), followed back half the interval, and kept inside the
+    range spanned by S_M and S_O (no overshoot).  Componentwise."""
+    dM = (SO - SM) / hM
+    dP = (SP - SO) / hP
+    dO = np.where(dM * dP > 0.0, (hM * dP + hP * dM) / (hM + hP), 0.0)
+    c = SO - 0.5 * hM * dO
+    return np.clip(c, np.minimum(SM, SO), np.maximum(SM, SO))
+
+
 def formal_solve(op, eps, boundary=True, I_bottom=None, scheme=None):
     """Lambda eps (+ t if boundary): DELO sweeps along every ray.
 
     scheme 'linear' (default, or op.opts['formal']): DELO-linear, S and K'I
     linear between the upwind and current points.  'delopar': S parabolic
     through the upwind, current and downwind points, K'I linear (the
-    DELOPAR integrator named in Sect. 3); the last point of a ray, which has
-    no downwind point, takes the DELO-linear step."""
+    DELOPAR integrator named in Sect. 3).  'besser': S a quadratic Bezier
+    curve between the upwind and current points whose control point follows
+    the three-point tangent at the current point and is kept inside the
+    range of the two end values (no overshoot; this makes Lambda slightly
+    nonlinear in eps, Sect. 6.1), K'I linear.  In both three-point schemes
+    the last point of a ray, which has no downwind point, takes the
+    DELO-linear step."""
     scheme = scheme or op.opts.get("formal", "linear")
-    if scheme not in ("linear", "delopar"):
+    if scheme not in ("linear", "delopar", "besser"):
         raise ValueError(f"unknown formal scheme {scheme}")
     prob = op.prob
     nz, nd, nn = prob.n_z, prob.n_dir, prob.n_nu
@@ -437,6 +467,12 @@ def formal_solve(op, eps, boundary=True, I_bottom=None, scheme=None):
                 xd = 0.5 * (ratio[zc, o] + ratio[zd, o]) * dtl[min(zc, zd)] / abs(mu[o])
                 wM, wO, wP = _psi_parabolic(x, xd)
                 src = wM[:, None] * S[zu, o] + wO[:, None] * S[zc, o] + wP[:, None] * S[zd, o]
+            elif scheme == "besser" and k + 1 < nz:
+                zd = order[k + 1]
+                xd = 0.5 * (ratio[zc, o] + ratio[zd, o]) * dtl[min(zc, zd)] / abs(mu[o])
+                c = _besser_control(S[zu, o], S[zc, o], S[zd, o], x[:, None], xd[:, None])
+                wM, wC, wO = _bezier_weights(x)
+                src = wM[:, None] * S[zu, o] + wC[:, None] * c + wO[:, None] * S[zc, o]
             else:
                 src = pu[:, None] * S[zu, o] + pc[:, None] * S[zc, o]
             b = np.einsum("nij,nj->ni", rhs, Icur) + src
@@ -474,6 +510,50 @@ def solve(op, tol=1e-12, method="gmres", restart=200, maxiter=4000):
     if info != 0:
         raise RuntimeError(f"oracle GMRES did not converge (info={info})")
     return xsol.reshape(shape)
+
+
+def fixed_point_map(op, I):
+    """G(I) = Lambda (Sigma I + eps_th) + t with the problem's formal solver.
+    The solution of Eq. linear_system is its fixed point; with BESSER, whose
+    Lambda is not linear, the fixed point is the definition of the solution."""
+    return formal_solve(op, sigma_apply(op, I) + op.eps_th, boundary=True)
+
+
+def solve_aar(op, tol=1e-12, omega=1.0, beta=1.0, depth=7, period=6, maxiter=3000, precond=None):
+    """Alternating Anderson-Richardson iteration (Sect. 5.1, the method of the
+    cited AAR paper) for the fixed point of G.  With r = G(x) - x and
+    f = M r (M = precond, a callable, or the identity), every step is a
+    Richardson step x <- x + omega f except every `period`-th, which is an
+    Anderson step x <- x + beta f - (X + beta F) gamma, gamma the least-squares
+    solution of F gamma = f over the last `depth` differences F of f (X those
+    of x).  Stops when ||r|| / ||G(0)|| < tol, the paper's relative residual.
+    Returns (x, steps)."""
+    b = fixed_point_map(op, np.zeros_like(op.eps_th))
+    bn = np.linalg.norm(b)
+    x = np.zeros_like(b)
+    r = b - x
+    Xh, Fh = [], []
+    x_prev = f_prev = None
+    for k in range(maxiter):
+        if np.linalg.norm(r) / bn < tol:
+            return x, k
+        f = precond(r) if precond is not None else r
+        if x_prev is not None and depth > 0:
+            Xh.append((x - x_prev).ravel())
+            Fh.append((f - f_prev).ravel())
+            if len(Xh) > depth:
+                Xh.pop(0)
+                Fh.pop(0)
+        x_prev, f_prev = x, f
+        if depth > 0 and (k + 1) % period == 0 and Fh:
+            F = np.stack(Fh, axis=1)
+            X = np.stack(Xh, axis=1)
+            gamma = np.linalg.lstsq(F, f.ravel(), rcond=None)[0]
+            x = x + beta * f - ((X + beta * F) @ gamma).reshape(x.shape)
+        else:
+            x = x + omega * f
+        r = fixed_point_map(op, x) - x
+    raise RuntimeError("oracle AAR did not converge")
 
 
 def emergent(op, I):
