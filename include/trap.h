@@ -227,12 +227,19 @@ int trap_formal_solve(trap_ctx* ctx, const void* eps, void* I, int with_boundary
 /* Formal solver of Lambda (Sect. 3).  TRAP_FORMAL_DELO_LINEAR (default): S and
  * K'I linear between the upwind and current points.  TRAP_FORMAL_DELOPAR: S
  * integrated with the parabola through the upwind, current and downwind
- * points (weights from the moments int_0^m t^k e^{-t} dt, FP64), K'I linear;
- * a ray's last point takes the DELO-linear step.  Applies to trap_formal_solve,
- * the operator and the right-hand side, so it is set before trap_precompute
- * (TRAP_ESTATE when changed after it for the loaded problem; a new problem
- * frees it again).  The preconditioner's scalar sweep stays DELO-linear. */
-enum { TRAP_FORMAL_DELO_LINEAR = 0, TRAP_FORMAL_DELOPAR = 1 };
+ * points (weights from the moments int_0^m t^k e^{-t} dt, FP64), K'I linear.
+ * TRAP_FORMAL_BESSER: S a quadratic Bezier curve between the upwind and
+ * current points whose control point follows the tangent at the current point
+ * of the parabola through the three points (slope zero at a local extremum)
+ * and is kept inside the range of the two end values, per Stokes component;
+ * K'I linear.  The range limit makes Lambda slightly nonlinear (Sect. 6.1), so
+ * a BESSER problem is solved by trap_aar_solve (GMRES returns TRAP_EINVAL).
+ * In both three-point schemes a ray's last point takes the DELO-linear step.
+ * Applies to trap_formal_solve, the operator, the right-hand side and
+ * trap_formal_from_field, so it is set before trap_precompute (TRAP_ESTATE
+ * when changed after it for the loaded problem; a new problem frees it
+ * again).  The preconditioner's scalar sweep stays DELO-linear. */
+enum { TRAP_FORMAL_DELO_LINEAR = 0, TRAP_FORMAL_DELOPAR = 1, TRAP_FORMAL_BESSER = 2 };
 int trap_set_formal_scheme(trap_ctx* ctx, int scheme);
 
 /* y = (Id - Lambda Sigma) x, the operator of Eq. linear_system. */
@@ -247,6 +254,35 @@ int trap_rhs(trap_ctx* ctx, double* b_out_device);
  * refinement updates are FP64.  I is FP64 device memory: initial guess in,
  * solution out.  Returns TRAP_ENOCONV if tol is not reached.  Synchronises. */
 int trap_gmres_solve(trap_ctx* ctx, const trap_solve_opts* opts, double* I, trap_solve_stats* stats);
+
+/* Options of the alternating Anderson-Richardson iteration (Sect. 5.1; the
+ * method of the AAR paper the text cites). */
+typedef struct {
+  double tol;          /* stop when ||G(I) - I|| / ||G(0)|| < tol, G(I) = Lambda (Sigma I + eps_th) + t */
+  int max_iters;       /* residual evaluations allowed */
+  int depth;           /* Anderson history: the last `depth` differences, 0..16 (0 = Richardson) */
+  int period;          /* every period-th step is an Anderson step, >= 1 */
+  double omega;        /* Richardson relaxation, > 0 */
+  double beta;         /* Anderson relaxation, > 0 */
+  int zero_guess;      /* nonzero: I is set to zero first (its first G is the right-hand side) */
+  int precond_sweeps;  /* 0, or k in [1, 64]: f = M r with k block-Jacobi steps of the
+                          physics-based preconditioner (FP64; needs
+                          trap_precompute_preconditioner) */
+} trap_aar_opts;
+
+/* Solve I = G(I) = Lambda (Sigma I + eps_th) + t, the fixed-point form of
+ * Eq. linear_system, by alternating Anderson-Richardson iteration, all in FP64
+ * on the device: with r = G(I) - I and f = M r (M the identity or the
+ * preconditioner), each step is I <- I + omega f, except every period-th,
+ * which is I <- I + beta f - (X + beta F) gamma with gamma the least-squares
+ * coefficients of f on the last `depth` differences F of f (X those of I;
+ * normal equations solved on the host).  It needs no linearity of Lambda, so
+ * it also solves BESSER problems.  I is FP64 device memory: initial guess in,
+ * solution out.  stats: outer_steps = Anderson steps, inner_iters = residual
+ * evaluations, applies_fp64 = Sigma applies.  The (4 + 2 depth) FP64 work
+ * vectors are allocated at the first call (not counted by trap_footprint).
+ * Returns TRAP_ENOCONV if tol is not reached.  Synchronises. */
+int trap_aar_solve(trap_ctx* ctx, const trap_aar_opts* opts, double* I, trap_solve_stats* stats);
 
 /* Batched solving for a serving loop: the solve of trap_gmres_solve split into
  * steps so that many contexts (requests) advance together.

@@ -440,7 +440,8 @@ int trap_set_prd_mode(trap_ctx* ctx, int mode) {
 
 int trap_set_formal_scheme(trap_ctx* ctx, int scheme) {
   if (!ctx) return fail(TRAP_EINVAL, "null context");
-  if (scheme != TRAP_FORMAL_DELO_LINEAR && scheme != TRAP_FORMAL_DELOPAR) return fail(TRAP_EINVAL, "unknown formal scheme");
+  if (scheme != TRAP_FORMAL_DELO_LINEAR && scheme != TRAP_FORMAL_DELOPAR && scheme != TRAP_FORMAL_BESSER)
+    return fail(TRAP_EINVAL, "unknown formal scheme");
   if (ctx->pre.done && scheme != ctx->formal_scheme)
     return fail(TRAP_ESTATE, "the formal scheme is fixed once trap_precompute has run for the problem");
   ctx->formal_scheme = scheme;

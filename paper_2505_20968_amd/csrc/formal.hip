@@ -95,16 +95,9 @@ __device__ inline void delo_solve(const T* k, T p, const T* b, T* xout) {
   }
 }
 
-// DELOPAR (Sect. 3): the source S integrated against e^{-t} over the upwind
-// interval [0, m] (t from the current point O back to the upwind point M)
-// with the parabola through M (t = m), O (t = 0) and the downwind point P
-// (t = -p).  With E_k = int_0^m t^k e^{-t} dt:
-//   w_M = (E2 + p E1) / (m (m + p)),   w_O = -(E2 + (p - m) E1 - m p E0) / (m p),
-//   w_P = (E2 - m E1) / (p (m + p)).
-// E_k from the closed forms, or below m = 0.5 (where they cancel) from
-// sum_j (-1)^j m^(k+j+1) / (j! (k+j+1)).  Always FP64.
-__device__ inline void parabolic_weights(double m, double p, double& wM, double& wO, double& wP) {
-  double E0, E1, E2;
+// E_k = int_0^m t^k e^{-t} dt for k = 0, 1, 2: the closed forms, or below
+// m = 0.5 (where they cancel) sum_j (-1)^j m^(k+j+1) / (j! (k+j+1)).  FP64.
+__device__ inline void exp_moments(double m, double& E0, double& E1, double& E2) {
   if (m < 0.5) {
     // E_k = m^(k+1) sum_j t_j / (k + j + 1), t_j = (-m)^j / j!; 16 terms
     // leave a relative remainder below 1e-16 for m < 0.5 (unrolled, so the
@@ -126,12 +119,49 @@ __device__ inline void parabolic_weights(double m, double p, double& wM, double&
     E1 = E0 - m * ex;
     E2 = 2.0 * E1 - m * m * ex;
   }
+}
+
+// DELOPAR (Sect. 3): the source S integrated against e^{-t} over the upwind
+// interval [0, m] (t from the current point O back to the upwind point M)
+// with the parabola through M (t = m), O (t = 0) and the downwind point P
+// (t = -p):
+//   w_M = (E2 + p E1) / (m (m + p)),   w_O = -(E2 + (p - m) E1 - m p E0) / (m p),
+//   w_P = (E2 - m E1) / (p (m + p)).
+__device__ inline void parabolic_weights(double m, double p, double& wM, double& wO, double& wP) {
+  double E0, E1, E2;
+  exp_moments(m, E0, E1, E2);
   wM = (E2 + p * E1) / (m * (m + p));
   wO = -(E2 + (p - m) * E1 - m * p * E0) / (m * p);
   wP = (E2 - m * E1) / (p * (m + p));
 }
 
-// PAR: 0 = DELO-linear only, 1 = DELOPAR only, -1 = the scheme argument decides
+// BESSER (Sect. 3): S over the upwind interval is the quadratic Bezier curve
+// from S_M to S_O with one control point c; its Bernstein factors (t/m)^2,
+// 2 (t/m)(1 - t/m), (1 - t/m)^2 against e^{-t} give
+//   w_M = E2/m^2,   w_C = 2 (E1/m - E2/m^2),   w_O = E0 - 2 E1/m + E2/m^2.
+__device__ inline void bezier_weights(double m, double& wM, double& wC, double& wO) {
+  double E0, E1, E2;
+  exp_moments(m, E0, E1, E2);
+  const double a = E1 / m, b = E2 / (m * m);
+  wM = b;
+  wC = 2.0 * (a - b);
+  wO = E0 - 2.0 * a + b;
+}
+
+// The control point: the tangent at O of the parabola through M, O and P
+// (slope zero where O is a local extremum of S), followed back half the
+// upwind interval, and kept inside the range of S_M and S_O so that the
+// curve does not overshoot.  hM, hP are the upwind and downwind optical steps.
+template <typename T>
+__device__ inline T besser_control(T SM, T SO, T SP, T hM, T hP) {
+  const T dM = (SO - SM) / hM, dP = (SP - SO) / hP;
+  const T dO = dM * dP > T(0) ? (hM * dP + hP * dM) / (hM + hP) : T(0);
+  const T c = SO - T(0.5) * hM * dO;
+  return fmin(fmax(c, fmin(SM, SO)), fmax(SM, SO));
+}
+
+// PAR: 0 = DELO-linear only, 1 = DELOPAR only, 2 = BESSER only, -1 = the scheme
+// argument decides between DELO-linear and DELOPAR
 template <typename T, int PAR>
 __device__ __forceinline__ void formal_body(int bx, int nz, int nd, int nn, const double* __restrict__ mu,
                                             const double* __restrict__ tau, const double* __restrict__ K8,
@@ -204,6 +234,16 @@ __device__ __forceinline__ void formal_body(int bx, int nz, int nd, int nn, cons
       const T inP = T(kn[6]);
       for (int s = 0; s < 4; ++s)
         b[s] = ex * Icur[s] - pu * kv[s] + T(wM) * Su[s] + T(wO) * Sc[s] + T(wP) * (en[s] * inP);
+    } else if (PAR == 2 && step + 1 < nz) {
+      const double hM = 0.5 * (double(ru) + kr[7]) * fabs(tz - tzc) / fabs(m);
+      const double hP = 0.5 * (kr[7] + kn[7]) * fabs(tzc - tn) / fabs(m);
+      double wM, wC, wO;
+      bezier_weights(hM, wM, wC, wO);
+      const T inP = T(kn[6]);
+      for (int s = 0; s < 4; ++s) {
+        const T c = besser_control<T>(Su[s], Sc[s], en[s] * inP, T(hM), T(hP));
+        b[s] = ex * Icur[s] - pu * kv[s] + T(wM) * Su[s] + T(wC) * c + T(wO) * Sc[s];
+      }
     } else {
       for (int s = 0; s < 4; ++s) b[s] = ex * Icur[s] - pu * kv[s] + pu * Su[s] + pc * Sc[s];
     }
@@ -381,14 +421,16 @@ int formal_apply(trap_ctx* ctx, const void* eps, void* I, int with_boundary, int
   Problem& P = ctx->pb;
   const int rays = P.nd * P.nn;
   const int pr = prof_begin(ctx, TRAP_STAGE_FORMAL);
-  const bool par = ctx->formal_scheme == TRAP_FORMAL_DELOPAR;
+  const int sch = ctx->formal_scheme;
   if (prec == TRAP_FP64) {
-    auto kern = par ? k_formal<double, 1> : k_formal<double, 0>;
+    auto kern = sch == TRAP_FORMAL_BESSER ? k_formal<double, 2>
+                : (sch == TRAP_FORMAL_DELOPAR ? k_formal<double, 1> : k_formal<double, 0>);
     hipLaunchKernelGGL(kern, dim3(ceil_div(rays, 64)), dim3(64), 0, ctx->stream, P.nz, P.nd, P.nn, P.d_mu,
                        P.d_tau, ctx->pre.d_K, P.d_WT, static_cast<const double*>(eps), static_cast<double*>(I),
                        with_boundary);
   } else if (prec == TRAP_FP32) {
-    auto kern = par ? k_formal<float, 1> : k_formal<float, 0>;
+    auto kern = sch == TRAP_FORMAL_BESSER ? k_formal<float, 2>
+                : (sch == TRAP_FORMAL_DELOPAR ? k_formal<float, 1> : k_formal<float, 0>);
     hipLaunchKernelGGL(kern, dim3(ceil_div(rays, 64)), dim3(64), 0, ctx->stream, P.nz, P.nd, P.nn, P.d_mu,
                        P.d_tau, ctx->pre.d_K, P.d_WT, static_cast<const float*>(eps), static_cast<float*>(I),
                        with_boundary);

@@ -243,6 +243,8 @@ int gmres_begin(trap_ctx* ctx, const trap_solve_opts* opts, double* I) {
   if (!opts || !I) return fail(TRAP_EINVAL, "null argument");
   if (!(opts->tol > 0) || opts->restart < 1 || opts->max_iters < 0)
     return fail(TRAP_EINVAL, "bad solver options");
+  if (ctx->formal_scheme == TRAP_FORMAL_BESSER)
+    return fail(TRAP_EINVAL, "BESSER makes Lambda nonlinear: solve with trap_aar_solve");
   const int inner = opts->inner;
   if (inner != TRAP_FP64 && inner != TRAP_FP32) return fail(TRAP_EINVAL, "bad inner precision");
   if (inner == TRAP_FP32 && !ctx->pre.d_M32) return fail(TRAP_ESTATE, "FP32 kernels not stored");

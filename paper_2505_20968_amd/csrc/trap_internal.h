@@ -187,6 +187,10 @@ struct Work {
   double *pc_x = nullptr, *pc_e = nullptr, *pc_res = nullptr;
   double *pc_h = nullptr;     // [z][2][nn]: comoving vector and its spline second derivatives
   double *pc_gc = nullptr;    // [z][class][nn]: comoving interpolation of each Doppler class's angular sum
+  // alternating Anderson-Richardson: r, f, previous x and f, then `aar_cap`
+  // differences of x and of f, all N long; block partial dot products
+  double *aar = nullptr, *aar_part = nullptr;
+  int aar_cap = -1;
 };
 
 struct ProfRec {

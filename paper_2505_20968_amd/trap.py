@@ -20,7 +20,7 @@ TRAP_FP64 = 0
 TRAP_FP32 = 1
 TRAP_PATH_AUTO, TRAP_PATH_FUSED, TRAP_PATH_CHUNKED = 0, 1, 2
 TRAP_PRD_AD, TRAP_PRD_AA = 0, 1
-TRAP_FORMAL_DELO_LINEAR, TRAP_FORMAL_DELOPAR = 0, 1
+TRAP_FORMAL_DELO_LINEAR, TRAP_FORMAL_DELOPAR, TRAP_FORMAL_BESSER = 0, 1, 2
 STATUS = {0: "TRAP_OK", -1: "TRAP_EINVAL", -2: "TRAP_ENOMEM", -3: "TRAP_EDEVICE",
           -4: "TRAP_ENOCONV", -5: "TRAP_ESTATE", -6: "TRAP_ENAN"}
 
@@ -30,7 +30,7 @@ EXPORTED = ["trap_create", "trap_destroy", "trap_set_problem", "trap_precompute"
             "trap_profile", "trap_stage_times", "trap_set_path", "trap_set_prd_mode", "trap_gmres_begin",
             "trap_gmres_step_batch", "trap_gmres_end", "trap_precompute_preconditioner",
             "trap_apply_preconditioner", "trap_preconditioner_tables", "trap_set_formal_scheme",
-            "trap_formal_from_field", "trap_emergent_los", "trap_last_error"]
+            "trap_formal_from_field", "trap_emergent_los", "trap_aar_solve", "trap_last_error"]
 STAGES = ["comoving", "contract_fp32", "r3", "angular", "backinterp", "formal", "kernel_rows",
           "contract_fp64"]
 
@@ -64,6 +64,12 @@ class Info(ctypes.Structure):
 class SolveOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("restart", ctypes.c_int), ("max_iters", ctypes.c_int),
                 ("max_outer", ctypes.c_int), ("inner", ctypes.c_int), ("inner_tol", ctypes.c_double),
+                ("zero_guess", ctypes.c_int), ("precond_sweeps", ctypes.c_int)]
+
+
+class AarOpts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("max_iters", ctypes.c_int), ("depth", ctypes.c_int),
+                ("period", ctypes.c_int), ("omega", ctypes.c_double), ("beta", ctypes.c_double),
                 ("zero_guess", ctypes.c_int), ("precond_sweeps", ctypes.c_int)]
 
 
@@ -117,6 +123,7 @@ def load_library(path: str = LIB_PATH):
     lib.trap_apply_preconditioner.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.c_int]
     lib.trap_preconditioner_tables.argtypes = [vp, _dp, _dp, _dp]
     lib.trap_formal_from_field.argtypes = [vp, vp, ctypes.c_int, vp]
+    lib.trap_aar_solve.argtypes = [vp, ctypes.POINTER(AarOpts), vp, ctypes.POINTER(SolveStats)]
     lib.trap_emergent_los.argtypes = [vp, vp, _dp]
     lib.trap_last_error.restype = ctypes.c_char_p
     for name in EXPORTED:
@@ -241,7 +248,8 @@ class Context:
         _check(self.lib.trap_precompute(self.h, store_mask))
 
     def set_formal_scheme(self, scheme: int):
-        """TRAP_FORMAL_DELO_LINEAR (0) or TRAP_FORMAL_DELOPAR (1), before precompute."""
+        """TRAP_FORMAL_DELO_LINEAR (0), TRAP_FORMAL_DELOPAR (1) or TRAP_FORMAL_BESSER (2),
+        before precompute."""
         _check(self.lib.trap_set_formal_scheme(self.h, int(scheme)))
 
     def precompute_preconditioner(self):
@@ -288,6 +296,20 @@ class Context:
                 "applies_fp64": st.applies_fp64, "applies_fp32": st.applies_fp32, "applies_grouped": st.applies_grouped,
                 "applies_precond": st.applies_precond,
                 "final_rel_res": st.final_rel_res, "ms_total": st.ms_total, "status": code}
+
+    def aar_solve(self, I, tol: float = 1e-8, max_iters: int = 2000, depth: int = 7, period: int = 6,
+                  omega: float = 1.0, beta: float = 1.0, zero_guess: bool = False, precond_sweeps: int = 0,
+                  raise_on_noconv: bool = True):
+        """Alternating Anderson-Richardson solve (trap_aar_solve, FP64)."""
+        o = AarOpts(tol=tol, max_iters=max_iters, depth=depth, period=period, omega=omega, beta=beta,
+                    zero_guess=int(zero_guess), precond_sweeps=int(precond_sweeps))
+        st = SolveStats()
+        code = self.lib.trap_aar_solve(self.h, ctypes.byref(o), self._vec(I, TRAP_FP64), ctypes.byref(st))
+        if code != 0 and (raise_on_noconv or code != -4):
+            _check(code)
+        return {"anderson_steps": st.outer_steps, "residuals": st.inner_iters, "applies_fp64": st.applies_fp64,
+                "applies_precond": st.applies_precond, "final_rel_res": st.final_rel_res, "ms_total": st.ms_total,
+                "status": code}
 
     def gmres_begin(self, I, tol: float = 1e-8, restart: int = 40, max_iters: int = 2000,
                     inner: int = TRAP_FP64, max_outer: int = 8, inner_tol: float = 1e-7,
