@@ -153,3 +153,38 @@ def test_footprint_and_errors():
             c.emergent_los(torch.zeros(c.shape, dtype=torch.float64, device="cuda"))
     finally:
         c.close()
+
+
+def test_grouped_solve_with_rings_equals_alone():
+    """A problem with line-of-sight rings solved together with one without
+    (FP32 applies in shared launches) gives bitwise the solution it gives
+    alone."""
+    torch = _torch()
+    from paper_2505_20968_amd import TRAP_FP32, gmres_step_batch
+    probs = [tiny(**CASES["two_level_moving_seeded"], los_mu=LOS),
+             tiny(n_z=5, n_nu=21, x_max=6, n_mu=4, n_chi=4, B=(30.0, 1.1, 0.4), a=1e-2, eps=5e-2, v_z=1.0, seed=4)]
+    opts = dict(tol=1e-10, restart=30, max_iters=600, max_outer=10, inner=TRAP_FP32, inner_tol=1e-6,
+                zero_guess=True)
+    alone = []
+    for p in probs:
+        c = _ctx(p)
+        x = torch.zeros(c.shape, dtype=torch.float64, device="cuda")
+        c.gmres_solve(x, **opts)
+        alone.append(x.cpu().numpy())
+        c.close()
+    ctxs = [_ctx(p) for p in probs]
+    xs = [torch.zeros(c.shape, dtype=torch.float64, device="cuda") for c in ctxs]
+    try:
+        for c, x in zip(ctxs, xs):
+            c.gmres_begin(x, **opts)
+        for _ in range(2000):
+            if all(s != 1 for s in gmres_step_batch(ctxs)):
+                break
+        stats = [c.gmres_end() for c in ctxs]
+        print(f"[line-of-sight batch] {stats}", flush=True)
+        assert all(s["applies_grouped"] > 0 for s in stats)
+        for x, a in zip(xs, alone):
+            assert np.array_equal(x.cpu().numpy(), a)
+    finally:
+        for c in ctxs:
+            c.close()
