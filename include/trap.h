@@ -9,15 +9,19 @@
  * with Sigma the scattering operator (Eq. eps_sc_l with R = R_II + R_III,
  * Eqs. RQIIKKp, G and RIIIQKKp, evaluated in the comoving frame of Sect. 4.1
  * through the intermediate W of App. D, normalised as in App. E) and Lambda the
- * formal solution (Sect. 3, DELO-linear ray sweeps).
+ * formal solution (Sect. 3, ray sweeps: DELO-linear, DELOPAR or BESSER).  It
+ * is solved by mixed-precision GMRES (Sect. 5.1), optionally with the
+ * physics-based preconditioner of Sect. 5.3 and App. F, or by alternating
+ * Anderson-Richardson iteration (the only choice with BESSER).
  *
  * Conventions shared by every entry point
  * ---------------------------------------
  * Vector layout: a Stokes field or emissivity is a contiguous device array
  *   V[z][o][n][s]  (n_z x n_dir x n_nu x 4), z = height index from the bottom
  *   (z_min) to the top, o = direction index mu-major (mu ascending from -1 to
- *   1, n_mu/2 Gauss-Legendre nodes per hemisphere) and chi-minor (chi_k =
- *   2 pi k / n_chi), n = frequency node, s = Stokes (I, Q, U, V).
+ *   1, n_mu/2 Gauss-Legendre nodes per hemisphere, then any line-of-sight
+ *   rings) and chi-minor (chi_k = 2 pi k / n_chi), n = frequency node,
+ *   s = Stokes (I, Q, U, V).
  *   Positive Q is parallel to the limb (perpendicular to the vertical plane
  *   containing the ray); (e_Q, e_perp, Omega) is right-handed; the V sign makes
  *   eta_V = (phi_r - phi_b) cos(theta_B)/2.
@@ -30,9 +34,10 @@
  *   allocation it makes and frees it in trap_destroy.
  * Streams: work is enqueued on the stream given to trap_create (a hipStream_t,
  *   NULL = default stream).  trap_set_problem (after its host work),
- *   trap_precompute, trap_apply_sigma, trap_formal_solve, trap_apply_operator
- *   and trap_gmres_begin are asynchronous; trap_gmres_solve, trap_gmres_end
- *   and trap_emergent synchronise the stream.
+ *   trap_precompute, trap_apply_sigma, trap_formal_solve, trap_apply_operator,
+ *   trap_formal_from_field and trap_gmres_begin are asynchronous;
+ *   trap_gmres_solve, trap_gmres_end, trap_aar_solve, trap_emergent and
+ *   trap_emergent_los synchronise the stream.
  * Errors: every call returns a trap_status; negative values are failures and
  *   trap_last_error() returns a thread-local message.  A failed call leaves the
  *   context usable.  No call aborts or throws.
@@ -221,7 +226,8 @@ int trap_preconditioner_tables(trap_ctx* ctx, double* phi, double* c, double* ll
  * thermal emissivity eps_th is added.  I and eps are device arrays in `prec`. */
 int trap_apply_sigma(trap_ctx* ctx, const void* I, void* eps, int prec, int add_thermal);
 
-/* I = Lambda eps (+ t if with_boundary): DELO-linear sweeps (Sect. 3). */
+/* I = Lambda eps (+ t if with_boundary): ray sweeps with the context's formal
+ * scheme (Sect. 3; trap_set_formal_scheme). */
 int trap_formal_solve(trap_ctx* ctx, const void* eps, void* I, int with_boundary, int prec);
 
 /* Formal solver of Lambda (Sect. 3).  TRAP_FORMAL_DELO_LINEAR (default): S and
@@ -242,7 +248,8 @@ int trap_formal_solve(trap_ctx* ctx, const void* eps, void* I, int with_boundary
 enum { TRAP_FORMAL_DELO_LINEAR = 0, TRAP_FORMAL_DELOPAR = 1, TRAP_FORMAL_BESSER = 2 };
 int trap_set_formal_scheme(trap_ctx* ctx, int scheme);
 
-/* y = (Id - Lambda Sigma) x, the operator of Eq. linear_system. */
+/* y = (Id - Lambda Sigma) x, the operator of Eq. linear_system (with BESSER,
+ * whose Lambda is not linear, x - Lambda(Sigma x) evaluated as written). */
 int trap_apply_operator(trap_ctx* ctx, const void* x, void* y, int prec);
 
 /* Copy b = Lambda eps_th + t (FP64, computed by trap_precompute) into b_out. */
