@@ -273,8 +273,17 @@ typedef struct {
   double beta;         /* Anderson relaxation, > 0 */
   int zero_guess;      /* nonzero: I is set to zero first (its first G is the right-hand side) */
   int precond_sweeps;  /* 0, or k in [1, 64]: f = M r with k block-Jacobi steps of the
-                          physics-based preconditioner (FP64; needs
-                          trap_precompute_preconditioner) */
+                          physics-based preconditioner (needs
+                          trap_precompute_preconditioner; its scalar sweeps in the
+                          precision of the iteration they serve) */
+  trap_prec inner;     /* TRAP_FP64: the iteration above on G in FP64.  TRAP_FP32: defect
+                          correction, each step the FP64 residual r = G(I) - I, then the
+                          iteration above on d = r + Lambda Sigma d with the FP32 operator
+                          (for BESSER its Jacobian at I: each point's branch follows the
+                          source of I), to inner_tol ||r||, and I <- I + d, at most
+                          max_outer times */
+  double inner_tol;    /* 0 < inner_tol < 1 (TRAP_FP32 only) */
+  int max_outer;       /* >= 1 (TRAP_FP32 only) */
 } trap_aar_opts;
 
 /* Solve I = G(I) = Lambda (Sigma I + eps_th) + t, the fixed-point form of
@@ -285,9 +294,10 @@ typedef struct {
  * coefficients of f on the last `depth` differences F of f (X those of I;
  * normal equations solved on the host).  It needs no linearity of Lambda, so
  * it also solves BESSER problems.  I is FP64 device memory: initial guess in,
- * solution out.  stats: outer_steps = Anderson steps, inner_iters = residual
- * evaluations, applies_fp64 = Sigma applies.  The (4 + 2 depth) FP64 work
- * vectors are allocated at the first call (not counted by trap_footprint).
+ * solution out.  stats: outer_steps = Anderson steps, inner_iters = residuals
+ * of the iteration, applies_fp64 / applies_fp32 = evaluations of G (FP64) and
+ * of the FP32 operator.  The (8 + 2 depth) FP64 work vectors are allocated at
+ * the first call with that depth (not counted by trap_footprint).
  * Returns TRAP_ENOCONV if tol is not reached.  Synchronises. */
 int trap_aar_solve(trap_ctx* ctx, const trap_aar_opts* opts, double* I, trap_solve_stats* stats);
 

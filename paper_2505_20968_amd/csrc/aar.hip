@@ -149,99 +149,74 @@ bool normal_solve(std::vector<double> A, std::vector<double> h, int n, std::vect
 
 }  // namespace
 
-int aar_solve(trap_ctx* ctx, const trap_aar_opts* o, double* x, trap_solve_stats* st) {
-  if (!ctx->has_problem || !ctx->pre.done) return fail(TRAP_ESTATE, "precompute not run");
-  if (!o || !x) return fail(TRAP_EINVAL, "null argument");
-  if (!(o->tol > 0) || o->max_iters < 0 || o->depth < 0 || o->depth > kAarMax || o->period < 1 ||
-      !(o->omega > 0) || !(o->beta > 0))
-    return fail(TRAP_EINVAL, "bad AAR options (depth in [0, 16], period >= 1, omega, beta > 0)");
-  if (o->precond_sweeps < 0 || o->precond_sweeps > 64)
-    return fail(TRAP_EINVAL, "preconditioner sweeps must be in [0, 64]");
-  if (o->precond_sweeps > 0 && !ctx->pre.pc_done) return fail(TRAP_ESTATE, "preconditioner tables not computed");
-  const auto t0 = std::chrono::steady_clock::now();
-  const Problem& P = ctx->pb;
-  const long long N = 4LL * P.nz * P.nd * P.nn;
-  Work& K = ctx->wk;
-  TRAP_TRY(ensure_work(ctx, TRAP_FP64));
-  if (o->precond_sweeps > 0) TRAP_TRY(precond_ensure(ctx));
-  if (!K.aar_part) TRAP_TRY(dalloc_t(ctx, &K.aar_part, (size_t)kDotBlocks * (kAarMax + 1)));
-  if (K.aar_cap < o->depth) {
-    TRAP_TRY(dalloc_t(ctx, &K.aar, (size_t)(4 + 2 * o->depth) * N));
-    K.aar_cap = o->depth;
-  }
-  const int cap = K.aar_cap, depth = o->depth;
-  double* r = K.aar;
-  double* f = o->precond_sweeps > 0 ? K.aar + N : r;
-  double* xp = K.aar + 2 * N;
-  double* fp = K.aar + 3 * N;
-  auto Xs = [&](int j) { return K.aar + (size_t)(4 + j) * N; };
-  auto Fs = [&](int j) { return K.aar + (size_t)(4 + cap + j) * N; };
+// The AAR loop on the iterate x whose residual r = res(x) is already in r:
+// stops when ||r|| <= target (status TRAP_OK), after `max_evals` further
+// residuals (TRAP_ENOCONV) or at a non-finite residual (TRAP_ENAN); returns
+// the last ||r|| in *rnorm.  The loop's work vectors and history are the
+// context's AAR block (f, previous x and f, the differences).
+struct AarBufs {
+  double *f, *xp, *fp;
+  double* X[kAarMax];
+  double* F[kAarMax];
+};
 
-  trap_solve_stats S{};
-  double bn2 = 0.0;
-  TRAP_TRY(dots(ctx, N, ctx->pre.d_b, {ctx->pre.d_b}, &bn2));
-  const double bn = std::sqrt(bn2);
-  if (!(bn > 0.0) || !std::isfinite(bn)) return fail(TRAP_EINVAL, "zero or non-finite right-hand side");
-  if (o->zero_guess) {
-    // G(0) is the right-hand side Lambda eps_th + t
-    TRAP_HIP(hipMemsetAsync(x, 0, N * sizeof(double), ctx->stream));
-    TRAP_HIP(hipMemcpyAsync(r, ctx->pre.d_b, N * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
-  } else {
-    TRAP_TRY(fixed_point_residual(ctx, N, x, r));
-    ++S.applies_fp64;
-    ++S.inner_iters;
-  }
+template <typename Res>
+int aar_loop(trap_ctx* ctx, long long N, const trap_aar_opts* o, const AarBufs& B, double* x, double* r,
+             double target, int max_evals, int pc_prec, Res&& res, trap_solve_stats& S, double* rnorm, int* status) {
+  const int depth = o->depth;
+  double* f = o->precond_sweeps > 0 ? B.f : r;
   std::vector<double> gram((size_t)kAarMax * kAarMax, 0.0);
   std::vector<int> slots;              // history slots, oldest first
-  int status = TRAP_ENOCONV;
+  int evals = 0;
+  *status = TRAP_ENOCONV;
   for (int k = 0;; ++k) {
     double rn2 = 0.0;
     TRAP_TRY(dots(ctx, N, r, {r}, &rn2));
-    S.final_rel_res = std::sqrt(rn2) / bn;
-    if (!std::isfinite(S.final_rel_res)) {
-      status = TRAP_ENAN;
-      break;
+    *rnorm = std::sqrt(rn2);
+    if (!std::isfinite(*rnorm)) {
+      *status = TRAP_ENAN;
+      return TRAP_OK;
     }
-    if (S.final_rel_res < o->tol) {
-      status = TRAP_OK;
-      break;
+    if (*rnorm <= target) {
+      *status = TRAP_OK;
+      return TRAP_OK;
     }
-    if (S.inner_iters >= o->max_iters) break;
+    if (evals >= max_evals) return TRAP_OK;
     if (o->precond_sweeps > 0) {
-      TRAP_TRY(precond_apply(ctx, r, f, o->precond_sweeps, TRAP_FP64));
+      TRAP_TRY(precond_apply(ctx, r, f, o->precond_sweeps, pc_prec));
       ++S.applies_precond;
     }
     if (depth > 0) {
       if (k > 0) {
         // new differences into the oldest slot once the history is full
-        int s;
+        int sl;
         if ((int)slots.size() < depth) {
-          s = (int)slots.size();
+          sl = (int)slots.size();
         } else {
-          s = slots.front();
+          sl = slots.front();
           slots.erase(slots.begin());
         }
-        slots.push_back(s);
-        hipLaunchKernelGGL(k_aar_sub, dim3(kVecBlocks), dim3(256), 0, ctx->stream, N, x, xp, Xs(s));
-        hipLaunchKernelGGL(k_aar_sub, dim3(kVecBlocks), dim3(256), 0, ctx->stream, N, f, fp, Fs(s));
+        slots.push_back(sl);
+        hipLaunchKernelGGL(k_aar_sub, dim3(kVecBlocks), dim3(256), 0, ctx->stream, N, x, B.xp, B.X[sl]);
+        hipLaunchKernelGGL(k_aar_sub, dim3(kVecBlocks), dim3(256), 0, ctx->stream, N, f, B.fp, B.F[sl]);
         TRAP_HIP(hipGetLastError());
         std::vector<const double*> b;
-        for (int j : slots) b.push_back(Fs(j));
+        for (int j : slots) b.push_back(B.F[j]);
         std::vector<double> d(slots.size());
-        TRAP_TRY(dots(ctx, N, Fs(s), b, d.data()));
+        TRAP_TRY(dots(ctx, N, B.F[sl], b, d.data()));
         for (size_t q = 0; q < slots.size(); ++q) {
-          gram[(size_t)s * kAarMax + slots[q]] = d[q];
-          gram[(size_t)slots[q] * kAarMax + s] = d[q];
+          gram[(size_t)sl * kAarMax + slots[q]] = d[q];
+          gram[(size_t)slots[q] * kAarMax + sl] = d[q];
         }
       }
-      TRAP_HIP(hipMemcpyAsync(xp, x, N * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
-      TRAP_HIP(hipMemcpyAsync(fp, f, N * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+      TRAP_HIP(hipMemcpyAsync(B.xp, x, N * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+      TRAP_HIP(hipMemcpyAsync(B.fp, f, N * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
     }
     bool anderson = false;
     if (depth > 0 && (k + 1) % o->period == 0 && !slots.empty()) {
       const int nh = (int)slots.size();
       std::vector<const double*> b;
-      for (int j : slots) b.push_back(Fs(j));
+      for (int j : slots) b.push_back(B.F[j]);
       std::vector<double> h(nh), A((size_t)nh * nh), g;
       TRAP_TRY(dots(ctx, N, f, b, h.data()));
       for (int i = 0; i < nh; ++i)
@@ -249,8 +224,8 @@ int aar_solve(trap_ctx* ctx, const trap_aar_opts* o, double* x, trap_solve_stats
       if (normal_solve(A, h, nh, g)) {
         AarUpd U{};
         for (int i = 0; i < nh; ++i) {
-          U.X[i] = Xs(slots[i]);
-          U.F[i] = Fs(slots[i]);
+          U.X[i] = B.X[slots[i]];
+          U.F[i] = B.F[slots[i]];
           U.g[i] = g[i];
         }
         hipLaunchKernelGGL(k_aar_anderson, dim3(kVecBlocks), dim3(256), 0, ctx->stream, N, x, f, o->beta, U, nh);
@@ -263,9 +238,154 @@ int aar_solve(trap_ctx* ctx, const trap_aar_opts* o, double* x, trap_solve_stats
       hipLaunchKernelGGL(k_aar_axpy, dim3(kVecBlocks), dim3(256), 0, ctx->stream, N, x, f, o->omega);
       TRAP_HIP(hipGetLastError());
     }
-    TRAP_TRY(fixed_point_residual(ctx, N, x, r));
-    ++S.applies_fp64;
+    TRAP_TRY(res(x, r));
+    ++evals;
     ++S.inner_iters;
+  }
+}
+
+__global__ void k_aar_to_f32(long long N, const double* __restrict__ x, float* __restrict__ y) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < N; i += (long long)gridDim.x * blockDim.x)
+    y[i] = (float)x[i];
+}
+
+// r = r0 - y (y FP32)
+__global__ void k_aar_defect(long long N, const double* __restrict__ r0, const float* __restrict__ y,
+                             double* __restrict__ r) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < N; i += (long long)gridDim.x * blockDim.x)
+    r[i] = r0[i] - (double)y[i];
+}
+
+int aar_solve(trap_ctx* ctx, const trap_aar_opts* o, double* x, trap_solve_stats* st) {
+  if (!ctx->has_problem || !ctx->pre.done) return fail(TRAP_ESTATE, "precompute not run");
+  if (!o || !x) return fail(TRAP_EINVAL, "null argument");
+  if (!(o->tol > 0) || o->max_iters < 0 || o->depth < 0 || o->depth > kAarMax || o->period < 1 ||
+      !(o->omega > 0) || !(o->beta > 0))
+    return fail(TRAP_EINVAL, "bad AAR options (depth in [0, 16], period >= 1, omega, beta > 0)");
+  if (o->inner != TRAP_FP64 && o->inner != TRAP_FP32) return fail(TRAP_EINVAL, "bad inner precision");
+  const bool mixed = o->inner == TRAP_FP32;
+  if (mixed && (!(o->inner_tol > 0 && o->inner_tol < 1) || o->max_outer < 1))
+    return fail(TRAP_EINVAL, "bad refinement options (0 < inner_tol < 1, max_outer >= 1)");
+  if (mixed && !ctx->pre.d_M32) return fail(TRAP_ESTATE, "FP32 kernels not stored");
+  if (o->precond_sweeps < 0 || o->precond_sweeps > 64)
+    return fail(TRAP_EINVAL, "preconditioner sweeps must be in [0, 64]");
+  if (o->precond_sweeps > 0 && !ctx->pre.pc_done) return fail(TRAP_ESTATE, "preconditioner tables not computed");
+  const auto t0 = std::chrono::steady_clock::now();
+  const Problem& P = ctx->pb;
+  const long long N = 4LL * P.nz * P.nd * P.nn;
+  Work& K = ctx->wk;
+  TRAP_TRY(ensure_work(ctx, TRAP_FP64));
+  if (mixed) TRAP_TRY(ensure_work(ctx, TRAP_FP32));
+  if (o->precond_sweeps > 0) TRAP_TRY(precond_ensure(ctx));
+  if (!K.aar_part) TRAP_TRY(dalloc_t(ctx, &K.aar_part, (size_t)kDotBlocks * (kAarMax + 1)));
+  // r, f, previous x and f, correction d, outer residual, FP32 pair, FP32
+  // reference emissivity, differences
+  constexpr int kFixed = 8;
+  if (K.aar_cap < o->depth) {
+    TRAP_TRY(dalloc_t(ctx, &K.aar, (size_t)(kFixed + 2 * o->depth) * N));
+    K.aar_cap = o->depth;
+  }
+  const int cap = K.aar_cap;
+  AarBufs B{};
+  double* r = K.aar;
+  B.f = K.aar + N;
+  B.xp = K.aar + 2 * N;
+  B.fp = K.aar + 3 * N;
+  double* d = K.aar + 4 * N;
+  double* r64 = K.aar + 5 * N;
+  float* v32 = reinterpret_cast<float*>(K.aar + 6 * N);     // two FP32 vectors in one FP64 slot
+  float* y32 = v32 + N;
+  float* eref32 = reinterpret_cast<float*>(K.aar + 7 * N);
+  for (int j = 0; j < cap; ++j) {
+    B.X[j] = K.aar + (size_t)(kFixed + j) * N;
+    B.F[j] = K.aar + (size_t)(kFixed + cap + j) * N;
+  }
+
+  trap_solve_stats S{};
+  double bn2 = 0.0;
+  TRAP_TRY(dots(ctx, N, ctx->pre.d_b, {ctx->pre.d_b}, &bn2));
+  const double bn = std::sqrt(bn2);
+  if (!(bn > 0.0) || !std::isfinite(bn)) return fail(TRAP_EINVAL, "zero or non-finite right-hand side");
+  double* r_out = mixed ? r64 : r;     // the FP64 residual G(x) - x
+  // the emissivity Sigma x + eps_th of the current iterate
+  const double* e_cur = static_cast<const double*>(ctx->wk.opeps[0]);
+  if (o->zero_guess) {
+    // G(0) is the right-hand side Lambda eps_th + t
+    TRAP_HIP(hipMemsetAsync(x, 0, N * sizeof(double), ctx->stream));
+    TRAP_HIP(hipMemcpyAsync(r_out, ctx->pre.d_b, N * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+    e_cur = ctx->pre.d_epsth;
+  } else {
+    TRAP_TRY(fixed_point_residual(ctx, N, x, r_out));
+    ++S.applies_fp64;
+  }
+  int status = TRAP_ENOCONV;
+  double rn = 0.0;
+  if (!mixed) {
+    auto res = [&](const double* xx, double* rr) -> int {
+      ++S.applies_fp64;
+      return fixed_point_residual(ctx, N, xx, rr);
+    };
+    TRAP_TRY(aar_loop(ctx, N, o, B, x, r, o->tol * bn, o->max_iters, TRAP_FP64, res, S, &rn, &status));
+    S.final_rel_res = rn / bn;
+  } else {
+    // defect correction: the FP64 residual r64 = G(x) - x, then the
+    // correction d with d = r64 + Lambda Sigma d in the FP32 operator
+    // (inner residual r64 - (d - Lambda Sigma d)), x += d, until ||r64|| meets tol.
+    // With BESSER the inner Lambda is the Jacobian of the BESSER map at x: its
+    // branches follow the source of x (the reference emissivity).
+    const bool besser = ctx->formal_scheme == TRAP_FORMAL_BESSER;
+    struct RefGuard {
+      trap_ctx* c;
+      ~RefGuard() {
+        c->besser_ref = nullptr;
+        c->besser_ref_prec = -1;
+      }
+    } guard{ctx};
+    auto res = [&](const double* dd, double* rr) -> int {
+      hipLaunchKernelGGL(k_aar_to_f32, dim3(kVecBlocks), dim3(256), 0, ctx->stream, N, dd, v32);
+      TRAP_HIP(hipGetLastError());
+      TRAP_TRY(operator_apply(ctx, v32, y32, TRAP_FP32));
+      hipLaunchKernelGGL(k_aar_defect, dim3(kVecBlocks), dim3(256), 0, ctx->stream, N, r64, y32, rr);
+      TRAP_HIP(hipGetLastError());
+      ++S.applies_fp32;
+      return TRAP_OK;
+    };
+    for (int outer = 0;; ++outer) {
+      double r2 = 0.0;
+      TRAP_TRY(dots(ctx, N, r64, {r64}, &r2));
+      S.final_rel_res = std::sqrt(r2) / bn;
+      if (!std::isfinite(S.final_rel_res)) {
+        status = TRAP_ENAN;
+        break;
+      }
+      if (S.final_rel_res < o->tol) {
+        status = TRAP_OK;
+        break;
+      }
+      if (outer >= o->max_outer || S.inner_iters >= o->max_iters) break;
+      TRAP_HIP(hipMemsetAsync(d, 0, N * sizeof(double), ctx->stream));
+      TRAP_HIP(hipMemcpyAsync(r, r64, N * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+      if (besser) {
+        hipLaunchKernelGGL(k_aar_to_f32, dim3(kVecBlocks), dim3(256), 0, ctx->stream, N, e_cur, eref32);
+        TRAP_HIP(hipGetLastError());
+        ctx->besser_ref = eref32;
+        ctx->besser_ref_prec = TRAP_FP32;
+      }
+      int st_in = TRAP_ENOCONV;
+      TRAP_TRY(aar_loop(ctx, N, o, B, d, r, o->inner_tol * std::sqrt(r2), o->max_iters - S.inner_iters, TRAP_FP32,
+                        res, S, &rn, &st_in));
+      ctx->besser_ref = nullptr;
+      ctx->besser_ref_prec = -1;
+      if (st_in == TRAP_ENAN) {
+        status = TRAP_ENAN;
+        break;
+      }
+      hipLaunchKernelGGL(k_aar_axpy, dim3(kVecBlocks), dim3(256), 0, ctx->stream, N, x, d, 1.0);
+      TRAP_HIP(hipGetLastError());
+      TRAP_TRY(fixed_point_residual(ctx, N, x, r64));
+      e_cur = static_cast<const double*>(ctx->wk.opeps[0]);
+      ++S.applies_fp64;
+    }
   }
   TRAP_HIP(hipStreamSynchronize(ctx->stream));
   S.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();

@@ -160,13 +160,33 @@ __device__ inline T besser_control(T SM, T SO, T SP, T hM, T hP) {
   return fmin(fmax(c, fmin(SM, SO)), fmax(SM, SO));
 }
 
-// PAR: 0 = DELO-linear only, 1 = DELOPAR only, 2 = BESSER only, -1 = the scheme
-// argument decides between DELO-linear and DELOPAR
+// The BESSER step linearised about a reference source (its Jacobian): the
+// branch taken at each point (zero slope at an extremum, the range limit
+// towards S_M or S_O, or the tangent) is the one the reference source takes
+// there, and that branch's linear weights are applied to the source S.
+template <typename T>
+__device__ inline T besser_control_lin(T SM, T SO, T SP, T RM, T RO, T RP, T hM, T hP) {
+  const T rM = (RO - RM) / hM, rP = (RP - RO) / hP;
+  const bool ext = !(rM * rP > T(0));
+  const T rO = ext ? T(0) : (hM * rP + hP * rM) / (hM + hP);
+  const T cr = RO - T(0.5) * hM * rO;
+  const T lo = fmin(RM, RO), hi = fmax(RM, RO);
+  if (cr < lo) return RM <= RO ? SM : SO;
+  if (cr > hi) return RM >= RO ? SM : SO;
+  if (ext) return SO;
+  const T dM = (SO - SM) / hM, dP = (SP - SO) / hP;
+  return SO - T(0.5) * hM * ((hM * dP + hP * dM) / (hM + hP));
+}
+
+// PAR: 0 = DELO-linear only, 1 = DELOPAR only, 2 = BESSER only, 3 = BESSER
+// linearised about the reference emissivity eref, -1 = the scheme argument
+// decides between DELO-linear and DELOPAR
 template <typename T, int PAR>
 __device__ __forceinline__ void formal_body(int bx, int nz, int nd, int nn, const double* __restrict__ mu,
                                             const double* __restrict__ tau, const double* __restrict__ K8,
                                             const double* __restrict__ WT, const T* __restrict__ eps,
-                                            T* __restrict__ I, int with_boundary, int scheme) {
+                                            T* __restrict__ I, int with_boundary, int scheme,
+                                            const T* __restrict__ eref = nullptr) {
   const int id = bx * blockDim.x + threadIdx.x;
   if (id >= nd * nn) return;
   const int o = id / nn, n = id % nn;
@@ -180,6 +200,7 @@ __device__ __forceinline__ void formal_body(int bx, int nz, int nd, int nn, cons
   T Icur[4] = {T(0), T(0), T(0), T(0)};
   if (up && with_boundary) Icur[0] = T(WT[0]);
   T ku[6], Su[4], ru;
+  T Ru[4];                                          // reference source (PAR 3)
   double tz = tau[z];
   {
     const long long p = pidx(z);
@@ -188,12 +209,14 @@ __device__ __forceinline__ void formal_body(int bx, int nz, int nd, int nn, cons
     const T inv = T(k[6]);
     ru = T(k[7]);
     for (int s = 0; s < 4; ++s) Su[s] = eps[p * 4 + s] * inv;
+    if constexpr (PAR == 3)
+      for (int s = 0; s < 4; ++s) Ru[s] = eref[p * 4 + s] * inv;
     for (int s = 0; s < 4; ++s) I[p * 4 + s] = Icur[s];
   }
   // the raw data of the next height are loaded one step ahead, so their
   // latency overlaps the current step's arithmetic
   double kn[8], tn = 0.0;
-  T en[4];
+  T en[4], enr[4];
   auto fetch = [&](int zz) {
     const long long p = pidx(zz);
     const double* k = K8 + p * 8;
@@ -201,6 +224,9 @@ __device__ __forceinline__ void formal_body(int bx, int nz, int nd, int nn, cons
     for (int i = 0; i < 8; ++i) kn[i] = k[i];
 #pragma unroll
     for (int s = 0; s < 4; ++s) en[s] = eps[p * 4 + s];
+    if constexpr (PAR == 3)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) enr[s] = eref[p * 4 + s];
     tn = tau[zz];
   };
   if (nz > 1) fetch(z + dz);
@@ -208,11 +234,14 @@ __device__ __forceinline__ void formal_body(int bx, int nz, int nd, int nn, cons
     const int zc = z + dz;
     const long long p = pidx(zc);
     double kr[8];
-    T er[4];
+    T er[4], err[4];
 #pragma unroll
     for (int i = 0; i < 8; ++i) kr[i] = kn[i];
 #pragma unroll
     for (int s = 0; s < 4; ++s) er[s] = en[s];
+    if constexpr (PAR == 3)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) err[s] = enr[s];
     const double tzc = tn;
     if (step + 1 < nz) fetch(zc + dz);
     T kc[6], Sc[4];
@@ -220,6 +249,9 @@ __device__ __forceinline__ void formal_body(int bx, int nz, int nd, int nn, cons
     const T inv = T(kr[6]);
     const T rc = T(kr[7]);
     for (int s = 0; s < 4; ++s) Sc[s] = er[s] * inv;
+    T Rc[4];
+    if constexpr (PAR == 3)
+      for (int s = 0; s < 4; ++s) Rc[s] = err[s] * inv;
     const T x = T(0.5) * (ru + rc) * T(fabs(tz - tzc)) / amu;
     T pu, pc, ex;
     delo_weights<T>(x, pu, pc, ex);
@@ -234,14 +266,18 @@ __device__ __forceinline__ void formal_body(int bx, int nz, int nd, int nn, cons
       const T inP = T(kn[6]);
       for (int s = 0; s < 4; ++s)
         b[s] = ex * Icur[s] - pu * kv[s] + T(wM) * Su[s] + T(wO) * Sc[s] + T(wP) * (en[s] * inP);
-    } else if (PAR == 2 && step + 1 < nz) {
+    } else if ((PAR == 2 || PAR == 3) && step + 1 < nz) {
       const double hM = 0.5 * (double(ru) + kr[7]) * fabs(tz - tzc) / fabs(m);
       const double hP = 0.5 * (kr[7] + kn[7]) * fabs(tzc - tn) / fabs(m);
       double wM, wC, wO;
       bezier_weights(hM, wM, wC, wO);
       const T inP = T(kn[6]);
       for (int s = 0; s < 4; ++s) {
-        const T c = besser_control<T>(Su[s], Sc[s], en[s] * inP, T(hM), T(hP));
+        T c;
+        if constexpr (PAR == 3)
+          c = besser_control_lin<T>(Su[s], Sc[s], en[s] * inP, Ru[s], Rc[s], enr[s] * inP, T(hM), T(hP));
+        else
+          c = besser_control<T>(Su[s], Sc[s], en[s] * inP, T(hM), T(hP));
         b[s] = ex * Icur[s] - pu * kv[s] + T(wM) * Su[s] + T(wC) * c + T(wO) * Sc[s];
       }
     } else {
@@ -254,6 +290,8 @@ __device__ __forceinline__ void formal_body(int bx, int nz, int nd, int nn, cons
       I[p * 4 + s] = Inew[s];
       Su[s] = Sc[s];
     }
+    if constexpr (PAR == 3)
+      for (int s = 0; s < 4; ++s) Ru[s] = Rc[s];
     for (int i = 0; i < 6; ++i) ku[i] = kc[i];
     ru = rc;
     z = zc;
@@ -265,8 +303,8 @@ template <typename T, int PAR>
 __global__ void __launch_bounds__(64) k_formal(int nz, int nd, int nn, const double* __restrict__ mu,
                          const double* __restrict__ tau, const double* __restrict__ K8,
                          const double* __restrict__ WT, const T* __restrict__ eps, T* __restrict__ I,
-                         int with_boundary) {
-  formal_body<T, PAR>(blockIdx.x, nz, nd, nn, mu, tau, K8, WT, eps, I, with_boundary, PAR);
+                         int with_boundary, const T* __restrict__ eref) {
+  formal_body<T, PAR>(blockIdx.x, nz, nd, nn, mu, tau, K8, WT, eps, I, with_boundary, PAR, eref);
 }
 
 // one launch over several contexts: block b is context r's block b - off[r]
@@ -422,18 +460,23 @@ int formal_apply(trap_ctx* ctx, const void* eps, void* I, int with_boundary, int
   const int rays = P.nd * P.nn;
   const int pr = prof_begin(ctx, TRAP_STAGE_FORMAL);
   const int sch = ctx->formal_scheme;
+  // BESSER linearised about a reference emissivity (set by the mixed-precision
+  // Anderson-Richardson solve for its inner corrections)
+  const bool lin = sch == TRAP_FORMAL_BESSER && ctx->besser_ref && ctx->besser_ref_prec == prec;
   if (prec == TRAP_FP64) {
-    auto kern = sch == TRAP_FORMAL_BESSER ? k_formal<double, 2>
-                : (sch == TRAP_FORMAL_DELOPAR ? k_formal<double, 1> : k_formal<double, 0>);
+    auto kern = lin ? k_formal<double, 3>
+                : (sch == TRAP_FORMAL_BESSER ? k_formal<double, 2>
+                   : (sch == TRAP_FORMAL_DELOPAR ? k_formal<double, 1> : k_formal<double, 0>));
     hipLaunchKernelGGL(kern, dim3(ceil_div(rays, 64)), dim3(64), 0, ctx->stream, P.nz, P.nd, P.nn, P.d_mu,
                        P.d_tau, ctx->pre.d_K, P.d_WT, static_cast<const double*>(eps), static_cast<double*>(I),
-                       with_boundary);
+                       with_boundary, lin ? static_cast<const double*>(ctx->besser_ref) : nullptr);
   } else if (prec == TRAP_FP32) {
-    auto kern = sch == TRAP_FORMAL_BESSER ? k_formal<float, 2>
-                : (sch == TRAP_FORMAL_DELOPAR ? k_formal<float, 1> : k_formal<float, 0>);
+    auto kern = lin ? k_formal<float, 3>
+                : (sch == TRAP_FORMAL_BESSER ? k_formal<float, 2>
+                   : (sch == TRAP_FORMAL_DELOPAR ? k_formal<float, 1> : k_formal<float, 0>));
     hipLaunchKernelGGL(kern, dim3(ceil_div(rays, 64)), dim3(64), 0, ctx->stream, P.nz, P.nd, P.nn, P.d_mu,
                        P.d_tau, ctx->pre.d_K, P.d_WT, static_cast<const float*>(eps), static_cast<float*>(I),
-                       with_boundary);
+                       with_boundary, lin ? static_cast<const float*>(ctx->besser_ref) : nullptr);
   } else {
     return fail(TRAP_EINVAL, "unknown precision");
   }

@@ -221,6 +221,10 @@ struct trap_ctx {
   int path = 0;                     // TRAP_PATH_* of trap.h
   int prd_mode = 0;                 // TRAP_PRD_* of trap.h, applied at trap_set_problem
   int formal_scheme = 0;            // TRAP_FORMAL_* of trap.h
+  // while set: BESSER formal solutions in this precision are linearised about
+  // this reference emissivity (device vector of the full layout)
+  const void* besser_ref = nullptr;
+  int besser_ref_prec = -1;
   int max_lds = 64 * 1024;          // device limit of LDS bytes per block
   int n_cu = 256;                   // compute units of the device
   // the preconditioner tables are built on a stream of the library's own

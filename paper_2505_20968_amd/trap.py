@@ -70,7 +70,8 @@ class SolveOpts(ctypes.Structure):
 class AarOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iters", ctypes.c_int), ("depth", ctypes.c_int),
                 ("period", ctypes.c_int), ("omega", ctypes.c_double), ("beta", ctypes.c_double),
-                ("zero_guess", ctypes.c_int), ("precond_sweeps", ctypes.c_int)]
+                ("zero_guess", ctypes.c_int), ("precond_sweeps", ctypes.c_int), ("inner", ctypes.c_int),
+                ("inner_tol", ctypes.c_double), ("max_outer", ctypes.c_int)]
 
 
 class SolveStats(ctypes.Structure):
@@ -299,16 +300,19 @@ class Context:
 
     def aar_solve(self, I, tol: float = 1e-8, max_iters: int = 2000, depth: int = 7, period: int = 6,
                   omega: float = 1.0, beta: float = 1.0, zero_guess: bool = False, precond_sweeps: int = 0,
+                  inner: int = TRAP_FP64, inner_tol: float = 1e-4, max_outer: int = 10,
                   raise_on_noconv: bool = True):
-        """Alternating Anderson-Richardson solve (trap_aar_solve, FP64)."""
+        """Alternating Anderson-Richardson solve (trap_aar_solve): FP64, or with
+        inner=TRAP_FP32 FP64 defect correction around FP32 inner iterations."""
         o = AarOpts(tol=tol, max_iters=max_iters, depth=depth, period=period, omega=omega, beta=beta,
-                    zero_guess=int(zero_guess), precond_sweeps=int(precond_sweeps))
+                    zero_guess=int(zero_guess), precond_sweeps=int(precond_sweeps), inner=int(inner),
+                    inner_tol=float(inner_tol), max_outer=int(max_outer))
         st = SolveStats()
         code = self.lib.trap_aar_solve(self.h, ctypes.byref(o), self._vec(I, TRAP_FP64), ctypes.byref(st))
         if code != 0 and (raise_on_noconv or code != -4):
             _check(code)
         return {"anderson_steps": st.outer_steps, "residuals": st.inner_iters, "applies_fp64": st.applies_fp64,
-                "applies_precond": st.applies_precond, "final_rel_res": st.final_rel_res, "ms_total": st.ms_total,
+                "applies_fp32": st.applies_fp32, "applies_precond": st.applies_precond, "final_rel_res": st.final_rel_res, "ms_total": st.ms_total,
                 "status": code}
 
     def gmres_begin(self, I, tol: float = 1e-8, restart: int = 40, max_iters: int = 2000,

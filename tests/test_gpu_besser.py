@@ -4,7 +4,8 @@ the BESSER formal solution per field (FP64 1e-12, FP32 1e-6 relative), AAR
 on a linear (DELO-linear) problem against the GMRES solution (solution 1e-9,
 with and without the preconditioner), AAR on BESSER problems against the
 oracle's own AAR fixed point (parity contract on the emergent profiles, and
-the fixed-point residual through the C ABI), and the error paths."""
+the fixed-point residual through the C ABI), the mixed-precision defect
+correction reaching the same fixed points, and the error paths."""
 import numpy as np
 import pytest
 
@@ -96,6 +97,24 @@ def test_besser_aar_matches_oracle(case):
     assert (torch.linalg.norm(g - x) / torch.linalg.norm(b)).item() < 1e-11
 
 
+@pytest.mark.parametrize("sweeps", [0, 2])
+def test_besser_mixed_aar_matches_oracle(case, sweeps):
+    """FP64 defect correction around FP32 inner iterations reaches the same
+    fixed point (the FP64 residual meets the tolerance)."""
+    name, prob, op, ctx, torch = case
+    from oracle import transfer as T
+    from paper_2505_20968_amd import TRAP_FP32
+    ref, _ = T.solve_aar(op, tol=1e-12)
+    if sweeps:
+        ctx.precompute_preconditioner()
+    x = torch.zeros(ctx.shape, dtype=torch.float64, device="cuda")
+    st = ctx.aar_solve(x, tol=1e-11, max_iters=800, zero_guess=True, inner=TRAP_FP32, inner_tol=1e-4,
+                       max_outer=12, precond_sweeps=sweeps)
+    print(f"[{name}] BESSER mixed AAR, {sweeps} sweeps: {st}", flush=True)
+    assert st["final_rel_res"] < 1e-11 and st["applies_fp32"] > 0 and st["applies_fp64"] >= 1
+    assert np.abs(x.cpu().numpy() - ref).max() < 1e-8 * np.abs(ref).max()
+
+
 def test_gmres_refuses_besser(case):
     name, prob, op, ctx, torch = case
     from paper_2505_20968_amd import TrapError
@@ -121,6 +140,12 @@ def test_aar_on_a_linear_problem_matches_gmres(sweeps):
         print(f"[linear AAR, {sweeps} sweeps] {st}", flush=True)
         assert st["final_rel_res"] < 1e-11
         assert (st["applies_precond"] > 0) == (sweeps > 0)
+        from paper_2505_20968_amd import TRAP_FP32
+        xm = torch.zeros_like(x)
+        sm = c.aar_solve(xm, tol=1e-11, max_iters=800, zero_guess=True, precond_sweeps=sweeps, inner=TRAP_FP32,
+                         inner_tol=1e-4, max_outer=12)
+        print(f"[linear mixed AAR, {sweeps} sweeps] {sm}", flush=True)
+        assert sm["final_rel_res"] < 1e-11 and np.abs(xm.cpu().numpy() - ref).max() < 1e-9 * np.abs(ref).max()
         xg = torch.zeros_like(x)
         sg = c.gmres_solve(xg, tol=1e-11, restart=30, max_iters=600, zero_guess=True)
         assert np.abs(x.cpu().numpy() - ref).max() < 1e-9 * np.abs(ref).max()
@@ -144,6 +169,11 @@ def test_aar_errors():
         x = torch.zeros(c.shape, dtype=torch.float64, device="cuda")
         for bad in (dict(depth=17), dict(depth=-1), dict(period=0), dict(omega=0.0), dict(beta=-1.0),
                     dict(tol=0.0), dict(precond_sweeps=65)):
+            with pytest.raises(TrapError, match="EINVAL"):
+                c.aar_solve(x, **bad)
+        from paper_2505_20968_amd import TRAP_FP32
+        for bad in (dict(inner=5), dict(inner=TRAP_FP32, inner_tol=0.0), dict(inner=TRAP_FP32, inner_tol=1.0),
+                    dict(inner=TRAP_FP32, max_outer=0)):
             with pytest.raises(TrapError, match="EINVAL"):
                 c.aar_solve(x, **bad)
         with pytest.raises(TrapError, match="ESTATE"):
