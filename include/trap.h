@@ -280,8 +280,8 @@ typedef struct {
                           correction, each step the FP64 residual r = G(I) - I, then the
                           iteration above on d = r + Lambda Sigma d with the FP32 operator
                           (for BESSER its Jacobian at I: each point's branch follows the
-                          source of I), to inner_tol ||r||, and I <- I + d, at most
-                          max_outer times */
+                          source of I), to max(inner_tol ||r||, tol ||G(0)|| / 2), and
+                          I <- I + d, at most max_outer times */
   double inner_tol;    /* 0 < inner_tol < 1 (TRAP_FP32 only) */
   int max_outer;       /* >= 1 (TRAP_FP32 only) */
 } trap_aar_opts;

@@ -9,6 +9,7 @@
 // Everything is FP64 on the device; the small least-squares problem is solved
 // on the host from dot products (the Gram matrix of F is kept up to date one
 // new column at a time).
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <vector>
@@ -372,8 +373,10 @@ int aar_solve(trap_ctx* ctx, const trap_aar_opts* o, double* x, trap_solve_stats
         ctx->besser_ref_prec = TRAP_FP32;
       }
       int st_in = TRAP_ENOCONV;
-      TRAP_TRY(aar_loop(ctx, N, o, B, d, r, o->inner_tol * std::sqrt(r2), o->max_iters - S.inner_iters, TRAP_FP32,
-                        res, S, &rn, &st_in));
+      // no tighter than the final tolerance needs: half of it leaves room for
+      // the FP32 error of the correction
+      const double target = std::max(o->inner_tol * std::sqrt(r2), 0.5 * o->tol * bn);
+      TRAP_TRY(aar_loop(ctx, N, o, B, d, r, target, o->max_iters - S.inner_iters, TRAP_FP32, res, S, &rn, &st_in));
       ctx->besser_ref = nullptr;
       ctx->besser_ref_prec = -1;
       if (st_in == TRAP_ENAN) {
