@@ -6,8 +6,9 @@
 * cfg2 (chromosphere column, N = 1 809 920): Sigma is height-local, so the
   full-size GPU apply is compared with the oracle's Sigma at sampled heights
   (the oracle builds those heights' kernels itself); Lambda is compared for
-  every ray; the mixed solve's FP64 residual and its agreement with the FP64
-  solve are checked.
+  every ray, with DELO-linear and with BESSER; the mixed solve's FP64
+  residual and its agreement with the FP64 solve are checked; lines of sight
+  placed on quadrature mu values reproduce the converged solution there.
 Tolerances as in the small-case parity tests: FP64 operator 1e-10, FP32
 operator 2e-5 (relative 2-norm), FP32 formal solution 1e-6, emergent I 1e-6
 relative and Q/I, U/I, V/I 1e-4 absolute.
@@ -128,3 +129,57 @@ def test_cfg2_mixed_solve_agrees_with_fp64_solve(big):
     assert (np.abs(a[..., 0] - b[..., 0]) / np.abs(b[..., 0])).max() < 1e-6
     for s in (1, 2, 3):
         assert np.abs(a[..., s] / a[..., 0] - b[..., s] / b[..., 0]).max() < 1e-4
+
+
+def test_cfg2_besser_formal_solution_every_ray(big):
+    """The BESSER formal solution at the full chromosphere-like size against
+    the oracle's on every ray (FP64 1e-12, FP32 1e-6)."""
+    prob, ctx, I, torch = big
+    from oracle import transfer as T
+    from paper_2505_20968_amd import Context, TRAP_FORMAL_BESSER
+    op = T.setup(prob, {"normalize": False, "formal": "besser"})
+    eps = np.abs(I) * 0.3
+    ref = T.formal_solve(op, eps, boundary=True)
+    c = Context(0)
+    try:
+        c.set_formal_scheme(TRAP_FORMAL_BESSER)
+        c.set_problem(prob)
+        c.precompute(1)
+        for dt, tol in ((torch.float64, 1e-12), (torch.float32, 1e-6)):
+            et = torch.tensor(eps, dtype=dt, device="cuda")
+            out = torch.empty_like(et)
+            c.formal_solve(et, out, with_boundary=True)
+            torch.cuda.synchronize()
+            r = _rel(out.double().cpu().numpy(), ref)
+            print(f"[cfg2] BESSER formal {dt} rel {r:.2e}", flush=True)
+            assert r < tol
+    finally:
+        c.close()
+
+
+def test_cfg2_line_of_sight_on_a_quadrature_mu(big):
+    """At full size: a mixed-precision solve, then lines of sight placed on two
+    quadrature mu values reproduce the solution's emergent profiles there
+    (the extra formal solution of a converged field is the field)."""
+    prob, ctx, I, torch = big
+    from paper_2505_20968_amd import Context, TRAP_FP32
+    x = torch.zeros(ctx.shape, dtype=torch.float64, device="cuda")
+    st = ctx.gmres_solve(x, tol=1e-10, restart=40, max_iters=2000, inner=TRAP_FP32, inner_tol=1e-7, max_outer=10,
+                         zero_guess=True)
+    assert st["final_rel_res"] < 1e-10
+    mu = np.polynomial.legendre.leggauss(prob.n_mu // 2)[0] * 0.5 + 0.5
+    pick = [0, prob.n_mu // 2 - 1]
+    c = Context(0)
+    try:
+        c.set_problem(prob.with_(los_mu=mu[pick]))
+        c.precompute(3)
+        full = torch.empty(c.shape, dtype=torch.float64, device="cuda")
+        c.formal_from_field(x, full)
+        got = c.emergent_los(full)                              # [2, chi, n, 4]
+        em = ctx.emergent(x).reshape(prob.n_mu // 2, prob.n_chi, prob.n_nu, 4)
+        want = em[pick]
+        r = np.abs(got - want).max() / np.abs(want[..., 0]).max()
+        print(f"[cfg2] lines of sight on quadrature mu {mu[pick]}: rel {r:.2e}", flush=True)
+        assert r < 1e-7
+    finally:
+        c.close()
