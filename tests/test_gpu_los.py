@@ -89,14 +89,17 @@ def test_quadrature_block_unchanged_by_rings(case):
     assert np.abs(a - b).max() < 1e-12 * np.abs(b).max()
 
 
-@pytest.mark.parametrize("inner", ["fp64", "fp32"])
-def test_solve_with_rings_matches_oracle(case, inner):
+@pytest.mark.parametrize("inner,sweeps", [("fp64", 0), ("fp32", 0), ("fp32", 2)])
+def test_solve_with_rings_matches_oracle(case, inner, sweeps):
     name, p0, p1, op0, op1, sol, want, c0, c1, torch = case
     from paper_2505_20968_amd import TRAP_FP32, TRAP_FP64
+    if sweeps:
+        c1.precompute_preconditioner()
     x = torch.zeros(c1.shape, dtype=torch.float64, device="cuda")
     st = c1.gmres_solve(x, tol=1e-10, restart=30, max_iters=600, max_outer=10,
-                        inner=TRAP_FP64 if inner == "fp64" else TRAP_FP32, inner_tol=1e-6, zero_guess=True)
-    print(f"[{name}] solve with rings {inner}: {st}", flush=True)
+                        inner=TRAP_FP64 if inner == "fp64" else TRAP_FP32, inner_tol=1e-6, zero_guess=True,
+                        precond_sweeps=sweeps)
+    print(f"[{name}] solve with rings {inner}, {sweeps} sweeps: {st}", flush=True)
     assert st["final_rel_res"] < 1e-10
     for got, ref in ((c1.emergent_los(x), want),
                      (c1.emergent(x), sol[-1][op0.ang["mu"] > 0])):
