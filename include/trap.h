@@ -135,6 +135,10 @@ typedef struct {
   double flops_contraction;     /* algorithmic flops of one R_II contraction */
   double bytes_contraction_fp64;/* algorithmic HBM bytes of one contraction */
   double bytes_contraction_fp32;
+  long long kernel_rows_mirrored; /* per height and scattering angle: complex kernel rows
+                                     filled from the mirror image of a computed row
+                                     (frequency grid symmetric about 0 and transition shifts
+                                     in +-s pairs, as M_s[n][m] = conj(M_-s[N-1-n][N-1-m])) */
 } trap_info;
 
 typedef struct {

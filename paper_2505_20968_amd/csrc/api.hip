@@ -405,6 +405,7 @@ int trap_get_info(const trap_ctx* ctx, trap_info* info) {
   const double ibytes = (double)P.nz * P.nd * P.nn * 4;
   info->bytes_contraction_fp64 = 8.0 * (kel + wbytes + ibytes);
   info->bytes_contraction_fp32 = 4.0 * (kel + wbytes + ibytes);
+  info->kernel_rows_mirrored = P.rows_mirrored;
   return TRAP_OK;
 }
 

@@ -1054,6 +1054,36 @@ int build_problem(trap_ctx* ctx, const trap_atom_desc* at, const trap_problem_de
   up.add(&P.d_WT, P.WT);
   up.add(&P.d_eta0, P.eta0);
   up.add(&P.d_ub, ub);
+  // mirror roles of the kernel rows (see Problem::row_role): the grid must be
+  // exactly symmetric and a partner's shifts exactly the negated ones at every height
+  P.row_role.clear();
+  P.rows_mirrored = 0;
+  {
+    // symmetric to rounding (a grid built as start + k step is not bitwise
+    // symmetric); the mirrored rows then differ from direct ones by far less
+    // than the quadrature error
+    const double xs = std::max(std::fabs(P.x[0]), std::fabs(P.x[nn - 1]));
+    bool sym = true;
+    for (int n = 0; n < nn && sym; ++n) sym = std::fabs(P.x[n] + P.x[nn - 1 - n]) <= 1e-13 * xs;
+    if (sym) {
+      std::vector<int> role(nt, -1);
+      auto negated = [&](int t, int t2) {
+        for (int z = 0; z < nz; ++z)
+          if (st[z * nt + t2] != -st[z * nt + t]) return false;
+        return true;
+      };
+      for (int t = 0; t < nt; ++t) {
+        for (int t2 = 0; t2 < t && role[t] < 0; ++t2)
+          if (role[t2] == -1 && negated(t, t2)) role[t] = t2;
+        if (role[t] < 0 && negated(t, t)) role[t] = t;
+      }
+      bool any = false;
+      for (int t = 0; t < nt; ++t) any = any || role[t] >= 0;
+      if (any) P.row_role = role;
+      for (int t = 0; t < nt; ++t)
+        if (role[t] >= 0) P.rows_mirrored += (role[t] == t ? nn / 2 : nn);
+    }
+  }
   up.add(&P.d_st, st);
   up.add(&P.d_sll, sll);
   up.add(&P.d_theta, P.theta);

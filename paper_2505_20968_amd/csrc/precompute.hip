@@ -225,6 +225,20 @@ __global__ void k_kernel_tables(int z0, int nth, int nt, int nn, int ntail, doub
 // written here, the dense product is one batched GEMM (k_sig_gemm).
 constexpr int kRowWavesMax = 2;       // rows (one per wave) per block of the kernel-row precompute
 
+// Mirror roles of the transitions' kernel rows (Problem::row_role), by value.
+constexpr int kMaxRoles = 128;
+struct RowRoles {
+  int on;                 // 0: every row is computed
+  int role[kMaxRoles];
+};
+
+// Rows that come from the mirror image of a computed row instead.
+__device__ __forceinline__ bool row_mirrored(const RowRoles& R, int t, int n, int nn) {
+  if (!R.on) return false;
+  const int r = R.role[t];
+  return r >= 0 && (r != t || n > nn - 1 - n);
+}
+
 // The kernel is latency bound; a register cap for three waves per SIMD (a few
 // bytes of spill) measured faster than the uncapped two or a four-wave cap.
 __global__ void __launch_bounds__(64 * kRowWavesMax, 3) k_kernel_rows(
@@ -232,19 +246,20 @@ __global__ void __launch_bounds__(64 * kRowWavesMax, 3) k_kernel_rows(
     const double* __restrict__ lam, const double* __restrict__ av, const double* __restrict__ st,
     const double* __restrict__ theta, double* __restrict__ Lout, double* __restrict__ Gout,
     long long row0, int z0, double h_uniform, const double* __restrict__ Gt,
-    const double2* __restrict__ Vt, int ntail) {
+    const double2* __restrict__ Vt, int ntail, RowRoles roles) {
   extern __shared__ double2 smem[];    // per wave: [(nn+1)][4], piece index shifted by one
   __shared__ double2 tred[kRowWavesMax][2][64];
   const int waves = blockDim.x >> 6;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   double2* mom = smem + (size_t)wave * (nn + 1) * 4;
   const long long rl = (long long)blockIdx.x * waves + wave;     // row within this launch
-  const bool live = rl < nrows;
+  bool live = rl < nrows;
   const long long row = row0 + (live ? rl : 0);
   const int n = row % nn;
   const int t = (row / nn) % nt;
   const int th = (row / ((long long)nn * nt)) % nth;
   const int z = z0 + (int)(row / ((long long)nn * nt * nth));
+  if (row_mirrored(roles, t, n, nn)) live = false;               // filled by k_mirror_rows
   const double L = lam[z], a = av[z], s = st[z * nt + t], Th = theta[th];
   // chunk-local row index of the real plane; the imaginary plane follows nn rows later
   const size_t cbase = (size_t)((((size_t)(z - z0) * nth + th) * nt + t) * 2) * nn * ldm;
@@ -470,6 +485,34 @@ __global__ void __launch_bounds__(64 * kRowWavesMax, 3) k_kernel_rows(
 // D[(l/16) + 4 r][l % 16].  Block: 4 waves x 16 rows = 64 rows, 8 column tiles.
 constexpr int kSigColTiles = 8;
 typedef double doublex4_g __attribute__((ext_vector_type(4)));
+
+// Rows of a mirrored transition from their mirror images (Problem::row_role):
+// M[t][c][n][m] = (c ? -1 : 1) M[src][c][nn-1-n][nn-1-m] for m < nn, zero in
+// the padding; heights [z0, z0 + zc) of the stored kernels [z][th][t][2][nn][ldm].
+template <typename T>
+__global__ void k_mirror_rows(int z0, int zc, int nth, int nt, int nn, int ldm, RowRoles roles, T* __restrict__ M) {
+  const long long total = (long long)zc * nth * nt * 2 * nn * ldm;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int m = i % ldm;
+    long long q = i / ldm;
+    const int n = q % nn;
+    q /= nn;
+    const int c = q % 2;
+    q /= 2;
+    const int t = q % nt;
+    const long long zt = q / nt;                       // (z - z0) * nth + th
+    if (!row_mirrored(roles, t, n, nn)) continue;
+    const size_t base = (size_t)(z0 * (long long)nth + zt) * nt;
+    T v = T(0);
+    if (m < nn) {
+      const int src = roles.role[t];
+      v = M[(((base + src) * 2 + c) * nn + (nn - 1 - n)) * ldm + (nn - 1 - m)];
+      if (c) v = -v;
+    }
+    M[(((base + t) * 2 + c) * nn + n) * ldm + m] = v;
+  }
+}
 
 __global__ void __launch_bounds__(256) k_sig_gemm(long long nrows, int nn, int ldm,
                                                   const double* __restrict__ Gam,
@@ -926,6 +969,11 @@ int run_precompute(trap_ctx* ctx, int store_mask) {
     if (aa) TRAP_TRY(dalloc_t(ctx, &C.d_Mtmp, (size_t)zc_tab * rows_per_z * P.ldm));
     C.zc_rows = zc_tab;
   }
+  RowRoles roles{};
+  if (!P.row_role.empty() && nt <= kMaxRoles) {
+    roles.on = 1;
+    for (int t = 0; t < nt; ++t) roles.role[t] = P.row_role[t];
+  }
   const int pr = prof_begin(ctx, TRAP_STAGE_KERNEL_ROWS);
   for (int z0 = 0; z0 < nz; z0 += zc_tab) {
     const int zc = std::min(zc_tab, nz - z0);
@@ -941,7 +989,7 @@ int run_precompute(trap_ctx* ctx, int store_mask) {
       hipLaunchKernelGGL(k_kernel_rows, dim3((unsigned)ceil_div(nr, rw)), dim3(64 * rw), rw * lds, s, nr, nthr, nt,
                          nn, P.ldm, P.d_x,
                          P.d_lam, P.d_a, P.d_st, P.d_theta_rows, C.d_Lrow, C.d_Grow, r0, z0, h,
-                         uniform ? C.d_Gt : nullptr, uniform ? C.d_Vt : nullptr, ntail);
+                         uniform ? C.d_Gt : nullptr, uniform ? C.d_Vt : nullptr, ntail, roles);
       TRAP_HIP(hipGetLastError());
     }
     const long long rrows = 2 * nrows;                           // real rows (both planes)
@@ -955,6 +1003,15 @@ int run_precompute(trap_ctx* ctx, int store_mask) {
       hipLaunchKernelGGL(k_theta_average, dim3(ceil_div(per_z_out * zc, 256)), dim3(256), 0, s, per_z_out, nthr,
                          zc, P.d_theta_rw, C.d_Mtmp, (mask & 1) ? C.d_M64 : nullptr, (mask & 2) ? C.d_M32 : nullptr,
                          (long long)z0 * per_z_out);
+      TRAP_HIP(hipGetLastError());
+    }
+    if (roles.on) {
+      if (mask & 1)
+        hipLaunchKernelGGL(k_mirror_rows<double>, dim3(2048), dim3(256), 0, s, z0, zc, nth, nt, nn, P.ldm, roles,
+                           C.d_M64);
+      if (mask & 2)
+        hipLaunchKernelGGL(k_mirror_rows<float>, dim3(2048), dim3(256), 0, s, z0, zc, nth, nt, nn, P.ldm, roles,
+                           C.d_M32);
       TRAP_HIP(hipGetLastError());
     }
   }
@@ -1223,7 +1280,7 @@ static int precompute_precond_body(trap_ctx* ctx) {
     const long long nrows = (long long)zc * ng * nk * nn;
     hipLaunchKernelGGL(k_kernel_rows, dim3((unsigned)ceil_div(nrows, rw)), dim3(64 * rw), rw * lds_row, s, nrows, ng,
                        nk, nn, ldm, P.d_x, P.d_lam, P.d_a, C.d_pcSt, C.d_pcTheta, Lrow, Grow, 0LL, z0, lay.h,
-                       lay.uniform ? Gt : nullptr, lay.uniform ? Vt : nullptr, lay.ntail);
+                       lay.uniform ? Gt : nullptr, lay.uniform ? Vt : nullptr, lay.ntail, RowRoles{});
     TRAP_HIP(hipGetLastError());
     TRAP_TRY(launch_sig_gemm(ctx, 2 * nrows, Grow, Lrow, Mtmp, (float*)nullptr, 0LL));
     hipLaunchKernelGGL(k_theta_average, dim3(ceil_div(per_z_out * zc, 256)), dim3(256), 0, s, per_z_out, ng, zc,

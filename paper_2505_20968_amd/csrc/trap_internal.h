@@ -62,6 +62,13 @@ struct DevBuf {
 struct Problem {
   int nz = 0, nn = 0, nmu = 0, nchi = 0, nd = 0;
   int nlos = 0, ngrid = 0;                 // line-of-sight rings; quadrature directions nmu * nchi
+  // kernel rows by mirror symmetry (empty: every row is computed).  On a grid
+  // symmetric about x = 0 the rows of shift s and -s satisfy
+  // M_s[n][m] = conj(M_{-s}[nn-1-n][nn-1-m]); row_role[t] = -1: all rows of t
+  // computed; = t: rows n <= nn-1-n computed, the others mirrored from t; = t2
+  // < t: every row mirrored from the fully computed t2
+  std::vector<int> row_role;
+  long long rows_mirrored = 0;             // complex kernel rows per (height, angle) taken from mirror images
   std::vector<double> los_mu;              // [nlos] mu of each zero-weight ring
   int nth = 0, nslot = 0, nu = 0, nl = 0, nt = 0;
   int max_slots_per_theta = 0;

@@ -58,7 +58,8 @@ class Info(ctypes.Structure):
                 ("n_lo", ctypes.c_int), ("n_trans", ctypes.c_int), ("n_unknowns", ctypes.c_size_t),
                 ("bytes_kernel_fp64", ctypes.c_size_t), ("bytes_kernel_fp32", ctypes.c_size_t),
                 ("bytes_device_total", ctypes.c_size_t), ("flops_contraction", ctypes.c_double),
-                ("bytes_contraction_fp64", ctypes.c_double), ("bytes_contraction_fp32", ctypes.c_double)]
+                ("bytes_contraction_fp64", ctypes.c_double), ("bytes_contraction_fp32", ctypes.c_double),
+                ("kernel_rows_mirrored", ctypes.c_longlong)]
 
 
 class SolveOpts(ctypes.Structure):

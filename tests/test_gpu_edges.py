@@ -177,3 +177,34 @@ def test_zero_guess_skips_the_first_apply_and_changes_nothing(inner):
     with pytest.raises(TrapError):
         ctx.gmres_solve(xc, zero_guess=True, **opts)
     ctx.close()
+
+
+def test_kernel_rows_by_mirror_symmetry():
+    """On a frequency grid symmetric about 0, the kernel rows of the shift +s
+    transition (and half of those of the unshifted one) are taken from mirror
+    images; Sigma still matches the oracle (1e-10), and an asymmetric grid,
+    which computes every row, does too."""
+    torch = _torch()
+    from oracle import transfer as T
+    from paper_2505_20968_amd import Context
+    base = tiny(n_z=4, n_nu=17, x_max=6.0, n_mu=4, n_chi=3, B=(40.0, 1.0, 0.4), a=2e-2, eps=5e-2, v_z=1.5, seed=9)
+    for prob, mirrored in ((base, 17 + 8), (base.with_(x=np.linspace(-6.0, 6.5, 17)), 0),
+                           (base.with_(B=np.zeros_like(base.B)), 3 * 8)):
+        c = Context(0)
+        try:
+            c.set_problem(prob)
+            c.precompute(3)
+            assert c.info()["kernel_rows_mirrored"] == mirrored
+            rng = np.random.default_rng(3)
+            I = rng.random((prob.n_z, prob.n_dir, prob.n_nu, 4))
+            ref = T.sigma_apply(T.setup(prob), I)
+            for dt, tol in ((torch.float64, 1e-10), (torch.float32, 2e-5)):
+                It = torch.tensor(I, dtype=dt, device="cuda")
+                e = torch.empty_like(It)
+                c.apply_sigma(It, e)
+                torch.cuda.synchronize()
+                r = np.linalg.norm(e.double().cpu().numpy() - ref) / np.linalg.norm(ref)
+                print(f"mirrored rows {mirrored}: sigma {dt} rel {r:.2e}", flush=True)
+                assert r < tol
+        finally:
+            c.close()
