@@ -489,8 +489,10 @@ typedef double doublex4_g __attribute__((ext_vector_type(4)));
 // Rows of a mirrored transition from their mirror images (Problem::row_role):
 // M[t][c][n][m] = (c ? -1 : 1) M[src][c][nn-1-n][nn-1-m] for m < nn, zero in
 // the padding; heights [z0, z0 + zc) of the stored kernels [z][th][t][2][nn][ldm].
-template <typename T>
-__global__ void k_mirror_rows(int z0, int zc, int nth, int nt, int nn, int ldm, RowRoles roles, T* __restrict__ M) {
+// The FP64 kernels are read once; the FP32 copy (when stored) gets the same
+// values rounded, as the product writes it.
+__global__ void k_mirror_rows(int z0, int zc, int nth, int nt, int nn, int ldm, RowRoles roles,
+                              double* __restrict__ M, float* __restrict__ M32) {
   const long long total = (long long)zc * nth * nt * 2 * nn * ldm;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
        i += (long long)gridDim.x * blockDim.x) {
@@ -504,13 +506,15 @@ __global__ void k_mirror_rows(int z0, int zc, int nth, int nt, int nn, int ldm, 
     const long long zt = q / nt;                       // (z - z0) * nth + th
     if (!row_mirrored(roles, t, n, nn)) continue;
     const size_t base = (size_t)(z0 * (long long)nth + zt) * nt;
-    T v = T(0);
+    double v = 0.0;
     if (m < nn) {
       const int src = roles.role[t];
       v = M[(((base + src) * 2 + c) * nn + (nn - 1 - n)) * ldm + (nn - 1 - m)];
       if (c) v = -v;
     }
-    M[(((base + t) * 2 + c) * nn + n) * ldm + m] = v;
+    const size_t o = (((base + t) * 2 + c) * nn + n) * ldm + m;
+    M[o] = v;
+    if (M32) M32[o] = (float)v;
   }
 }
 
@@ -1006,12 +1010,9 @@ int run_precompute(trap_ctx* ctx, int store_mask) {
       TRAP_HIP(hipGetLastError());
     }
     if (roles.on) {
-      if (mask & 1)
-        hipLaunchKernelGGL(k_mirror_rows<double>, dim3(2048), dim3(256), 0, s, z0, zc, nth, nt, nn, P.ldm, roles,
-                           C.d_M64);
-      if (mask & 2)
-        hipLaunchKernelGGL(k_mirror_rows<float>, dim3(2048), dim3(256), 0, s, z0, zc, nth, nt, nn, P.ldm, roles,
-                           C.d_M32);
+      // the FP64 kernels are always stored (mask bit 0)
+      hipLaunchKernelGGL(k_mirror_rows, dim3(2048), dim3(256), 0, s, z0, zc, nth, nt, nn, P.ldm, roles, C.d_M64,
+                         (mask & 2) ? C.d_M32 : nullptr);
       TRAP_HIP(hipGetLastError());
     }
   }
