@@ -668,3 +668,23 @@ def test_continuum_lte_column_keeps_the_planck_value():
     ref = np.zeros_like(b[:, up])
     ref[..., 0] = p.W_T[:, None, None]
     assert np.abs(b[:, up] - ref).max() < 1e-12
+
+
+def test_kernel_rows_mirror_symmetry():
+    """The comoving kernel rows of shift s and -s on a grid symmetric about 0
+    are conjugate mirror images, M_s[n][m] = conj(M_-s[N-1-n][N-1-m]): the
+    redistribution function is even under reversing both frequencies except
+    for its dispersion part, which is odd (w(-x + ia) = conj w(x + ia)), and the
+    spline basis of a symmetric grid is mirror symmetric.  A wrong sign of the
+    shift or of the dispersion part breaks it."""
+    from oracle.redistribution import kernel_matrix
+    x = np.linspace(-6.0, 6.0, 21)
+    basis = SplineBasis(x)
+    for th in (0.0, 0.4, 1.7, np.pi):
+        for s in (0.0, 0.45):
+            Mp = kernel_matrix(th, s, 0.03, 1.2, basis)
+            Mm = kernel_matrix(th, -s, 0.03, 1.2, basis)
+            scale = np.abs(Mp).max()
+            assert np.abs(Mp - np.conj(Mm[::-1, ::-1])).max() < 1e-12 * scale
+            if s and th:
+                assert np.abs(Mp - Mm[::-1, ::-1]).max() > 1e-3 * scale     # not without the conjugate
