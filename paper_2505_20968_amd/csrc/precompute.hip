@@ -493,26 +493,25 @@ typedef double doublex4_g __attribute__((ext_vector_type(4)));
 // values rounded, as the product writes it.
 __global__ void k_mirror_rows(int z0, int zc, int nth, int nt, int nn, int ldm, RowRoles roles,
                               double* __restrict__ M, float* __restrict__ M32) {
-  const long long total = (long long)zc * nth * nt * 2 * nn * ldm;
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
-       i += (long long)gridDim.x * blockDim.x) {
-    const int m = i % ldm;
-    long long q = i / ldm;
-    const int n = q % nn;
-    q /= nn;
-    const int c = q % 2;
-    q /= 2;
-    const int t = q % nt;
-    const long long zt = q / nt;                       // (z - z0) * nth + th
-    if (!row_mirrored(roles, t, n, nn)) continue;
-    const size_t base = (size_t)(z0 * (long long)nth + zt) * nt;
+  // grid z: height in the chunk; y: (angle, transition, plane); x: the plane's mirrored rows x ldm
+  const int plane = blockIdx.y;
+  const int c = plane & 1, t = (plane >> 1) % nt;
+  const int zt = blockIdx.z * nth + (plane >> 1) / nt;   // (z - z0) * nth + th
+  const int r = roles.role[t];
+  if (r < 0) return;
+  const int nfirst = r == t ? nn / 2 + (nn & 1) : 0;     // first mirrored row: n > nn-1-n
+  const int cnt = (nn - nfirst) * ldm;
+  const size_t base = (size_t)(z0 * (long long)nth + zt) * nt;
+  const double* src = M + ((base + r) * 2 + c) * (size_t)nn * ldm;
+  const size_t dst = ((base + t) * 2 + c) * (size_t)nn * ldm;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += gridDim.x * blockDim.x) {
+    const int n = nfirst + i / ldm, m = i - (i / ldm) * ldm;
     double v = 0.0;
     if (m < nn) {
-      const int src = roles.role[t];
-      v = M[(((base + src) * 2 + c) * nn + (nn - 1 - n)) * ldm + (nn - 1 - m)];
+      v = src[(size_t)(nn - 1 - n) * ldm + (nn - 1 - m)];
       if (c) v = -v;
     }
-    const size_t o = (((base + t) * 2 + c) * nn + n) * ldm + m;
+    const size_t o = dst + (size_t)n * ldm + m;
     M[o] = v;
     if (M32) M32[o] = (float)v;
   }
@@ -974,7 +973,8 @@ int run_precompute(trap_ctx* ctx, int store_mask) {
     C.zc_rows = zc_tab;
   }
   RowRoles roles{};
-  if (!P.row_role.empty() && nt <= kMaxRoles) {
+  // (the mirror pass takes one grid row per angle, transition and plane)
+  if (!P.row_role.empty() && nt <= kMaxRoles && (long long)nth * nt * 2 <= 65535) {
     roles.on = 1;
     for (int t = 0; t < nt; ++t) roles.role[t] = P.row_role[t];
   }
@@ -1011,7 +1011,9 @@ int run_precompute(trap_ctx* ctx, int store_mask) {
     }
     if (roles.on) {
       // the FP64 kernels are always stored (mask bit 0)
-      hipLaunchKernelGGL(k_mirror_rows, dim3(2048), dim3(256), 0, s, z0, zc, nth, nt, nn, P.ldm, roles, C.d_M64,
+      const dim3 mg((unsigned)std::min<long long>(64, ceil_div((long long)nn * P.ldm, 256)), (unsigned)(nth * nt * 2),
+                    (unsigned)zc);
+      hipLaunchKernelGGL(k_mirror_rows, mg, dim3(256), 0, s, z0, zc, nth, nt, nn, P.ldm, roles, C.d_M64,
                          (mask & 2) ? C.d_M32 : nullptr);
       TRAP_HIP(hipGetLastError());
     }
