@@ -583,7 +583,7 @@ __global__ void __launch_bounds__(512, 1) k_sig_gemm_lds(long long nrows, int nn
                                                          const double* __restrict__ Lrow,
                                                          const double* __restrict__ Sig,
                                                          double* __restrict__ M64, float* __restrict__ M32,
-                                                         long long out_row0) {
+                                                         long long out_row0, RowRoles roles, int nt) {
   constexpr int KP = 8 * NH, CP = 16 * NCT, BST = CP + 4;
   extern __shared__ double sgs[];      // [KP][BST]
   for (int e = threadIdx.x; e < KP * CP; e += blockDim.x) {
@@ -607,6 +607,15 @@ __global__ void __launch_bounds__(512, 1) k_sig_gemm_lds(long long nrows, int nn
   double2 fa[NH];
   const double* bcol = sgs + 2 * lk * BST + lr;
   for (long long tile = (long long)blockIdx.x * 8 + wave; tile < ntile; tile += step) {
+    // tiles of mirrored rows only are left to k_mirror_rows (rows [..][t][c][n])
+    if (roles.on) {
+      bool all = true;
+      for (int i = 0; i < 16 && all; ++i) {
+        const long long gr = tile * 16 + i;
+        all = gr >= nrows || row_mirrored(roles, (int)((gr / (2LL * nn)) % nt), (int)(gr % nn), nn);
+      }
+      if (all) continue;
+    }
     load(tile, fa);
     doublex4_g acc[NCT];
 #pragma unroll
@@ -662,8 +671,10 @@ __global__ void __launch_bounds__(512, 1) k_sig_gemm_lds(long long nrows, int nn
 }
 
 // M = L + Gam Sig for `rrows` real rows; the persistent form when Sig fits
+// `roles` (optional): mirror roles of rows laid out [..][t][c][n]; tiles made
+// only of mirrored rows are skipped (the persistent form), k_mirror_rows fills them
 int launch_sig_gemm(trap_ctx* ctx, long long rrows, const double* Gam, const double* Lrow, double* M64,
-                    float* M32, long long out_row0) {
+                    float* M32, long long out_row0, const RowRoles* roles = nullptr) {
   Problem& P = ctx->pb;
   const int nn = P.nn, ldm = P.ldm;
   const int nh = ldm / 8, nct = (nn + 15) / 16;
@@ -677,12 +688,13 @@ int launch_sig_gemm(trap_ctx* ctx, long long rrows, const double* Gam, const dou
   };
   if (lds > (size_t)ctx->max_lds || nh < 1 || nh > 16 || nct > 8) return fallback();
   const int grid = (int)std::min<long long>(ctx->n_cu, ceil_div((rrows + 15) / 16, 8));
+  const RowRoles rr = roles ? *roles : RowRoles{};
   auto launch = [&](auto kern) -> int {
     if (lds > 64 * 1024)
       TRAP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
                                    (int)lds));
     hipLaunchKernelGGL(kern, dim3(grid), dim3(512), lds, ctx->stream, rrows, nn, ldm, Gam, Lrow, P.d_Sig, M64, M32,
-                       out_row0);
+                       out_row0, rr, P.nt);
     TRAP_HIP(hipGetLastError());
     return TRAP_OK;
   };
@@ -999,7 +1011,7 @@ int run_precompute(trap_ctx* ctx, int store_mask) {
     const long long rrows = 2 * nrows;                           // real rows (both planes)
     if (!aa) {
       TRAP_TRY(launch_sig_gemm(ctx, rrows, C.d_Grow, C.d_Lrow, (mask & 1) ? C.d_M64 : nullptr,
-                               (mask & 2) ? C.d_M32 : nullptr, (long long)z0 * nth * nt * 2 * nn));
+                               (mask & 2) ? C.d_M32 : nullptr, (long long)z0 * nth * nt * 2 * nn, &roles));
     } else {
       // rows at the Gauss-Legendre angles into the scratch store, then their weighted sum
       TRAP_TRY(launch_sig_gemm(ctx, rrows, C.d_Grow, C.d_Lrow, C.d_Mtmp, (float*)nullptr, 0LL));
