@@ -478,9 +478,13 @@ int launch_pc_local_lambda(trap_ctx* ctx);
 int launch_formal_scalar(trap_ctx* ctx, int prec, const double* e, const double* y, int y_stride,
                          const double* x, double* res);
 
+// Every entry point holds one.  It also clears the thread's last HIP error, so
+// that the launch checks inside (hipGetLastError after each launch) report the
+// library's own errors, not one left by an earlier call of the caller's.
 struct DeviceGuard {
   int prev = -1;
   explicit DeviceGuard(int dev) {
+    (void)hipGetLastError();
     if (hipGetDevice(&prev) != hipSuccess) prev = -1;
     if (prev != dev) (void)hipSetDevice(dev);
   }
