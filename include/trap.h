@@ -224,6 +224,24 @@ int trap_precompute_preconditioner(trap_ctx* ctx);
 int trap_apply_preconditioner(trap_ctx* ctx, const double* r, double* out, int sweeps, int prec);
 int trap_preconditioner_tables(trap_ctx* ctx, double* phi, double* c, double* lloc);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the apply of
+ * trap_apply_preconditioner (same arguments, same kernels, same result) with
+ * its scratch vectors (the iterate, Sigma* x, the residual and the per-height
+ * comoving vectors, about 3 n_z n_dir N_nu + (2 + classes) n_z N_nu doubles)
+ * taken from a fixed 128 MiB device array instead of context allocations.  It
+ * calls no hipMalloc, hipFree or other allocating routine; the caller passes
+ * r and out as for trap_apply_preconditioner.  Each device the library runs
+ * on holds its own copy of the array until the process ends (its address is
+ * looked up at the first call on the device).  Every call on a device shares
+ * that device's array and leaves its contents behind (each apply writes every
+ * value it reads, so no clearing is needed): calls that overlap on one device
+ * (other streams, other host threads) race and must be serialised by the
+ * caller.  TRAP_ENOMEM, with the sizes in the message, for a problem whose
+ * scratch exceeds the array; otherwise the errors of
+ * trap_apply_preconditioner.  Asynchronous on the context's stream. */
+int trap_apply_preconditioner_noalloc(trap_ctx* ctx, const double* r, double* out, int sweeps, int prec);
+
 /* eps = Sigma I (Eq. matrix_form_2 without eps_th): comoving interpolation,
  * R_II contraction with the stored kernels, angular/sublevel sum, R_III,
  * back-interpolation and the factor f on Stokes I.  If add_thermal != 0 the

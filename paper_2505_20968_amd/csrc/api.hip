@@ -265,6 +265,12 @@ int trap_apply_preconditioner(trap_ctx* ctx, const double* r, double* out, int s
   return precond_apply(ctx, r, out, sweeps, prec);
 }
 
+int trap_apply_preconditioner_noalloc(trap_ctx* ctx, const double* r, double* out, int sweeps, int prec) {
+  if (!ctx) return fail(TRAP_EINVAL, "null context");
+  DeviceGuard g(ctx->device);
+  return precond_apply_noalloc(ctx, r, out, sweeps, prec);
+}
+
 int trap_preconditioner_tables(trap_ctx* ctx, double* phi, double* c, double* lloc) {
   if (!ctx) return fail(TRAP_EINVAL, "null context");
   if (!ctx->has_problem || !ctx->pre.pc_done) return fail(TRAP_ESTATE, "preconditioner tables not computed");

@@ -17,6 +17,10 @@
 // derivatives of the result) and a per-point one (interpolation back to every
 // direction, combined with the local Lambda and the running iterate); the
 // sweeps add the scalar formal solution with the residual fused into it.
+#include <mutex>
+#include <string>
+#include <vector>
+
 #include "trap_internal.h"
 
 namespace trap {
@@ -242,57 +246,135 @@ int precond_ensure(trap_ctx* ctx) {
   return TRAP_OK;
 }
 
-static int pc_gather(trap_ctx* ctx, const double* src, int stride, const double* Mat) {
+// Scratch vectors of one preconditioner apply: the iterate x, Sigma* x and the
+// residual ([z][o][n] each), the per-height comoving vector with its spline
+// second derivatives h [z][2][nn] and the class sums gc [z][ncmax][nn].
+struct PcWork {
+  double *x, *e, *res, *h, *gc;
+};
+
+static int pc_gather(trap_ctx* ctx, const PcWork& ws, const double* src, int stride, const double* Mat) {
   Problem& P = ctx->pb;
   Precomp& C = ctx->pre;
   hipLaunchKernelGGL(k_pc_gather_cls, dim3(P.nz * C.pc_ncmax), dim3(kGatherThreads),
                      (2 + kGatherParts) * P.nn * sizeof(double), ctx->stream, P.nd, P.nn, C.pc_ncmax, P.d_x,
-                     P.d_SigT, P.d_lam, P.d_w, C.d_pcMem, C.d_pcMoff, C.d_pcNcls, C.d_pcCub, src, stride,
-                     ctx->wk.pc_gc);
+                     P.d_SigT, P.d_lam, P.d_w, C.d_pcMem, C.d_pcMoff, C.d_pcNcls, C.d_pcCub, src, stride, ws.gc);
   TRAP_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_pc_gather_fin, dim3(P.nz), dim3(kGatherThreads), (2 + kGatherParts) * P.nn * sizeof(double),
-                     ctx->stream, P.nn, C.pc_ncmax, P.d_SigT, C.d_pcNcls, ctx->wk.pc_gc, Mat, ctx->wk.pc_h);
+                     ctx->stream, P.nn, C.pc_ncmax, P.d_SigT, C.d_pcNcls, ws.gc, Mat, ws.h);
   TRAP_HIP(hipGetLastError());
   return TRAP_OK;
 }
 
-static int pc_scatter(trap_ctx* ctx, int mode, const double* src, int src_stride, const double* xin,
-                      const double* res, double* dst, int dst_stride) {
+static int pc_scatter(trap_ctx* ctx, const PcWork& ws, int mode, const double* src, int src_stride,
+                      const double* xin, const double* res, double* dst, int dst_stride) {
   Problem& P = ctx->pb;
   const long long ns = (long long)P.nz * P.nd * P.nn;
   hipLaunchKernelGGL(k_pc_scatter, dim3(ceil_div(ns, 256)), dim3(256), 0, ctx->stream, mode, P.nz, P.nd, P.nn,
-                     P.d_x, P.d_lam, P.d_ub, ctx->wk.pc_h, ctx->pre.d_pcL, src, src_stride, xin, res, dst,
-                     dst_stride);
+                     P.d_x, P.d_lam, P.d_ub, ws.h, ctx->pre.d_pcL, src, src_stride, xin, res, dst, dst_stride);
   TRAP_HIP(hipGetLastError());
   return TRAP_OK;
 }
 
-int precond_apply(trap_ctx* ctx, const double* r, double* out, int sweeps, int prec) {
+static int precond_check(trap_ctx* ctx, const double* r, double* out, int sweeps, int prec) {
   if (!ctx->has_problem || !ctx->pre.pc_done) return fail(TRAP_ESTATE, "preconditioner tables not computed");
   if (!r || !out) return fail(TRAP_EINVAL, "null vector");
   if (sweeps < 1 || sweeps > 64) return fail(TRAP_EINVAL, "preconditioner sweeps must be in [1, 64]");
   if (prec != TRAP_FP64 && prec != TRAP_FP32) return fail(TRAP_EINVAL, "unknown precision");
+  return TRAP_OK;
+}
+
+// out = M r with the scratch vectors ws; every value of ws that a kernel reads
+// was written earlier in the same apply, so ws needs no clearing.
+static int precond_apply_ws(trap_ctx* ctx, const PcWork& ws, const double* r, double* out, int sweeps, int prec) {
   Problem& P = ctx->pb;
   Precomp& C = ctx->pre;
-  Work& K = ctx->wk;
   const long long ns = (long long)P.nz * P.nd * P.nn;
-  TRAP_TRY(precond_ensure(ctx));
   if (out != r) TRAP_HIP(hipMemcpyAsync(out, r, 4 * ns * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
   // x_1 = P^^-1 y with y the Stokes I of `out` (read until the last write)
-  TRAP_TRY(pc_gather(ctx, out, 4, C.d_pcC));
-  if (sweeps == 1) return pc_scatter(ctx, PC_FIRST, out, 4, nullptr, nullptr, out, 4);
-  TRAP_TRY(pc_scatter(ctx, PC_FIRST, out, 4, nullptr, nullptr, K.pc_x, 1));
+  TRAP_TRY(pc_gather(ctx, ws, out, 4, C.d_pcC));
+  if (sweeps == 1) return pc_scatter(ctx, ws, PC_FIRST, out, 4, nullptr, nullptr, out, 4);
+  TRAP_TRY(pc_scatter(ctx, ws, PC_FIRST, out, 4, nullptr, nullptr, ws.x, 1));
   for (int k = 2; k <= sweeps; ++k) {
     // res = y - P x = y - x + Lambda* Sigma* x
-    TRAP_TRY(pc_gather(ctx, K.pc_x, 1, C.d_pcPhi));
-    TRAP_TRY(pc_scatter(ctx, PC_SIGMA, nullptr, 0, nullptr, nullptr, K.pc_e, 1));
-    TRAP_TRY(launch_formal_scalar(ctx, prec, K.pc_e, out, 4, K.pc_x, K.pc_res));
+    TRAP_TRY(pc_gather(ctx, ws, ws.x, 1, C.d_pcPhi));
+    TRAP_TRY(pc_scatter(ctx, ws, PC_SIGMA, nullptr, 0, nullptr, nullptr, ws.e, 1));
+    TRAP_TRY(launch_formal_scalar(ctx, prec, ws.e, out, 4, ws.x, ws.res));
     // x += P^^-1 res
-    TRAP_TRY(pc_gather(ctx, K.pc_res, 1, C.d_pcC));
+    TRAP_TRY(pc_gather(ctx, ws, ws.res, 1, C.d_pcC));
     const bool last = k == sweeps;
-    TRAP_TRY(pc_scatter(ctx, PC_UPDATE, nullptr, 0, K.pc_x, K.pc_res, last ? out : K.pc_x, last ? 4 : 1));
+    TRAP_TRY(pc_scatter(ctx, ws, PC_UPDATE, nullptr, 0, ws.x, ws.res, last ? out : ws.x, last ? 4 : 1));
   }
   return TRAP_OK;
+}
+
+int precond_apply(trap_ctx* ctx, const double* r, double* out, int sweeps, int prec) {
+  TRAP_TRY(precond_check(ctx, r, out, sweeps, prec));
+  TRAP_TRY(precond_ensure(ctx));
+  Work& K = ctx->wk;
+  const PcWork ws{K.pc_x, K.pc_e, K.pc_res, K.pc_h, K.pc_gc};
+  return precond_apply_ws(ctx, ws, r, out, sweeps, prec);
+}
+
+// ---------------------------------------------------------------- allocation-free apply
+// The same apply with its scratch vectors in a file-scope device array of
+// fixed size instead of context allocations.  Every device the library runs
+// on holds its own copy of the array for the life of the process; its
+// address on a device is looked up once, with that device current, and kept.
+// Calls on one device share the array, so calls that overlap on one device
+// (on different streams, or from different host threads) race.
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+static std::mutex g_scratch_mu;
+static std::vector<unsigned char*> g_scratch_dev;   // per device: device address of `scratch`
+
+static int scratch_address(int device, unsigned char** out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if ((int)g_scratch_dev.size() <= device) g_scratch_dev.resize(device + 1, nullptr);
+  if (!g_scratch_dev[device]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(TRAP_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_dev[device] = static_cast<unsigned char*>(ptr);
+  }
+  *out = g_scratch_dev[device];
+  return TRAP_OK;
+}
+
+static size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+size_t precond_noalloc_bytes(const Problem& P, int ncmax) {
+  const size_t ns = (size_t)P.nz * P.nd * P.nn;
+  return 3 * align256(ns * sizeof(double)) + align256((size_t)P.nz * 2 * P.nn * sizeof(double)) +
+         align256((size_t)P.nz * ncmax * P.nn * sizeof(double));
+}
+
+int precond_apply_noalloc(trap_ctx* ctx, const double* r, double* out, int sweeps, int prec) {
+  if (ctx->has_problem) {
+    const size_t need = precond_noalloc_bytes(ctx->pb, ctx->pre.pc_done ? ctx->pre.pc_ncmax : 0);
+    if (need > kNoAllocScratchBytes)
+      return fail(TRAP_ENOMEM, "allocation-free preconditioner apply: the problem needs " + std::to_string(need) +
+                                   " bytes of scratch, above the fixed " + std::to_string(kNoAllocScratchBytes));
+  }
+  TRAP_TRY(precond_check(ctx, r, out, sweeps, prec));
+  unsigned char* base = nullptr;
+  TRAP_TRY(scratch_address(ctx->device, &base));
+  const Problem& P = ctx->pb;
+  const size_t ns = (size_t)P.nz * P.nd * P.nn;
+  PcWork ws;
+  size_t off = 0;
+  auto carve = [&](size_t bytes) {
+    double* p = reinterpret_cast<double*>(base + off);
+    off += align256(bytes);
+    return p;
+  };
+  ws.x = carve(ns * sizeof(double));
+  ws.e = carve(ns * sizeof(double));
+  ws.res = carve(ns * sizeof(double));
+  ws.h = carve((size_t)P.nz * 2 * P.nn * sizeof(double));
+  ws.gc = carve((size_t)P.nz * ctx->pre.pc_ncmax * P.nn * sizeof(double));
+  return precond_apply_ws(ctx, ws, r, out, sweeps, prec);
 }
 
 }  // namespace trap

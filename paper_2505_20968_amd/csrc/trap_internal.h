@@ -471,6 +471,11 @@ int launch_formal_grouped(hipStream_t s, const GFormal* args, const int* off, in
 // (precond.hip; out may equal r)
 int run_precompute_precond(trap_ctx* ctx);
 int precond_apply(trap_ctx* ctx, const double* r, double* out, int sweeps, int prec);
+// the same apply with its scratch in a fixed device array (no allocation):
+// kNoAllocScratchBytes per device, shared by every call on that device
+constexpr size_t kNoAllocScratchBytes = size_t(128) << 20;
+size_t precond_noalloc_bytes(const Problem& P, int ncmax);
+int precond_apply_noalloc(trap_ctx* ctx, const double* r, double* out, int sweeps, int prec);
 // local Lambda and step coefficients of the scalar formal solution, and the
 // sweep of Lambda* with the fused residual res = y - x + Lambda* e
 // (formal.hip; the sweep's arithmetic is FP64 whatever prec)

@@ -29,7 +29,7 @@ EXPORTED = ["trap_create", "trap_destroy", "trap_set_problem", "trap_precompute"
             "trap_gmres_solve", "trap_emergent", "trap_get_info", "trap_footprint",
             "trap_profile", "trap_stage_times", "trap_set_path", "trap_set_prd_mode", "trap_gmres_begin",
             "trap_gmres_step_batch", "trap_gmres_end", "trap_precompute_preconditioner",
-            "trap_apply_preconditioner", "trap_preconditioner_tables", "trap_set_formal_scheme",
+            "trap_apply_preconditioner", "trap_apply_preconditioner_noalloc", "trap_preconditioner_tables", "trap_set_formal_scheme",
             "trap_formal_from_field", "trap_emergent_los", "trap_aar_solve", "trap_last_error"]
 STAGES = ["comoving", "contract_fp32", "r3", "angular", "backinterp", "formal", "kernel_rows",
           "contract_fp64"]
@@ -123,6 +123,7 @@ def load_library(path: str = LIB_PATH):
     lib.trap_precompute_preconditioner.argtypes = [vp]
     lib.trap_set_formal_scheme.argtypes = [vp, ctypes.c_int]
     lib.trap_apply_preconditioner.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.c_int]
+    lib.trap_apply_preconditioner_noalloc.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.c_int]
     lib.trap_preconditioner_tables.argtypes = [vp, _dp, _dp, _dp]
     lib.trap_formal_from_field.argtypes = [vp, vp, ctypes.c_int, vp]
     lib.trap_aar_solve.argtypes = [vp, ctypes.POINTER(AarOpts), vp, ctypes.POINTER(SolveStats)]
@@ -260,6 +261,11 @@ class Context:
     def apply_preconditioner(self, r, out, sweeps: int, prec: int = TRAP_FP64):
         _check(self.lib.trap_apply_preconditioner(self.h, self._vec(r, TRAP_FP64), self._vec(out, TRAP_FP64),
                                                   int(sweeps), int(prec)))
+
+    def apply_preconditioner_noalloc(self, r, out, sweeps: int, prec: int = TRAP_FP64):
+        """apply_preconditioner with the library's fixed device scratch (no allocation)."""
+        _check(self.lib.trap_apply_preconditioner_noalloc(self.h, self._vec(r, TRAP_FP64),
+                                                          self._vec(out, TRAP_FP64), int(sweeps), int(prec)))
 
     def preconditioner_tables(self) -> dict:
         nz, nd, nn = self.shape[0], self.shape[1], self.shape[2]
