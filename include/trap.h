@@ -139,6 +139,14 @@ typedef struct {
                                      filled from the mirror image of a computed row
                                      (frequency grid symmetric about 0 and transition shifts
                                      in +-s pairs, as M_s[n][m] = conj(M_-s[N-1-n][N-1-m])) */
+  long long kernel_entries;     /* complex kernel entries inside the rows' bands (Sect. 4.3):
+                                   each row keeps the columns its redistribution function
+                                   reaches (6.6 Gaussian widths 2 sin(Theta/2)) plus the reach
+                                   of the spline basis (entries below 1e-13 of the row dropped);
+                                   flops_contraction counts 16 per entry and incoming slot.
+                                   The store holds 16-row tiles over the union of their rows'
+                                   bands: bytes_kernel_fp32 / 4 real entries */
+  int band_reach;               /* that reach, in frequency nodes */
 } trap_info;
 
 typedef struct {
@@ -388,6 +396,23 @@ int trap_get_info(const trap_ctx* ctx, trap_info* info);
  * device. */
 int trap_footprint(const trap_atom_desc* atom, const trap_problem_desc* prob, int store_mask,
                    size_t* bytes);
+
+/* Diagnostics of the stored kernels and of the device Faddeeva function.
+ * trap_kernel_rows copies the FP64 R_II kernel M[z][theta][t] (Sect. 4.3; rows
+ * n, columns m of the comoving spline basis, real plane then imaginary plane,
+ * zero outside each row's stored band) to host_out [2][n_nu][n_nu], with the
+ * scattering angle (radians; for the angle-averaged mode theta = 0 names the
+ * averaged kernel) and the transition's reduced shift s_t (u units) of that
+ * height; TRAP_ESTATE before trap_precompute, TRAP_EINVAL for indices out of
+ * range.  Synchronises.
+ * trap_faddeeva evaluates the library's device Faddeeva function
+ * W(a, v) = w(v + i a) (Sect. 2.3; Weideman's rational expansion, a continued
+ * fraction far out) at n points (v[i], a[i]), a >= 0, into out [n][2] (real,
+ * imaginary); host arrays; allocates and frees device scratch; synchronises
+ * the device. */
+int trap_kernel_rows(trap_ctx* ctx, int z, int theta, int t, double* theta_out, double* shift_out,
+                     double* host_out);
+int trap_faddeeva(int device, const double* v, const double* a, int n, double* out);
 
 /* Per-stage device timing.  trap_profile(ctx, 1) starts recording HIP events
  * around every kernel launch of the listed stages on the context's stream

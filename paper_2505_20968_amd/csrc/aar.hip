@@ -267,7 +267,7 @@ int aar_solve(trap_ctx* ctx, const trap_aar_opts* o, double* x, trap_solve_stats
   const bool mixed = o->inner == TRAP_FP32;
   if (mixed && (!(o->inner_tol > 0 && o->inner_tol < 1) || o->max_outer < 1))
     return fail(TRAP_EINVAL, "bad refinement options (0 < inner_tol < 1, max_outer >= 1)");
-  if (mixed && !ctx->pre.d_M32) return fail(TRAP_ESTATE, "FP32 kernels not stored");
+  if (mixed && !ctx->pre.d_cf32) return fail(TRAP_ESTATE, "FP32 kernels not stored");
   if (o->precond_sweeps < 0 || o->precond_sweeps > 64)
     return fail(TRAP_EINVAL, "preconditioner sweeps must be in [0, 64]");
   if (o->precond_sweeps > 0 && !ctx->pre.pc_done) return fail(TRAP_ESTATE, "preconditioner tables not computed");

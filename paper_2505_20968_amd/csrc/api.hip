@@ -6,6 +6,10 @@
 #include <set>
 #include <string>
 
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
 #include "trap_internal.h"
 
 namespace trap {
@@ -397,22 +401,74 @@ int trap_get_info(const trap_ctx* ctx, trap_info* info) {
   info->n_lo = P.nl;
   info->n_trans = P.nt;
   info->n_unknowns = 4ull * P.nz * P.nd * P.nn;
-  const double kel = (double)P.nz * P.nth * P.nt * 2.0 * P.nn * P.nn;
-  info->bytes_kernel_fp64 = (size_t)((double)P.nz * P.nth * P.nt * 2.0 * P.nn * P.ldm * 8);
-  info->bytes_kernel_fp32 = (size_t)((double)P.nz * P.nth * P.nt * 2.0 * P.nn * P.ldm * 4);
+  // the banded store: FP32 values (the FP32 kernel) and FP32 remainders (with
+  // the values, the FP64 kernel)
+  const double kel = (double)P.kentries;
+  info->bytes_kernel_fp64 = P.kentries * 8;
+  info->bytes_kernel_fp32 = P.kentries * 4;
+  info->kernel_entries = (long long)P.band_nnz;
+  info->band_reach = P.band_reach;
   size_t tot = 0;
   for (auto& b : ctx->bufs) tot += b.bytes;
   for (auto& b : ctx->spare) tot += b.bytes;
   info->bytes_device_total = tot;
-  // per complex kernel entry: 4 Stokes columns x (real, imag) multiply-adds = 16 flops per slot
-  info->flops_contraction = 16.0 * P.nz * P.nt * (double)P.nn * P.nn * P.nslot;
-  // algorithmic bytes: every kernel entry read once, Ibar read, W written once
+  // per stored complex kernel entry: 4 Stokes columns x (real, imag) multiply-adds = 16 flops per slot
+  info->flops_contraction = chunk_flops(P, 0, P.nz);
+  // algorithmic bytes: every stored kernel entry read once (FP32 values; FP64
+  // adds the remainders), Ibar read, W written once
   const double wbytes = (double)P.nz * P.nt * P.nslot * 2.0 * P.nn * 4;
   const double ibytes = (double)P.nz * P.nd * P.nn * 4;
   info->bytes_contraction_fp64 = 8.0 * (kel + wbytes + ibytes);
   info->bytes_contraction_fp32 = 4.0 * (kel + wbytes + ibytes);
   info->kernel_rows_mirrored = P.rows_mirrored;
   return TRAP_OK;
+}
+
+int trap_kernel_rows(trap_ctx* ctx, int z, int theta, int t, double* theta_out, double* shift_out,
+                     double* host_out) {
+  if (!ctx || !host_out) return fail(TRAP_EINVAL, "null argument");
+  if (!ctx->has_problem || !ctx->pre.done) return fail(TRAP_ESTATE, "precompute not run");
+  const Problem& P = ctx->pb;
+  if (z < 0 || z >= P.nz || theta < 0 || theta >= P.nth || t < 0 || t >= P.nt)
+    return fail(TRAP_EINVAL, "kernel index out of range");
+  DeviceGuard g(ctx->device);
+  const size_t zt = (size_t)z * P.nth + theta, nn = P.nn;
+  const long long first = P.kbase[zt];
+  const long long last = zt + 1 < P.kbase.size() ? P.kbase[zt + 1] : (long long)P.kentries;
+  const size_t cnt = (size_t)(last - first);
+  std::vector<float> hi(cnt), lo(cnt);
+  TRAP_HIP(hipMemcpyAsync(hi.data(), ctx->pre.d_Mhi + first, cnt * sizeof(float), hipMemcpyDeviceToHost,
+                          ctx->stream));
+  TRAP_HIP(hipMemcpyAsync(lo.data(), ctx->pre.d_Mlo + first, cnt * sizeof(float), hipMemcpyDeviceToHost,
+                          ctx->stream));
+  TRAP_HIP(hipStreamSynchronize(ctx->stream));
+  std::fill(host_out, host_out + 2 * nn * nn, 0.0);
+  for (int c = 0; c < 2; ++c)
+    for (size_t n = 0; n < nn; ++n) {
+      int q, lr;
+      row_tile(P.qpad, 2 * P.nt, P.nn, 2 * t + c, (int)n, &q, &lr);
+      const unsigned w = P.qk[zt * P.nq + q];
+      const int a = (int)(w & 0xffffu), b = (int)(w >> 16);
+      const size_t row = (size_t)P.tofs[zt * P.nq + q] + (size_t)lr * (b - a);
+      for (int m = a; m < b && m < (int)nn; ++m)
+        host_out[(c * nn + n) * nn + m] = (double)hi[row + m - a] + (double)lo[row + m - a];
+    }
+  if (theta_out) *theta_out = P.theta[theta];
+  if (shift_out) {
+    std::vector<double> st(P.nt);
+    TRAP_HIP(hipMemcpy(st.data(), P.d_st + (size_t)z * P.nt, P.nt * sizeof(double), hipMemcpyDeviceToHost));
+    *shift_out = st[t];
+  }
+  return TRAP_OK;
+}
+
+int trap_faddeeva(int device, const double* v, const double* a, int n, double* out) {
+  if (!v || !a || !out || n < 0) return fail(TRAP_EINVAL, "null argument or negative count");
+  for (int i = 0; i < n; ++i)
+    if (!(a[i] >= 0.0) || !std::isfinite(v[i])) return fail(TRAP_EINVAL, "points need finite v and a >= 0");
+  if (n == 0) return TRAP_OK;
+  DeviceGuard g(device);
+  return faddeeva_eval(device, v, a, n, out);
 }
 
 int trap_gmres_begin(trap_ctx* ctx, const trap_solve_opts* opts, double* I) {

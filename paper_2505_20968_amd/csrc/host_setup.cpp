@@ -577,6 +577,188 @@ PrecompLayout precomp_layout(int nz, int nn, int ldm, int nt, int nthr, bool aa,
   return L;
 }
 
+// ---------------------------------------------------------------- banded kernel store
+// Largest k with x[k] <= v (-1 below the grid, nn - 1 at or past its end):
+// the interval search of the kernel-row precompute.
+static int upper_node(const std::vector<double>& x, double v) {
+  const int nn = static_cast<int>(x.size());
+  if (v < x[0]) return -1;
+  if (v >= x[nn - 1]) return nn - 1;
+  int lo = 0, hi = nn - 1;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (x[mid] <= v) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+void kernel_bands(Problem& P, const std::vector<double>& sig) {
+  const int nz = P.nz, nn = P.nn, nth = P.nth, np = 2 * P.nt;
+  const bool aa = P.prd_mode == TRAP_PRD_AA;
+  // reach of the spline map: column m of M = L + Gam Sig receives node j's
+  // weight through Sig[j][m], which decays geometrically away from j; beyond
+  // `reach` nodes every entry is below 1e-13 of its row's largest
+  int reach = 0;
+  for (int j = 0; j < nn; ++j) {
+    double mx = 0.0;
+    for (int m = 0; m < nn; ++m) mx = std::max(mx, std::fabs(sig[(size_t)j * nn + m]));
+    for (int m = 0; m < nn; ++m)
+      if (std::fabs(sig[(size_t)j * nn + m]) > 1e-13 * mx) reach = std::max(reach, std::abs(m - j));
+  }
+  P.band_reach = reach;
+  // Gaussian half-width factor of each stored angle: sin(Theta/2) (1 at
+  // Theta = pi, 0 at Theta = 0: the diagonal row); the angle average takes
+  // its widest node
+  std::vector<double> sg(nth);
+  for (int t = 0; t < nth; ++t) {
+    if (aa) {
+      double th = 0.0;
+      for (double v : P.theta_rows) th = std::max(th, v);
+      sg[t] = th >= kPi ? 1.0 : std::sin(0.5 * th);
+    } else {
+      const double th = P.theta[t];
+      sg[t] = th == 0.0 ? 0.0 : (th >= kPi ? 1.0 : std::sin(0.5 * th));
+    }
+  }
+  std::vector<int> nslots(nth);
+  for (int t = 0; t < nth; ++t) nslots[t] = P.slot_off[t + 1] - P.slot_off[t];
+  // band [lo, hi) of every row n of every (z, theta): the knot intervals within
+  // 6.6 Gaussian widths 2 sin(Theta/2)/lam of x_n (what the kernel-row
+  // precompute integrates), one node of margin for rounding, then the spline's
+  // reach; the in-band entries are the algorithmic work
+  std::vector<short> blo((size_t)nz * nth * nn), bhi((size_t)nz * nth * nn);
+  P.kflops_z.assign(nz, 0.0);
+  P.band_nnz = 0.0;
+  for (int z = 0; z < nz; ++z)
+    for (int t = 0; t < nth; ++t) {
+      const size_t zt = (size_t)z * nth + t;
+      const double R = 6.6 * 2.0 * sg[t] / P.lam[z];
+      long long cnt = 0;
+      // x_n - R and x_n + R increase with n: the interval searches walk forward
+      int plo = -1, phi = -1;
+      for (int n = 0; n < nn; ++n) {
+        int lo, hi;
+        if (sg[t] == 0.0) {
+          lo = n;
+          hi = n + 1;
+        } else {
+          const double xn = P.x[n], a = xn - R, b = xn + R;
+          if (n == 0) {
+            plo = upper_node(P.x, a);
+            phi = upper_node(P.x, b);
+          } else {
+            while (plo + 1 < nn && P.x[plo + 1] <= a) ++plo;
+            while (phi + 1 < nn && P.x[phi + 1] <= b) ++phi;
+          }
+          int ph = phi;
+          if (ph >= 0 && ph < nn - 1 && P.x[ph] >= b) ph -= 1;
+          const int jlo = std::max(plo, 0), jhi = std::min(ph + 1, nn - 1);
+          lo = std::max(0, jlo - 1 - reach);
+          hi = std::min(nn, jhi + 2 + reach);
+        }
+        blo[zt * nn + n] = static_cast<short>(lo);
+        bhi[zt * nn + n] = static_cast<short>(hi);
+        cnt += hi - lo;
+      }
+      P.band_nnz += (double)P.nt * cnt;
+      P.kflops_z[z] += 16.0 * P.nt * (double)cnt * nslots[t];
+    }
+  // wave tiles in both row layouts; the one with less column work is kept:
+  // every wave of a block steps through the block's column range (the union
+  // of its eight tiles' ranges), times the incoming slots of the angle
+  auto tiles = [&](bool pad, std::vector<int>& row0, std::vector<unsigned>& qk, double* work) {
+    const int nnp = pad ? (nn + 15) / 16 * 16 : nn;
+    const int rows = np * nnp;
+    const int nq = (rows + 15) / 16;
+    row0.assign(nq, 0);
+    for (int q = 0; q < nq; ++q) row0[q] = pad ? (q % np) * nnp + 16 * (q / np) : 16 * q;
+    qk.assign((size_t)nz * nth * nq, 0u);
+    *work = 0.0;
+    // the band ends never decrease with n, so a run of rows n_a..n_b of one
+    // plane spans [lo(n_a), hi(n_b))
+    for (size_t zt = 0; zt < (size_t)nz * nth; ++zt) {
+      const short* bl = &blo[zt * nn];
+      const short* bh = &bhi[zt * nn];
+      for (int q = 0; q < nq; ++q) {
+        int lo = P.ldm, hi = 0;
+        const int r1 = std::min(row0[q] + 16, rows);
+        for (int r = row0[q]; r < r1;) {
+          const int p = r / nnp, n = r - p * nnp;
+          const int run = std::min(r1 - r, nnp - n);        // rows left in this plane
+          const int nb = std::min(n + run, nn) - 1;
+          if (nb >= n) {
+            lo = std::min(lo, (int)bl[n]);
+            hi = std::max(hi, (int)bh[nb]);
+          }
+          r += run;
+        }
+        if (hi <= lo) lo = hi = 0;
+        lo = lo / 8 * 8;
+        hi = std::min((hi + 7) / 8 * 8, P.ldm);
+        qk[zt * nq + q] = (unsigned)lo | ((unsigned)hi << 16);
+      }
+      for (int q0 = 0; q0 < nq; q0 += 8) {
+        int lo = P.ldm, hi = 0;
+        for (int q = q0; q < std::min(q0 + 8, nq); ++q) {
+          const unsigned v = qk[zt * nq + q];
+          if ((v >> 16) > (v & 0xffffu)) {
+            lo = std::min(lo, (int)(v & 0xffffu));
+            hi = std::max(hi, (int)(v >> 16));
+          }
+        }
+        if (hi > lo) *work += 8.0 * (hi - lo) * nslots[zt % nth];
+      }
+    }
+    return nnp;
+  };
+  std::vector<int> r0a, r0b;
+  std::vector<unsigned> qka, qkb;
+  double wa = 0.0, wb = 0.0;
+  const int nnpa = tiles(false, r0a, qka, &wa);
+  const int nnpb = tiles(true, r0b, qkb, &wb);
+  const bool pad = wb < wa;
+  P.qpad = pad ? 1 : 0;
+  P.nnp = pad ? nnpb : nnpa;
+  P.qrow0 = pad ? r0b : r0a;
+  P.qk = pad ? qkb : qka;
+  P.nq = static_cast<int>(P.qrow0.size());
+  P.nqb = (P.nq + 7) / 8;
+  // tile offsets: tiles of (z, theta) back to back in block order, each
+  // [16][hi - lo]
+  P.tofs.assign((size_t)nz * nth * P.nq, 0);
+  P.td.assign((size_t)nz * nth * P.nq, TileDesc{0, 0, 0});
+  P.kbase.assign((size_t)nz * nth, 0);
+  P.qb.assign((size_t)nz * nth * P.nqb, 0u);
+  long long total = 0;
+  for (size_t zt = 0; zt < (size_t)nz * nth; ++zt) {
+    P.kbase[zt] = total;
+    int off = 0;
+    for (int q = 0; q < P.nq; ++q) {
+      const unsigned v = P.qk[zt * P.nq + q];
+      P.tofs[zt * P.nq + q] = off;
+      off += 16 * (int)((v >> 16) - (v & 0xffffu));
+    }
+    total += off;
+    for (int q = 0; q < P.nq; ++q) {
+      const unsigned v = P.qk[zt * P.nq + q];
+      P.td[zt * P.nq + q] = TileDesc{P.kbase[zt] + P.tofs[zt * P.nq + q], (int)(v & 0xffffu), (int)(v >> 16)};
+    }
+    for (int bq = 0; bq < P.nqb; ++bq) {
+      unsigned lo = 0xffffu, hi = 0;
+      for (int q = 8 * bq; q < std::min(8 * bq + 8, P.nq); ++q) {
+        const unsigned v = P.qk[zt * P.nq + q];
+        if ((v >> 16) > (v & 0xffffu)) {
+          lo = std::min(lo, v & 0xffffu);
+          hi = std::max(hi, v >> 16);
+        }
+      }
+      if (hi <= lo) lo = hi = 0;
+      P.qb[zt * P.nqb + bq] = lo | (hi << 16);
+    }
+  }
+  P.kentries = (size_t)total;
+}
+
 static int zero_field_classes(const trap_atom_desc& at, double dnuD_ref, std::vector<double>* dE,
                               std::vector<int>* cls);
 
@@ -625,15 +807,37 @@ size_t estimate_bytes(const trap_atom_desc* atom, const trap_problem_desc* pd, i
   const size_t nz = P.nz, nn = P.nn, nd = P.nd, nth = P.nth, nslot = P.nslot, ldm = P.ldm;
   const size_t N = 4 * nz * nd * nn;
   const int mask = store_mask | 1;
-  const size_t ker = nz * nth * nt * 2 * nn * ldm;       // stored kernel entries per precision
+  // the banded kernel store: bands from the grids and the Doppler widths
+  std::vector<double> lam_b(nz);
+  {
+    const double mass = atom->mass_amu * kAMU;
+    const double Tref = pd->T_ref > 0 ? pd->T_ref : 6000.0;
+    const double vref = std::sqrt(2.0 * kKB * Tref / mass);
+    for (size_t z = 0; z < nz; ++z) {
+      const double xi = pd->xi ? pd->xi[z] * 1e5 : 0.0;
+      lam_b[z] = vref / std::sqrt(2.0 * kKB * pd->T[z] / mass + xi * xi);
+    }
+    P.x.assign(pd->x, pd->x + nn);
+    for (size_t k = 0; k + 1 < nn; ++k)
+      if (!(P.x[k + 1] > P.x[k])) {
+        *err = 1;
+        return 0;
+      }
+    P.lam = lam_b;
+    P.nt = static_cast<int>(nt);
+    std::vector<double> sig;
+    spline_map(P.x, &sig);
+    kernel_bands(P, sig);
+  }
   const size_t cfe = nz * nd * nd * nt * 2 * nl * 16;    // angular coefficients per precision
   size_t b = 0;
   auto add = [&b](size_t bytes) { b += bytes ? bytes : 16; };   // one allocation
   auto add_vec = [&add](const auto& v) { add(v.size() * sizeof(v[0])); };
+  add(P.kentries * 4);                                  // kernel values (FP32)
+  add(P.kentries * 4);                                  //   and remainders
   for (int pi = 0; pi < 2; ++pi) {
     if (!(mask & (1 << pi))) continue;
     const size_t es = pi == 0 ? 8 : 4;
-    add(ker * es);
     add(cfe * es);
     for (int k = 0; k < 3; ++k) add(N * es);           // comoving field, two work vectors
     add(nz * nl * nl * nd * nn * 4 * es);               // eps_bar
@@ -690,6 +894,8 @@ size_t estimate_bytes(const trap_atom_desc* atom, const trap_problem_desc* pd, i
     item(nz * nu * nu * 16);                             // alpha
     item(nz * nu * nu * 16);                             // beta - alpha
     item(nz * nt * nd * 4 * 8);                          // g
+    item_vec(P.td);                                      // banded store layout
+    item_vec(P.qb);
     if (pd->kappa_c || pd->sigma_c) {
       item(nz * nn * 8);                                 // kappa_c
       item(nz * nn * 8);                                 // sigma_c
@@ -1035,6 +1241,7 @@ int build_problem(trap_ctx* ctx, const trap_atom_desc* at, const trap_problem_de
   // ---- upload
   std::vector<double> sig;
   auto spl = spline_map(P.x, &sig);
+  kernel_bands(P, sig);
   std::vector<double> sigT(sig.size());
   for (int i = 0; i < nn; ++i)
     for (int j = 0; j < nn; ++j) sigT[(size_t)j * nn + i] = sig[(size_t)i * nn + j];
@@ -1106,6 +1313,8 @@ int build_problem(trap_ctx* ctx, const trap_atom_desc* at, const trap_problem_de
   up.add(&P.d_alpha, alpha);
   up.add(&P.d_bma, bma);
   up.add(reinterpret_cast<void**>(&P.d_g), g, n_g * sizeof(double));
+  up.add(&P.d_td, P.td);
+  up.add(&P.d_qb, P.qb);
   if (P.has_cont) {
     up.add(&P.d_kc, P.kc);
     up.add(&P.d_sc, P.sc);

@@ -486,34 +486,100 @@ __global__ void __launch_bounds__(64 * kRowWavesMax, 3) k_kernel_rows(
 constexpr int kSigColTiles = 8;
 typedef double doublex4_g __attribute__((ext_vector_type(4)));
 
+// Banded output of the kernel rows: chunk-local real row gr = [zl][th][t][c][n]
+// of heights z0 + zl goes to its 16-row tile of the store (KStore), which
+// keeps the columns of the tile's range; each value is split into an FP32
+// value and its FP32 remainder (hi + lo carries the FP64 row to 2^-48).
+struct BandOut {
+  float* hi = nullptr;
+  float* lo = nullptr;
+  const TileDesc* td = nullptr;
+  int z0 = 0, nth = 0, nt = 0, nn = 0, nq = 0, pad = 0;
+};
+
+// store index of (plane p, row n, column col) of (z, theta), or -1 outside its tile's range
+__device__ __forceinline__ long long band_at(const BandOut& B, size_t zt, int p, int n, int col) {
+  int q, lr;
+  row_tile(B.pad, 2 * B.nt, B.nn, p, n, &q, &lr);
+  const TileDesc d = B.td[zt * B.nq + q];
+  if (col < d.lo || col >= d.hi) return -1;
+  return d.off + (long long)lr * (d.hi - d.lo) + (col - d.lo);
+}
+
+__device__ __forceinline__ long long band_index(const BandOut& B, long long gr, int col) {
+  const int n = (int)(gr % B.nn);
+  long long q = gr / B.nn;
+  const int p = (int)(q % (2 * B.nt));
+  q /= 2 * B.nt;
+  const int th = (int)(q % B.nth), zl = (int)(q / B.nth);
+  return band_at(B, (size_t)(B.z0 + zl) * B.nth + th, p, n, col);
+}
+
+// The stored columns [lo, hi) of chunk-local row gr (< 2^31) and the store
+// index of its column 0.
+struct BandRow {
+  long long base;
+  int lo, hi;
+};
+__device__ __forceinline__ BandRow band_row(const BandOut& B, int gr) {
+  const int n = gr % B.nn;
+  int q = gr / B.nn;
+  const int p = q % (2 * B.nt);
+  q /= 2 * B.nt;
+  const int th = q % B.nth, zl = q / B.nth;
+  const size_t zt = (size_t)(B.z0 + zl) * B.nth + th;
+  int tq, lr;
+  row_tile(B.pad, 2 * B.nt, B.nn, p, n, &tq, &lr);
+  const TileDesc d = B.td[zt * B.nq + tq];
+  BandRow r;
+  r.lo = d.lo;
+  r.hi = d.hi;
+  r.base = d.off + (long long)lr * (r.hi - r.lo) - r.lo;
+  return r;
+}
+
+__device__ __forceinline__ void band_put(const BandOut& B, long long i, double v) {
+  const float h = (float)v;
+  B.hi[i] = h;
+  B.lo[i] = (float)(v - (double)h);
+}
+
+__global__ void k_fill_zero(float* __restrict__ a, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    a[i] = 0.0f;
+}
+
 // Rows of a mirrored transition from their mirror images (Problem::row_role):
 // M[t][c][n][m] = (c ? -1 : 1) M[src][c][nn-1-n][nn-1-m] for m < nn, zero in
-// the padding; heights [z0, z0 + zc) of the stored kernels [z][th][t][2][nn][ldm].
-// The FP64 kernels are read once; the FP32 copy (when stored) gets the same
-// values rounded, as the product writes it.
-__global__ void k_mirror_rows(int z0, int zc, int nth, int nt, int nn, int ldm, RowRoles roles,
-                              double* __restrict__ M, float* __restrict__ M32) {
-  // grid z: height in the chunk; y: (angle, transition, plane); x: the plane's mirrored rows x ldm
+// the padding, over the tile range of each mirrored row, heights [z0, z0 + zc).
+// A source entry outside its tile's range is below the band's cut and taken
+// as zero.  One wave per row.
+__global__ void __launch_bounds__(256) k_mirror_rows(int nth, int nt, int nn, RowRoles roles, BandOut B) {
+  // grid z: height in the chunk; y: (angle, transition, plane); x: rows, four per block
   const int plane = blockIdx.y;
-  const int c = plane & 1, t = (plane >> 1) % nt;
-  const int zt = blockIdx.z * nth + (plane >> 1) / nt;   // (z - z0) * nth + th
+  const int c = plane & 1, t = (plane >> 1) % nt, th = (plane >> 1) / nt;
   const int r = roles.role[t];
   if (r < 0) return;
   const int nfirst = r == t ? nn / 2 + (nn & 1) : 0;     // first mirrored row: n > nn-1-n
-  const int cnt = (nn - nfirst) * ldm;
-  const size_t base = (size_t)(z0 * (long long)nth + zt) * nt;
-  const double* src = M + ((base + r) * 2 + c) * (size_t)nn * ldm;
-  const size_t dst = ((base + t) * 2 + c) * (size_t)nn * ldm;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += gridDim.x * blockDim.x) {
-    const int n = nfirst + i / ldm, m = i - (i / ldm) * ldm;
-    double v = 0.0;
+  const int n = nfirst + blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (n >= nn) return;
+  const size_t zt = (size_t)(B.z0 + blockIdx.z) * nth + th;
+  int q, lr;
+  row_tile(B.pad, 2 * nt, nn, 2 * t + c, n, &q, &lr);
+  const TileDesc d = B.td[zt * B.nq + q];
+  const int lo = d.lo, hi = d.hi;
+  const long long dst = d.off + (long long)lr * (hi - lo) - lo;
+  for (int m = lo + (threadIdx.x & 63); m < hi; m += 64) {
+    float h = 0.0f, l = 0.0f;
     if (m < nn) {
-      v = src[(size_t)(nn - 1 - n) * ldm + (nn - 1 - m)];
-      if (c) v = -v;
+      const long long i = band_at(B, zt, 2 * r + c, nn - 1 - n, nn - 1 - m);
+      if (i >= 0) {
+        h = B.hi[i];
+        l = B.lo[i];
+      }
     }
-    const size_t o = dst + (size_t)n * ldm + m;
-    M[o] = v;
-    if (M32) M32[o] = (float)v;
+    B.hi[dst + m] = c ? -h : h;
+    B.lo[dst + m] = c ? -l : l;
   }
 }
 
@@ -522,7 +588,7 @@ __global__ void __launch_bounds__(256) k_sig_gemm(long long nrows, int nn, int l
                                                   const double* __restrict__ Lrow,
                                                   const double* __restrict__ Sig,
                                                   double* __restrict__ M64, float* __restrict__ M32,
-                                                  long long out_row0) {
+                                                  long long out_row0, BandOut bo) {
   constexpr int KC = 16;
   __shared__ double As[64][KC + 1];
   __shared__ double Bs[KC][kSigColTiles * 16 + 4];
@@ -564,6 +630,11 @@ __global__ void __launch_bounds__(256) k_sig_gemm(long long nrows, int nn, int l
       const long long gr = row0 + wave * 16 + lk + 4 * r;
       if (gr >= nrows) continue;
       const double v = (col < nn) ? acc[j][r] + Lrow[gr * ldm + col] : 0.0;
+      if (bo.hi) {
+        const long long i = band_index(bo, gr, col);
+        if (i >= 0) band_put(bo, i, v);
+        continue;
+      }
       const size_t o = (size_t)(out_row0 + gr) * ldm + col;
       if (M64) M64[o] = v;
       if (M32) M32[o] = (float)v;
@@ -583,7 +654,8 @@ __global__ void __launch_bounds__(512, 1) k_sig_gemm_lds(long long nrows, int nn
                                                          const double* __restrict__ Lrow,
                                                          const double* __restrict__ Sig,
                                                          double* __restrict__ M64, float* __restrict__ M32,
-                                                         long long out_row0, RowRoles roles, int nt) {
+                                                         long long out_row0, RowRoles roles, int nt,
+                                                         BandOut bo) {
   constexpr int KP = 8 * NH, CP = 16 * NCT, BST = CP + 4;
   extern __shared__ double sgs[];      // [KP][BST]
   for (int e = threadIdx.x; e < KP * CP; e += blockDim.x) {
@@ -653,6 +725,22 @@ __global__ void __launch_bounds__(512, 1) k_sig_gemm_lds(long long nrows, int nn
       }
     }
     // lane holds D[row lk + 4 r][column 16 j + lr]
+    if (bo.hi) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const long long gr = tile * 16 + lk + 4 * r;
+        if (gr >= nrows) continue;
+        const BandRow br = band_row(bo, (int)gr);
+#pragma unroll
+        for (int j = 0; j < NCT; ++j) {
+          const int col = j * 16 + lr;
+          if (col < br.lo || col >= br.hi) continue;
+          const double v = (col < nn) ? acc[j][r] + Lrow[gr * ldm + col] : 0.0;
+          band_put(bo, br.base + col, v);
+        }
+      }
+      continue;
+    }
 #pragma unroll
     for (int j = 0; j < NCT; ++j) {
       const int col = j * 16 + lr;
@@ -674,7 +762,8 @@ __global__ void __launch_bounds__(512, 1) k_sig_gemm_lds(long long nrows, int nn
 // `roles` (optional): mirror roles of rows laid out [..][t][c][n]; tiles made
 // only of mirrored rows are skipped (the persistent form), k_mirror_rows fills them
 int launch_sig_gemm(trap_ctx* ctx, long long rrows, const double* Gam, const double* Lrow, double* M64,
-                    float* M32, long long out_row0, const RowRoles* roles = nullptr) {
+                    float* M32, long long out_row0, const RowRoles* roles = nullptr, const BandOut* band = nullptr) {
+  const BandOut bo = band ? *band : BandOut{};
   Problem& P = ctx->pb;
   const int nn = P.nn, ldm = P.ldm;
   const int nh = ldm / 8, nct = (nn + 15) / 16;
@@ -682,7 +771,7 @@ int launch_sig_gemm(trap_ctx* ctx, long long rrows, const double* Gam, const dou
   auto fallback = [&]() -> int {
     dim3 gg(ceil_div(rrows, 64), ceil_div(ldm, kSigColTiles * 16));
     hipLaunchKernelGGL(k_sig_gemm, gg, dim3(256), 0, ctx->stream, rrows, nn, ldm, Gam, Lrow, P.d_Sig, M64, M32,
-                       out_row0);
+                       out_row0, bo);
     TRAP_HIP(hipGetLastError());
     return TRAP_OK;
   };
@@ -694,7 +783,7 @@ int launch_sig_gemm(trap_ctx* ctx, long long rrows, const double* Gam, const dou
       TRAP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
                                    (int)lds));
     hipLaunchKernelGGL(kern, dim3(grid), dim3(512), lds, ctx->stream, rrows, nn, ldm, Gam, Lrow, P.d_Sig, M64, M32,
-                       out_row0, rr, P.nt);
+                       out_row0, rr, P.nt, bo);
     TRAP_HIP(hipGetLastError());
     return TRAP_OK;
   };
@@ -873,16 +962,32 @@ __global__ void k_coef_table(int nd, int nu, int nl, double c_sc, const double* 
 
 // Angle-averaged kernels (Sect. 5.2, Eq. R_AA): M[z][0][t][c][n][m] =
 // sum_g w_g Mg[z][g][t][c][n][m] over the Theta nodes of one height chunk.
-__global__ void k_theta_average(long long per_z_out, int ng, int zc, const double* __restrict__ w,
-                                const double* __restrict__ Mg, double* __restrict__ M64, float* __restrict__ M32,
-                                long long out_offset) {
+// The angle-averaged class kernels of the preconditioner, dense [zl][t][c][n][ldm].
+__global__ void k_theta_average_dense(long long per_z_out, int ng, int zc, const double* __restrict__ w,
+                                      const double* __restrict__ Mg, double* __restrict__ M64,
+                                      long long out_offset) {
   const long long id = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   if (id >= per_z_out * zc) return;
   const long long zl = id / per_z_out, r = id % per_z_out;
   double v = 0.0;
   for (int g = 0; g < ng; ++g) v += w[g] * Mg[(zl * ng + g) * per_z_out + r];
-  if (M64) M64[out_offset + id] = v;
-  if (M32) M32[out_offset + id] = (float)v;
+  M64[out_offset + id] = v;
+}
+
+// The angle-averaged kernel of heights [z0, z0 + zc) from the rows at the
+// Gauss-Legendre angles (scratch [zl][g][t][c][n][ldm]) into the banded store
+// (one stored angle).
+__global__ void k_theta_average(long long per_z_out, int ng, int zc, int ldm, const double* __restrict__ w,
+                                const double* __restrict__ Mg, BandOut B) {
+  const long long id = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (id >= per_z_out * zc) return;
+  const long long zl = id / per_z_out, r = id % per_z_out;
+  const int col = (int)(r % ldm);
+  const long long i = band_index(B, zl * (per_z_out / ldm) + r / ldm, col);
+  if (i < 0) return;
+  double v = 0.0;
+  for (int g = 0; g < ng; ++g) v += w[g] * Mg[(zl * ng + g) * per_z_out + r];
+  band_put(B, i, v);
 }
 
 // The Faddeeva and quadrature constants: computed once per process, copied to
@@ -933,6 +1038,37 @@ static int load_constants(int device) {
   return TRAP_OK;
 }
 
+__global__ void k_faddeeva_eval(int n, const double* __restrict__ v, const double* __restrict__ a,
+                                double2* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = wz(v[i], a[i]);
+}
+
+int faddeeva_eval(int device, const double* v, const double* a, int n, double* out) {
+  TRAP_TRY(load_constants(device));
+  double *dv = nullptr, *da = nullptr;
+  double2* dout = nullptr;
+  const size_t b = (size_t)n * sizeof(double);
+  TRAP_HIP(hipMalloc(&dv, b));
+  int rc = TRAP_OK;
+  if (hipMalloc(&da, b) != hipSuccess || hipMalloc(&dout, 2 * b) != hipSuccess) {
+    rc = fail(TRAP_ENOMEM, "faddeeva scratch");
+  } else if (hipMemcpy(dv, v, b, hipMemcpyHostToDevice) != hipSuccess ||
+             hipMemcpy(da, a, b, hipMemcpyHostToDevice) != hipSuccess) {
+    rc = fail(TRAP_EDEVICE, "faddeeva upload");
+  } else {
+    hipLaunchKernelGGL(k_faddeeva_eval, dim3(ceil_div(n, 256)), dim3(256), 0, nullptr, n, dv, da, dout);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) rc = fail(TRAP_EDEVICE, std::string("k_faddeeva_eval: ") + hipGetErrorString(e));
+    else if (hipMemcpy(out, dout, 2 * b, hipMemcpyDeviceToHost) != hipSuccess)
+      rc = fail(TRAP_EDEVICE, "faddeeva download");
+  }
+  if (dout) (void)hipFree(dout);
+  if (da) (void)hipFree(da);
+  (void)hipFree(dv);
+  return rc;
+}
+
 int run_precompute(trap_ctx* ctx, int store_mask) {
   Problem& P = ctx->pb;
   Precomp& C = ctx->pre;
@@ -958,11 +1094,30 @@ int run_precompute(trap_ctx* ctx, int store_mask) {
   if (!ctx->ev_fork) TRAP_HIP(hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming));
   TRAP_HIP(hipEventRecord(ctx->ev_fork, s));
   ctx->fork_recorded = true;
-  const size_t kelems = (size_t)nz * nth * nt * 2 * nn * P.ldm;
-  const int mask = store_mask | 1;     // FP64 kernels always exist (residual, f, b)
-  if ((mask & 1) && !C.d_M64) TRAP_TRY(dalloc_t(ctx, &C.d_M64, kelems));
-  if ((mask & 2) && !C.d_M32) TRAP_TRY(dalloc_t(ctx, &C.d_M32, kelems));
+  // the banded store holds both precisions at once: FP32 values and their
+  // FP32 remainders (the FP64 kernel is their sum); store_mask bit 1 decides
+  // only whether the FP32 applies' coefficient tables are built
+  const int mask = store_mask | 1;     // FP64 applies always exist (residual, f, b)
+  if (!C.d_Mhi) {
+    const size_t ne = std::max<size_t>(P.kentries, 2);
+    TRAP_TRY(dalloc_t(ctx, &C.d_Mhi, ne));
+    TRAP_TRY(dalloc_t(ctx, &C.d_Mlo, ne));
+    // rows of a tile past the grid (padding) are never written: zero
+    const int fg = (int)std::min<long long>(4096, ceil_div((long long)ne, 256));
+    hipLaunchKernelGGL(k_fill_zero, dim3(fg), dim3(256), 0, s, C.d_Mhi, (long long)ne);
+    hipLaunchKernelGGL(k_fill_zero, dim3(fg), dim3(256), 0, s, C.d_Mlo, (long long)ne);
+    TRAP_HIP(hipGetLastError());
+  }
   C.store_mask = mask;
+  BandOut bo;
+  bo.hi = C.d_Mhi;
+  bo.lo = C.d_Mlo;
+  bo.td = P.d_td;
+  bo.nth = nth;
+  bo.nt = nt;
+  bo.nn = nn;
+  bo.nq = P.nq;
+  bo.pad = P.qpad;
   const size_t lds = (size_t)(nn + 1) * 4 * sizeof(double2);
   if (lds > 64 * 1024) return fail(TRAP_EINVAL, "frequency grid too large for the kernel precompute");
   // rows per block of k_kernel_rows: two when their moments and lane partial
@@ -1009,24 +1164,20 @@ int run_precompute(trap_ctx* ctx, int store_mask) {
       TRAP_HIP(hipGetLastError());
     }
     const long long rrows = 2 * nrows;                           // real rows (both planes)
+    bo.z0 = z0;
     if (!aa) {
-      TRAP_TRY(launch_sig_gemm(ctx, rrows, C.d_Grow, C.d_Lrow, (mask & 1) ? C.d_M64 : nullptr,
-                               (mask & 2) ? C.d_M32 : nullptr, (long long)z0 * nth * nt * 2 * nn, &roles));
+      TRAP_TRY(launch_sig_gemm(ctx, rrows, C.d_Grow, C.d_Lrow, nullptr, nullptr, 0LL, &roles, &bo));
     } else {
       // rows at the Gauss-Legendre angles into the scratch store, then their weighted sum
       TRAP_TRY(launch_sig_gemm(ctx, rrows, C.d_Grow, C.d_Lrow, C.d_Mtmp, (float*)nullptr, 0LL));
       const long long per_z_out = (long long)nt * 2 * nn * P.ldm;
       hipLaunchKernelGGL(k_theta_average, dim3(ceil_div(per_z_out * zc, 256)), dim3(256), 0, s, per_z_out, nthr,
-                         zc, P.d_theta_rw, C.d_Mtmp, (mask & 1) ? C.d_M64 : nullptr, (mask & 2) ? C.d_M32 : nullptr,
-                         (long long)z0 * per_z_out);
+                         zc, P.ldm, P.d_theta_rw, C.d_Mtmp, bo);
       TRAP_HIP(hipGetLastError());
     }
     if (roles.on) {
-      // the FP64 kernels are always stored (mask bit 0)
-      const dim3 mg((unsigned)std::min<long long>(64, ceil_div((long long)nn * P.ldm, 256)), (unsigned)(nth * nt * 2),
-                    (unsigned)zc);
-      hipLaunchKernelGGL(k_mirror_rows, mg, dim3(256), 0, s, z0, zc, nth, nt, nn, P.ldm, roles, C.d_M64,
-                         (mask & 2) ? C.d_M32 : nullptr);
+      const dim3 mg((unsigned)ceil_div(nn, 4), (unsigned)(nth * nt * 2), (unsigned)zc);
+      hipLaunchKernelGGL(k_mirror_rows, mg, dim3(256), 0, s, nth, nt, nn, roles, bo);
       TRAP_HIP(hipGetLastError());
     }
   }
@@ -1298,8 +1449,8 @@ static int precompute_precond_body(trap_ctx* ctx) {
                        lay.uniform ? Gt : nullptr, lay.uniform ? Vt : nullptr, lay.ntail, RowRoles{});
     TRAP_HIP(hipGetLastError());
     TRAP_TRY(launch_sig_gemm(ctx, 2 * nrows, Grow, Lrow, Mtmp, (float*)nullptr, 0LL));
-    hipLaunchKernelGGL(k_theta_average, dim3(ceil_div(per_z_out * zc, 256)), dim3(256), 0, s, per_z_out, ng, zc,
-                       C.d_pcRw, Mtmp, C.d_pcM, (float*)nullptr, (long long)z0 * per_z_out);
+    hipLaunchKernelGGL(k_theta_average_dense, dim3(ceil_div(per_z_out * zc, 256)), dim3(256), 0, s, per_z_out, ng,
+                       zc, C.d_pcRw, Mtmp, C.d_pcM, (long long)z0 * per_z_out);
     TRAP_HIP(hipGetLastError());
   }
   hipLaunchKernelGGL(k_r3_rows, dim3(nz * nk), dim3(64), lds_row, s, nk, nn, P.d_x, P.d_P, P.d_lam, P.d_a, C.d_pcSt,

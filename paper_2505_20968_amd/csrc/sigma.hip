@@ -151,7 +151,6 @@ template <> struct MfmaOp<double> {
   }
 };
 
-constexpr int kRowsPerBlock = 128; // 8 waves x 16 rows
 
 template <typename T> struct Vec4;
 template <> struct Vec4<float> { typedef float4 type; };
@@ -160,27 +159,72 @@ template <typename T> struct T2of;
 template <> struct T2of<float> { typedef float2 type; };
 template <> struct T2of<double> { typedef double2 type; };
 
-// Block: 8 waves = 128 rows (16 per wave) x one column group (up to 4 NCT
-// slots of one Theta, 16 NCT columns).  K is taken in chunks of 8 NH: each
-// lane loads its kernel-row fragment straight into registers with two-element
-// vector loads, using the permuted K order k = k0 + 2 (4 h + lk) + jj for step
-// (h, jj) of the matrix-core chain; the column group's comoving field for the
-// chunk is staged once in LDS and read with the same k.  With one chunk
-// (padded N_nu <= 128) a block synchronises once before its products.
+// Block: 8 waves, each one 16-row wave tile of the banded store (the block's
+// eight tiles in block order, KStore), x one column group (up to 4 NCT slots of
+// one Theta, 16 NCT columns).  K runs over the block's column range [klo, khi)
+// (the union of its rows' bands) in chunks of 8 NH: each lane loads its
+// kernel-row fragment straight into registers with two-element vector loads,
+// using the permuted K order k = k0 + 2 (4 h + lk) + jj for step (h, jj) of
+// the matrix-core chain, zero outside its row's band; the column group's
+// comoving field for the chunk is staged once in LDS and read with the same k.
+// A wave issues only the steps that meet its own tile's column range.
 // LDS row strides are padded so that the four k rows read by one matrix-core
 // step (rows 2 apart) fall in different bank groups.
 template <typename T> struct ContractCfg;
 template <> struct ContractCfg<float> { static constexpr int BST = 136; };   // 128 columns + pad
 template <> struct ContractCfg<double> { static constexpr int BST = 72; };   // 64 columns + pad
 
-// The products of one K chunk: for step (h, jj) every column tile jt takes
-// its B value from LDS (row 8 h + jj of the lane's k group) and the lane's
-// kernel-row fragment.  The B values of step h + 1 are read into registers
-// before the products of step h are issued, so LDS latency overlaps the
-// matrix cores.
+// Two consecutive kernel-row entries at index i of the store: the FP32 values,
+// or (FP64) the sums of values and remainders.
+template <typename T> struct KLoad;
+template <> struct KLoad<float> {
+  __device__ static inline float2 at(const KStore& ks, long long i) {
+    return *reinterpret_cast<const float2*>(ks.hi + i);
+  }
+};
+template <> struct KLoad<double> {
+  __device__ static inline double2 at(const KStore& ks, long long i) {
+    const float2 h = *reinterpret_cast<const float2*>(ks.hi + i);
+    const float2 l = *reinterpret_cast<const float2*>(ks.lo + i);
+    return make_double2((double)h.x + (double)l.x, (double)h.y + (double)l.y);
+  }
+};
+
+// The row a lane multiplies in wave tile q of (z, theta): plane p = 2 t + c,
+// frequency n and whether it is a grid row; the wave's stored column range
+// [wlo, whi) (wave-uniform) and the store index of the lane's column 0 in
+// the tile (`base`, so column k in range is at base + k).
+struct KRow {
+  long long base;
+  int p, n, wlo, whi;
+  bool live;
+};
+
+__device__ __forceinline__ KRow krow(const KStore& ks, long long zt, int q, int lr, int nt, int nn) {
+  KRow r;
+  q = __builtin_amdgcn_readfirstlane(q);
+  const bool qv = q < ks.nq;
+  const int grow = tile_row0(ks.pad, ks.np, ks.nnp, q) + lr;
+  r.p = grow / ks.nnp;
+  r.n = grow - r.p * ks.nnp;
+  r.live = qv && r.p < 2 * nt && r.n < nn;
+  TileDesc d{0, 0, 0};
+  if (qv) d = ks.td[zt * ks.nq + q];
+  r.wlo = __builtin_amdgcn_readfirstlane(d.lo);
+  r.whi = __builtin_amdgcn_readfirstlane(d.hi);
+  r.base = d.off + (long long)lr * (r.whi - r.wlo) - r.wlo;
+  return r;
+}
+
+// The products of one K chunk starting at column k0: for step (h, jj) every
+// column tile jt takes its B value from LDS (row 8 h + jj of the lane's k
+// group) and the lane's kernel-row fragment.  The B values of step h + 1 are
+// read into registers before the products of step h are issued, so LDS
+// latency overlaps the matrix cores.  Steps outside [hlo, hhi) (wave-uniform)
+// are skipped.
 template <typename T, int NH, int NCT>
 __device__ __forceinline__ void mfma_chunk(const T* bcol, int bst, const typename T2of<T>::type (&mf)[NH],
-                                           typename MfmaOp<T>::acc_t (&acc)[NCT]) {
+                                           typename MfmaOp<T>::acc_t (&acc)[NCT], int hlo, int hhi) {
   using Op = MfmaOp<T>;
   T bc[2][NCT], bx[2][NCT];
 #pragma unroll
@@ -198,11 +242,13 @@ __device__ __forceinline__ void mfma_chunk(const T* bcol, int bst, const typenam
     // keep the reads of step h + 1 ahead of the products of step h (the
     // scheduler would otherwise sink each read next to its use)
     __builtin_amdgcn_sched_barrier(0);
+    if (h >= hlo && h < hhi) {
 #pragma unroll
-    for (int jj = 0; jj < 2; ++jj) {
-      const T bf = jj ? mf[h].y : mf[h].x;
+      for (int jj = 0; jj < 2; ++jj) {
+        const T bf = jj ? mf[h].y : mf[h].x;
 #pragma unroll
-      for (int jt = 0; jt < NCT; ++jt) acc[jt] = Op::run(bc[jj][jt], bf, acc[jt]);
+        for (int jt = 0; jt < NCT; ++jt) acc[jt] = Op::run(bc[jj][jt], bf, acc[jt]);
+      }
     }
     __builtin_amdgcn_sched_barrier(0);
     if (h + 1 < NH) {
@@ -214,9 +260,35 @@ __device__ __forceinline__ void mfma_chunk(const T* bcol, int bst, const typenam
   }
 }
 
+// step range of a wave whose columns are [wlo, whi) in the chunk at k0
+template <int NH>
+__device__ __forceinline__ void wave_steps(int wlo, int whi, int k0, int* hlo, int* hhi) {
+  const int a = max(0, (wlo - k0) >> 3), b = min(NH, (whi - k0 + 7) >> 3);
+  *hlo = __builtin_amdgcn_readfirstlane(a);
+  *hhi = __builtin_amdgcn_readfirstlane(b);
+}
+
+// lane holds C[row][slot s0 + 4 jt + lk][Stokes]: W[zl][t][slot][c][n][s]
+template <typename T, int NCT>
+__device__ __forceinline__ void store_w(const KRow& r, int zl, int nt, int nn, int nslot, int s0, int cnt, int lk,
+                                        const typename MfmaOp<T>::acc_t (&acc)[NCT], T* __restrict__ W) {
+  using V4 = typename Vec4<T>::type;
+  if (!r.live) return;
+  const int rt = r.p >> 1, rc = r.p & 1;
+#pragma unroll
+  for (int jt = 0; jt < NCT; ++jt) {
+    const int sl = 4 * jt + lk;
+    if (sl < cnt) {
+      V4 o;
+      o.x = acc[jt][0]; o.y = acc[jt][1]; o.z = acc[jt][2]; o.w = acc[jt][3];
+      *reinterpret_cast<V4*>(W + (((((size_t)zl * nt + rt) * nslot + s0 + sl) * 2 + rc) * nn + r.n) * 4) = o;
+    }
+  }
+}
+
 template <typename T, int NH, int NCT>
-__device__ __forceinline__ void contract_block(int rb, int g, int zl, int z0, int nth, int nt, int nn, int ldm, int nd,
-                                               int nkc, const T* __restrict__ M, const T* __restrict__ Ibar,
+__device__ __forceinline__ void contract_block(int rb, int g, int zl, int z0, int nth, int nt, int nn, int nd,
+                                               const KStore& ks, const T* __restrict__ Ibar,
                                                const int* __restrict__ cgrp, const int* __restrict__ slot_dir,
                                                T* __restrict__ W, int nslot, T* Bs) {
   using Op = MfmaOp<T>;
@@ -227,27 +299,28 @@ __device__ __forceinline__ void contract_block(int rb, int g, int zl, int z0, in
   constexpr int BST = ContractCfg<T>::BST;
   constexpr int CG = 4 * NCT;                       // slots per column group
   const int th = cgrp[3 * g], s0 = cgrp[3 * g + 1], cnt = cgrp[3 * g + 2];
-  const int z = z0 + zl;
-  const int R = 2 * nt * nn;
-  const int row0 = rb * kRowsPerBlock;
-  const T* Mb = M + ((size_t)z * nth + th) * (size_t)R * ldm;
+  const long long zt = (long long)(z0 + zl) * nth + th;
+  const unsigned bw = ks.qb[zt * ks.nqb + rb];
+  const int klo = (int)(bw & 0xffffu), khi = (int)(bw >> 16);
+  const int nkc = max(1, (khi - klo + KCH - 1) / KCH);
   const T* Ib = Ibar + (size_t)zl * nd * nn * 4;
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int tid = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   const int lr = lane & 15, lk = lane >> 4;
-  const int grow = row0 + wave * 16 + lr;
-  const T* arow = Mb + (size_t)min(grow, R - 1) * ldm;
+  const KRow r = krow(ks, zt, rb * 8 + wave, lr, nt, nn);
   acc_t acc[NCT];
 #pragma unroll
   for (int j = 0; j < NCT; ++j)
-    for (int r = 0; r < 4; ++r) acc[j][r] = T(0);
+    for (int q = 0; q < 4; ++q) acc[j][q] = T(0);
   for (int kc = 0; kc < nkc; ++kc) {
-    const int k0 = kc * KCH;
+    const int k0 = klo + kc * KCH;
+    int hlo, hhi;
+    wave_steps<NH>(r.wlo, r.whi, k0, &hlo, &hhi);
     T2 mf[NH];
+    const long long i0 = r.base + k0 + 2 * lk;
 #pragma unroll
     for (int h = 0; h < NH; ++h) {
-      const int k = k0 + 2 * (4 * h + lk);
-      if (grow < R && k < ldm) {
-        mf[h] = *reinterpret_cast<const T2*>(arow + k);
+      if (h >= hlo && h < hhi) {       // wave-uniform: the wave tile's stored columns
+        mf[h] = KLoad<T>::at(ks, i0 + 8 * h);
       } else {
         mf[h].x = T(0);
         mf[h].y = T(0);
@@ -274,21 +347,9 @@ __device__ __forceinline__ void contract_block(int rb, int g, int zl, int z0, in
       }
     }
     __syncthreads();
-    mfma_chunk<T, NH, NCT>(Bs + 2 * lk * BST + lr, BST, mf, acc);
+    mfma_chunk<T, NH, NCT>(Bs + 2 * lk * BST + lr, BST, mf, acc, hlo, hhi);
   }
-  // lane holds C[grow][slot s0 + 4 jt + lk][Stokes r]
-  if (grow < R) {
-    const int rt = grow / (2 * nn), rc = (grow / nn) & 1, rn = grow % nn;
-#pragma unroll
-    for (int jt = 0; jt < NCT; ++jt) {
-      const int sl = 4 * jt + lk;
-      if (sl < cnt) {
-        V4 o;
-        o.x = acc[jt][0]; o.y = acc[jt][1]; o.z = acc[jt][2]; o.w = acc[jt][3];
-        *reinterpret_cast<V4*>(W + (((((size_t)zl * nt + rt) * nslot + s0 + sl) * 2 + rc) * nn + rn) * 4) = o;
-      }
-    }
-  }
+  store_w<T, NCT>(r, zl, nt, nn, nslot, s0, cnt, lk, acc, W);
 }
 
 
@@ -297,9 +358,8 @@ __device__ __forceinline__ void contract_block(int rb, int g, int zl, int z0, in
 // groups come first in the dispatch order (the group index is the slowest grid
 // dimension).
 template <typename T, int NH>
-__global__ void __launch_bounds__(512, 2) k_contract(int z0, int nth, int nt, int nn, int ldm, int nd, int nkc,
-                                                     const T* __restrict__ M, const T* __restrict__ Ibar,
-                                                     const int* __restrict__ cgrp, int n8,
+__global__ void __launch_bounds__(512, 2) k_contract(int z0, int nth, int nt, int nn, int nd, KStore ks,
+                                                     const T* __restrict__ Ibar, const int* __restrict__ cgrp, int n8,
                                                      const int* __restrict__ slot_dir, T* __restrict__ W,
                                                      int nslot) {
   extern __shared__ __align__(16) unsigned char csh[];
@@ -307,12 +367,11 @@ __global__ void __launch_bounds__(512, 2) k_contract(int z0, int nth, int nt, in
   const int g = blockIdx.z, zl = blockIdx.y;
   if constexpr (sizeof(T) == sizeof(float)) {
     if (g < n8) {
-      contract_block<T, NH, 8>(blockIdx.x, g, zl, z0, nth, nt, nn, ldm, nd, nkc, M, Ibar, cgrp, slot_dir, W, nslot,
-                               Bs);
+      contract_block<T, NH, 8>(blockIdx.x, g, zl, z0, nth, nt, nn, nd, ks, Ibar, cgrp, slot_dir, W, nslot, Bs);
       return;
     }
   }
-  contract_block<T, NH, 4>(blockIdx.x, g, zl, z0, nth, nt, nn, ldm, nd, nkc, M, Ibar, cgrp, slot_dir, W, nslot, Bs);
+  contract_block<T, NH, 4>(blockIdx.x, g, zl, z0, nth, nt, nn, nd, ks, Ibar, cgrp, slot_dir, W, nslot, Bs);
 }
 
 // chunking of K: the fewest chunks of at most 128 columns, NH = chunk / 8
@@ -323,62 +382,66 @@ static void contract_chunks(int ldm, int* nkc, int* nh) {
 
 // ---- persistent, software-pipelined FP32 contraction
 // The same products as k_contract, with one block per compute unit looping
-// over the tiles (row block, height, column group) x K chunks.  While the
-// matrix cores work on stage s (kernel-row fragments in registers, comoving
-// tile in LDS buffer s % 2), the block already has the loads of stage s + 1 in
-// flight: its kernel-row fragments into a second register set and its
-// comoving tile into registers, written to the other LDS buffer once the
-// products are issued.  One barrier per stage.  The slot -> direction table is
-// copied to LDS at the start so the comoving gather has no dependent global
-// load.  Groups with up to 32 slots (8 column tiles) are processed first, then
-// those with up to 16.
+// over the tiles (block of wave tiles, height, column group), each in as many
+// K chunks as its column range needs.  While the matrix cores work on one
+// stage (kernel-row fragments in registers, comoving tile in LDS buffer b),
+// the block already has the loads of the next stage in flight: its kernel-row
+// fragments into a second register set and its comoving tile into registers,
+// written to the other LDS buffer once the products are issued.  One barrier
+// per stage.  The slot -> direction table is copied to LDS at the start so
+// the comoving gather has no dependent global load.  Groups with up to 32
+// slots (8 column tiles) are processed first, then those with up to 16.
 template <int NH, int NCT>
 __device__ __forceinline__ void contract_pipe_class(
-    int first, int count, int step, int gbase, int zc, int z0, int nth, int nt, int nn, int ldm, int nd, int nkc,
-    int rb_n, const float* __restrict__ M, const float* __restrict__ Ibar, const int* __restrict__ cgrp,
-    const int* sdir, float* __restrict__ W, int nslot, float* Bs0, float* Bs1) {
+    int first, int count, int step, int gbase, int zc, int z0, int nth, int nt, int nn, int nd, const KStore& ks,
+    const float* __restrict__ Ibar, const int* __restrict__ cgrp, const int* sdir, float* __restrict__ W, int nslot,
+    float* Bs0, float* Bs1) {
   using acc_t = floatx4_t;
   constexpr int KCH = 8 * NH;
   constexpr int BST = ContractCfg<float>::BST;
   constexpr int CG = 4 * NCT;
   constexpr int NB = (KCH * CG + 511) / 512;
-  const int ntile = count > first ? (count - first + step - 1) / step : 0;
-  const int nst = ntile * nkc;
-  if (nst == 0) return;
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  if (first >= count) {
+    return;
+  }
+  const int tid = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   const int lr = lane & 15, lk = lane >> 4;
-  const int R = 2 * nt * nn;
+  const int rb_n = ks.nqb;
   const int per_g = zc * rb_n;
   struct St {
-    int rb, zl, g, kc;
+    int t, kc, nkc, klo, g, zl;
+    long long zt;
   };
-  auto decode = [&](int s) {
-    St d;
-    const int t = first + (s / nkc) * step;
-    d.kc = s % nkc;
+  auto decode = [&](int t, St& d) {
+    d.t = t;
+    d.kc = 0;
     d.g = gbase + t / per_g;
     const int r = t % per_g;
     d.zl = r / rb_n;
-    d.rb = r % rb_n;
-    return d;
+    const int rb = r % rb_n;
+    d.zt = (long long)(z0 + d.zl) * nth + cgrp[3 * d.g];
+    const unsigned bw = ks.qb[d.zt * ks.nqb + rb];
+    d.klo = (int)(bw & 0xffffu);
+    d.nkc = max(1, ((int)(bw >> 16) - d.klo + KCH - 1) / KCH);
+    return rb;
   };
-  // Loads read a valid clamped address and keep the raw values; the masks
-  // (zero past the last k, zero past the last slot or frequency of the tile)
-  // are applied when the values are consumed, after the products of the
-  // current stage are issued, so no load of the next stage is waited for early.
-  // Rows past the end need no mask: their outputs are not stored.
-  unsigned amask = 0;
-  auto load_a = [&](const St& d, float2 (&dst)[NH]) {
-    const int th = cgrp[3 * d.g];
-    const int grow = d.rb * kRowsPerBlock + wave * 16 + lr;
-    const float* arow = M + (((size_t)(z0 + d.zl) * nth + th) * (size_t)R + min(grow, R - 1)) * ldm;
-    const int k0 = d.kc * KCH;
-    amask = 0;
+  // Loads read a valid address and keep the raw values; the masks (zero
+  // outside the wave tile's column range, past the last slot or frequency of
+  // the tile) are applied when the values are consumed, after the products of
+  // the current stage are issued, so no load of the next stage is waited for
+  // early.
+  // the steps of a stage that meet the wave tile's stored columns (uniform)
+  auto load_a = [&](const St& d, const KRow& r, float2 (&dst)[NH], int* hlo, int* hhi) {
+    const int k0 = d.klo + d.kc * KCH;
+    wave_steps<NH>(r.wlo, r.whi, k0, hlo, hhi);
+    const float* ptr = ks.hi + (r.base + k0 + 2 * lk);
 #pragma unroll
     for (int h = 0; h < NH; ++h) {
-      const int k = k0 + 2 * (4 * h + lk);
-      dst[h] = *reinterpret_cast<const float2*>(arow + min(k, ldm - 2));
-      amask |= (k < ldm ? 1u : 0u) << h;
+      if (h >= *hlo && h < *hhi) {
+        dst[h] = *reinterpret_cast<const float2*>(ptr + 8 * h);
+      } else {
+        dst[h] = make_float2(0.0f, 0.0f);
+      }
     }
   };
   float4 bn[NB];
@@ -386,7 +449,7 @@ __device__ __forceinline__ void contract_pipe_class(
   auto load_b = [&](const St& d) {
     const int s0 = cgrp[3 * d.g + 1], cnt = cgrp[3 * d.g + 2];
     const float* Ib = Ibar + (size_t)d.zl * nd * nn * 4;
-    const int k0 = d.kc * KCH;
+    const int k0 = d.klo + d.kc * KCH;
     int dir[NB];
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
@@ -416,65 +479,62 @@ __device__ __forceinline__ void contract_pipe_class(
   };
   auto take_a = [&](float2 (&dst)[NH], const float2 (&src)[NH]) {
 #pragma unroll
-    for (int h = 0; h < NH; ++h) {
-      const bool ok = (amask >> h) & 1u;
-      dst[h].x = ok ? src[h].x : 0.0f;
-      dst[h].y = ok ? src[h].y : 0.0f;
-    }
+    for (int h = 0; h < NH; ++h) dst[h] = src[h];
   };
   float2 mf[NH], mfn[NH];
   acc_t acc[NCT];
 #pragma unroll
   for (int j = 0; j < NCT; ++j)
-    for (int r = 0; r < 4; ++r) acc[j][r] = 0.0f;
-  {
-    const St d0 = decode(0);
-    load_a(d0, mfn);
-    load_b(d0);
-    store_b(Bs0);
-    take_a(mf, mfn);
-  }
+    for (int q = 0; q < 4; ++q) acc[j][q] = 0.0f;
+  St cur;
+  int rb = decode(first, cur);
+  KRow rc = krow(ks, cur.zt, rb * 8 + wave, lr, nt, nn);
+  int hlo, hhi, hlo_n = 0, hhi_n = 0;
+  load_a(cur, rc, mfn, &hlo, &hhi);
+  load_b(cur);
+  store_b(Bs0);
+  take_a(mf, mfn);
   __syncthreads();
-  for (int s = 0; s < nst; ++s) {
-    const St d = decode(s);
-    const bool more = s + 1 < nst;
-    if (more) {
-      const St dn = decode(s + 1);
-      load_a(dn, mfn);
-      load_b(dn);
+  int buf = 0;
+  while (true) {
+    St nx = cur;
+    KRow rn = rc;
+    bool more = true;
+    if (cur.kc + 1 < cur.nkc) {
+      nx.kc = cur.kc + 1;
+    } else if (cur.t + step < count) {
+      const int rbn = decode(cur.t + step, nx);
+      rn = krow(ks, nx.zt, rbn * 8 + wave, lr, nt, nn);
+    } else {
+      more = false;
     }
-    mfma_chunk<float, NH, NCT>(((s & 1) ? Bs1 : Bs0) + 2 * lk * BST + lr, BST, mf, acc);
-    if (d.kc == nkc - 1) {
-      // lane holds C[grow][slot s0 + 4 jt + lk][Stokes r]
-      const int s0 = cgrp[3 * d.g + 1], cnt = cgrp[3 * d.g + 2];
-      const int grow = d.rb * kRowsPerBlock + wave * 16 + lr;
-      if (grow < R) {
-        const int rt = grow / (2 * nn), rc = (grow / nn) & 1, rn = grow % nn;
-#pragma unroll
-        for (int jt = 0; jt < NCT; ++jt) {
-          const int sl = 4 * jt + lk;
-          if (sl < cnt) {
-            float4 o;
-            o.x = acc[jt][0]; o.y = acc[jt][1]; o.z = acc[jt][2]; o.w = acc[jt][3];
-            *reinterpret_cast<float4*>(W + (((((size_t)d.zl * nt + rt) * nslot + s0 + sl) * 2 + rc) * nn + rn) * 4) = o;
-          }
-        }
-      }
+    if (more) {
+      load_a(nx, rn, mfn, &hlo_n, &hhi_n);
+      load_b(nx);
+    }
+    mfma_chunk<float, NH, NCT>((buf ? Bs1 : Bs0) + 2 * lk * BST + lr, BST, mf, acc, hlo, hhi);
+    if (cur.kc == cur.nkc - 1) {
+      store_w<float, NCT>(rc, cur.zl, nt, nn, nslot, cgrp[3 * cur.g + 1], cgrp[3 * cur.g + 2], lk, acc, W);
 #pragma unroll
       for (int j = 0; j < NCT; ++j)
-        for (int r = 0; r < 4; ++r) acc[j][r] = 0.0f;
+        for (int q = 0; q < 4; ++q) acc[j][q] = 0.0f;
     }
-    if (more) {
-      store_b((s & 1) ? Bs0 : Bs1);
-      take_a(mf, mfn);
-    }
+    if (!more) break;
+    store_b(buf ? Bs0 : Bs1);
+    take_a(mf, mfn);
     __syncthreads();
+    buf ^= 1;
+    cur = nx;
+    rc = rn;
+    hlo = hlo_n;
+    hhi = hhi_n;
   }
+  // the next class starts by writing LDS buffer 0: every wave is done reading
+  __syncthreads();
 }
 
 template <int NH>
-__global__ void __launch_bounds__(512, 1) k_contract_pipe(int z0, int zc, int nth, int nt, int nn, int ldm, int nd,
-                                                          int nkc, int rb_n, const float* __restrict__ M,
+__global__ void __launch_bounds__(512, 1) k_contract_pipe(int z0, int zc, int nth, int nt, int nn, int nd, KStore ks,
                                                           const float* __restrict__ Ibar,
                                                           const int* __restrict__ cgrp, int ngrp, int n8,
                                                           const int* __restrict__ slot_dir, float* __restrict__ W,
@@ -486,11 +546,11 @@ __global__ void __launch_bounds__(512, 1) k_contract_pipe(int z0, int zc, int nt
   int* sdir = reinterpret_cast<int*>(Bs1 + KCH * ContractCfg<float>::BST);
   for (int i = threadIdx.x; i < nslot; i += blockDim.x) sdir[i] = slot_dir[i];
   __syncthreads();
-  const int per_g = zc * rb_n;
-  contract_pipe_class<NH, 8>(blockIdx.x, n8 * per_g, gridDim.x, 0, zc, z0, nth, nt, nn, ldm, nd, nkc, rb_n, M,
-                             Ibar, cgrp, sdir, W, nslot, Bs0, Bs1);
-  contract_pipe_class<NH, 4>(blockIdx.x, (ngrp - n8) * per_g, gridDim.x, n8, zc, z0, nth, nt, nn, ldm, nd, nkc,
-                             rb_n, M, Ibar, cgrp, sdir, W, nslot, Bs0, Bs1);
+  const int per_g = zc * ks.nqb;
+  contract_pipe_class<NH, 8>(blockIdx.x, n8 * per_g, gridDim.x, 0, zc, z0, nth, nt, nn, nd, ks, Ibar, cgrp, sdir, W,
+                             nslot, Bs0, Bs1);
+  contract_pipe_class<NH, 4>(blockIdx.x, (ngrp - n8) * per_g, gridDim.x, n8, zc, z0, nth, nt, nn, nd, ks, Ibar, cgrp,
+                             sdir, W, nslot, Bs0, Bs1);
 }
 
 static size_t contract_pipe_lds(int nh, int nslot) {
@@ -498,36 +558,35 @@ static size_t contract_pipe_lds(int nh, int nslot) {
 }
 
 template <int NH>
-static int launch_contract_pipe_nh(trap_ctx* ctx, hipStream_t stream, int zc, int z0, const float* Mk,
-                                   const float* Ibar, float* W, size_t lds, int nkc) {
+static int launch_contract_pipe_nh(trap_ctx* ctx, hipStream_t stream, int zc, int z0, const KStore& ks,
+                                   const float* Ibar, float* W, size_t lds) {
   Problem& P = ctx->pb;
   const int ngrp = (int)P.cgrp[1].size() / 3;
-  const int rb_n = ceil_div(2LL * P.nt * P.nn, kRowsPerBlock);
-  const long long ntiles = (long long)ngrp * zc * rb_n;
+  const long long ntiles = (long long)ngrp * zc * ks.nqb;
   const int grid = (int)std::min<long long>(ntiles, ctx->n_cu);
   auto kern = k_contract_pipe<NH>;
   if (lds > 64 * 1024)
     TRAP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
                                  (int)lds));
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(512), lds, stream, z0, zc, P.nth, P.nt, P.nn, P.ldm, P.nd, nkc,
-                     rb_n, Mk, Ibar, P.d_cgrp[1], ngrp, P.cgrp_n8[1], P.d_slot_dir, W, P.nslot);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(512), lds, stream, z0, zc, P.nth, P.nt, P.nn, P.nd, ks, Ibar,
+                     P.d_cgrp[1], ngrp, P.cgrp_n8[1], P.d_slot_dir, W, P.nslot);
   TRAP_HIP(hipGetLastError());
   return TRAP_OK;
 }
 
 // 1 when launched, 0 when the problem does not fit the pipelined kernel's LDS
-static int launch_contract_pipe(trap_ctx* ctx, hipStream_t stream, int zc, int z0, const float* Mk,
-                                const float* Ibar, float* W) {
+static int launch_contract_pipe(trap_ctx* ctx, hipStream_t stream, int zc, int z0, const float* Ibar, float* W) {
   Problem& P = ctx->pb;
   if ((int)P.cgrp[1].size() / 3 == 0) return 1;
   int nkc, nh;
   contract_chunks(P.ldm, &nkc, &nh);
   const size_t lds = contract_pipe_lds(nh, P.nslot);
   if (lds > (size_t)ctx->max_lds) return 0;
+  const KStore ks = kernel_store(ctx);
   switch (nh) {
 #define TRAP_PIPE_CASE(NHV) \
   case NHV:                 \
-    TRAP_TRY(launch_contract_pipe_nh<NHV>(ctx, stream, zc, z0, Mk, Ibar, W, lds, nkc)); \
+    TRAP_TRY(launch_contract_pipe_nh<NHV>(ctx, stream, zc, z0, ks, Ibar, W, lds)); \
     return 1;
     TRAP_PIPE_CASE(1) TRAP_PIPE_CASE(2) TRAP_PIPE_CASE(3) TRAP_PIPE_CASE(4)
     TRAP_PIPE_CASE(5) TRAP_PIPE_CASE(6) TRAP_PIPE_CASE(7) TRAP_PIPE_CASE(8)
@@ -540,7 +599,7 @@ static int launch_contract_pipe(trap_ctx* ctx, hipStream_t stream, int zc, int z
 }
 
 template <typename T>
-static int launch_contract(trap_ctx* ctx, int zc, int z0, const T* Mk, const T* Ibar, T* W) {
+static int launch_contract(trap_ctx* ctx, int zc, int z0, const T* Ibar, T* W) {
   Problem& P = ctx->pb;
   const int pi = sizeof(T) == 8 ? 0 : 1;
   const int ngrp = (int)P.cgrp[pi].size() / 3;
@@ -548,13 +607,14 @@ static int launch_contract(trap_ctx* ctx, int zc, int z0, const T* Mk, const T* 
   int nkc, nh;
   contract_chunks(P.ldm, &nkc, &nh);
   const size_t lds = (size_t)8 * nh * ContractCfg<T>::BST * sizeof(T);
-  dim3 grid(ceil_div(2LL * P.nt * P.nn, kRowsPerBlock), zc, ngrp);
+  const KStore ks = kernel_store(ctx);
+  dim3 grid(ks.nqb, zc, ngrp);
   const int n8 = P.cgrp_n8[pi];
   switch (nh) {
 #define TRAP_CONTRACT_CASE(NHV)                                                                               \
   case NHV:                                                                                                   \
-    hipLaunchKernelGGL((k_contract<T, NHV>), grid, dim3(512), lds, ctx->stream, z0, P.nth, P.nt, P.nn, P.ldm,  \
-                       P.nd, nkc, Mk, Ibar, P.d_cgrp[pi], n8, P.d_slot_dir, W, P.nslot);                     \
+    hipLaunchKernelGGL((k_contract<T, NHV>), grid, dim3(512), lds, ctx->stream, z0, P.nth, P.nt, P.nn, P.nd, ks, \
+                       Ibar, P.d_cgrp[pi], n8, P.d_slot_dir, W, P.nslot);                                     \
     break;
     TRAP_CONTRACT_CASE(1) TRAP_CONTRACT_CASE(2) TRAP_CONTRACT_CASE(3) TRAP_CONTRACT_CASE(4)
     TRAP_CONTRACT_CASE(5) TRAP_CONTRACT_CASE(6) TRAP_CONTRACT_CASE(7) TRAP_CONTRACT_CASE(8)
@@ -789,7 +849,7 @@ __host__ __device__ inline FusedLayout fused_layout(int ldm, int nd, int nu, int
 template <typename T, int TPW, int NH>
 __global__ void __launch_bounds__(512, TPW == 1 ? 3 : 2) k_fused(
     int nn, int ldm, int nd, int nth, int nt, int nu, int nl, int ntile, int nblk,
-    const T* __restrict__ M, const T* __restrict__ Ibar, const int* __restrict__ grp, int ngrp,
+    const KStore ks, const T* __restrict__ Ibar, const int* __restrict__ grp, int ngrp,
     const int* __restrict__ slot_dir, const int* __restrict__ pair_off, const int* __restrict__ pair_o,
     const T* __restrict__ cf, double c_sc, const double2* __restrict__ E, const double2* __restrict__ bma,
     const double2* __restrict__ X, const double2* __restrict__ prof, T* __restrict__ Eb) {
@@ -917,12 +977,21 @@ __global__ void __launch_bounds__(512, TPW == 1 ? 3 : 2) k_fused(
 #pragma unroll
     for (int q = 0; q < TPW; ++q) {
       const int t = uq[q] * nl + l;
-      const T* row = M + ((((size_t)z * nth + th) * nt + t) * 2 + cq[q]) * (size_t)nn * ldm +
-                     (size_t)min(n, nn - 1) * ldm;
+      const long long zt = (long long)z * nth + th;
+      int tq = 0, tr = 0, lo = 0, hi = 0;
+      long long base = 0;
+      if (n < nn) {
+        row_tile(ks.pad, ks.np, nn, 2 * t + cq[q], n, &tq, &tr);
+        const TileDesc d = ks.td[zt * ks.nq + tq];
+        lo = d.lo;
+        hi = d.hi;
+        base = d.off + (long long)tr * (hi - lo) - lo;
+      }
 #pragma unroll
       for (int h = 0; h < NH; ++h) {
-        if (n < nn) {
-          dst[q][h] = *reinterpret_cast<const T2*>(row + 2 * (4 * h + lk));
+        const int k = 2 * (4 * h + lk);
+        if (k >= lo && k < hi) {
+          dst[q][h] = KLoad<T>::at(ks, base + k);
         } else {
           dst[q][h].x = T(0);
           dst[q][h].y = T(0);
@@ -1039,7 +1108,7 @@ static size_t fused_lds(const trap_ctx* ctx, int prec) {
 }
 
 template <typename T, int TPW, int NH>
-static int launch_fused_t(trap_ctx* ctx, size_t lds, int nw, const T* Mk, const T* Ibar, const T* cf, T* Eb) {
+static int launch_fused_t(trap_ctx* ctx, size_t lds, int nw, const T* Ibar, const T* cf, T* Eb) {
   Problem& P = ctx->pb;
   const int pi = sizeof(T) == 8 ? 0 : 1;
   const int ntile = ceil_div(P.nn, 16);
@@ -1049,17 +1118,17 @@ static int launch_fused_t(trap_ctx* ctx, size_t lds, int nw, const T* Mk, const 
     TRAP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
                                  (int)lds));
   hipLaunchKernelGGL(kern, dim3(nblk), dim3(64 * nw), lds, ctx->stream, P.nn, P.ldm, P.nd, P.nth, P.nt, P.nu,
-                     P.nl, ntile, nblk, Mk, Ibar, P.d_grp[pi], (int)P.grp[pi].size() / 3, P.d_slot_dir,
+                     P.nl, ntile, nblk, kernel_store(ctx), Ibar, P.d_grp[pi], (int)P.grp[pi].size() / 3, P.d_slot_dir,
                      P.d_pair_off, P.d_pair_o, cf, P.c_sc, P.d_E, P.d_bma, ctx->wk.X, ctx->pre.d_prof, Eb);
   TRAP_HIP(hipGetLastError());
   return TRAP_OK;
 }
 
 template <typename T, int TPW>
-static int launch_fused_nh(trap_ctx* ctx, size_t lds, int nw, const T* Mk, const T* Ibar, const T* cf, T* Eb) {
+static int launch_fused_nh(trap_ctx* ctx, size_t lds, int nw, const T* Ibar, const T* cf, T* Eb) {
   switch (ctx->pb.ldm / 8) {
 #define TRAP_FUSED_CASE(NHV) \
-  case NHV: return launch_fused_t<T, TPW, NHV>(ctx, lds, nw, Mk, Ibar, cf, Eb);
+  case NHV: return launch_fused_t<T, TPW, NHV>(ctx, lds, nw, Ibar, cf, Eb);
     TRAP_FUSED_CASE(1) TRAP_FUSED_CASE(2) TRAP_FUSED_CASE(3) TRAP_FUSED_CASE(4)
     TRAP_FUSED_CASE(5) TRAP_FUSED_CASE(6) TRAP_FUSED_CASE(7) TRAP_FUSED_CASE(8)
     TRAP_FUSED_CASE(9) TRAP_FUSED_CASE(10) TRAP_FUSED_CASE(11) TRAP_FUSED_CASE(12)
@@ -1070,14 +1139,41 @@ static int launch_fused_nh(trap_ctx* ctx, size_t lds, int nw, const T* Mk, const
 }
 
 template <typename T>
-static int launch_fused(trap_ctx* ctx, size_t lds, const T* Mk, const T* Ibar, const T* cf, T* Eb) {
+static int launch_fused(trap_ctx* ctx, size_t lds, const T* Ibar, const T* cf, T* Eb) {
   const int nu = ctx->pb.nu;
-  if (2 * nu <= 8) return launch_fused_nh<T, 1>(ctx, lds, 2 * nu, Mk, Ibar, cf, Eb);
-  return launch_fused_nh<T, 2>(ctx, lds, nu, Mk, Ibar, cf, Eb);
+  if (2 * nu <= 8) return launch_fused_nh<T, 1>(ctx, lds, 2 * nu, Ibar, cf, Eb);
+  return launch_fused_nh<T, 2>(ctx, lds, nu, Ibar, cf, Eb);
 }
 
 // ------------------------------------------------------------------ driver
 static size_t elem_size(int prec) { return prec == TRAP_FP64 ? sizeof(double) : sizeof(float); }
+
+// stored real kernel entries of heights [z0, z0 + zc) and their contraction flops
+double chunk_entries(const Problem& P, int z0, int zc) {
+  const size_t a = (size_t)z0 * P.nth, b = (size_t)(z0 + zc) * P.nth;
+  const long long e1 = b < P.kbase.size() ? P.kbase[b] : (long long)P.kentries;
+  return (double)(e1 - P.kbase[a]);
+}
+double chunk_flops(const Problem& P, int z0, int zc) {
+  double f = 0.0;
+  for (int z = z0; z < z0 + zc; ++z) f += P.kflops_z[z];
+  return f;
+}
+
+KStore kernel_store(const trap_ctx* ctx) {
+  const Problem& P = ctx->pb;
+  KStore k;
+  k.hi = ctx->pre.d_Mhi;
+  k.lo = ctx->pre.d_Mlo;
+  k.td = P.d_td;
+  k.qb = P.d_qb;
+  k.np = 2 * P.nt;
+  k.nnp = P.nnp;
+  k.nq = P.nq;
+  k.nqb = P.nqb;
+  k.pad = P.qpad;
+  return k;
+}
 
 int ensure_work(trap_ctx* ctx, int prec) {
   Problem& P = ctx->pb;
@@ -1111,8 +1207,7 @@ int ensure_work(trap_ctx* ctx, int prec) {
 }
 
 template <typename T>
-static int sigma_apply_t(trap_ctx* ctx, const T* I, T* eps, int prec, int add_thermal, int normalize,
-                         const T* Mk) {
+static int sigma_apply_t(trap_ctx* ctx, const T* I, T* eps, int prec, int add_thermal, int normalize) {
   Problem& P = ctx->pb;
   Precomp& C = ctx->pre;
   Work& K = ctx->wk;
@@ -1151,14 +1246,14 @@ static int sigma_apply_t(trap_ctx* ctx, const T* I, T* eps, int prec, int add_th
     prof_end(ctx, pr);
     // 3. fused R_II contraction, angular/sublevel sum and R_III into eps_bar
     {
-      const double kel = (double)nz * nth * nt * 2.0 * nn * P.ldm;
-      const double flops = 16.0 * nz * nt * (double)nn * nn * P.nslot;
-      const double bytes = sizeof(T) * (kel + (double)nz * nd * nn * 4 + (double)nz * nd * nd * nt * 2 * nl * 16 +
+      const double kel = chunk_entries(P, 0, nz) * (sizeof(T) / sizeof(float));
+      const double flops = chunk_flops(P, 0, nz);
+      const double bytes = sizeof(float) * kel + sizeof(T) * ((double)nz * nd * nn * 4 + (double)nz * nd * nd * nt * 2 * nl * 16 +
                                         (double)nz * ncls * nd * nn * 4);
       pr = prof_begin(ctx, sizeof(T) == 8 ? TRAP_STAGE_CONTRACT_FP64 : TRAP_STAGE_CONTRACT, flops, bytes);
     }
     if constexpr (sizeof(T) == sizeof(float)) {
-      TRAP_TRY(launch_fused<T>(ctx, flds, Mk, Ibar, cf, Eb));
+      TRAP_TRY(launch_fused<T>(ctx, flds, Ibar, cf, Eb));
     }
     prof_end(ctx, pr);
   }
@@ -1186,9 +1281,13 @@ static int sigma_apply_t(trap_ctx* ctx, const T* I, T* eps, int prec, int add_th
     int pr;
     // 2. contraction
     {
-      const double kel = (double)zc * nth * nt * 2.0 * nn * P.ldm;
-      const double flops = 16.0 * zc * nt * (double)nn * nn * P.nslot;
-      const double bytes = sizeof(T) * (kel + (double)zc * nt * P.nslot * 2.0 * nn * 4 + (double)zc * nd * nn * 4);
+      // algorithmic work of the chunk: 16 flops per stored complex kernel entry
+      // and incoming slot of its angle; bytes: the stored rows (FP32 values,
+      // plus the remainders in FP64), W written and the comoving field read
+      const double kel = chunk_entries(P, z0, zc) * (sizeof(T) / sizeof(float));
+      const double flops = chunk_flops(P, z0, zc);
+      const double bytes = sizeof(float) * kel + sizeof(T) * ((double)zc * nt * P.nslot * 2.0 * nn * 4 +
+                                                               (double)zc * nd * nn * 4);
       pr = prof_begin(ctx, sizeof(T) == 8 ? TRAP_STAGE_CONTRACT_FP64 : TRAP_STAGE_CONTRACT, flops, bytes);
     }
     if (!W) {
@@ -1196,11 +1295,11 @@ static int sigma_apply_t(trap_ctx* ctx, const T* I, T* eps, int prec, int add_th
       W = static_cast<T*>(K.W[pi]);
     }
     if constexpr (sizeof(T) == sizeof(float)) {
-      const int launched = launch_contract_pipe(ctx, ctx->stream, zc, z0, Mk, Ibar + (size_t)z0 * nd * nn * 4, W);
+      const int launched = launch_contract_pipe(ctx, ctx->stream, zc, z0, Ibar + (size_t)z0 * nd * nn * 4, W);
       if (launched < 0) return launched;
-      if (!launched) TRAP_TRY(launch_contract<T>(ctx, zc, z0, Mk, Ibar + (size_t)z0 * nd * nn * 4, W));
+      if (!launched) TRAP_TRY(launch_contract<T>(ctx, zc, z0, Ibar + (size_t)z0 * nd * nn * 4, W));
     } else {
-      TRAP_TRY(launch_contract<T>(ctx, zc, z0, Mk, Ibar + (size_t)z0 * nd * nn * 4, W));
+      TRAP_TRY(launch_contract<T>(ctx, zc, z0, Ibar + (size_t)z0 * nd * nn * 4, W));
     }
     prof_end(ctx, pr);
     // 4. angular / sublevel sum into Eb (chunk-local heights)
@@ -1338,13 +1437,13 @@ int sigma_apply_line(trap_ctx* ctx, const void* I, void* eps, int prec, int add_
   if (!I || !eps) return fail(TRAP_EINVAL, "null vector");
   TRAP_TRY(ensure_work(ctx, prec));
   if (prec == TRAP_FP64) {
-    if (!ctx->pre.d_M64) return fail(TRAP_ESTATE, "FP64 kernels not stored");
+    if (!ctx->pre.d_Mhi || !ctx->pre.d_cf64) return fail(TRAP_ESTATE, "FP64 kernels not stored");
     return sigma_apply_t<double>(ctx, static_cast<const double*>(I), static_cast<double*>(eps), prec,
-                                 add_thermal, normalize, ctx->pre.d_M64);
+                                 add_thermal, normalize);
   }
-  if (!ctx->pre.d_M32) return fail(TRAP_ESTATE, "FP32 kernels not stored (store_mask bit 1)");
+  if (!ctx->pre.d_Mhi || !ctx->pre.d_cf32) return fail(TRAP_ESTATE, "FP32 kernels not stored (store_mask bit 1)");
   return sigma_apply_t<float>(ctx, static_cast<const float*>(I), static_cast<float*>(eps), prec,
-                              add_thermal, normalize, ctx->pre.d_M32);
+                              add_thermal, normalize);
 }
 
 }  // namespace trap
@@ -1399,14 +1498,14 @@ __global__ void __launch_bounds__(512, 2) k_contract_grouped(const GContract* __
   const int r = find_req(blockIdx.x, off, n);
   const GContract& a = A[r];
   const int local = blockIdx.x - off[r];
-  const int rb = local % a.rb_n, rest = local / a.rb_n;
+  const int rb = local % a.ks.nqb, rest = local / a.ks.nqb;
   const int zl = rest % a.zc, g = rest / a.zc;     // column group slowest, as in k_contract
   if (g < a.n8)
-    contract_block<float, NH, 8>(rb, g, zl, a.z0, a.nth, a.nt, a.nn, a.ldm, a.nd, a.nkc, a.M, a.Ibar, a.cgrp,
-                                 a.slot_dir, a.W, a.nslot, Bs);
+    contract_block<float, NH, 8>(rb, g, zl, a.z0, a.nth, a.nt, a.nn, a.nd, a.ks, a.Ibar, a.cgrp, a.slot_dir, a.W,
+                                 a.nslot, Bs);
   else
-    contract_block<float, NH, 4>(rb, g, zl, a.z0, a.nth, a.nt, a.nn, a.ldm, a.nd, a.nkc, a.M, a.Ibar, a.cgrp,
-                                 a.slot_dir, a.W, a.nslot, Bs);
+    contract_block<float, NH, 4>(rb, g, zl, a.z0, a.nth, a.nt, a.nn, a.nd, a.ks, a.Ibar, a.cgrp, a.slot_dir, a.W,
+                                 a.nslot, Bs);
 }
 
 template <int NLM>
@@ -1589,7 +1688,7 @@ int stage_upload_batch(trap_ctx* ctx, const UploadBatch& up, void* dev) {
 int sigma_batch_ready(trap_ctx* ctx) {
   Problem& P = ctx->pb;
   Work& K = ctx->wk;
-  if (!ctx->has_problem || !ctx->pre.done || !ctx->pre.d_M32 || !ctx->pre.d_cf32) return 0;
+  if (!ctx->has_problem || !ctx->pre.done || !ctx->pre.d_Mhi || !ctx->pre.d_cf32) return 0;
   if (ctx->path == TRAP_PATH_FUSED || ctx->prof.on) return 0;
   // the shared launches carry no continuum term
   if (P.has_cont) return 0;
@@ -1676,7 +1775,7 @@ int op_apply_batch_f32(trap_ctx** ctxs, int n, const double* const* x, double* c
       // its own: it keeps the persistent pipelined contraction (launched here,
       // on the batch stream); smaller ones share one launch
       const int zc = std::min(ctxs[i]->wk.zchunk, P.nz - ch * ctxs[i]->wk.zchunk);
-      const long long tiles = (long long)ceil_div(2LL * P.nt * P.nn, kRowsPerBlock) * zc * ((int)P.cgrp[1].size() / 3);
+      const long long tiles = (long long)P.nqb * zc * ((int)P.cgrp[1].size() / 3);
       int nkc, nh;
       contract_chunks(P.ldm, &nkc, &nh);
       if (tiles >= 2LL * ctxs[i]->n_cu && contract_pipe_lds(nh, P.nslot) <= (size_t)ctxs[i]->max_lds) {
@@ -1691,12 +1790,9 @@ int op_apply_batch_f32(trap_ctx** ctxs, int n, const double* const* x, double* c
       for (int i : kv.second) {
         const Problem& P = ctxs[i]->pb;
         const int z0 = ch * ctxs[i]->wk.zchunk, zc = std::min(ctxs[i]->wk.zchunk, P.nz - z0);
-        int nkc, nh;
-        contract_chunks(P.ldm, &nkc, &nh);
-        const int rb_n = ceil_div(2LL * P.nt * P.nn, kRowsPerBlock);
+        const int rb_n = P.nqb;
         const int ngrp = (int)P.cgrp[1].size() / 3;
-        a.push_back(GContract{z0, P.nth, P.nt, P.nn, P.ldm, P.nd, nkc, P.cgrp_n8[1], P.nslot, rb_n, zc,
-                              ctxs[i]->pre.d_M32,
+        a.push_back(GContract{z0, P.nth, P.nt, P.nn, P.nd, P.cgrp_n8[1], P.nslot, zc, kernel_store(ctxs[i]),
                               static_cast<const float*>(ctxs[i]->wk.Ibar[1]) + (size_t)z0 * P.nd * P.nn * 4,
                               P.d_cgrp[1], P.d_slot_dir, static_cast<float*>(ctxs[i]->wk.W[1])});
         cnt.push_back(rb_n * zc * ngrp);
@@ -1936,7 +2032,7 @@ int op_apply_batch_f32(trap_ctx** ctxs, int n, const double* const* x, double* c
         const int z0 = (int)st.args * c->wk.zchunk, zc = std::min(c->wk.zchunk, P.nz - z0);
         const float* Ib = static_cast<const float*>(c->wk.Ibar[1]) + (size_t)z0 * P.nd * P.nn * 4;
         float* Wc = static_cast<float*>(c->wk.W[1]);
-        const int launched = launch_contract_pipe(c, ar.stream, zc, z0, c->pre.d_M32, Ib, Wc);
+        const int launched = launch_contract_pipe(c, ar.stream, zc, z0, Ib, Wc);
         if (launched < 0) return launched;
         if (!launched) return fail(TRAP_EINVAL, "internal: contraction does not fit the pipelined kernel");
         break;

@@ -247,7 +247,7 @@ int gmres_begin(trap_ctx* ctx, const trap_solve_opts* opts, double* I) {
     return fail(TRAP_EINVAL, "BESSER makes Lambda nonlinear: solve with trap_aar_solve");
   const int inner = opts->inner;
   if (inner != TRAP_FP64 && inner != TRAP_FP32) return fail(TRAP_EINVAL, "bad inner precision");
-  if (inner == TRAP_FP32 && !ctx->pre.d_M32) return fail(TRAP_ESTATE, "FP32 kernels not stored");
+  if (inner == TRAP_FP32 && !ctx->pre.d_cf32) return fail(TRAP_ESTATE, "FP32 kernels not stored");
   if (opts->precond_sweeps < 0 || opts->precond_sweeps > 64)
     return fail(TRAP_EINVAL, "preconditioner sweeps must be in [0, 64]");
   if (opts->precond_sweeps > 0 && !ctx->pre.pc_done)

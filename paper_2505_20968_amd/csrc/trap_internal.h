@@ -46,12 +46,55 @@ struct DevBuf {
   bool pooled = false;     // from the device's stream-ordered pool (freed with hipFreeAsync)
 };
 
+// ---------------------------------------------------------------- banded kernel store
+// Each R_II kernel row is nonzero only where the Gaussian factor of F reaches
+// (Sect. 2.3, App. C) plus the reach of the cardinal spline basis (its band).
+// The contraction multiplies 16-row wave tiles; the store keeps, per tile,
+// the 16 rows over the union of their bands (columns lo .. hi - 1, multiples
+// of 8) as one dense [16][hi - lo] block.  The GEMM rows of (z, theta) are
+// np = 2 nt planes (transition t, real/imaginary c, p = 2 t + c) of nnp rows:
+// nnp = nn, or nn padded to 16 when that wastes less work than tiles that
+// straddle two planes.  Tiles are numbered in `block order` (tile_row0: first
+// row of each), eight per block of the contraction; td holds each tile's
+// store offset and column range, qb each block's range as lo | hi << 16.
+struct TileDesc {
+  long long off;    // store index of the tile's row 0, column lo
+  int lo, hi;       // column range, multiples of 8
+};
+struct KStore {
+  const float* hi = nullptr;          // FP32 kernel values
+  const float* lo = nullptr;          // FP32 remainders: hi + lo is the FP64 kernel
+  const TileDesc* td = nullptr;       // [nz][nth][nq]
+  const unsigned* qb = nullptr;       // [nz][nth][nqb]
+  int np = 0, nnp = 0, nq = 0, nqb = 0;
+  int pad = 0;
+};
+
+// first GEMM row of wave tile q (block order)
+__host__ __device__ inline int tile_row0(int pad, int np, int nnp, int q) {
+  return pad ? (q % np) * nnp + 16 * (q / np) : 16 * q;
+}
+
+// wave tile and row within it of GEMM row (plane p, frequency n)
+__host__ __device__ inline void row_tile(int pad, int np, int nn, int p, int n, int* q, int* lr) {
+  if (pad) {
+    *q = (n >> 4) * np + p;
+    *lr = n & 15;
+  } else {
+    const int r = p * nn + n;
+    *q = r >> 4;
+    *lr = r & 15;
+  }
+}
+
 // ---------------------------------------------------------------- context
 // Index conventions (all row-major, last index fastest):
 //   vectors        V[z][o][n][s]
 //   spline map     P[k][p][m]      interval k (0..nn-2), power p of t=(x-x_k)/h_k, node m
-//   kernels        M[z][theta][t][c][n][m]   c = 0 real / 1 imaginary, row n, column m
-//                  (row stride ldm >= nn, zero padded)
+//   kernels        banded, in 16-row tiles (KStore): row (z, theta, plane p = 2 t + c, n),
+//                  c = 0 real / 1 imaginary, in tile q at row lr, columns [lo_q, hi_q)
+//                  at base[z][theta] + tofs[z][theta][q] + lr (hi_q - lo_q); FP32 hi and
+//                  lo words (hi = the FP32 kernel, hi + lo the FP64 one)
 //   W intermediate W[zc][t][slot][c][n][s]   (height chunk zc)
 //   eps_bar        Eb[z][l][l'][o][n][s]
 //   coefficients   cf[z][p][t][c][l'][i][j]  p = pair index in slot-major order; c = 0 multiplies
@@ -72,7 +115,22 @@ struct Problem {
   std::vector<double> los_mu;              // [nlos] mu of each zero-weight ring
   int nth = 0, nslot = 0, nu = 0, nl = 0, nt = 0;
   int max_slots_per_theta = 0;
-  int ldm = 0;                             // padded row length of the stored kernels (multiple of 8)
+  int ldm = 0;                             // row length of the precompute's dense row scratch (multiple of 8)
+  // banded kernel store (see KStore): spline reach in nodes, the layout of
+  // the tiles, the stored real entries, the complex entries inside the rows'
+  // own bands, and the algorithmic flops of one contraction per height
+  // (16 per in-band complex entry and incoming slot of its angle)
+  int band_reach = 0;
+  int nnp = 0, nq = 0, nqb = 0, qpad = 0;
+  std::vector<long long> kbase;
+  std::vector<int> tofs, qrow0;
+  std::vector<unsigned> qk, qb;
+  size_t kentries = 0;
+  double band_nnz = 0.0;
+  std::vector<double> kflops_z;
+  std::vector<TileDesc> td;
+  TileDesc* d_td = nullptr;
+  unsigned* d_qb = nullptr;
   double c_abs = 0, c_sc = 0;
   // host copies used by host-side logic
   std::vector<double> x, mu, w, tau, lam, a, eps, WT, eta0, dnuD;
@@ -142,8 +200,8 @@ struct Precomp {
   double *d_K = nullptr;      // [z][o][n][8]: kQ,kU,kV,rQ,rU,rV (over eta_I), 1/eta_I, eta_I/eta_0
   double *d_epsth = nullptr;  // [z][o][n][4]
   double *d_f = nullptr;      // [z][o][n]
-  double *d_M64 = nullptr;    // kernels FP64
-  float *d_M32 = nullptr;     // kernels FP32
+  float *d_Mhi = nullptr;     // banded kernels: FP32 values (the FP32 kernel)
+  float *d_Mlo = nullptr;     //   and the FP32 remainders (hi + lo = the FP64 kernel)
   double2 *d_r3 = nullptr;    // [z][t][n] R_III incoming weights
   double2 *d_prof = nullptr;  // [z][t][n] outgoing profiles on the comoving grid
   double *d_b = nullptr;      // right-hand side, FP64 vector
@@ -308,6 +366,16 @@ __device__ inline double spline_at(const double* __restrict__ x, int nn, const d
 
 // host setup (host_setup.cpp)
 int build_problem(trap_ctx* ctx, const trap_atom_desc* atom, const trap_problem_desc* pd);
+// the banded layout of the kernel store for the loaded grids (fills the band
+// fields of P from P.x, P.lam, P.theta / P.theta_rows, P.nt, P.ldm, the slot
+// counts and the spline's second-derivative map sig [nn][nn])
+void kernel_bands(Problem& P, const std::vector<double>& sig);
+// the store's device view of a context (after trap_set_problem and the precompute)
+KStore kernel_store(const trap_ctx* ctx);
+// stored real kernel entries of heights [z0, z0 + zc) and their algorithmic
+// contraction flops (sigma.hip)
+double chunk_entries(const Problem& P, int z0, int zc);
+double chunk_flops(const Problem& P, int z0, int zc);
 size_t estimate_bytes(const trap_atom_desc* atom, const trap_problem_desc* pd, int store_mask,
                       int* err);
 
@@ -323,6 +391,8 @@ struct PrecompLayout {
 PrecompLayout precomp_layout(int nz, int nn, int ldm, int nt, int nthr, bool aa, const double* x,
                              const double* lam);
 int run_precompute(trap_ctx* ctx, int store_mask);
+// the device Faddeeva function at n host points (precompute.hip)
+int faddeeva_eval(int device, const double* v, const double* a, int n, double* out);
 
 // applies (sigma.hip, formal.hip)
 // (normalize != 0: the App. E factor on the line part and, with a continuum,
@@ -370,8 +440,8 @@ struct GR3X {
   double2* X;
 };
 struct GContract {
-  int z0, nth, nt, nn, ldm, nd, nkc, n8, nslot, rb_n, zc;
-  const float* M;
+  int z0, nth, nt, nn, nd, n8, nslot, zc;
+  KStore ks;
   const float* Ibar;
   const int* cgrp;
   const int* slot_dir;

@@ -30,7 +30,8 @@ EXPORTED = ["trap_create", "trap_destroy", "trap_set_problem", "trap_precompute"
             "trap_profile", "trap_stage_times", "trap_set_path", "trap_set_prd_mode", "trap_gmres_begin",
             "trap_gmres_step_batch", "trap_gmres_end", "trap_precompute_preconditioner",
             "trap_apply_preconditioner", "trap_apply_preconditioner_noalloc", "trap_preconditioner_tables", "trap_set_formal_scheme",
-            "trap_formal_from_field", "trap_emergent_los", "trap_aar_solve", "trap_last_error"]
+            "trap_formal_from_field", "trap_emergent_los", "trap_aar_solve", "trap_kernel_rows",
+            "trap_faddeeva", "trap_last_error"]
 STAGES = ["comoving", "contract_fp32", "r3", "angular", "backinterp", "formal", "kernel_rows",
           "contract_fp64"]
 
@@ -59,7 +60,8 @@ class Info(ctypes.Structure):
                 ("bytes_kernel_fp64", ctypes.c_size_t), ("bytes_kernel_fp32", ctypes.c_size_t),
                 ("bytes_device_total", ctypes.c_size_t), ("flops_contraction", ctypes.c_double),
                 ("bytes_contraction_fp64", ctypes.c_double), ("bytes_contraction_fp32", ctypes.c_double),
-                ("kernel_rows_mirrored", ctypes.c_longlong)]
+                ("kernel_rows_mirrored", ctypes.c_longlong), ("kernel_entries", ctypes.c_longlong),
+                ("band_reach", ctypes.c_int)]
 
 
 class SolveOpts(ctypes.Structure):
@@ -128,6 +130,8 @@ def load_library(path: str = LIB_PATH):
     lib.trap_formal_from_field.argtypes = [vp, vp, ctypes.c_int, vp]
     lib.trap_aar_solve.argtypes = [vp, ctypes.POINTER(AarOpts), vp, ctypes.POINTER(SolveStats)]
     lib.trap_emergent_los.argtypes = [vp, vp, _dp]
+    lib.trap_kernel_rows.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp, _dp, _dp]
+    lib.trap_faddeeva.argtypes = [ctypes.c_int, _dp, _dp, ctypes.c_int, _dp]
     lib.trap_last_error.restype = ctypes.c_char_p
     for name in EXPORTED:
         if name != "trap_last_error":
@@ -180,6 +184,17 @@ def footprint(prob, store_mask: int = 3) -> int:
     _check(lib.trap_footprint(ctypes.byref(_atom_desc(prob.atom)), ctypes.byref(d), store_mask,
                               ctypes.byref(out)))
     return int(out.value)
+
+
+def faddeeva(v, a, device: int = 0) -> np.ndarray:
+    """The library's device Faddeeva function W(a, v) = w(v + i a) at the points (v, a)."""
+    lib = load_library()
+    v = np.ascontiguousarray(np.broadcast_arrays(np.asarray(v, float), np.asarray(a, float))[0], dtype=float)
+    a = np.ascontiguousarray(np.broadcast_to(np.asarray(a, float), v.shape), dtype=float)
+    out = np.zeros(v.shape + (2,))
+    _check(lib.trap_faddeeva(int(device), v.ravel().ctypes.data_as(_dp), a.ravel().ctypes.data_as(_dp),
+                             int(v.size), out.ctypes.data_as(_dp)))
+    return out[..., 0] + 1j * out[..., 1]
 
 
 def gmres_step_batch(contexts) -> list:
@@ -383,6 +398,17 @@ class Context:
         out["flops_contraction"] = {"fp32": st.flops_contraction[0], "fp64": st.flops_contraction[1]}
         out["bytes_contraction"] = {"fp32": st.bytes_contraction[0], "fp64": st.bytes_contraction[1]}
         return out
+
+    def kernel_rows(self, z: int, theta: int, t: int):
+        """FP64 kernel M[z][theta][t] as a dense complex [n_nu][n_nu] array, with
+        its scattering angle and the transition's reduced shift."""
+        nn = self.shape[2]
+        out = np.zeros((2, nn, nn))
+        th = ctypes.c_double()
+        sh = ctypes.c_double()
+        _check(self.lib.trap_kernel_rows(self.h, int(z), int(theta), int(t), ctypes.byref(th), ctypes.byref(sh),
+                                         out.ctypes.data_as(_dp)))
+        return out[0] + 1j * out[1], th.value, sh.value
 
     def info(self) -> dict:
         i = Info()
