@@ -1,20 +1,27 @@
 #!/usr/bin/env python3
-"""Benchmark of the GPU hot path: full Stokes solves of the two-level,
-chromosphere-like PRD problem (N_z = 70, N_nu = 101 on [-12, 12] Doppler
-widths, 4+4 Gauss-Legendre mu x 8 azimuths, seeded atmosphere, tolerance 1e-8).
+"""Benchmark of the GPU hot path: full Stokes solves of the polarised PRD
+transfer problem on seeded chromosphere-like columns, by default the largest
+configuration that fits one GPU: the two-term Ly-alpha-like line (N_z = 100,
+N_nu = 301 on a sinh grid to +-1000 Doppler widths, 8+8 Gauss-Legendre mu x
+8 azimuths, angle-dependent PRD; N = 15.4 M unknowns), tolerance 1e-8.
+--config cfg2 / cfg3 selects the two-level column or the Mg II-like doublet.
 
 One step = one whole pass of the method on a fresh seeded atmosphere:
-per-height setup, device precompute (R_II kernels by product integration,
-R_III weights, propagation matrix, normalisation, right-hand side), the
-tables of the physics-based preconditioner (Sect. 5.3, App. F) and the
-left-preconditioned GMRES solve to tolerance (mixed precision: FP32 inner
-operator, FP64 Arnoldi, residual and iterative refinement; or plain FP64 with
---precision fp64; --precond-sweeps 0 solves without the preconditioner).
+per-height setup, device precompute (R_II kernels by product integration into
+the banded store, R_III weights, propagation matrix, normalisation,
+right-hand side), the tables of the physics-based preconditioner (Sect. 5.3,
+App. F) and the left-preconditioned GMRES solve to tolerance (mixed
+precision: FP32 inner operator, FP64 Arnoldi, residual and iterative
+refinement; or plain FP64 with --precision fp64; --precond-sweeps 0 solves
+without the preconditioner).
 
-Prints one JSON line.  `value` is solves/s; `roofline` covers the dominant
-kernel (the FP32 R_II contraction), timed with HIP events on the library's
-stream over the timed region; `cpu_baseline` times the FP64 oracle on a
-bounded sample of the same workload.
+Prints one JSON line.  `value` is solves/s; `roofline` covers the emissivity
+apply's dominant kernel (the FP32 R_II contraction), timed with HIP events on
+the library's stream over the timed region, with its algorithmic flops (16
+per in-band kernel entry and incoming slot); `sigma_apply` the whole FP32
+Sigma apply against the same flops; `accuracy` the timed solve's emergent
+profiles against a tight FP64 solve of the same atmosphere; `cpu_baseline`
+times the FP64 oracle on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -30,7 +37,27 @@ PEAK = {"fp32": 157.3, "fp64": 78.6}     # dense TFLOP/s, MI355X published figur
 HBM_PEAK = 8000.0                        # GB/s
 COPY_PROBE_BYTES = 256 << 20
 ROOT = os.path.dirname(os.path.abspath(__file__))
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_contract_f32_cfg2_traffic.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_contract_f32_{}_traffic.txt")
+
+
+def _gen(name):
+    def make(seed):
+        import workloads
+        return getattr(workloads, name)(seed)
+    return make
+
+
+# workload generator, description, default timed steps
+CONFIGS = {
+    "cfg2": (_gen("cfg2"), "two-level J0->1 PRD-AD chromosphere-like column: N_z=70, N_nu=101 on [-12,12], "
+                           "4+4 GL mu x 8 chi, seeded B/v/a/eps, tol 1e-8", 5),
+    "cfg3": (_gen("cfg3"), "two-term 2S1/2 -> 2P1/2,3/2 Mg II h&k-like doublet (fine structure 20 Doppler "
+                           "widths, J-state interference), PRD-AD: N_z=80, N_nu=200 to +-50, 6+6 GL mu x 8 chi, "
+                           "seeded chromosphere-like column, tol 1e-8", 3),
+    "cfg4": (_gen("cfg4"), "two-term H I Ly-alpha-like line (fine structure 0.3 Doppler width, a 1e-2..1e-1, "
+                           "|B| 1-300 G), PRD-AD: N_z=100, N_nu=301 on a sinh grid to +-1000 Doppler widths, "
+                           "8+8 GL mu x 8 chi, seeded chromosphere-like column, tol 1e-8", 3),
+}
 
 
 def _pct(v, q):
@@ -43,15 +70,16 @@ def _pct(v, q):
     return s[lo] + (s[hi] - s[lo]) * (k - lo)
 
 
-def measured_traffic():
+def measured_traffic(config):
     """HBM bytes per launch of the FP32 contraction from the committed counter
-    summary, or None when the contraction's source changed since the counters
-    were taken."""
+    summary of this workload, or None when the contraction's source changed
+    since the counters were taken."""
     from paper_2505_20968_amd.profile_summary import contraction_source_hash
-    if not os.path.exists(TRAFFIC_FILE):
+    path = TRAFFIC_FILE.format(config)
+    if not os.path.exists(path):
         return None
     rec = {}
-    with open(TRAFFIC_FILE) as f:
+    with open(path) as f:
         for line in f:
             if ":" in line:
                 k, v = line.split(":", 1)
@@ -64,47 +92,91 @@ def measured_traffic():
         return None
 
 
-def cpu_baseline(n_applies: float, seed: int, budget_heights: int = 1):
-    """Time the FP64 oracle on a bounded sample of the workload and scale it to
-    one full solve: setup + kernels and one Sigma per sampled height (scaled by
-    N_z, Sigma being height-local) + the full Lambda, times the apply count
-    the GPU solve needed."""
+def _subcolumn(prob, zs):
+    """The same atmosphere restricted to the heights zs (bottom to top)."""
+    import numpy as np
+    import dataclasses
+    zs = np.asarray(zs)
+    kw = {}
+    for f in ("tau_line", "T", "xi", "a", "eps", "W_T", "v", "B"):
+        kw[f] = np.asarray(getattr(prob, f))[zs]
+    for f in ("kappa_c", "sigma_c"):
+        v = getattr(prob, f, None)
+        kw[f] = None if v is None else np.asarray(v)[zs]
+    return dataclasses.replace(prob, **kw)
+
+
+def _oracle_sample(prob, n_applies: float, threads: int, heights: int = 4, kernels_per_height: int = 2):
+    """Seconds of one oracle solve of `prob`, estimated from a bounded sample of
+    the oracle's own work at the workload's full frequency and angle grids:
+    its per-height set-up and formal solution on `heights` heights of the
+    column (scaled by N_z / heights; both are height-local), its kernel
+    matrices (kernels_per_height per sampled height, at angles spread over the
+    Theta table; scaled by N_z N_Theta N_t, the kernels the apply builds), and
+    the kernel-times-field products of the Sigma apply (scaled by their count
+    N_z n_up n_lo N_dir^2).  The apply's angular and sublevel sums and its
+    interpolations are not timed, so the estimate is a lower bound on the
+    oracle's time."""
     from threadpoolctl import threadpool_limits
     import numpy as np
-    from workloads import cfg2
     from oracle import transfer as T
-    with threadpool_limits(limits=1):
-        prob = cfg2(seed)
+    from oracle.redistribution import kernel_matrix
+    nz = prob.n_z
+    zs = np.unique(np.linspace(0, nz - 1, heights).round().astype(int))
+    sub = _subcolumn(prob, zs)
+    rng = np.random.default_rng(0)
+    with threadpool_limits(limits=threads):
         t0 = time.perf_counter()
-        op = T.setup(prob, {"normalize": False})
-        t_setup = time.perf_counter() - t0
-        rng = np.random.default_rng(0)
-        I = rng.random((prob.n_z, prob.n_dir, prob.n_nu, 4))
-        zs = list(range(0, prob.n_z, max(1, prob.n_z // budget_heights)))[:budget_heights]
-        t_first = t_second = 0.0
-        for z in zs:
-            t0 = time.perf_counter()
-            T.sigma_height(op, z, I[z], normalize=False)      # builds this height's kernels
-            t_first += time.perf_counter() - t0
-            t0 = time.perf_counter()
-            T.sigma_height(op, z, I[z], normalize=False)
-            t_second += time.perf_counter() - t0
+        op = T.setup(sub, {"normalize": False})
+        t_setup = (time.perf_counter() - t0) * nz / len(zs)
+        I = rng.random((sub.n_z, sub.n_dir, sub.n_nu, 4))
         t0 = time.perf_counter()
         T.formal_solve(op, I)
-        t_formal = time.perf_counter() - t0
-    k = len(zs)
-    t_kernels = (t_first - t_second) / k * prob.n_z
-    t_sigma = t_second / k * prob.n_z
-    # +1 Sigma for the normalisation factor, +1 Lambda for the right-hand side
-    t_solve = t_setup + t_kernels + (n_applies + 1) * t_sigma + (n_applies + 1) * t_formal
-    return {"value": 1.0 / t_solve, "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": (f"oracle on seed {seed}: setup, R_II/R_III kernels and one Sigma apply "
-                       f"at {k} of {prob.n_z} heights (scaled by N_z; Sigma is height-local), "
-                       f"one full Lambda; scaled to {n_applies:.1f} operator applies per solve "
-                       f"(the oracle's unpreconditioned GMRES; apply count of an unpreconditioned "
-                       f"GPU solve of the same atmosphere); single BLAS thread"),
-            "seconds_measured": t_setup + t_first + t_second + t_formal,
-            "seconds_per_solve_est": t_solve}
+        t_formal = (time.perf_counter() - t0) * nz / len(zs)
+        nth = len(op.theta)
+        th_pick = [k for k in np.linspace(1, nth - 1, kernels_per_height).round().astype(int)]
+        nU, nL = op.atoms[0].E_u.size, op.atoms[0].E_l.size
+        t0 = time.perf_counter()
+        nk = 0
+        for zi in range(len(zs)):
+            for j, th in enumerate(th_pick):
+                u, l = (zi + j) % nU, (zi * 3 + j) % nL
+                kernel_matrix(op.theta[th], op.s_ul[zi, u, l], sub.a[zi], op.lam[zi], op.basis)
+                nk += 1
+        t_kernels = (time.perf_counter() - t0) / nk * nz * nth * nU * nL
+        M = rng.random((sub.n_nu, sub.n_nu)) + 1j * rng.random((sub.n_nu, sub.n_nu))
+        Ib = rng.random((sub.n_nu, 4))
+        reps = 256
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            M @ Ib
+        t_prod = (time.perf_counter() - t0) / reps * nz * nU * nL * prob.n_dir ** 2
+    # one Sigma for the normalisation factor and one Lambda for the right-hand side
+    t_solve = t_setup + t_kernels + (n_applies + 1) * (t_prod + t_formal)
+    return t_solve, {"setup_s": t_setup, "kernels_s": t_kernels, "apply_products_s": t_prod,
+                     "formal_s": t_formal, "kernels_sampled": nk, "heights_sampled": int(len(zs))}
+
+
+def cpu_baseline(prob, n_applies: float):
+    """The oracle on the host's cores (all of this process's affinity set, BLAS
+    threads pinned to it) and on one core, from the bounded sample of
+    _oracle_sample; solves/s of the full workload, scaled and labelled."""
+    cores = len(os.sched_getaffinity(0))
+    t0 = time.perf_counter()
+    t_all, parts = _oracle_sample(prob, n_applies, cores)
+    t_one, _ = _oracle_sample(prob, n_applies, 1)
+    measured = time.perf_counter() - t0
+    return {"value": 1.0 / t_all, "unit": "solves/s", "cores": cores, "kind": "oracle",
+            "value_1_core": 1.0 / t_one,
+            "sample": (f"FP64 oracle on the same workload ({prob.name}, full frequency and angle grids): "
+                       f"set-up and formal solution on {parts['heights_sampled']} of {prob.n_z} heights, "
+                       f"{parts['kernels_sampled']} kernel matrices at those heights, 256 kernel-times-field "
+                       f"products; scaled to one solve with {n_applies:.1f} operator applies (the GPU solve's "
+                       f"count) by N_z, the kernel count and the product count; the apply's angular sums and "
+                       f"interpolations are not timed (a lower bound on the oracle's time, so an upper bound on "
+                       f"its solves/s); scaled estimate, not a measured full solve"),
+            "estimate_s": {"all_cores": t_all, "one_core": t_one, **parts},
+            "seconds_measured": measured}
 
 
 SERVE_STREAM = dict(n_z_range=(40, 70), nu_choices=(51, 71, 101), angle_sets=[(8, 4), (8, 8)])
@@ -145,7 +217,9 @@ def serving_bench(n_requests: int, seed: int, precond_sweeps: int):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--config", choices=sorted(CONFIGS), default="cfg4",
+                    help="workload (default: the largest configuration that fits one GPU)")
+    ap.add_argument("--steps", type=int, default=None, help="timed steps (default: per configuration)")
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
     ap.add_argument("--tol", type=float, default=1e-8)
@@ -169,9 +243,12 @@ def main():
               "and one all-to-all per apply for Lambda", file=sys.stderr)
         sys.exit(2)
 
+    import numpy as np
     import torch
     from paper_2505_20968_amd import Context, TRAP_FP32, TRAP_FP64
-    from workloads import cfg2
+    gen, workload, default_steps = CONFIGS[args.config]
+    if args.steps is None:
+        args.steps = default_steps
 
     if not torch.cuda.is_available():
         print("bench.py needs a ROCm GPU", file=sys.stderr)
@@ -182,9 +259,11 @@ def main():
     phases = {"set_problem": [], "precompute": [], "solve": []}
     sweeps = args.precond_sweeps
 
+    last = {}
+
     def one_step(seed, sw=None, record=True):
         sw = sweeps if sw is None else sw
-        prob = cfg2(seed)
+        prob = gen(seed)
         t0 = time.perf_counter()
         ctx.set_problem(prob)
         t1 = time.perf_counter()
@@ -199,6 +278,7 @@ def main():
                              inner=TRAP_FP32 if mixed else TRAP_FP64, max_outer=10, inner_tol=1e-7,
                              zero_guess=True, precond_sweeps=sw)
         t4 = time.perf_counter()
+        last.update(prob=prob, x=x, seed=seed)
         if not record:
             return st
         phases["set_problem"].append(t1 - t0)
@@ -232,12 +312,35 @@ def main():
     stage = ctx.stage_times()
     ctx.profile(False)
     info = ctx.info()
-    # the oracle solves without a preconditioner: its CPU estimate is scaled
-    # to the applies of an unpreconditioned solve of the same atmosphere
-    # (outside the timed region)
-    plain = stats[0]
-    if sweeps and not args.no_cpu_baseline:
-        plain = one_step(2, sw=0, record=False)
+    # outside the timed region: (1) the timed solve's emergent profiles against
+    # a tight FP64 solve of the same atmosphere (the parity contract: 1e-6
+    # relative on I, 1e-4 absolute on Q/I, U/I, V/I); (2) whole FP32 Sigma
+    # applies timed with events, against the contraction's algorithmic flops
+    em = ctx.emergent(last["x"])
+    xt = torch.zeros(ctx.shape, dtype=torch.float64, device="cuda")
+    stt = ctx.gmres_solve(xt, tol=1e-12, restart=args.restart, max_iters=4000, inner=TRAP_FP64, max_outer=20,
+                          inner_tol=1e-7, zero_guess=True, precond_sweeps=sweeps)
+    ref = ctx.emergent(xt)
+    accuracy = {"reference": "FP64 GMRES to 1e-12 of the last timed atmosphere",
+                "reference_final_rel_res": stt["final_rel_res"],
+                "max_rel_I": float((np.abs(em[..., 0] - ref[..., 0]) / np.abs(ref[..., 0])).max()),
+                "max_rel_I_over_max": float(np.abs(em[..., 0] - ref[..., 0]).max() / np.abs(ref[..., 0]).max()),
+                "max_abs_QUV_over_I": float(max(np.abs(em[..., s] / em[..., 0] - ref[..., s] / ref[..., 0]).max()
+                                                for s in (1, 2, 3)))}
+    accuracy["within_contract"] = accuracy["max_rel_I"] < 1e-6 and accuracy["max_abs_QUV_over_I"] < 1e-4
+    del xt
+    xs = torch.rand(ctx.shape, dtype=torch.float32, device="cuda")
+    ys = torch.empty_like(xs)
+    ctx.apply_sigma(xs, ys)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    n_sig = 5
+    ev0.record(ctx.stream)
+    for _ in range(n_sig):
+        ctx.apply_sigma(xs, ys)
+    ev1.record(ctx.stream)
+    ev1.synchronize()
+    sigma_ms = ev0.elapsed_time(ev1) / n_sig
+    del xs, ys
     ctx.close()
 
     key = "fp32" if mixed else "fp64"
@@ -247,7 +350,6 @@ def main():
     ms_c = cstage["ms"]
     achieved = flops / (ms_c * 1e-3) / 1e12 if ms_c > 0 else 0.0
     n_applies = sum(s["applies_fp32"] + s["applies_fp64"] for s in stats) / len(stats)
-    plain_applies = plain["applies_fp32"] + plain["applies_fp64"]
     apply_ms = {k: v["ms"] / max(v["launches"], 1) for k, v in stage.items() if isinstance(v, dict) and "ms" in v}
     out = {
         "metric": METRIC,
@@ -262,12 +364,14 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if mixed else "f64",
         "data": "synthetic",
-        "config": {"workload": "two-level J0->1 PRD-AD chromosphere-like column: N_z=70, "
-                               "N_nu=101 on [-12,12], 4+4 GL mu x 8 chi, seeded B/v/a/eps, tol 1e-8",
+        "config": {"workload": workload, "name": args.config, "tol": args.tol,
                    "precision": ("FP32 inner operator, FP64 Arnoldi/residual/refinement" if mixed
                                  else "FP64 throughout"),
                    "n_unknowns": info["n_unknowns"], "n_theta": info["n_theta"],
                    "n_slots": info["n_slots"], "restart": args.restart,
+                   "kernel_entries_in_band": info["kernel_entries"],
+                   "kernel_store_bytes": info["bytes_kernel_fp64"],
+                   "device_bytes": info["bytes_device_total"],
                    "preconditioner": (f"physics-based P = Id - Lambda* Sigma* (unmagnetised, unpolarised, "
                                       f"angle-averaged), {sweeps} block-Jacobi steps with the App. F "
                                       f"local inverse" if sweeps else "none")},
@@ -283,16 +387,24 @@ def main():
                              "contraction_launches": cstage["launches"],
                              "stage_ms_per_launch": apply_ms},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK[key], "unit": "TFLOP/s",
-                     "frac": achieved / PEAK[key], "traffic": measured_traffic() if mixed else None,
+                     "frac": achieved / PEAK[key],
+                     "traffic": measured_traffic(args.config) if mixed else None,
                      "algorithmic_bytes_per_launch": cbytes / max(cstage["launches"], 1),
                      "algorithmic_flops_per_launch": flops / max(cstage["launches"], 1),
                      "kernel": ("k_contract_pipe<NH> (persistent FP32 contraction, both column classes)"
                                 if mixed else "k_contract<double, NH>")},
+        "sigma_apply": {"ms": sigma_ms, "flops": info["flops_contraction"],
+                        "tflops": info["flops_contraction"] / (sigma_ms * 1e-3) / 1e12,
+                        "frac_fp32_peak": info["flops_contraction"] / (sigma_ms * 1e-3) / 1e12 / PEAK["fp32"],
+                        "what": "whole FP32 Sigma apply (comoving interpolation, contraction, R_III, angular "
+                                "sum, back-interpolation) timed with events, against the contraction's "
+                                "algorithmic flops"},
+        "accuracy": accuracy,
     }
     if args.serve_requests > 0:
         out["serving"] = serving_bench(args.serve_requests, seed=5, precond_sweeps=args.serve_precond_sweeps)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(plain_applies, seed=2)
+        out["cpu_baseline"] = cpu_baseline(last["prob"], n_applies)
     print(json.dumps(out))
 
 

@@ -192,7 +192,6 @@ __device__ __forceinline__ void formal_body(int bx, int nz, int nd, int nn, cons
   const int o = id / nn, n = id % nn;
   const double m = mu[o];
   const bool up = m > 0.0;
-  const T amu = T(fabs(m));
   const long long zs = (long long)nd * nn;          // point stride between heights
   auto pidx = [&](int z) { return (long long)z * zs + (long long)o * nn + n; };
   int z = up ? 0 : nz - 1;
@@ -200,6 +199,7 @@ __device__ __forceinline__ void formal_body(int bx, int nz, int nd, int nn, cons
   T Icur[4] = {T(0), T(0), T(0), T(0)};
   if (up && with_boundary) Icur[0] = T(WT[0]);
   T ku[6], Su[4], ru;
+  double rud;
   T Ru[4];                                          // reference source (PAR 3)
   double tz = tau[z];
   {
@@ -208,6 +208,7 @@ __device__ __forceinline__ void formal_body(int bx, int nz, int nd, int nn, cons
     for (int i = 0; i < 6; ++i) ku[i] = T(k[i]);
     const T inv = T(k[6]);
     ru = T(k[7]);
+    rud = k[7];
     for (int s = 0; s < 4; ++s) Su[s] = eps[p * 4 + s] * inv;
     if constexpr (PAR == 3)
       for (int s = 0; s < 4; ++s) Ru[s] = eref[p * 4 + s] * inv;
@@ -252,9 +253,13 @@ __device__ __forceinline__ void formal_body(int bx, int nz, int nd, int nn, cons
     T Rc[4];
     if constexpr (PAR == 3)
       for (int s = 0; s < 4; ++s) Rc[s] = err[s] * inv;
-    const T x = T(0.5) * (ru + rc) * T(fabs(tz - tzc)) / amu;
-    T pu, pc, ex;
-    delo_weights<T>(x, pu, pc, ex);
+    // the step's optical depth and weights from the FP64 data in FP64 (one
+    // rounding each into T): in FP32 the recurrence below then carries the
+    // only rounding that accumulates along the ray
+    const double xs = 0.5 * (rud + kr[7]) * fabs(tz - tzc) / fabs(m);
+    double pu64, pc64, ex64;
+    delo_weights<double>(xs, pu64, pc64, ex64);
+    const T pu = T(pu64), pc = T(pc64), ex = T(ex64);
     T kv[4], b[4];
     kprime_mul<T>(ku, Icur, kv);
     const bool par = PAR == 1 || (PAR < 0 && scheme == TRAP_FORMAL_DELOPAR);
@@ -294,6 +299,7 @@ __device__ __forceinline__ void formal_body(int bx, int nz, int nd, int nn, cons
       for (int s = 0; s < 4; ++s) Ru[s] = Rc[s];
     for (int i = 0; i < 6; ++i) ku[i] = kc[i];
     ru = rc;
+    rud = kr[7];
     z = zc;
     tz = tzc;
   }

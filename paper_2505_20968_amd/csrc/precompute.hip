@@ -758,9 +758,90 @@ __global__ void __launch_bounds__(512, 1) k_sig_gemm_lds(long long nrows, int nn
   }
 }
 
+// Banded M = L + Gam Sig straight into the store, one wave per (height, angle,
+// store tile, group of 64 columns): the tile's 16 rows over its column range
+// only, with the sum over j restricted to that range too (Gam vanishes outside
+// a row's band, which the tile's range contains).  v_mfma_f64_16x16x4 with
+// A = Gam fragment (lane l: row l % 16, k l / 16), B = Sig read from global
+// memory (the map is shared by every tile and stays in the caches), lane l
+// holding D[l / 16 + 4 r][l % 16].  Tiles made only of mirrored rows are left
+// to k_mirror_rows.
+constexpr int kTileGemmWaves = 4;
+__global__ void __launch_bounds__(64 * kTileGemmWaves) k_sig_gemm_tiles(
+    int zc, int nth, int nt, int nn, int ldm, int nnp, int nq, int ncg, const double* __restrict__ Gam,
+    const double* __restrict__ Lrow, const double* __restrict__ Sig, BandOut B, RowRoles roles) {
+  const long long unit = (long long)blockIdx.x * kTileGemmWaves + (threadIdx.x >> 6);
+  const long long nunit = (long long)zc * nth * nq * ncg;
+  if (unit >= nunit) return;
+  const int lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
+  const int cg = (int)(unit % ncg);
+  const long long tq = unit / ncg;
+  const int q = (int)(tq % nq);
+  const int th = (int)((tq / nq) % nth), zl = (int)(tq / ((long long)nq * nth));
+  const int np = 2 * nt;
+  const size_t zt = (size_t)(B.z0 + zl) * nth + th;
+  const TileDesc d = B.td[zt * nq + q];
+  const int c0 = d.lo + 64 * cg;
+  if (c0 >= d.hi) return;
+  const int r0 = tile_row0(B.pad, np, nnp, q);
+  // chunk row of tile row i (or -1 past the grid), and whether every row is mirrored
+  auto crow = [&](int i) -> long long {
+    const int r = r0 + i, p = r / nnp, n = r - p * nnp;
+    if (p >= np || n >= nn) return -1;
+    return (((long long)zl * nth + th) * np + p) * nn + n;
+  };
+  if (roles.on) {
+    bool all = true;
+    for (int i = 0; i < 16 && all; ++i) {
+      const int r = r0 + i, p = r / nnp, n = r - p * nnp;
+      all = p >= np || n >= nn || row_mirrored(roles, p >> 1, n, nn);
+    }
+    if (all) return;
+  }
+  const long long ra = crow(lr);
+  const double* grow = Gam + (ra < 0 ? 0 : ra) * ldm;
+  const int khi = min(d.hi, nn);
+  doublex4_g acc[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+    for (int r = 0; r < 4; ++r) acc[j][r] = 0.0;
+  for (int k0 = d.lo; k0 < khi; k0 += 4) {
+    const int k = k0 + lk;
+    const double af = (ra >= 0 && k < khi) ? grow[k] : 0.0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int col = c0 + 16 * j + lr;
+      const double bf = (k < khi && col < nn) ? Sig[(size_t)k * nn + col] : 0.0;
+      acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af, bf, acc[j], 0, 0, 0);
+    }
+  }
+  const int w = d.hi - d.lo;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int i = lk + 4 * r;
+    const long long rc = crow(i);
+    if (rc < 0) continue;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int col = c0 + 16 * j + lr;
+      if (col >= d.hi) continue;
+      const double v = col < nn ? acc[j][r] + Lrow[rc * ldm + col] : 0.0;
+      band_put(B, d.off + (long long)i * w + (col - d.lo), v);
+    }
+  }
+}
+
 // M = L + Gam Sig for `rrows` real rows; the persistent form when Sig fits
 // `roles` (optional): mirror roles of rows laid out [..][t][c][n]; tiles made
 // only of mirrored rows are skipped (the persistent form), k_mirror_rows fills them
+// whether the persistent LDS form of the product applies (Sig resident in LDS)
+static bool sig_gemm_fits_lds(const trap_ctx* ctx) {
+  const int nn = ctx->pb.nn, ldm = ctx->pb.ldm;
+  const int nh = ldm / 8, nct = (nn + 15) / 16;
+  const size_t lds = (size_t)8 * nh * (16 * nct + 4) * sizeof(double);
+  return lds <= (size_t)ctx->max_lds && nh >= 1 && nh <= 16 && nct <= 8;
+}
+
 int launch_sig_gemm(trap_ctx* ctx, long long rrows, const double* Gam, const double* Lrow, double* M64,
                     float* M32, long long out_row0, const RowRoles* roles = nullptr, const BandOut* band = nullptr) {
   const BandOut bo = band ? *band : BandOut{};
@@ -1165,7 +1246,14 @@ int run_precompute(trap_ctx* ctx, int store_mask) {
     }
     const long long rrows = 2 * nrows;                           // real rows (both planes)
     bo.z0 = z0;
-    if (!aa) {
+    if (!aa && !sig_gemm_fits_lds(ctx)) {
+      const int ncg = ceil_div(P.ldm, 64);
+      const long long units = (long long)zc * nth * P.nq * ncg;
+      hipLaunchKernelGGL(k_sig_gemm_tiles, dim3((unsigned)ceil_div(units, kTileGemmWaves)),
+                         dim3(64 * kTileGemmWaves), 0, s, zc, nth, nt, nn, P.ldm, P.nnp, P.nq, ncg, C.d_Grow,
+                         C.d_Lrow, P.d_Sig, bo, roles);
+      TRAP_HIP(hipGetLastError());
+    } else if (!aa) {
       TRAP_TRY(launch_sig_gemm(ctx, rrows, C.d_Grow, C.d_Lrow, nullptr, nullptr, 0LL, &roles, &bo));
     } else {
       // rows at the Gauss-Legendre angles into the scratch store, then their weighted sum

@@ -57,6 +57,12 @@ def test_cfg1_full_solve_matches_oracle(inner):
     assert relI.max() < 1e-6
     for s in (1, 2, 3):
         assert np.abs(em[..., s] / em[..., 0] - ref[..., s] / ref[..., 0]).max() < 1e-4
+    if inner == "fp64":
+        # every Stokes component to 1e-8 of the largest I (Q, U, V are far
+        # smaller than I, so this holds them to more than the 1e-4 gate on Q/I)
+        full = np.abs(em - ref).max(axis=(0, 1)) / np.abs(ref[..., 0]).max()
+        print(f"[cfg1 fp64] max |diff| / max I per Stokes {full}", flush=True)
+        assert full.max() < 1e-8
 
 
 @pytest.fixture(scope="module")
@@ -94,9 +100,14 @@ def test_cfg2_sigma_at_sampled_heights(big):
         ref = T.sigma_height(op, z, I[z], normalize=False)
         ref[..., 0] *= T.normalization_height(op, z)
         r64, r32 = _rel(g64[z], ref), _rel(g32[z], ref)
-        print(f"[cfg2] height {z}: sigma fp64 rel {r64:.2e}, fp32 rel {r32:.2e}", flush=True)
-        assert r64 < 1e-10
-        assert r32 < 2e-5
+        # element by element, each Stokes component against the height's largest |eps_I|
+        scale = np.abs(ref[..., 0]).max()
+        e64 = np.abs(g64[z] - ref).max(axis=(0, 1)) / scale
+        e32 = np.abs(g32[z] - ref).max(axis=(0, 1)) / scale
+        print(f"[cfg2] height {z}: sigma fp64 rel {r64:.2e} (element-wise per Stokes {e64}), "
+              f"fp32 rel {r32:.2e} (element-wise {e32})", flush=True)
+        assert r64 < 1e-10 and e64.max() < 1e-10
+        assert r32 < 2e-5 and e32.max() < 2e-5
 
 
 def test_cfg2_formal_solution_every_ray(big):
@@ -105,14 +116,25 @@ def test_cfg2_formal_solution_every_ray(big):
     op = T.setup(prob, {"normalize": False})
     eps = np.abs(I) * 0.3
     ref = T.formal_solve(op, eps, boundary=True)
-    for dt, tol in ((torch.float64, 1e-12), (torch.float32, 1e-6)):
+    # per ray (direction, frequency): the largest difference over heights and
+    # Stokes against the ray's largest |I|.  FP64 1e-11: 70 sequential steps
+    # whose exponentials and weights round differently on the two sides.  FP32
+    # 5e-6: the recurrence carries one FP32 rounding of the intensity per
+    # operation of each step (about 2^-24 relative each, a few per step), and
+    # on optically thin rays nothing damps it, so it grows with the 70 steps to
+    # a few 1e-6 of the ray's largest value (measured 1.9e-6); the 2-norm over
+    # all rays stays within 1e-6
+    for dt, tol, tol_ray in ((torch.float64, 1e-12, 1e-11), (torch.float32, 1e-6, 5e-6)):
         et = torch.tensor(eps, dtype=dt, device="cuda")
         out = torch.empty_like(et)
         ctx.formal_solve(et, out, with_boundary=True)
         torch.cuda.synchronize()
-        r = _rel(out.double().cpu().numpy(), ref)
-        print(f"[cfg2] formal {dt} rel {r:.2e}", flush=True)
+        got = out.double().cpu().numpy()
+        r = _rel(got, ref)
+        per_ray = np.abs(got - ref).max(axis=(0, 3)) / np.abs(ref[..., 0]).max(axis=0)
+        print(f"[cfg2] formal {dt} rel {r:.2e}, worst ray {per_ray.max():.2e}", flush=True)
         assert r < tol
+        assert per_ray.max() < tol_ray
 
 
 def test_cfg2_mixed_solve_agrees_with_fp64_solve(big):
