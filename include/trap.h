@@ -457,6 +457,17 @@ int trap_set_path(trap_ctx* ctx, int path);
 /* Thread-local description of the last failure. */
 const char* trap_last_error(void);
 
+/* HIP failures the library noticed outside any failing call's own return:
+ * teardown and bookkeeping calls whose failure changes nothing the caller
+ * gets (releases, synchronisations in trap_destroy, profiling events), and a
+ * HIP error already pending in the thread when an entry point starts (left
+ * by an earlier call of the caller's or of a runtime component).  Each is
+ * recorded with the call (or "error pending at entry") and the function or
+ * entry point, and cleared so that it cannot surface as a later launch's
+ * error.  *count receives the number recorded in the process; buf (n bytes)
+ * the latest record, NUL-terminated.  Either may be NULL. */
+int trap_hip_notes(long long* count, char* buf, size_t n);
+
 #ifdef __cplusplus
 }
 #endif

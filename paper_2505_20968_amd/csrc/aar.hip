@@ -402,6 +402,6 @@ int aar_solve(trap_ctx* ctx, const trap_aar_opts* o, double* x, trap_solve_stats
 
 int trap_aar_solve(trap_ctx* ctx, const trap_aar_opts* opts, double* I, trap_solve_stats* stats) {
   if (!ctx) return trap::fail(TRAP_EINVAL, "null context");
-  trap::DeviceGuard g(ctx->device);
+  trap::DeviceGuard g(ctx->device, __func__);
   return trap::aar_solve(ctx, opts, I, stats);
 }

@@ -1,13 +1,11 @@
 // C-ABI entry points of the trap library (declared in include/trap.h), the
 // context's allocation bookkeeping and the operator apply y = x - Lambda Sigma x.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <mutex>
 #include <set>
 #include <string>
-
-#include <algorithm>
-#include <cmath>
 #include <vector>
 
 #include "trap_internal.h"
@@ -23,6 +21,20 @@ void set_error(const std::string& msg) { g_last_error = msg; }
 int fail(int code, const std::string& msg) {
   set_error(msg);
   return code;
+}
+
+namespace {
+std::mutex g_note_mu;
+long long g_note_count = 0;
+std::string g_note_last;
+}  // namespace
+
+void note_hip(const char* what, const char* where, hipError_t e) {
+  if (e == hipSuccess) return;
+  (void)hipGetLastError();           // the failure is recorded here, not left for a later check
+  std::lock_guard<std::mutex> lk(g_note_mu);
+  ++g_note_count;
+  g_note_last = std::string(where) + ": " + what + " -> " + hipGetErrorName(e) + " (" + hipGetErrorString(e) + ")";
 }
 
 // Device memory comes from the device's stream-ordered pool, allocated and
@@ -85,14 +97,14 @@ int dalloc(trap_ctx* ctx, void** p, size_t bytes) {
 // replaced, in stream order after the context's work.
 void release_spare(trap_ctx* ctx) {
   for (auto& b : ctx->spare) {
-    if (b.pooled) (void)hipFreeAsync(b.p, ctx->stream);
-    else (void)hipFree(b.p);
+    if (b.pooled) TRAP_NOTE(hipFreeAsync(b.p, ctx->stream));
+    else TRAP_NOTE(hipFree(b.p));
   }
   ctx->spare.clear();
 }
 
 void free_all(trap_ctx* ctx) {
-  if (!ctx->bufs.empty()) (void)hipStreamSynchronize(ctx->stream);
+  if (!ctx->bufs.empty()) TRAP_NOTE(hipStreamSynchronize(ctx->stream));
   gmres_release(ctx);
   release_spare(ctx);
   ctx->spare.swap(ctx->bufs);
@@ -143,7 +155,7 @@ int prof_begin(trap_ctx* ctx, int stage, double flops, double bytes) {
     ProfRec r{stage, nullptr, nullptr, 0.0, 0.0};
     if (hipEventCreate(&r.a) != hipSuccess) return -1;
     if (hipEventCreate(&r.b) != hipSuccess) {
-      (void)hipEventDestroy(r.a);
+      TRAP_NOTE(hipEventDestroy(r.a));
       return -1;
     }
     P.rec.push_back(r);
@@ -152,20 +164,20 @@ int prof_begin(trap_ctx* ctx, int stage, double flops, double bytes) {
   r.stage = stage;
   r.flops = flops;
   r.bytes = bytes;
-  (void)hipEventRecord(r.a, ctx->stream);
+  TRAP_NOTE(hipEventRecord(r.a, ctx->stream));
   return static_cast<int>(P.used++);
 }
 
 void prof_end(trap_ctx* ctx, int idx) {
   if (idx < 0) return;
-  (void)hipEventRecord(ctx->prof.rec[idx].b, ctx->stream);
+  TRAP_NOTE(hipEventRecord(ctx->prof.rec[idx].b, ctx->stream));
 }
 
 static void prof_clear(trap_ctx* ctx, bool release) {
   if (release) {
     for (auto& r : ctx->prof.rec) {
-      (void)hipEventDestroy(r.a);
-      (void)hipEventDestroy(r.b);
+      TRAP_NOTE(hipEventDestroy(r.a));
+      TRAP_NOTE(hipEventDestroy(r.b));
     }
     ctx->prof.rec.clear();
   }
@@ -177,6 +189,17 @@ static void prof_clear(trap_ctx* ctx, bool release) {
 using namespace trap;
 
 extern "C" {
+
+int trap_hip_notes(long long* count, char* buf, size_t n) {
+  std::lock_guard<std::mutex> lk(trap::g_note_mu);
+  if (count) *count = trap::g_note_count;
+  if (buf && n > 0) {
+    const size_t k = std::min(n - 1, trap::g_note_last.size());
+    std::memcpy(buf, trap::g_note_last.data(), k);
+    buf[k] = 0;
+  }
+  return TRAP_OK;
+}
 
 const char* trap_last_error(void) { return g_last_error.c_str(); }
 
@@ -212,16 +235,16 @@ int trap_create(trap_ctx** out, int device, void* stream) {
 
 int trap_destroy(trap_ctx* ctx) {
   if (!ctx) return TRAP_OK;
-  DeviceGuard g(ctx->device);
+  DeviceGuard g(ctx->device, __func__);
   prof_clear(ctx, true);
   free_all(ctx);
   release_spare(ctx);
   if (ctx->side) {
-    (void)hipStreamSynchronize(ctx->side);
-    (void)hipStreamDestroy(ctx->side);
+    TRAP_NOTE(hipStreamSynchronize(ctx->side));
+    TRAP_NOTE(hipStreamDestroy(ctx->side));
   }
-  if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
-  if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
+  if (ctx->ev_fork) TRAP_NOTE(hipEventDestroy(ctx->ev_fork));
+  if (ctx->ev_join) TRAP_NOTE(hipEventDestroy(ctx->ev_join));
   batch_arena_release(ctx->device);
   delete ctx;
   return TRAP_OK;
@@ -229,7 +252,7 @@ int trap_destroy(trap_ctx* ctx) {
 
 int trap_set_problem(trap_ctx* ctx, const trap_atom_desc* atom, const trap_problem_desc* prob) {
   if (!ctx) return fail(TRAP_EINVAL, "null context");
-  DeviceGuard g(ctx->device);
+  DeviceGuard g(ctx->device, __func__);
   free_all(ctx);
   int s = build_problem(ctx, atom, prob);
   if (s != TRAP_OK) {
@@ -251,7 +274,7 @@ int trap_precompute(trap_ctx* ctx, int store_mask) {
   if (!ctx) return fail(TRAP_EINVAL, "null context");
   if (!ctx->has_problem) return fail(TRAP_ESTATE, "no problem loaded");
   if (store_mask & ~3) return fail(TRAP_EINVAL, "store_mask has unknown bits");
-  DeviceGuard g(ctx->device);
+  DeviceGuard g(ctx->device, __func__);
   return run_precompute(ctx, store_mask);
 }
 
@@ -259,26 +282,26 @@ int trap_precompute_preconditioner(trap_ctx* ctx) {
   if (!ctx) return fail(TRAP_EINVAL, "null context");
   if (!ctx->has_problem || !ctx->pre.done) return fail(TRAP_ESTATE, "precompute not run");
   if (ctx->pre.pc_done) return TRAP_OK;
-  DeviceGuard g(ctx->device);
+  DeviceGuard g(ctx->device, __func__);
   return run_precompute_precond(ctx);
 }
 
 int trap_apply_preconditioner(trap_ctx* ctx, const double* r, double* out, int sweeps, int prec) {
   if (!ctx) return fail(TRAP_EINVAL, "null context");
-  DeviceGuard g(ctx->device);
+  DeviceGuard g(ctx->device, __func__);
   return precond_apply(ctx, r, out, sweeps, prec);
 }
 
 int trap_apply_preconditioner_noalloc(trap_ctx* ctx, const double* r, double* out, int sweeps, int prec) {
   if (!ctx) return fail(TRAP_EINVAL, "null context");
-  DeviceGuard g(ctx->device);
+  DeviceGuard g(ctx->device, __func__);
   return precond_apply_noalloc(ctx, r, out, sweeps, prec);
 }
 
 int trap_preconditioner_tables(trap_ctx* ctx, double* phi, double* c, double* lloc) {
   if (!ctx) return fail(TRAP_EINVAL, "null context");
   if (!ctx->has_problem || !ctx->pre.pc_done) return fail(TRAP_ESTATE, "preconditioner tables not computed");
-  DeviceGuard g(ctx->device);
+  DeviceGuard g(ctx->device, __func__);
   const Problem& P = ctx->pb;
   const size_t nmat = (size_t)P.nz * P.nn * P.nn, nloc = (size_t)P.nz * P.nd * P.nn;
   if (phi) TRAP_HIP(hipMemcpyAsync(phi, ctx->pre.d_pcPhi, nmat * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
@@ -290,13 +313,13 @@ int trap_preconditioner_tables(trap_ctx* ctx, double* phi, double* c, double* ll
 
 int trap_apply_sigma(trap_ctx* ctx, const void* I, void* eps, int prec, int add_thermal) {
   if (!ctx) return fail(TRAP_EINVAL, "null context");
-  DeviceGuard g(ctx->device);
+  DeviceGuard g(ctx->device, __func__);
   return sigma_apply(ctx, I, eps, prec, add_thermal, 1);
 }
 
 int trap_formal_solve(trap_ctx* ctx, const void* eps, void* I, int with_boundary, int prec) {
   if (!ctx) return fail(TRAP_EINVAL, "null context");
-  DeviceGuard g(ctx->device);
+  DeviceGuard g(ctx->device, __func__);
   return formal_apply(ctx, eps, I, with_boundary, prec);
 }
 
@@ -304,7 +327,7 @@ int trap_apply_operator(trap_ctx* ctx, const void* x, void* y, int prec) {
   if (!ctx) return fail(TRAP_EINVAL, "null context");
   if (!ctx->has_problem || !ctx->pre.done) return fail(TRAP_ESTATE, "precompute not run");
   if (!x || !y) return fail(TRAP_EINVAL, "null vector");
-  DeviceGuard g(ctx->device);
+  DeviceGuard g(ctx->device, __func__);
   return operator_apply(ctx, x, y, prec);
 }
 
@@ -312,7 +335,7 @@ int trap_rhs(trap_ctx* ctx, double* b_out) {
   if (!ctx) return fail(TRAP_EINVAL, "null context");
   if (!ctx->has_problem || !ctx->pre.done) return fail(TRAP_ESTATE, "precompute not run");
   if (!b_out) return fail(TRAP_EINVAL, "null vector");
-  DeviceGuard g(ctx->device);
+  DeviceGuard g(ctx->device, __func__);
   const size_t N = 4ull * ctx->pb.nz * ctx->pb.nd * ctx->pb.nn;
   TRAP_HIP(hipMemcpyAsync(b_out, ctx->pre.d_b, N * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
   return TRAP_OK;
@@ -320,7 +343,7 @@ int trap_rhs(trap_ctx* ctx, double* b_out) {
 
 int trap_gmres_solve(trap_ctx* ctx, const trap_solve_opts* opts, double* I, trap_solve_stats* stats) {
   if (!ctx) return fail(TRAP_EINVAL, "null context");
-  DeviceGuard g(ctx->device);
+  DeviceGuard g(ctx->device, __func__);
   return gmres_solve(ctx, opts, I, stats);
 }
 
@@ -328,7 +351,7 @@ int trap_emergent(trap_ctx* ctx, const double* I, double* host_out) {
   if (!ctx) return fail(TRAP_EINVAL, "null context");
   if (!ctx->has_problem) return fail(TRAP_ESTATE, "no problem loaded");
   if (!I || !host_out) return fail(TRAP_EINVAL, "null pointer");
-  DeviceGuard g(ctx->device);
+  DeviceGuard g(ctx->device, __func__);
   const Problem& P = ctx->pb;
   const size_t rec = (size_t)P.nn * 4;
   const double* top = I + (size_t)(P.nz - 1) * P.nd * rec;
@@ -355,7 +378,7 @@ int trap_formal_from_field(trap_ctx* ctx, const double* I, int n_dir_in, double*
   const char* ib = reinterpret_cast<const char*>(I);
   const char* ob = reinterpret_cast<const char*>(out);
   if (ib < ob + N && ob < ib + (size_t)P.nz * n_dir_in * rec) return fail(TRAP_EINVAL, "out overlaps I");
-  DeviceGuard g(ctx->device);
+  DeviceGuard g(ctx->device, __func__);
   TRAP_TRY(ensure_work(ctx, TRAP_FP64));
   const double* x = I;
   if (n_dir_in != P.nd) {
@@ -378,7 +401,7 @@ int trap_emergent_los(trap_ctx* ctx, const double* I, double* host_out) {
   if (!I || !host_out) return fail(TRAP_EINVAL, "null pointer");
   const Problem& P = ctx->pb;
   if (P.nlos == 0) return fail(TRAP_EINVAL, "the problem has no lines of sight");
-  DeviceGuard g(ctx->device);
+  DeviceGuard g(ctx->device, __func__);
   const size_t rec = (size_t)P.nn * 4;
   const double* top = I + ((size_t)(P.nz - 1) * P.nd + P.ngrid) * rec;   // the rings follow the quadrature
   TRAP_HIP(hipMemcpyAsync(host_out, top, (size_t)(P.nd - P.ngrid) * rec * sizeof(double), hipMemcpyDeviceToHost,
@@ -431,7 +454,7 @@ int trap_kernel_rows(trap_ctx* ctx, int z, int theta, int t, double* theta_out, 
   const Problem& P = ctx->pb;
   if (z < 0 || z >= P.nz || theta < 0 || theta >= P.nth || t < 0 || t >= P.nt)
     return fail(TRAP_EINVAL, "kernel index out of range");
-  DeviceGuard g(ctx->device);
+  DeviceGuard g(ctx->device, __func__);
   const size_t zt = (size_t)z * P.nth + theta, nn = P.nn;
   const long long first = P.kbase[zt];
   const long long last = zt + 1 < P.kbase.size() ? P.kbase[zt + 1] : (long long)P.kentries;
@@ -467,13 +490,13 @@ int trap_faddeeva(int device, const double* v, const double* a, int n, double* o
   for (int i = 0; i < n; ++i)
     if (!(a[i] >= 0.0) || !std::isfinite(v[i])) return fail(TRAP_EINVAL, "points need finite v and a >= 0");
   if (n == 0) return TRAP_OK;
-  DeviceGuard g(device);
+  DeviceGuard g(device, __func__);
   return faddeeva_eval(device, v, a, n, out);
 }
 
 int trap_gmres_begin(trap_ctx* ctx, const trap_solve_opts* opts, double* I) {
   if (!ctx) return fail(TRAP_EINVAL, "null context");
-  DeviceGuard g(ctx->device);
+  DeviceGuard g(ctx->device, __func__);
   return gmres_begin(ctx, opts, I);
 }
 
@@ -490,7 +513,7 @@ int trap_gmres_step_batch(trap_ctx** ctxs, int n, int* status) {
 
 int trap_gmres_end(trap_ctx* ctx, trap_solve_stats* stats) {
   if (!ctx) return fail(TRAP_EINVAL, "null context");
-  DeviceGuard g(ctx->device);
+  DeviceGuard g(ctx->device, __func__);
   return gmres_end(ctx, stats);
 }
 
@@ -521,7 +544,7 @@ int trap_set_path(trap_ctx* ctx, int path) {
 
 int trap_profile(trap_ctx* ctx, int enable) {
   if (!ctx) return fail(TRAP_EINVAL, "null context");
-  DeviceGuard g(ctx->device);
+  DeviceGuard g(ctx->device, __func__);
   if (enable) {
     TRAP_HIP(hipStreamSynchronize(ctx->stream));
     prof_clear(ctx, false);
@@ -532,7 +555,7 @@ int trap_profile(trap_ctx* ctx, int enable) {
 
 int trap_stage_times(trap_ctx* ctx, trap_stage_stats* out) {
   if (!ctx || !out) return fail(TRAP_EINVAL, "null argument");
-  DeviceGuard g(ctx->device);
+  DeviceGuard g(ctx->device, __func__);
   std::memset(out, 0, sizeof(*out));
   TRAP_HIP(hipStreamSynchronize(ctx->stream));
   for (size_t i = 0; i < ctx->prof.used; ++i) {

@@ -10,7 +10,8 @@
 // Quadrature: Gauss-Legendre 16 on panels chosen per knot interval.  Panels
 // grow geometrically away from the Voigt/Lorentz centre of F at
 // u' = -u_n - 2 s_t (first width 2 max(cos(Theta/2), a)), and never exceed
-// half the Gaussian width 2 sin(Theta/2); the Gaussian factor is cut where
+// 1.5 Gaussian widths 2 sin(Theta/2) (GL-16 integrates the Gaussian factor
+// over such a panel to rounding); the Gaussian factor is cut where
 // it falls below e^-43.
 #include <cmath>
 #include <mutex>
@@ -287,7 +288,7 @@ __global__ void __launch_bounds__(64 * kRowWavesMax, 3) k_kernel_rows(
   const double lo = xn - R, hi = xn + R;
   const double xc = -xn - 2.0 * s / L;
   const double wc = 2.0 * fmax(fp.cG, a) / L;
-  const double Lg = 0.5 * sigma;
+  const double Lg = 1.5 * sigma;
   for (int i = lane; i < (nn + 1) * 4; i += 64) mom[i] = make_double2(0.0, 0.0);
   __syncthreads();
   // pieces: -1 left tail, 0..nn-2 knot intervals, nn-1 right tail
@@ -1144,9 +1145,9 @@ int faddeeva_eval(int device, const double* v, const double* a, int n, double* o
     else if (hipMemcpy(out, dout, 2 * b, hipMemcpyDeviceToHost) != hipSuccess)
       rc = fail(TRAP_EDEVICE, "faddeeva download");
   }
-  if (dout) (void)hipFree(dout);
-  if (da) (void)hipFree(da);
-  (void)hipFree(dv);
+  if (dout) TRAP_NOTE(hipFree(dout));
+  if (da) TRAP_NOTE(hipFree(da));
+  TRAP_NOTE(hipFree(dv));
   return rc;
 }
 

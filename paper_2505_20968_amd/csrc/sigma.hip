@@ -1548,20 +1548,20 @@ std::map<int, BatchArena> g_arena;
 void arena_free(BatchArena& a) {
   for (StagingBuf& b : a.staging) {
     if (b.ev) {
-      (void)hipEventSynchronize(b.ev);
-      (void)hipEventDestroy(b.ev);
+      TRAP_NOTE(hipEventSynchronize(b.ev));
+      TRAP_NOTE(hipEventDestroy(b.ev));
     }
-    if (b.host) (void)hipHostFree(b.host);
+    if (b.host) TRAP_NOTE(hipHostFree(b.host));
   }
   a.staging.clear();
-  if (a.stream) (void)hipStreamSynchronize(a.stream);
-  for (hipEvent_t e : a.ev) (void)hipEventDestroy(e);
+  if (a.stream) TRAP_NOTE(hipStreamSynchronize(a.stream));
+  for (hipEvent_t e : a.ev) TRAP_NOTE(hipEventDestroy(e));
   a.ev.clear();
-  if (a.copied) (void)hipEventDestroy(a.copied);
-  if (a.done) (void)hipEventDestroy(a.done);
-  if (a.host) (void)hipHostFree(a.host);
-  if (a.dev) (void)hipFree(a.dev);
-  if (a.stream) (void)hipStreamDestroy(a.stream);
+  if (a.copied) TRAP_NOTE(hipEventDestroy(a.copied));
+  if (a.done) TRAP_NOTE(hipEventDestroy(a.done));
+  if (a.host) TRAP_NOTE(hipHostFree(a.host));
+  if (a.dev) TRAP_NOTE(hipFree(a.dev));
+  if (a.stream) TRAP_NOTE(hipStreamDestroy(a.stream));
   a = BatchArena();
 }
 
@@ -1967,6 +1967,9 @@ int op_apply_batch_f32(trap_ctx** ctxs, int n, const double* const* x, double* c
   TRAP_HIP(hipMemcpyAsync(ar.dev, ar.host, blob.h.size(), hipMemcpyHostToDevice, ar.stream));
   TRAP_HIP(hipEventRecord(ar.copied, ar.stream));
   const unsigned char* base = static_cast<const unsigned char*>(ar.dev);
+  // every exit after the first launch goes through the join below, so the
+  // contexts' streams stay ordered after whatever the batch stream has begun
+  auto launch_stages = [&]() -> int {
   for (const Stage& st : stages) {
     const int* off = reinterpret_cast<const int*>(base + st.off);
     const void* args = base + st.args;
@@ -2052,9 +2055,21 @@ int op_apply_batch_f32(trap_ctx** ctxs, int n, const double* const* x, double* c
     TRAP_HIP(hipGetLastError());
   }
   // ... and each context's later work waits for the batch
-  TRAP_HIP(hipEventRecord(ar.done, ar.stream));
-  for (int i = 0; i < n; ++i) TRAP_HIP(hipStreamWaitEvent(ctxs[i]->stream, ar.done, 0));
   return TRAP_OK;
+  };
+  const int rc = launch_stages();
+  const hipError_t e = hipEventRecord(ar.done, ar.stream);
+  bool joined = e == hipSuccess;
+  for (int i = 0; i < n && joined; ++i) joined = hipStreamWaitEvent(ctxs[i]->stream, ar.done, 0) == hipSuccess;
+  if (!joined) {
+    // without the join, wait for the batch here before any context reuses its buffers
+    (void)hipGetLastError();
+    const hipError_t w = hipStreamSynchronize(ar.stream);
+    if (rc == TRAP_OK)
+      return fail(TRAP_EDEVICE, std::string("joining the shared launches: ") +
+                                    hipGetErrorString(e != hipSuccess ? e : w));
+  }
+  return rc;
 }
 
 }  // namespace trap

@@ -270,7 +270,7 @@ int gmres_begin(trap_ctx* ctx, const trap_solve_opts* opts, double* I) {
   if (!ctx->run) return fail(TRAP_ENOMEM, "host allocation failed");
   GmresRun& R = *ctx->run;
   if (R.hbuf && R.m < m) {
-    (void)hipHostFree(R.hbuf);
+    TRAP_NOTE(hipHostFree(R.hbuf));
     R.hbuf = nullptr;
   }
   if (!R.hbuf) TRAP_HIP(hipHostMalloc(reinterpret_cast<void**>(&R.hbuf), 4 * (m + 2) * sizeof(double)));
@@ -595,7 +595,7 @@ int gmres_step_batch(trap_ctx** ctxs, int n, int* status) {
   for (int i = 0; i < n; ++i) {
     GmresRun& R = *ctxs[i]->run;
     if (R.phase == GP_DONE) continue;
-    DeviceGuard g(ctxs[i]->device);
+    DeviceGuard g(ctxs[i]->device, __func__);
     int prec;
     const double* x;
     double* y;
@@ -620,11 +620,11 @@ int gmres_step_batch(trap_ctx** ctxs, int n, int* status) {
   }
   if (grp.size() == 1) {
     GmresRun& R = *ctxs[grp[0]]->run;
-    DeviceGuard g(gdev);
+    DeviceGuard g(gdev, __func__);
     const int rc = unit_issue1(ctxs[grp[0]], R);
     if (rc < 0) run_finish(R, rc);
   } else if (grp.size() > 1) {
-    DeviceGuard g(gdev);
+    DeviceGuard g(gdev, __func__);
     // Arnoldi vectors are preconditioned in place right after the apply, so
     // their preconditioner joins the shared launches
     std::vector<int> pcs(grp.size(), 0);
@@ -649,14 +649,14 @@ int gmres_step_batch(trap_ctx** ctxs, int n, int* status) {
   for (int i = 0; i < n; ++i) {
     GmresRun& R = *ctxs[i]->run;
     if (R.phase == GP_DONE) continue;
-    DeviceGuard g(ctxs[i]->device);
+    DeviceGuard g(ctxs[i]->device, __func__);
     if (hipStreamSynchronize(ctxs[i]->stream) != hipSuccess) run_finish(R, fail(TRAP_EDEVICE, "stream error"));
   }
   bool any2 = false;
   for (int i = 0; i < n; ++i) {
     GmresRun& R = *ctxs[i]->run;
     if (R.phase == GP_DONE) continue;
-    DeviceGuard g(ctxs[i]->device);
+    DeviceGuard g(ctxs[i]->device, __func__);
     const int rc = unit_after1(ctxs[i], R);
     if (rc < 0) run_finish(R, rc);
     any2 = any2 || (R.phase == GP_ARNOLDI && R.p2);
@@ -665,12 +665,12 @@ int gmres_step_batch(trap_ctx** ctxs, int n, int* status) {
     for (int i = 0; i < n; ++i) {
       GmresRun& R = *ctxs[i]->run;
       if (R.phase != GP_ARNOLDI || !R.p2) continue;
-      DeviceGuard g(ctxs[i]->device);
+      DeviceGuard g(ctxs[i]->device, __func__);
       if (hipStreamSynchronize(ctxs[i]->stream) != hipSuccess) run_finish(R, fail(TRAP_EDEVICE, "stream error"));
     }
     for (int i = 0; i < n; ++i) {
       GmresRun& R = *ctxs[i]->run;
-      DeviceGuard g(ctxs[i]->device);
+      DeviceGuard g(ctxs[i]->device, __func__);
       const int rc = unit_after2(ctxs[i], R);
       if (rc < 0) run_finish(R, rc);
     }
@@ -691,7 +691,7 @@ int gmres_end(trap_ctx* ctx, trap_solve_stats* st) {
 
 void gmres_release(trap_ctx* ctx) {
   if (!ctx->run) return;
-  if (ctx->run->hbuf) (void)hipHostFree(ctx->run->hbuf);
+  if (ctx->run->hbuf) TRAP_NOTE(hipHostFree(ctx->run->hbuf));
   delete ctx->run;
   ctx->run = nullptr;
 }

@@ -553,19 +553,30 @@ int launch_pc_local_lambda(trap_ctx* ctx);
 int launch_formal_scalar(trap_ctx* ctx, int prec, const double* e, const double* y, int y_stride,
                          const double* x, double* res);
 
-// Every entry point holds one.  It also clears the thread's last HIP error, so
-// that the launch checks inside (hipGetLastError after each launch) report the
-// library's own errors, not one left by an earlier call of the caller's.
+// HIP calls whose failure cannot change what the caller gets (releases,
+// synchronisations in teardown, profiling events) go through note_hip: a
+// failure is recorded with the call's text and the place (trap_hip_notes
+// reads the count and the latest record) and the thread's last-error slot is
+// cleared, so it cannot reappear as the error of a later launch check.
+void note_hip(const char* what, const char* where, hipError_t e);
+#define TRAP_NOTE(call) ::trap::note_hip(#call, __func__, (call))
+
+// Every entry point holds one.  A HIP error already pending in the thread's
+// last-error slot when the entry point starts (left by a call outside the
+// library, or by a library call that did not check it) is recorded with the
+// entry point's name (trap_hip_notes) and cleared, so that the launch checks
+// inside (hipGetLastError after each launch) report this call's own errors.
 struct DeviceGuard {
   int prev = -1;
-  explicit DeviceGuard(int dev) {
-    (void)hipGetLastError();
+  DeviceGuard(int dev, const char* entry) {
+    const hipError_t stale = hipGetLastError();
+    if (stale != hipSuccess) note_hip("error pending at entry", entry, stale);
     if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-    if (prev != dev) (void)hipSetDevice(dev);
+    if (prev != dev) TRAP_NOTE(hipSetDevice(dev));
   }
   ~DeviceGuard() {
     int cur = -1;
-    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) TRAP_NOTE(hipSetDevice(prev));
   }
 };
 

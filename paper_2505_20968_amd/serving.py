@@ -25,6 +25,7 @@ import time
 from typing import Any, Callable, List, Optional, Sequence
 
 TRAP_ENOMEM = -2
+TRAP_EDEVICE = -3
 
 
 @dataclasses.dataclass
@@ -49,7 +50,9 @@ class Scheduler:
 
     backend must provide ``footprint(problem) -> bytes``, ``admit(problem) ->
     handle``, ``step(handles) -> list of status`` (1 running, else final status)
-    and ``finish(handle) -> (status, stats, result)``."""
+    and ``finish(handle) -> (status, stats, result)``.  An admit that raises
+    ends that request only (status: the exception's ``code``, else
+    TRAP_EDEVICE); the backend releases what it had built for it."""
 
     def __init__(self, backend, mem_budget: int, max_active: int = 16,
                  clock: Callable[[], float] = time.perf_counter,
@@ -89,7 +92,14 @@ class Scheduler:
                 queue.popleft()
                 req.admitted = self.clock() - t0
                 ta = self.clock()
-                handle = self.backend.admit(req.problem)
+                try:
+                    handle = self.backend.admit(req.problem)
+                except Exception as e:       # the request fails alone; the stream goes on
+                    self.time_admit += self.clock() - ta
+                    req.status = int(getattr(e, "code", TRAP_EDEVICE))
+                    req.stats = {"error": str(e)}
+                    req.done = self.clock() - t0
+                    continue
                 self.time_admit += self.clock() - ta
                 active.append((req, handle, need))
                 used += need
@@ -148,16 +158,20 @@ class DeviceBackend:
         t0 = time.perf_counter()
         stream = torch.cuda.Stream(self.device)
         ctx = Context(self.device, stream)
-        t1 = time.perf_counter()
-        ctx.set_problem(problem)
-        t2 = time.perf_counter()
-        ctx.precompute(self.store)
-        if self.precond:
-            ctx.precompute_preconditioner()
-        t3 = time.perf_counter()
-        with torch.cuda.stream(stream):
-            x = torch.zeros(ctx.shape, dtype=torch.float64, device=f"cuda:{self.device}")
-        ctx.gmres_begin(x, **self.opts)
+        try:
+            t1 = time.perf_counter()
+            ctx.set_problem(problem)
+            t2 = time.perf_counter()
+            ctx.precompute(self.store)
+            if self.precond:
+                ctx.precompute_preconditioner()
+            t3 = time.perf_counter()
+            with torch.cuda.stream(stream):
+                x = torch.zeros(ctx.shape, dtype=torch.float64, device=f"cuda:{self.device}")
+            ctx.gmres_begin(x, **self.opts)
+        except Exception:
+            ctx.close()                   # what the failed admission allocated goes back at once
+            raise
         ready = torch.cuda.Event()
         ready.record(stream)
         t4 = time.perf_counter()

@@ -31,7 +31,7 @@ EXPORTED = ["trap_create", "trap_destroy", "trap_set_problem", "trap_precompute"
             "trap_gmres_step_batch", "trap_gmres_end", "trap_precompute_preconditioner",
             "trap_apply_preconditioner", "trap_apply_preconditioner_noalloc", "trap_preconditioner_tables", "trap_set_formal_scheme",
             "trap_formal_from_field", "trap_emergent_los", "trap_aar_solve", "trap_kernel_rows",
-            "trap_faddeeva", "trap_last_error"]
+            "trap_faddeeva", "trap_hip_notes", "trap_last_error"]
 STAGES = ["comoving", "contract_fp32", "r3", "angular", "backinterp", "formal", "kernel_rows",
           "contract_fp64"]
 
@@ -132,6 +132,7 @@ def load_library(path: str = LIB_PATH):
     lib.trap_emergent_los.argtypes = [vp, vp, _dp]
     lib.trap_kernel_rows.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp, _dp, _dp]
     lib.trap_faddeeva.argtypes = [ctypes.c_int, _dp, _dp, ctypes.c_int, _dp]
+    lib.trap_hip_notes.argtypes = [ctypes.POINTER(ctypes.c_longlong), ctypes.c_char_p, ctypes.c_size_t]
     lib.trap_last_error.restype = ctypes.c_char_p
     for name in EXPORTED:
         if name != "trap_last_error":
@@ -184,6 +185,16 @@ def footprint(prob, store_mask: int = 3) -> int:
     _check(lib.trap_footprint(ctypes.byref(_atom_desc(prob.atom)), ctypes.byref(d), store_mask,
                               ctypes.byref(out)))
     return int(out.value)
+
+
+def hip_notes():
+    """(count, latest record) of the HIP failures the library recorded outside
+    a call's own return (teardown calls, errors pending at an entry point)."""
+    lib = load_library()
+    n = ctypes.c_longlong()
+    buf = ctypes.create_string_buffer(512)
+    _check(lib.trap_hip_notes(ctypes.byref(n), buf, 512))
+    return n.value, buf.value.decode(errors="replace")
 
 
 def faddeeva(v, a, device: int = 0) -> np.ndarray:

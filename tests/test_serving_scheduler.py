@@ -90,3 +90,35 @@ def test_arrival_order_is_kept_and_latency_is_measured():
     assert adm == sorted(adm)
     for r in out:
         assert r.status == 0 and r.latency == r.done - r.arrival and r.latency > 0
+
+
+class FailingBackend(FakeBackend):
+    """Admission of requests marked 'bad' raises, as a set-up or precompute
+    error of the library does (an exception carrying the status code)."""
+
+    class Failure(RuntimeError):
+        def __init__(self, code):
+            super().__init__(f"admission failed with {code}")
+            self.code = code
+
+    def admit(self, p):
+        if p.get("bad"):
+            self.log.append(("fail", p["id"], self.clock()))
+            raise self.Failure(-1)
+        return super().admit(p)
+
+
+def test_an_admission_failure_ends_that_request_only():
+    clock = FakeClock()
+    be = FailingBackend(clock)
+    s = Scheduler(be, 100, 4, clock=clock, sleep=clock.sleep)
+    reqs = [Request(i, 0.0, {"id": i, "mem": 40, "steps": 2, "bad": i == 1}) for i in range(4)]
+    out = s.run(reqs)
+    bad = out[1]
+    assert bad.status == -1 and bad.done is not None and "admission failed" in bad.stats["error"]
+    assert all(r.status == 0 for r in out if r.rid != 1)
+    # its memory was never held: two requests fit the budget at a time, and the
+    # failed one did not delay the others
+    assert s.peak_used <= 100
+    assert [e[1] for e in be.log if e[0] == "admit"] == [0, 2, 3]
+    assert max(r.done for r in out) <= 4.0 + 1e-9
