@@ -179,15 +179,18 @@ def cpu_baseline(prob, n_applies: float):
             "seconds_measured": measured}
 
 
-SERVE_STREAM = dict(n_z_range=(40, 70), nu_choices=(51, 71, 101), angle_sets=[(8, 4), (8, 8)])
+# a bounded stream over the serving configuration's full ranges: N_z 40-100,
+# N_nu 31-301, N_dir 16-128, all four generators
+SERVE_STREAM = dict(n_z_range=(40, 100), nu_choices=tuple(range(31, 302, 30)),
+                    angle_sets=[(4, 4), (8, 4), (8, 8), (12, 8), (16, 8)])
 
 
 def serving_bench(n_requests: int, seed: int, precond_sweeps: int):
     """Continuous-batching serving of a bounded request stream (all four atom/grid
-    generators, N_z 40-70, N_nu 51-101, N_dir 32-64): saturated runs (all
-    requests at t = 0) in mixed precision and in plain FP64; the mixed one fixes
-    the arrival rate, then Poisson arrivals at 0.8 x that rate are served in
-    both precisions."""
+    generators over the full serving ranges): saturated runs (all requests at
+    t = 0) in mixed precision and in plain FP64, both to the same FP64 residual
+    tolerance; the mixed one fixes the arrival rate, then Poisson arrivals at
+    0.8 x that rate are served in both precisions."""
     from workloads import serving_stream
     from paper_2505_20968_amd.serving import Request, serve
     base = serving_stream(n_requests, seed=seed, rate_hz=1.0, **SERVE_STREAM)
@@ -200,18 +203,28 @@ def serving_bench(n_requests: int, seed: int, precond_sweeps: int):
                 "peak_active": res["peak_active"], "wall_s": res["wall_s"]}
 
     sat = serve([Request(i, 0.0, p) for i, (_, p) in enumerate(base)], "mixed", max_active=16, **solver)
+    _progress(f"serving: saturated mixed run done, {sat['solves_per_s']:.3f} solves/s")
     sat64 = serve([Request(i, 0.0, p) for i, (_, p) in enumerate(base)], "fp64", max_active=16, **solver)
+    _progress(f"serving: saturated FP64 run done, {sat64['solves_per_s']:.3f} solves/s")
     lam = 0.8 * sat["solves_per_s"]
     runs = {}
     for prec in ("mixed", "fp64"):
         reqs = [Request(i, t / lam, p) for i, (t, p) in enumerate(base)]
         runs[prec] = summary(serve(reqs, prec, max_active=16, **solver))
-    return {"requests": n_requests, "stream": "seeded mix of the four generators, N_z 40-70, N_nu 51-101, "
-                                              "N_dir 32-64, tol 1e-8",
+        _progress(f"serving: paced {prec} run done")
+    return {"requests": n_requests, "stream": "seeded mix of the four generators over the full serving ranges "
+                                              "(N_z 40-100, N_nu 31-301, N_dir 16-128), tol 1e-8; "
+                                              f"{n_requests} requests instead of 1024 to bound the run",
+            "sizes": [[p.n_z, p.n_nu, p.n_dir] for _, p in base],
             "saturated_solves_per_s": {"mixed": sat["solves_per_s"], "fp64": sat64["solves_per_s"]},
             "arrival_rate_hz": lam, "precond_sweeps": precond_sweeps,
             "mixed": runs["mixed"], "fp64": runs["fp64"],
             "mixed_over_fp64_throughput": runs["mixed"]["solves_per_s"] / max(runs["fp64"]["solves_per_s"], 1e-30)}
+
+
+def _progress(msg: str) -> None:
+    """One line on stderr per finished phase, so a long run shows where it is."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def main():
@@ -230,7 +243,7 @@ def main():
                     help="the same for the serving measurement (its requests are smaller and its host "
                          "loop issues every request's preconditioner launches, so fewer steps pay)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=16,
+    ap.add_argument("--serve-requests", type=int, default=12,
                     help="requests in the serving measurement (0 skips it)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="before the timed region, run one elementwise kernel over a known byte "
@@ -294,6 +307,7 @@ def main():
         del xs, ys
     for i in range(args.warmup):
         one_step(1000 + i)
+        _progress(f"warmup step {i} done")
     for v in phases.values():
         v.clear()
     torch.cuda.synchronize()
@@ -307,6 +321,7 @@ def main():
         torch.cuda.synchronize()
         lat.append(time.perf_counter() - ts)
         stats.append(st)
+        _progress(f"timed step {i} done: {lat[-1]:.2f} s, {st['inner_iters']} inner iterations")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     stage = ctx.stage_times()
@@ -328,6 +343,7 @@ def main():
                 "max_abs_QUV_over_I": float(max(np.abs(em[..., s] / em[..., 0] - ref[..., s] / ref[..., 0]).max()
                                                 for s in (1, 2, 3)))}
     accuracy["within_contract"] = accuracy["max_rel_I"] < 1e-6 and accuracy["max_abs_QUV_over_I"] < 1e-4
+    _progress(f"accuracy check done: {accuracy}")
     del xt
     xs = torch.rand(ctx.shape, dtype=torch.float32, device="cuda")
     ys = torch.empty_like(xs)
@@ -340,6 +356,7 @@ def main():
     ev1.record(ctx.stream)
     ev1.synchronize()
     sigma_ms = ev0.elapsed_time(ev1) / n_sig
+    _progress(f"Sigma apply timing done: {sigma_ms:.2f} ms")
     del xs, ys
     ctx.close()
 
@@ -402,7 +419,9 @@ def main():
         "accuracy": accuracy,
     }
     if args.serve_requests > 0:
+        torch.cuda.empty_cache()
         out["serving"] = serving_bench(args.serve_requests, seed=5, precond_sweeps=args.serve_precond_sweeps)
+        _progress("serving measurement done")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(last["prob"], n_applies)
     print(json.dumps(out))

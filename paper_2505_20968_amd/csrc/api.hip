@@ -47,6 +47,19 @@ std::mutex g_pool_mu;
 std::set<int> g_pool_ready, g_pool_absent;
 }  // namespace
 
+void device_pool_trim(int device) {
+  {
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    if (!g_pool_ready.count(device)) return;
+  }
+  hipMemPool_t pool;
+  if (hipDeviceGetDefaultMemPool(&pool, device) != hipSuccess) {
+    (void)hipGetLastError();
+    return;
+  }
+  TRAP_NOTE(hipMemPoolTrimTo(pool, 0));
+}
+
 void device_pool_setup(int device) {
   std::lock_guard<std::mutex> lk(g_pool_mu);
   if (g_pool_ready.count(device) || g_pool_absent.count(device)) return;
@@ -245,7 +258,12 @@ int trap_destroy(trap_ctx* ctx) {
   }
   if (ctx->ev_fork) TRAP_NOTE(hipEventDestroy(ctx->ev_fork));
   if (ctx->ev_join) TRAP_NOTE(hipEventDestroy(ctx->ev_join));
-  batch_arena_release(ctx->device);
+  if (batch_arena_release(ctx->device)) {
+    // the device's last context: the pool's memory goes back to the device,
+    // once the context's stream-ordered frees have run
+    TRAP_NOTE(hipStreamSynchronize(ctx->stream));
+    device_pool_trim(ctx->device);
+  }
   delete ctx;
   return TRAP_OK;
 }

@@ -1631,13 +1631,14 @@ void batch_arena_acquire(int device) {
   g_arena[device].users++;
 }
 
-void batch_arena_release(int device) {
+bool batch_arena_release(int device) {
   std::lock_guard<std::mutex> lk(g_arena_mu);
   auto it = g_arena.find(device);
-  if (it == g_arena.end()) return;
-  if (--it->second.users > 0) return;
+  if (it == g_arena.end()) return false;
+  if (--it->second.users > 0) return false;
   arena_free(it->second);
   g_arena.erase(it);
+  return true;
 }
 
 int stage_upload(trap_ctx* ctx, const void* host, size_t bytes, void* dev) {

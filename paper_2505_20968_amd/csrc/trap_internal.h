@@ -524,7 +524,10 @@ struct BatchArena {
   int users = 0;
 };
 void batch_arena_acquire(int device);
-void batch_arena_release(int device);
+// true when the device's last context released it
+bool batch_arena_release(int device);
+// return the device pool's unused memory to the device (no context left on it)
+void device_pool_trim(int device);
 // 1 when the context's FP32 operator can join a grouped apply (W allocated
 // for all heights at once), 0 when it cannot, < 0 on error
 int sigma_batch_ready(trap_ctx* ctx);
