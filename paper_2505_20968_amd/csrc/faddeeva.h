@@ -12,7 +12,11 @@
 //    by a direct discrete Fourier transform and copied to constant memory.
 //  * |z| >= 15: the Laplace continued fraction (Gautschi 1970; Jones, Thron &
 //    Waadeland 1981) w(z) = (i/sqrt(pi)) / (z - (1/2)/(z - 1/(z - (3/2)/(z - ...)))),
-//    evaluated bottom-up with 24 levels.
+//    evaluated bottom-up.  The depth falls with |z|: the truncation error
+//    of n levels shrinks roughly like (n / (2|z|^2))^n, so ten levels reach
+//    FP64 rounding at |z| = 15 and three beyond |z| ~ 3000.  The depth table
+//    below keeps one to two levels above the smallest depth that agrees with a
+//    40-level evaluation to rounding on both half-plane axes and in between.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -34,8 +38,10 @@ __host__ __device__ inline double2 faddeeva_w(double x, double y, const Faddeeva
   const double r2 = x * x + y * y;
   if (r2 >= 225.0) {
     // continued fraction, bottom-up: f_k = z - (k/2)/f_{k+1}
+    const int depth = r2 < 400.0 ? 10 : r2 < 900.0 ? 9 : r2 < 2500.0 ? 8 : r2 < 1e4 ? 7
+                    : r2 < 4e4 ? 6 : r2 < 2.5e5 ? 5 : r2 < 1e7 ? 4 : 3;
     double fr = x, fi = y;       // f = z
-    for (int k = 24; k >= 1; --k) {
+    for (int k = depth; k >= 1; --k) {
       // f = z - (k/2) / f
       const double d = fr * fr + fi * fi;
       const double c = 0.5 * k / d;
@@ -51,9 +57,9 @@ __host__ __device__ inline double2 faddeeva_w(double x, double y, const Faddeeva
   const double tr = C.L + y, ti = -x;
   // Z = (L + i z)/(L - i z); L + i z = (L - y) + i x
   const double nr = C.L - y, ni = x;
-  const double td = tr * tr + ti * ti;
-  const double Zr = (nr * tr + ni * ti) / td;
-  const double Zi = (ni * tr - nr * ti) / td;
+  const double itd = 1.0 / (tr * tr + ti * ti);
+  const double Zr = (nr * tr + ni * ti) * itd;
+  const double Zi = (ni * tr - nr * ti) * itd;
   double pr = C.a[0], pi = 0.0;
   for (int k = 1; k < kWeidemanN; ++k) {
     const double qr = pr * Zr - pi * Zi + C.a[k];
@@ -62,7 +68,7 @@ __host__ __device__ inline double2 faddeeva_w(double x, double y, const Faddeeva
     pi = qi;
   }
   // 1/t and 1/t^2
-  const double ir = tr / td, ii = -ti / td;
+  const double ir = tr * itd, ii = -ti * itd;
   const double i2r = ir * ir - ii * ii, i2i = 2.0 * ir * ii;
   const double wr = 2.0 * (pr * i2r - pi * i2i) + 0.56418958354775628695 * ir;
   const double wi = 2.0 * (pr * i2i + pi * i2r) + 0.56418958354775628695 * ii;

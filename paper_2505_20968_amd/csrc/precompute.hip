@@ -35,23 +35,41 @@ static constexpr double kPiD = 3.14159265358979323846;
 __device__ inline double2 wz(double x, double y) { return faddeeva_w(x, y, c_fad); }
 
 // F(Theta, up, u) in reduced units; pi_limit selects the Theta = pi form.
+// The per-row divisors are kept as reciprocals (an FP64 division costs about
+// ten vector instructions, a product one).
 struct FParams {
-  double sG, cG, inv_sinT, a;
+  double inv2sG;     // 1 / (2 sin(Theta/2))
+  double inv2cG;     // 1 / (2 cos(Theta/2))
+  double a_cG;       // a / cos(Theta/2)
+  double inv_sinT;   // 1 / sin(Theta)
+  double a;
   bool pi_limit;
 };
+
+__device__ inline FParams f_params(double Th, double a) {
+  FParams p;
+  p.pi_limit = (Th >= kPiD);
+  const double sG = p.pi_limit ? 1.0 : sin(0.5 * Th), cG = p.pi_limit ? 1.0 : cos(0.5 * Th);
+  p.inv2sG = 0.5 / sG;
+  p.inv2cG = 0.5 / cG;
+  p.a_cG = a / cG;
+  p.inv_sinT = p.pi_limit ? 0.0 : 1.0 / sin(Th);
+  p.a = a;
+  return p;
+}
 
 __device__ inline double2 Ffun(const FParams& p, double up, double u) {
   if (p.pi_limit) {
     const double g = exp(-0.25 * (u - up) * (u - up));
     // i / (2 sqrt(pi) (m + i a)) = i (m - i a) / (2 sqrt(pi) (m^2 + a^2))
     const double m = 0.5 * (u + up);
-    const double d = 2.0 * kSqrtPi * (m * m + p.a * p.a);
-    return make_double2(g * p.a / d, g * m / d);
+    const double r = g / (2.0 * kSqrtPi * (m * m + p.a * p.a));
+    return make_double2(r * p.a, r * m);
   }
-  const double q = (u - up) / (2.0 * p.sG);
+  const double q = (u - up) * p.inv2sG;
   const double g = exp(-q * q);
   if (g == 0.0) return make_double2(0.0, 0.0);
-  const double2 w = wz((u + up) / (2.0 * p.cG), p.a / p.cG);
+  const double2 w = wz((u + up) * p.inv2cG, p.a_cG);
   return make_double2(g * w.x * p.inv_sinT, g * w.y * p.inv_sinT);
 }
 
@@ -104,28 +122,13 @@ __global__ void k_profiles(int nz, int nd, int nn, int nt, const double* __restr
 }
 
 // ------------------------------------------------------------------ panel integration helper
-// Integrate f(x) * t^q (q = 0..nq-1, t = (x - x0)/h) over [pa, pb] with panels
-// graded away from xc.  Accumulates into acc[q] (complex).
+// Panels of the graded rule on [pa, pb]: swept away from the end nearest the
+// core xc (from xc outwards on both sides when it lies inside), each of width
+// min(Lg, max(wc, |x - xc|)); a remainder under a quarter of the next width
+// joins the last panel.  fn(l, r) is called per panel, in sweep order.
 template <typename Fn>
-__device__ void graded_integrate(double pa, double pb, double xc, double wc, double Lg, double x0,
-                                 double invh, int nq, Fn f, double2* acc) {
-  auto panel = [&](double l, double r) {
-    const double hw = r - l;
-    for (int i = 0; i < 16; ++i) {
-      const double xx = l + hw * c_gl_t[i];
-      const double2 v = f(xx);
-      const double ww = hw * c_gl_w[i];
-      double tp = ww;
-      const double t = (xx - x0) * invh;
-      for (int q = 0; q < nq; ++q) {
-        acc[q].x += tp * v.x;
-        acc[q].y += tp * v.y;
-        tp *= t;
-      }
-    }
-  };
+__device__ inline void graded_panels(double pa, double pb, double xc, double wc, double Lg, Fn fn) {
   auto sweep = [&](double start, double end) {
-    // from `start` (nearest the centre) towards `end`
     const double dir = end > start ? 1.0 : -1.0;
     double pos = start;
     int guard = 0;
@@ -134,7 +137,7 @@ __device__ void graded_integrate(double pa, double pb, double xc, double wc, dou
       double w = fmin(Lg, fmax(wc, dist));
       double nxt = pos + dir * w;
       if (dir * (end - nxt) < 0.25 * w) nxt = end;
-      panel(fmin(pos, nxt), fmax(pos, nxt));
+      fn(fmin(pos, nxt), fmax(pos, nxt));
       pos = nxt;
       ++guard;
     }
@@ -148,6 +151,36 @@ __device__ void graded_integrate(double pa, double pb, double xc, double wc, dou
   } else {
     sweep(pb, pa);
   }
+}
+
+// Integrate f(x) * t^q (q = 0..nq-1, t = (x - x0)/h) over [pa, pb] with
+// Gauss-Legendre 16 on the graded panels.  Accumulates into acc[q] (complex).
+template <typename Fn>
+__device__ void graded_integrate(double pa, double pb, double xc, double wc, double Lg, double x0,
+                                 double invh, int nq, Fn f, double2* acc) {
+  graded_panels(pa, pb, xc, wc, Lg, [&](double l, double r) {
+    const double hw = r - l;
+    for (int i = 0; i < 16; ++i) {
+      const double xx = l + hw * c_gl_t[i];
+      const double2 v = f(xx);
+      const double ww = hw * c_gl_w[i];
+      double tp = ww;
+      const double t = (xx - x0) * invh;
+      for (int q = 0; q < nq; ++q) {
+        acc[q].x += tp * v.x;
+        acc[q].y += tp * v.y;
+        tp *= t;
+      }
+    }
+  });
+}
+
+// Orders this wave's LDS writes before its later reads (the other waves of
+// the block are not waited for).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 __device__ inline int upper_interval(const double* x, int nn, double v) {
@@ -215,16 +248,24 @@ __global__ void k_kernel_tables(int z0, int nth, int nt, int nn, int ntail, doub
 }
 
 // ------------------------------------------------------------------ R_II kernel rows
-// One 64-thread block per complex row (z, theta, t, n) of a height chunk.
-// The integral of F against the spline piece on interval k is written with the
-// piece's node values v_k, v_{k+1} and second derivatives s_k, s_{k+1}:
+// One wave (a 64-thread block) per complex row (z, theta, t, n) of a height
+// chunk.  The integral of F against the spline piece on interval k is written
+// with the piece's node values v_k, v_{k+1} and second derivatives s_k, s_{k+1}:
 //   int F S = mu0 v_k + mu1 (v_{k+1} - v_k)
 //           + h^2 (-mu1/3 + mu2/2 - mu3/6) s_k + h^2 (mu3 - mu1)/6 s_{k+1},
 // mu_q = int_0^1 F t^q.  Collecting per node gives the row as
 //   M[n][m] = L[m] + sum_j Gam[j] Sig[j][m]
 // with Sig = d s / d v the spline's second-derivative map; L and Gam are
-// written here, the dense product is one batched GEMM (k_sig_gemm).
-constexpr int kRowWavesMax = 2;       // rows (one per wave) per block of the kernel-row precompute
+// accumulated per node in LDS and written here, the product with Sig is one
+// batched GEMM (k_sig_gemm, k_sig_gemm_tiles).
+constexpr int kPanelCap = 64;         // graded panels listed per window of one row
+
+// LDS of one row: node accumulators L[nn], Gam[nn] (complex), then one window
+// of the graded panel list: {left, width}, {t at left, t span} and the knot
+// interval of each panel (-1 and nn - 1 for the tails).
+__host__ __device__ constexpr size_t kernel_row_lds(int nn) {
+  return ((size_t)nn * 2 + 2 * kPanelCap) * sizeof(double2) + kPanelCap * sizeof(int);
+}
 
 // Mirror roles of the transitions' kernel rows (Problem::row_role), by value.
 constexpr int kMaxRoles = 128;
@@ -240,32 +281,62 @@ __device__ __forceinline__ bool row_mirrored(const RowRoles& R, int t, int n, in
   return r >= 0 && (r != t || n > nn - 1 - n);
 }
 
-// The kernel is latency bound; a register cap for three waves per SIMD (a few
-// bytes of spill) measured faster than the uncapped two or a four-wave cap.
-__global__ void __launch_bounds__(64 * kRowWavesMax, 3) k_kernel_rows(
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+  return v;
+}
+
+// Moments mu_q of knot interval k (or the zeroth moment of a tail, k = -1 or
+// nn - 1) into the node accumulators, by the collection formula above.
+__device__ __forceinline__ void add_moments(double2* Lacc, double2* Gacc, const double* __restrict__ x, int nn,
+                                            int k, const double2* mu) {
+  if (k < 0 || k >= nn - 1) {
+    const int m = k < 0 ? 0 : nn - 1;
+    atomicAdd(&Lacc[m].x, mu[0].x);
+    atomicAdd(&Lacc[m].y, mu[0].y);
+    return;
+  }
+  const double h = x[k + 1] - x[k], hh = h * h;
+  atomicAdd(&Lacc[k].x, mu[0].x - mu[1].x);
+  atomicAdd(&Lacc[k].y, mu[0].y - mu[1].y);
+  atomicAdd(&Lacc[k + 1].x, mu[1].x);
+  atomicAdd(&Lacc[k + 1].y, mu[1].y);
+  atomicAdd(&Gacc[k].x, hh * (-mu[1].x * (1.0 / 3.0) + 0.5 * mu[2].x - mu[3].x * (1.0 / 6.0)));
+  atomicAdd(&Gacc[k].y, hh * (-mu[1].y * (1.0 / 3.0) + 0.5 * mu[2].y - mu[3].y * (1.0 / 6.0)));
+  atomicAdd(&Gacc[k + 1].x, hh * (mu[3].x - mu[1].x) * (1.0 / 6.0));
+  atomicAdd(&Gacc[k + 1].y, hh * (mu[3].y - mu[1].y) * (1.0 / 6.0));
+}
+
+// Latency bound: occupancy is what counts.  Three waves per SIMD fit the
+// registers without spills, and the LDS of one row (about 14 KB at 301
+// frequencies) lets eleven rows share a compute unit.
+__global__ void __launch_bounds__(64, 3) k_kernel_rows(
     long long nrows, int nth, int nt, int nn, int ldm, const double* __restrict__ x,
     const double* __restrict__ lam, const double* __restrict__ av, const double* __restrict__ st,
     const double* __restrict__ theta, double* __restrict__ Lout, double* __restrict__ Gout,
     long long row0, int z0, double h_uniform, const double* __restrict__ Gt,
     const double2* __restrict__ Vt, int ntail, RowRoles roles) {
-  extern __shared__ double2 smem[];    // per wave: [(nn+1)][4], piece index shifted by one
-  __shared__ double2 tred[kRowWavesMax][2][64];
-  const int waves = blockDim.x >> 6;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  double2* mom = smem + (size_t)wave * (nn + 1) * 4;
-  const long long rl = (long long)blockIdx.x * waves + wave;     // row within this launch
-  bool live = rl < nrows;
-  const long long row = row0 + (live ? rl : 0);
+  extern __shared__ double2 smem[];    // kernel_row_lds(nn) bytes
+  const int lane = threadIdx.x;
+  double2* Lacc = smem;
+  double2* Gacc = smem + nn;
+  double2* plw = Gacc + nn;                      // graded panels: {left, width}
+  double2* pts = plw + kPanelCap;                // {t at left, t span} in the piece's knot interval
+  int* pk = (int*)(pts + kPanelCap);             // knot interval of the panel
+  const long long rl = blockIdx.x;               // row within this launch
+  if (rl >= nrows) return;
+  const long long row = row0 + rl;
   const int n = row % nn;
   const int t = (row / nn) % nt;
   const int th = (row / ((long long)nn * nt)) % nth;
   const int z = z0 + (int)(row / ((long long)nn * nt * nth));
-  if (row_mirrored(roles, t, n, nn)) live = false;               // filled by k_mirror_rows
+  if (row_mirrored(roles, t, n, nn)) return;                    // filled by k_mirror_rows
   const double L = lam[z], a = av[z], s = st[z * nt + t], Th = theta[th];
   // chunk-local row index of the real plane; the imaginary plane follows nn rows later
   const size_t cbase = (size_t)((((size_t)(z - z0) * nth + th) * nt + t) * 2) * nn * ldm;
   const size_t rre = cbase + (size_t)n * ldm, rim = cbase + (size_t)nn * ldm + (size_t)n * ldm;
-  if (live && Th == 0.0) {
+  if (Th == 0.0) {
     const double2 w = wz(L * x[n] + s, a);
     for (int m = lane; m < ldm; m += 64) {
       Lout[rre + m] = (m == n) ? kSqrtPi * w.x : 0.0;
@@ -273,24 +344,18 @@ __global__ void __launch_bounds__(64 * kRowWavesMax, 3) k_kernel_rows(
       Gout[rre + m] = 0.0;
       Gout[rim + m] = 0.0;
     }
+    return;
   }
-  // every wave of the block reaches the barriers below; only `work` rows integrate
-  const bool work = live && Th != 0.0;
-  FParams fp;
-  fp.pi_limit = (Th >= kPiD);
-  fp.sG = fp.pi_limit ? 1.0 : sin(0.5 * Th);
-  fp.cG = fp.pi_limit ? 0.0 : cos(0.5 * Th);
-  fp.inv_sinT = fp.pi_limit ? 0.0 : 1.0 / sin(Th);
-  fp.a = a;
-  const double sigma = 2.0 * fp.sG / L;
+  const FParams fp = f_params(Th, a);
+  const double sigma = 2.0 * sin(0.5 * fmin(Th, kPiD)) / L;
   const double R = 6.6 * sigma;
   const double xn = x[n];
   const double lo = xn - R, hi = xn + R;
   const double xc = -xn - 2.0 * s / L;
-  const double wc = 2.0 * fmax(fp.cG, a) / L;
+  const double wc = 2.0 * fmax(fp.pi_limit ? 0.0 : cos(0.5 * Th), a) / L;
   const double Lg = 1.5 * sigma;
-  for (int i = lane; i < (nn + 1) * 4; i += 64) mom[i] = make_double2(0.0, 0.0);
-  __syncthreads();
+  for (int i = lane; i < 2 * nn; i += 64) Lacc[i] = make_double2(0.0, 0.0);
+  wave_sync();
   // pieces: -1 left tail, 0..nn-2 knot intervals, nn-1 right tail
   int plo = upper_interval(x, nn, lo);          // -1 if lo < x0
   int phi = upper_interval(x, nn, hi);
@@ -311,11 +376,15 @@ __global__ void __launch_bounds__(64 * kRowWavesMax, 3) k_kernel_rows(
   // Graded region: where the 16-node rule per interval does not resolve F --
   // the whole support when the Gaussian is narrower than half an interval or
   // the grid is not uniform, else the intervals next to a sharp Voigt core.
-  // It is split into 64 equal pieces, one per lane; each lane integrates its
-  // piece with panels graded towards the core, interval by interval, and adds
-  // the moments into LDS.  Every other interval of the support takes the
-  // table rule, one lane per interval (virtual intervals of width h past the
-  // grid ends for the tails, where the spline is extended flat).
+  // Its pieces (knot intervals, and the tails past the grid ends) are cut
+  // into panels graded towards the core; the row's panel list is built in
+  // LDS (a lane per piece, offsets from a prefix sum over the wave) and its
+  // (panel, node) pairs are spread over the lanes, sixteen lanes per panel,
+  // so the work per lane follows the row's panel count and not the number of
+  // pieces a lane's share of the support happens to cross.  Every other
+  // interval of the support takes the table rule, one lane per interval
+  // (virtual intervals of width h past the grid ends for the tails, where the
+  // spline is extended flat).
   const double x0 = x[0];
   auto xk = [&](int k) { return (k >= 0 && k < nn) ? x[k] : x0 + h_uniform * k; };
   const int kmin = fast ? (int)floor((lo - x0) / h_uniform) : 0;
@@ -326,32 +395,30 @@ __global__ void __launch_bounds__(64 * kRowWavesMax, 3) k_kernel_rows(
   bool graded = false;
   int kA = 1, kB = 0;                  // table-rule intervals skip [kA, kB]
   double ga = 0.0, gb = 0.0;
-  if (work) {
-    if (!fast || !tail_tab) {
-      graded = true;
-      ga = lo;
-      gb = hi;
-      kA = -(1 << 30);
-      kB = 1 << 30;
-    } else if (sharp) {
-      const int kc = (int)floor((xc - x0) / h_uniform);
-      kA = 1 << 30;
-      kB = -(1 << 30);
-      for (int k = kc - 3; k <= kc + 2; ++k)
-        if (k >= kmin && k <= kmax && near_core(k)) {
-          kA = min(kA, k);
-          kB = max(kB, k);
-        }
-      if (kA <= kB) {
-        graded = true;
-        ga = fmax(xk(kA), lo);
-        gb = fmin(xk(kB + 1), hi);
+  if (!fast || !tail_tab) {
+    graded = true;
+    ga = lo;
+    gb = hi;
+    kA = -(1 << 30);
+    kB = 1 << 30;
+  } else if (sharp) {
+    const int kc = (int)floor((xc - x0) / h_uniform);
+    kA = 1 << 30;
+    kB = -(1 << 30);
+    for (int k = kc - 3; k <= kc + 2; ++k)
+      if (k >= kmin && k <= kmax && near_core(k)) {
+        kA = min(kA, k);
+        kB = max(kB, k);
       }
+    if (kA <= kB) {
+      graded = true;
+      ga = fmax(xk(kA), lo);
+      gb = fmin(xk(kB + 1), hi);
     }
   }
   // table rule: knot intervals inside the support, one lane per interval
   const int ilo = max(plo, 0), ihi = min(phi, nn - 2);
-  for (int p = ilo + lane; work && fast && p <= ihi; p += 64) {
+  for (int p = ilo + lane; fast && p <= ihi; p += 64) {
     if (p >= kA && p <= kB) continue;
     double2 acc[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
     const double* g = Grow + (size_t)(g_off - p) * 16;
@@ -367,116 +434,124 @@ __global__ void __launch_bounds__(64 * kRowWavesMax, 3) k_kernel_rows(
         tp *= ti;
       }
     }
-    for (int q = 0; q < 4; ++q) mom[(p + 1) * 4 + q] = acc[q];
+    add_moments(Lacc, Gacc, x, nn, p, acc);
   }
-  // graded pieces: moments of knot intervals into mom[k + 1], tails (q = 0)
-  // into mom[0] and mom[nn]
+  // graded pieces (the region is per row, so every branch here is uniform
+  // over the wave)
   if (graded && gb > ga) {
-    const double wpiece = (gb - ga) / 64.0;
-    const double pe = (lane == 63) ? gb : ga + wpiece * (lane + 1);
-    double pa = ga + wpiece * lane;
-    int guard = 0;
-    while (pa < pe && guard < 2 * nn + 4) {
-      ++guard;
-      const int k = upper_interval(x, nn, pa);       // -1: left of the grid, nn - 1: right
-      double pb;
-      int slot, nq;
-      double xl, invh;
-      if (k < 0) {
-        pb = fmin(pe, x0);
-        slot = 0;
-        nq = 1;
-        xl = 0.0;
-        invh = 0.0;
-      } else if (k >= nn - 1) {
-        pb = pe;
-        slot = nn * 4;
-        nq = 1;
-        xl = 0.0;
-        invh = 0.0;
-      } else {
-        pb = fmin(pe, x[k + 1]);
-        slot = (k + 1) * 4;
-        nq = 4;
-        xl = x[k];
-        invh = 1.0 / (x[k + 1] - x[k]);
+    const int gA = upper_interval(x, nn, ga);        // -1: left tail, nn - 1: right tail
+    const int gB = upper_interval(x, nn, gb);
+    const int npc = gB - gA + 1;
+    // piece k: its clipped range and the map to t of its knot interval
+    auto piece = [&](int k, double& pa, double& pb, double& xl, double& invh) {
+      pa = (k < 0) ? ga : fmax(ga, x[k]);
+      pb = (k >= nn - 1) ? gb : fmin(gb, x[k + 1]);
+      const bool inner = k >= 0 && k < nn - 1;
+      xl = inner ? x[k] : 0.0;
+      invh = inner ? 1.0 / (x[k + 1] - x[k]) : 0.0;
+    };
+    int mine = 0;                                    // this lane's panel count
+    for (int j = lane; j < npc; j += 64) {
+      double pa, pb, xl, invh;
+      piece(gA + j, pa, pb, xl, invh);
+      graded_panels(pa, pb, xc, wc, Lg, [&](double, double) { ++mine; });
+    }
+    int off = mine;                                  // inclusive prefix over lanes
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int v = __shfl_up(off, d, 64);
+      if (lane >= d) off += v;
+    }
+    const int total = __shfl(off, 63, 64);
+    off -= mine;
+    const int g = lane >> 4, i = lane & 15;
+    const double tg = c_gl_t[i], wg = c_gl_w[i];
+    for (int w0 = 0; w0 < total; w0 += kPanelCap) {
+      const int w1 = min(total, w0 + kPanelCap);
+      // this window's panels into LDS
+      int e = off;
+      for (int j = lane; j < npc && e < w1; j += 64) {
+        double pa, pb, xl, invh;
+        piece(gA + j, pa, pb, xl, invh);
+        graded_panels(pa, pb, xc, wc, Lg, [&](double l, double r) {
+          if (e >= w0 && e < w1) {
+            plw[e - w0] = make_double2(l, r - l);
+            pts[e - w0] = make_double2((l - xl) * invh, (r - l) * invh);
+            pk[e - w0] = gA + j;
+          }
+          ++e;
+        });
       }
-      if (pb > pa) {
-        // four moments always (constant trip counts keep acc in registers);
-        // a tail has invh = 0 and uses the zeroth only
-        double2 acc[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
-        graded_integrate(pa, pb, xc, wc, Lg, xl, invh, 4, integrand, acc);
+      wave_sync();
+      // node i of panels g, g + 4, ...: moments summed in registers while the
+      // interval stays the same, then over the sixteen lanes of the panel and
+      // into the node accumulators
+      double2 acc[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+      int cur = -2;
+      const int np = w1 - w0;
+      auto flush = [&]() {
 #pragma unroll
         for (int q = 0; q < 4; ++q)
-          if (q < nq) {
-            atomicAdd(&mom[slot + q].x, acc[q].x);
-            atomicAdd(&mom[slot + q].y, acc[q].y);
+#pragma unroll
+          for (int d = 8; d >= 1; d >>= 1) {
+            acc[q].x += __shfl_xor(acc[q].x, d, 16);
+            acc[q].y += __shfl_xor(acc[q].y, d, 16);
           }
-      }
-      pa = fmax(pb, pa);
-      if (pb <= pa && k >= nn - 1) break;
-    }
-  }
-  // table rule on the tails: virtual intervals past the ends, reduced over lanes
-  for (int side = 0; side < 2; ++side) {
-    const bool present = work && tail_tab && (side == 0 ? (plo < 0) : (phi >= nn - 1));
-    double2 acc = make_double2(0.0, 0.0);
-    if (present) {
-      const int ka = side == 0 ? kmin : nn - 1, kb = side == 0 ? -1 : kmax;
-      for (int k = ka + lane; k <= kb; k += 64) {
-        if (k >= kA && k <= kB) continue;
-        const double* g = Grow + (size_t)(g_off - k) * 16;
-        const double2* v = Vrow + (size_t)(v_off + k) * 16;
-        for (int i = 0; i < 16; ++i) {
-          const double f = fscale * c_gl_w[i] * g[i];
-          const double2 vv = v[i];
-          acc.x += f * vv.x;
-          acc.y += f * vv.y;
+        if (i == 0) add_moments(Lacc, Gacc, x, nn, cur, acc);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[q] = make_double2(0.0, 0.0);
+      };
+      for (int pb0 = 0; pb0 < np; pb0 += 4) {
+        const int pi = pb0 + g;
+        const int k = pi < np ? pk[pi] : -2;
+        if (cur != -2 && k != cur) flush();         // uniform over the sixteen lanes of group g
+        cur = k;
+        if (pi < np) {
+          const double2 lw = plw[pi], tt = pts[pi];
+          const double2 v = integrand(lw.x + lw.y * tg);
+          double tp = lw.y * wg;
+          const double tq = tt.x + tt.y * tg;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            acc[q].x += tp * v.x;
+            acc[q].y += tp * v.y;
+            tp *= tq;
+          }
         }
       }
+      if (cur != -2) flush();
+      wave_sync();                                   // the list is rewritten by the next window
     }
-    tred[wave][side][lane] = acc;
   }
-  __syncthreads();
-  if (work && lane < 2) {
-    double2 tot = make_double2(0.0, 0.0);
-    for (int i = 0; i < 64; ++i) {
-      tot.x += tred[wave][lane][i].x;
-      tot.y += tred[wave][lane][i].y;
+  // table rule on the tails: virtual intervals past the ends, summed over the wave
+  for (int side = 0; side < 2; ++side) {
+    const bool present = tail_tab && (side == 0 ? (plo < 0) : (phi >= nn - 1));
+    if (!present) continue;
+    double2 acc = make_double2(0.0, 0.0);
+    const int ka = side == 0 ? kmin : nn - 1, kb = side == 0 ? -1 : kmax;
+    for (int k = ka + lane; k <= kb; k += 64) {
+      if (k >= kA && k <= kB) continue;
+      const double* gg = Grow + (size_t)(g_off - k) * 16;
+      const double2* v = Vrow + (size_t)(v_off + k) * 16;
+      for (int i = 0; i < 16; ++i) {
+        const double f = fscale * c_gl_w[i] * gg[i];
+        const double2 vv = v[i];
+        acc.x += f * vv.x;
+        acc.y += f * vv.y;
+      }
     }
-    const int slot = (lane == 0 ? 0 : nn) * 4;
-    mom[slot].x += tot.x;
-    mom[slot].y += tot.y;
+    acc.x = wave_sum(acc.x);
+    acc.y = wave_sum(acc.y);
+    if (lane == 0) add_moments(Lacc, Gacc, x, nn, side == 0 ? -1 : nn - 1, &acc);
   }
-  __syncthreads();
-  // per node m: L[m] = (mu0 - mu1)_m + (mu1)_{m-1} (+ tails), Gam[m] = g_m + e_{m-1}
-  for (int m = lane; work && m < ldm; m += 64) {
-    double lr = 0.0, li = 0.0, gr = 0.0, gi = 0.0;
-    if (m < nn) {
-      if (m <= nn - 2) {          // interval m starts at node m
-        const double2 m0 = mom[(m + 1) * 4 + 0], m1 = mom[(m + 1) * 4 + 1];
-        const double2 m2 = mom[(m + 1) * 4 + 2], m3 = mom[(m + 1) * 4 + 3];
-        const double hh = (x[m + 1] - x[m]) * (x[m + 1] - x[m]);
-        lr += m0.x - m1.x;
-        li += m0.y - m1.y;
-        gr += hh * (-m1.x / 3.0 + 0.5 * m2.x - m3.x / 6.0);
-        gi += hh * (-m1.y / 3.0 + 0.5 * m2.y - m3.y / 6.0);
-      }
-      if (m >= 1) {               // interval m-1 ends at node m
-        const double2 m1 = mom[m * 4 + 1], m3 = mom[m * 4 + 3];
-        const double hh = (x[m] - x[m - 1]) * (x[m] - x[m - 1]);
-        lr += m1.x;
-        li += m1.y;
-        gr += hh * (m3.x - m1.x) / 6.0;
-        gi += hh * (m3.y - m1.y) / 6.0;
-      }
-      if (m == 0) { lr += mom[0].x; li += mom[0].y; }
-      if (m == nn - 1) { lr += mom[nn * 4].x; li += mom[nn * 4].y; }
-    }
-    Lout[rre + m] = lr;
-    Lout[rim + m] = li;
-    Gout[rre + m] = gr;
-    Gout[rim + m] = gi;
+  wave_sync();
+  for (int m = lane; m < ldm; m += 64) {
+    const double2 lv = m < nn ? Lacc[m] : make_double2(0.0, 0.0);
+    const double2 gv = m < nn ? Gacc[m] : make_double2(0.0, 0.0);
+    Lout[rre + m] = lv.x;
+    Lout[rim + m] = lv.y;
+    Gout[rre + m] = gv.x;
+    Gout[rim + m] = gv.y;
   }
 }
 
@@ -1200,11 +1275,8 @@ int run_precompute(trap_ctx* ctx, int store_mask) {
   bo.nn = nn;
   bo.nq = P.nq;
   bo.pad = P.qpad;
-  const size_t lds = (size_t)(nn + 1) * 4 * sizeof(double2);
+  const size_t lds = kernel_row_lds(nn);
   if (lds > 64 * 1024) return fail(TRAP_EINVAL, "frequency grid too large for the kernel precompute");
-  // rows per block of k_kernel_rows: two when their moments and lane partial
-  // sums fit in 64 KB
-  const int rw = (int)std::max<size_t>(1, std::min<size_t>(kRowWavesMax, (56 * 1024) / lds));
   // uniform grid -> factor tables, heights in chunks so the tables stay cache sized
   const PrecompLayout lay = precomp_layout(nz, nn, P.ldm, nt, nthr, aa, P.x.data(), P.lam.data());
   const bool uniform = lay.uniform;
@@ -1239,7 +1311,7 @@ int run_precompute(trap_ctx* ctx, int store_mask) {
     const long long chunk = 1 << 22;
     for (long long r0 = 0; r0 < nrows; r0 += chunk) {
       const long long nr = std::min(chunk, nrows - r0);
-      hipLaunchKernelGGL(k_kernel_rows, dim3((unsigned)ceil_div(nr, rw)), dim3(64 * rw), rw * lds, s, nr, nthr, nt,
+      hipLaunchKernelGGL(k_kernel_rows, dim3((unsigned)nr), dim3(64), lds, s, nr, nthr, nt,
                          nn, P.ldm, P.d_x,
                          P.d_lam, P.d_a, P.d_st, P.d_theta_rows, C.d_Lrow, C.d_Grow, r0, z0, h,
                          uniform ? C.d_Gt : nullptr, uniform ? C.d_Vt : nullptr, ntail, roles);
@@ -1271,7 +1343,8 @@ int run_precompute(trap_ctx* ctx, int store_mask) {
     }
   }
   prof_end(ctx, pr);
-  hipLaunchKernelGGL(k_r3_rows, dim3(nz * nt), dim3(64), lds, s, nt, nn, P.d_x, P.d_P, P.d_lam, P.d_a,
+  hipLaunchKernelGGL(k_r3_rows, dim3(nz * nt), dim3(64), (size_t)(nn + 1) * 4 * sizeof(double2), s, nt, nn, P.d_x,
+                     P.d_P, P.d_lam, P.d_a,
                      P.d_st, C.d_r3, C.d_prof);
   TRAP_HIP(hipGetLastError());
   {
@@ -1523,7 +1596,8 @@ static int precompute_precond_body(trap_ctx* ctx) {
   TRAP_TRY(dalloc_t(ctx, &Lrow, (size_t)zc_max * rows_per_z * ldm));
   TRAP_TRY(dalloc_t(ctx, &Grow, (size_t)zc_max * rows_per_z * ldm));
   TRAP_TRY(dalloc_t(ctx, &Mtmp, (size_t)zc_max * rows_per_z * ldm));
-  const int rw = (int)std::max<size_t>(1, std::min<size_t>(kRowWavesMax, (56 * 1024) / lds_row));
+  const size_t lds_kr = kernel_row_lds(nn);
+  if (lds_kr > 64 * 1024) return fail(TRAP_EINVAL, "frequency grid too large for the kernel precompute");
   const long long per_z_out = (long long)nk * 2 * nn * ldm;
   for (int z0 = 0; z0 < nz; z0 += zc_max) {
     const int zc = std::min(zc_max, nz - z0);
@@ -1533,7 +1607,7 @@ static int precompute_precond_body(trap_ctx* ctx) {
       TRAP_HIP(hipGetLastError());
     }
     const long long nrows = (long long)zc * ng * nk * nn;
-    hipLaunchKernelGGL(k_kernel_rows, dim3((unsigned)ceil_div(nrows, rw)), dim3(64 * rw), rw * lds_row, s, nrows, ng,
+    hipLaunchKernelGGL(k_kernel_rows, dim3((unsigned)nrows), dim3(64), lds_kr, s, nrows, ng,
                        nk, nn, ldm, P.d_x, P.d_lam, P.d_a, C.d_pcSt, C.d_pcTheta, Lrow, Grow, 0LL, z0, lay.h,
                        lay.uniform ? Gt : nullptr, lay.uniform ? Vt : nullptr, lay.ntail, RowRoles{});
     TRAP_HIP(hipGetLastError());

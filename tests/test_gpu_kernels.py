@@ -41,6 +41,30 @@ def test_device_faddeeva_matches_wofz():
     assert rel.max() < 1e-13
 
 
+def test_device_faddeeva_far_out_matches_wofz():
+    """The continued-fraction branch (|z| >= 15) with its |z|-dependent depth:
+    random points of the upper half plane out to |z| = 1e7, a third of them
+    within 1e-4 rad of the real axis and some on it, plus every depth band's
+    edges."""
+    _torch()
+    from paper_2505_20968_amd import faddeeva
+    rng = np.random.default_rng(11)
+    n = 200_000
+    r = np.exp(rng.uniform(np.log(15.0), np.log(1e7), n))
+    edges = np.sqrt(np.array([225.0, 400.0, 900.0, 2500.0, 1e4, 4e4, 2.5e5, 1e7]))
+    r[: 4 * edges.size] = np.repeat(edges, 4) * np.tile([1 - 1e-12, 1.0, 1 + 1e-12, 1.001], edges.size)
+    ang = np.where(rng.uniform(size=n) < 0.35, rng.uniform(0.0, 1e-4, n), rng.uniform(0.0, np.pi, n))
+    ang = np.where(rng.uniform(size=n) < 0.5, ang, np.pi - ang)
+    ang[:500] = np.where(np.arange(500) % 2 == 0, 0.0, np.pi)
+    X, Y = r * np.cos(ang), np.maximum(r * np.sin(ang), 0.0)
+    got = faddeeva(X, Y)
+    ref = wofz(X + 1j * Y)
+    rel = np.abs(got - ref) / np.abs(ref)
+    i = int(np.argmax(rel))
+    print(f"[faddeeva far] max rel {rel.max():.2e} at x={X[i]:.6g}, y={Y[i]:.3g}", flush=True)
+    assert rel.max() < 1e-13
+
+
 def _kernel_case(prob, z, th_idx):
     torch = _torch()
     from paper_2505_20968_amd import Context
