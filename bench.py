@@ -9,7 +9,7 @@ N_nu = 301 on a sinh grid to +-1000 Doppler widths, 8+8 Gauss-Legendre mu x
 One step = one whole pass of the method on a fresh seeded atmosphere:
 per-height setup, device precompute (R_II kernels by product integration into
 the banded store, R_III weights, propagation matrix, normalisation,
-right-hand side), the tables of the physics-based preconditioner (Sect. 5.3,
+right-hand side), the tables of the physics-based preconditioner (Sect. 5.2,
 App. F) and the left-preconditioned GMRES solve to tolerance (mixed
 precision: FP32 inner operator, FP64 Arnoldi, residual and iterative
 refinement; or plain FP64 with --precision fp64; --precond-sweeps 0 solves

@@ -4,14 +4,14 @@
  * polarisation signals of strong resonance lines with partial frequency
  * redistribution".
  *
- * The problem is the linear system (Sect. 2.6, Eq. linear_system)
+ * The problem is the linear system (Sect. 2.7, Eq. linear_system)
  *     (Id - Lambda Sigma) I = Lambda eps_th + t,
  * with Sigma the scattering operator (Eq. eps_sc_l with R = R_II + R_III,
  * Eqs. RQIIKKp, G and RIIIQKKp, evaluated in the comoving frame of Sect. 4.1
  * through the intermediate W of App. D, normalised as in App. E) and Lambda the
  * formal solution (Sect. 3, ray sweeps: DELO-linear, DELOPAR or BESSER).  It
  * is solved by mixed-precision GMRES (Sect. 5.1), optionally with the
- * physics-based preconditioner of Sect. 5.3 and App. F, or by alternating
+ * physics-based preconditioner of Sect. 5.2 and App. F, or by alternating
  * Anderson-Richardson iteration (the only choice with BESSER).
  *
  * Conventions shared by every entry point
@@ -204,7 +204,7 @@ int trap_set_problem(trap_ctx* ctx, const trap_atom_desc* atom, const trap_probl
  * ordered after it. */
 int trap_precompute(trap_ctx* ctx, int store_mask);
 
-/* Physics-based preconditioner (Sect. 5.3) with the block-diagonal local
+/* Physics-based preconditioner (Sect. 5.2) with the block-diagonal local
  * inverse of App. F.  P = Id - Lambda* Sigma* in the unmagnetised,
  * unpolarised, angle-averaged setting, multipole K = Q = 0: Sigma* maps Stokes
  * I to a Stokes-I emissivity through the comoving interpolation per
@@ -268,7 +268,7 @@ int trap_formal_solve(trap_ctx* ctx, const void* eps, void* I, int with_boundary
  * current points whose control point follows the tangent at the current point
  * of the parabola through the three points (slope zero at a local extremum)
  * and is kept inside the range of the two end values, per Stokes component;
- * K'I linear.  The range limit makes Lambda slightly nonlinear (Sect. 6.1), so
+ * K'I linear.  The range limit makes Lambda slightly nonlinear (Sect. 6.2), so
  * a BESSER problem is solved by trap_aar_solve (GMRES returns TRAP_EINVAL).
  * In both three-point schemes a ray's last point takes the DELO-linear step.
  * Applies to trap_formal_solve, the operator, the right-hand side and
@@ -406,7 +406,7 @@ int trap_footprint(const trap_atom_desc* atom, const trap_problem_desc* prob, in
  * height; TRAP_ESTATE before trap_precompute, TRAP_EINVAL for indices out of
  * range.  Synchronises.
  * trap_faddeeva evaluates the library's device Faddeeva function
- * W(a, v) = w(v + i a) (Sect. 2.3; Weideman's rational expansion, a continued
+ * W(a, v) = w(v + i a) (Sect. 2.4; Weideman's rational expansion, a continued
  * fraction far out) at n points (v[i], a[i]), a >= 0, into out [n][2] (real,
  * imaginary); host arrays; allocates and frees device scratch; synchronises
  * the device. */

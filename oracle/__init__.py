@@ -8,7 +8,7 @@ library; only the seeded problem descriptions in ``workloads`` serve both.
 It follows Riva et al., "A numerical approach for modelling the polarisation
 signals of strong resonance lines with partial frequency redistribution":
 
-* the linear system (Id - Lambda Sigma) I = Lambda eps_th + t  (Sect. 2.6,
+* the linear system (Id - Lambda Sigma) I = Lambda eps_th + t  (Sect. 2.7,
   Eq. linear_system), solved by dense LU on tiny grids or FP64 GMRES;
 * Sigma: the scattering integral (Eq. eps_sc_l) with R = R_II + R_III
   (Eqs. RQIIKKp, G, RIIIQKKp), evaluated in the comoving frame (Sect. 4.1,

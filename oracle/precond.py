@@ -1,11 +1,11 @@
-"""Physics-based preconditioner (Sect. 5.3) with the block-diagonal
+"""Physics-based preconditioner (Sect. 5.2) with the block-diagonal
 preconditioner of App. F (oracle, FP64).
 
 TEST INFRASTRUCTURE ONLY, like the rest of this package.
 
 Left preconditioning replaces (Id - Lambda Sigma) I = b by
 M (Id - Lambda Sigma) I = M b with M ~ P^-1 and P = Id - Lambda* Sigma*, the
-operator of a simplified physical setting (Sect. 5.3).  The setting taken
+operator of a simplified physical setting (Sect. 5.2).  The setting taken
 here is the one App. F builds its local blocks from:
 
 * Sigma*: unmagnetised, unpolarised, angle-averaged R_II (Eq. R_AA) plus

@@ -1,9 +1,9 @@
 """Redistribution functions and their frequency integrals (oracle).
 
-* Faddeeva function W(a, v) = w(v + i a) (reading of Sect. 2.3: Re W is the
+* Faddeeva function W(a, v) = w(v + i a) (reading of Sect. 2.4: Re W is the
   Voigt function H with integral sqrt(pi), which makes the Theta = 0 identity
   of Sect. 4.3 consistent).  Evaluated with scipy.special.wofz.
-* F(Theta, u', u) (Sect. 2.3, below Eq. G):
+* F(Theta, u', u) (Sect. 2.4, below Eq. G):
       F = exp(-((u - u')/(2 sin(Theta/2)))^2)
           * W(a / cos(Theta/2), (u + u')/(2 cos(Theta/2))) / sin(Theta).
   Theta = 0 is the distribution sqrt(pi) delta(u - u') W(a, u') (Sect. 4.3);

@@ -429,7 +429,7 @@ def formal_solve(op, eps, boundary=True, I_bottom=None, scheme=None):
     curve between the upwind and current points whose control point follows
     the three-point tangent at the current point and is kept inside the
     range of the two end values (no overshoot; this makes Lambda slightly
-    nonlinear in eps, Sect. 6.1), K'I linear.  In both three-point schemes
+    nonlinear in eps, Sect. 6.2), K'I linear.  In both three-point schemes
     the last point of a ray, which has no downwind point, takes the
     DELO-linear step."""
     scheme = scheme or op.opts.get("formal", "linear")

@@ -1,5 +1,5 @@
 // FP64 Faddeeva function w(z) = exp(-z^2) erfc(-i z) for Im z >= 0, usable on
-// host and device.  The paper (Sect. 2.3) writes W(a, v) = w(v + i a).
+// host and device.  The paper (Sect. 2.4) writes W(a, v) = w(v + i a).
 //
 // Two published methods are combined:
 //  * |z| < 15: J.A.C. Weideman, "Computation of the complex error function",

@@ -330,7 +330,7 @@ int launch_formal_grouped(hipStream_t s, const GFormal* args, const int* off, in
   return TRAP_OK;
 }
 
-// ------------------------------------------------------------------ preconditioner (Sect. 5.3, App. F)
+// ------------------------------------------------------------------ preconditioner (Sect. 5.2, App. F)
 // Local Lambda of the unpolarised formal solution: along each ray the
 // response of I at a height to the emissivity at that height is psi_c/eta_I
 // of the step that ends there; zero at the first point of the sweep.

@@ -1018,7 +1018,7 @@ static int zero_field_classes(const trap_atom_desc& at, double dnuD_ref, std::ve
   return static_cast<int>(e_k.size());
 }
 
-// Weights of the preconditioner's comoving coupling (Sect. 5.3, App. F): the
+// Weights of the preconditioner's comoving coupling (Sect. 5.2, App. F): the
 // comoving Stokes-I emissivity of the zero-field atom for an isotropic,
 // unpolarised comoving field J (K = Q = 0).  With the angle-averaged kernels
 // M_k and R_III rows R_k / profiles P_k of the zero-field transition classes k,

@@ -1373,7 +1373,7 @@ int run_precompute(trap_ctx* ctx, int store_mask) {
 }
 
 // ------------------------------------------------------------------ preconditioner tables
-// Comoving coupling of the preconditioner (Sect. 5.3): for height z and row n,
+// Comoving coupling of the preconditioner (Sect. 5.2): for height z and row n,
 //   Phi[z][n][m] = sum_k (cr_k M_k^re[n][m] + ci_k M_k^im[n][m])
 //                + sum_{a,b} Re[X1_ab P_a(n) R_b(m) + X2_ab conj(P_a(n)) R_b(m)
 //                               + X3_ab P_a(n) conj(R_b(m)) + X4_ab conj(P_a(n)) conj(R_b(m))]

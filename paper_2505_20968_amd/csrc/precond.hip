@@ -1,4 +1,4 @@
-// Physics-based preconditioner (paper Sect. 5.3) with the block-diagonal
+// Physics-based preconditioner (paper Sect. 5.2) with the block-diagonal
 // local inverse of App. F, applied as a fixed number of block-Jacobi steps.
 //
 // P = Id - Lambda* Sigma* acts on Stokes I only (Q, U, V pass through):

@@ -48,7 +48,7 @@ struct DevBuf {
 
 // ---------------------------------------------------------------- banded kernel store
 // Each R_II kernel row is nonzero only where the Gaussian factor of F reaches
-// (Sect. 2.3, App. C) plus the reach of the cardinal spline basis (its band).
+// (Sect. 2.4, App. C) plus the reach of the cardinal spline basis (its band).
 // The contraction multiplies 16-row wave tiles; the store keeps, per tile,
 // the 16 rows over the union of their bands (columns lo .. hi - 1, multiples
 // of 8) as one dense [16][hi - lo] block.  The GEMM rows of (z, theta) are
@@ -538,7 +538,7 @@ int sigma_batch_ready(trap_ctx* ctx);
 int op_apply_batch_f32(trap_ctx** ctxs, int n, const double* const* x, double* const* y, const int* pc = nullptr);
 int launch_formal_grouped(hipStream_t s, const GFormal* args, const int* off, int n, int blocks);
 
-// physics-based preconditioner (Sect. 5.3, App. F): tables after the kernel
+// physics-based preconditioner (Sect. 5.2, App. F): tables after the kernel
 // precompute (precompute.hip); out = M r for FP64 vectors, `sweeps`
 // block-Jacobi steps, the scalar formal solution in precision prec
 // (precond.hip; out may equal r)

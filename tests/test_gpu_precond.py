@@ -1,4 +1,4 @@
-"""GPU parity of the physics-based preconditioner (Sect. 5.3, App. F) against
+"""GPU parity of the physics-based preconditioner (Sect. 5.2, App. F) against
 the oracle: the per-height tables, the preconditioner apply for one and
 several block-Jacobi steps, and preconditioned solves that reach the same
 solution in fewer iterations.

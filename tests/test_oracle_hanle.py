@@ -21,7 +21,7 @@
   Stokes I obeys the scalar angle-dependent PRD scattering integral
       eps_I(Omega, u) = sum_{Omega'} w' int du' [alpha Re F(Theta, u', u)/pi
                         + (beta - alpha) phi(u) phi(u')] S[I(Omega', .)](u'),
-  written here with the paper's F (Sect. 2.3), scipy's spline and adaptive
+  written here with the paper's F (Sect. 2.4), scipy's spline and adaptive
   quadrature: a scalar solver of its own.
 """
 import numpy as np
@@ -184,7 +184,7 @@ def test_hanle_rotation_sense_of_u():
 # ---------------------------------------------------------------- unpolarised limit (scalar PRD)
 
 def _F(theta, up, u, a):
-    """R_II angle-dependent redistribution function of Sect. 2.3 (0 < Theta < pi)."""
+    """R_II angle-dependent redistribution function of Sect. 2.4 (0 < Theta < pi)."""
     s, c = np.sin(theta / 2.0), np.cos(theta / 2.0)
     return np.exp(-((u - up) / (2.0 * s)) ** 2) * wofz((u + up) / (2.0 * c) + 1j * a / c) / np.sin(theta)
 

@@ -59,7 +59,7 @@ def test_spline_reproduces_cubics_and_flat_extension():
     assert np.allclose(b.matrix(x), np.eye(x.size), atol=1e-13)
 
 
-# ---------------------------------------------------------------- Faddeeva and F (Sect. 2.3, 4.3)
+# ---------------------------------------------------------------- Faddeeva and F (Sect. 2.4, 4.3)
 
 def test_faddeeva_reading():
     """Reading of W(a, v): Re W(a, 0) = e^{a^2} erfc(a) and int Re W dv = sqrt(pi)."""
@@ -357,7 +357,7 @@ def test_two_term_fine_structure_limit():
 # ---------------------------------------------------------------- operator properties
 
 def test_sigma_linearity_and_azimuthal_equivariance():
-    """Sigma is linear in I (Sect. 2.4); rotating the field azimuth by one
+    """Sigma is linear in I (Sect. 2.5); rotating the field azimuth by one
     grid step permutes the chi index of the emissivity (Sect. 4.2 grid)."""
     rng = np.random.default_rng(9)
     kw = dict(n_z=2, n_nu=13, n_mu=4, n_chi=4, a=2e-2, eps=0.03, v_z=0.0)

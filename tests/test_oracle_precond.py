@@ -1,4 +1,4 @@
-"""Pins of the oracle's preconditioner (Sect. 5.3, App. F) against routes that
+"""Pins of the oracle's preconditioner (Sect. 5.2, App. F) against routes that
 do not go through its closed forms: brute-force inverses and diagonals, the
 flat-field identity of App. E, and the linear solve it must not change."""
 import numpy as np
