@@ -4,12 +4,16 @@
   mu = cos(theta), one per hemisphere [-1,0] and [0,1], and a trapezoidal rule
   in the azimuth chi on [0, 2pi).  Weights are normalised to the measure
   dOmega/(4 pi).
-* Scattering angles (Sects. 2.3 and 4.2): Theta = arccos(Omega . Omega'); the
+* Scattering angles (Sects. 2.4 and 4.2): Theta = arccos(Omega . Omega'); the
   comoving redistribution function depends on the pair only through Theta, so
   the distinct values are tabulated once.
 * Interpolation (Sect. 6.2): all observer/comoving frequency interpolations are
   cubic splines.  Reading: not-a-knot end conditions and flat (edge-value)
   extension outside the grid.
+* Non-oscillatory interpolation (Sect. 4.1 names high-order non-oscillatory
+  interpolation as the remedy for oscillations under strong velocities and
+  points to a weighted essentially non-oscillatory scheme; it gives no
+  formulas, so the scheme below is a reading): weno4_interpolate.
 """
 from __future__ import annotations
 
@@ -112,3 +116,65 @@ class SplineBasis:
         v = np.moveaxis(values, axis, 0)
         out = np.tensordot(S, v, axes=([1], [0]))
         return np.moveaxis(out, 0, axis)
+
+
+def weno4_interpolate(x: np.ndarray, values: np.ndarray, y: np.ndarray, axis: int = 0,
+                      eps_rel: float = 1e-12) -> np.ndarray:
+    """Fourth-order weighted essentially non-oscillatory interpolation of
+    ``values`` (nodes x along ``axis``, each trailing column separately) at y,
+    flat (edge-value) extension outside [x_0, x_{n-1}].
+
+    Reading of the remedy named in Sect. 4.1.  On the interval [x_i, x_{i+1}]
+    holding y, the two quadratics through the three-node stencils
+    {x_{i-1}, x_i, x_{i+1}} and {x_i, x_{i+1}, x_{i+2}} share the line through
+    the interval's end values:
+        q_k(y) = v_i + d (y - x_i) + D_k (y - x_i)(y - x_{i+1}),
+    d the first divided difference on the interval, D_k the second divided
+    difference of stencil k.  With the linear weights
+        g_1 = (x_{i+2} - y) / (x_{i+2} - x_{i-1}),  g_2 = 1 - g_1
+    (Neville's recursion) g_1 q_1 + g_2 q_2 is the cubic through the four
+    nodes.  The nonlinear weights replace them:
+        b_k = (h_i^2 D_k)^2            (h_i = x_{i+1} - x_i)
+        e   = eps_rel * mean(v_{i-1}^2, v_i^2, v_{i+1}^2, v_{i+2}^2)
+        a_k = g_k / (e + b_k)^2,   w_k = a_k / (a_1 + a_2),
+    so a stencil that straddles a jump (large b) loses its weight and the
+    result follows the smooth side.  e keeps the scheme invariant under a
+    scaling of the data and gives the linear weights on flat data (a floor of
+    1e-150, whose square is still a normal number, covers all-zero data).  The first
+    and last intervals have one stencil only and take its quadratic.
+    Any weights reproduce a quadratic exactly (q_1 = q_2 there); a very large
+    eps_rel gives the linear weights and so the four-node cubic.
+    """
+    x = np.asarray(x, float)
+    n = x.size
+    if n < 4:
+        raise ValueError("need >= 4 frequency nodes")
+    v = np.moveaxis(np.asarray(values, float), axis, 0)
+    yy = np.clip(np.asarray(y, float), x[0], x[-1])
+    out = np.empty((yy.size,) + v.shape[1:])
+    for j, t in enumerate(yy.ravel()):
+        i = int(np.searchsorted(x, t, side="right")) - 1
+        i = min(max(i, 0), n - 2)
+        h = x[i + 1] - x[i]
+        d = (v[i + 1] - v[i]) / h
+        lin = v[i] + d * (t - x[i])
+        bub = (t - x[i]) * (t - x[i + 1])
+        if i == 0 or i == n - 2:
+            # one stencil: the one that stays on the grid
+            a, b, c = (i, i + 1, i + 2) if i == 0 else (i - 1, i, i + 1)
+            D = ((v[c] - v[b]) / (x[c] - x[b]) - (v[b] - v[a]) / (x[b] - x[a])) / (x[c] - x[a])
+            out[j] = lin + D * bub
+            continue
+        D1 = (d - (v[i] - v[i - 1]) / (x[i] - x[i - 1])) / (x[i + 1] - x[i - 1])
+        D2 = ((v[i + 2] - v[i + 1]) / (x[i + 2] - x[i + 1]) - d) / (x[i + 2] - x[i])
+        g1 = (x[i + 2] - t) / (x[i + 2] - x[i - 1])
+        g2 = 1.0 - g1
+        b1 = (h * h * D1) ** 2
+        b2 = (h * h * D2) ** 2
+        e = eps_rel * (v[i - 1] ** 2 + v[i] ** 2 + v[i + 1] ** 2 + v[i + 2] ** 2) / 4.0 + 1e-150
+        a1 = g1 / (e + b1) ** 2
+        a2 = g2 / (e + b2) ** 2
+        w1 = a1 / (a1 + a2)
+        out[j] = lin + (w1 * D1 + (1.0 - w1) * D2) * bub
+    out = out.reshape(np.shape(yy) + v.shape[1:])
+    return np.moveaxis(out, 0, axis) if np.ndim(yy) == 1 else out

@@ -66,7 +66,7 @@ import numpy as np
 from scipy.sparse.linalg import LinearOperator, gmres
 
 from .atom import build_atom
-from .grids import angular_grid, theta_table, SplineBasis
+from .grids import angular_grid, theta_table, SplineBasis, weno4_interpolate
 from .redistribution import SQRT_PI, faddeeva, kernel_matrix, kernel_matrix_aa, r3_weights
 
 C_CGS = 2.99792458e10
@@ -125,6 +125,10 @@ def setup(prob, opts=None) -> OracleProblem:
       aa:           angle-averaged R_II (Sect. 5.2, Eq. R_AA) in place of the
                     angle-dependent kernel (default False)
       formal:       'linear' (DELO-linear, default), 'delopar' or 'besser' formal solver
+      interp:       'spline' (default, Sect. 6.2) or 'weno4' (the non-oscillatory
+                    interpolation named in Sect. 4.1, grids.weno4_interpolate)
+                    for the observer/comoving frequency transforms; the kernel
+                    rows keep the spline basis.  'weno4' makes Sigma nonlinear.
     """
     opts = dict({"normalize": True}, **(opts or {}))
     atom = prob.atom
@@ -222,6 +226,19 @@ def _r3(op, z, u, l):
     return op.r3[key]
 
 
+def _frame_interp(op, values, y):
+    """Frequency transform between the observer and comoving grids (Sect. 4.1):
+    the interpolant of values[n, ...] on the grid evaluated at y."""
+    if op.opts.get("interp", "spline") == "weno4":
+        return weno4_interpolate(op.basis.x, values, y, axis=0)
+    return op.basis.interpolate(values, y, axis=0)
+
+
+def comoving_field(op, z, Iz, o):
+    """Ibar(u_m) = I(u_m - u_b(Omega')) for incoming direction o at height z (Sect. 4.1)."""
+    return _frame_interp(op, Iz[o], op.prob.x - op.ub[z, o] / op.lam[z])
+
+
 def sigma_height(op, z, Iz, normalize=True):
     """eps^sc at height z for the local field Iz[Omega, n, 4]."""
     prob = op.prob
@@ -234,7 +251,7 @@ def sigma_height(op, z, Iz, normalize=True):
     # 1. comoving field: Ibar(u_m) = S[I](u_m - u_b(Omega'))
     Ibar = np.empty_like(Iz)
     for o in range(nd):
-        Ibar[o] = op.basis.interpolate(Iz[o], x - op.ub[z, o] / lam, axis=0)
+        Ibar[o] = comoving_field(op, z, Iz, o)
     # 2. W for every ordered pair (outgoing Omega, incoming Omega')
     W = np.zeros((nU, nL, nd, nd, nn, 4), complex)
     if not op.opts.get("no_RII"):
@@ -281,7 +298,7 @@ def sigma_height(op, z, Iz, normalize=True):
         for lp in range(nL):
             for o in range(nd):
                 y = x + (op.ub[z, o] + op.s_ll[z, l, lp]) / lam
-                out[o] += op.basis.interpolate(eps_bar[l, lp, o], y, axis=0)
+                out[o] += _frame_interp(op, eps_bar[l, lp, o], y)
     if normalize:
         out[..., 0] *= op.f[z]
         if op.sigma_c is not None and np.any(op.sigma_c[z] != 0.0):
@@ -493,6 +510,9 @@ def rhs(op):
 
 def solve(op, tol=1e-12, method="gmres", restart=200, maxiter=4000):
     """Solution of (Id - Lambda Sigma) I = Lambda eps_th + t."""
+    if op.opts.get("interp", "spline") == "weno4":
+        raise ValueError("the non-oscillatory transforms make Sigma nonlinear: "
+                         "solve its fixed point with solve_aar")
     b = rhs(op)
     shape = b.shape
     n = b.size
