@@ -278,6 +278,34 @@ int trap_formal_solve(trap_ctx* ctx, const void* eps, void* I, int with_boundary
 enum { TRAP_FORMAL_DELO_LINEAR = 0, TRAP_FORMAL_DELOPAR = 1, TRAP_FORMAL_BESSER = 2 };
 int trap_set_formal_scheme(trap_ctx* ctx, int scheme);
 
+/* Interpolant of the frequency transforms between the observer and the
+ * comoving frame (Sect. 4.1: the comoving field Ibar(u) = I(u - u_b) before
+ * the scattering integral and the emissivity back to the observer frame
+ * after it).  TRAP_INTERP_SPLINE (default): the not-a-knot cubic spline of
+ * Sect. 6.2, flat beyond the grid ends.  TRAP_INTERP_WENO4: the
+ * non-oscillatory interpolation that Sect. 4.1 names as the remedy for
+ * oscillating profiles under strong velocities, read as a fourth-order
+ * weighted essentially non-oscillatory scheme: on [x_i, x_{i+1}] the two
+ * quadratics through {x_{i-1}, x_i, x_{i+1}} and {x_i, x_{i+1}, x_{i+2}},
+ * q_k = v_i + d (u - x_i) + D_k (u - x_i)(u - x_{i+1}) (d, D_k the first and
+ * second divided differences), are blended with weights a_k / (a_1 + a_2),
+ * a_k = g_k / (e + (h_i^2 D_k)^2)^2, g_1 = (x_{i+2} - u) / (x_{i+2} - x_{i-1}),
+ * g_2 = 1 - g_1, e = 1e-12 times the mean square of the four values plus
+ * 1e-150; the first and last intervals take their one quadratic; flat beyond
+ * the ends; per Stokes component, in FP64.  The kernel rows keep the spline
+ * basis.  The blend depends on the data, so Sigma is then nonlinear: it is
+ * used by trap_apply_sigma, trap_apply_operator, the normalisation factor f,
+ * every FP64 residual of trap_gmres_solve / trap_gmres_begin and every
+ * evaluation of G in trap_aar_solve, while the inner Krylov and
+ * defect-correction applies (which need a linear operator) keep the spline,
+ * so the outer refinement converges to the nonlinear fixed point when the two
+ * transforms are close; where they are not (shifts of several grid steps on a
+ * coarse grid) trap_aar_solve with inner = TRAP_FP64 iterates G itself.  Set
+ * before trap_precompute (TRAP_ESTATE when changed after it for the loaded
+ * problem; a new problem frees it again); TRAP_EINVAL for an unknown mode. */
+enum { TRAP_INTERP_SPLINE = 0, TRAP_INTERP_WENO4 = 1 };
+int trap_set_interpolation(trap_ctx* ctx, int mode);
+
 /* y = (Id - Lambda Sigma) x, the operator of Eq. linear_system (with BESSER,
  * whose Lambda is not linear, x - Lambda(Sigma x) evaluated as written). */
 int trap_apply_operator(trap_ctx* ctx, const void* x, void* y, int prec);

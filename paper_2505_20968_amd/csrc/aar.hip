@@ -345,7 +345,11 @@ int aar_solve(trap_ctx* ctx, const trap_aar_opts* o, double* x, trap_solve_stats
     auto res = [&](const double* dd, double* rr) -> int {
       hipLaunchKernelGGL(k_aar_to_f32, dim3(kVecBlocks), dim3(256), 0, ctx->stream, N, dd, v32);
       TRAP_HIP(hipGetLastError());
-      TRAP_TRY(operator_apply(ctx, v32, y32, TRAP_FP32));
+      // the inner operator is linear: spline frame transforms
+      ctx->interp_lin = 1;
+      const int rc = operator_apply(ctx, v32, y32, TRAP_FP32);
+      ctx->interp_lin = 0;
+      TRAP_TRY(rc);
       hipLaunchKernelGGL(k_aar_defect, dim3(kVecBlocks), dim3(256), 0, ctx->stream, N, r64, y32, rr);
       TRAP_HIP(hipGetLastError());
       ++S.applies_fp32;

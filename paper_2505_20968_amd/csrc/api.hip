@@ -542,6 +542,15 @@ int trap_set_prd_mode(trap_ctx* ctx, int mode) {
   return TRAP_OK;
 }
 
+int trap_set_interpolation(trap_ctx* ctx, int mode) {
+  if (!ctx) return fail(TRAP_EINVAL, "null context");
+  if (mode != TRAP_INTERP_SPLINE && mode != TRAP_INTERP_WENO4) return fail(TRAP_EINVAL, "unknown interpolation");
+  if (ctx->pre.done && mode != ctx->interp)
+    return fail(TRAP_ESTATE, "the interpolation is fixed once trap_precompute has run for the problem");
+  ctx->interp = mode;
+  return TRAP_OK;
+}
+
 int trap_set_formal_scheme(trap_ctx* ctx, int scheme) {
   if (!ctx) return fail(TRAP_EINVAL, "null context");
   if (scheme != TRAP_FORMAL_DELO_LINEAR && scheme != TRAP_FORMAL_DELOPAR && scheme != TRAP_FORMAL_BESSER)

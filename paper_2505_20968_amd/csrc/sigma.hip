@@ -24,6 +24,44 @@ namespace trap {
 
 static constexpr double kInvPi = 0.31830988618379067154;
 
+// Non-oscillatory value at xs in [x_lo, x_lo+1] of the four Stokes columns of
+// v [nn][4] (the blend of the two three-node quadratics documented with
+// trap_set_interpolation): both quadratics pass through the interval's end
+// values, q_k = v_lo + d (xs - x_lo) + D_k (xs - x_lo)(xs - x_lo+1), and
+// their second differences are blended with weights that follow the smoother
+// stencil.  The first and last intervals take their one quadratic.
+__device__ inline void weno4_point(const double* __restrict__ x, int nn, const double* v, int lo, double xs,
+                                   double* val) {
+  const double x0 = x[lo], x1 = x[lo + 1];
+  const double h = x1 - x0;
+  const double bub = (xs - x0) * (xs - x1);
+  const bool left = lo == 0, right = lo == nn - 2;
+  const double xm = left ? 0.0 : x[lo - 1], xp = right ? 0.0 : x[lo + 2];
+  const double g1 = (left || right) ? 0.0 : (xp - xs) / (xp - xm);
+  for (int q = 0; q < 4; ++q) {
+    const double v0 = v[4 * lo + q], v1 = v[4 * (lo + 1) + q];
+    const double d = (v1 - v0) / h;
+    const double lin = v0 + d * (xs - x0);
+    if (left || right) {
+      // the stencil that stays on the grid: {0, 1, 2} or {nn-3, nn-2, nn-1}
+      const int a = left ? 0 : nn - 3;
+      const double fa = v[4 * a + q], fb = v[4 * (a + 1) + q], fc = v[4 * (a + 2) + q];
+      const double D = ((fc - fb) / (x[a + 2] - x[a + 1]) - (fb - fa) / (x[a + 1] - x[a])) / (x[a + 2] - x[a]);
+      val[q] = lin + D * bub;
+      continue;
+    }
+    const double vm = v[4 * (lo - 1) + q], vp = v[4 * (lo + 2) + q];
+    const double D1 = (d - (v0 - vm) / (x0 - xm)) / (x1 - xm);
+    const double D2 = ((vp - v1) / (xp - x1) - d) / (xp - x0);
+    const double b1 = (h * h * D1) * (h * h * D1), b2 = (h * h * D2) * (h * h * D2);
+    const double e = 1e-12 * (vm * vm + v0 * v0 + v1 * v1 + vp * vp) * 0.25 + 1e-150;
+    const double a1 = g1 / ((e + b1) * (e + b1)), a2 = (1.0 - g1) / ((e + b2) * (e + b2));
+    const double w1 = a1 / (a1 + a2);
+    val[q] = lin + (w1 * D1 + (1.0 - w1) * D2) * bub;
+  }
+}
+
+
 // ------------------------------------------------------------------ spline evaluation
 // out[z][o][n][s] (+)= S[in[z][o][:][s]](x_n + shift) for one (l, l') class,
 // flat extension outside [x_0, x_{nn-1}];  shift (x units) =
@@ -38,7 +76,7 @@ __device__ __forceinline__ void spline_shift_body(
     const double* __restrict__ lam, const double* __restrict__ ub, double ub_sign,
     const double* __restrict__ sll, int ncls, int cls, const T* __restrict__ in, long long in_z_stride,
     long long in_o_stride, T* __restrict__ out, int accumulate, const double* __restrict__ f,
-    const double* __restrict__ epsth) {
+    const double* __restrict__ epsth, int weno) {
   double* v = spl;               // [nn][4]
   double* sd = spl + 4 * nn;     // [nn][4]
   const int zl = bx / nd, o = bx % nd;
@@ -51,7 +89,8 @@ __device__ __forceinline__ void spline_shift_body(
   if (shifted) {
     for (int e = threadIdx.x; e < 4 * nn; e += blockDim.x) v[e] = (double)src[e];
     __syncthreads();
-    for (int m = threadIdx.x; m < nn; m += blockDim.x) {
+    // the spline's second derivatives (the non-oscillatory blend needs none)
+    for (int m = threadIdx.x; m < nn && !weno; m += blockDim.x) {
       double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
       for (int j = 0; j < nn; ++j) {
         const double g = SigT[(size_t)j * nn + m];
@@ -84,12 +123,16 @@ __device__ __forceinline__ void spline_shift_body(
           const int mid = (lo + hi) >> 1;
           if (x[mid] <= xs) lo = mid; else hi = mid;
         }
-        const double h = x[lo + 1] - x[lo];
-        const double t = (xs - x[lo]) / h, u = 1.0 - t;
-        const double cs = h * h / 6.0;
-        const double wk = cs * (u * u * u - u), wk1 = cs * (t * t * t - t);
-        for (int q = 0; q < 4; ++q)
-          val[q] = u * v[4 * lo + q] + t * v[4 * lo + 4 + q] + wk * sd[4 * lo + q] + wk1 * sd[4 * lo + 4 + q];
+        if (weno) {
+          weno4_point(x, nn, v, lo, xs, val);
+        } else {
+          const double h = x[lo + 1] - x[lo];
+          const double t = (xs - x[lo]) / h, u = 1.0 - t;
+          const double cs = h * h / 6.0;
+          const double wk = cs * (u * u * u - u), wk1 = cs * (t * t * t - t);
+          for (int q = 0; q < 4; ++q)
+            val[q] = u * v[4 * lo + q] + t * v[4 * lo + 4 + q] + wk * sd[4 * lo + q] + wk1 * sd[4 * lo + 4 + q];
+        }
       }
     }
     const long long pidx = ((long long)z * nd + o) * nn + n;
@@ -113,11 +156,11 @@ __global__ void __launch_bounds__(128) k_spline_shift(
     const double* __restrict__ lam, const double* __restrict__ ub, double ub_sign,
     const double* __restrict__ sll, int ncls, int cls, const T* __restrict__ in, long long in_z_stride,
     long long in_o_stride, T* __restrict__ out, int accumulate, const double* __restrict__ f,
-    const double* __restrict__ epsth) {
+    const double* __restrict__ epsth, int weno) {
   extern __shared__ double spl[];
   (void)nzc;
   spline_shift_body<T>(blockIdx.x, spl, nz0, nd, nn, x, SigT, lam, ub, ub_sign, sll, ncls, cls, in, in_z_stride,
-                       in_o_stride, out, accumulate, f, epsth);
+                       in_o_stride, out, accumulate, f, epsth, weno);
 }
 
 // ------------------------------------------------------------------ R_II contraction
@@ -1219,6 +1262,8 @@ static int sigma_apply_t(trap_ctx* ctx, const T* I, T* eps, int prec, int add_th
   T* Eb = static_cast<T*>(K.Eb[pi]);
   const int ncls = nl * nl;
   const size_t spl_lds = (size_t)8 * nn * sizeof(double);
+  // frame transforms: the context's interpolant, except in inner (linearised) applies
+  const int weno = (ctx->interp == TRAP_INTERP_WENO4 && !ctx->interp_lin) ? 1 : 0;
   // the fused kernel runs only when asked for: its LDS scatter of the angular
   // sum is still slower than materialising W per height chunk
   const size_t flds = ctx->path == TRAP_PATH_FUSED ? fused_lds(ctx, prec) : 0;
@@ -1231,7 +1276,7 @@ static int sigma_apply_t(trap_ctx* ctx, const T* I, T* eps, int prec, int add_th
     hipLaunchKernelGGL(k_spline_shift<T>, dim3(nz * nd), dim3(128), spl_lds, s, 0, nz, nd, nn, P.d_x,
                        P.d_SigT, P.d_lam, P.d_ub, -1.0, (const double*)nullptr, 1, 0, I,
                        (long long)nd * nn * 4, (long long)nn * 4, Ibar, 0, (const double*)nullptr,
-                       (const double*)nullptr);
+                       (const double*)nullptr, weno);
     TRAP_HIP(hipGetLastError());
     prof_end(ctx, pr);
     // 2. R_III factors, all heights
@@ -1263,7 +1308,7 @@ static int sigma_apply_t(trap_ctx* ctx, const T* I, T* eps, int prec, int add_th
     hipLaunchKernelGGL(k_spline_shift<T>, dim3(nz * nd), dim3(128), spl_lds, s, 0, nz, nd, nn, P.d_x,
                        P.d_SigT, P.d_lam, P.d_ub, -1.0, (const double*)nullptr, 1, 0, I,
                        (long long)nd * nn * 4, (long long)nn * 4, Ibar, 0, (const double*)nullptr,
-                       (const double*)nullptr);
+                       (const double*)nullptr, weno);
     TRAP_HIP(hipGetLastError());
     prof_end(ctx, pr);
     pr = prof_begin(ctx, TRAP_STAGE_R3);
@@ -1325,7 +1370,7 @@ static int sigma_apply_t(trap_ctx* ctx, const T* I, T* eps, int prec, int add_th
                          P.d_x, P.d_SigT, P.d_lam, P.d_ub, 1.0, P.d_sll, ncls, cls,
                          Eb + (size_t)cls * nd * nn * 4, (long long)ncls * nd * nn * 4, (long long)nn * 4,
                          eps, first ? 0 : 1, (normalize && ncls == 1) ? C.d_f : (const double*)nullptr,
-                         (add_thermal && last && ncls == 1) ? C.d_epsth : (const double*)nullptr);
+                         (add_thermal && last && ncls == 1) ? C.d_epsth : (const double*)nullptr, weno);
       TRAP_HIP(hipGetLastError());
     }
   if (ncls > 1 && (normalize || add_thermal)) {
@@ -1336,7 +1381,7 @@ static int sigma_apply_t(trap_ctx* ctx, const T* I, T* eps, int prec, int add_th
                        P.d_x, P.d_SigT, P.d_lam, P.d_ub, 0.0, (const double*)nullptr, 1, 0, tmp,
                        (long long)nd * nn * 4, (long long)nn * 4, eps, 0,
                        normalize ? C.d_f : (const double*)nullptr,
-                       add_thermal ? C.d_epsth : (const double*)nullptr);
+                       add_thermal ? C.d_epsth : (const double*)nullptr, 0);
     TRAP_HIP(hipGetLastError());
   }
   prof_end(ctx, prb);
@@ -1472,8 +1517,9 @@ __global__ void __launch_bounds__(128) k_spline_shift_grouped(const GSpline* __r
   extern __shared__ double spl[];
   const int r = find_req(blockIdx.x, off, n);
   const GSpline& a = A[r];
+  // the batched FP32 applies are inner (linearised) applies: spline transforms
   spline_shift_body<float>(blockIdx.x - off[r], spl, a.nz0, a.nd, a.nn, a.x, a.SigT, a.lam, a.ub, a.ub_sign, a.sll,
-                           a.ncls, a.cls, a.in, a.in_z_stride, a.in_o_stride, a.out, a.accumulate, a.f, a.epsth);
+                           a.ncls, a.cls, a.in, a.in_z_stride, a.in_o_stride, a.out, a.accumulate, a.f, a.epsth, 0);
 }
 
 __global__ void __launch_bounds__(256) k_r3_Y_grouped(const GR3Y* __restrict__ A, const int* __restrict__ off,

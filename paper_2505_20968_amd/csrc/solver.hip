@@ -143,10 +143,17 @@ namespace {
 
 constexpr int kBlocks = 1024;
 
-// y = A x with the operator in precision `prec` (x, y FP64)
-int op_apply(trap_ctx* ctx, int prec, const double* x, double* y, trap_solve_stats* st) {
+// y = A x with the operator in precision `prec` (x, y FP64); `lin`: an inner
+// Krylov apply, whose frame transforms are the spline (a linear operator)
+// whatever interpolant the context uses for its residuals
+int op_apply(trap_ctx* ctx, int prec, const double* x, double* y, trap_solve_stats* st, bool lin) {
   Work& K = ctx->wk;
   const long long N = 4LL * ctx->pb.nz * ctx->pb.nd * ctx->pb.nn;
+  struct LinGuard {
+    trap_ctx* c;
+    ~LinGuard() { c->interp_lin = 0; }
+  } guard{ctx};
+  ctx->interp_lin = lin ? 1 : 0;
   if (prec == TRAP_FP64) {
     TRAP_TRY(operator_apply(ctx, x, y, TRAP_FP64));
     st->applies_fp64++;
@@ -405,7 +412,7 @@ int unit_issue1(trap_ctx* ctx, GmresRun& R) {
     hipLaunchKernelGGL(k_scale_copy, dim3(kBlocks), dim3(256), 0, ctx->stream, R.N, 0.0, ctx->pre.d_b, y);
     TRAP_HIP(hipGetLastError());
   } else {
-    TRAP_TRY(op_apply(ctx, prec, x, y, &R.st));
+    TRAP_TRY(op_apply(ctx, prec, x, y, &R.st, R.phase != GP_RESID_OUTER));
   }
   return unit_issue1_rest(ctx, R);
 }

@@ -286,6 +286,9 @@ struct trap_ctx {
   int path = 0;                     // TRAP_PATH_* of trap.h
   int prd_mode = 0;                 // TRAP_PRD_* of trap.h, applied at trap_set_problem
   int formal_scheme = 0;            // TRAP_FORMAL_* of trap.h
+  int interp = 0;                   // TRAP_INTERP_* of trap.h: the frame transforms of Sigma
+  int interp_lin = 0;               // nonzero while an inner (linearised) Krylov apply runs:
+                                    // its transforms are the spline whatever `interp` says
   // while set: BESSER formal solutions in this precision are linearised about
   // this reference emissivity (device vector of the full layout)
   const void* besser_ref = nullptr;

@@ -21,6 +21,7 @@ TRAP_FP32 = 1
 TRAP_PATH_AUTO, TRAP_PATH_FUSED, TRAP_PATH_CHUNKED = 0, 1, 2
 TRAP_PRD_AD, TRAP_PRD_AA = 0, 1
 TRAP_FORMAL_DELO_LINEAR, TRAP_FORMAL_DELOPAR, TRAP_FORMAL_BESSER = 0, 1, 2
+TRAP_INTERP_SPLINE, TRAP_INTERP_WENO4 = 0, 1
 STATUS = {0: "TRAP_OK", -1: "TRAP_EINVAL", -2: "TRAP_ENOMEM", -3: "TRAP_EDEVICE",
           -4: "TRAP_ENOCONV", -5: "TRAP_ESTATE", -6: "TRAP_ENAN"}
 
@@ -30,6 +31,7 @@ EXPORTED = ["trap_create", "trap_destroy", "trap_set_problem", "trap_precompute"
             "trap_profile", "trap_stage_times", "trap_set_path", "trap_set_prd_mode", "trap_gmres_begin",
             "trap_gmres_step_batch", "trap_gmres_end", "trap_precompute_preconditioner",
             "trap_apply_preconditioner", "trap_apply_preconditioner_noalloc", "trap_preconditioner_tables", "trap_set_formal_scheme",
+            "trap_set_interpolation",
             "trap_formal_from_field", "trap_emergent_los", "trap_aar_solve", "trap_kernel_rows",
             "trap_faddeeva", "trap_hip_notes", "trap_last_error"]
 STAGES = ["comoving", "contract_fp32", "r3", "angular", "backinterp", "formal", "kernel_rows",
@@ -124,6 +126,7 @@ def load_library(path: str = LIB_PATH):
     lib.trap_stage_times.argtypes = [vp, ctypes.POINTER(StageStats)]
     lib.trap_precompute_preconditioner.argtypes = [vp]
     lib.trap_set_formal_scheme.argtypes = [vp, ctypes.c_int]
+    lib.trap_set_interpolation.argtypes = [vp, ctypes.c_int]
     lib.trap_apply_preconditioner.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.c_int]
     lib.trap_apply_preconditioner_noalloc.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.c_int]
     lib.trap_preconditioner_tables.argtypes = [vp, _dp, _dp, _dp]
@@ -280,6 +283,11 @@ class Context:
         """TRAP_FORMAL_DELO_LINEAR (0), TRAP_FORMAL_DELOPAR (1) or TRAP_FORMAL_BESSER (2),
         before precompute."""
         _check(self.lib.trap_set_formal_scheme(self.h, int(scheme)))
+
+    def set_interpolation(self, mode: int):
+        """TRAP_INTERP_SPLINE (0) or TRAP_INTERP_WENO4 (1) for the observer/comoving
+        frequency transforms, before precompute."""
+        _check(self.lib.trap_set_interpolation(self.h, int(mode)))
 
     def precompute_preconditioner(self):
         _check(self.lib.trap_precompute_preconditioner(self.h))
