@@ -20,8 +20,12 @@ apply's dominant kernel (the FP32 R_II contraction), timed with HIP events on
 the library's stream over the timed region, with its algorithmic flops (16
 per in-band kernel entry and incoming slot); `sigma_apply` the whole FP32
 Sigma apply against the same flops; `accuracy` the timed solve's emergent
-profiles against a tight FP64 solve of the same atmosphere; `cpu_baseline`
-times the FP64 oracle on a bounded sample of the same workload.
+profiles against a tight FP64 solve of the same atmosphere; `ad_vs_aa` solves
+that atmosphere again with angle-averaged PRD (Sect. 5.2) and reports its
+time and the emergent AD - AA differences (the comparison of Sect. 6.6);
+`serving` a bounded request stream (mixed precision against FP64);
+`cpu_baseline` times the FP64 oracle on a bounded sample of the same workload.
+Everything after the timed steps runs outside the timed region.
 """
 from __future__ import annotations
 
@@ -222,6 +226,45 @@ def serving_bench(n_requests: int, seed: int, precond_sweeps: int):
             "mixed_over_fp64_throughput": runs["mixed"]["solves_per_s"] / max(runs["fp64"]["solves_per_s"], 1e-30)}
 
 
+def ad_versus_aa(prob, em_ad, tol, restart, sweeps, mixed):
+    """Sect. 6.6 on the GPU at the bench's size: the same atmosphere solved with
+    the angle-averaged redistribution (Sect. 5.2, Eq. R_AA) and the same solver
+    settings, its wall time (set-up, precompute and solve) and the emergent
+    differences from the timed angle-dependent solve."""
+    import numpy as np
+    import torch
+    from paper_2505_20968_amd import Context, TRAP_FP32, TRAP_FP64, TRAP_PRD_AA
+    ctx = Context(0)
+    ctx.set_prd_mode(TRAP_PRD_AA)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.set_problem(prob)
+    ctx.precompute(3 if mixed else 1)
+    if sweeps:
+        ctx.precompute_preconditioner()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    x = torch.zeros(ctx.shape, dtype=torch.float64, device="cuda")
+    st = ctx.gmres_solve(x, tol=tol, restart=restart, max_iters=2000, inner=TRAP_FP32 if mixed else TRAP_FP64,
+                         max_outer=10, inner_tol=1e-7, zero_guess=True, precond_sweeps=sweeps)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    em = ctx.emergent(x)
+    info = ctx.info()
+    ctx.close()
+    d_rel_I = np.abs(em_ad[..., 0] - em[..., 0]) / np.abs(em_ad[..., 0])
+    return {"what": "the timed atmosphere solved with angle-averaged PRD (same solver settings); "
+                    "differences of the emergent profiles, AD minus AA",
+            "aa_seconds": t2 - t0, "aa_precompute_s": t1 - t0, "aa_solve_s": t2 - t1,
+            "aa_inner_iters": st["inner_iters"], "aa_final_rel_res": st["final_rel_res"],
+            "aa_kernel_store_bytes": info["bytes_kernel_fp64"],
+            "max_rel_dI": float(d_rel_I.max()),
+            "max_abs_d_Q_over_I": float(np.abs(em_ad[..., 1] / em_ad[..., 0] - em[..., 1] / em[..., 0]).max()),
+            "max_abs_d_U_over_I": float(np.abs(em_ad[..., 2] / em_ad[..., 0] - em[..., 2] / em[..., 0]).max()),
+            "max_abs_d_V_over_I": float(np.abs(em_ad[..., 3] / em_ad[..., 0] - em[..., 3] / em[..., 0]).max()),
+            "max_abs_Q_over_I_ad": float(np.abs(em_ad[..., 1] / em_ad[..., 0]).max())}
+
+
 def _progress(msg: str) -> None:
     """One line on stderr per finished phase, so a long run shows where it is."""
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
@@ -245,6 +288,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=12,
                     help="requests in the serving measurement (0 skips it)")
+    ap.add_argument("--no-aa", action="store_true",
+                    help="skip the angle-averaged solve of the timed atmosphere (outside the timed region)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="before the timed region, run one elementwise kernel over a known byte "
                          "count (reads and writes 256 MiB) to calibrate HBM traffic counters")
@@ -418,6 +463,10 @@ def main():
                                 "algorithmic flops"},
         "accuracy": accuracy,
     }
+    if not args.no_aa:
+        torch.cuda.empty_cache()
+        out["ad_vs_aa"] = ad_versus_aa(last["prob"], em, args.tol, args.restart, sweeps, mixed)
+        _progress(f"AD versus AA done: {out['ad_vs_aa']}")
     if args.serve_requests > 0:
         torch.cuda.empty_cache()
         out["serving"] = serving_bench(args.serve_requests, seed=5, precond_sweeps=args.serve_precond_sweeps)
