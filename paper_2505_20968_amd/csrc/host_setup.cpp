@@ -14,7 +14,9 @@
 #include <algorithm>
 #include <cmath>
 #include <complex>
+#include <memory>
 #include <numeric>
+#include <thread>
 #include <vector>
 
 #include "faddeeva.h"
@@ -592,6 +594,27 @@ static int upper_node(const std::vector<double>& x, double v) {
   return lo;
 }
 
+// f(i0, i1) over [0, n) in contiguous ranges on up to 16 host threads (one
+// when the work is small); f must only write what its range owns.
+template <typename F>
+static void host_parallel(size_t n, size_t min_per_thread, F f) {
+  const size_t hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  const size_t nt = std::max<size_t>(1, std::min(hw, n / std::max<size_t>(1, min_per_thread)));
+  if (nt <= 1) {
+    f(size_t(0), n);
+    return;
+  }
+  std::vector<std::thread> pool;
+  pool.reserve(nt - 1);
+  const size_t per = (n + nt - 1) / nt;
+  for (size_t k = 1; k < nt; ++k) {
+    const size_t a = std::min(n, k * per), b = std::min(n, a + per);
+    pool.emplace_back([=, &f]() { f(a, b); });
+  }
+  f(size_t(0), std::min(n, per));
+  for (auto& t : pool) t.join();
+}
+
 void kernel_bands(Problem& P, const std::vector<double>& sig) {
   const int nz = P.nz, nn = P.nn, nth = P.nth, np = 2 * P.nt;
   const bool aa = P.prd_mode == TRAP_PRD_AA;
@@ -626,12 +649,14 @@ void kernel_bands(Problem& P, const std::vector<double>& sig) {
   // 6.6 Gaussian widths 2 sin(Theta/2)/lam of x_n (what the kernel-row
   // precompute integrates), one node of margin for rounding, then the spline's
   // reach; the in-band entries are the algorithmic work
-  std::vector<short> blo((size_t)nz * nth * nn), bhi((size_t)nz * nth * nn);
-  P.kflops_z.assign(nz, 0.0);
-  P.band_nnz = 0.0;
-  for (int z = 0; z < nz; ++z)
-    for (int t = 0; t < nth; ++t) {
-      const size_t zt = (size_t)z * nth + t;
+  // (every entry is written below, by the thread that owns its (z, theta):
+  // no zero fill, and the first touch of each page happens in that thread)
+  std::unique_ptr<short[]> blo(new short[(size_t)nz * nth * nn]), bhi(new short[(size_t)nz * nth * nn]);
+  std::vector<long long> cnt_zt((size_t)nz * nth);
+  const size_t nzt = (size_t)nz * nth;
+  host_parallel(nzt, 64, [&](size_t zt0, size_t zt1) {
+    for (size_t zt = zt0; zt < zt1; ++zt) {
+      const int z = static_cast<int>(zt / nth), t = static_cast<int>(zt % nth);
       const double R = 6.6 * 2.0 * sg[t] / P.lam[z];
       long long cnt = 0;
       // x_n - R and x_n + R increase with n: the interval searches walk forward
@@ -660,102 +685,125 @@ void kernel_bands(Problem& P, const std::vector<double>& sig) {
         bhi[zt * nn + n] = static_cast<short>(hi);
         cnt += hi - lo;
       }
-      P.band_nnz += (double)P.nt * cnt;
-      P.kflops_z[z] += 16.0 * P.nt * (double)cnt * nslots[t];
+      cnt_zt[zt] = cnt;
     }
+  });
+  P.kflops_z.assign(nz, 0.0);
+  P.band_nnz = 0.0;
+  for (size_t zt = 0; zt < nzt; ++zt) {
+    P.band_nnz += (double)P.nt * cnt_zt[zt];
+    P.kflops_z[zt / nth] += 16.0 * P.nt * (double)cnt_zt[zt] * nslots[zt % nth];
+  }
   // wave tiles in both row layouts; the one with less column work is kept:
   // every wave of a block steps through the block's column range (the union
   // of its eight tiles' ranges), times the incoming slots of the angle
-  auto tiles = [&](bool pad, std::vector<int>& row0, std::vector<unsigned>& qk, double* work) {
+  auto tiles = [&](bool pad, std::vector<int>& row0, host_vec<unsigned>& qk, double* work) {
     const int nnp = pad ? (nn + 15) / 16 * 16 : nn;
     const int rows = np * nnp;
     const int nq = (rows + 15) / 16;
     row0.assign(nq, 0);
     for (int q = 0; q < nq; ++q) row0[q] = pad ? (q % np) * nnp + 16 * (q / np) : 16 * q;
-    qk.assign((size_t)nz * nth * nq, 0u);
-    *work = 0.0;
+    qk.resize((size_t)nz * nth * nq);                  // every entry written below
+    std::vector<double> work_zt(nzt, 0.0);
     // the band ends never decrease with n, so a run of rows n_a..n_b of one
     // plane spans [lo(n_a), hi(n_b))
-    for (size_t zt = 0; zt < (size_t)nz * nth; ++zt) {
-      const short* bl = &blo[zt * nn];
-      const short* bh = &bhi[zt * nn];
-      for (int q = 0; q < nq; ++q) {
-        int lo = P.ldm, hi = 0;
-        const int r1 = std::min(row0[q] + 16, rows);
-        for (int r = row0[q]; r < r1;) {
-          const int p = r / nnp, n = r - p * nnp;
-          const int run = std::min(r1 - r, nnp - n);        // rows left in this plane
-          const int nb = std::min(n + run, nn) - 1;
-          if (nb >= n) {
-            lo = std::min(lo, (int)bl[n]);
-            hi = std::max(hi, (int)bh[nb]);
+    host_parallel(nzt, 64, [&](size_t zt0, size_t zt1) {
+      for (size_t zt = zt0; zt < zt1; ++zt) {
+        const short* bl = &blo[zt * nn];
+        const short* bh = &bhi[zt * nn];
+        for (int q = 0; q < nq; ++q) {
+          int lo = P.ldm, hi = 0;
+          const int r1 = std::min(row0[q] + 16, rows);
+          for (int r = row0[q]; r < r1;) {
+            const int p = r / nnp, n = r - p * nnp;
+            const int run = std::min(r1 - r, nnp - n);        // rows left in this plane
+            const int nb = std::min(n + run, nn) - 1;
+            if (nb >= n) {
+              lo = std::min(lo, (int)bl[n]);
+              hi = std::max(hi, (int)bh[nb]);
+            }
+            r += run;
           }
-          r += run;
+          if (hi <= lo) lo = hi = 0;
+          lo = lo / 8 * 8;
+          hi = std::min((hi + 7) / 8 * 8, P.ldm);
+          qk[zt * nq + q] = (unsigned)lo | ((unsigned)hi << 16);
         }
-        if (hi <= lo) lo = hi = 0;
-        lo = lo / 8 * 8;
-        hi = std::min((hi + 7) / 8 * 8, P.ldm);
-        qk[zt * nq + q] = (unsigned)lo | ((unsigned)hi << 16);
-      }
-      for (int q0 = 0; q0 < nq; q0 += 8) {
-        int lo = P.ldm, hi = 0;
-        for (int q = q0; q < std::min(q0 + 8, nq); ++q) {
-          const unsigned v = qk[zt * nq + q];
-          if ((v >> 16) > (v & 0xffffu)) {
-            lo = std::min(lo, (int)(v & 0xffffu));
-            hi = std::max(hi, (int)(v >> 16));
+        for (int q0 = 0; q0 < nq; q0 += 8) {
+          int lo = P.ldm, hi = 0;
+          for (int q = q0; q < std::min(q0 + 8, nq); ++q) {
+            const unsigned v = qk[zt * nq + q];
+            if ((v >> 16) > (v & 0xffffu)) {
+              lo = std::min(lo, (int)(v & 0xffffu));
+              hi = std::max(hi, (int)(v >> 16));
+            }
           }
+          if (hi > lo) work_zt[zt] += 8.0 * (hi - lo) * nslots[zt % nth];
         }
-        if (hi > lo) *work += 8.0 * (hi - lo) * nslots[zt % nth];
       }
-    }
+    });
+    *work = 0.0;
+    for (double w : work_zt) *work += w;
     return nnp;
   };
   std::vector<int> r0a, r0b;
-  std::vector<unsigned> qka, qkb;
+  host_vec<unsigned> qka, qkb;
   double wa = 0.0, wb = 0.0;
   const int nnpa = tiles(false, r0a, qka, &wa);
   const int nnpb = tiles(true, r0b, qkb, &wb);
   const bool pad = wb < wa;
   P.qpad = pad ? 1 : 0;
   P.nnp = pad ? nnpb : nnpa;
-  P.qrow0 = pad ? r0b : r0a;
-  P.qk = pad ? qkb : qka;
+  P.qrow0 = std::move(pad ? r0b : r0a);
+  P.qk = std::move(pad ? qkb : qka);
   P.nq = static_cast<int>(P.qrow0.size());
   P.nqb = (P.nq + 7) / 8;
   // tile offsets: tiles of (z, theta) back to back in block order, each
   // [16][hi - lo]
-  P.tofs.assign((size_t)nz * nth * P.nq, 0);
-  P.td.assign((size_t)nz * nth * P.nq, TileDesc{0, 0, 0});
-  P.kbase.assign((size_t)nz * nth, 0);
-  P.qb.assign((size_t)nz * nth * P.nqb, 0u);
-  long long total = 0;
-  for (size_t zt = 0; zt < (size_t)nz * nth; ++zt) {
-    P.kbase[zt] = total;
-    int off = 0;
-    for (int q = 0; q < P.nq; ++q) {
-      const unsigned v = P.qk[zt * P.nq + q];
-      P.tofs[zt * P.nq + q] = off;
-      off += 16 * (int)((v >> 16) - (v & 0xffffu));
-    }
-    total += off;
-    for (int q = 0; q < P.nq; ++q) {
-      const unsigned v = P.qk[zt * P.nq + q];
-      P.td[zt * P.nq + q] = TileDesc{P.kbase[zt] + P.tofs[zt * P.nq + q], (int)(v & 0xffffu), (int)(v >> 16)};
-    }
-    for (int bq = 0; bq < P.nqb; ++bq) {
-      unsigned lo = 0xffffu, hi = 0;
-      for (int q = 8 * bq; q < std::min(8 * bq + 8, P.nq); ++q) {
+  // (all four are written in full below)
+  P.tofs.resize((size_t)nz * nth * P.nq);
+  P.td.resize((size_t)nz * nth * P.nq);
+  P.kbase.resize((size_t)nz * nth);
+  P.qb.resize((size_t)nz * nth * P.nqb);
+  // per (z, theta): tile offsets and size, then the running base, then the
+  // descriptors and block ranges
+  std::vector<long long> size_zt(nzt);
+  host_parallel(nzt, 256, [&](size_t zt0, size_t zt1) {
+    for (size_t zt = zt0; zt < zt1; ++zt) {
+      int off = 0;
+      for (int q = 0; q < P.nq; ++q) {
         const unsigned v = P.qk[zt * P.nq + q];
-        if ((v >> 16) > (v & 0xffffu)) {
-          lo = std::min(lo, v & 0xffffu);
-          hi = std::max(hi, v >> 16);
-        }
+        P.tofs[zt * P.nq + q] = off;
+        off += 16 * (int)((v >> 16) - (v & 0xffffu));
       }
-      if (hi <= lo) lo = hi = 0;
-      P.qb[zt * P.nqb + bq] = lo | (hi << 16);
+      size_zt[zt] = off;
     }
+  });
+  long long total = 0;
+  for (size_t zt = 0; zt < nzt; ++zt) {
+    P.kbase[zt] = total;
+    total += size_zt[zt];
   }
+  host_parallel(nzt, 256, [&](size_t zt0, size_t zt1) {
+    for (size_t zt = zt0; zt < zt1; ++zt) {
+      for (int q = 0; q < P.nq; ++q) {
+        const unsigned v = P.qk[zt * P.nq + q];
+        P.td[zt * P.nq + q] = TileDesc{P.kbase[zt] + P.tofs[zt * P.nq + q], (int)(v & 0xffffu), (int)(v >> 16)};
+      }
+      for (int bq = 0; bq < P.nqb; ++bq) {
+        unsigned lo = 0xffffu, hi = 0;
+        for (int q = 8 * bq; q < std::min(8 * bq + 8, P.nq); ++q) {
+          const unsigned v = P.qk[zt * P.nq + q];
+          if ((v >> 16) > (v & 0xffffu)) {
+            lo = std::min(lo, v & 0xffffu);
+            hi = std::max(hi, v >> 16);
+          }
+        }
+        if (hi <= lo) lo = hi = 0;
+        P.qb[zt * P.nqb + bq] = lo | (hi << 16);
+      }
+    }
+  });
   P.kentries = (size_t)total;
 }
 

@@ -881,15 +881,27 @@ __global__ void __launch_bounds__(64 * kTileGemmWaves) k_sig_gemm_tiles(
 #pragma unroll
   for (int j = 0; j < 4; ++j)
     for (int r = 0; r < 4; ++r) acc[j][r] = 0.0;
-  for (int k0 = d.lo; k0 < khi; k0 += 4) {
-    const int k = k0 + lk;
-    const double af = (ra >= 0 && k < khi) ? grow[k] : 0.0;
+  // Four K steps per iteration, their loads issued together ahead of the
+  // products.  The loads are unconditional (indices clamped into the valid
+  // range): a bounds test around each load becomes a branch with a wait in
+  // front of its product.  Steps past the range are cancelled through the
+  // Gam operand (times 0); columns past the grid are not stored.
+  const int kmax = max(khi - 1, 0);
+  constexpr int KU = 4;
+  for (int k0 = d.lo; k0 < khi; k0 += 4 * KU) {
+    double af[KU], bf[KU][4];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int col = c0 + 16 * j + lr;
-      const double bf = (k < khi && col < nn) ? Sig[(size_t)k * nn + col] : 0.0;
-      acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af, bf, acc[j], 0, 0, 0);
+    for (int u = 0; u < KU; ++u) {
+      const int k = k0 + 4 * u + lk;
+      const int kc = min(k, kmax);
+      af[u] = grow[kc] * ((ra >= 0 && k < khi) ? 1.0 : 0.0);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bf[u][j] = Sig[(size_t)kc * nn + min(c0 + 16 * j + lr, nn - 1)];
     }
+#pragma unroll
+    for (int u = 0; u < KU; ++u)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[u], bf[u][j], acc[j], 0, 0, 0);
   }
   const int w = d.hi - d.lo;
 #pragma unroll

@@ -748,15 +748,19 @@ __global__ void k_r3_X(int z0, int nu, int nl, int nd, const double* __restrict_
 //                                  W[z][(u',l)][slot(o,o')][c][n][j]  +  R_III term
 // with the angular coefficients precomputed per pair (c = 0 multiplies Re W,
 // c = 1 multiplies Im W).  A block covers one outgoing direction o and 64
-// frequencies (one per lane); its kAngQ waves split the incoming directions
+// frequencies (one per lane); its KQ waves split the incoming directions
 // into contiguous ranges, so within a wave the slot, the pair and hence the
 // coefficients are uniform (scalar loads) and each W load is 64 consecutive
-// frequencies.  The partial sums meet in LDS.
+// frequencies.  The waves also share the R_III outer product (its
+// transition pairs dealt round-robin); the partial sums meet in LDS.  The
+// kernel streams W once and waits on memory: more waves per block keep
+// more loads in flight (KQ = 16 for the single-problem launch at 64 or more
+// directions, 4 otherwise).
 constexpr int kAngQ = 4;
 
-template <typename T, int kAngMaxNl>
+template <typename T, int kAngMaxNl, int KQ>
 __device__ __forceinline__ void angular_body(
-    int bx, int by, T (&red)[kAngQ][64][kAngMaxNl][4], int z0, int nd, int nn, int nu, int nl, int nslot,
+    int bx, int by, T (&red)[KQ][64][kAngMaxNl][4], int z0, int nd, int nn, int nu, int nl, int nslot,
     const int* __restrict__ pair_slot, const int* __restrict__ pair_index, const T* __restrict__ cf,
     const T* __restrict__ W, double c_sc, const double2* __restrict__ E, const double2* __restrict__ bma,
     const double2* __restrict__ X, const double2* __restrict__ prof, T* __restrict__ Eb) {
@@ -779,7 +783,7 @@ __device__ __forceinline__ void angular_body(
 #pragma unroll
     for (int a = 0; a < kAngMaxNl; ++a)
       for (int i = 0; i < 4; ++i) acc[a][i] = T(0);
-    const int chunk = (nd + kAngQ - 1) / kAngQ;
+    const int chunk = (nd + KQ - 1) / KQ;
     const int op1 = min(nd, (q + 1) * chunk);
 #pragma unroll 4
     for (int op = q * chunk; op < op1; ++op) {
@@ -806,6 +810,25 @@ __device__ __forceinline__ void angular_body(
         }
       }
     }
+    // R_III:  D_i(o, l', u, u') = c_sc/(4 pi) (beta - alpha)_{u u'} E_i(o; u', u, l') X[u][u'][l],
+    // this wave's share of the (u, u') pairs
+#pragma unroll
+    for (int lp = 0; lp < kAngMaxNl; ++lp) {
+      if (lp < nl) {
+        double r3[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int k = q; k < nu * nu; k += KQ) {
+          const int u = k / nu, upr = k - u * nu;
+          const double2 bx = cmul(bma[((size_t)z * nu + u) * nu + upr], X[(((size_t)z * nu + u) * nu + upr) * nl + l]);
+          const double2 pa = prof[((size_t)z * nt + upr * nl + l) * nn + nc];
+          const double2 pb = prof[((size_t)z * nt + u * nl + l) * nn + nc];
+          for (int i = 0; i < 4; ++i) {
+            const double2 d = cmul(Ez[((size_t)(i * nu + upr) * nu + u) * nl + lp], bx);
+            r3[i] += d.x * (pa.x + pb.x) - d.y * (pa.y - pb.y);
+          }
+        }
+        for (int i = 0; i < 4; ++i) acc[lp][i] += (T)(sc3 * r3[i]);
+      }
+    }
     if (l > 0) __syncthreads();                        // previous class's partial sums consumed
 #pragma unroll
     for (int lp = 0; lp < kAngMaxNl; ++lp)
@@ -813,41 +836,29 @@ __device__ __forceinline__ void angular_body(
         for (int i = 0; i < 4; ++i) red[q][lane][lp][i] = acc[lp][i];
     __syncthreads();
     if (q != 0 || !live) continue;
-    // R_III:  D_i(o, l', u, u') = c_sc/(4 pi) (beta - alpha)_{u u'} E_i(o; u', u, l') X[u][u'][l]
 #pragma unroll
     for (int lp = 0; lp < kAngMaxNl; ++lp) {
       if (lp < nl) {
-        double r3[4] = {0.0, 0.0, 0.0, 0.0};
-        for (int u = 0; u < nu; ++u)
-          for (int upr = 0; upr < nu; ++upr) {
-            const double2 bx = cmul(bma[((size_t)z * nu + u) * nu + upr], X[(((size_t)z * nu + u) * nu + upr) * nl + l]);
-            const double2 pa = prof[((size_t)z * nt + upr * nl + l) * nn + n];
-            const double2 pb = prof[((size_t)z * nt + u * nl + l) * nn + n];
-            for (int i = 0; i < 4; ++i) {
-              const double2 d = cmul(Ez[((size_t)(i * nu + upr) * nu + u) * nl + lp], bx);
-              r3[i] += d.x * (pa.x + pb.x) - d.y * (pa.y - pb.y);
-            }
-          }
         T* dst = Eb + ((((size_t)zl * nl + l) * nl + lp) * nd + o) * (size_t)nn * 4 + (size_t)n * 4;
         for (int i = 0; i < 4; ++i) {
           T sum = T(0);
-          for (int qq = 0; qq < kAngQ; ++qq) sum += red[qq][lane][lp][i];
-          dst[i] = (T)((double)sum + sc3 * r3[i]);
+          for (int qq = 0; qq < KQ; ++qq) sum += red[qq][lane][lp][i];
+          dst[i] = sum;
         }
       }
     }
   }
 }
 
-template <typename T, int kAngMaxNl>
-__global__ void __launch_bounds__(64 * kAngQ) k_angular(
+template <typename T, int kAngMaxNl, int KQ>
+__global__ void __launch_bounds__(64 * KQ) k_angular(
     int z0, int nd, int nn, int nu, int nl, int nslot, const int* __restrict__ pair_slot,
     const int* __restrict__ pair_index, const T* __restrict__ cf, const T* __restrict__ W, double c_sc,
     const double2* __restrict__ E, const double2* __restrict__ bma, const double2* __restrict__ X,
     const double2* __restrict__ prof, T* __restrict__ Eb) {
-  __shared__ T red[kAngQ][64][kAngMaxNl][4];
-  angular_body<T, kAngMaxNl>(blockIdx.x, blockIdx.y, red, z0, nd, nn, nu, nl, nslot, pair_slot, pair_index, cf,
-                             W, c_sc, E, bma, X, prof, Eb);
+  __shared__ T red[KQ][64][kAngMaxNl][4];
+  angular_body<T, kAngMaxNl, KQ>(blockIdx.x, blockIdx.y, red, z0, nd, nn, nu, nl, nslot, pair_slot, pair_index,
+                                 cf, W, c_sc, E, bma, X, prof, Eb);
 }
 
 // ------------------------------------------------------------------ fused R_II contraction + angular sum
@@ -1350,8 +1361,16 @@ static int sigma_apply_t(trap_ctx* ctx, const T* I, T* eps, int prec, int add_th
     // 4. angular / sublevel sum into Eb (chunk-local heights)
     pr = prof_begin(ctx, TRAP_STAGE_ANGULAR);
     {
-      auto kern = nl == 1 ? k_angular<T, 1> : nl == 2 ? k_angular<T, 2> : nl <= 4 ? k_angular<T, 4> : k_angular<T, 8>;
-      hipLaunchKernelGGL(kern, dim3(zc * nd, ceil_div(nn, 64)), dim3(64 * kAngQ), 0, s, z0, nd, nn, nu, nl,
+      // more waves per block where the directions are many and the partial
+      // sums fit (32 KB of LDS: 16 waves in FP32, 8 in FP64, up to two lower
+      // sublevels)
+      constexpr int KW = sizeof(T) == 4 ? 16 : 8;
+      const bool wide = nd >= 64 && nl <= 2;
+      auto kern = wide ? (nl == 1 ? k_angular<T, 1, KW> : k_angular<T, 2, KW>)
+                       : (nl == 1 ? k_angular<T, 1, kAngQ> : nl == 2 ? k_angular<T, 2, kAngQ>
+                                                            : nl <= 4 ? k_angular<T, 4, kAngQ> : k_angular<T, 8, kAngQ>);
+      const int kq = wide ? KW : kAngQ;
+      hipLaunchKernelGGL(kern, dim3(zc * nd, ceil_div(nn, 64)), dim3(64 * kq), 0, s, z0, nd, nn, nu, nl,
                          P.nslot, P.d_pair_slot, P.d_pair_index, cf, W, P.c_sc, P.d_E, P.d_bma, K.X, C.d_prof,
                          Eb + (size_t)z0 * ncls * nd * nn * 4);
     }
@@ -1561,7 +1580,7 @@ __global__ void __launch_bounds__(64 * kAngQ) k_angular_grouped(const GAngular* 
   const int r = find_req(blockIdx.x, off, n);
   const GAngular& a = A[r];
   const int local = blockIdx.x - off[r];
-  angular_body<float, NLM>(local % a.nbx, local / a.nbx, red, a.z0, a.nd, a.nn, a.nu, a.nl, a.nslot, a.pair_slot,
+  angular_body<float, NLM, kAngQ>(local % a.nbx, local / a.nbx, red, a.z0, a.nd, a.nn, a.nu, a.nl, a.nslot, a.pair_slot,
                            a.pair_index, a.cf, a.W, a.c_sc, a.E, a.bma, a.X, a.prof, a.Eb);
 }
 

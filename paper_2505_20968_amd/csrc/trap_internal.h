@@ -6,7 +6,11 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <memory>
+#include <new>
 #include <string>
+#include <type_traits>
+#include <utility>
 #include <vector>
 
 #include "../../include/trap.h"
@@ -45,6 +49,32 @@ struct DevBuf {
   size_t bytes = 0;
   bool pooled = false;     // from the device's stream-ordered pool (freed with hipFreeAsync)
 };
+
+// ---------------------------------------------------------------- host tables written in full
+// An allocator whose resize leaves trivially constructible elements
+// unwritten (default-initialised): for large host tables that are filled
+// completely right afterwards, often by several threads, so that no serial
+// zero fill precedes the work and each page is first touched by its writer.
+template <typename T>
+struct DefaultInitAlloc : std::allocator<T> {
+  template <typename U>
+  struct rebind {
+    using other = DefaultInitAlloc<U>;
+  };
+  DefaultInitAlloc() = default;
+  template <typename U>
+  DefaultInitAlloc(const DefaultInitAlloc<U>&) noexcept {}
+  template <typename U>
+  void construct(U* p) noexcept(std::is_nothrow_default_constructible<U>::value) {
+    ::new (static_cast<void*>(p)) U;
+  }
+  template <typename U, typename... A>
+  void construct(U* p, A&&... a) {
+    ::new (static_cast<void*>(p)) U(std::forward<A>(a)...);
+  }
+};
+template <typename T>
+using host_vec = std::vector<T, DefaultInitAlloc<T>>;
 
 // ---------------------------------------------------------------- banded kernel store
 // Each R_II kernel row is nonzero only where the Gaussian factor of F reaches
@@ -123,12 +153,13 @@ struct Problem {
   int band_reach = 0;
   int nnp = 0, nq = 0, nqb = 0, qpad = 0;
   std::vector<long long> kbase;
-  std::vector<int> tofs, qrow0;
-  std::vector<unsigned> qk, qb;
+  host_vec<int> tofs;
+  std::vector<int> qrow0;
+  host_vec<unsigned> qk, qb;
   size_t kentries = 0;
   double band_nnz = 0.0;
   std::vector<double> kflops_z;
-  std::vector<TileDesc> td;
+  host_vec<TileDesc> td;
   TileDesc* d_td = nullptr;
   unsigned* d_qb = nullptr;
   double c_abs = 0, c_sc = 0;
@@ -339,8 +370,8 @@ struct UploadBatch {
     items.push_back(Item{dst, src, bytes, off});
     total = off + (bytes ? bytes : 16);
   }
-  template <typename T>
-  void add(T** dst, const std::vector<T>& v) {
+  template <typename T, typename A>
+  void add(T** dst, const std::vector<T, A>& v) {
     add(reinterpret_cast<void**>(dst), v.data(), v.size() * sizeof(T));
   }
   int commit(trap_ctx* ctx);
