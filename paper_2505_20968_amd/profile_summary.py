@@ -2,8 +2,11 @@
 
     python -m paper_2505_20968_amd.profile_summary stats KERNEL_STATS_CSV OUT --command "..."
     python -m paper_2505_20968_amd.profile_summary traffic FETCH_CSV WRITE_CSV OUT --command "..."
+    python -m paper_2505_20968_amd.profile_summary counters PASS_CSV [PASS_CSV ...] OUT --command "..."
 
 `stats` keeps the per-kernel table of a `--kernel-trace --stats` run.
+`counters` sums `--pmc` passes per kernel and derives matrix-core busy time,
+executed matrix-core flops, VALU and wait fractions of the wave cycles.
 `traffic` takes two `--pmc FETCH_SIZE` / `--pmc WRITE_SIZE` runs of a command
 that also launched the calibration kernel (an elementwise negation reading and
 writing COPY_BYTES), scales both counters by what they read for that kernel,
@@ -105,6 +108,49 @@ def traffic(fetch_csv: str, write_csv: str, out: str, command: str) -> None:
         f.write("\n".join(lines) + "\n")
 
 
+def counters(paths, out: str, command: str, xcds: int = 8, simds: int = 1024) -> None:
+    """Per kernel: counters summed over dispatches (each pass divided by its
+    own dispatch count), then
+      mfma_busy = SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE / xcds * simds)
+    (GRBM_GUI_ACTIVE adds the active cycles of every XCD; the busy cycles add
+    over every SIMD), executed matrix-core flops = 512 x the MOPS counters,
+    and SQ_ACTIVE_INST_VALU, SQ_WAIT_ANY, SQ_WAIT_INST_ANY over SQ_WAVE_CYCLES."""
+    tot: dict[str, dict[str, float]] = {}
+    for path in paths:
+        per: dict[str, dict[str, float]] = {}
+        disp: dict[str, set] = {}
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                k = r["Kernel_Name"].split("(")[0].replace("void ", "")
+                per.setdefault(k, {}).setdefault(r["Counter_Name"], 0.0)
+                per[k][r["Counter_Name"]] += float(r["Counter_Value"])
+                disp.setdefault(k, set()).add(r["Dispatch_Id"])
+        for k, v in per.items():
+            d = tot.setdefault(k, {"dispatches": float(len(disp[k]))})
+            for c, x in v.items():
+                d[c] = x / len(disp[k])           # per dispatch
+    lines = [f"command: {command}",
+             f"per dispatch, averaged; mfma_busy = SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE / {xcds} x {simds} SIMDs)",
+             "",
+             f"{'kernel':44s} {'disp':>6s} {'mfma_busy':>9s} {'mfma_GF':>9s} {'valu_act':>8s} {'wait_any':>8s} "
+             f"{'wait_dep':>8s} {'valu/wave':>9s}"]
+    for k, d in sorted(tot.items(), key=lambda kv: -kv[1].get("GRBM_GUI_ACTIVE", 0.0) * kv[1]["dispatches"]):
+        g = d.get("GRBM_GUI_ACTIVE", 0.0)
+        busy = d.get("SQ_VALU_MFMA_BUSY_CYCLES")
+        mb = f"{100 * busy / (g / xcds * simds):8.1f}%" if busy is not None and g else f"{'-':>9s}"
+        gf = sum(d.get(c, 0.0) for c in ("SQ_INSTS_VALU_MFMA_MOPS_F32", "SQ_INSTS_VALU_MFMA_MOPS_F64",
+                                          "SQ_INSTS_VALU_MFMA_MOPS_F16", "SQ_INSTS_VALU_MFMA_MOPS_BF16")) * 512 / 1e9
+        wc = d.get("SQ_WAVE_CYCLES")
+
+        def frac(c):
+            return f"{d[c] / wc:8.3f}" if wc and c in d else f"{'-':>8s}"
+        vpw = f"{d['SQ_INSTS_VALU'] / d['SQ_WAVES']:9.0f}" if "SQ_INSTS_VALU" in d and d.get("SQ_WAVES") else f"{'-':>9s}"
+        lines.append(f"{_short(k, 44):44s} {int(d['dispatches']):6d} {mb} {gf:9.2f} {frac('SQ_ACTIVE_INST_VALU')} "
+                     f"{frac('SQ_WAIT_ANY')} {frac('SQ_WAIT_INST_ANY')} {vpw}")
+    with open(out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     sub = ap.add_subparsers(dest="mode", required=True)
@@ -117,9 +163,15 @@ def main():
     b.add_argument("write_csv")
     b.add_argument("out")
     b.add_argument("--command", required=True)
+    c = sub.add_parser("counters")
+    c.add_argument("csvs", nargs="+")
+    c.add_argument("out")
+    c.add_argument("--command", required=True)
     args = ap.parse_args()
     if args.mode == "stats":
         stats(args.csv, args.out, args.command)
+    elif args.mode == "counters":
+        counters(args.csvs, args.out, args.command)
     else:
         traffic(args.fetch_csv, args.write_csv, args.out, args.command)
 
