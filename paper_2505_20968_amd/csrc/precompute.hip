@@ -38,6 +38,7 @@ __device__ inline double2 wz(double x, double y) { return faddeeva_w(x, y, c_fad
 // The per-row divisors are kept as reciprocals (an FP64 division costs about
 // ten vector instructions, a product one).
 struct FParams {
+  double sG, cG;     // sin(Theta/2), cos(Theta/2) (1, 0 at Theta = pi)
   double inv2sG;     // 1 / (2 sin(Theta/2))
   double inv2cG;     // 1 / (2 cos(Theta/2))
   double a_cG;       // a / cos(Theta/2)
@@ -49,11 +50,14 @@ struct FParams {
 __device__ inline FParams f_params(double Th, double a) {
   FParams p;
   p.pi_limit = (Th >= kPiD);
-  const double sG = p.pi_limit ? 1.0 : sin(0.5 * Th), cG = p.pi_limit ? 1.0 : cos(0.5 * Th);
+  double sG = 1.0, cG = 0.0;
+  if (!p.pi_limit) sincos(0.5 * Th, &sG, &cG);
+  p.sG = sG;
+  p.cG = cG;
   p.inv2sG = 0.5 / sG;
-  p.inv2cG = 0.5 / cG;
-  p.a_cG = a / cG;
-  p.inv_sinT = p.pi_limit ? 0.0 : 1.0 / sin(Th);
+  p.inv2cG = p.pi_limit ? 0.0 : 0.5 / cG;
+  p.a_cG = p.pi_limit ? 0.0 : a / cG;
+  p.inv_sinT = p.pi_limit ? 0.0 : 1.0 / (2.0 * sG * cG);      // sin(Theta) = 2 sin(Theta/2) cos(Theta/2)
   p.a = a;
   return p;
 }
@@ -347,12 +351,12 @@ __global__ void __launch_bounds__(64, 3) k_kernel_rows(
     return;
   }
   const FParams fp = f_params(Th, a);
-  const double sigma = 2.0 * sin(0.5 * fmin(Th, kPiD)) / L;
+  const double sigma = 2.0 * fp.sG / L;
   const double R = 6.6 * sigma;
   const double xn = x[n];
   const double lo = xn - R, hi = xn + R;
   const double xc = -xn - 2.0 * s / L;
-  const double wc = 2.0 * fmax(fp.pi_limit ? 0.0 : cos(0.5 * Th), a) / L;
+  const double wc = 2.0 * fmax(fp.cG, a) / L;
   const double Lg = 1.5 * sigma;
   for (int i = lane; i < 2 * nn; i += 64) Lacc[i] = make_double2(0.0, 0.0);
   wave_sync();
@@ -379,9 +383,12 @@ __global__ void __launch_bounds__(64, 3) k_kernel_rows(
   // Its pieces (knot intervals, and the tails past the grid ends) are cut
   // into panels graded towards the core; the row's panel list is built in
   // LDS (a lane per piece, offsets from a prefix sum over the wave) and its
-  // (panel, node) pairs are spread over the lanes, sixteen lanes per panel,
-  // so the work per lane follows the row's panel count and not the number of
-  // pieces a lane's share of the support happens to cross.  Every other
+  // (panel, node) pairs are spread over the lanes, four lanes per panel and
+  // four nodes per lane, so the work per lane follows the row's panel count
+  // and not the number of pieces a lane's share of the support happens to
+  // cross.  (Four lanes per panel: with sixteen, rows whose support crosses
+  // many short knot intervals reduce over sixteen lanes at nearly every
+  // panel; with one, rows of few panels leave most lanes idle.)  Every other
   // interval of the support takes the table rule, one lane per interval
   // (virtual intervals of width h past the grid ends for the tails, where the
   // spline is extended flat).
@@ -464,8 +471,13 @@ __global__ void __launch_bounds__(64, 3) k_kernel_rows(
     }
     const int total = __shfl(off, 63, 64);
     off -= mine;
-    const int g = lane >> 4, i = lane & 15;
-    const double tg = c_gl_t[i], wg = c_gl_w[i];
+    const int g = lane >> 2, i4 = lane & 3;        // panel group, first node
+    double tg[4], wg[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      tg[u] = c_gl_t[i4 + 4 * u];
+      wg[u] = c_gl_w[i4 + 4 * u];
+    }
     for (int w0 = 0; w0 < total; w0 += kPanelCap) {
       const int w1 = min(total, w0 + kPanelCap);
       // this window's panels into LDS
@@ -483,9 +495,9 @@ __global__ void __launch_bounds__(64, 3) k_kernel_rows(
         });
       }
       wave_sync();
-      // node i of panels g, g + 4, ...: moments summed in registers while the
-      // interval stays the same, then over the sixteen lanes of the panel and
-      // into the node accumulators
+      // nodes i4, i4 + 4, i4 + 8, i4 + 12 of panels g, g + 16, ...: moments
+      // summed in registers while the interval stays the same, then over the
+      // four lanes of the panel and into the node accumulators
       double2 acc[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
       int cur = -2;
       const int np = w1 - w0;
@@ -493,29 +505,32 @@ __global__ void __launch_bounds__(64, 3) k_kernel_rows(
 #pragma unroll
         for (int q = 0; q < 4; ++q)
 #pragma unroll
-          for (int d = 8; d >= 1; d >>= 1) {
-            acc[q].x += __shfl_xor(acc[q].x, d, 16);
-            acc[q].y += __shfl_xor(acc[q].y, d, 16);
+          for (int d = 2; d >= 1; d >>= 1) {
+            acc[q].x += __shfl_xor(acc[q].x, d, 4);
+            acc[q].y += __shfl_xor(acc[q].y, d, 4);
           }
-        if (i == 0) add_moments(Lacc, Gacc, x, nn, cur, acc);
+        if (i4 == 0) add_moments(Lacc, Gacc, x, nn, cur, acc);
 #pragma unroll
         for (int q = 0; q < 4; ++q) acc[q] = make_double2(0.0, 0.0);
       };
-      for (int pb0 = 0; pb0 < np; pb0 += 4) {
+      for (int pb0 = 0; pb0 < np; pb0 += 16) {
         const int pi = pb0 + g;
         const int k = pi < np ? pk[pi] : -2;
-        if (cur != -2 && k != cur) flush();         // uniform over the sixteen lanes of group g
+        if (cur != -2 && k != cur) flush();         // uniform over the four lanes of group g
         cur = k;
         if (pi < np) {
           const double2 lw = plw[pi], tt = pts[pi];
-          const double2 v = integrand(lw.x + lw.y * tg);
-          double tp = lw.y * wg;
-          const double tq = tt.x + tt.y * tg;
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            acc[q].x += tp * v.x;
-            acc[q].y += tp * v.y;
-            tp *= tq;
+          for (int u = 0; u < 4; ++u) {
+            const double2 v = integrand(lw.x + lw.y * tg[u]);
+            double tp = lw.y * wg[u];
+            const double tq = tt.x + tt.y * tg[u];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              acc[q].x += tp * v.x;
+              acc[q].y += tp * v.y;
+              tp *= tq;
+            }
           }
         }
       }
