@@ -51,16 +51,19 @@ def _gen(name):
     return make
 
 
-# workload generator, description, default timed steps
+# workload generator, description, default timed steps, default preconditioner
+# steps (a block-Jacobi step costs about 1 % of an operator apply at the
+# Ly-alpha-like size, where 32 steps cut the iterations from 10 to 7, and
+# about 6 % at cfg2, where 4 steps do best)
 CONFIGS = {
     "cfg2": (_gen("cfg2"), "two-level J0->1 PRD-AD chromosphere-like column: N_z=70, N_nu=101 on [-12,12], "
-                           "4+4 GL mu x 8 chi, seeded B/v/a/eps, tol 1e-8", 5),
+                           "4+4 GL mu x 8 chi, seeded B/v/a/eps, tol 1e-8", 5, 4),
     "cfg3": (_gen("cfg3"), "two-term 2S1/2 -> 2P1/2,3/2 Mg II h&k-like doublet (fine structure 20 Doppler "
                            "widths, J-state interference), PRD-AD: N_z=80, N_nu=200 to +-50, 6+6 GL mu x 8 chi, "
-                           "seeded chromosphere-like column, tol 1e-8", 3),
+                           "seeded chromosphere-like column, tol 1e-8", 3, 4),
     "cfg4": (_gen("cfg4"), "two-term H I Ly-alpha-like line (fine structure 0.3 Doppler width, a 1e-2..1e-1, "
                            "|B| 1-300 G), PRD-AD: N_z=100, N_nu=301 on a sinh grid to +-1000 Doppler widths, "
-                           "8+8 GL mu x 8 chi, seeded chromosphere-like column, tol 1e-8", 3),
+                           "8+8 GL mu x 8 chi, seeded chromosphere-like column, tol 1e-8", 3, 32),
 }
 
 
@@ -280,7 +283,7 @@ def main():
     ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--restart", type=int, default=40)
-    ap.add_argument("--precond-sweeps", type=int, default=4,
+    ap.add_argument("--precond-sweeps", type=int, default=None,
                     help="block-Jacobi steps of the physics-based preconditioner (0: none)")
     ap.add_argument("--serve-precond-sweeps", type=int, default=1,
                     help="the same for the serving measurement (its requests are smaller and its host "
@@ -304,7 +307,9 @@ def main():
     import numpy as np
     import torch
     from paper_2505_20968_amd import Context, TRAP_FP32, TRAP_FP64
-    gen, workload, default_steps = CONFIGS[args.config]
+    gen, workload, default_steps, default_sweeps = CONFIGS[args.config]
+    if args.precond_sweeps is None:
+        args.precond_sweeps = default_sweeps
     if args.steps is None:
         args.steps = default_steps
 
