@@ -289,7 +289,7 @@ def main():
                     help="the same for the serving measurement (its requests are smaller and its host "
                          "loop issues every request's preconditioner launches, so fewer steps pay)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=12,
+    ap.add_argument("--serve-requests", type=int, default=24,
                     help="requests in the serving measurement (0 skips it)")
     ap.add_argument("--no-aa", action="store_true",
                     help="skip the angle-averaged solve of the timed atmosphere (outside the timed region)")
