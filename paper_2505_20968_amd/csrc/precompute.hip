@@ -27,6 +27,8 @@ namespace trap {
 __constant__ FaddeevaCoef c_fad;
 __constant__ double c_gl_t[16];
 __constant__ double c_gl_w[16];
+__constant__ double c_gl8_t[8];      // Gauss-Legendre 8 on [0, 1]
+__constant__ double c_gl8_w[8];
 
 static constexpr double kSqrtPi = 1.7724538509055160273;
 static constexpr double kInvSqrtPi = 0.56418958354775628695;
@@ -75,6 +77,28 @@ __device__ inline double2 Ffun(const FParams& p, double up, double u) {
   if (g == 0.0) return make_double2(0.0, 0.0);
   const double2 w = wz((u + up) * p.inv2cG, p.a_cG);
   return make_double2(g * w.x * p.inv_sinT, g * w.y * p.inv_sinT);
+}
+
+// F(Theta, up_j, u) at K frequencies up_j of one row, their Faddeeva factors
+// evaluated side by side (faddeeva_wk).
+template <int K>
+__device__ inline void Ffun_k(const FParams& p, const double (&up)[K], double u, double2 (&out)[K]) {
+  if (p.pi_limit) {
+#pragma unroll
+    for (int j = 0; j < K; ++j) out[j] = Ffun(p, up[j], u);
+    return;
+  }
+  double xw[K], g[K];
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    const double q = (u - up[j]) * p.inv2sG;
+    g[j] = exp(-q * q) * p.inv_sinT;
+    xw[j] = (u + up[j]) * p.inv2cG;
+  }
+  double2 w[K];
+  faddeeva_wk<K>(xw, p.a_cG, c_fad, w);
+#pragma unroll
+  for (int j = 0; j < K; ++j) out[j] = make_double2(g[j] * w[j].x, g[j] * w[j].y);
 }
 
 // ------------------------------------------------------------------ profiles
@@ -262,7 +286,8 @@ __global__ void k_kernel_tables(int z0, int nth, int nt, int nn, int ntail, doub
 // with Sig = d s / d v the spline's second-derivative map; L and Gam are
 // accumulated per node in LDS and written here, the product with Sig is one
 // batched GEMM (k_sig_gemm, k_sig_gemm_tiles).
-constexpr int kPanelCap = 64;         // graded panels listed per window of one row
+constexpr int kPanelCap = 64;         // graded work units listed per window of one row
+constexpr double kGl8Ratio = 0.15;    // panels up to this fraction of F's local scale take 8 nodes
 
 // LDS of one row: node accumulators L[nn], Gam[nn] (complex), then one window
 // of the graded panel list: {left, width}, {t at left, t span} and the knot
@@ -320,7 +345,7 @@ __global__ void __launch_bounds__(64, 3) k_kernel_rows(
     const double* __restrict__ lam, const double* __restrict__ av, const double* __restrict__ st,
     const double* __restrict__ theta, double* __restrict__ Lout, double* __restrict__ Gout,
     long long row0, int z0, double h_uniform, const double* __restrict__ Gt,
-    const double2* __restrict__ Vt, int ntail, RowRoles roles) {
+    const double2* __restrict__ Vt, int ntail, RowRoles roles, int2* __restrict__ gspan) {
   extern __shared__ double2 smem[];    // kernel_row_lds(nn) bytes
   const int lane = threadIdx.x;
   double2* Lacc = smem;
@@ -335,13 +360,19 @@ __global__ void __launch_bounds__(64, 3) k_kernel_rows(
   const int t = (row / nn) % nt;
   const int th = (row / ((long long)nn * nt)) % nth;
   const int z = z0 + (int)(row / ((long long)nn * nt * nth));
-  if (row_mirrored(roles, t, n, nn)) return;                    // filled by k_mirror_rows
+  // gspan (optional): the node range [x, y] outside which the row's Gam is
+  // zero (empty: x > y), for the K range of the product with Sig
+  if (row_mirrored(roles, t, n, nn)) {                          // filled by k_mirror_rows
+    if (gspan && lane == 0) gspan[row] = make_int2(nn, -1);
+    return;
+  }
   const double L = lam[z], a = av[z], s = st[z * nt + t], Th = theta[th];
   // chunk-local row index of the real plane; the imaginary plane follows nn rows later
   const size_t cbase = (size_t)((((size_t)(z - z0) * nth + th) * nt + t) * 2) * nn * ldm;
   const size_t rre = cbase + (size_t)n * ldm, rim = cbase + (size_t)nn * ldm + (size_t)n * ldm;
   if (Th == 0.0) {
     const double2 w = wz(L * x[n] + s, a);
+    if (gspan && lane == 0) gspan[row] = make_int2(nn, -1);
     for (int m = lane; m < ldm; m += 64) {
       Lout[rre + m] = (m == n) ? kSqrtPi * w.x : 0.0;
       Lout[rim + m] = (m == n) ? kSqrtPi * w.y : 0.0;
@@ -365,10 +396,6 @@ __global__ void __launch_bounds__(64, 3) k_kernel_rows(
   int phi = upper_interval(x, nn, hi);
   if (phi >= 0 && phi < nn - 1 && x[phi] >= hi) phi -= 1;
   const double un = L * xn + s;
-  auto integrand = [&](double xp) {
-    const double2 F = Ffun(fp, L * xp + s, un);
-    return make_double2(L * F.x, L * F.y);
-  };
   // table fast path: uniform grid, Gaussian resolved by the interval nodes
   const bool fast = (Gt != nullptr) && (sigma >= 0.5 * h_uniform);
   const int nd2 = 2 * nn - 1 + 2 * ntail;
@@ -381,17 +408,19 @@ __global__ void __launch_bounds__(64, 3) k_kernel_rows(
   // the whole support when the Gaussian is narrower than half an interval or
   // the grid is not uniform, else the intervals next to a sharp Voigt core.
   // Its pieces (knot intervals, and the tails past the grid ends) are cut
-  // into panels graded towards the core; the row's panel list is built in
-  // LDS (a lane per piece, offsets from a prefix sum over the wave) and its
-  // (panel, node) pairs are spread over the lanes, four lanes per panel and
-  // four nodes per lane, so the work per lane follows the row's panel count
-  // and not the number of pieces a lane's share of the support happens to
-  // cross.  (Four lanes per panel: with sixteen, rows whose support crosses
-  // many short knot intervals reduce over sixteen lanes at nearly every
-  // panel; with one, rows of few panels leave most lanes idle.)  Every other
-  // interval of the support takes the table rule, one lane per interval
-  // (virtual intervals of width h past the grid ends for the tails, where the
-  // spline is extended flat).
+  // into panels graded towards the core, each taking the 16-node rule or,
+  // when it is short against the local scale of F, the 8-node rule; the
+  // row's list of eight-node work units is built in LDS (a lane per piece,
+  // offsets from a prefix sum over the wave) and the units are spread over
+  // the lanes, four lanes per unit and two nodes per lane (their Faddeeva
+  // factors evaluated side by side), so the work per lane follows the row's
+  // node count and not the number of pieces a lane's share of the support
+  // happens to cross.  (Four lanes per unit: with sixteen, rows whose
+  // support crosses many short knot intervals reduce over sixteen lanes at
+  // nearly every unit; with one, rows of few units leave most lanes idle.)
+  // Every other interval of the support takes the table rule, one lane per
+  // interval (virtual intervals of width h past the grid ends for the tails,
+  // where the spline is extended flat).
   const double x0 = x[0];
   auto xk = [&](int k) { return (k >= 0 && k < nn) ? x[k] : x0 + h_uniform * k; };
   const int kmin = fast ? (int)floor((lo - x0) / h_uniform) : 0;
@@ -425,6 +454,9 @@ __global__ void __launch_bounds__(64, 3) k_kernel_rows(
   }
   // table rule: knot intervals inside the support, one lane per interval
   const int ilo = max(plo, 0), ihi = min(phi, nn - 2);
+  // Gam gets the moments of inner knot intervals only (the tails add to L),
+  // all of them in [ilo, ihi] (the graded pieces lie inside [plo, phi])
+  if (gspan && lane == 0) gspan[row] = ilo <= ihi ? make_int2(ilo, ihi + 1) : make_int2(nn, -1);
   for (int p = ilo + lane; fast && p <= ihi; p += 64) {
     if (p >= kA && p <= kB) continue;
     double2 acc[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
@@ -457,11 +489,20 @@ __global__ void __launch_bounds__(64, 3) k_kernel_rows(
       xl = inner ? x[k] : 0.0;
       invh = inner ? 1.0 / (x[k + 1] - x[k]) : 0.0;
     };
-    int mine = 0;                                    // this lane's panel count
+    // Work units of eight nodes: a panel takes the 16-node rule (two units)
+    // unless it spans at most kGl8Ratio of the local scale of F, the
+    // smaller of the Gaussian's panel cap Lg and the Voigt scale
+    // max(wc, distance to the core); there the 8-node rule (one unit) is
+    // as accurate.
+    auto units_of = [&](double l, double r) -> int {
+      const double d = (xc > l && xc < r) ? 0.0 : fmin(fabs(l - xc), fabs(r - xc));
+      return (r - l) <= kGl8Ratio * fmin(Lg, fmax(wc, d)) ? 1 : 2;
+    };
+    int mine = 0;                                    // this lane's unit count
     for (int j = lane; j < npc; j += 64) {
       double pa, pb, xl, invh;
       piece(gA + j, pa, pb, xl, invh);
-      graded_panels(pa, pb, xc, wc, Lg, [&](double, double) { ++mine; });
+      graded_panels(pa, pb, xc, wc, Lg, [&](double l, double r) { mine += units_of(l, r); });
     }
     int off = mine;                                  // inclusive prefix over lanes
 #pragma unroll
@@ -471,33 +512,43 @@ __global__ void __launch_bounds__(64, 3) k_kernel_rows(
     }
     const int total = __shfl(off, 63, 64);
     off -= mine;
-    const int g = lane >> 2, i4 = lane & 3;        // panel group, first node
-    double tg[4], wg[4];
+    const int g = lane >> 2, i4 = lane & 3;        // unit group, first node
+    double tg[4], wg[4], t8[2], w8[2];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       tg[u] = c_gl_t[i4 + 4 * u];
       wg[u] = c_gl_w[i4 + 4 * u];
     }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      t8[u] = c_gl8_t[i4 + 4 * u];
+      w8[u] = c_gl8_w[i4 + 4 * u];
+    }
     for (int w0 = 0; w0 < total; w0 += kPanelCap) {
       const int w1 = min(total, w0 + kPanelCap);
-      // this window's panels into LDS
+      // this window's units into LDS: the panel, and its knot interval k and
+      // node set (0, 1: the two halves of the 16-node rule, 2: the 8-node
+      // rule) packed as (k + 1) << 2 | set
       int e = off;
       for (int j = lane; j < npc && e < w1; j += 64) {
         double pa, pb, xl, invh;
         piece(gA + j, pa, pb, xl, invh);
         graded_panels(pa, pb, xc, wc, Lg, [&](double l, double r) {
-          if (e >= w0 && e < w1) {
-            plw[e - w0] = make_double2(l, r - l);
-            pts[e - w0] = make_double2((l - xl) * invh, (r - l) * invh);
-            pk[e - w0] = gA + j;
+          const int nu = units_of(l, r);
+          for (int h = 0; h < nu; ++h, ++e) {
+            if (e >= w0 && e < w1) {
+              plw[e - w0] = make_double2(l, r - l);
+              pts[e - w0] = make_double2((l - xl) * invh, (r - l) * invh);
+              pk[e - w0] = ((gA + j + 1) << 2) | (nu == 1 ? 2 : h);
+            }
           }
-          ++e;
         });
       }
       wave_sync();
-      // nodes i4, i4 + 4, i4 + 8, i4 + 12 of panels g, g + 16, ...: moments
-      // summed in registers while the interval stays the same, then over the
-      // four lanes of the panel and into the node accumulators
+      // nodes i4 and i4 + 4 of each unit's node set (of the 16-node rule:
+      // i4 + 8 and i4 + 12 in its second half) of units g, g + 16, ...:
+      // moments summed in registers while the interval stays the same, then
+      // over the four lanes of the unit and into the node accumulators
       double2 acc[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
       int cur = -2;
       const int np = w1 - w0;
@@ -515,16 +566,27 @@ __global__ void __launch_bounds__(64, 3) k_kernel_rows(
       };
       for (int pb0 = 0; pb0 < np; pb0 += 16) {
         const int pi = pb0 + g;
-        const int k = pi < np ? pk[pi] : -2;
+        const int code = pi < np ? pk[pi] : 0;
+        const int k = pi < np ? (code >> 2) - 1 : -2;
         if (cur != -2 && k != cur) flush();         // uniform over the four lanes of group g
         cur = k;
         if (pi < np) {
           const double2 lw = plw[pi], tt = pts[pi];
+          const int set = code & 3;
+          const double tn[2] = {set == 2 ? t8[0] : set == 1 ? tg[2] : tg[0],
+                                set == 2 ? t8[1] : set == 1 ? tg[3] : tg[1]};
+          const double wn[2] = {set == 2 ? w8[0] : set == 1 ? wg[2] : wg[0],
+                                set == 2 ? w8[1] : set == 1 ? wg[3] : wg[1]};
+          double upn[2];
+          double2 Fn[2];
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const double2 v = integrand(lw.x + lw.y * tg[u]);
-            double tp = lw.y * wg[u];
-            const double tq = tt.x + tt.y * tg[u];
+          for (int u = 0; u < 2; ++u) upn[u] = L * (lw.x + lw.y * tn[u]) + s;
+          Ffun_k<2>(fp, upn, un, Fn);
+#pragma unroll
+          for (int u = 0; u < 2; ++u) {
+            const double2 v = make_double2(L * Fn[u].x, L * Fn[u].y);
+            double tp = lw.y * wn[u];
+            const double tq = tt.x + tt.y * tn[u];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
               acc[q].x += tp * v.x;
@@ -860,7 +922,8 @@ __global__ void __launch_bounds__(512, 1) k_sig_gemm_lds(long long nrows, int nn
 constexpr int kTileGemmWaves = 4;
 __global__ void __launch_bounds__(64 * kTileGemmWaves) k_sig_gemm_tiles(
     int zc, int nth, int nt, int nn, int ldm, int nnp, int nq, int ncg, const double* __restrict__ Gam,
-    const double* __restrict__ Lrow, const double* __restrict__ Sig, BandOut B, RowRoles roles) {
+    const double* __restrict__ Lrow, const double* __restrict__ Sig, BandOut B, RowRoles roles,
+    const int2* __restrict__ gspan) {
   const long long unit = (long long)blockIdx.x * kTileGemmWaves + (threadIdx.x >> 6);
   const long long nunit = (long long)zc * nth * nq * ncg;
   if (unit >= nunit) return;
@@ -891,7 +954,21 @@ __global__ void __launch_bounds__(64 * kTileGemmWaves) k_sig_gemm_tiles(
   }
   const long long ra = crow(lr);
   const double* grow = Gam + (ra < 0 ? 0 : ra) * ldm;
-  const int khi = min(d.hi, nn);
+  // K range: the tile's column range, cut to the union of its rows' Gam
+  // spans (Gam is zero outside them, so the sum is the same)
+  int klo = d.lo, khi = min(d.hi, nn);
+  if (gspan) {
+    // complex row of real row ra = [zl][th][t][c][n]: [zl][th][t][n]
+    const int2 sp = ra < 0 ? make_int2(nn, -1) : gspan[(ra / (2LL * nn)) * nn + ra % nn];
+    int a0 = sp.x, a1 = sp.y;
+#pragma unroll
+    for (int m = 1; m < 16; m <<= 1) {
+      a0 = min(a0, __shfl_xor(a0, m, 64));
+      a1 = max(a1, __shfl_xor(a1, m, 64));
+    }
+    klo = max(klo, a0);
+    khi = min(khi, a1 + 1);
+  }
   doublex4_g acc[4];
 #pragma unroll
   for (int j = 0; j < 4; ++j)
@@ -903,7 +980,7 @@ __global__ void __launch_bounds__(64 * kTileGemmWaves) k_sig_gemm_tiles(
   // Gam operand (times 0); columns past the grid are not stored.
   const int kmax = max(khi - 1, 0);
   constexpr int KU = 4;
-  for (int k0 = d.lo; k0 < khi; k0 += 4 * KU) {
+  for (int k0 = klo; k0 < khi; k0 += 4 * KU) {
     double af[KU], bf[KU][4];
 #pragma unroll
     for (int u = 0; u < KU; ++u) {
@@ -1174,49 +1251,54 @@ __global__ void k_theta_average(long long per_z_out, int ng, int zc, int ldm, co
   band_put(B, i, v);
 }
 
+// Gauss-Legendre rule of n nodes on [0, 1], nodes ascending: the roots of
+// P_n by Newton's method from the usual cosine guesses, weights
+// 1 / ((1 - z^2) P_n'(z)^2) (halved with the map from [-1, 1]).
+static void gauss_legendre01(int n, double* t, double* w) {
+  auto legendre = [n](double z, double* dp) {
+    double p0 = 1.0, p1 = z;
+    for (int k = 2; k <= n; ++k) {
+      const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+      p0 = p1;
+      p1 = p2;
+    }
+    *dp = n * (z * p1 - p0) / (z * z - 1.0);
+    return p1;
+  };
+  for (int i = 0; i < n; ++i) {
+    double z = cos(kPiD * (i + 0.75) / (n + 0.5)), dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      const double dz = legendre(z, &dp) / dp;
+      z -= dz;
+      if (fabs(dz) < 1e-16) break;
+    }
+    legendre(z, &dp);
+    t[i] = 0.5 * (1.0 - z);
+    w[i] = 1.0 / ((1.0 - z * z) * dp * dp);
+  }
+}
+
 // The Faddeeva and quadrature constants: computed once per process, copied to
 // each device's constant memory once (the copy waits for the device).
 static int load_constants(int device) {
   static std::mutex mu;
   static bool coef_ready = false;
   static FaddeevaCoef hc;
-  static double gt[16], gw[16];
+  static double gt[16], gw[16], gt8[8], gw8[8];
   static std::set<int> devices_loaded;
   std::lock_guard<std::mutex> lk(mu);
   if (!coef_ready) {
     faddeeva_coefficients(&hc);
-    // Gauss-Legendre 16 on [0,1] (Newton on P_16)
-    const int n = 16;
-    for (int i = 0; i < n; ++i) {
-      double zz = cos(kPiD * (i + 0.75) / (n + 0.5)), dp = 1.0;
-      for (int it = 0; it < 100; ++it) {
-        double p0 = 1.0, p1 = zz;
-        for (int k = 2; k <= n; ++k) {
-          double p2 = ((2.0 * k - 1.0) * zz * p1 - (k - 1.0) * p0) / k;
-          p0 = p1;
-          p1 = p2;
-        }
-        dp = n * (zz * p1 - p0) / (zz * zz - 1.0);
-        const double dz = p1 / dp;
-        zz -= dz;
-        if (fabs(dz) < 1e-16) break;
-      }
-      double p0 = 1.0, p1 = zz;
-      for (int k = 2; k <= n; ++k) {
-        double p2 = ((2.0 * k - 1.0) * zz * p1 - (k - 1.0) * p0) / k;
-        p0 = p1;
-        p1 = p2;
-      }
-      dp = n * (zz * p1 - p0) / (zz * zz - 1.0);
-      gt[i] = 0.5 * (1.0 - zz);
-      gw[i] = 1.0 / ((1.0 - zz * zz) * dp * dp);
-    }
+    gauss_legendre01(16, gt, gw);
+    gauss_legendre01(8, gt8, gw8);
     coef_ready = true;
   }
   if (!devices_loaded.count(device)) {
     TRAP_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_fad), &hc, sizeof(hc)));
     TRAP_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_gl_t), gt, sizeof(gt)));
     TRAP_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_gl_w), gw, sizeof(gw)));
+    TRAP_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_gl8_t), gt8, sizeof(gt8)));
+    TRAP_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_gl8_w), gw8, sizeof(gw8)));
     devices_loaded.insert(device);
   }
   return TRAP_OK;
@@ -1317,6 +1399,7 @@ int run_precompute(trap_ctx* ctx, int store_mask) {
   if (!C.d_Lrow || C.zc_rows < zc_tab) {
     TRAP_TRY(dalloc_t(ctx, &C.d_Lrow, (size_t)zc_tab * rows_per_z * P.ldm));
     TRAP_TRY(dalloc_t(ctx, &C.d_Grow, (size_t)zc_tab * rows_per_z * P.ldm));
+    TRAP_TRY(dalloc_t(ctx, &C.d_gspan, (size_t)zc_tab * rows_per_z / 2));
     if (aa) TRAP_TRY(dalloc_t(ctx, &C.d_Mtmp, (size_t)zc_tab * rows_per_z * P.ldm));
     C.zc_rows = zc_tab;
   }
@@ -1341,7 +1424,7 @@ int run_precompute(trap_ctx* ctx, int store_mask) {
       hipLaunchKernelGGL(k_kernel_rows, dim3((unsigned)nr), dim3(64), lds, s, nr, nthr, nt,
                          nn, P.ldm, P.d_x,
                          P.d_lam, P.d_a, P.d_st, P.d_theta_rows, C.d_Lrow, C.d_Grow, r0, z0, h,
-                         uniform ? C.d_Gt : nullptr, uniform ? C.d_Vt : nullptr, ntail, roles);
+                         uniform ? C.d_Gt : nullptr, uniform ? C.d_Vt : nullptr, ntail, roles, C.d_gspan);
       TRAP_HIP(hipGetLastError());
     }
     const long long rrows = 2 * nrows;                           // real rows (both planes)
@@ -1351,7 +1434,7 @@ int run_precompute(trap_ctx* ctx, int store_mask) {
       const long long units = (long long)zc * nth * P.nq * ncg;
       hipLaunchKernelGGL(k_sig_gemm_tiles, dim3((unsigned)ceil_div(units, kTileGemmWaves)),
                          dim3(64 * kTileGemmWaves), 0, s, zc, nth, nt, nn, P.ldm, P.nnp, P.nq, ncg, C.d_Grow,
-                         C.d_Lrow, P.d_Sig, bo, roles);
+                         C.d_Lrow, P.d_Sig, bo, roles, C.d_gspan);
       TRAP_HIP(hipGetLastError());
     } else if (!aa) {
       TRAP_TRY(launch_sig_gemm(ctx, rrows, C.d_Grow, C.d_Lrow, nullptr, nullptr, 0LL, &roles, &bo));
@@ -1636,7 +1719,7 @@ static int precompute_precond_body(trap_ctx* ctx) {
     const long long nrows = (long long)zc * ng * nk * nn;
     hipLaunchKernelGGL(k_kernel_rows, dim3((unsigned)nrows), dim3(64), lds_kr, s, nrows, ng,
                        nk, nn, ldm, P.d_x, P.d_lam, P.d_a, C.d_pcSt, C.d_pcTheta, Lrow, Grow, 0LL, z0, lay.h,
-                       lay.uniform ? Gt : nullptr, lay.uniform ? Vt : nullptr, lay.ntail, RowRoles{});
+                       lay.uniform ? Gt : nullptr, lay.uniform ? Vt : nullptr, lay.ntail, RowRoles{}, nullptr);
     TRAP_HIP(hipGetLastError());
     TRAP_TRY(launch_sig_gemm(ctx, 2 * nrows, Grow, Lrow, Mtmp, (float*)nullptr, 0LL));
     hipLaunchKernelGGL(k_theta_average_dense, dim3(ceil_div(per_z_out * zc, 256)), dim3(256), 0, s, per_z_out, ng,

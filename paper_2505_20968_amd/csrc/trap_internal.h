@@ -243,6 +243,7 @@ struct Precomp {
   double2 *d_Vt = nullptr;    // Faddeeva factor table of the kernel precompute (uniform grids)
   double *d_Lrow = nullptr;   // local part of the kernel rows, [rows][ldm] (height chunk)
   double *d_Grow = nullptr;   // second-derivative weights of the kernel rows, [rows][ldm]
+  int2* d_gspan = nullptr;    // node span of each complex row's nonzero weights (height chunk)
   int zc_rows = 0;            // heights per precompute chunk
   // preconditioner tables (FP64), present once pc_done
   bool pc_done = false;
