@@ -8,10 +8,11 @@
 //        w(z) = 2 p(Z)/(L - i z)^2 + 1/(sqrt(pi) (L - i z)),
 //    p a polynomial of degree N-1 whose coefficients are the Fourier
 //    coefficients of exp(-t^2)(L^2 + t^2) on t = L tan(theta/2).  Here
-//    N = 36, a relative error of about 2e-14 inside |z| = 15 (N = 32 gives
-//    3e-13, N = 40 2e-14); the coefficients are computed on the host at
-//    library load (faddeeva_init) by a direct discrete Fourier transform and
-//    copied to constant memory.
+//    N = 40, a relative error of about 1.7e-14 inside |z| = 15 (N = 36 gives
+//    2.4e-14 and is spread wider, enough to move formal solutions through
+//    optically thick slabs by 1e-12); the coefficients are computed on the
+//    host at library load (faddeeva_init) by a direct discrete Fourier
+//    transform and copied to constant memory.
 //  * |z| >= 15: the Laplace continued fraction (Gautschi 1970; Jones, Thron &
 //    Waadeland 1981) w(z) = (i/sqrt(pi)) / (z - (1/2)/(z - 1/(z - (3/2)/(z - ...)))),
 //    evaluated bottom-up.  The depth falls with |z|: the truncation error
@@ -25,7 +26,7 @@
 
 namespace trap {
 
-constexpr int kWeidemanN = 36;
+constexpr int kWeidemanN = 40;
 
 struct FaddeevaCoef {
   double L;

@@ -967,6 +967,7 @@ size_t estimate_bytes(const trap_atom_desc* atom, const trap_problem_desc* pd, i
     const size_t rows = (size_t)lay.zc_tab * P.nth_rows * nt * 2 * nn * ldm * 8;
     add(rows);                                          // L and Gamma row stores
     add(rows);
+    add((size_t)lay.zc_tab * P.nth_rows * nt * nn * 8);  // node spans of the Gamma rows (int2 each)
     if (lay.uniform) {
       add((size_t)lay.zc_tab * P.nth_rows * lay.nd2 * 16 * 8);        // Gaussian factors
       add((size_t)lay.zc_tab * P.nth_rows * nt * lay.nd2 * 16 * 16);  // Faddeeva factors

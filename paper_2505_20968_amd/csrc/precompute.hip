@@ -289,11 +289,45 @@ __global__ void k_kernel_tables(int z0, int nth, int nt, int nn, int ntail, doub
 constexpr int kPanelCap = 64;         // graded work units listed per window of one row
 constexpr double kGl8Ratio = 0.15;    // panels up to this fraction of F's local scale take 8 nodes
 
-// LDS of one row: node accumulators L[nn], Gam[nn] (complex), then one window
-// of the graded panel list: {left, width}, {t at left, t span} and the knot
-// interval of each panel (-1 and nn - 1 for the tails).
-__host__ __device__ constexpr size_t kernel_row_lds(int nn) {
-  return ((size_t)nn * 2 + 2 * kPanelCap) * sizeof(double2) + kPanelCap * sizeof(int);
+// LDS of one row: node accumulators L[nacc], Gam[nacc] (complex) for the
+// nodes from the first one the row's support reaches, then one window of the
+// graded work-unit list: {left, width}, {t at left, t span} and the packed
+// knot interval and node set of each unit.  nacc bounds the node span of
+// every row (kernel_row_span); it is nn at most.
+__host__ __device__ constexpr size_t kernel_row_lds(int nacc) {
+  return ((size_t)nacc * 2 + 2 * kPanelCap) * sizeof(double2) + kPanelCap * sizeof(int);
+}
+
+// Largest node span (top - base + 1 in k_kernel_rows) of any kernel row of
+// the problem: the rows of Theta = pi have the widest support, 6.6 sigma with
+// sigma = 2 / lambda on either side of the row's frequency, and narrower
+// supports reach a subset of its knot intervals.  The same interval search
+// as the kernel's (upper_interval), on the host.
+static int kernel_row_span(const Problem& P) {
+  const int nn = P.nn;
+  const double* x = P.x.data();
+  auto upper = [&](double v) {
+    if (v < x[0]) return -1;
+    if (v >= x[nn - 1]) return nn - 1;
+    int lo = 0, hi = nn - 1;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (x[mid] <= v) lo = mid; else hi = mid;
+    }
+    return lo;
+  };
+  int span = 1;
+  for (int z = 0; z < P.nz; ++z) {
+    const double R = 6.6 * (2.0 / P.lam[z]);
+    for (int n = 0; n < nn; ++n) {
+      const int plo = upper(x[n] - R);
+      int phi = upper(x[n] + R);
+      if (phi >= 0 && phi < nn - 1 && x[phi] >= x[n] + R) phi -= 1;
+      const int base = std::min(std::max(plo, 0), nn - 1), top = std::min(std::max(phi + 1, 0), nn - 1);
+      span = std::max(span, top - base + 1);
+    }
+  }
+  return std::min(nn, span + 2);    // two nodes of margin against rounding in the support's ends
 }
 
 // Mirror roles of the transitions' kernel rows (Problem::row_role), by value.
@@ -318,39 +352,43 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 // Moments mu_q of knot interval k (or the zeroth moment of a tail, k = -1 or
 // nn - 1) into the node accumulators, by the collection formula above.
+// The accumulators hold nodes base, base + 1, ... of the row.
 __device__ __forceinline__ void add_moments(double2* Lacc, double2* Gacc, const double* __restrict__ x, int nn,
-                                            int k, const double2* mu) {
+                                            int base, int k, const double2* mu) {
   if (k < 0 || k >= nn - 1) {
-    const int m = k < 0 ? 0 : nn - 1;
+    const int m = (k < 0 ? 0 : nn - 1) - base;
     atomicAdd(&Lacc[m].x, mu[0].x);
     atomicAdd(&Lacc[m].y, mu[0].y);
     return;
   }
   const double h = x[k + 1] - x[k], hh = h * h;
-  atomicAdd(&Lacc[k].x, mu[0].x - mu[1].x);
-  atomicAdd(&Lacc[k].y, mu[0].y - mu[1].y);
-  atomicAdd(&Lacc[k + 1].x, mu[1].x);
-  atomicAdd(&Lacc[k + 1].y, mu[1].y);
-  atomicAdd(&Gacc[k].x, hh * (-mu[1].x * (1.0 / 3.0) + 0.5 * mu[2].x - mu[3].x * (1.0 / 6.0)));
-  atomicAdd(&Gacc[k].y, hh * (-mu[1].y * (1.0 / 3.0) + 0.5 * mu[2].y - mu[3].y * (1.0 / 6.0)));
-  atomicAdd(&Gacc[k + 1].x, hh * (mu[3].x - mu[1].x) * (1.0 / 6.0));
-  atomicAdd(&Gacc[k + 1].y, hh * (mu[3].y - mu[1].y) * (1.0 / 6.0));
+  const int m = k - base;
+  atomicAdd(&Lacc[m].x, mu[0].x - mu[1].x);
+  atomicAdd(&Lacc[m].y, mu[0].y - mu[1].y);
+  atomicAdd(&Lacc[m + 1].x, mu[1].x);
+  atomicAdd(&Lacc[m + 1].y, mu[1].y);
+  atomicAdd(&Gacc[m].x, hh * (-mu[1].x * (1.0 / 3.0) + 0.5 * mu[2].x - mu[3].x * (1.0 / 6.0)));
+  atomicAdd(&Gacc[m].y, hh * (-mu[1].y * (1.0 / 3.0) + 0.5 * mu[2].y - mu[3].y * (1.0 / 6.0)));
+  atomicAdd(&Gacc[m + 1].x, hh * (mu[3].x - mu[1].x) * (1.0 / 6.0));
+  atomicAdd(&Gacc[m + 1].y, hh * (mu[3].y - mu[1].y) * (1.0 / 6.0));
 }
 
-// Latency bound: occupancy is what counts.  Three waves per SIMD fit the
-// registers without spills, and the LDS of one row (about 14 KB at 301
-// frequencies) lets eleven rows share a compute unit.
-__global__ void __launch_bounds__(64, 3) k_kernel_rows(
+// Bound by vector issue (FP64 arithmetic of the Faddeeva and Gaussian
+// factors) with the waves' dependency chains in between: occupancy counts.
+// Four waves per SIMD fit 128 registers with a few spilled dwords (measured
+// faster than three without spills, and than five with more spills); the LDS
+// of one row covers only the nodes its support reaches.
+__global__ void __launch_bounds__(64, 4) k_kernel_rows(
     long long nrows, int nth, int nt, int nn, int ldm, const double* __restrict__ x,
     const double* __restrict__ lam, const double* __restrict__ av, const double* __restrict__ st,
     const double* __restrict__ theta, double* __restrict__ Lout, double* __restrict__ Gout,
     long long row0, int z0, double h_uniform, const double* __restrict__ Gt,
-    const double2* __restrict__ Vt, int ntail, RowRoles roles, int2* __restrict__ gspan) {
-  extern __shared__ double2 smem[];    // kernel_row_lds(nn) bytes
+    const double2* __restrict__ Vt, int ntail, RowRoles roles, int2* __restrict__ gspan, int nacc) {
+  extern __shared__ double2 smem[];    // kernel_row_lds(nacc) bytes
   const int lane = threadIdx.x;
   double2* Lacc = smem;
-  double2* Gacc = smem + nn;
-  double2* plw = Gacc + nn;                      // graded panels: {left, width}
+  double2* Gacc = smem + nacc;
+  double2* plw = Gacc + nacc;                    // graded work units: {left, width}
   double2* pts = plw + kPanelCap;                // {t at left, t span} in the piece's knot interval
   int* pk = (int*)(pts + kPanelCap);             // knot interval of the panel
   const long long rl = blockIdx.x;               // row within this launch
@@ -389,12 +427,19 @@ __global__ void __launch_bounds__(64, 3) k_kernel_rows(
   const double xc = -xn - 2.0 * s / L;
   const double wc = 2.0 * fmax(fp.cG, a) / L;
   const double Lg = 1.5 * sigma;
-  for (int i = lane; i < 2 * nn; i += 64) Lacc[i] = make_double2(0.0, 0.0);
-  wave_sync();
   // pieces: -1 left tail, 0..nn-2 knot intervals, nn-1 right tail
   int plo = upper_interval(x, nn, lo);          // -1 if lo < x0
   int phi = upper_interval(x, nn, hi);
   if (phi >= 0 && phi < nn - 1 && x[phi] >= hi) phi -= 1;
+  // every node the row's moments reach: knot intervals plo..phi and the
+  // tails' end nodes (no more than nacc of them, kernel_row_span)
+  const int base = min(max(plo, 0), nn - 1);
+  const int top = min(max(phi + 1, 0), nn - 1);
+  for (int i = lane; i <= top - base; i += 64) {
+    Lacc[i] = make_double2(0.0, 0.0);
+    Gacc[i] = make_double2(0.0, 0.0);
+  }
+  wave_sync();
   const double un = L * xn + s;
   // table fast path: uniform grid, Gaussian resolved by the interval nodes
   const bool fast = (Gt != nullptr) && (sigma >= 0.5 * h_uniform);
@@ -473,7 +518,7 @@ __global__ void __launch_bounds__(64, 3) k_kernel_rows(
         tp *= ti;
       }
     }
-    add_moments(Lacc, Gacc, x, nn, p, acc);
+    add_moments(Lacc, Gacc, x, nn, base, p, acc);
   }
   // graded pieces (the region is per row, so every branch here is uniform
   // over the wave)
@@ -513,17 +558,6 @@ __global__ void __launch_bounds__(64, 3) k_kernel_rows(
     const int total = __shfl(off, 63, 64);
     off -= mine;
     const int g = lane >> 2, i4 = lane & 3;        // unit group, first node
-    double tg[4], wg[4], t8[2], w8[2];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      tg[u] = c_gl_t[i4 + 4 * u];
-      wg[u] = c_gl_w[i4 + 4 * u];
-    }
-#pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      t8[u] = c_gl8_t[i4 + 4 * u];
-      w8[u] = c_gl8_w[i4 + 4 * u];
-    }
     for (int w0 = 0; w0 < total; w0 += kPanelCap) {
       const int w1 = min(total, w0 + kPanelCap);
       // this window's units into LDS: the panel, and its knot interval k and
@@ -560,7 +594,7 @@ __global__ void __launch_bounds__(64, 3) k_kernel_rows(
             acc[q].x += __shfl_xor(acc[q].x, d, 4);
             acc[q].y += __shfl_xor(acc[q].y, d, 4);
           }
-        if (i4 == 0) add_moments(Lacc, Gacc, x, nn, cur, acc);
+        if (i4 == 0) add_moments(Lacc, Gacc, x, nn, base, cur, acc);
 #pragma unroll
         for (int q = 0; q < 4; ++q) acc[q] = make_double2(0.0, 0.0);
       };
@@ -572,11 +606,13 @@ __global__ void __launch_bounds__(64, 3) k_kernel_rows(
         cur = k;
         if (pi < np) {
           const double2 lw = plw[pi], tt = pts[pi];
+          // the lane's nodes, read per unit (registers are what limits occupancy)
           const int set = code & 3;
-          const double tn[2] = {set == 2 ? t8[0] : set == 1 ? tg[2] : tg[0],
-                                set == 2 ? t8[1] : set == 1 ? tg[3] : tg[1]};
-          const double wn[2] = {set == 2 ? w8[0] : set == 1 ? wg[2] : wg[0],
-                                set == 2 ? w8[1] : set == 1 ? wg[3] : wg[1]};
+          const double* nt_ = set == 2 ? c_gl8_t : c_gl_t;
+          const double* nw_ = set == 2 ? c_gl8_w : c_gl_w;
+          const int i0 = i4 + (set == 1 ? 8 : 0);
+          const double tn[2] = {nt_[i0], nt_[i0 + 4]};
+          const double wn[2] = {nw_[i0], nw_[i0 + 4]};
           double upn[2];
           double2 Fn[2];
 #pragma unroll
@@ -619,12 +655,13 @@ __global__ void __launch_bounds__(64, 3) k_kernel_rows(
     }
     acc.x = wave_sum(acc.x);
     acc.y = wave_sum(acc.y);
-    if (lane == 0) add_moments(Lacc, Gacc, x, nn, side == 0 ? -1 : nn - 1, &acc);
+    if (lane == 0) add_moments(Lacc, Gacc, x, nn, base, side == 0 ? -1 : nn - 1, &acc);
   }
   wave_sync();
   for (int m = lane; m < ldm; m += 64) {
-    const double2 lv = m < nn ? Lacc[m] : make_double2(0.0, 0.0);
-    const double2 gv = m < nn ? Gacc[m] : make_double2(0.0, 0.0);
+    const bool in = m >= base && m <= top;
+    const double2 lv = in ? Lacc[m - base] : make_double2(0.0, 0.0);
+    const double2 gv = in ? Gacc[m - base] : make_double2(0.0, 0.0);
     Lout[rre + m] = lv.x;
     Lout[rim + m] = lv.y;
     Gout[rre + m] = gv.x;
@@ -1384,7 +1421,8 @@ int run_precompute(trap_ctx* ctx, int store_mask) {
   bo.nn = nn;
   bo.nq = P.nq;
   bo.pad = P.qpad;
-  const size_t lds = kernel_row_lds(nn);
+  const int nacc = kernel_row_span(P);
+  const size_t lds = kernel_row_lds(nacc);
   if (lds > 64 * 1024) return fail(TRAP_EINVAL, "frequency grid too large for the kernel precompute");
   // uniform grid -> factor tables, heights in chunks so the tables stay cache sized
   const PrecompLayout lay = precomp_layout(nz, nn, P.ldm, nt, nthr, aa, P.x.data(), P.lam.data());
@@ -1424,7 +1462,7 @@ int run_precompute(trap_ctx* ctx, int store_mask) {
       hipLaunchKernelGGL(k_kernel_rows, dim3((unsigned)nr), dim3(64), lds, s, nr, nthr, nt,
                          nn, P.ldm, P.d_x,
                          P.d_lam, P.d_a, P.d_st, P.d_theta_rows, C.d_Lrow, C.d_Grow, r0, z0, h,
-                         uniform ? C.d_Gt : nullptr, uniform ? C.d_Vt : nullptr, ntail, roles, C.d_gspan);
+                         uniform ? C.d_Gt : nullptr, uniform ? C.d_Vt : nullptr, ntail, roles, C.d_gspan, nacc);
       TRAP_HIP(hipGetLastError());
     }
     const long long rrows = 2 * nrows;                           // real rows (both planes)
@@ -1706,7 +1744,8 @@ static int precompute_precond_body(trap_ctx* ctx) {
   TRAP_TRY(dalloc_t(ctx, &Lrow, (size_t)zc_max * rows_per_z * ldm));
   TRAP_TRY(dalloc_t(ctx, &Grow, (size_t)zc_max * rows_per_z * ldm));
   TRAP_TRY(dalloc_t(ctx, &Mtmp, (size_t)zc_max * rows_per_z * ldm));
-  const size_t lds_kr = kernel_row_lds(nn);
+  const int nacc = kernel_row_span(P);
+  const size_t lds_kr = kernel_row_lds(nacc);
   if (lds_kr > 64 * 1024) return fail(TRAP_EINVAL, "frequency grid too large for the kernel precompute");
   const long long per_z_out = (long long)nk * 2 * nn * ldm;
   for (int z0 = 0; z0 < nz; z0 += zc_max) {
@@ -1719,7 +1758,7 @@ static int precompute_precond_body(trap_ctx* ctx) {
     const long long nrows = (long long)zc * ng * nk * nn;
     hipLaunchKernelGGL(k_kernel_rows, dim3((unsigned)nrows), dim3(64), lds_kr, s, nrows, ng,
                        nk, nn, ldm, P.d_x, P.d_lam, P.d_a, C.d_pcSt, C.d_pcTheta, Lrow, Grow, 0LL, z0, lay.h,
-                       lay.uniform ? Gt : nullptr, lay.uniform ? Vt : nullptr, lay.ntail, RowRoles{}, nullptr);
+                       lay.uniform ? Gt : nullptr, lay.uniform ? Vt : nullptr, lay.ntail, RowRoles{}, nullptr, nacc);
     TRAP_HIP(hipGetLastError());
     TRAP_TRY(launch_sig_gemm(ctx, 2 * nrows, Grow, Lrow, Mtmp, (float*)nullptr, 0LL));
     hipLaunchKernelGGL(k_theta_average_dense, dim3(ceil_div(per_z_out * zc, 256)), dim3(256), 0, s, per_z_out, ng,

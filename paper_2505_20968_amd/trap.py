@@ -102,6 +102,12 @@ def load_library(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise RuntimeError(f"HIP library not built: {path} is missing "
                            "(run `python -m paper_2505_20968_amd.build`)")
+    # torch first: the HIP runtime it brings is then the one the library binds
+    # to (loaded the other way round, the two runtimes see no device)
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     vp = ctypes.c_void_p
     lib.trap_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, vp]
