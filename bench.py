@@ -437,6 +437,7 @@ def main():
                    "n_unknowns": info["n_unknowns"], "n_theta": info["n_theta"],
                    "n_slots": info["n_slots"], "restart": args.restart,
                    "kernel_entries_in_band": info["kernel_entries"],
+                   "kernel_entries_in_fp32_windows": info["kernel_entries_fp32"],
                    "kernel_store_bytes": info["bytes_kernel_fp64"],
                    "device_bytes": info["bytes_device_total"],
                    "preconditioner": (f"physics-based P = Id - Lambda* Sigma* (unmagnetised, unpolarised, "
@@ -460,12 +461,12 @@ def main():
                      "algorithmic_flops_per_launch": flops / max(cstage["launches"], 1),
                      "kernel": ("k_contract_pipe<NH> (persistent FP32 contraction, both column classes)"
                                 if mixed else "k_contract<double, NH>")},
-        "sigma_apply": {"ms": sigma_ms, "flops": info["flops_contraction"],
-                        "tflops": info["flops_contraction"] / (sigma_ms * 1e-3) / 1e12,
-                        "frac_fp32_peak": info["flops_contraction"] / (sigma_ms * 1e-3) / 1e12 / PEAK["fp32"],
+        "sigma_apply": {"ms": sigma_ms, "flops": info["flops_contraction_fp32"],
+                        "tflops": info["flops_contraction_fp32"] / (sigma_ms * 1e-3) / 1e12,
+                        "frac_fp32_peak": info["flops_contraction_fp32"] / (sigma_ms * 1e-3) / 1e12 / PEAK["fp32"],
                         "what": "whole FP32 Sigma apply (comoving interpolation, contraction, R_III, angular "
-                                "sum, back-interpolation) timed with events, against the contraction's "
-                                "algorithmic flops"},
+                                "sum, back-interpolation) timed with events, against the FP32 contraction's "
+                                "algorithmic flops (its column windows)"},
         "accuracy": accuracy,
     }
     if not args.no_aa:

@@ -147,6 +147,15 @@ typedef struct {
                                    The store holds 16-row tiles over the union of their rows'
                                    bands: bytes_kernel_fp32 / 4 real entries */
   int band_reach;               /* that reach, in frequency nodes */
+  /* The FP32 operator steps through narrower column windows of the same
+     stored tiles: knot intervals within 4.6 Gaussian widths and the reach
+     where the spline map falls below 1e-9 (what it leaves out is below the
+     FP32 sum's resolution).  Its complex entries, flops (16 per entry and
+     incoming slot) and reach; bytes_contraction_fp32 counts the stored
+     entries inside those windows. */
+  double flops_contraction_fp32;
+  long long kernel_entries_fp32;
+  int band_reach_fp32;
 } trap_info;
 
 typedef struct {

@@ -460,7 +460,10 @@ int trap_get_info(const trap_ctx* ctx, trap_info* info) {
   const double wbytes = (double)P.nz * P.nt * P.nslot * 2.0 * P.nn * 4;
   const double ibytes = (double)P.nz * P.nd * P.nn * 4;
   info->bytes_contraction_fp64 = 8.0 * (kel + wbytes + ibytes);
-  info->bytes_contraction_fp32 = 4.0 * (kel + wbytes + ibytes);
+  info->bytes_contraction_fp32 = 4.0 * (chunk_entries32(P, 0, P.nz) + wbytes + ibytes);
+  info->flops_contraction_fp32 = chunk_flops32(P, 0, P.nz);
+  info->kernel_entries_fp32 = (long long)P.band_nnz32;
+  info->band_reach_fp32 = P.band_reach32;
   info->kernel_rows_mirrored = P.rows_mirrored;
   return TRAP_OK;
 }

@@ -629,6 +629,20 @@ void kernel_bands(Problem& P, const std::vector<double>& sig) {
       if (std::fabs(sig[(size_t)j * nn + m]) > 1e-13 * mx) reach = std::max(reach, std::abs(m - j));
   }
   P.band_reach = reach;
+  // the FP32 operator keeps less: a value below about 1e-9 of its row's
+  // largest is below the resolution of the FP32 sum (2^-24 ~ 6e-8), so its
+  // window takes the knot intervals within kCut32 Gaussian widths
+  // (exp(-4.6^2) ~ 6.5e-10) and the reach where Sig falls below 1e-9
+  constexpr double kCut = 6.6, kCut32 = 4.6;
+  int reach32 = 0;
+  for (int j = 0; j < nn; ++j) {
+    double mx = 0.0;
+    for (int m = 0; m < nn; ++m) mx = std::max(mx, std::fabs(sig[(size_t)j * nn + m]));
+    for (int m = 0; m < nn; ++m)
+      if (std::fabs(sig[(size_t)j * nn + m]) > 1e-9 * mx) reach32 = std::max(reach32, std::abs(m - j));
+  }
+  reach32 = std::min(reach32, reach);
+  P.band_reach32 = reach32;
   // Gaussian half-width factor of each stored angle: sin(Theta/2) (1 at
   // Theta = pi, 0 at Theta = 0: the diagonal row); the angle average takes
   // its widest node
@@ -651,59 +665,78 @@ void kernel_bands(Problem& P, const std::vector<double>& sig) {
   // reach; the in-band entries are the algorithmic work
   // (every entry is written below, by the thread that owns its (z, theta):
   // no zero fill, and the first touch of each page happens in that thread)
+  // (the FP32 window [blo32, bhi32) likewise, inside [blo, bhi))
   std::unique_ptr<short[]> blo(new short[(size_t)nz * nth * nn]), bhi(new short[(size_t)nz * nth * nn]);
-  std::vector<long long> cnt_zt((size_t)nz * nth);
+  std::unique_ptr<short[]> blo32(new short[(size_t)nz * nth * nn]), bhi32(new short[(size_t)nz * nth * nn]);
+  std::vector<long long> cnt_zt((size_t)nz * nth), cnt32_zt((size_t)nz * nth);
   const size_t nzt = (size_t)nz * nth;
   host_parallel(nzt, 64, [&](size_t zt0, size_t zt1) {
     for (size_t zt = zt0; zt < zt1; ++zt) {
       const int z = static_cast<int>(zt / nth), t = static_cast<int>(zt % nth);
-      const double R = 6.6 * 2.0 * sg[t] / P.lam[z];
-      long long cnt = 0;
+      long long cnt = 0, cnt32 = 0;
       // x_n - R and x_n + R increase with n: the interval searches walk forward
-      int plo = -1, phi = -1;
+      struct Walk {
+        double R;
+        int rch, plo = -1, phi = -1;
+      } wk[2] = {{kCut * 2.0 * sg[t] / P.lam[z], reach}, {kCut32 * 2.0 * sg[t] / P.lam[z], reach32}};
       for (int n = 0; n < nn; ++n) {
-        int lo, hi;
-        if (sg[t] == 0.0) {
-          lo = n;
-          hi = n + 1;
-        } else {
-          const double xn = P.x[n], a = xn - R, b = xn + R;
-          if (n == 0) {
-            plo = upper_node(P.x, a);
-            phi = upper_node(P.x, b);
-          } else {
-            while (plo + 1 < nn && P.x[plo + 1] <= a) ++plo;
-            while (phi + 1 < nn && P.x[phi + 1] <= b) ++phi;
+        int lo[2], hi[2];
+        for (int v = 0; v < 2; ++v) {
+          Walk& w = wk[v];
+          if (sg[t] == 0.0) {
+            lo[v] = n;
+            hi[v] = n + 1;
+            continue;
           }
-          int ph = phi;
+          const double xn = P.x[n], a = xn - w.R, b = xn + w.R;
+          if (n == 0) {
+            w.plo = upper_node(P.x, a);
+            w.phi = upper_node(P.x, b);
+          } else {
+            while (w.plo + 1 < nn && P.x[w.plo + 1] <= a) ++w.plo;
+            while (w.phi + 1 < nn && P.x[w.phi + 1] <= b) ++w.phi;
+          }
+          int ph = w.phi;
           if (ph >= 0 && ph < nn - 1 && P.x[ph] >= b) ph -= 1;
-          const int jlo = std::max(plo, 0), jhi = std::min(ph + 1, nn - 1);
-          lo = std::max(0, jlo - 1 - reach);
-          hi = std::min(nn, jhi + 2 + reach);
+          const int jlo = std::max(w.plo, 0), jhi = std::min(ph + 1, nn - 1);
+          lo[v] = std::max(0, jlo - 1 - w.rch);
+          hi[v] = std::min(nn, jhi + 2 + w.rch);
         }
-        blo[zt * nn + n] = static_cast<short>(lo);
-        bhi[zt * nn + n] = static_cast<short>(hi);
-        cnt += hi - lo;
+        lo[1] = std::max(lo[1], lo[0]);
+        hi[1] = std::max(lo[1], std::min(hi[1], hi[0]));
+        blo[zt * nn + n] = static_cast<short>(lo[0]);
+        bhi[zt * nn + n] = static_cast<short>(hi[0]);
+        blo32[zt * nn + n] = static_cast<short>(lo[1]);
+        bhi32[zt * nn + n] = static_cast<short>(hi[1]);
+        cnt += hi[0] - lo[0];
+        cnt32 += hi[1] - lo[1];
       }
       cnt_zt[zt] = cnt;
+      cnt32_zt[zt] = cnt32;
     }
   });
   P.kflops_z.assign(nz, 0.0);
+  P.kflops32_z.assign(nz, 0.0);
   P.band_nnz = 0.0;
+  P.band_nnz32 = 0.0;
   for (size_t zt = 0; zt < nzt; ++zt) {
     P.band_nnz += (double)P.nt * cnt_zt[zt];
+    P.band_nnz32 += (double)P.nt * cnt32_zt[zt];
     P.kflops_z[zt / nth] += 16.0 * P.nt * (double)cnt_zt[zt] * nslots[zt % nth];
+    P.kflops32_z[zt / nth] += 16.0 * P.nt * (double)cnt32_zt[zt] * nslots[zt % nth];
   }
   // wave tiles in both row layouts; the one with less column work is kept:
   // every wave of a block steps through the block's column range (the union
   // of its eight tiles' ranges), times the incoming slots of the angle
-  auto tiles = [&](bool pad, std::vector<int>& row0, host_vec<unsigned>& qk, double* work) {
+  auto tiles = [&](bool pad, std::vector<int>& row0, host_vec<unsigned>& qk, host_vec<unsigned>& qk32,
+                   double* work) {
     const int nnp = pad ? (nn + 15) / 16 * 16 : nn;
     const int rows = np * nnp;
     const int nq = (rows + 15) / 16;
     row0.assign(nq, 0);
     for (int q = 0; q < nq; ++q) row0[q] = pad ? (q % np) * nnp + 16 * (q / np) : 16 * q;
     qk.resize((size_t)nz * nth * nq);                  // every entry written below
+    qk32.resize((size_t)nz * nth * nq);
     std::vector<double> work_zt(nzt, 0.0);
     // the band ends never decrease with n, so a run of rows n_a..n_b of one
     // plane spans [lo(n_a), hi(n_b))
@@ -711,8 +744,10 @@ void kernel_bands(Problem& P, const std::vector<double>& sig) {
       for (size_t zt = zt0; zt < zt1; ++zt) {
         const short* bl = &blo[zt * nn];
         const short* bh = &bhi[zt * nn];
+        const short* bl32 = &blo32[zt * nn];
+        const short* bh32 = &bhi32[zt * nn];
         for (int q = 0; q < nq; ++q) {
-          int lo = P.ldm, hi = 0;
+          int lo = P.ldm, hi = 0, lo32 = P.ldm, hi32 = 0;
           const int r1 = std::min(row0[q] + 16, rows);
           for (int r = row0[q]; r < r1;) {
             const int p = r / nnp, n = r - p * nnp;
@@ -721,6 +756,8 @@ void kernel_bands(Problem& P, const std::vector<double>& sig) {
             if (nb >= n) {
               lo = std::min(lo, (int)bl[n]);
               hi = std::max(hi, (int)bh[nb]);
+              lo32 = std::min(lo32, (int)bl32[n]);
+              hi32 = std::max(hi32, (int)bh32[nb]);
             }
             r += run;
           }
@@ -728,6 +765,11 @@ void kernel_bands(Problem& P, const std::vector<double>& sig) {
           lo = lo / 8 * 8;
           hi = std::min((hi + 7) / 8 * 8, P.ldm);
           qk[zt * nq + q] = (unsigned)lo | ((unsigned)hi << 16);
+          // inside the tile's range (rounded the same way)
+          lo32 = std::max(lo, lo32 / 8 * 8);
+          hi32 = std::min(hi, (hi32 + 7) / 8 * 8);
+          if (hi32 <= lo32) lo32 = hi32 = lo;
+          qk32[zt * nq + q] = (unsigned)lo32 | ((unsigned)hi32 << 16);
         }
         for (int q0 = 0; q0 < nq; q0 += 8) {
           int lo = P.ldm, hi = 0;
@@ -747,15 +789,16 @@ void kernel_bands(Problem& P, const std::vector<double>& sig) {
     return nnp;
   };
   std::vector<int> r0a, r0b;
-  host_vec<unsigned> qka, qkb;
+  host_vec<unsigned> qka, qkb, qk32a, qk32b;
   double wa = 0.0, wb = 0.0;
-  const int nnpa = tiles(false, r0a, qka, &wa);
-  const int nnpb = tiles(true, r0b, qkb, &wb);
+  const int nnpa = tiles(false, r0a, qka, qk32a, &wa);
+  const int nnpb = tiles(true, r0b, qkb, qk32b, &wb);
   const bool pad = wb < wa;
   P.qpad = pad ? 1 : 0;
   P.nnp = pad ? nnpb : nnpa;
   P.qrow0 = std::move(pad ? r0b : r0a);
   P.qk = std::move(pad ? qkb : qka);
+  P.qk32 = std::move(pad ? qk32b : qk32a);
   P.nq = static_cast<int>(P.qrow0.size());
   P.nqb = (P.nq + 7) / 8;
   // tile offsets: tiles of (z, theta) back to back in block order, each
@@ -765,6 +808,8 @@ void kernel_bands(Problem& P, const std::vector<double>& sig) {
   P.td.resize((size_t)nz * nth * P.nq);
   P.kbase.resize((size_t)nz * nth);
   P.qb.resize((size_t)nz * nth * P.nqb);
+  P.qb32.resize((size_t)nz * nth * P.nqb);
+  std::vector<long long> ent32_zt(nzt);
   // per (z, theta): tile offsets and size, then the running base, then the
   // descriptors and block ranges
   std::vector<long long> size_zt(nzt);
@@ -801,10 +846,28 @@ void kernel_bands(Problem& P, const std::vector<double>& sig) {
         }
         if (hi <= lo) lo = hi = 0;
         P.qb[zt * P.nqb + bq] = lo | (hi << 16);
+        unsigned lo32 = 0xffffu, hi32 = 0;
+        for (int q = 8 * bq; q < std::min(8 * bq + 8, P.nq); ++q) {
+          const unsigned v = P.qk32[zt * P.nq + q];
+          if ((v >> 16) > (v & 0xffffu)) {
+            lo32 = std::min(lo32, v & 0xffffu);
+            hi32 = std::max(hi32, v >> 16);
+          }
+        }
+        if (hi32 <= lo32) lo32 = hi32 = 0;
+        P.qb32[zt * P.nqb + bq] = lo32 | (hi32 << 16);
       }
+      long long e32 = 0;
+      for (int q = 0; q < P.nq; ++q) {
+        const unsigned v = P.qk32[zt * P.nq + q];
+        e32 += 16LL * (int)((v >> 16) - (v & 0xffffu));
+      }
+      ent32_zt[zt] = e32;
     }
   });
   P.kentries = (size_t)total;
+  P.kent32_z.assign(nz, 0.0);
+  for (size_t zt = 0; zt < nzt; ++zt) P.kent32_z[zt / nth] += (double)ent32_zt[zt];
 }
 
 static int zero_field_classes(const trap_atom_desc& at, double dnuD_ref, std::vector<double>* dE,
@@ -944,6 +1007,8 @@ size_t estimate_bytes(const trap_atom_desc* atom, const trap_problem_desc* pd, i
     item(nz * nt * nd * 4 * 8);                          // g
     item_vec(P.td);                                      // banded store layout
     item_vec(P.qb);
+    item_vec(P.qk32);                                    //   and the FP32 windows
+    item_vec(P.qb32);
     if (pd->kappa_c || pd->sigma_c) {
       item(nz * nn * 8);                                 // kappa_c
       item(nz * nn * 8);                                 // sigma_c
@@ -1364,6 +1429,8 @@ int build_problem(trap_ctx* ctx, const trap_atom_desc* at, const trap_problem_de
   up.add(reinterpret_cast<void**>(&P.d_g), g, n_g * sizeof(double));
   up.add(&P.d_td, P.td);
   up.add(&P.d_qb, P.qb);
+  up.add(&P.d_qk32, P.qk32);
+  up.add(&P.d_qb32, P.qb32);
   if (P.has_cont) {
     up.add(&P.d_kc, P.kc);
     up.add(&P.d_sc, P.sc);

@@ -256,6 +256,12 @@ __device__ __forceinline__ KRow krow(const KStore& ks, long long zt, int q, int 
   r.wlo = __builtin_amdgcn_readfirstlane(d.lo);
   r.whi = __builtin_amdgcn_readfirstlane(d.hi);
   r.base = d.off + (long long)lr * (r.whi - r.wlo) - r.wlo;
+  if (qv && ks.t32) {
+    // the products step through the narrower window only (same addresses)
+    const unsigned v = __builtin_amdgcn_readfirstlane(ks.t32[zt * ks.nq + q]);
+    r.wlo = (int)(v & 0xffffu);
+    r.whi = (int)(v >> 16);
+  }
   return r;
 }
 
@@ -343,7 +349,7 @@ __device__ __forceinline__ void contract_block(int rb, int g, int zl, int z0, in
   constexpr int CG = 4 * NCT;                       // slots per column group
   const int th = cgrp[3 * g], s0 = cgrp[3 * g + 1], cnt = cgrp[3 * g + 2];
   const long long zt = (long long)(z0 + zl) * nth + th;
-  const unsigned bw = ks.qb[zt * ks.nqb + rb];
+  const unsigned bw = (ks.qb32 ? ks.qb32 : ks.qb)[zt * ks.nqb + rb];
   const int klo = (int)(bw & 0xffffu), khi = (int)(bw >> 16);
   const int nkc = max(1, (khi - klo + KCH - 1) / KCH);
   const T* Ib = Ibar + (size_t)zl * nd * nn * 4;
@@ -463,7 +469,7 @@ __device__ __forceinline__ void contract_pipe_class(
     d.zl = r / rb_n;
     const int rb = r % rb_n;
     d.zt = (long long)(z0 + d.zl) * nth + cgrp[3 * d.g];
-    const unsigned bw = ks.qb[d.zt * ks.nqb + rb];
+    const unsigned bw = (ks.qb32 ? ks.qb32 : ks.qb)[d.zt * ks.nqb + rb];
     d.klo = (int)(bw & 0xffffu);
     d.nkc = max(1, ((int)(bw >> 16) - d.klo + KCH - 1) / KCH);
     return rb;
@@ -625,7 +631,7 @@ static int launch_contract_pipe(trap_ctx* ctx, hipStream_t stream, int zc, int z
   contract_chunks(P.ldm, &nkc, &nh);
   const size_t lds = contract_pipe_lds(nh, P.nslot);
   if (lds > (size_t)ctx->max_lds) return 0;
-  const KStore ks = kernel_store(ctx);
+  const KStore ks = kernel_store(ctx, true);
   switch (nh) {
 #define TRAP_PIPE_CASE(NHV) \
   case NHV:                 \
@@ -650,7 +656,7 @@ static int launch_contract(trap_ctx* ctx, int zc, int z0, const T* Ibar, T* W) {
   int nkc, nh;
   contract_chunks(P.ldm, &nkc, &nh);
   const size_t lds = (size_t)8 * nh * ContractCfg<T>::BST * sizeof(T);
-  const KStore ks = kernel_store(ctx);
+  const KStore ks = kernel_store(ctx, sizeof(T) == sizeof(float));
   dim3 grid(ks.nqb, zc, ngrp);
   const int n8 = P.cgrp_n8[pi];
   switch (nh) {
@@ -1172,7 +1178,7 @@ static int launch_fused_t(trap_ctx* ctx, size_t lds, int nw, const T* Ibar, cons
     TRAP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
                                  (int)lds));
   hipLaunchKernelGGL(kern, dim3(nblk), dim3(64 * nw), lds, ctx->stream, P.nn, P.ldm, P.nd, P.nth, P.nt, P.nu,
-                     P.nl, ntile, nblk, kernel_store(ctx), Ibar, P.d_grp[pi], (int)P.grp[pi].size() / 3, P.d_slot_dir,
+                     P.nl, ntile, nblk, kernel_store(ctx, false), Ibar, P.d_grp[pi], (int)P.grp[pi].size() / 3, P.d_slot_dir,
                      P.d_pair_off, P.d_pair_o, cf, P.c_sc, P.d_E, P.d_bma, ctx->wk.X, ctx->pre.d_prof, Eb);
   TRAP_HIP(hipGetLastError());
   return TRAP_OK;
@@ -1213,14 +1219,29 @@ double chunk_flops(const Problem& P, int z0, int zc) {
   for (int z = z0; z < z0 + zc; ++z) f += P.kflops_z[z];
   return f;
 }
+// the same for the FP32 operator's windows
+double chunk_entries32(const Problem& P, int z0, int zc) {
+  double e = 0.0;
+  for (int z = z0; z < z0 + zc; ++z) e += P.kent32_z[z];
+  return e;
+}
+double chunk_flops32(const Problem& P, int z0, int zc) {
+  double f = 0.0;
+  for (int z = z0; z < z0 + zc; ++z) f += P.kflops32_z[z];
+  return f;
+}
 
-KStore kernel_store(const trap_ctx* ctx) {
+KStore kernel_store(const trap_ctx* ctx, bool fp32) {
   const Problem& P = ctx->pb;
   KStore k;
   k.hi = ctx->pre.d_Mhi;
   k.lo = ctx->pre.d_Mlo;
   k.td = P.d_td;
   k.qb = P.d_qb;
+  if (fp32) {
+    k.t32 = P.d_qk32;
+    k.qb32 = P.d_qb32;
+  }
   k.np = 2 * P.nt;
   k.nnp = P.nnp;
   k.nq = P.nq;
@@ -1302,6 +1323,7 @@ static int sigma_apply_t(trap_ctx* ctx, const T* I, T* eps, int prec, int add_th
     prof_end(ctx, pr);
     // 3. fused R_II contraction, angular/sublevel sum and R_III into eps_bar
     {
+      // (the fused kernel steps through the full tile ranges)
       const double kel = chunk_entries(P, 0, nz) * (sizeof(T) / sizeof(float));
       const double flops = chunk_flops(P, 0, nz);
       const double bytes = sizeof(float) * kel + sizeof(T) * ((double)nz * nd * nn * 4 + (double)nz * nd * nd * nt * 2 * nl * 16 +
@@ -1337,11 +1359,12 @@ static int sigma_apply_t(trap_ctx* ctx, const T* I, T* eps, int prec, int add_th
     int pr;
     // 2. contraction
     {
-      // algorithmic work of the chunk: 16 flops per stored complex kernel entry
-      // and incoming slot of its angle; bytes: the stored rows (FP32 values,
-      // plus the remainders in FP64), W written and the comoving field read
-      const double kel = chunk_entries(P, z0, zc) * (sizeof(T) / sizeof(float));
-      const double flops = chunk_flops(P, z0, zc);
+      // algorithmic work of the chunk: 16 flops per in-band complex kernel
+      // entry and incoming slot of its angle; bytes: the stored rows (FP32
+      // values inside the FP32 windows, or values and remainders), W written
+      // and the comoving field read
+      const double kel = sizeof(T) == 8 ? 2.0 * chunk_entries(P, z0, zc) : chunk_entries32(P, z0, zc);
+      const double flops = sizeof(T) == 8 ? chunk_flops(P, z0, zc) : chunk_flops32(P, z0, zc);
       const double bytes = sizeof(float) * kel + sizeof(T) * ((double)zc * nt * P.nslot * 2.0 * nn * 4 +
                                                                (double)zc * nd * nn * 4);
       pr = prof_begin(ctx, sizeof(T) == 8 ? TRAP_STAGE_CONTRACT_FP64 : TRAP_STAGE_CONTRACT, flops, bytes);
@@ -1858,7 +1881,7 @@ int op_apply_batch_f32(trap_ctx** ctxs, int n, const double* const* x, double* c
         const int z0 = ch * ctxs[i]->wk.zchunk, zc = std::min(ctxs[i]->wk.zchunk, P.nz - z0);
         const int rb_n = P.nqb;
         const int ngrp = (int)P.cgrp[1].size() / 3;
-        a.push_back(GContract{z0, P.nth, P.nt, P.nn, P.nd, P.cgrp_n8[1], P.nslot, zc, kernel_store(ctxs[i]),
+        a.push_back(GContract{z0, P.nth, P.nt, P.nn, P.nd, P.cgrp_n8[1], P.nslot, zc, kernel_store(ctxs[i], true),
                               static_cast<const float*>(ctxs[i]->wk.Ibar[1]) + (size_t)z0 * P.nd * P.nn * 4,
                               P.d_cgrp[1], P.d_slot_dir, static_cast<float*>(ctxs[i]->wk.W[1])});
         cnt.push_back(rb_n * zc * ngrp);

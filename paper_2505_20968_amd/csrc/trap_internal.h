@@ -96,6 +96,10 @@ struct KStore {
   const float* lo = nullptr;          // FP32 remainders: hi + lo is the FP64 kernel
   const TileDesc* td = nullptr;       // [nz][nth][nq]
   const unsigned* qb = nullptr;       // [nz][nth][nqb]
+  // optional column windows inside td / qb (lo | hi << 16) that the products
+  // step through (the FP32 operator's), the addresses still from td
+  const unsigned* t32 = nullptr;      // [nz][nth][nq]
+  const unsigned* qb32 = nullptr;     // [nz][nth][nqb]
   int np = 0, nnp = 0, nq = 0, nqb = 0;
   int pad = 0;
 };
@@ -162,6 +166,16 @@ struct Problem {
   host_vec<TileDesc> td;
   TileDesc* d_td = nullptr;
   unsigned* d_qb = nullptr;
+  // the FP32 operator's narrower window inside each tile and block (lo | hi
+  // << 16, columns, multiples of 8): the same stored rows cut where the
+  // kernel falls below the FP32 operator's resolution (kernel_bands); its
+  // reach, in-band complex entries, stored real entries and flops per height
+  int band_reach32 = 0;
+  host_vec<unsigned> qk32, qb32;
+  double band_nnz32 = 0.0;
+  std::vector<double> kflops32_z, kent32_z;
+  unsigned* d_qk32 = nullptr;
+  unsigned* d_qb32 = nullptr;
   double c_abs = 0, c_sc = 0;
   // host copies used by host-side logic
   std::vector<double> x, mu, w, tau, lam, a, eps, WT, eta0, dnuD;
@@ -406,11 +420,14 @@ int build_problem(trap_ctx* ctx, const trap_atom_desc* atom, const trap_problem_
 // counts and the spline's second-derivative map sig [nn][nn])
 void kernel_bands(Problem& P, const std::vector<double>& sig);
 // the store's device view of a context (after trap_set_problem and the precompute)
-KStore kernel_store(const trap_ctx* ctx);
+// the store as the contraction kernels see it; fp32: with the FP32 windows
+KStore kernel_store(const trap_ctx* ctx, bool fp32);
 // stored real kernel entries of heights [z0, z0 + zc) and their algorithmic
 // contraction flops (sigma.hip)
 double chunk_entries(const Problem& P, int z0, int zc);
 double chunk_flops(const Problem& P, int z0, int zc);
+double chunk_entries32(const Problem& P, int z0, int zc);
+double chunk_flops32(const Problem& P, int z0, int zc);
 size_t estimate_bytes(const trap_atom_desc* atom, const trap_problem_desc* pd, int store_mask,
                       int* err);
 

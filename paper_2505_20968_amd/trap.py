@@ -63,7 +63,8 @@ class Info(ctypes.Structure):
                 ("bytes_device_total", ctypes.c_size_t), ("flops_contraction", ctypes.c_double),
                 ("bytes_contraction_fp64", ctypes.c_double), ("bytes_contraction_fp32", ctypes.c_double),
                 ("kernel_rows_mirrored", ctypes.c_longlong), ("kernel_entries", ctypes.c_longlong),
-                ("band_reach", ctypes.c_int)]
+                ("band_reach", ctypes.c_int), ("flops_contraction_fp32", ctypes.c_double),
+                ("kernel_entries_fp32", ctypes.c_longlong), ("band_reach_fp32", ctypes.c_int)]
 
 
 class SolveOpts(ctypes.Structure):
