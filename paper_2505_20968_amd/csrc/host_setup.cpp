@@ -992,6 +992,7 @@ size_t estimate_bytes(const trap_atom_desc* atom, const trap_problem_desc* pd, i
     item_vec(P.slot_dir);
     item_vec(P.slot_off);
     item_vec(P.pair_slot);
+    item_vec(P.pair_theta);
     item_vec(P.pair_off);
     item_vec(P.pair_o);
     item_vec(P.pair_dir);
@@ -1414,6 +1415,7 @@ int build_problem(trap_ctx* ctx, const trap_atom_desc* at, const trap_problem_de
   up.add(&P.d_slot_dir, P.slot_dir);
   up.add(&P.d_slot_off, P.slot_off);
   up.add(&P.d_pair_slot, P.pair_slot);
+  up.add(&P.d_pair_theta, P.pair_theta);
   up.add(&P.d_pair_off, P.pair_off);
   up.add(&P.d_pair_o, P.pair_o);
   up.add(&P.d_pair_dir, P.pair_dir);

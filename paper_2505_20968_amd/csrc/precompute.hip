@@ -1511,7 +1511,11 @@ int run_precompute(trap_ctx* ctx, int store_mask) {
   double* num = ctx->wk.r;
   hipLaunchKernelGGL(k_flat_field, dim3(ceil_div(npt, 256)), dim3(256), 0, s, npt, nd, nn, P.d_WT, flat);
   TRAP_HIP(hipGetLastError());
-  TRAP_TRY(sigma_apply(ctx, flat, num, TRAP_FP64, 0, 0));
+  // (its contraction reduces to the stored rows' sums: k_flat_contract)
+  ctx->flat_field = 1;
+  const int rcn = sigma_apply(ctx, flat, num, TRAP_FP64, 0, 0);
+  ctx->flat_field = 0;
+  TRAP_TRY(rcn);
   hipLaunchKernelGGL(k_norm_factor, dim3(ceil_div(npt, 256)), dim3(256), 0, s, npt, nd, nn, P.d_eps,
                      P.d_WT, C.d_K, num, P.d_kc, P.d_sc, P.d_eta0, C.d_f);
   TRAP_HIP(hipGetLastError());

@@ -423,6 +423,47 @@ __global__ void __launch_bounds__(512, 2) k_contract(int z0, int nth, int nt, in
   contract_block<T, NH, 4>(blockIdx.x, g, zl, z0, nth, nt, nn, nd, ks, Ibar, cgrp, slot_dir, W, nslot, Bs);
 }
 
+// The contraction of a flat incoming field, W_T in Stokes I at every
+// direction and frequency (Q, U, V zero), as the normalisation factor of
+// App. E asks for: every slot of angle Theta receives W_T times the sum of
+// its stored kernel row in Stokes I and zero in Q, U, V, the same for every
+// incoming direction.  So the intermediate is kept per Theta instead of per
+// slot, Wf[zl][t][theta][c][n][s] (the angular sum then reads it through the
+// pairs' Theta index), and one pass over the store (FP32 values plus
+// remainders, in FP64) replaces the products.  One wave per 16-row tile of
+// (height, Theta): the sixteen row sums, then one coalesced write of the
+// tile's 16 x 4 values.
+__global__ void __launch_bounds__(64) k_flat_contract(int z0, int nth, int nt, int nn, KStore ks,
+                                                      const double* __restrict__ WT, double* __restrict__ Wf) {
+  const int lane = threadIdx.x;
+  const long long u = blockIdx.x;                  // (zl, theta, tile)
+  const int q = (int)(u % ks.nq);
+  const int th = (int)((u / ks.nq) % nth), zl = (int)(u / ((long long)ks.nq * nth));
+  const long long zt = (long long)(z0 + zl) * nth + th;
+  const TileDesc d = ks.td[zt * ks.nq + q];
+  const int w = d.hi - d.lo;
+  // four lanes per row, float4 loads (every tile row starts at a multiple of
+  // 8 entries), sixteen columns per step of the four lanes
+  const int i = lane >> 2, sk = lane & 3;
+  const long long base = d.off + (long long)i * w;
+  double acc = 0.0;
+#pragma unroll 4
+  for (int c = 4 * sk; c < w; c += 16) {
+    const float4 h = *reinterpret_cast<const float4*>(ks.hi + base + c);
+    const float4 l = *reinterpret_cast<const float4*>(ks.lo + base + c);
+    acc += ((double)h.x + (double)l.x) + ((double)h.y + (double)l.y) + ((double)h.z + (double)l.z) +
+           ((double)h.w + (double)l.w);
+  }
+  acc += __shfl_xor(acc, 1, 4);
+  acc += __shfl_xor(acc, 2, 4);
+  const double v = acc;
+  // lane: row i = lane / 4, Stokes lane % 4
+  const int gr = tile_row0(ks.pad, ks.np, ks.nnp, q) + i, p = gr / ks.nnp, n = gr - p * ks.nnp;
+  if (p >= ks.np || n >= nn) return;
+  const int t = p >> 1, c = p & 1;
+  Wf[((((size_t)zl * nt + t) * nth + th) * 2 + c) * nn * 4 + (size_t)n * 4 + sk] = sk == 0 ? WT[z0 + zl] * v : 0.0;
+}
+
 // chunking of K: the fewest chunks of at most 128 columns, NH = chunk / 8
 static void contract_chunks(int ldm, int* nkc, int* nh) {
   *nkc = (ldm + 127) / 128;
@@ -1367,7 +1408,10 @@ static int sigma_apply_t(trap_ctx* ctx, const T* I, T* eps, int prec, int add_th
       const double flops = sizeof(T) == 8 ? chunk_flops(P, z0, zc) : chunk_flops32(P, z0, zc);
       const double bytes = sizeof(float) * kel + sizeof(T) * ((double)zc * nt * P.nslot * 2.0 * nn * 4 +
                                                                (double)zc * nd * nn * 4);
-      pr = prof_begin(ctx, sizeof(T) == 8 ? TRAP_STAGE_CONTRACT_FP64 : TRAP_STAGE_CONTRACT, flops, bytes);
+      // (the flat field's row sums are not a contraction: not recorded as one)
+      pr = ctx->flat_field ? -1
+                           : prof_begin(ctx, sizeof(T) == 8 ? TRAP_STAGE_CONTRACT_FP64 : TRAP_STAGE_CONTRACT, flops,
+                                        bytes);
     }
     if (!W) {
       TRAP_TRY(dalloc(ctx, &K.W[pi], (size_t)K.zchunk * nt * P.nslot * 2 * nn * 4 * sizeof(T)));
@@ -1377,6 +1421,10 @@ static int sigma_apply_t(trap_ctx* ctx, const T* I, T* eps, int prec, int add_th
       const int launched = launch_contract_pipe(ctx, ctx->stream, zc, z0, Ibar + (size_t)z0 * nd * nn * 4, W);
       if (launched < 0) return launched;
       if (!launched) TRAP_TRY(launch_contract<T>(ctx, zc, z0, Ibar + (size_t)z0 * nd * nn * 4, W));
+    } else if (ctx->flat_field) {
+      hipLaunchKernelGGL(k_flat_contract, dim3((unsigned)((long long)zc * nth * P.nq)), dim3(64), 0, s, z0, nth,
+                         nt, nn, kernel_store(ctx, false), P.d_WT, W);
+      TRAP_HIP(hipGetLastError());
     } else {
       TRAP_TRY(launch_contract<T>(ctx, zc, z0, Ibar + (size_t)z0 * nd * nn * 4, W));
     }
@@ -1393,9 +1441,11 @@ static int sigma_apply_t(trap_ctx* ctx, const T* I, T* eps, int prec, int add_th
                        : (nl == 1 ? k_angular<T, 1, kAngQ> : nl == 2 ? k_angular<T, 2, kAngQ>
                                                             : nl <= 4 ? k_angular<T, 4, kAngQ> : k_angular<T, 8, kAngQ>);
       const int kq = wide ? KW : kAngQ;
+      // (a flat field's intermediate is per Theta: k_flat_contract)
+      const bool flat = sizeof(T) == 8 && ctx->flat_field;
       hipLaunchKernelGGL(kern, dim3(zc * nd, ceil_div(nn, 64)), dim3(64 * kq), 0, s, z0, nd, nn, nu, nl,
-                         P.nslot, P.d_pair_slot, P.d_pair_index, cf, W, P.c_sc, P.d_E, P.d_bma, K.X, C.d_prof,
-                         Eb + (size_t)z0 * ncls * nd * nn * 4);
+                         flat ? nth : P.nslot, flat ? P.d_pair_theta : P.d_pair_slot, P.d_pair_index, cf, W,
+                         P.c_sc, P.d_E, P.d_bma, K.X, C.d_prof, Eb + (size_t)z0 * ncls * nd * nn * 4);
     }
     TRAP_HIP(hipGetLastError());
     prof_end(ctx, pr);

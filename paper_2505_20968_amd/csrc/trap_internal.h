@@ -213,6 +213,7 @@ struct Problem {
   double *d_theta_rows = nullptr;          // [nth_rows]
   double *d_theta_rw = nullptr;            // [nth_rows] AA weights
   int *d_slot_theta = nullptr, *d_slot_dir = nullptr, *d_slot_off = nullptr, *d_pair_slot = nullptr;
+  int* d_pair_theta = nullptr;             // [nd][nd] Theta index of each pair (flat-field applies)
   int *d_pair_off = nullptr, *d_pair_o = nullptr, *d_pair_dir = nullptr, *d_pair_index = nullptr;
   int *d_grp[2] = {nullptr, nullptr};
   int *d_cgrp[2] = {nullptr, nullptr};
@@ -333,6 +334,8 @@ struct trap_ctx {
   int prd_mode = 0;                 // TRAP_PRD_* of trap.h, applied at trap_set_problem
   int formal_scheme = 0;            // TRAP_FORMAL_* of trap.h
   int interp = 0;                   // TRAP_INTERP_* of trap.h: the frame transforms of Sigma
+  int flat_field = 0;               // nonzero while the FP64 apply of the normalisation runs: its
+                                    // field is W_T in Stokes I at every direction and frequency
   int interp_lin = 0;               // nonzero while an inner (linearised) Krylov apply runs:
                                     // its transforms are the spline whatever `interp` says
   // while set: BESSER formal solutions in this precision are linearised about
