@@ -383,7 +383,8 @@ __global__ void __launch_bounds__(64, 4) k_kernel_rows(
     const double* __restrict__ lam, const double* __restrict__ av, const double* __restrict__ st,
     const double* __restrict__ theta, double* __restrict__ Lout, double* __restrict__ Gout,
     long long row0, int z0, double h_uniform, const double* __restrict__ Gt,
-    const double2* __restrict__ Vt, int ntail, RowRoles roles, int2* __restrict__ gspan, int nacc) {
+    const double2* __restrict__ Vt, int ntail, RowRoles roles, int2* __restrict__ gspan, int nacc,
+    int span_only) {
   extern __shared__ double2 smem[];    // kernel_row_lds(nacc) bytes
   const int lane = threadIdx.x;
   double2* Lacc = smem;
@@ -398,8 +399,10 @@ __global__ void __launch_bounds__(64, 4) k_kernel_rows(
   const int t = (row / nn) % nt;
   const int th = (row / ((long long)nn * nt)) % nth;
   const int z = z0 + (int)(row / ((long long)nn * nt * nth));
-  // gspan (optional): the node range [x, y] outside which the row's Gam is
-  // zero (empty: x > y), for the K range of the product with Sig
+  // gspan (optional): the node range [x, y] outside which the row's L and
+  // Gam are zero (empty: x > y), for the product with Sig; with span_only
+  // the row stores hold the row inside that range only (the product reads
+  // nothing else), otherwise whole rows
   if (row_mirrored(roles, t, n, nn)) {                          // filled by k_mirror_rows
     if (gspan && lane == 0) gspan[row] = make_int2(nn, -1);
     return;
@@ -410,7 +413,16 @@ __global__ void __launch_bounds__(64, 4) k_kernel_rows(
   const size_t rre = cbase + (size_t)n * ldm, rim = cbase + (size_t)nn * ldm + (size_t)n * ldm;
   if (Th == 0.0) {
     const double2 w = wz(L * x[n] + s, a);
-    if (gspan && lane == 0) gspan[row] = make_int2(nn, -1);
+    if (gspan && lane == 0) gspan[row] = make_int2(n, n);
+    if (span_only) {
+      if (lane == 0) {
+        Lout[rre + n] = kSqrtPi * w.x;
+        Lout[rim + n] = kSqrtPi * w.y;
+        Gout[rre + n] = 0.0;
+        Gout[rim + n] = 0.0;
+      }
+      return;
+    }
     for (int m = lane; m < ldm; m += 64) {
       Lout[rre + m] = (m == n) ? kSqrtPi * w.x : 0.0;
       Lout[rim + m] = (m == n) ? kSqrtPi * w.y : 0.0;
@@ -499,9 +511,7 @@ __global__ void __launch_bounds__(64, 4) k_kernel_rows(
   }
   // table rule: knot intervals inside the support, one lane per interval
   const int ilo = max(plo, 0), ihi = min(phi, nn - 2);
-  // Gam gets the moments of inner knot intervals only (the tails add to L),
-  // all of them in [ilo, ihi] (the graded pieces lie inside [plo, phi])
-  if (gspan && lane == 0) gspan[row] = ilo <= ihi ? make_int2(ilo, ihi + 1) : make_int2(nn, -1);
+  if (gspan && lane == 0) gspan[row] = make_int2(base, top);
   for (int p = ilo + lane; fast && p <= ihi; p += 64) {
     if (p >= kA && p <= kB) continue;
     double2 acc[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
@@ -658,6 +668,16 @@ __global__ void __launch_bounds__(64, 4) k_kernel_rows(
     if (lane == 0) add_moments(Lacc, Gacc, x, nn, base, side == 0 ? -1 : nn - 1, &acc);
   }
   wave_sync();
+  if (span_only) {
+    for (int m = base + lane; m <= top; m += 64) {
+      const double2 lv = Lacc[m - base], gv = Gacc[m - base];
+      Lout[rre + m] = lv.x;
+      Lout[rim + m] = lv.y;
+      Gout[rre + m] = gv.x;
+      Gout[rim + m] = gv.y;
+    }
+    return;
+  }
   for (int m = lane; m < ldm; m += 64) {
     const bool in = m >= base && m <= top;
     const double2 lv = in ? Lacc[m - base] : make_double2(0.0, 0.0);
@@ -994,9 +1014,13 @@ __global__ void __launch_bounds__(64 * kTileGemmWaves) k_sig_gemm_tiles(
   // K range: the tile's column range, cut to the union of its rows' Gam
   // spans (Gam is zero outside them, so the sum is the same)
   int klo = d.lo, khi = min(d.hi, nn);
+  // complex row of real row r = [zl][th][t][c][n]: [zl][th][t][n]
+  auto span_of = [&](long long r) {
+    return r < 0 ? make_int2(nn, -1) : gspan[(r / (2LL * nn)) * nn + r % nn];
+  };
+  // the lane's own row span: the row stores hold nothing valid outside it
+  const int2 sp = gspan ? span_of(ra) : make_int2(0, nn - 1);
   if (gspan) {
-    // complex row of real row ra = [zl][th][t][c][n]: [zl][th][t][n]
-    const int2 sp = ra < 0 ? make_int2(nn, -1) : gspan[(ra / (2LL * nn)) * nn + ra % nn];
     int a0 = sp.x, a1 = sp.y;
 #pragma unroll
     for (int m = 1; m < 16; m <<= 1) {
@@ -1023,7 +1047,9 @@ __global__ void __launch_bounds__(64 * kTileGemmWaves) k_sig_gemm_tiles(
     for (int u = 0; u < KU; ++u) {
       const int k = k0 + 4 * u + lk;
       const int kc = min(k, kmax);
-      af[u] = grow[kc] * ((ra >= 0 && k < khi) ? 1.0 : 0.0);
+      // (a select, not a product: outside the span the stores hold stale values)
+      const double g = grow[kc];
+      af[u] = (ra >= 0 && k < khi && k >= sp.x && k <= sp.y) ? g : 0.0;
 #pragma unroll
       for (int j = 0; j < 4; ++j) bf[u][j] = Sig[(size_t)kc * nn + min(c0 + 16 * j + lr, nn - 1)];
     }
@@ -1038,11 +1064,13 @@ __global__ void __launch_bounds__(64 * kTileGemmWaves) k_sig_gemm_tiles(
     const int i = lk + 4 * r;
     const long long rc = crow(i);
     if (rc < 0) continue;
+    const int2 si = gspan ? span_of(rc) : make_int2(0, nn - 1);
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int col = c0 + 16 * j + lr;
       if (col >= d.hi) continue;
-      const double v = col < nn ? acc[j][r] + Lrow[rc * ldm + col] : 0.0;
+      const double lv = Lrow[rc * ldm + min(col, nn - 1)];
+      const double v = col < nn ? acc[j][r] + ((col >= si.x && col <= si.y) ? lv : 0.0) : 0.0;
       band_put(B, d.off + (long long)i * w + (col - d.lo), v);
     }
   }
@@ -1447,6 +1475,9 @@ int run_precompute(trap_ctx* ctx, int store_mask) {
     roles.on = 1;
     for (int t = 0; t < nt; ++t) roles.role[t] = P.row_role[t];
   }
+  // the tile product reads each row inside its span only: the kernel rows
+  // then write just that part (the other products read whole rows)
+  const int span_only = (!aa && !sig_gemm_fits_lds(ctx)) ? 1 : 0;
   const int pr = prof_begin(ctx, TRAP_STAGE_KERNEL_ROWS);
   for (int z0 = 0; z0 < nz; z0 += zc_tab) {
     const int zc = std::min(zc_tab, nz - z0);
@@ -1462,7 +1493,8 @@ int run_precompute(trap_ctx* ctx, int store_mask) {
       hipLaunchKernelGGL(k_kernel_rows, dim3((unsigned)nr), dim3(64), lds, s, nr, nthr, nt,
                          nn, P.ldm, P.d_x,
                          P.d_lam, P.d_a, P.d_st, P.d_theta_rows, C.d_Lrow, C.d_Grow, r0, z0, h,
-                         uniform ? C.d_Gt : nullptr, uniform ? C.d_Vt : nullptr, ntail, roles, C.d_gspan, nacc);
+                         uniform ? C.d_Gt : nullptr, uniform ? C.d_Vt : nullptr, ntail, roles, C.d_gspan, nacc,
+                         span_only);
       TRAP_HIP(hipGetLastError());
     }
     const long long rrows = 2 * nrows;                           // real rows (both planes)
@@ -1762,7 +1794,7 @@ static int precompute_precond_body(trap_ctx* ctx) {
     const long long nrows = (long long)zc * ng * nk * nn;
     hipLaunchKernelGGL(k_kernel_rows, dim3((unsigned)nrows), dim3(64), lds_kr, s, nrows, ng,
                        nk, nn, ldm, P.d_x, P.d_lam, P.d_a, C.d_pcSt, C.d_pcTheta, Lrow, Grow, 0LL, z0, lay.h,
-                       lay.uniform ? Gt : nullptr, lay.uniform ? Vt : nullptr, lay.ntail, RowRoles{}, nullptr, nacc);
+                       lay.uniform ? Gt : nullptr, lay.uniform ? Vt : nullptr, lay.ntail, RowRoles{}, nullptr, nacc, 0);
     TRAP_HIP(hipGetLastError());
     TRAP_TRY(launch_sig_gemm(ctx, 2 * nrows, Grow, Lrow, Mtmp, (float*)nullptr, 0LL));
     hipLaunchKernelGGL(k_theta_average_dense, dim3(ceil_div(per_z_out * zc, 256)), dim3(256), 0, s, per_z_out, ng,
