@@ -978,22 +978,20 @@ __global__ void __launch_bounds__(512, 1) k_sig_gemm_lds(long long nrows, int nn
 // to k_mirror_rows.
 constexpr int kTileGemmWaves = 4;
 __global__ void __launch_bounds__(64 * kTileGemmWaves) k_sig_gemm_tiles(
-    int zc, int nth, int nt, int nn, int ldm, int nnp, int nq, int ncg, const double* __restrict__ Gam,
+    int zc, int nth, int nt, int nn, int ldm, int nnp, int nq, const double* __restrict__ Gam,
     const double* __restrict__ Lrow, const double* __restrict__ Sig, BandOut B, RowRoles roles,
     const int2* __restrict__ gspan) {
-  const long long unit = (long long)blockIdx.x * kTileGemmWaves + (threadIdx.x >> 6);
-  const long long nunit = (long long)zc * nth * nq * ncg;
-  if (unit >= nunit) return;
+  // one wave per tile, looping over its 64-column groups (the rows' setup
+  // and their Gam, cached after the first group, serve every group)
+  const long long tq = (long long)blockIdx.x * kTileGemmWaves + (threadIdx.x >> 6);
+  if (tq >= (long long)zc * nth * nq) return;
   const int lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
-  const int cg = (int)(unit % ncg);
-  const long long tq = unit / ncg;
   const int q = (int)(tq % nq);
   const int th = (int)((tq / nq) % nth), zl = (int)(tq / ((long long)nq * nth));
   const int np = 2 * nt;
   const size_t zt = (size_t)(B.z0 + zl) * nth + th;
   const TileDesc d = B.td[zt * nq + q];
-  const int c0 = d.lo + 64 * cg;
-  if (c0 >= d.hi) return;
+  if (d.hi <= d.lo) return;
   const int r0 = tile_row0(B.pad, np, nnp, q);
   // chunk row of tile row i (or -1 past the grid), and whether every row is mirrored
   auto crow = [&](int i) -> long long {
@@ -1030,48 +1028,54 @@ __global__ void __launch_bounds__(64 * kTileGemmWaves) k_sig_gemm_tiles(
     klo = max(klo, a0);
     khi = min(khi, a1 + 1);
   }
-  doublex4_g acc[4];
+  // the stored rows' spans of this lane's output rows (epilogue)
+  int2 si[4];
 #pragma unroll
-  for (int j = 0; j < 4; ++j)
-    for (int r = 0; r < 4; ++r) acc[j][r] = 0.0;
-  // Four K steps per iteration, their loads issued together ahead of the
-  // products.  The loads are unconditional (indices clamped into the valid
-  // range): a bounds test around each load becomes a branch with a wait in
-  // front of its product.  Steps past the range are cancelled through the
-  // Gam operand (times 0); columns past the grid are not stored.
-  const int kmax = max(khi - 1, 0);
-  constexpr int KU = 4;
-  for (int k0 = klo; k0 < khi; k0 += 4 * KU) {
-    double af[KU], bf[KU][4];
+  for (int r = 0; r < 4; ++r) si[r] = gspan ? span_of(crow(lk + 4 * r)) : make_int2(0, nn - 1);
+  const int w = d.hi - d.lo;
+  for (int c0 = d.lo; c0 < d.hi; c0 += 64) {
+    doublex4_g acc[4];
 #pragma unroll
-    for (int u = 0; u < KU; ++u) {
-      const int k = k0 + 4 * u + lk;
-      const int kc = min(k, kmax);
-      // (a select, not a product: outside the span the stores hold stale values)
-      const double g = grow[kc];
-      af[u] = (ra >= 0 && k < khi && k >= sp.x && k <= sp.y) ? g : 0.0;
+    for (int j = 0; j < 4; ++j)
+      for (int r = 0; r < 4; ++r) acc[j][r] = 0.0;
+    // Four K steps per iteration, their loads issued together ahead of the
+    // products.  The loads are unconditional (indices clamped into the valid
+    // range): a bounds test around each load becomes a branch with a wait in
+    // front of its product.  Steps outside the range or the row's span are
+    // cancelled through the Gam operand (selected to 0); columns past the
+    // grid are not stored.
+    const int kmax = max(khi - 1, 0);
+    constexpr int KU = 4;
+    for (int k0 = klo; k0 < khi; k0 += 4 * KU) {
+      double af[KU], bf[KU][4];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) bf[u][j] = Sig[(size_t)kc * nn + min(c0 + 16 * j + lr, nn - 1)];
+      for (int u = 0; u < KU; ++u) {
+        const int k = k0 + 4 * u + lk;
+        const int kc = min(k, kmax);
+        // (a select, not a product: outside the span the stores hold stale values)
+        const double g = grow[kc];
+        af[u] = (ra >= 0 && k < khi && k >= sp.x && k <= sp.y) ? g : 0.0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) bf[u][j] = Sig[(size_t)kc * nn + min(c0 + 16 * j + lr, nn - 1)];
+      }
+#pragma unroll
+      for (int u = 0; u < KU; ++u)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[u], bf[u][j], acc[j], 0, 0, 0);
     }
 #pragma unroll
-    for (int u = 0; u < KU; ++u)
+    for (int r = 0; r < 4; ++r) {
+      const int i = lk + 4 * r;
+      const long long rc = crow(i);
+      if (rc < 0) continue;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[u], bf[u][j], acc[j], 0, 0, 0);
-  }
-  const int w = d.hi - d.lo;
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int i = lk + 4 * r;
-    const long long rc = crow(i);
-    if (rc < 0) continue;
-    const int2 si = gspan ? span_of(rc) : make_int2(0, nn - 1);
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int col = c0 + 16 * j + lr;
-      if (col >= d.hi) continue;
-      const double lv = Lrow[rc * ldm + min(col, nn - 1)];
-      const double v = col < nn ? acc[j][r] + ((col >= si.x && col <= si.y) ? lv : 0.0) : 0.0;
-      band_put(B, d.off + (long long)i * w + (col - d.lo), v);
+      for (int j = 0; j < 4; ++j) {
+        const int col = c0 + 16 * j + lr;
+        if (col >= d.hi) continue;
+        const double lv = Lrow[rc * ldm + min(col, nn - 1)];
+        const double v = col < nn ? acc[j][r] + ((col >= si[r].x && col <= si[r].y) ? lv : 0.0) : 0.0;
+        band_put(B, d.off + (long long)i * w + (col - d.lo), v);
+      }
     }
   }
 }
@@ -1500,10 +1504,9 @@ int run_precompute(trap_ctx* ctx, int store_mask) {
     const long long rrows = 2 * nrows;                           // real rows (both planes)
     bo.z0 = z0;
     if (!aa && !sig_gemm_fits_lds(ctx)) {
-      const int ncg = ceil_div(P.ldm, 64);
-      const long long units = (long long)zc * nth * P.nq * ncg;
+      const long long units = (long long)zc * nth * P.nq;          // tiles
       hipLaunchKernelGGL(k_sig_gemm_tiles, dim3((unsigned)ceil_div(units, kTileGemmWaves)),
-                         dim3(64 * kTileGemmWaves), 0, s, zc, nth, nt, nn, P.ldm, P.nnp, P.nq, ncg, C.d_Grow,
+                         dim3(64 * kTileGemmWaves), 0, s, zc, nth, nt, nn, P.ldm, P.nnp, P.nq, C.d_Grow,
                          C.d_Lrow, P.d_Sig, bo, roles, C.d_gspan);
       TRAP_HIP(hipGetLastError());
     } else if (!aa) {
