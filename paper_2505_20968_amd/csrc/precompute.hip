@@ -1067,7 +1067,15 @@ __global__ void __launch_bounds__(64 * kTileGemmWaves) k_sig_gemm_tiles(
     for (int r = 0; r < 4; ++r) {
       const int i = lk + 4 * r;
       const long long rc = crow(i);
-      if (rc < 0) continue;
+      if (rc < 0) {
+        // a row past the grid (padding): zeros, so the store holds no stale values
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int col = c0 + 16 * j + lr;
+          if (col < d.hi) band_put(B, d.off + (long long)i * w + (col - d.lo), 0.0);
+        }
+        continue;
+      }
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int col = c0 + 16 * j + lr;
@@ -1433,15 +1441,28 @@ int run_precompute(trap_ctx* ctx, int store_mask) {
   // FP32 remainders (the FP64 kernel is their sum); store_mask bit 1 decides
   // only whether the FP32 applies' coefficient tables are built
   const int mask = store_mask | 1;     // FP64 applies always exist (residual, f, b)
+  // mirror roles of the transitions' rows: mirrored rows come from their
+  // mirror images (the mirror pass takes one grid row per angle, transition
+  // and plane)
+  RowRoles roles{};
+  if (!P.row_role.empty() && nt <= kMaxRoles && (long long)nth * nt * 2 <= 65535) {
+    roles.on = 1;
+    for (int t = 0; t < nt; ++t) roles.role[t] = P.row_role[t];
+  }
+  // the tile product writes every row of every tile, the rows past the grid
+  // (padding) as zeros, unless mirror roles let it skip tiles
+  const bool tile_path = !aa && !sig_gemm_fits_lds(ctx);
   if (!C.d_Mhi) {
     const size_t ne = std::max<size_t>(P.kentries, 2);
     TRAP_TRY(dalloc_t(ctx, &C.d_Mhi, ne));
     TRAP_TRY(dalloc_t(ctx, &C.d_Mlo, ne));
-    // rows of a tile past the grid (padding) are never written: zero
-    const int fg = (int)std::min<long long>(4096, ceil_div((long long)ne, 256));
-    hipLaunchKernelGGL(k_fill_zero, dim3(fg), dim3(256), 0, s, C.d_Mhi, (long long)ne);
-    hipLaunchKernelGGL(k_fill_zero, dim3(fg), dim3(256), 0, s, C.d_Mlo, (long long)ne);
-    TRAP_HIP(hipGetLastError());
+    if (!tile_path || roles.on) {
+      // rows of a tile past the grid (padding) are never written otherwise: zero
+      const int fg = (int)std::min<long long>(4096, ceil_div((long long)ne, 256));
+      hipLaunchKernelGGL(k_fill_zero, dim3(fg), dim3(256), 0, s, C.d_Mhi, (long long)ne);
+      hipLaunchKernelGGL(k_fill_zero, dim3(fg), dim3(256), 0, s, C.d_Mlo, (long long)ne);
+      TRAP_HIP(hipGetLastError());
+    }
   }
   C.store_mask = mask;
   BandOut bo;
@@ -1473,15 +1494,9 @@ int run_precompute(trap_ctx* ctx, int store_mask) {
     if (aa) TRAP_TRY(dalloc_t(ctx, &C.d_Mtmp, (size_t)zc_tab * rows_per_z * P.ldm));
     C.zc_rows = zc_tab;
   }
-  RowRoles roles{};
-  // (the mirror pass takes one grid row per angle, transition and plane)
-  if (!P.row_role.empty() && nt <= kMaxRoles && (long long)nth * nt * 2 <= 65535) {
-    roles.on = 1;
-    for (int t = 0; t < nt; ++t) roles.role[t] = P.row_role[t];
-  }
   // the tile product reads each row inside its span only: the kernel rows
   // then write just that part (the other products read whole rows)
-  const int span_only = (!aa && !sig_gemm_fits_lds(ctx)) ? 1 : 0;
+  const int span_only = tile_path ? 1 : 0;
   const int pr = prof_begin(ctx, TRAP_STAGE_KERNEL_ROWS);
   for (int z0 = 0; z0 < nz; z0 += zc_tab) {
     const int zc = std::min(zc_tab, nz - z0);
@@ -1503,7 +1518,7 @@ int run_precompute(trap_ctx* ctx, int store_mask) {
     }
     const long long rrows = 2 * nrows;                           // real rows (both planes)
     bo.z0 = z0;
-    if (!aa && !sig_gemm_fits_lds(ctx)) {
+    if (tile_path) {
       const long long units = (long long)zc * nth * P.nq;          // tiles
       hipLaunchKernelGGL(k_sig_gemm_tiles, dim3((unsigned)ceil_div(units, kTileGemmWaves)),
                          dim3(64 * kTileGemmWaves), 0, s, zc, nth, nt, nn, P.ldm, P.nnp, P.nq, C.d_Grow,
