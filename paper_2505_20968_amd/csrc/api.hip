@@ -38,10 +38,11 @@ void note_hip(const char* what, const char* where, hipError_t e) {
 }
 
 // Device memory comes from the device's stream-ordered pool, allocated and
-// returned on the context's stream: a freed buffer stays in the pool (its
-// release threshold is raised once per device) and serves the next context
-// without a device-wide synchronisation or a new mapping.  Devices whose
-// runtime has no pool take hipMalloc / hipFree.
+// returned on the context's stream: a buffer a context frees while it lives
+// (a new problem's spares) stays in the pool (its release threshold is raised
+// once per device) without a device-wide synchronisation; a destroyed
+// context's memory is trimmed back to the device.  Devices whose runtime has
+// no pool take hipMalloc / hipFree.
 namespace {
 std::mutex g_pool_mu;
 std::set<int> g_pool_ready, g_pool_absent;
@@ -94,6 +95,14 @@ int dalloc(trap_ctx* ctx, void** p, size_t bytes) {
     }
   const bool pooled = device_pooled(ctx->device);
   hipError_t e = pooled ? hipMallocAsync(&q, bytes, ctx->stream) : hipMalloc(&q, bytes);
+  if (e != hipSuccess && pooled) {
+    // the pool may hold freed blocks that fit no request: return them to the
+    // device (once this stream's frees have run) and try once more
+    (void)hipGetLastError();
+    TRAP_NOTE(hipStreamSynchronize(ctx->stream));
+    device_pool_trim(ctx->device);
+    e = hipMallocAsync(&q, bytes, ctx->stream);
+  }
   if (e != hipSuccess) {
     (void)hipGetLastError();
     return fail(TRAP_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed: " +
@@ -258,12 +267,13 @@ int trap_destroy(trap_ctx* ctx) {
   }
   if (ctx->ev_fork) TRAP_NOTE(hipEventDestroy(ctx->ev_fork));
   if (ctx->ev_join) TRAP_NOTE(hipEventDestroy(ctx->ev_join));
-  if (batch_arena_release(ctx->device)) {
-    // the device's last context: the pool's memory goes back to the device,
-    // once the context's stream-ordered frees have run
-    TRAP_NOTE(hipStreamSynchronize(ctx->stream));
-    device_pool_trim(ctx->device);
-  }
+  (void)batch_arena_release(ctx->device);
+  // the context's memory goes back to the device once its stream-ordered
+  // frees have run: freed blocks kept in the pool are invisible to every
+  // other allocator, the runtime's own (kernel scratch) included, so a
+  // stream of contexts of different sizes would otherwise exhaust the device
+  TRAP_NOTE(hipStreamSynchronize(ctx->stream));
+  device_pool_trim(ctx->device);
   delete ctx;
   return TRAP_OK;
 }

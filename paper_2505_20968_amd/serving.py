@@ -52,7 +52,12 @@ class Scheduler:
     handle``, ``step(handles) -> list of status`` (1 running, else final status)
     and ``finish(handle) -> (status, stats, result)``.  An admit that raises
     ends that request only (status: the exception's ``code``, else
-    TRAP_EDEVICE); the backend releases what it had built for it."""
+    TRAP_EDEVICE); the backend releases what it had built for it.  A backend
+    with ``device_free() -> bytes`` and ``reserve`` (bytes) is also held to
+    what the device has free: a request waits until the device keeps
+    ``reserve`` free beside it (room for the runtime's own allocations, kernel
+    scratch among them), and is rejected when nothing runs and it still does
+    not fit."""
 
     def __init__(self, backend, mem_budget: int, max_active: int = 16,
                  clock: Callable[[], float] = time.perf_counter,
@@ -89,6 +94,14 @@ class Scheduler:
                     continue
                 if used + need > self.mem_budget:     # wait for memory (arrival order is kept)
                     break
+                if hasattr(self.backend, "device_free"):
+                    if self.backend.device_free() - need < getattr(self.backend, "reserve", 0):
+                        if active:                    # finished requests give memory back
+                            break
+                        queue.popleft()               # nothing runs: it cannot fit now
+                        req.status = TRAP_ENOMEM
+                        req.admitted = req.done = self.clock() - t0
+                        continue
                 queue.popleft()
                 req.admitted = self.clock() - t0
                 ta = self.clock()
@@ -144,6 +157,11 @@ class DeviceBackend:
                          precond_sweeps=self.precond)
         self._footprint = footprint
         self.admit_parts = {"context": 0.0, "set_problem": 0.0, "precompute": 0.0, "begin": 0.0}
+        # device memory kept free beside the admitted requests (5 % of the device)
+        self.reserve = int(0.05 * torch.cuda.mem_get_info(device)[1])
+
+    def device_free(self) -> int:
+        return int(self.torch.cuda.mem_get_info(self.device)[0])
 
     def footprint(self, problem) -> int:
         # library allocations plus the solution vector held by the caller
@@ -195,9 +213,14 @@ class DeviceBackend:
         return [next(st) if h["is_ready"] else 1 for h in handles]
 
     def finish(self, handle):
+        from .trap import TrapError
         ctx, x = handle["ctx"], handle["x"]
-        stats = ctx.gmres_end(raise_on_noconv=False)
-        em = ctx.emergent(x)
+        try:
+            stats = ctx.gmres_end(raise_on_noconv=False)
+            em = ctx.emergent(x)
+        except TrapError as e:            # the request fails alone
+            ctx.close()
+            return int(e.code), {"error": str(e)}, None
         ctx.close()
         return stats["status"], stats, em
 

@@ -122,3 +122,41 @@ def test_an_admission_failure_ends_that_request_only():
     assert s.peak_used <= 100
     assert [e[1] for e in be.log if e[0] == "admit"] == [0, 2, 3]
     assert max(r.done for r in out) <= 4.0 + 1e-9
+
+
+class DeviceHoldingBackend(FakeBackend):
+    """A device of `total` bytes of which `held_elsewhere` are taken by others
+    (memory no footprint counts); it keeps `reserve` free beside the requests."""
+
+    def __init__(self, clock, total, held_elsewhere, reserve):
+        super().__init__(clock)
+        self.total, self.held_elsewhere, self.reserve = total, held_elsewhere, reserve
+        self.mem = {}
+
+    def admit(self, p):
+        h = super().admit(p)
+        self.mem[h] = p["mem"]
+        assert self.device_free() >= self.reserve            # never admitted past the reserve
+        return h
+
+    def finish(self, h):
+        del self.mem[h]
+        return super().finish(h)
+
+    def device_free(self):
+        return self.total - self.held_elsewhere - sum(self.mem.values())
+
+
+def test_device_free_memory_and_reserve_are_respected():
+    """The budget alone would admit all four at once; the device has less free
+    than the budget assumes, so requests wait for finished ones, and one that
+    cannot fit beside the reserve even on an idle device is rejected."""
+    clock = FakeClock()
+    be = DeviceHoldingBackend(clock, total=200, held_elsewhere=60, reserve=20)
+    reqs = [Request(i, 0.0, {"id": i, "mem": 50, "steps": 2}) for i in range(4)]
+    reqs.append(Request(4, 0.0, {"id": 4, "mem": 130, "steps": 1}))      # 200 - 60 - 130 < 20
+    s = Scheduler(be, mem_budget=1000, max_active=8, clock=clock, sleep=clock.sleep)
+    out = s.run(reqs)
+    assert [r.status for r in out[:4]] == [0, 0, 0, 0]
+    assert out[4].status == TRAP_ENOMEM
+    assert s.peak_active == 2                                 # 140 free - 2 x 50 leaves the 20 reserve
