@@ -38,14 +38,17 @@ __device__ inline void pc_second_derivs(int nn, const double* __restrict__ SigT,
   const int q = threadIdx.x / per, i0 = threadIdx.x % per;
   const int j0 = q * nn / kGatherParts, j1 = (q + 1) * nn / kGatherParts;
   for (int i = i0; i < nn; i += per) {
-    double a0 = 0.0, a1 = 0.0;
+    // four independent chains: four loads in flight per thread
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
     int j = j0;
-    for (; j + 2 <= j1; j += 2) {
+    for (; j + 4 <= j1; j += 4) {
       a0 += SigT[(size_t)j * nn + i] * v[j];
       a1 += SigT[(size_t)(j + 1) * nn + i] * v[j + 1];
+      a2 += SigT[(size_t)(j + 2) * nn + i] * v[j + 2];
+      a3 += SigT[(size_t)(j + 3) * nn + i] * v[j + 3];
     }
-    if (j < j1) a0 += SigT[(size_t)j * nn + i] * v[j];
-    part[q * nn + i] = a0 + a1;
+    for (; j < j1; ++j) a0 += SigT[(size_t)j * nn + i] * v[j];
+    part[q * nn + i] = (a0 + a1) + (a2 + a3);
   }
   __syncthreads();
   for (int i = threadIdx.x; i < nn; i += blockDim.x) {
@@ -126,11 +129,20 @@ __device__ __forceinline__ void pc_gather_fin_body(int bx, int nn, int ncmax, co
   __syncthreads();
   const double* Mz = Mat + (size_t)z * nn * nn;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  for (int n = wave; n < nn; n += nw) {
-    double a = 0.0;
-    for (int m = lane; m < nn; m += 64) a += Mz[(size_t)n * nn + m] * G[m];
-    for (int off = 32; off > 0; off >>= 1) a += __shfl_down(a, off, 64);
-    if (lane == 0) hv[n] = a;
+  // four rows per wave at a time (their loads in flight together; rows past
+  // the end read the last row and are not stored)
+  for (int n0 = 4 * wave; n0 < nn; n0 += 4 * nw) {
+    double a[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int m = lane; m < nn; m += 64) {
+      const double g = G[m];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) a[r] += Mz[(size_t)min(n0 + r, nn - 1) * nn + m] * g;
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      for (int off = 32; off > 0; off >>= 1) a[r] += __shfl_down(a[r], off, 64);
+      if (lane == 0 && n0 + r < nn) hv[n0 + r] = a[r];
+    }
   }
   __syncthreads();
   double* hz = h + (size_t)z * 2 * nn;
