@@ -69,12 +69,14 @@ __device__ __forceinline__ void pc_gather_cls_body(int bx, int nd, int nn, int n
                                                    const int* __restrict__ moff, const int* __restrict__ ncls,
                                                    const double* __restrict__ cub, const double* __restrict__ src,
                                                    int stride, double* __restrict__ gc) {
-  extern __shared__ double sh[];
+  extern __shared__ double sh[];     // pc_gather_lds(nn) bytes
   double* v = sh;
   double* sd = sh + nn;
   double* part = sh + 2 * nn;       // [kGatherParts][nn]
+  double* xg = sh + (2 + kGatherParts) * nn;   // the frequency grid
   const int z = bx / ncmax, c = bx % ncmax;
   if (c >= ncls[z]) return;
+  for (int n = threadIdx.x; n < nn; n += blockDim.x) xg[n] = x[n];
   const double shf = cub[(size_t)z * nd + c] / lam[z];
   const int* mz = mem + (size_t)z * nd;
   const int k0 = moff[(size_t)z * (nd + 1) + c], k1 = moff[(size_t)z * (nd + 1) + c + 1];
@@ -92,7 +94,7 @@ __device__ __forceinline__ void pc_gather_cls_body(int bx, int nd, int nn, int n
   __syncthreads();
   pc_second_derivs(nn, SigT, v, part, sd);
   double* g = gc + ((size_t)z * ncmax + c) * nn;
-  for (int m = threadIdx.x; m < nn; m += blockDim.x) g[m] = spline_at(x, nn, v, sd, x[m] - shf);
+  for (int m = threadIdx.x; m < nn; m += blockDim.x) g[m] = spline_at(xg, nn, v, sd, xg[m] - shf);
 }
 
 __global__ void __launch_bounds__(kGatherThreads) k_pc_gather_cls(int nd, int nn, int ncmax,
@@ -269,10 +271,10 @@ static int pc_gather(trap_ctx* ctx, const PcWork& ws, const double* src, int str
   Problem& P = ctx->pb;
   Precomp& C = ctx->pre;
   hipLaunchKernelGGL(k_pc_gather_cls, dim3(P.nz * C.pc_ncmax), dim3(kGatherThreads),
-                     (2 + kGatherParts) * P.nn * sizeof(double), ctx->stream, P.nd, P.nn, C.pc_ncmax, P.d_x,
+                     pc_gather_lds(P.nn), ctx->stream, P.nd, P.nn, C.pc_ncmax, P.d_x,
                      P.d_SigT, P.d_lam, P.d_w, C.d_pcMem, C.d_pcMoff, C.d_pcNcls, C.d_pcCub, src, stride, ws.gc);
   TRAP_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_pc_gather_fin, dim3(P.nz), dim3(kGatherThreads), (2 + kGatherParts) * P.nn * sizeof(double),
+  hipLaunchKernelGGL(k_pc_gather_fin, dim3(P.nz), dim3(kGatherThreads), pc_gather_lds(P.nn),
                      ctx->stream, P.nn, C.pc_ncmax, P.d_SigT, C.d_pcNcls, ws.gc, Mat, ws.h);
   TRAP_HIP(hipGetLastError());
   return TRAP_OK;

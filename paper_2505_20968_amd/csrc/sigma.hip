@@ -2036,7 +2036,7 @@ int op_apply_batch_f32(trap_ctx** ctxs, int n, const double* const* x, double* c
       b.push_back(GPcFin{P.nn, C.pc_ncmax, P.d_SigT, C.d_pcNcls, K.pc_gc, phi ? C.d_pcPhi : C.d_pcC, K.pc_h});
       ca.push_back(P.nz * C.pc_ncmax);
       cb.push_back(P.nz);
-      lds = std::max(lds, (size_t)6 * P.nn * sizeof(double));
+      lds = std::max(lds, pc_gather_lds(P.nn));
     }
     add_stage(SK_PC_CLS, 0, blob.put(a), ca, lds);
     add_stage(SK_PC_FIN, 0, blob.put(b), cb, lds);

@@ -525,6 +525,10 @@ struct GPcCls {
   const double *cub, *src;
   double* gc;
 };
+// LDS of the preconditioner's gather kernels (per block): the vector, its
+// spline second derivatives, four rows of partial sums and a copy of the
+// frequency grid (the spline evaluations search it there).
+constexpr size_t pc_gather_lds(int nn) { return (size_t)7 * nn * sizeof(double); }
 struct GPcFin {
   int nn, ncmax;
   const double* SigT;
