@@ -130,6 +130,13 @@ void free_all(trap_ctx* ctx) {
   gmres_release(ctx);
   release_spare(ctx);
   ctx->spare.swap(ctx->bufs);
+  auto& hs = ctx->host_spare;
+  hs.td = std::move(ctx->pb.td);
+  hs.qk = std::move(ctx->pb.qk);
+  hs.qk32 = std::move(ctx->pb.qk32);
+  hs.qb = std::move(ctx->pb.qb);
+  hs.qb32 = std::move(ctx->pb.qb32);
+  hs.tofs = std::move(ctx->pb.tofs);
   ctx->pb = Problem();
   ctx->pre = Precomp();
   ctx->wk = Work();

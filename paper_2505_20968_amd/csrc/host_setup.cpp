@@ -728,19 +728,23 @@ void kernel_bands(Problem& P, const std::vector<double>& sig) {
   // wave tiles in both row layouts; the one with less column work is kept:
   // every wave of a block steps through the block's column range (the union
   // of its eight tiles' ranges), times the incoming slots of the angle
-  auto tiles = [&](bool pad, std::vector<int>& row0, host_vec<unsigned>& qk, host_vec<unsigned>& qk32,
+  // tiles(pad, row0, qk, qk32, work): the column work of a layout, and with
+  // qk / qk32 given, every tile's range and FP32 window (the layout is first
+  // chosen by its work alone, then only the chosen one is filled)
+  auto tiles = [&](bool pad, std::vector<int>& row0, host_vec<unsigned>* qk, host_vec<unsigned>* qk32,
                    double* work) {
     const int nnp = pad ? (nn + 15) / 16 * 16 : nn;
     const int rows = np * nnp;
     const int nq = (rows + 15) / 16;
     row0.assign(nq, 0);
     for (int q = 0; q < nq; ++q) row0[q] = pad ? (q % np) * nnp + 16 * (q / np) : 16 * q;
-    qk.resize((size_t)nz * nth * nq);                  // every entry written below
-    qk32.resize((size_t)nz * nth * nq);
+    if (qk) qk->resize((size_t)nz * nth * nq);         // every entry written below
+    if (qk32) qk32->resize((size_t)nz * nth * nq);
     std::vector<double> work_zt(nzt, 0.0);
     // the band ends never decrease with n, so a run of rows n_a..n_b of one
     // plane spans [lo(n_a), hi(n_b))
     host_parallel(nzt, 64, [&](size_t zt0, size_t zt1) {
+      std::vector<unsigned> qz(nq);                    // this (z, theta)'s tile ranges
       for (size_t zt = zt0; zt < zt1; ++zt) {
         const short* bl = &blo[zt * nn];
         const short* bh = &bhi[zt * nn];
@@ -764,17 +768,20 @@ void kernel_bands(Problem& P, const std::vector<double>& sig) {
           if (hi <= lo) lo = hi = 0;
           lo = lo / 8 * 8;
           hi = std::min((hi + 7) / 8 * 8, P.ldm);
-          qk[zt * nq + q] = (unsigned)lo | ((unsigned)hi << 16);
-          // inside the tile's range (rounded the same way)
-          lo32 = std::max(lo, lo32 / 8 * 8);
-          hi32 = std::min(hi, (hi32 + 7) / 8 * 8);
-          if (hi32 <= lo32) lo32 = hi32 = lo;
-          qk32[zt * nq + q] = (unsigned)lo32 | ((unsigned)hi32 << 16);
+          qz[q] = (unsigned)lo | ((unsigned)hi << 16);
+          if (qk) (*qk)[zt * nq + q] = qz[q];
+          if (qk32) {
+            // inside the tile's range (rounded the same way)
+            lo32 = std::max(lo, lo32 / 8 * 8);
+            hi32 = std::min(hi, (hi32 + 7) / 8 * 8);
+            if (hi32 <= lo32) lo32 = hi32 = lo;
+            (*qk32)[zt * nq + q] = (unsigned)lo32 | ((unsigned)hi32 << 16);
+          }
         }
         for (int q0 = 0; q0 < nq; q0 += 8) {
           int lo = P.ldm, hi = 0;
           for (int q = q0; q < std::min(q0 + 8, nq); ++q) {
-            const unsigned v = qk[zt * nq + q];
+            const unsigned v = qz[q];
             if ((v >> 16) > (v & 0xffffu)) {
               lo = std::min(lo, (int)(v & 0xffffu));
               hi = std::max(hi, (int)(v >> 16));
@@ -789,16 +796,15 @@ void kernel_bands(Problem& P, const std::vector<double>& sig) {
     return nnp;
   };
   std::vector<int> r0a, r0b;
-  host_vec<unsigned> qka, qkb, qk32a, qk32b;
   double wa = 0.0, wb = 0.0;
-  const int nnpa = tiles(false, r0a, qka, qk32a, &wa);
-  const int nnpb = tiles(true, r0b, qkb, qk32b, &wb);
+  const int nnpa = tiles(false, r0a, nullptr, nullptr, &wa);
+  const int nnpb = tiles(true, r0b, nullptr, nullptr, &wb);
   const bool pad = wb < wa;
   P.qpad = pad ? 1 : 0;
   P.nnp = pad ? nnpb : nnpa;
+  double wsel = 0.0;
+  tiles(pad, pad ? r0b : r0a, &P.qk, &P.qk32, &wsel);
   P.qrow0 = std::move(pad ? r0b : r0a);
-  P.qk = std::move(pad ? qkb : qka);
-  P.qk32 = std::move(pad ? qk32b : qk32a);
   P.nq = static_cast<int>(P.qrow0.size());
   P.nqb = (P.nq + 7) / 8;
   // tile offsets: tiles of (z, theta) back to back in block order, each
@@ -1231,6 +1237,22 @@ int build_problem(trap_ctx* ctx, const trap_atom_desc* at, const trap_problem_de
   if (!(at->lambda0_A > 0) || !(at->mass_amu > 0)) return fail(TRAP_EINVAL, "bad atomic constants");
   Problem& P = ctx->pb;
   P = Problem();
+  {
+    // the previous problem's table storage (kernel_bands resizes, keeping capacity)
+    auto& hs = ctx->host_spare;
+    P.td = std::move(hs.td);
+    P.qk = std::move(hs.qk);
+    P.qk32 = std::move(hs.qk32);
+    P.qb = std::move(hs.qb);
+    P.qb32 = std::move(hs.qb32);
+    P.tofs = std::move(hs.tofs);
+    P.td.clear();
+    P.qk.clear();
+    P.qk32.clear();
+    P.qb.clear();
+    P.qb32.clear();
+    P.tofs.clear();
+  }
   P.nz = pd->n_z;
   P.nn = pd->n_nu;
   if (const char* why = set_directions(P, pd)) return fail(TRAP_EINVAL, why);

@@ -326,6 +326,14 @@ struct trap_ctx {
   hipStream_t stream = nullptr;
   bool has_problem = false;
   trap::Problem pb;
+  // the previous problem's largest host tables (tile layout of the banded
+  // store), handed to the next problem so that refilling them touches no new
+  // pages when the sizes repeat
+  struct {
+    trap::host_vec<trap::TileDesc> td;
+    trap::host_vec<unsigned> qk, qk32, qb, qb32;
+    trap::host_vec<int> tofs;
+  } host_spare;
   trap::Precomp pre;
   trap::Work wk;
   trap::Prof prof;
