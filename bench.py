@@ -459,7 +459,7 @@ def main():
                      "traffic": measured_traffic(args.config) if mixed else None,
                      "algorithmic_bytes_per_launch": cbytes / max(cstage["launches"], 1),
                      "algorithmic_flops_per_launch": flops / max(cstage["launches"], 1),
-                     "kernel": ("k_contract_pipe<NH> (persistent FP32 contraction, both column classes)"
+                     "kernel": ("k_contract_res (resident-field FP32 contraction, both column classes)"
                                 if mixed else "k_contract<double, NH>")},
         "sigma_apply": {"ms": sigma_ms, "flops": info["flops_contraction_fp32"],
                         "tflops": info["flops_contraction_fp32"] / (sigma_ms * 1e-3) / 1e12,

@@ -532,6 +532,7 @@ static void angular_setup(Problem& P, std::vector<double>& dirs, std::vector<dou
     P.cgrp[pi] = wide;
     P.cgrp[pi].insert(P.cgrp[pi].end(), narrow.begin(), narrow.end());
   }
+
   // a group holds at most sg slots of one theta and at most 2 sg pairs
   for (int pi = 0; pi < 2; ++pi) {
     const int sg = pi == 0 ? 8 : 16;
@@ -874,6 +875,22 @@ void kernel_bands(Problem& P, const std::vector<double>& sig) {
   P.kentries = (size_t)total;
   P.kent32_z.assign(nz, 0.0);
   for (size_t zt = 0; zt < nzt; ++zt) P.kent32_z[zt / nth] += (double)ent32_zt[zt];
+  {
+    // FP32 column groups by decreasing matrix-core work (window entries of the
+    // theta over all heights x column tiles): the resident-field contraction
+    // hands its work units out in this order
+    std::vector<double> eth(nth, 0.0);
+    for (size_t zt = 0; zt < nzt; ++zt) eth[zt % nth] += (double)ent32_zt[zt];
+    const int ng = (int)P.cgrp[1].size() / 3;
+    std::vector<double> wg(ng);
+    P.cord.resize(ng);
+    for (int g = 0; g < ng; ++g) {
+      P.cord[g] = g;
+      wg[g] = eth[P.cgrp[1][3 * g]] * (g < P.cgrp_n8[1] ? 8 : 4);
+    }
+    std::stable_sort(P.cord.begin(), P.cord.end(), [&](int a, int b) { return wg[a] > wg[b]; });
+    P.unit_ctr.assign(2, 0);
+  }
 }
 
 static int zero_field_classes(const trap_atom_desc& at, double dnuD_ref, std::vector<double>* dE,
@@ -1007,6 +1024,8 @@ size_t estimate_bytes(const trap_atom_desc* atom, const trap_problem_desc* pd, i
     item_vec(P.grp[1]);
     item_vec(P.cgrp[0]);
     item_vec(P.cgrp[1]);
+    item_vec(P.cord);
+    item_vec(P.unit_ctr);
     item(nz * nd * 4 * nu * nu * nl * 16);               // E
     item(nz * nd * 4 * nu * nu * nl * 16);               // A
     item(nz * nu * nu * 16);                             // alpha
@@ -1446,6 +1465,8 @@ int build_problem(trap_ctx* ctx, const trap_atom_desc* at, const trap_problem_de
   up.add(&P.d_grp[1], P.grp[1]);
   up.add(&P.d_cgrp[0], P.cgrp[0]);
   up.add(&P.d_cgrp[1], P.cgrp[1]);
+  up.add(&P.d_cord, P.cord);
+  up.add(&P.d_unit_ctr, P.unit_ctr);
   up.add(reinterpret_cast<void**>(&P.d_E), E, n_e * sizeof(double2));
   up.add(reinterpret_cast<void**>(&P.d_A), A, n_e * sizeof(double2));
   up.add(&P.d_alpha, alpha);

@@ -664,6 +664,236 @@ static int launch_contract_pipe_nh(trap_ctx* ctx, hipStream_t stream, int zc, in
   return TRAP_OK;
 }
 
+// ---- resident-field FP32 contraction
+// One work unit is (column group, slice of the (height, theta) plane's wave
+// tiles, height): the group's comoving field over every frequency is staged in
+// LDS once, and the block's eight waves then take the slice's tiles one at a
+// time from a counter in LDS, each wave stepping through its own tile's column
+// window with no barrier between waves.  A wave keeps the kernel-row
+// fragments of its next D steps in flight while the matrix cores work on the
+// current D, across tile boundaries (the next tile's descriptor is read one
+// tile ahead).  Blocks take units from a global ticket in order of decreasing
+// work (the groups sorted on the host), the next ticket fetched while the
+// current unit runs; the last block to finish resets the ticket and its own
+// count to zero for the next launch.  LDS layout: frequency pairs (k, k + 1)
+// interleaved per column, [k / 2][column][k & 1]; column c of pair row kp
+// sits at c ^ 16 (kp & 3), so the four pair rows one matrix-core step reads
+// fall in different bank halves.
+constexpr int kResD = 8;
+constexpr int kResStage = 10;    // staging items per thread: (320 / 2) x 32 slots / 512 threads
+
+__device__ __forceinline__ int res_grab(int* ctr, int lane) {
+  int v = 0;
+  if (lane == 0) v = atomicAdd(ctr, 1);
+  return __builtin_amdgcn_readfirstlane(__shfl(v, 0));
+}
+
+template <int D>
+__device__ __forceinline__ void res_load(const float* __restrict__ hi, const KRow& r, int s, int e, int lk,
+                                         float2 (&a)[D]) {
+  const float* ptr = hi + (r.base + 8LL * s + 2 * lk);
+#pragma unroll
+  for (int h = 0; h < D; ++h) {
+    if (s + h < e) {
+      a[h] = *reinterpret_cast<const float2*>(ptr + 8 * h);
+    } else {
+      a[h] = make_float2(0.0f, 0.0f);
+    }
+  }
+}
+
+// the products of steps s .. min(s + D, e) - 1; bl: the lane's pair row lk
+// and column lr; the B values of step h + 1 are read before the products of h
+template <int NCT, int D>
+__device__ __forceinline__ void res_mfma(const float* bl, const int (&co)[NCT], int s, int e, const float2 (&a)[D],
+                                         floatx4_t (&acc)[NCT]) {
+  constexpr int CW = 16 * NCT;
+  const int n = e - s;
+  const float* b0 = bl + (size_t)s * 8 * CW;
+  float2 b[2][NCT];
+  if (n > 0) {
+#pragma unroll
+    for (int jt = 0; jt < NCT; ++jt) b[0][jt] = *reinterpret_cast<const float2*>(b0 + co[jt]);
+  }
+#pragma unroll
+  for (int h = 0; h < D; ++h) {
+    if (h + 1 < D && h + 1 < n) {
+#pragma unroll
+      for (int jt = 0; jt < NCT; ++jt)
+        b[(h + 1) & 1][jt] = *reinterpret_cast<const float2*>(b0 + (h + 1) * 8 * CW + co[jt]);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    if (h < n) {
+#pragma unroll
+      for (int jt = 0; jt < NCT; ++jt)
+        acc[jt] = __builtin_amdgcn_mfma_f32_16x16x4f32(b[h & 1][jt].x, a[h].x, acc[jt], 0, 0, 0);
+#pragma unroll
+      for (int jt = 0; jt < NCT; ++jt)
+        acc[jt] = __builtin_amdgcn_mfma_f32_16x16x4f32(b[h & 1][jt].y, a[h].y, acc[jt], 0, 0, 0);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+// the wave's share of tiles [.., t1) of one unit (the LDS counter starts at the slice's first)
+template <int NCT>
+__device__ __forceinline__ void res_tiles(const KStore& ks, long long zt, int t1, int zl, int nt, int nn, int nslot,
+                                          int s0, int cnt, const float* Bs, int* ctr, float* __restrict__ W,
+                                          int lane) {
+  constexpr int D = kResD;
+  constexpr int CW = 16 * NCT;
+  const int lr = lane & 15, lk = lane >> 4;
+  const float* bl = Bs + (size_t)lk * 2 * CW + 2 * lr;
+  int co[NCT];
+#pragma unroll
+  for (int jt = 0; jt < NCT; ++jt) co[jt] = 32 * (jt ^ lk);
+  int q = res_grab(ctr, lane);
+  if (q >= t1) return;
+  KRow r = krow(ks, zt, q, lr, nt, nn);
+  int qn = res_grab(ctr, lane);
+  KRow rnext = r;
+  if (qn < t1) rnext = krow(ks, zt, qn, lr, nt, nn);
+  int s = r.wlo >> 3, e = r.whi >> 3;
+  float2 ac[D], an[D];
+  res_load<D>(ks.hi, r, s, e, lk, ac);
+  floatx4_t acc[NCT];
+#pragma unroll
+  for (int j = 0; j < NCT; ++j)
+    for (int c = 0; c < 4; ++c) acc[j][c] = 0.0f;
+  while (true) {
+    const bool done = s + D >= e;
+    bool more = true;
+    KRow rn = r;
+    int sn = s + D, en = e;
+    if (done) {
+      if (qn < t1) {
+        rn = rnext;
+        sn = rn.wlo >> 3;
+        en = rn.whi >> 3;
+      } else {
+        more = false;
+      }
+    }
+    if (more) res_load<D>(ks.hi, rn, sn, en, lk, an);
+    res_mfma<NCT, D>(bl, co, s, e, ac, acc);
+    if (done) {
+      store_w<float, NCT>(r, zl, nt, nn, nslot, s0, cnt, lk, acc, W);
+#pragma unroll
+      for (int j = 0; j < NCT; ++j)
+        for (int c = 0; c < 4; ++c) acc[j][c] = 0.0f;
+      if (!more) break;
+      // one tile ahead: the descriptor after the one just taken
+      qn = res_grab(ctr, lane);
+      if (qn < t1) rnext = krow(ks, zt, qn, lr, nt, nn);
+    }
+#pragma unroll
+    for (int h = 0; h < D; ++h) ac[h] = an[h];
+    r = rn;
+    s = sn;
+    e = en;
+  }
+}
+
+// unit ui -> (group cord[j], slice, height): ui = (j nsl + slice) zc + zl
+__global__ void __launch_bounds__(512, 1) k_contract_res(int z0, int zc, int nth, int nt, int nn, int nd, int ldm,
+                                                         KStore ks, const float* __restrict__ Ibar,
+                                                         const int* __restrict__ cgrp, const int* __restrict__ cord,
+                                                         int ngrp, int n8, int nsl, int* __restrict__ uctr,
+                                                         const int* __restrict__ slot_dir, float* __restrict__ W,
+                                                         int nslot) {
+  extern __shared__ __align__(16) unsigned char rsh[];
+  float* Bs = reinterpret_cast<float*>(rsh);
+  // [0] tile counter, [2 + (i & 1)] the ticket of unit iteration i
+  int* ctr = reinterpret_cast<int*>(Bs + (size_t)ldm * 128);
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int nunit = zc * ngrp * nsl;
+  const int np2 = ldm >> 1;
+  if (tid == 0) ctr[2] = atomicAdd(&uctr[0], 1);
+  __syncthreads();
+  for (int it = 0;; ++it) {
+    const int ui = ctr[2 + (it & 1)];
+    if (ui >= nunit) break;
+    const int zl = ui % zc, js = ui / zc, j = js / nsl, slice = js - j * nsl;
+    const int g = cord[j];
+    const int th = cgrp[3 * g], s0 = cgrp[3 * g + 1], cnt = cgrp[3 * g + 2];
+    const bool wide = g < n8;
+    const int cgs = wide ? 32 : 16, cw = 4 * cgs;
+    const int t0 = (int)((long long)slice * ks.nq / nsl), t1 = (int)((long long)(slice + 1) * ks.nq / nsl);
+    // stage the field: all loads first, then the LDS writes
+    const float* Ib = Ibar + (size_t)zl * nd * nn * 4;
+    const int nit = np2 * cgs;
+    float4 v0[kResStage], v1[kResStage];
+#pragma unroll
+    for (int q = 0; q < kResStage; ++q) {
+      const int e = tid + 512 * q;
+      const int kp = e / cgs, sl = e - kp * cgs;
+      const float* src = Ib + (size_t)slot_dir[s0 + min(sl, cnt - 1)] * nn * 4;
+      const int k0 = min(2 * kp, nn - 1), k1 = min(2 * kp + 1, nn - 1);
+      if (e < nit) {
+        v0[q] = *reinterpret_cast<const float4*>(src + (size_t)k0 * 4);
+        v1[q] = *reinterpret_cast<const float4*>(src + (size_t)k1 * 4);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < kResStage; ++q) {
+      const int e = tid + 512 * q;
+      if (e < nit) {
+        const int kp = e / cgs, sl = e - kp * cgs;
+        const float4 z4 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        const float4 a0 = (sl < cnt && 2 * kp < nn) ? v0[q] : z4;
+        const float4 a1 = (sl < cnt && 2 * kp + 1 < nn) ? v1[q] : z4;
+        const int pc = (4 * sl) ^ (16 * (kp & 3));
+        float* dst = Bs + ((size_t)kp * cw + pc) * 2;
+        *reinterpret_cast<float4*>(dst) = make_float4(a0.x, a1.x, a0.y, a1.y);
+        *reinterpret_cast<float4*>(dst + 4) = make_float4(a0.z, a1.z, a0.w, a1.w);
+      }
+    }
+    if (tid == 0) {
+      ctr[0] = t0;
+      ctr[2 + ((it + 1) & 1)] = atomicAdd(&uctr[0], 1);
+    }
+    __syncthreads();
+    const long long zt = (long long)(z0 + zl) * nth + th;
+    if (wide) {
+      res_tiles<8>(ks, zt, t1, zl, nt, nn, nslot, s0, cnt, Bs, ctr, W, lane);
+    } else {
+      res_tiles<4>(ks, zt, t1, zl, nt, nn, nslot, s0, cnt, Bs, ctr, W, lane);
+    }
+    __syncthreads();    // every wave is done with the field and the tile counter
+  }
+  if (tid == 0) {
+    __threadfence();
+    if (atomicAdd(&uctr[1], 1) == (int)gridDim.x - 1) {
+      atomicExch(&uctr[0], 0);
+      atomicExch(&uctr[1], 0);
+    }
+  }
+}
+
+static size_t contract_res_lds(int ldm) { return (size_t)ldm * 128 * sizeof(float) + 16; }
+
+// 1 when launched, 0 when one group's field over all frequencies does not fit LDS
+static int launch_contract_res(trap_ctx* ctx, hipStream_t stream, int zc, int z0, const float* Ibar, float* W) {
+  Problem& P = ctx->pb;
+  const int ngrp = (int)P.cgrp[1].size() / 3;
+  if (ngrp == 0) return 1;
+  const size_t lds = contract_res_lds(P.ldm);
+  if (lds > (size_t)ctx->max_lds || P.ldm > 320) return 0;
+  const KStore ks = kernel_store(ctx, true);
+  // slices per plane: about four units per compute unit
+  const long long base = (long long)zc * ngrp;
+  const int nsl = (int)std::max<long long>(1, std::min<long long>({8, ks.nq, (4LL * ctx->n_cu + base - 1) / base}));
+  const int nunit = (int)(base * nsl);
+  const int grid = std::min(nunit, ctx->n_cu);
+  if (lds > 64 * 1024)
+    TRAP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_contract_res),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  hipLaunchKernelGGL(k_contract_res, dim3(grid), dim3(512), lds, stream, z0, zc, P.nth, P.nt, P.nn, P.nd, P.ldm, ks,
+                     Ibar, P.d_cgrp[1], P.d_cord, ngrp, P.cgrp_n8[1], nsl, P.d_unit_ctr, P.d_slot_dir, W, P.nslot);
+  TRAP_HIP(hipGetLastError());
+  return 1;
+}
+
 // 1 when launched, 0 when the problem does not fit the pipelined kernel's LDS
 static int launch_contract_pipe(trap_ctx* ctx, hipStream_t stream, int zc, int z0, const float* Ibar, float* W) {
   Problem& P = ctx->pb;
@@ -1418,7 +1648,9 @@ static int sigma_apply_t(trap_ctx* ctx, const T* I, T* eps, int prec, int add_th
       W = static_cast<T*>(K.W[pi]);
     }
     if constexpr (sizeof(T) == sizeof(float)) {
-      const int launched = launch_contract_pipe(ctx, ctx->stream, zc, z0, Ibar + (size_t)z0 * nd * nn * 4, W);
+      int launched = launch_contract_res(ctx, ctx->stream, zc, z0, Ibar + (size_t)z0 * nd * nn * 4, W);
+      if (launched == 0)
+        launched = launch_contract_pipe(ctx, ctx->stream, zc, z0, Ibar + (size_t)z0 * nd * nn * 4, W);
       if (launched < 0) return launched;
       if (!launched) TRAP_TRY(launch_contract<T>(ctx, zc, z0, Ibar + (size_t)z0 * nd * nn * 4, W));
     } else if (ctx->flat_field) {

@@ -201,6 +201,10 @@ struct Problem {
   // precision: FP64 <= 16 slots; FP32 <= 32, the cgrp_n8 groups of 17..32 slots first
   std::vector<int> cgrp[2];
   int cgrp_n8[2] = {0, 0};
+  // the FP32 groups by decreasing work (both classes interleaved): the
+  // resident-field contraction's work order; its unit ticket and finished-block
+  // count (zero between launches: the last block to finish resets them)
+  std::vector<int> cord, unit_ctr;
   // device copies
   double *d_x = nullptr, *d_P = nullptr, *d_mu = nullptr, *d_w = nullptr, *d_tau = nullptr;
   double *d_Sig = nullptr;                 // [nn][nn] second-derivative map of the spline
@@ -217,6 +221,8 @@ struct Problem {
   int *d_pair_off = nullptr, *d_pair_o = nullptr, *d_pair_dir = nullptr, *d_pair_index = nullptr;
   int *d_grp[2] = {nullptr, nullptr};
   int *d_cgrp[2] = {nullptr, nullptr};
+  int* d_cord = nullptr;
+  int* d_unit_ctr = nullptr;
   double2 *d_E = nullptr, *d_A = nullptr;  // see above
   double2 *d_alpha = nullptr, *d_bma = nullptr; // [nz][nu][nu]
   double *d_g = nullptr;                   // [nz][nt][nd][4] geometric factors of K

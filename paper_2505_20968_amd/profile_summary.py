@@ -25,7 +25,7 @@ import statistics
 HERE = os.path.dirname(os.path.abspath(__file__))
 SIGMA_SRC = os.path.join(HERE, "csrc", "sigma.hip")
 COPY_BYTES = 256 << 20
-CONTRACT_NAME = "k_contract_pipe<"     # the persistent FP32 contraction (one dispatch per height chunk)
+CONTRACT_NAME = "k_contract_res"      # the resident-field FP32 contraction (one dispatch per height chunk)
 COPY_NAME = "neg"
 
 
