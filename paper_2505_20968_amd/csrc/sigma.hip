@@ -688,39 +688,39 @@ __device__ __forceinline__ int res_grab(int* ctr, int lane) {
   return __builtin_amdgcn_readfirstlane(__shfl(v, 0));
 }
 
+// The loads take no branch (a step past the window re-reads its last step;
+// its products are skipped), so the wait counts stay exact and the next
+// group's loads are never waited for by the current group's products.
 template <int D>
 __device__ __forceinline__ void res_load(const float* __restrict__ hi, const KRow& r, int s, int e, int lk,
                                          float2 (&a)[D]) {
-  const float* ptr = hi + (r.base + 8LL * s + 2 * lk);
+  // an empty window reads the store's first entries instead
+  const bool any = e > s;
+  const int last = max(e - 1, s);
+  const float* ptr = any ? hi + (r.base + 2 * lk) : hi;
 #pragma unroll
-  for (int h = 0; h < D; ++h) {
-    if (s + h < e) {
-      a[h] = *reinterpret_cast<const float2*>(ptr + 8 * h);
-    } else {
-      a[h] = make_float2(0.0f, 0.0f);
-    }
-  }
+  for (int h = 0; h < D; ++h) a[h] = *reinterpret_cast<const float2*>(ptr + (any ? 8LL * min(s + h, last) : 0LL));
 }
 
 // the products of steps s .. min(s + D, e) - 1; bl: the lane's pair row lk
-// and column lr; the B values of step h + 1 are read before the products of h
+// and column lr; the B values of step h + 1 are read (unconditionally, a step
+// past the window re-reading the last one) before the products of h
 template <int NCT, int D>
 __device__ __forceinline__ void res_mfma(const float* bl, const int (&co)[NCT], int s, int e, const float2 (&a)[D],
                                          floatx4_t (&acc)[NCT]) {
   constexpr int CW = 16 * NCT;
   const int n = e - s;
+  if (n <= 0) return;
   const float* b0 = bl + (size_t)s * 8 * CW;
   float2 b[2][NCT];
-  if (n > 0) {
 #pragma unroll
-    for (int jt = 0; jt < NCT; ++jt) b[0][jt] = *reinterpret_cast<const float2*>(b0 + co[jt]);
-  }
+  for (int jt = 0; jt < NCT; ++jt) b[0][jt] = *reinterpret_cast<const float2*>(b0 + co[jt]);
 #pragma unroll
   for (int h = 0; h < D; ++h) {
-    if (h + 1 < D && h + 1 < n) {
+    if (h + 1 < D) {
+      const float* bh = b0 + min(h + 1, n - 1) * 8 * CW;
 #pragma unroll
-      for (int jt = 0; jt < NCT; ++jt)
-        b[(h + 1) & 1][jt] = *reinterpret_cast<const float2*>(b0 + (h + 1) * 8 * CW + co[jt]);
+      for (int jt = 0; jt < NCT; ++jt) b[(h + 1) & 1][jt] = *reinterpret_cast<const float2*>(bh + co[jt]);
     }
     __builtin_amdgcn_sched_barrier(0);
     if (h < n) {
@@ -735,7 +735,43 @@ __device__ __forceinline__ void res_mfma(const float* bl, const int (&co)[NCT], 
   }
 }
 
-// the wave's share of tiles [.., t1) of one unit (the LDS counter starts at the slice's first)
+// krow with the tile descriptor read through the constant address space:
+// scalar loads, counted apart from the vector loads of the kernel rows
+__device__ __forceinline__ KRow krow_s(const KStore& ks, long long zt, int q, int lr, int nn) {
+  typedef const __attribute__((address_space(4))) TileDesc* CTile;
+  typedef const __attribute__((address_space(4))) unsigned* CWin;
+  KRow r;
+  q = __builtin_amdgcn_readfirstlane(q);
+  const long long i = zt * ks.nq + q;
+  const CTile d = (CTile)ks.td + i;
+  const long long off = d->off;
+  const int lo = d->lo, hi = d->hi;
+  const int grow = tile_row0(ks.pad, ks.np, ks.nnp, q) + lr;
+  r.p = grow / ks.nnp;
+  r.n = grow - r.p * ks.nnp;
+  r.live = r.p < ks.np && r.n < nn;
+  r.wlo = lo;
+  r.whi = hi;
+  r.base = off + (long long)lr * (hi - lo) - lo;
+  if (ks.t32) {
+    const unsigned v = ((CWin)ks.t32)[i];
+    r.wlo = (int)(v & 0xffffu);
+    r.whi = (int)(v >> 16);
+  }
+  return r;
+}
+
+// one stage of a wave's stream: D steps of one tile (s .. e the tile's
+// steps from s on); ok = 0 past the wave's last tile
+struct RStage {
+  KRow r;
+  int s, e, ok;
+};
+
+// the wave's share of tiles [.., t1) of one unit (the LDS counter starts at
+// the slice's first).  Kernel-row loads run two stages ahead through three
+// register buffers; every stage issues its D loads so the wait counts stay
+// exact.
 template <int NCT>
 __device__ __forceinline__ void res_tiles(const KStore& ks, long long zt, int t1, int zl, int nt, int nn, int nslot,
                                           int s0, int cnt, const float* Bs, int* ctr, float* __restrict__ W,
@@ -747,50 +783,72 @@ __device__ __forceinline__ void res_tiles(const KStore& ks, long long zt, int t1
   int co[NCT];
 #pragma unroll
   for (int jt = 0; jt < NCT; ++jt) co[jt] = 32 * (jt ^ lk);
-  int q = res_grab(ctr, lane);
-  if (q >= t1) return;
-  KRow r = krow(ks, zt, q, lr, nt, nn);
-  int qn = res_grab(ctr, lane);
-  KRow rnext = r;
-  if (qn < t1) rnext = krow(ks, zt, qn, lr, nt, nn);
-  int s = r.wlo >> 3, e = r.whi >> 3;
-  float2 ac[D], an[D];
-  res_load<D>(ks.hi, r, s, e, lk, ac);
+  // the stage after st: the tile's next D steps, else the next tile's first
+  auto advance = [&](const RStage& st) {
+    RStage n = st;
+    if (!st.ok) return n;
+    if (st.s + D < st.e) {
+      n.s = st.s + D;
+      return n;
+    }
+    const int q = res_grab(ctr, lane);
+    if (q >= t1) {
+      n.ok = 0;
+      return n;
+    }
+    n.r = krow_s(ks, zt, q, lr, nn);
+    n.s = n.r.wlo >> 3;
+    n.e = n.r.whi >> 3;
+    return n;
+  };
+  // a stage past the wave's end keeps the last stage's addresses; an empty
+  // window reads D distinct steps at the start of the store (never a branch,
+  // never one address for several loads)
+  auto load = [&](const RStage& st, float2 (&a)[D]) {
+    const bool any = st.e > st.s;
+    const long long base = any ? st.r.base + 2 * lk : 2LL * lk;
+    const int s = any ? st.s : 0, last = any ? st.e - 1 : D - 1;
+#pragma unroll
+    for (int h = 0; h < D; ++h) a[h] = *reinterpret_cast<const float2*>(ks.hi + base + 8LL * min(s + h, last));
+  };
   floatx4_t acc[NCT];
 #pragma unroll
   for (int j = 0; j < NCT; ++j)
     for (int c = 0; c < 4; ++c) acc[j][c] = 0.0f;
-  while (true) {
-    const bool done = s + D >= e;
-    bool more = true;
-    KRow rn = r;
-    int sn = s + D, en = e;
-    if (done) {
-      if (qn < t1) {
-        rn = rnext;
-        sn = rn.wlo >> 3;
-        en = rn.whi >> 3;
-      } else {
-        more = false;
-      }
-    }
-    if (more) res_load<D>(ks.hi, rn, sn, en, lk, an);
-    res_mfma<NCT, D>(bl, co, s, e, ac, acc);
-    if (done) {
-      store_w<float, NCT>(r, zl, nt, nn, nslot, s0, cnt, lk, acc, W);
+  RStage s0st;
+  s0st.ok = 1;
+  s0st.s = 0;
+  s0st.e = 0;     // "tile finished": advance takes the first tile
+  s0st.r = KRow{0, 0, 0, 0, 0, false};
+  RStage st0 = advance(s0st);
+  if (!st0.ok) return;
+  RStage st1 = advance(st0);
+  float2 a0[D], a1[D], a2[D];
+  load(st0, a0);
+  load(st1, a1);
+  // compute stage st0 from buffer c while the stage two ahead loads into l;
+  // false once the wave's last stage is done
+  auto body = [&](float2 (&l)[D], const float2 (&c)[D]) {
+    const RStage st2 = advance(st1);
+    load(st2, l);
+    // the buffer's loads (issued two stages ago) are complete here on every
+    // path, whether or not the products below use all of it, so no later
+    // reuse of its registers waits on the loads in flight (an empty asm that
+    // only reads the registers: no instruction is emitted)
+#pragma unroll
+    for (int h = 0; h < D; ++h) asm volatile("" ::"v"(c[h].x), "v"(c[h].y));
+    res_mfma<NCT, D>(bl, co, st0.s, st0.e, c, acc);
+    if (st0.s + D >= st0.e) {
+      store_w<float, NCT>(st0.r, zl, nt, nn, nslot, s0, cnt, lk, acc, W);
 #pragma unroll
       for (int j = 0; j < NCT; ++j)
-        for (int c = 0; c < 4; ++c) acc[j][c] = 0.0f;
-      if (!more) break;
-      // one tile ahead: the descriptor after the one just taken
-      qn = res_grab(ctr, lane);
-      if (qn < t1) rnext = krow(ks, zt, qn, lr, nt, nn);
+        for (int c4 = 0; c4 < 4; ++c4) acc[j][c4] = 0.0f;
     }
-#pragma unroll
-    for (int h = 0; h < D; ++h) ac[h] = an[h];
-    r = rn;
-    s = sn;
-    e = en;
+    st0 = st1;
+    st1 = st2;
+    return st0.ok != 0;
+  };
+  while (body(a2, a0) && body(a0, a1) && body(a1, a2)) {
   }
 }
 
@@ -821,24 +879,24 @@ __global__ void __launch_bounds__(512, 1) k_contract_res(int z0, int zc, int nth
     const int t0 = (int)((long long)slice * ks.nq / nsl), t1 = (int)((long long)(slice + 1) * ks.nq / nsl);
     // stage the field: all loads first, then the LDS writes
     const float* Ib = Ibar + (size_t)zl * nd * nn * 4;
+    // item e = tid + 512 q is (pair row e / cgs, slot e % cgs): the slot is
+    // the same for all of a thread's items (512 is a multiple of cgs)
     const int nit = np2 * cgs;
+    const int sl = tid % cgs, kpb = tid / cgs, kps = 512 / cgs;
+    const float* src = Ib + (size_t)slot_dir[s0 + min(sl, cnt - 1)] * nn * 4;
     float4 v0[kResStage], v1[kResStage];
 #pragma unroll
     for (int q = 0; q < kResStage; ++q) {
-      const int e = tid + 512 * q;
-      const int kp = e / cgs, sl = e - kp * cgs;
-      const float* src = Ib + (size_t)slot_dir[s0 + min(sl, cnt - 1)] * nn * 4;
+      const int kp = kpb + q * kps;
       const int k0 = min(2 * kp, nn - 1), k1 = min(2 * kp + 1, nn - 1);
-      if (e < nit) {
-        v0[q] = *reinterpret_cast<const float4*>(src + (size_t)k0 * 4);
-        v1[q] = *reinterpret_cast<const float4*>(src + (size_t)k1 * 4);
-      }
+      v0[q] = *reinterpret_cast<const float4*>(src + (size_t)k0 * 4);
+      v1[q] = *reinterpret_cast<const float4*>(src + (size_t)k1 * 4);
     }
 #pragma unroll
     for (int q = 0; q < kResStage; ++q) {
       const int e = tid + 512 * q;
       if (e < nit) {
-        const int kp = e / cgs, sl = e - kp * cgs;
+        const int kp = kpb + q * kps;
         const float4 z4 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         const float4 a0 = (sl < cnt && 2 * kp < nn) ? v0[q] : z4;
         const float4 a1 = (sl < cnt && 2 * kp + 1 < nn) ? v1[q] : z4;
