@@ -1129,7 +1129,7 @@ size_t estimate_bytes(const trap_atom_desc* atom, const trap_problem_desc* pd, i
   // the height-chunked Sigma path materialises W for one chunk of heights
   // (at most ~512 MiB in FP64, half that in FP32)
   {
-    const size_t per_z = nt * nslot * 2 * nn * 4;
+    const size_t per_z = nt * nslot * 2 * (size_t)w_stride((int)nn) * 4;
     const size_t zc = std::max<size_t>(1, std::min<size_t>(nz, (size_t(1) << 29) / std::max<size_t>(per_z * 8, 1)));
     add(zc * per_z * 8);
     if (mask & 2) add(zc * per_z * 4);

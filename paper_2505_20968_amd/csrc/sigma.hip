@@ -330,7 +330,7 @@ __device__ __forceinline__ void store_w(const KRow& r, int zl, int nt, int nn, i
     if (sl < cnt) {
       V4 o;
       o.x = acc[jt][0]; o.y = acc[jt][1]; o.z = acc[jt][2]; o.w = acc[jt][3];
-      *reinterpret_cast<V4*>(W + (((((size_t)zl * nt + rt) * nslot + s0 + sl) * 2 + rc) * nn + r.n) * 4) = o;
+      *reinterpret_cast<V4*>(W + (((((size_t)zl * nt + rt) * nslot + s0 + sl) * 2 + rc) * w_stride(nn) + r.n) * 4) = o;
     }
   }
 }
@@ -461,7 +461,7 @@ __global__ void __launch_bounds__(64) k_flat_contract(int z0, int nth, int nt, i
   const int gr = tile_row0(ks.pad, ks.np, ks.nnp, q) + i, p = gr / ks.nnp, n = gr - p * ks.nnp;
   if (p >= ks.np || n >= nn) return;
   const int t = p >> 1, c = p & 1;
-  Wf[((((size_t)zl * nt + t) * nth + th) * 2 + c) * nn * 4 + (size_t)n * 4 + sk] = sk == 0 ? WT[z0 + zl] * v : 0.0;
+  Wf[((((size_t)zl * nt + t) * nth + th) * 2 + c) * w_stride(nn) * 4 + (size_t)n * 4 + sk] = sk == 0 ? WT[z0 + zl] * v : 0.0;
 }
 
 // chunking of K: the fewest chunks of at most 128 columns, NH = chunk / 8
@@ -1126,9 +1126,9 @@ __device__ __forceinline__ void angular_body(
       const T* cp = cfz + (size_t)pair_index[o * nd + op] * pstride;
       for (int upr = 0; upr < nu; ++upr) {
         const int t = upr * nl + l;
-        const T* Wp = W + (((size_t)zl * nt + t) * nslot + slot) * 2 * (size_t)nn * 4 + (size_t)nc * 4;
+        const T* Wp = W + (((size_t)zl * nt + t) * nslot + slot) * 2 * (size_t)w_stride(nn) * 4 + (size_t)nc * 4;
         const V4 wr = *reinterpret_cast<const V4*>(Wp);
-        const V4 wi = *reinterpret_cast<const V4*>(Wp + (size_t)nn * 4);
+        const V4 wi = *reinterpret_cast<const V4*>(Wp + (size_t)w_stride(nn) * 4);
         const T* c0 = cp + (size_t)t * 2 * nl * 16;
         const T* c1 = c0 + (size_t)nl * 16;
 #pragma unroll
@@ -1594,7 +1594,7 @@ int ensure_work(trap_ctx* ctx, int prec) {
     // height chunk: one chunk of W within 512 MiB in FP64 (half that in FP32),
     // so that the FP32 intermediate written by the contraction is still in the
     // 256 MB last-level cache when the angular sum reads it
-    const size_t per_z = (size_t)P.nt * P.nslot * 2 * nn * 4 * sizeof(double);
+    const size_t per_z = (size_t)P.nt * P.nslot * 2 * w_stride(nn) * 4 * sizeof(double);
     K.zchunk = (int)std::max<size_t>(1, std::min<size_t>(nz, (size_t(1) << 29) / std::max<size_t>(per_z, 1)));
   }
   const int pi = prec == TRAP_FP64 ? 0 : 1;
@@ -1702,7 +1702,7 @@ static int sigma_apply_t(trap_ctx* ctx, const T* I, T* eps, int prec, int add_th
                                         bytes);
     }
     if (!W) {
-      TRAP_TRY(dalloc(ctx, &K.W[pi], (size_t)K.zchunk * nt * P.nslot * 2 * nn * 4 * sizeof(T)));
+      TRAP_TRY(dalloc(ctx, &K.W[pi], (size_t)K.zchunk * nt * P.nslot * 2 * w_stride(nn) * 4 * sizeof(T)));
       W = static_cast<T*>(K.W[pi]);
     }
     if constexpr (sizeof(T) == sizeof(float)) {
@@ -2127,7 +2127,8 @@ int sigma_batch_ready(trap_ctx* ctx) {
   // (measured: serving throughput 7-10% higher than grouping it)
   if (K.zchunk < P.nz) return 0;
   TRAP_TRY(ensure_work(ctx, TRAP_FP32));
-  if (!K.W[1]) TRAP_TRY(dalloc(ctx, &K.W[1], (size_t)K.zchunk * P.nt * P.nslot * 2 * P.nn * 4 * sizeof(float)));
+  if (!K.W[1])
+    TRAP_TRY(dalloc(ctx, &K.W[1], (size_t)K.zchunk * P.nt * P.nslot * 2 * w_stride(P.nn) * 4 * sizeof(float)));
   return (K.v32a && K.v32b) ? 1 : 0;
 }
 
@@ -2464,7 +2465,8 @@ int op_apply_batch_f32(trap_ctx** ctxs, int n, const double* const* x, double* c
         const int z0 = (int)st.args * c->wk.zchunk, zc = std::min(c->wk.zchunk, P.nz - z0);
         const float* Ib = static_cast<const float*>(c->wk.Ibar[1]) + (size_t)z0 * P.nd * P.nn * 4;
         float* Wc = static_cast<float*>(c->wk.W[1]);
-        const int launched = launch_contract_pipe(c, ar.stream, zc, z0, Ib, Wc);
+        int launched = launch_contract_res(c, ar.stream, zc, z0, Ib, Wc);
+        if (launched == 0) launched = launch_contract_pipe(c, ar.stream, zc, z0, Ib, Wc);
         if (launched < 0) return launched;
         if (!launched) return fail(TRAP_EINVAL, "internal: contraction does not fit the pipelined kernel");
         break;

@@ -104,6 +104,12 @@ struct KStore {
   int pad = 0;
 };
 
+// row stride (frequencies) of the contraction's intermediate W[z][t][slot][c][n][s]:
+// the frequency count rounded up to 8, so that every row of W starts on a
+// 128-byte boundary in FP32 (the contraction's 256-byte tile runs and the
+// angular sum's 1 KB reads then cover whole cache lines)
+__host__ __device__ inline int w_stride(int nn) { return (nn + 7) & ~7; }
+
 // first GEMM row of wave tile q (block order)
 __host__ __device__ inline int tile_row0(int pad, int np, int nnp, int q) {
   return pad ? (q % np) * nnp + 16 * (q / np) : 16 * q;
