@@ -321,16 +321,18 @@ __device__ __forceinline__ void wave_steps(int wlo, int whi, int k0, int* hlo, i
 template <typename T, int NCT>
 __device__ __forceinline__ void store_w(const KRow& r, int zl, int nt, int nn, int nslot, int s0, int cnt, int lk,
                                         const typename MfmaOp<T>::acc_t (&acc)[NCT], T* __restrict__ W) {
-  using V4 = typename Vec4<T>::type;
   if (!r.live) return;
   const int rt = r.p >> 1, rc = r.p & 1;
 #pragma unroll
   for (int jt = 0; jt < NCT; ++jt) {
     const int sl = 4 * jt + lk;
     if (sl < cnt) {
-      V4 o;
-      o.x = acc[jt][0]; o.y = acc[jt][1]; o.z = acc[jt][2]; o.w = acc[jt][3];
-      *reinterpret_cast<V4*>(W + (((((size_t)zl * nt + rt) * nslot + s0 + sl) * 2 + rc) * w_stride(nn) + r.n) * 4) = o;
+      // non-temporal: W is read back once by the angular sum, after the
+      // kernel rows and fields of the whole launch have streamed through L2
+      typedef T NV __attribute__((ext_vector_type(4)));
+      const NV o = {acc[jt][0], acc[jt][1], acc[jt][2], acc[jt][3]};
+      __builtin_nontemporal_store(
+          o, reinterpret_cast<NV*>(W + (((((size_t)zl * nt + rt) * nslot + s0 + sl) * 2 + rc) * w_stride(nn) + r.n) * 4));
     }
   }
 }
