@@ -890,6 +890,11 @@ void kernel_bands(Problem& P, const std::vector<double>& sig) {
     }
     std::stable_sort(P.cord.begin(), P.cord.end(), [&](int a, int b) { return wg[a] > wg[b]; });
     P.unit_ctr.assign(2, 0);
+    const int ng0 = (int)P.cgrp[0].size() / 3;
+    P.cord0.resize(ng0);
+    for (int g = 0; g < ng0; ++g) P.cord0[g] = g;
+    std::stable_sort(P.cord0.begin(), P.cord0.end(),
+                     [&](int a, int b) { return eth[P.cgrp[0][3 * a]] > eth[P.cgrp[0][3 * b]]; });
   }
 }
 
@@ -1026,6 +1031,7 @@ size_t estimate_bytes(const trap_atom_desc* atom, const trap_problem_desc* pd, i
     item_vec(P.cgrp[1]);
     item_vec(P.cord);
     item_vec(P.unit_ctr);
+    item_vec(P.cord0);
     item(nz * nd * 4 * nu * nu * nl * 16);               // E
     item(nz * nd * 4 * nu * nu * nl * 16);               // A
     item(nz * nu * nu * 16);                             // alpha
@@ -1467,6 +1473,7 @@ int build_problem(trap_ctx* ctx, const trap_atom_desc* at, const trap_problem_de
   up.add(&P.d_cgrp[1], P.cgrp[1]);
   up.add(&P.d_cord, P.cord);
   up.add(&P.d_unit_ctr, P.unit_ctr);
+  up.add(&P.d_cord0, P.cord0);
   up.add(reinterpret_cast<void**>(&P.d_E), E, n_e * sizeof(double2));
   up.add(reinterpret_cast<void**>(&P.d_A), A, n_e * sizeof(double2));
   up.add(&P.d_alpha, alpha);

@@ -954,6 +954,212 @@ static int launch_contract_res(trap_ctx* ctx, hipStream_t stream, int zc, int z0
   return 1;
 }
 
+// ---- resident-field FP64 contraction
+// The FP32 kernel's scheme for the FP64 operator: groups of at most 16 slots
+// (four column tiles), the comoving field in LDS as doubles with frequency
+// pairs interleaved per column and each 16-column tile's columns transposed
+// as a 4 x 4 grid (the f64 matrix-core output then holds one slot's four
+// Stokes values per lane), kernel rows as value + remainder read two stages
+// ahead through three register buffers, products over the full bands.
+constexpr int kRes64D = 8;
+constexpr int kRes64Stage = 5;   // staging items per thread: (320 / 2) x 16 slots / 512 threads
+
+template <int D>
+__device__ __forceinline__ void res64_load(const KStore& ks, const RStage& st, int lk, double2 (&a)[D]) {
+  const bool any = st.e > st.s;
+  const long long base = any ? st.r.base + 2 * lk : 2LL * lk;
+  const int s = any ? st.s : 0, last = any ? st.e - 1 : D - 1;
+#pragma unroll
+  for (int h = 0; h < D; ++h) {
+    const long long i = base + 8LL * min(s + h, last);
+    const float2 vh = *reinterpret_cast<const float2*>(ks.hi + i);
+    const float2 vl = *reinterpret_cast<const float2*>(ks.lo + i);
+    a[h] = make_double2((double)vh.x + (double)vl.x, (double)vh.y + (double)vl.y);
+  }
+}
+
+template <int D>
+__device__ __forceinline__ void res64_mfma(const double* bl, int s, int e, const double2 (&a)[D],
+                                           doublex4_t (&acc)[4]) {
+  constexpr int CW = 64;
+  const int n = e - s;
+  if (n <= 0) return;
+  const double* b0 = bl + (size_t)s * 8 * CW;
+  double2 b[2][4];
+#pragma unroll
+  for (int jt = 0; jt < 4; ++jt) b[0][jt] = *reinterpret_cast<const double2*>(b0 + 32 * jt);
+#pragma unroll
+  for (int h = 0; h < D; ++h) {
+    if (h + 1 < D) {
+      const double* bh = b0 + min(h + 1, n - 1) * 8 * CW;
+#pragma unroll
+      for (int jt = 0; jt < 4; ++jt) b[(h + 1) & 1][jt] = *reinterpret_cast<const double2*>(bh + 32 * jt);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    if (h < n) {
+#pragma unroll
+      for (int jt = 0; jt < 4; ++jt)
+        acc[jt] = __builtin_amdgcn_mfma_f64_16x16x4f64(b[h & 1][jt].x, a[h].x, acc[jt], 0, 0, 0);
+#pragma unroll
+      for (int jt = 0; jt < 4; ++jt)
+        acc[jt] = __builtin_amdgcn_mfma_f64_16x16x4f64(b[h & 1][jt].y, a[h].y, acc[jt], 0, 0, 0);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+__device__ __forceinline__ void res64_tiles(const KStore& ks, long long zt, int t1, int zl, int nt, int nn, int nslot,
+                                            int s0, int cnt, const double* Bs, int* ctr, double* __restrict__ W,
+                                            int lane) {
+  constexpr int D = kRes64D;
+  constexpr int CW = 64;
+  const int lr = lane & 15, lk = lane >> 4;
+  const double* bl = Bs + (size_t)lk * 2 * CW + 2 * lr;
+  auto advance = [&](const RStage& st) {
+    RStage n = st;
+    if (!st.ok) return n;
+    if (st.s + D < st.e) {
+      n.s = st.s + D;
+      return n;
+    }
+    const int q = res_grab(ctr, lane);
+    if (q >= t1) {
+      n.ok = 0;
+      return n;
+    }
+    n.r = krow_s(ks, zt, q, lr, nn);
+    n.s = n.r.wlo >> 3;
+    n.e = n.r.whi >> 3;
+    return n;
+  };
+  doublex4_t acc[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+    for (int c = 0; c < 4; ++c) acc[j][c] = 0.0;
+  RStage s0st;
+  s0st.ok = 1;
+  s0st.s = 0;
+  s0st.e = 0;
+  s0st.r = KRow{0, 0, 0, 0, 0, false};
+  RStage st0 = advance(s0st);
+  if (!st0.ok) return;
+  RStage st1 = advance(st0);
+  double2 a0[D], a1[D], a2[D];
+  res64_load<D>(ks, st0, lk, a0);
+  res64_load<D>(ks, st1, lk, a1);
+  auto body = [&](double2 (&l)[D], const double2 (&c)[D]) {
+    const RStage st2 = advance(st1);
+    res64_load<D>(ks, st2, lk, l);
+    // the buffer's loads are complete here on every path (an empty asm that
+    // only reads the registers: no instruction is emitted)
+#pragma unroll
+    for (int h = 0; h < D; ++h) asm volatile("" ::"v"(c[h].x), "v"(c[h].y));
+    res64_mfma<D>(bl, st0.s, st0.e, c, acc);
+    if (st0.s + D >= st0.e) {
+      store_w<double, 4>(st0.r, zl, nt, nn, nslot, s0, cnt, lk, acc, W);
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        for (int c4 = 0; c4 < 4; ++c4) acc[j][c4] = 0.0;
+    }
+    st0 = st1;
+    st1 = st2;
+    return st0.ok != 0;
+  };
+  while (body(a2, a0) && body(a0, a1) && body(a1, a2)) {
+  }
+}
+
+// unit ui -> (group cord0[j], slice, height): ui = (j nsl + slice) zc + zl;
+// the ticket and count are the FP32 kernel's (one contraction at a time per context)
+__global__ void __launch_bounds__(512, 1) k_contract_res64(int z0, int zc, int nth, int nt, int nn, int nd, int ldm,
+                                                           KStore ks, const double* __restrict__ Ibar,
+                                                           const int* __restrict__ cgrp, const int* __restrict__ cord,
+                                                           int ngrp, int nsl, int* __restrict__ uctr,
+                                                           const int* __restrict__ slot_dir, double* __restrict__ W,
+                                                           int nslot) {
+  extern __shared__ __align__(16) unsigned char rsh64[];
+  double* Bs = reinterpret_cast<double*>(rsh64);
+  int* ctr = reinterpret_cast<int*>(Bs + (size_t)ldm * 64);
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int nunit = zc * ngrp * nsl;
+  const int np2 = ldm >> 1;
+  if (tid == 0) ctr[2] = atomicAdd(&uctr[0], 1);
+  __syncthreads();
+  for (int it = 0;; ++it) {
+    const int ui = ctr[2 + (it & 1)];
+    if (ui >= nunit) break;
+    const int zl = ui % zc, js = ui / zc, j = js / nsl, slice = js - j * nsl;
+    const int g = cord[j];
+    const int th = cgrp[3 * g], s0 = cgrp[3 * g + 1], cnt = cgrp[3 * g + 2];
+    const int t0 = (int)((long long)slice * ks.nq / nsl), t1 = (int)((long long)(slice + 1) * ks.nq / nsl);
+    // item e = tid + 512 q is (pair row e / 16, slot e % 16): one slot per thread
+    const double* Ib = Ibar + (size_t)zl * nd * nn * 4;
+    const int nit = np2 * 16;
+    const int sl = tid & 15, kpb = tid >> 4;
+    const double* src = Ib + (size_t)slot_dir[s0 + min(sl, cnt - 1)] * nn * 4;
+    double4 v0[kRes64Stage], v1[kRes64Stage];
+#pragma unroll
+    for (int q = 0; q < kRes64Stage; ++q) {
+      const int kp = kpb + 32 * q;
+      const int k0 = min(2 * kp, nn - 1), k1 = min(2 * kp + 1, nn - 1);
+      v0[q] = *reinterpret_cast<const double4*>(src + (size_t)k0 * 4);
+      v1[q] = *reinterpret_cast<const double4*>(src + (size_t)k1 * 4);
+    }
+    // column of (slot sl, Stokes st) inside its 16-column tile: st * 4 + sl % 4
+    const int cb = 16 * (sl >> 2) + (sl & 3);
+#pragma unroll
+    for (int q = 0; q < kRes64Stage; ++q) {
+      const int e = tid + 512 * q;
+      if (e < nit) {
+        const int kp = kpb + 32 * q;
+        const double4 z4 = make_double4(0.0, 0.0, 0.0, 0.0);
+        const double4 a0 = (sl < cnt && 2 * kp < nn) ? v0[q] : z4;
+        const double4 a1 = (sl < cnt && 2 * kp + 1 < nn) ? v1[q] : z4;
+        double* dst = Bs + ((size_t)kp * 64 + cb) * 2;
+        *reinterpret_cast<double2*>(dst) = make_double2(a0.x, a1.x);
+        *reinterpret_cast<double2*>(dst + 8) = make_double2(a0.y, a1.y);
+        *reinterpret_cast<double2*>(dst + 16) = make_double2(a0.z, a1.z);
+        *reinterpret_cast<double2*>(dst + 24) = make_double2(a0.w, a1.w);
+      }
+    }
+    if (tid == 0) {
+      ctr[0] = t0;
+      ctr[2 + ((it + 1) & 1)] = atomicAdd(&uctr[0], 1);
+    }
+    __syncthreads();
+    res64_tiles(ks, (long long)(z0 + zl) * nth + th, t1, zl, nt, nn, nslot, s0, cnt, Bs, ctr, W, lane);
+    __syncthreads();
+  }
+  if (tid == 0) {
+    __threadfence();
+    if (atomicAdd(&uctr[1], 1) == (int)gridDim.x - 1) {
+      atomicExch(&uctr[0], 0);
+      atomicExch(&uctr[1], 0);
+    }
+  }
+}
+
+// 1 when launched, 0 when one group's field over all frequencies does not fit LDS
+static int launch_contract_res64(trap_ctx* ctx, hipStream_t stream, int zc, int z0, const double* Ibar, double* W) {
+  Problem& P = ctx->pb;
+  const int ngrp = (int)P.cgrp[0].size() / 3;
+  if (ngrp == 0) return 1;
+  const size_t lds = contract_res_lds(P.ldm);
+  if (lds > (size_t)ctx->max_lds || P.ldm > 320) return 0;
+  const KStore ks = kernel_store(ctx, false);
+  const long long base = (long long)zc * ngrp;
+  const int nsl = (int)std::max<long long>(1, std::min<long long>({8, ks.nq, (4LL * ctx->n_cu + base - 1) / base}));
+  const int nunit = (int)(base * nsl);
+  const int grid = std::min(nunit, ctx->n_cu);
+  if (lds > 64 * 1024)
+    TRAP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_contract_res64),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  hipLaunchKernelGGL(k_contract_res64, dim3(grid), dim3(512), lds, stream, z0, zc, P.nth, P.nt, P.nn, P.nd, P.ldm,
+                     ks, Ibar, P.d_cgrp[0], P.d_cord0, ngrp, nsl, P.d_unit_ctr, P.d_slot_dir, W, P.nslot);
+  TRAP_HIP(hipGetLastError());
+  return 1;
+}
+
 // 1 when launched, 0 when the problem does not fit the pipelined kernel's LDS
 static int launch_contract_pipe(trap_ctx* ctx, hipStream_t stream, int zc, int z0, const float* Ibar, float* W) {
   Problem& P = ctx->pb;
@@ -1718,7 +1924,11 @@ static int sigma_apply_t(trap_ctx* ctx, const T* I, T* eps, int prec, int add_th
                          nt, nn, kernel_store(ctx, false), P.d_WT, W);
       TRAP_HIP(hipGetLastError());
     } else {
-      TRAP_TRY(launch_contract<T>(ctx, zc, z0, Ibar + (size_t)z0 * nd * nn * 4, W));
+      int launched = 0;
+      if constexpr (sizeof(T) == sizeof(double))
+        launched = launch_contract_res64(ctx, ctx->stream, zc, z0, Ibar + (size_t)z0 * nd * nn * 4, W);
+      if (launched < 0) return launched;
+      if (!launched) TRAP_TRY(launch_contract<T>(ctx, zc, z0, Ibar + (size_t)z0 * nd * nn * 4, W));
     }
     prof_end(ctx, pr);
     // 4. angular / sublevel sum into Eb (chunk-local heights)

@@ -211,6 +211,7 @@ struct Problem {
   // resident-field contraction's work order; its unit ticket and finished-block
   // count (zero between launches: the last block to finish resets them)
   std::vector<int> cord, unit_ctr;
+  std::vector<int> cord0;                  // the same order for the FP64 groups (at most 16 slots)
   // device copies
   double *d_x = nullptr, *d_P = nullptr, *d_mu = nullptr, *d_w = nullptr, *d_tau = nullptr;
   double *d_Sig = nullptr;                 // [nn][nn] second-derivative map of the spline
@@ -229,6 +230,7 @@ struct Problem {
   int *d_cgrp[2] = {nullptr, nullptr};
   int* d_cord = nullptr;
   int* d_unit_ctr = nullptr;
+  int* d_cord0 = nullptr;
   double2 *d_E = nullptr, *d_A = nullptr;  // see above
   double2 *d_alpha = nullptr, *d_bma = nullptr; // [nz][nu][nu]
   double *d_g = nullptr;                   // [nz][nt][nd][4] geometric factors of K
