@@ -77,10 +77,18 @@ def _pick(vals, needle):
     return [x for v in hits.values() for x in v]
 
 
+def _names_kernel(name: str, needle: str) -> bool:
+    """True when the kernel's name is `needle` itself, or a template instance
+    of it (`needle<...>`): not a kernel whose name only starts like it."""
+    base = name.split("(")[0].replace("void ", "").strip()
+    base = base.split("::")[-1] if "::" in base and not base.split("::")[-1].startswith("<") else base
+    return base == needle or base.startswith(needle + "<")
+
+
 def _per_launch(vals, needle):
     """Mean counter value of one launch of the stage: the stage issues one
     dispatch of each matching kernel, so the per-kernel means add up."""
-    hits = {k: v for k, v in vals.items() if needle in k}
+    hits = {k: v for k, v in vals.items() if _names_kernel(k, needle)}
     if not hits:
         raise SystemExit(f"no dispatch of a kernel named like {needle!r}")
     return sum(statistics.mean(v) for v in hits.values()), {k.split("(")[0]: len(v) for k, v in hits.items()}
