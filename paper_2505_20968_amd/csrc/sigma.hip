@@ -1297,7 +1297,7 @@ __global__ void k_r3_X(int z0, int nu, int nl, int nd, const double* __restrict_
 // frequencies.  The waves also share the R_III outer product (its
 // transition pairs dealt round-robin); the partial sums meet in LDS.  The
 // kernel streams W once and waits on memory: more waves per block keep
-// more loads in flight (KQ = 16 for the single-problem launch at 64 or more
+// more loads in flight (KQ = 8 for the single-problem launch at 64 or more
 // directions, 4 otherwise).
 constexpr int kAngQ = 4;
 
@@ -1935,9 +1935,11 @@ static int sigma_apply_t(trap_ctx* ctx, const T* I, T* eps, int prec, int add_th
     pr = prof_begin(ctx, TRAP_STAGE_ANGULAR);
     {
       // more waves per block where the directions are many and the partial
-      // sums fit (32 KB of LDS: 16 waves in FP32, 8 in FP64, up to two lower
-      // sublevels)
-      constexpr int KW = sizeof(T) == 4 ? 16 : 8;
+      // sums fit (up to two lower sublevels): 8 waves, so that a launch's
+      // blocks are resident at once (at 128 directions and 301 frequencies,
+      // 640 blocks of 16 waves ran in 2.5 rounds of one block per compute
+      // unit: 0.46 ms against 0.41 ms per height with 8 waves)
+      constexpr int KW = 8;
       const bool wide = nd >= 64 && nl <= 2;
       auto kern = wide ? (nl == 1 ? k_angular<T, 1, KW> : k_angular<T, 2, KW>)
                        : (nl == 1 ? k_angular<T, 1, kAngQ> : nl == 2 ? k_angular<T, 2, kAngQ>
